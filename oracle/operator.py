@@ -1,0 +1,391 @@
+"""SIPG operator of the paper, applied matrix-free by quadrature; assembled form; RHS; norms.
+
+Bilinear form (Sec. II.A.2, Eqs. lh / lh2 / lh3, read as -div(k grad u) + c u = g):
+  L(u, v) = sum_e int_e k grad u . grad v + c u v
+          - sum_{m in M_ID} int_m [[u]] . {{k grad v}} + [[v]] . {{k grad u}}
+          + sum_{m in M_ID} int_m sigma [[u]] . [[v]]
+with [[q]] = q+ n+ + q- n-, {{q}} = (q+ + q-)/2 inside (Eq. 20), [[q]] = q n,
+{{q}} = q on Dirichlet faces.  Neumann faces add no operator term.
+
+Quadrature (Sec. II.A.5, Eqs. stiffness-3, harald-stiff, temp-E): polynomials are
+interpolated from LGL nodes to GL points; geometry is evaluated at GL points.  The
+number of GL points is one of the readings listed with the design notes: q = p + 1 on
+affine elements with constant k (exact), q = p + 1 + quad_extra otherwise; mortars use
+q_m = p_m + 1 (+ quad_extra when a side is curved or k varies), p_m = max(p-, p+).
+Mortar geometry (S^m, normal) comes from the finer side (equal levels: the lower
+element index), whose face coordinates parametrise the mortar.
+
+Penalty (Eq. penaltyparameter): sigma = C p_m^2 / h_m, h_m = 2 min_side 1/|grad xi_j|
+(the thickness of the side normal to the face), evaluated at each mortar point,
+multiplied by k at the point.
+"""
+import numpy as np
+
+from . import geometry, rules, problems
+from .mesh import build_mortars, face_point, minus_to_plus
+
+DIRICHLET, NEUMANN, ROBIN = 1, 2, 3
+
+
+def _basis_at(n, xi):
+    """Tensor LGL basis of n nodes per axis at reference points xi [P, 3].
+
+    Returns V [P, n^3] and Dxi [3, P, n^3]; local index alpha = i + n j + n^2 k
+    (x fastest) for the node (xi_i, xi_j, xi_k).
+    """
+    nodes, _ = rules.lgl(n)
+    L = [rules.lagrange(nodes, xi[:, d]) for d in range(3)]
+    D = [rules.lagrange_deriv(nodes, xi[:, d]) for d in range(3)]
+    V = np.einsum("pk,pj,pi->pkji", L[2], L[1], L[0]).reshape(len(xi), -1)
+    D0 = np.einsum("pk,pj,pi->pkji", L[2], L[1], D[0]).reshape(len(xi), -1)
+    D1 = np.einsum("pk,pj,pi->pkji", L[2], D[1], L[0]).reshape(len(xi), -1)
+    D2 = np.einsum("pk,pj,pi->pkji", D[2], L[1], L[0]).reshape(len(xi), -1)
+    return V, np.stack([D0, D1, D2])
+
+
+class SIPG:
+    """The discrete operator A (y = A u) and right-hand side F on one cell mesh."""
+
+    def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, bc_override=None,
+                 mass=None):
+        self.mesh = mesh
+        self.problem = problem
+        self.C = float(C)
+        self.quad_extra = int(quad_extra)
+        self.mass = mass  # callable c(x) >= 0 or None
+        p = mesh["elem_p"].astype(np.int64)
+        self.E = len(p)
+        self.n = p + 1
+        self.offsets = np.concatenate([[0], np.cumsum(self.n ** 3)])
+        self.ndof = int(self.offsets[-1])
+        self.kconst = problems.k_is_constant(problem)
+        self.affine = geometry.is_affine_macro(mesh["macro_kind"][mesh["elem_macro"]])
+        self.mortars = build_mortars(mesh)
+        if bc_override is not None:
+            for mt in self.mortars:
+                if mt["ep"] < 0:
+                    mt["bc"] = bc_override
+        self._setup_volume()
+        self._setup_faces()
+
+    # -- quadrature choices -----------------------------------------------------
+    def q_volume(self, e):
+        exact = self.affine[e] and self.kconst and self.mass is None
+        return int(self.n[e]) + (0 if exact else self.quad_extra)
+
+    def q_mortar(self, mt):
+        pm = int(self.n[mt["em"]])
+        curved = not self.affine[mt["em"]]
+        if mt["ep"] >= 0:
+            pm = max(pm, int(self.n[mt["ep"]]))
+            curved = curved or not self.affine[mt["ep"]]
+        return pm + (self.quad_extra if (curved or not self.kconst) else 0)
+
+    def k(self, x):
+        return problems.k_of(self.problem, x)
+
+    # -- volume -------------------------------------------------------------------
+    def _setup_volume(self):
+        groups = {}
+        for e in range(self.E):
+            groups.setdefault((int(self.n[e]), self.q_volume(e)), []).append(e)
+        self.vgroups = []
+        for (n, q), elems in sorted(groups.items()):
+            elems = np.array(elems)
+            lgl_x, _ = rules.lgl(n)
+            eta, w = rules.gl(q)
+            B = rules.lagrange(lgl_x, eta)
+            Dt = rules.lagrange_deriv(lgl_x, eta)
+            xi = np.stack(np.meshgrid(eta, eta, eta, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+            W = np.einsum("c,b,a->cba", w, w, w).reshape(-1)
+            x, J = geometry.element_map(self.mesh, elems[:, None], xi[None])
+            det = np.linalg.det(J)
+            if np.any(det <= 0):
+                raise ValueError("non-positive Jacobian determinant")
+            Ji = np.linalg.inv(J)  # Ji[d, i] = dxi_d / dx_i
+            G = np.einsum("epdi,epci->epdc", Ji, Ji) * (W * det * self.k(x))[:, :, None, None]
+            M = None
+            if self.mass is not None:
+                M = W * det * self.mass(x)
+            idx = self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]
+            self.vgroups.append(dict(n=n, q=q, elems=elems, B=B, Dt=Dt, G=G, M=M, idx=idx,
+                                     x=x, W=W, det=det))
+
+    def _volume(self, u, y):
+        for g in self.vgroups:
+            n, q = g["n"], g["q"]
+            B, Dt = g["B"], g["Dt"]
+            U = u[g["idx"]].reshape(-1, n, n, n)
+            d0 = np.einsum("ck,bj,ai,ekji->ecba", B, B, Dt, U, optimize=True)
+            d1 = np.einsum("ck,bj,ai,ekji->ecba", B, Dt, B, U, optimize=True)
+            d2 = np.einsum("ck,bj,ai,ekji->ecba", Dt, B, B, U, optimize=True)
+            grad = np.stack([d0, d1, d2], axis=-1).reshape(len(U), q ** 3, 3)
+            F = np.einsum("epdc,epc->epd", g["G"], grad).reshape(len(U), q, q, q, 3)
+            Y = (np.einsum("ck,bj,ai,ecba->ekji", B, B, Dt, F[..., 0], optimize=True)
+                 + np.einsum("ck,bj,ai,ecba->ekji", B, Dt, B, F[..., 1], optimize=True)
+                 + np.einsum("ck,bj,ai,ecba->ekji", Dt, B, B, F[..., 2], optimize=True))
+            if g["M"] is not None:
+                uq = np.einsum("ck,bj,ai,ekji->ecba", B, B, B, U, optimize=True).reshape(len(U), -1)
+                Y += np.einsum("ck,bj,ai,ecba->ekji", B, B, B,
+                               (g["M"] * uq).reshape(len(U), q, q, q), optimize=True)
+            y[g["idx"]] += Y.reshape(len(U), -1)
+
+    # -- faces --------------------------------------------------------------------
+    def _setup_faces(self):
+        groups = {}
+        for mi, mt in enumerate(self.mortars):
+            if mt["ep"] < 0 and mt["bc"] != DIRICHLET:
+                continue  # Neumann faces: no operator term
+            nm = int(self.n[mt["em"]])
+            npl = int(self.n[mt["ep"]]) if mt["ep"] >= 0 else 0
+            key = (nm, npl, self.q_mortar(mt), mt["fm"], mt["fp"], mt["o"], mt["sub"], mt["bc"])
+            groups.setdefault(key, []).append(mi)
+        self.fgroups = []
+        for key, mis in groups.items():
+            nm, npl, qm, fm, fp, o, sub, bc = key
+            eta, w = rules.gl(qm)
+            s, t = np.meshgrid(eta, eta, indexing="xy")  # point rho = c + qm d: s = eta_c, t = eta_d
+            s, t = s.reshape(-1), t.reshape(-1)
+            wst = np.outer(w, w).reshape(-1)
+            mt0 = self.mortars[mis[0]]
+            xim = face_point(fm, s, t)
+            Vm, Dm = _basis_at(nm, xim)
+            em = np.array([self.mortars[i]["em"] for i in mis])
+            x, Jm = geometry.element_map(self.mesh, em[:, None], xim[None])
+            Jim = np.linalg.inv(Jm)
+            detm = np.linalg.det(Jm)
+            dm, sm = divmod(fm, 2)
+            row = Jim[:, :, dm, :]
+            nrm = np.linalg.norm(row, axis=-1)
+            S = detm * nrm
+            nhat = (1.0 if sm else -1.0) * row / nrm[..., None]
+            wS = wst[None, :] * S
+            hmin = 2.0 / nrm
+            pm = nm - 1
+            g = dict(key=key, mis=np.array(mis), em=em, wS=wS, x=x, Vm=Vm, Dm=Dm,
+                     mvec_m=np.einsum("mpdi,mpi->mpd", Jim, nhat), nhat=nhat,
+                     idx_m=self.offsets[em][:, None] + np.arange(nm ** 3)[None, :])
+            if npl:
+                a, b = minus_to_plus(mt0, s, t)
+                xip = face_point(fp, a, b)
+                Vp, Dp = _basis_at(npl, xip)
+                ep = np.array([self.mortars[i]["ep"] for i in mis])
+                xp, Jp = geometry.element_map(self.mesh, ep[:, None], xip[None])
+                Jip = np.linalg.inv(Jp)
+                dp_ = fp // 2
+                nrp = np.linalg.norm(Jip[:, :, dp_, :], axis=-1)
+                hmin = np.minimum(hmin, 2.0 / nrp)
+                pm = max(pm, npl - 1)
+                g.update(ep=ep, Vp=Vp, Dp=Dp, xp=xp,
+                         mvec_p=np.einsum("mpdi,mpi->mpd", Jip, -nhat),
+                         idx_p=self.offsets[ep][:, None] + np.arange(npl ** 3)[None, :])
+            kx = self.k(x)
+            g["kx"] = kx
+            g["sigma"] = self.C * pm * pm / hmin * kx
+            self.fgroups.append(g)
+
+    def _faces(self, u, y):
+        for g in self.fgroups:
+            wS, kx, sig = g["wS"], g["kx"], g["sigma"]
+            Um = u[g["idx_m"]]
+            um = Um @ g["Vm"].T
+            # physical normal derivative n.grad u = (J^-1 n) . grad_xi u
+            gm = np.einsum("mpd,dpa,ma->mp", g["mvec_m"], g["Dm"], Um)
+            if "ep" in g:
+                Up = u[g["idx_p"]]
+                up = Up @ g["Vp"].T
+                gp = np.einsum("mpd,dpa,ma->mp", g["mvec_p"], g["Dp"], Up)
+                # side -: jump j = u- - u+, n-.(grad u- + grad u+) = g- - g+
+                jm = um - up
+                Am = wS * (sig * jm - 0.5 * kx * (gm - gp))
+                Bm = -0.5 * wS * kx * jm
+                Ap, Bp = -Am, -Bm  # side +: j+ = -j-, n+ = -n-
+                ym = Am @ g["Vm"] + np.einsum("mp,mpd,dpa->ma", Bm, g["mvec_m"], g["Dm"])
+                yp = Ap @ g["Vp"] + np.einsum("mp,mpd,dpa->ma", Bp, g["mvec_p"], g["Dp"])
+                np.add.at(y, g["idx_m"], ym)
+                np.add.at(y, g["idx_p"], yp)
+            else:  # Dirichlet face: [[u]] = u n, {{k grad u}} = k grad u
+                A = wS * (sig * um - kx * gm)
+                Bc = -wS * kx * um
+                ym = A @ g["Vm"] + np.einsum("mp,mpd,dpa->ma", Bc, g["mvec_m"], g["Dm"])
+                np.add.at(y, g["idx_m"], ym)
+
+    # -- public ---------------------------------------------------------------------
+    def apply(self, u):
+        u = np.asarray(u, float)
+        y = np.zeros(self.ndof)
+        self._volume(u, y)
+        self._faces(u, y)
+        return y
+
+    def diagonal(self):
+        """diag(A): the bilinear form of each basis function with itself.
+
+        Volume: sum_sigma grad psi . G grad psi (+ mass).  Faces, side s with u = psi on
+        that side only: sum_rho wS (sigma psi^2 - k psi n.grad psi) inside (the two
+        halves of the consistency and symmetry terms), sum_rho wS (sigma psi^2 -
+        2 k psi n.grad psi) on Dirichlet faces.
+        """
+        dg = np.zeros(self.ndof)
+        for g in self.vgroups:
+            n, q = g["n"], g["q"]
+            B, Dt = g["B"], g["Dt"]
+            G = g["G"].reshape(-1, q, q, q, 3, 3)
+            ops = [(Dt, B, B), (B, Dt, B), (B, B, Dt)]  # (x, y, z) factor of d/dxi_d
+            out = np.zeros((len(G), n, n, n))
+            for d in range(3):
+                for e in range(3):
+                    fx = ops[d][0] * ops[e][0]
+                    fy = ops[d][1] * ops[e][1]
+                    fz = ops[d][2] * ops[e][2]
+                    out += np.einsum("ecba,ck,bj,ai->ekji", G[..., d, e], fz, fy, fx, optimize=True)
+            if g["M"] is not None:
+                out += np.einsum("ecba,ck,bj,ai->ekji", g["M"].reshape(-1, q, q, q),
+                                 B * B, B * B, B * B, optimize=True)
+            dg[g["idx"]] += out.reshape(len(G), -1)
+        for g in self.fgroups:
+            wS, kx, sig = g["wS"], g["kx"], g["sigma"]
+            sides = [("Vm", "Dm", "mvec_m", "idx_m")]
+            if "ep" in g:
+                sides.append(("Vp", "Dp", "mvec_p", "idx_p"))
+            factor = 1.0 if "ep" in g else 2.0
+            for V, D, mv, idx in sides:
+                psi = g[V]                                      # [p, a]
+                gn = np.einsum("mpd,dpa->mpa", g[mv], g[D])     # n.grad psi per mortar
+                val = (wS * sig) @ (psi * psi) - factor * np.einsum("mp,pa,mpa->ma", wS * kx, psi, gn)
+                np.add.at(dg, g[idx], val)
+        return dg
+
+    def rhs(self, problem=None):
+        """F(psi) = int g psi + sum_{Dirichlet} int g_D (-k n.grad psi + sigma psi)  (Eq. Fh2)."""
+        problem = problem if problem is not None else self.problem
+        F = np.zeros(self.ndof)
+        for g in self.vgroups:
+            n, q = g["n"], g["q"]
+            B = g["B"]
+            gx = problems.source_g(problem, g["x"]) * g["W"] * g["det"]
+            F[g["idx"]] += np.einsum("ck,bj,ai,ecba->ekji", B, B, B,
+                                     gx.reshape(-1, q, q, q), optimize=True).reshape(len(gx), -1)
+        for g in self.fgroups:
+            if "ep" in g:
+                continue
+            gd = problems.dirichlet_g(problem, g["x"])
+            A = g["wS"] * g["sigma"] * gd
+            Bc = -g["wS"] * g["kx"] * gd
+            ym = A @ g["Vm"] + np.einsum("mp,mpd,dpa->ma", Bc, g["mvec_m"], g["Dm"])
+            np.add.at(F, g["idx_m"], ym)
+        return F
+
+    def interpolate(self, func):
+        """Nodal interpolant: the value of func at every element's LGL nodes."""
+        u = np.zeros(self.ndof)
+        for n in sorted(set(int(x) for x in self.n)):
+            elems = np.where(self.n == n)[0]
+            xl, _ = rules.lgl(n)
+            xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+            x, _ = geometry.element_map(self.mesh, elems[:, None], xi[None])
+            u[self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]] = func(x)
+        return u
+
+    def nodes(self):
+        """Physical coordinates of every degree of freedom, [ndof, 3]."""
+        X = np.zeros((self.ndof, 3))
+        for n in sorted(set(int(x) for x in self.n)):
+            elems = np.where(self.n == n)[0]
+            xl, _ = rules.lgl(n)
+            xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+            x, _ = geometry.element_map(self.mesh, elems[:, None], xi[None])
+            X[self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]] = x
+        return X
+
+    def l2_error(self, u, func, extra=3):
+        """||u_h - func||_{L2} with q = p + 1 + extra GL points per axis (Eq. l2norm)."""
+        err2 = 0.0
+        for n in sorted(set(int(x) for x in self.n)):
+            elems = np.where(self.n == n)[0]
+            q = n + extra
+            eta, w = rules.gl(q)
+            xl, _ = rules.lgl(n)
+            B = rules.lagrange(xl, eta)
+            xi = np.stack(np.meshgrid(eta, eta, eta, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+            W = np.einsum("c,b,a->cba", w, w, w).reshape(-1)
+            x, J = geometry.element_map(self.mesh, elems[:, None], xi[None])
+            U = u[self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]].reshape(-1, n, n, n)
+            uq = np.einsum("ck,bj,ai,ekji->ecba", B, B, B, U, optimize=True).reshape(len(elems), -1)
+            err2 += float(np.sum(W * np.linalg.det(J) * (uq - func(x)) ** 2))
+        return np.sqrt(err2)
+
+
+def assemble_dense(op):
+    """Brute-force dense matrix A[beta, alpha] = L(psi_alpha, psi_beta) for tiny meshes.
+
+    Written independently of the matrix-free path: every basis function's physical
+    gradient is formed explicitly at every quadrature point, and the face terms use the
+    vector jumps and averages of Eq. 20 directly (the four blocks --, -+, +-, ++).
+    """
+    N = op.ndof
+    A = np.zeros((N, N))
+    for g in op.vgroups:
+        n, q = g["n"], g["q"]
+        lgl_x, _ = rules.lgl(n)
+        eta, w = rules.gl(q)
+        xi = np.stack(np.meshgrid(eta, eta, eta, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+        V, D = _basis_at(n, xi)
+        W = np.einsum("c,b,a->cba", w, w, w).reshape(-1)
+        for le, e in enumerate(g["elems"]):
+            x, J = geometry.element_map(op.mesh, np.full(len(xi), e), xi)
+            Ji = np.linalg.inv(J)
+            det = np.linalg.det(J)
+            kx = op.k(x)
+            grad = np.einsum("pdi,dpa->pai", Ji, D)  # physical gradient of every basis function
+            Ke = np.einsum("p,pai,pbi->ba", W * det * kx, grad, grad)
+            if op.mass is not None:
+                Ke += np.einsum("p,pa,pb->ba", W * det * op.mass(x), V, V)
+            sl = slice(op.offsets[e], op.offsets[e + 1])
+            A[sl, sl] += Ke
+    for mt in op.mortars:
+        if mt["ep"] < 0 and mt["bc"] != DIRICHLET:
+            continue
+        qm = op.q_mortar(mt)
+        eta, w = rules.gl(qm)
+        s, t = np.meshgrid(eta, eta, indexing="xy")
+        s, t = s.reshape(-1), t.reshape(-1)
+        wst = np.outer(w, w).reshape(-1)
+        sides = []
+        em, fm = mt["em"], mt["fm"]
+        xim = face_point(fm, s, t)
+        x, J = geometry.element_map(op.mesh, np.full(len(s), em), xim)
+        Ji = np.linalg.inv(J)
+        d, sd = divmod(fm, 2)
+        row = Ji[:, d, :]
+        nrm = np.linalg.norm(row, axis=-1)
+        nvec = (1.0 if sd else -1.0) * row / nrm[:, None]
+        dS = wst * np.linalg.det(J) * nrm
+        V, D = _basis_at(int(op.n[em]), xim)
+        sides.append((em, V, np.einsum("pdi,dpa->pai", Ji, D), nvec))
+        h = 2.0 / nrm
+        pm = int(op.n[em]) - 1
+        if mt["ep"] >= 0:
+            ep, fp = mt["ep"], mt["fp"]
+            a, b = minus_to_plus(mt, s, t)
+            xip = face_point(fp, a, b)
+            _, Jp = geometry.element_map(op.mesh, np.full(len(s), ep), xip)
+            Jip = np.linalg.inv(Jp)
+            Vp, Dp = _basis_at(int(op.n[ep]), xip)
+            sides.append((ep, Vp, np.einsum("pdi,dpa->pai", Jip, Dp), -nvec))
+            h = np.minimum(h, 2.0 / np.linalg.norm(Jip[:, fp // 2, :], axis=-1))
+            pm = max(pm, int(op.n[ep]) - 1)
+        kx = op.k(x)
+        sigma = op.C * pm * pm / h * kx
+        half = 0.5 if len(sides) == 2 else 1.0
+        for (eu, Vu, Gu, nu) in sides:        # trial side
+            for (ev, Vv, Gv, nv) in sides:    # test side
+                jump_u = Vu[:, :, None] * nu[:, None, :]          # [[psi_u]]  (p, a, i)
+                jump_v = Vv[:, :, None] * nv[:, None, :]
+                avg_u = half * kx[:, None, None] * Gu               # {{k grad psi_u}}
+                avg_v = half * kx[:, None, None] * Gv
+                blk = (-np.einsum("p,pai,pbi->ba", dS, jump_u, avg_v)
+                       - np.einsum("p,pbi,pai->ba", dS, jump_v, avg_u)
+                       + np.einsum("p,pai,pbi->ba", dS * sigma, jump_u, jump_v))
+                A[op.offsets[ev]:op.offsets[ev + 1], op.offsets[eu]:op.offsets[eu + 1]] += blk
+    return A

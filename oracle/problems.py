@@ -1,0 +1,97 @@
+"""Manufactured solutions, sources and coefficients for the descriptors named by ``meshgen``.
+
+Model problem (reading of Sec. II.A.2, Eq. Laplacian, with the sign of the bilinear
+form Eq. lh): -div(k grad u) + c u = g in the domain, u = g_D on Dirichlet faces.
+Each source g is derived from u by hand (the derivations are in the docstrings),
+never copied from a printed right-hand side.
+"""
+import numpy as np
+
+
+def k_of(problem, x):
+    """Diffusion coefficient at points x [..., 3]."""
+    if problem is not None and problem["kind"] == "radial_step":
+        r0, k_in, k_out = problem["params"][:3]
+        r = np.linalg.norm(x, axis=-1)
+        return np.where(r < r0, k_in, k_out)
+    return np.ones(x.shape[:-1])
+
+
+def k_is_constant(problem):
+    return problem is None or problem["kind"] != "radial_step"
+
+
+def exact_u(problem, x):
+    kind = problem["kind"]
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+    if kind == "sinsinsin":
+        return np.sin(np.pi * X) * np.sin(np.pi * Y) * np.sin(np.pi * Z)
+    if kind == "shell_harmonic":
+        c = problem["params"][0]
+        r = np.linalg.norm(x, axis=-1)
+        return 1.0 / r + c * X * Z / r ** 5
+    if kind == "radial_step":
+        r0, k_in, k_out = problem["params"][:3]
+        r2 = np.sum(x * x, axis=-1)
+        inside = np.sqrt(r2) < r0
+        c_in = r0 * r0 * (1.0 / k_out - 1.0 / k_in)
+        return np.where(inside, r2 / k_in + c_in, r2 / k_out)
+    if kind == "polynomial":
+        C = _poly_coeffs(problem)
+        P = C.shape[0]
+        u = np.zeros(x.shape[:-1])
+        for a in range(P):
+            for b in range(P):
+                for c in range(P):
+                    u += C[a, b, c] * X ** a * Y ** b * Z ** c
+        return u
+    if kind == "gaussians":
+        return np.zeros(x.shape[:-1])  # only used as Dirichlet data (g_D = 0)
+    raise ValueError(kind)
+
+
+def source_g(problem, x):
+    """g = -div(k grad u) for the manufactured u (or the given source)."""
+    kind = problem["kind"]
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+    if kind == "sinsinsin":
+        # -lap sin sin sin = 3 pi^2 sin sin sin
+        return 3.0 * np.pi ** 2 * exact_u(problem, x)
+    if kind == "shell_harmonic":
+        # 1/r and x z / r^5 (Kelvin transform of the harmonic x z) are harmonic away from 0
+        return np.zeros(x.shape[:-1])
+    if kind == "radial_step":
+        # k grad u = 2 x on both sides of r0, so -div(k grad u) = -6
+        return np.full(x.shape[:-1], -6.0)
+    if kind == "polynomial":
+        C = _poly_coeffs(problem)
+        P = C.shape[0]
+        g = np.zeros(x.shape[:-1])
+        for a in range(P):
+            for b in range(P):
+                for c in range(P):
+                    if a >= 2:
+                        g -= C[a, b, c] * a * (a - 1) * X ** (a - 2) * Y ** b * Z ** c
+                    if b >= 2:
+                        g -= C[a, b, c] * b * (b - 1) * X ** a * Y ** (b - 2) * Z ** c
+                    if c >= 2:
+                        g -= C[a, b, c] * c * (c - 1) * X ** a * Y ** b * Z ** (c - 2)
+        return g
+    if kind == "gaussians":
+        rows = np.asarray(problem["params"]).reshape(-1, 5)
+        g = np.zeros(x.shape[:-1])
+        for a, cx, cy, cz, s in rows:
+            d2 = (X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2
+            g += a * np.exp(-d2 / (2.0 * s * s))
+        return g
+    raise ValueError(kind)
+
+
+def dirichlet_g(problem, x):
+    return exact_u(problem, x)
+
+
+def _poly_coeffs(problem):
+    C = np.asarray(problem["params"], float)
+    P = int(round(len(C) ** (1.0 / 3.0)))
+    return C.reshape(P, P, P)

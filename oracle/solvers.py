@@ -1,0 +1,245 @@
+"""Multigrid-preconditioned Krylov solve: transfers, Chebyshev, CG spectral bound, V-cycle, FCG, PCG.
+
+* Prolongation (Sec. II.D.6, Eq. psi-interpolation): coarse basis functions are
+  interpolated exactly at the fine LGL nodes; restriction of residuals is the
+  transpose (Eq. temp-G).
+* Chebyshev smoother (Alg. 4) with the update p <- alpha r + beta p (the sign that
+  reproduces the Chebyshev polynomial; the printed minus sign diverges).
+  Optionally (the default here) the residual is scaled by the inverse diagonal of A,
+  i.e. the same recurrence on D^-1 A; the printed, unscaled form is jacobi=False.
+* CG spectral bound (Alg. 5): CG steps give the Lanczos tridiagonal of Eq. tridiag
+  (diagonal 1/alpha_k + beta_{k-1}/alpha_{k-1}, off-diagonal -sqrt(beta_k)/alpha_k);
+  lambda_max is the Gershgorin bound of the full tridiagonal.  It is computed once per
+  level and frozen (the V-cycle is then a fixed symmetric operator).
+* V-cycle (Alg. 3) over the stored hierarchy; the coarsest level is solved exactly by
+  a dense FP64 Cholesky factorisation (instead of being smoothed).
+* Flexible CG (Alg. 2) with r0 = b - A u0, stopping when |r|/|b| <= tol or after
+  max_iter iterations; plain preconditioned CG for comparison.
+"""
+import numpy as np
+import scipy.linalg
+
+from . import rules
+from .mesh import hierarchy, parent_map
+from .operator import SIPG
+
+
+class Transfer:
+    """Prolongation from a coarse cell mesh to the next finer one, and its transpose."""
+
+    def __init__(self, fine_op, coarse_op):
+        self.fine, self.coarse = fine_op, coarse_op
+        pm = parent_map(fine_op.mesh, coarse_op.mesh)
+        groups = {}
+        for k, (K, bits) in enumerate(pm):
+            key = (int(fine_op.n[k]), int(coarse_op.n[K]), bits)
+            groups.setdefault(key, []).append((k, K))
+        self.groups = []
+        for (nf, nc, bits), pairs in groups.items():
+            xf, _ = rules.lgl(nf)
+            xc, _ = rules.lgl(nc)
+            mats = []
+            for d in range(3):
+                pts = xf if bits is None else 0.5 * (xf + 2 * bits[d] - 1)
+                mats.append(rules.lagrange(xc, pts))  # [fine node, coarse node]
+            ks = np.array([p[0] for p in pairs])
+            Ks = np.array([p[1] for p in pairs])
+            self.groups.append(dict(
+                nf=nf, nc=nc, P=mats,
+                fidx=fine_op.offsets[ks][:, None] + np.arange(nf ** 3)[None, :],
+                cidx=coarse_op.offsets[Ks][:, None] + np.arange(nc ** 3)[None, :]))
+
+    def prolong(self, uc):
+        uf = np.zeros(self.fine.ndof)
+        for g in self.groups:
+            P0, P1, P2 = g["P"]
+            U = uc[g["cidx"]].reshape(-1, g["nc"], g["nc"], g["nc"])
+            uf[g["fidx"]] = np.einsum("zc,yb,xa,ecba->ezyx", P2, P1, P0, U,
+                                      optimize=True).reshape(len(U), -1)
+        return uf
+
+    def restrict(self, rf):
+        rc = np.zeros(self.coarse.ndof)
+        for g in self.groups:
+            P0, P1, P2 = g["P"]
+            R = rf[g["fidx"]].reshape(-1, g["nf"], g["nf"], g["nf"])
+            out = np.einsum("zc,yb,xa,ezyx->ecba", P2, P1, P0, R, optimize=True)
+            np.add.at(rc, g["cidx"], out.reshape(len(R), -1))
+        return rc
+
+
+def chebyshev(apply, b, x, lam_max, Lambda, n_iter, dinv=None):
+    """Alg. 4 with frozen lambda_max: n_iter Chebyshev steps on [lam_max/Lambda, lam_max].
+
+    With ``dinv`` (inverse diagonal of A) the residual is scaled, r = D^-1 (b - A x): the
+    same Chebyshev recurrence applied to D^-1 A (point-Jacobi-preconditioned Chebyshev);
+    lam_max is then a bound of the spectrum of D^-1 A.
+    """
+    lam_min = lam_max / Lambda
+    c = 0.5 * (lam_max - lam_min)
+    d = 0.5 * (lam_max + lam_min)
+    p = np.zeros_like(b)
+    x = x.copy()
+    alpha = 0.0
+    for k in range(1, n_iter + 1):
+        r = b - apply(x)
+        if dinv is not None:
+            r = dinv * r
+        if k == 1:
+            alpha = 1.0 / d
+        elif k == 2:
+            alpha = 2.0 * d / (2.0 * d * d - c * c)
+        else:
+            alpha = 1.0 / (d - alpha * c * c / 4.0)
+        beta = alpha * d - 1.0
+        p = alpha * r + beta * p
+        x = x + p
+    return x
+
+
+def cg_lanczos(apply, b, n_iter, x=None):
+    """Alg. 5: n_iter CG steps; returns (x, T) with the Lanczos tridiagonal T of Eq. tridiag."""
+    x = np.zeros_like(b) if x is None else x.copy()
+    r = b - apply(x)
+    p = r.copy()
+    rr = r @ r
+    alphas, betas = [], []
+    for _ in range(n_iter):
+        Ap = apply(p)
+        alpha = rr / (p @ Ap)
+        x = x + alpha * p
+        r = r - alpha * Ap
+        rr_new = r @ r
+        beta = rr_new / rr
+        alphas.append(alpha)
+        betas.append(beta)
+        p = r + beta * p
+        rr = rr_new
+    k = len(alphas)
+    T = np.zeros((k, k))
+    for i in range(k):
+        T[i, i] = 1.0 / alphas[i] + (betas[i - 1] / alphas[i - 1] if i > 0 else 0.0)
+        if i + 1 < k:
+            T[i, i + 1] = T[i + 1, i] = -np.sqrt(betas[i]) / alphas[i]
+    return x, T
+
+
+def gershgorin_max(T):
+    return float(np.max(np.diag(T) + np.sum(np.abs(T), axis=1) - np.abs(np.diag(T))))
+
+
+def splitmix64_uniform(n, seed):
+    """Uniform [-1, 1) values from the SplitMix64 generator (Steele, Lea, Flood 2014), counter i."""
+    mask = (1 << 64) - 1
+    out = np.empty(n)
+    for i in range(n):
+        z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & mask
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
+        z = z ^ (z >> 31)
+        out[i] = (z >> 11) * (2.0 ** -53) * 2.0 - 1.0
+    return out
+
+
+class Multigrid:
+    """Stored multigrid hierarchy with frozen Chebyshev bounds and an exact coarse solve."""
+
+    def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
+                 n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True):
+        meshes = hierarchy(mesh) if levels is None else levels
+        self.ops = [SIPG(m, problem, C=C, quad_extra=quad_extra, mass=mass) for m in meshes]
+        self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
+        self.n_cheb, self.Lambda = n_cheb, Lambda
+        self.dinv = [1.0 / op.diagonal() if jacobi else None for op in self.ops[:-1]]
+        A0 = np.column_stack([self.ops[-1].apply(e) for e in np.eye(self.ops[-1].ndof)])
+        self.A0 = 0.5 * (A0 + A0.T)
+        self.chol = scipy.linalg.cho_factor(self.A0)
+        if lam is None:
+            lam = []
+            for op, dinv in zip(self.ops[:-1], self.dinv):
+                b = np.random.default_rng(seed).uniform(-1.0, 1.0, op.ndof)
+                if dinv is None:
+                    _, T = cg_lanczos(op.apply, b, n_eigs)
+                else:  # D^-1 A is similar to the symmetric D^-1/2 A D^-1/2
+                    s = np.sqrt(dinv)
+                    _, T = cg_lanczos(lambda v, op=op, s=s: s * op.apply(s * v), b, n_eigs)
+                lam.append(gershgorin_max(T))
+        self.lam = list(lam)
+
+    @property
+    def nlevels(self):
+        return len(self.ops)
+
+    def smooth(self, level, b, x):
+        return chebyshev(self.ops[level].apply, b, x, self.lam[level], self.Lambda, self.n_cheb,
+                         self.dinv[level])
+
+    def coarse_solve(self, f):
+        return scipy.linalg.cho_solve(self.chol, f)
+
+    def vcycle(self, f):
+        """Alg. 3: z = V(f), from zero initial guesses on every level."""
+        L = self.nlevels - 1
+        fs = [None] * (L + 1)
+        vs = [None] * (L + 1)
+        fs[0] = f
+        for l in range(L):
+            vs[l] = self.smooth(l, fs[l], np.zeros_like(fs[l]))
+            fs[l + 1] = self.transfers[l].restrict(fs[l] - self.ops[l].apply(vs[l]))
+        vs[L] = self.coarse_solve(fs[L])
+        for l in range(L - 1, -1, -1):
+            vs[l] = self.transfers[l].prolong(vs[l + 1]) + vs[l]
+            vs[l] = self.smooth(l, fs[l], vs[l])
+        return vs[0]
+
+
+def fcg(apply, b, precond, u0=None, tol=1e-10, max_iter=200):
+    """Alg. 2 (flexible CG, one-vector truncation); returns (u, iterations, rel. residual history)."""
+    u = np.zeros_like(b) if u0 is None else u0.copy()
+    r = b - apply(u)
+    nb = np.linalg.norm(b)
+    hist = [np.linalg.norm(r) / nb]
+    d = q = None
+    rho = None
+    k = 0
+    while hist[-1] > tol and k < max_iter:
+        v = precond(r)
+        w = apply(v)
+        alpha = v @ r
+        beta = v @ w
+        if k == 0:
+            d, q, rho = v, w, beta
+        else:
+            gamma = v @ q
+            d = v - (gamma / rho) * d
+            q = w - (gamma / rho) * q
+            rho = beta - gamma * gamma / rho
+        u = u + (alpha / rho) * d
+        r = r - (alpha / rho) * q
+        k += 1
+        hist.append(np.linalg.norm(r) / nb)
+    return u, k, hist
+
+
+def pcg(apply, b, precond, u0=None, tol=1e-10, max_iter=200):
+    """Preconditioned CG (textbook); returns (u, iterations, rel. residual history)."""
+    u = np.zeros_like(b) if u0 is None else u0.copy()
+    r = b - apply(u)
+    nb = np.linalg.norm(b)
+    z = precond(r)
+    p = z.copy()
+    rz = r @ z
+    hist = [np.linalg.norm(r) / nb]
+    k = 0
+    while hist[-1] > tol and k < max_iter:
+        Ap = apply(p)
+        alpha = rz / (p @ Ap)
+        u = u + alpha * p
+        r = r - alpha * Ap
+        z = precond(r)
+        rz_new = r @ z
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        k += 1
+        hist.append(np.linalg.norm(r) / nb)
+    return u, k, hist

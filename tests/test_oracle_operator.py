@@ -1,0 +1,126 @@
+"""Pins for the oracle's SIPG operator (Eqs. lh2/Fh2, harald-stiff, temp-E, penaltyparameter).
+
+Each pin is fixed by the mathematics, not by the oracle's own formulas:
+* the matrix-free apply equals a brute-force assembled matrix built from the vector
+  jump/average form of Eq. 20 (different algebra, same bilinear form);
+* symmetry and positive definiteness of the SIPG form with an adequate penalty;
+* A 1 = 0 with Neumann boundaries (constants are in the kernel of the broken
+  gradient and have no jumps), on curved, 2:1 and variable-degree meshes;
+* polynomial consistency: on affine meshes all integrals are exact, SIPG is
+  consistent, so A u_I = F for u in Q_pmin with g = -lap u and g_D = u;
+* L2 convergence of order p + 1 for a smooth solution (the L2 rate of the
+  adjoint-consistent SIPG method; Sec. II.E.1 states the energy-norm rate p).
+"""
+import numpy as np
+import pytest
+
+import meshgen
+from meshgen.problems import polynomial_problem
+from oracle import problems as P
+from oracle.operator import SIPG, assemble_dense
+from oracle.solvers import Multigrid, fcg
+
+MESHES = {
+    "cube_p2": lambda: meshgen.unit_cube(1, 2),
+    "box_2to1_p2": lambda: meshgen.box_grid((1, 1, 1), 1, 2,
+                                            refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+    "hp_var_p": lambda: meshgen.hp_sphere_cube(level=1, p_lo=1, p_hi=3, seed=2, r_cut=0.9),
+    "shell_l1_p2": lambda: meshgen.cubed_sphere_shell(level=1, p=2, zeta_break=0.0, r_out=50.0),
+    "shell_l1_p1": lambda: meshgen.cubed_sphere_shell(level=1, p=1, zeta_break=0.0, r_out=50.0),
+    "skew_affine": lambda: _skew(),
+}
+
+
+def _skew():
+    m = meshgen.box_grid((2, 1, 1), 1, 2)
+    # shear both macros (still affine; faces still match)
+    for i in range(len(m["macro_params"])):
+        a0 = m["macro_params"][i, 3:6].copy()
+        a2 = m["macro_params"][i, 9:12]
+        m["macro_params"][i, 9:12] = a2 + 0.3 * np.array([1.0, 0.5, 0.0]) * a2[2]
+        m["macro_params"][i, 0:3] = m["macro_params"][i, 0:3] + 0.0 * a0
+    return m
+
+
+@pytest.mark.parametrize("name", [k for k in MESHES if k != "shell_l1_p2"])
+def test_matrix_free_equals_assembled_and_spd(name):
+    m = MESHES[name]()
+    op = SIPG(m, meshgen.problem_config1(), C=10.0)
+    A = assemble_dense(op)
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal(op.ndof)
+    y = op.apply(x)
+    assert np.linalg.norm(y - A @ x) <= 1e-13 * np.linalg.norm(A @ x)
+    assert np.max(np.abs(A - A.T)) <= 1e-13 * np.max(np.abs(A))
+    ev = np.linalg.eigvalsh(0.5 * (A + A.T))
+    assert ev.min() > 0
+
+
+@pytest.mark.parametrize("name", ["shell_l1_p2", "hp_var_p", "box_2to1_p2"])
+def test_symmetry_matrix_free(name):
+    op = SIPG(MESHES[name](), meshgen.problem_config3(r0=0.4), C=10.0)
+    rng = np.random.default_rng(3)
+    x, y = rng.standard_normal((2, op.ndof))
+    a, b = x @ op.apply(y), y @ op.apply(x)
+    assert abs(a - b) <= 1e-13 * (abs(a) + abs(b))
+
+
+@pytest.mark.parametrize("name", ["shell_l1_p2", "hp_var_p", "box_2to1_p2", "skew_affine"])
+def test_constants_in_kernel_with_neumann(name):
+    op = SIPG(MESHES[name](), meshgen.problem_config3(r0=0.4), bc_override=2)
+    one = np.ones(op.ndof)
+    ref = np.abs(op.apply(np.random.default_rng(1).standard_normal(op.ndof))).max()
+    assert np.abs(op.apply(one)).max() <= 1e-13 * ref
+
+
+@pytest.mark.parametrize("name,deg", [("cube_p2", 2), ("box_2to1_p2", 2), ("hp_var_p", 1),
+                                      ("skew_affine", 2)])
+def test_polynomial_consistency(name, deg):
+    # sheared cells map Q_p onto a larger space; total degree <= p is preserved by affine maps
+    prob = polynomial_problem(deg, seed=7, total=(name == "skew_affine"))
+    op = SIPG(MESHES[name](), prob)
+    u = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    assert np.linalg.norm(op.apply(u) - F) <= 1e-13 * np.linalg.norm(F)
+
+
+def test_polynomial_consistency_fails_with_planted_sign_error():
+    # a flipped consistency term must break the consistency pin (guards the pin itself)
+    prob = polynomial_problem(2, seed=7)
+    op = SIPG(MESHES["box_2to1_p2"](), prob)
+    for g in op.fgroups:
+        g["mvec_m"] = -g["mvec_m"]
+    u = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    assert np.linalg.norm(op.apply(u) - F) > 1e-6 * np.linalg.norm(F)
+
+
+def test_penalty_length_is_element_size():
+    # uniform cube of N^3 cells on [0,1]^3: h_m = 1/N, sigma = C p^2 N
+    N, p, C = 4, 3, 10.0
+    op = SIPG(meshgen.unit_cube(2, p), meshgen.problem_config1(), C=C)
+    for g in op.fgroups:
+        np.testing.assert_allclose(g["sigma"], C * p * p * N, rtol=1e-14)
+        np.testing.assert_allclose(g["wS"].sum(axis=1), 1.0 / N ** 2, rtol=1e-14)
+
+
+def _solve_sin(level, p):
+    prob = meshgen.problem_config1()
+    mg = Multigrid(meshgen.unit_cube(level, p), prob, n_cheb=4)
+    op = mg.ops[0]
+    u, it, hist = fcg(op.apply, op.rhs(), mg.vcycle, tol=1e-12)
+    return op.l2_error(u, lambda X: P.exact_u(prob, X))
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_l2_convergence_order(p):
+    e1, e2 = _solve_sin(2, p), _solve_sin(3, p)
+    rate = np.log2(e1 / e2)
+    assert abs(rate - (p + 1)) < 0.35, rate
+
+
+@pytest.mark.parametrize("name", ["hp_var_p", "shell_l1_p1", "box_2to1_p2"])
+def test_diagonal_equals_assembled_diagonal(name):
+    op = SIPG(MESHES[name](), meshgen.problem_config3(r0=0.7))
+    A = assemble_dense(op)
+    np.testing.assert_allclose(op.diagonal(), np.diag(A), rtol=1e-13, atol=1e-14 * np.abs(A).max())
