@@ -1,0 +1,198 @@
+"""Benchmark: MG-preconditioned FCG solves of the SIPG operator on one MI355X.
+
+Workload (default): Poisson on the six-patch cubed-sphere shell r in [1, 1e9] (linear radial
+map up to r = 10, inverse-radius compactification beyond), 8^3 cells per patch, innermost
+radial layer refined 2:1, degree p = 5 (1,244,160 DOF), manufactured harmonic solution
+u = 1/r + x z / r^5 with Dirichlet data.  One step = one solve from u = 0 to a relative
+residual of 1e-10 (FP64 flexible CG, V-cycle with Jacobi-Chebyshev smoothing, exact coarse
+solve): every row of the hot path runs inside it.  Printed: one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG operator DOF-applies/s (FP64 vs mixed); solves/s + p99 latency at 1e-10 residual"
+HBM_PEAK_GBS = 8000.0
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n-cheb", type=int, default=4)
+    ap.add_argument("--level", type=int, default=3)
+    ap.add_argument("--p", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported" % args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import meshgen
+    import paper_1907_01572_amd as hp
+
+    dev = torch.device("cuda:0")
+    mesh = meshgen.cubed_sphere_shell(level=args.level, p=args.p)
+    prob = meshgen.problem_config2()
+    ctx = hp.Context(0)
+    t0 = time.time()
+    M = ctx.upload(mesh, build_f32=True)
+    lam = M.setup_smoother(n_cheb=args.n_cheb, jacobi=True)
+    setup_s = time.time() - t0
+    N = M.n_dof[0]
+    F = torch.zeros(N, dtype=torch.float64, device=dev)
+    M.assemble_rhs(prob, F)
+    u = torch.zeros_like(F)
+    stream = torch.cuda.current_stream()
+
+    def solve(prec):
+        u.zero_()
+        return M.solve(F, u, tol=1e-10, max_iter=500, precision=prec)
+
+    for _ in range(args.warmup):
+        solve(hp.PREC_F64)
+    torch.cuda.synchronize()
+    lat = []
+    iters = []
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        st = solve(hp.PREC_F64)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - a) * 1e3)
+        iters.append(st["iterations"])
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ms_per_step = elapsed * 1e3 / args.steps
+    solves_per_s = args.steps / elapsed
+    final_res = st["rel_residual"]
+
+    # mixed precision (FP32 V-cycle inside FP64 FCG)
+    solve(hp.PREC_MIXED)
+    torch.cuda.synchronize()
+    lat_mx, it_mx = [], []
+    a0 = time.perf_counter()
+    for _ in range(args.steps):
+        a = time.perf_counter()
+        stm = solve(hp.PREC_MIXED)
+        torch.cuda.synchronize()
+        lat_mx.append((time.perf_counter() - a) * 1e3)
+        it_mx.append(stm["iterations"])
+    mixed_solves_per_s = args.steps / (time.perf_counter() - a0)
+
+    # operator apply throughput on the fine level, kernel time from HIP events on the stream
+    x64 = torch.randn(N, dtype=torch.float64, device=dev)
+    y64 = torch.zeros_like(x64)
+    x32, y32 = x64.float(), torch.zeros(N, dtype=torch.float32, device=dev)
+    for _ in range(3):
+        M.apply(x64, y64)
+        M.apply(x32, y32)
+    torch.cuda.synchronize()
+    M.timing()
+    M.timing_enable(True)
+    for _ in range(args.apply_reps):
+        M.apply(x64, y64)
+    ms64, n64 = M.timing()
+    for _ in range(args.apply_reps):
+        M.apply(x32, y32)
+    ms32, n32 = M.timing()
+    M.timing_enable(False)
+    apply_ms64 = ms64 / n64
+    apply_ms32 = ms32 / n32
+
+    # algorithmic bytes of one apply (vectors once, stored metric once, records once)
+    ndof = N
+    b_alg64 = M.algorithmic_bytes(0, 8)
+    b_alg32 = M.algorithmic_bytes(0, 4)
+    gbs64 = b_alg64 / (apply_ms64 * 1e-3) / 1e9
+    gbs32 = b_alg32 / (apply_ms32 * 1e-3) / 1e9
+
+    out = {
+        "metric": METRIC,
+        "value": round(solves_per_s, 4),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "cubed-sphere shell r=1..1e9 (compactified), 6x8^3 cells + 2:1 inner layer, "
+                               "p=%d, %d DOF, Poisson, FP64 MG-FCG to 1e-10" % (args.p, ndof),
+                   "elements": M.n_elem[0], "dof": ndof, "levels": M.n_levels, "n_cheb": args.n_cheb},
+        "solve": {"iterations": iters, "final_rel_residual": final_res,
+                  "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                  "setup_s": round(setup_s, 3), "lambda_max": [round(float(v), 4) for v in lam]},
+        "mixed": {"solves_per_s": round(mixed_solves_per_s, 4), "iterations": it_mx,
+                  "final_rel_residual": stm["rel_residual"],
+                  "p50_ms": float(np.percentile(lat_mx, 50)), "p99_ms": float(np.percentile(lat_mx, 99))},
+        "apply": {"dof_applies_per_s_f64": ndof / (apply_ms64 * 1e-3),
+                  "dof_applies_per_s_f32": ndof / (apply_ms32 * 1e-3),
+                  "kernel_ms_f64": apply_ms64, "kernel_ms_f32": apply_ms32,
+                  "alg_bytes_f64": b_alg64, "alg_bytes_f32": b_alg32, "gbs_f64": gbs64, "gbs_f32": gbs32},
+        "roofline": {"bound": "hbm", "achieved": round(gbs64, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(gbs64 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "apply_kernel<double> (fine level)"},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(mesh, prob, ndof, iters, M)
+    print(json.dumps(out))
+    M.free()
+    ctx.close()
+
+
+def cpu_baseline(mesh, prob, ndof, iters, M):
+    """The oracle's matrix-free apply on a bounded sample of the same mesh, on the host."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.operator import SIPG
+
+    rng = np.random.default_rng(0)
+    E = len(mesh["elem_p"])
+    sample = np.sort(rng.choice(E, size=min(E, 192), replace=False))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        op = SIPG(mesh, prob, active=sample)
+        t_setup = time.perf_counter() - t0
+        x = rng.standard_normal(op.ndof)
+        reps = 0
+        t0 = time.perf_counter()
+        while True:
+            op.apply(x)
+            reps += 1
+            if time.perf_counter() - t0 > 10.0 or reps >= 50:
+                break
+        t_apply = (time.perf_counter() - t0) / reps
+    sample_dof = int(np.sum((mesh["elem_p"][sample].astype(np.int64) + 1) ** 3))
+    dof_apply_per_s = sample_dof / t_apply
+    # applies of the fine operator per solve, counted from the GPU solve's structure:
+    # per FCG iteration 1 apply + V-cycle (2 n_cheb - 1 + 1 residual) on the fine level,
+    # coarse levels add ~1/8 each; the host oracle rate is scaled by this count
+    n_cheb = 4
+    per_iter = 1 + (2 * n_cheb - 1) + 1
+    applies = (np.mean(iters) + 1) * per_iter * 8 / 7
+    return {"value": dof_apply_per_s / (ndof * applies), "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "oracle matrix-free apply on %d of %d elements (%d DOF), %d reps, setup %.1fs; "
+                      "%.3e DOF-applies/s scaled by %.0f fine-level applies per solve"
+                      % (len(sample), E, sample_dof, reps, t_setup, dof_apply_per_s, applies),
+            "dof_applies_per_s": dof_apply_per_s}
+
+
+if __name__ == "__main__":
+    main()

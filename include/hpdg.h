@@ -1,0 +1,218 @@
+/*
+ * hpdg: matrix-free SIPG hp-DG elliptic operator and its multigrid-preconditioned
+ * Krylov solve on one AMD MI355X (gfx950).  C ABI.
+ *
+ * The problem follows arXiv:1907.01572:
+ *   - domain: a macro-mesh of mapped cubes refined by octrees with at most 2:1 face
+ *     balance, per-element polynomial degree p (Sec. II.A.1, II.A.2);
+ *   - discrete problem: find u_h in V_h with L_h(u_h, v) = F_h(v) for all v
+ *     (Eqs. lh2, Fh2), written as the linear system L u = F (Eq. semidiscrete) in the
+ *     nodal LGL basis (Eq. Lagrange_Basis), integrals by GL quadrature (Sec. II.A.5);
+ *   - solver: flexible CG (Alg. 2) preconditioned by a multigrid V-cycle (Alg. 3) with
+ *     Chebyshev smoothing (Alg. 4) and spectral bounds from CG (Alg. 5).
+ * The model equation is read as -div(k grad u) + c u = g, u = g_D on Dirichlet faces.
+ *
+ * Conventions shared by every call:
+ *   - Every function returns an int status: HPDG_OK (0) or a negative HPDG_ERR_* code;
+ *     hpdg_last_error() then describes the failure.  No C++ exception crosses the ABI.
+ *   - Device pointers are HIP device addresses (e.g. torch CUDA tensors on ROCm).  The
+ *     caller owns every pointer it passes; the library never frees or retains them
+ *     beyond the call.  Host arrays passed in are copied.
+ *   - ``stream`` is a hipStream_t passed as void* (NULL = the default stream).  Calls
+ *     that take a stream are enqueued on it and return without synchronising, unless
+ *     stated otherwise.
+ *   - Vector layout (a "level vector"): contiguous; elements in the level's element
+ *     order; element e occupies (p_e+1)^3 consecutive entries starting at its dof
+ *     offset (prefix sum of (p+1)^3); inside an element the LGL nodes are ordered
+ *     i + n j + n^2 k (reference axis 0 fastest).  Level 0 is the uploaded mesh, in
+ *     the caller's element order; coarser multigrid levels are 1, 2, ...
+ *   - Precision: HPDG_F64 vectors are double, HPDG_F32 vectors are float.
+ *   - A context is used by one host thread at a time; different contexts are
+ *     independent.
+ */
+#ifndef HPDG_H
+#define HPDG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  HPDG_OK = 0,
+  HPDG_ERR_INVALID_ARG = -1,   /* a NULL or out-of-range argument */
+  HPDG_ERR_INVALID_MESH = -2,  /* unmatched face, 4:1 face, J <= 0, p outside [1, 15] */
+  HPDG_ERR_OOM = -3,           /* device allocation failed or the HBM budget is exceeded */
+  HPDG_ERR_NOT_CONVERGED = -4, /* iteration cap reached before the tolerance */
+  HPDG_ERR_BREAKDOWN = -5,     /* non-positive curvature or a non-finite dot product */
+  HPDG_ERR_HIP = -6,           /* a HIP runtime call failed */
+  HPDG_ERR_UNSUPPORTED = -7    /* a feature not built into this library */
+};
+
+enum { HPDG_F64 = 0, HPDG_F32 = 1 };                 /* vector precision of a call */
+enum { HPDG_PREC_F64 = 0, HPDG_PREC_MIXED = 1 };       /* solve precision: FP64 or FP32 V-cycle */
+enum { HPDG_MAP_AFFINE = 0, HPDG_MAP_SHELL = 1, HPDG_MAP_CUBE_SPHERE = 2 };
+enum { HPDG_BC_INTERIOR = 0, HPDG_BC_DIRICHLET = 1, HPDG_BC_NEUMANN = 2 };
+enum { HPDG_COEF_CONSTANT = 0, HPDG_COEF_RADIAL_STEP = 1 };
+enum { HPDG_RHS_SINSINSIN = 0, HPDG_RHS_SHELL_HARMONIC = 1, HPDG_RHS_RADIAL_STEP = 2,
+       HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4 };
+enum { HPDG_SOLVER_FCG = 0, HPDG_SOLVER_PCG = 1 };
+
+typedef struct hpdg_ctx hpdg_ctx;
+typedef struct hpdg_mesh hpdg_mesh;
+
+/*
+ * Macro-mesh + refinement + degrees (Sec. II.A.1: macro-elements are images of
+ * [-1,1]^3 under analytic maps; fine elements are octree cells of their macro).
+ *   macro_kind[m]        HPDG_MAP_*; macro_params[16 m + i] its parameters:
+ *     AFFINE       x = o + sum_i (xi_i + 1)/2 a_i; params o(3), a0(3), a1(3), a2(3).
+ *     SHELL        cubed-sphere patch; params[0..8] = R (row-major, det +1), [9] radial
+ *                  kind (0 linear, 1 inverse (Eq. inverse_mapping), 2 linear up to
+ *                  zeta_break then inverse), [10] r_in, [11] r_out, [12] zeta_break,
+ *                  [13] r_break; direction v = R (tan(pi xi0/4), tan(pi xi1/4), 1),
+ *                  x = r(xi2) v / |v|.
+ *     CUBE_SPHERE  blend in xi2 of a R (xi0, xi1, 1) (a = params[10]) and the sphere
+ *                  point params[11] v/|v| (R as for SHELL).
+ *   macro_nbr[6 m + f], macro_nbr_face, macro_nbr_orient: neighbour macro across face f
+ *     (f = 2 d + s, axis d, s = 0 at xi_d = -1) or -1 on the boundary; the face it
+ *     meets; orientation o mapping face coordinates (a, b) (tangential axes in
+ *     increasing order) to the neighbour's: (s, t) = o & 1 ? (b, a) : (a, b),
+ *     a' = o & 2 ? -s : s, b' = o & 4 ? -t : t.
+ *   macro_bc[6 m + f]    HPDG_BC_* on boundary faces.
+ *   elem_macro, elem_level, elem_anchor[3 e + d], elem_p: octree cells; the cell
+ *     covers macro coordinates [-1 + 2 a/2^l, -1 + 2 (a+1)/2^l] per axis.
+ */
+typedef struct {
+  int32_t n_macro;
+  const int32_t* macro_kind;
+  const double* macro_params;
+  const int32_t* macro_nbr;
+  const int32_t* macro_nbr_face;
+  const int32_t* macro_nbr_orient;
+  const int32_t* macro_bc;
+  int64_t n_elem;
+  const int32_t* elem_macro;
+  const int32_t* elem_level;
+  const int32_t* elem_anchor;
+  const int32_t* elem_p;
+} hpdg_mesh_desc;
+
+/*
+ * Discretisation parameters.
+ *   penalty_C   C of Eq. penaltyparameter: sigma = C p_m^2 / h_m (default 10).
+ *   quad_extra  extra GL points per axis on curved elements or with a variable
+ *               coefficient (Sec. II.A.5 "higher order GL grids"; default 1).
+ *   coef_kind   HPDG_COEF_*: k = 1, or k = coef_params[1] for |x| < coef_params[0]
+ *               and coef_params[2] otherwise.
+ *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh).
+ *   build_f32   also build FP32 copies of every level (needed by HPDG_F32 calls and
+ *               mixed-precision solves).
+ */
+typedef struct {
+  double penalty_C;
+  int32_t quad_extra;
+  int32_t coef_kind;
+  double coef_params[4];
+  int32_t max_levels;
+  int32_t build_f32;
+} hpdg_disc_params;
+
+typedef struct {
+  int32_t n_levels;
+  int64_t n_elem[32];
+  int64_t n_dof[32];
+  int64_t n_mortar[32];
+  int64_t vgeo_scalars[32];  /* volume metric values stored per level */
+  int64_t mgeo_scalars[32];  /* mortar metric values stored per level */
+  int64_t table_bytes[32];   /* element + mortar records and face lists per level */
+  size_t device_bytes;   /* resident device memory of this mesh */
+} hpdg_mesh_info;
+
+/* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters. */
+typedef struct {
+  int32_t n_cheb;        /* Chebyshev steps per smoothing call (default 4) */
+  int32_t n_eigs;        /* CG steps for the bound (default 15) */
+  double Lambda;         /* lambda_min = lambda_max / Lambda (default 20) */
+  int32_t jacobi;        /* 1: recurrence on D^-1 A (default); 0: the printed form on A */
+  uint64_t seed;         /* SplitMix64 seed of the CG start vector */
+} hpdg_smoother_params;
+
+typedef struct {
+  int32_t solver;        /* HPDG_SOLVER_FCG (Alg. 2) or HPDG_SOLVER_PCG */
+  int32_t precision;     /* HPDG_PREC_F64 or HPDG_PREC_MIXED (FP32 V-cycle) */
+  double tol_rel;        /* stop when |b - A u|_2 <= tol_rel |b|_2 */
+  int32_t max_iter;
+} hpdg_solve_params;
+
+typedef struct {
+  int32_t iterations;
+  double rel_residual;   /* |b - A u| / |b| of the recurrence residual at exit */
+  double solve_ms;       /* wall time of the Krylov loop (host clock, synchronised) */
+  int32_t status;        /* the return code */
+} hpdg_solve_stats;
+
+/* RHS descriptor: analytic source / Dirichlet data (ids as HPDG_RHS_*). */
+typedef struct {
+  int32_t kind;
+  int32_t n_params;
+  const double* params;
+} hpdg_rhs_desc;
+
+/* Create a context on HIP device ``hip_device``; device memory of all its meshes is
+ * limited to ``hbm_budget_bytes`` (0 = no limit). */
+int hpdg_create(hpdg_ctx** out, int hip_device, size_t hbm_budget_bytes);
+/* Free the context and every mesh it still owns. */
+int hpdg_destroy(hpdg_ctx* ctx);
+/* Message of the last failure on this context (never NULL). */
+const char* hpdg_last_error(const hpdg_ctx* ctx);
+
+/* Build the level hierarchy (Sec. II.D.3: surrogate coarsening + 2:1 restoration,
+ * coarse degree = min over children), the mortar tables (Sec. II.A.1), FP64 geometry
+ * at GL points (Eqs. Jacobian, Surface-Jacobian), penalties (Eq. penaltyparameter),
+ * operator tables and transfer maps, and upload them.  Synchronises ``stream``. */
+int hpdg_mesh_upload(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_params* disc,
+                     hpdg_mesh** out, void* stream);
+int hpdg_mesh_info_get(const hpdg_mesh* mesh, hpdg_mesh_info* out);
+/* Cells of a level (host arrays of n_elem[level] entries each; anchor has 3 per cell). */
+int hpdg_level_cells(const hpdg_mesh* mesh, int level, int32_t* macro, int32_t* lvl,
+                     int32_t* anchor, int32_t* p);
+int hpdg_mesh_free(hpdg_mesh* mesh);
+
+/* F = F_h(psi) (Eq. Fh2) for an analytic source g and Dirichlet data g_D = u, written
+ * to the device FP64 vector F_dev of level 0.  Computed on the host in FP64, then
+ * copied (stream-ordered). */
+int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream);
+
+/* y = A_level x (Eq. lh2 applied matrix-free): volume stiffness by sum factorisation,
+ * SIPG fluxes on every mortar with hp-mortar projections (Fig. mortar).  x, y: level
+ * vectors of precision ``prec``; x != y. */
+int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream);
+
+/* Spectral bounds of every smoothed level.  With lambda_max[l] > 0 on entry the value
+ * is used as given (frozen); otherwise it is computed by Alg. 5 and written back.
+ * ``lambda_max`` is a host array of n_levels - 1 entries.  Synchronises ``stream``. */
+int hpdg_setup_smoother(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max,
+                        void* stream);
+/* x <- Chebyshev(x, b) on ``level`` with n_iter steps (Alg. 4, update p = alpha r + beta p). */
+int hpdg_smooth(hpdg_mesh* mesh, int level, int prec, const void* b_dev, void* x_dev, int n_iter,
+                void* stream);
+/* z = V(r): one V-cycle (Alg. 3) from zero initial guesses; level-0 vectors of ``prec``;
+ * coarsest level solved exactly (FP64 Cholesky factor formed at setup). */
+int hpdg_vcycle(hpdg_mesh* mesh, int prec, const void* r_dev, void* z_dev, void* stream);
+/* Solve A u = b (FP64 level-0 vectors).  u is the initial guess on entry (Alg. 2,
+ * r0 = b - A u0) and the solution on exit.  ``stats`` is filled even on failure;
+ * HPDG_ERR_NOT_CONVERGED leaves the last iterate in u.  Synchronises ``stream``. */
+int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b_dev,
+               double* u_dev, hpdg_solve_stats* stats, void* stream);
+
+/* Sum of the kernel time of the last ``hpdg_apply`` calls measured with HIP events on
+ * their stream: enable with on = 1, read and reset with hpdg_apply_timing(). */
+int hpdg_apply_timing_enable(hpdg_mesh* mesh, int on);
+int hpdg_apply_timing(hpdg_mesh* mesh, double* total_ms, int64_t* n_calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

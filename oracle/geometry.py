@@ -28,8 +28,10 @@ def inverse_radial(z, x1, x2, r1, r2):
 def radial(z, zc, par):
     """Radial coordinate of a SHELL macro at reference coordinate z.
 
-    ``zc`` selects the branch of a piecewise map (the element's cell centre), so that
-    the two elements meeting at the break each use their own smooth branch.
+    A piecewise map takes the branch of the point itself; only exactly at the break
+    does ``zc`` (the element's cell centre) decide, so that the two elements meeting there
+    each use their own smooth branch while a coarse cell spanning the break follows the
+    true map at every quadrature point.
     """
     kind = par[..., 9]
     r_in, r_out, zb, rb = par[..., 10], par[..., 11], par[..., 12], par[..., 13]
@@ -42,11 +44,11 @@ def radial(z, zc, par):
     ri, dri = inverse_radial(z, -1.0, 1.0, r_in, r_out)
     r[inv], dr[inv] = ri[inv], dri[inv]
     pw = kind == 2
-    low = pw & (zc <= zb)
+    low = pw & ((z < zb) | ((z == zb) & (zc <= zb)))
     rl = r_in + (z + 1.0) / (zb + 1.0) * (rb - r_in)
     drl = (rb - r_in) / (zb + 1.0) * np.ones_like(z)
     r[low], dr[low] = rl[low], drl[low]
-    high = pw & (zc > zb)
+    high = pw & ~low
     rh, drh = inverse_radial(z, zb, 1.0, rb, r_out)
     r[high], dr[high] = rh[high], drh[high]
     return r, dr

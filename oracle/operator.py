@@ -47,7 +47,10 @@ class SIPG:
     """The discrete operator A (y = A u) and right-hand side F on one cell mesh."""
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, bc_override=None,
-                 mass=None):
+                 mass=None, active=None):
+        """``active``: optional element subset; the operator is then formed only for the
+        rows of those elements (their volume terms and the mortars touching them), so that
+        (A x) restricted to them is exact while the rest of the output stays zero."""
         self.mesh = mesh
         self.problem = problem
         self.C = float(C)
@@ -61,6 +64,10 @@ class SIPG:
         self.kconst = problems.k_is_constant(problem)
         self.affine = geometry.is_affine_macro(mesh["macro_kind"][mesh["elem_macro"]])
         self.mortars = build_mortars(mesh)
+        self.active = None
+        if active is not None:
+            self.active = np.zeros(self.E, bool)
+            self.active[np.asarray(active)] = True
         if bc_override is not None:
             for mt in self.mortars:
                 if mt["ep"] < 0:
@@ -88,6 +95,8 @@ class SIPG:
     def _setup_volume(self):
         groups = {}
         for e in range(self.E):
+            if self.active is not None and not self.active[e]:
+                continue
             groups.setdefault((int(self.n[e]), self.q_volume(e)), []).append(e)
         self.vgroups = []
         for (n, q), elems in sorted(groups.items()):
@@ -136,6 +145,9 @@ class SIPG:
         for mi, mt in enumerate(self.mortars):
             if mt["ep"] < 0 and mt["bc"] != DIRICHLET:
                 continue  # Neumann faces: no operator term
+            if self.active is not None and not (self.active[mt["em"]] or
+                                                (mt["ep"] >= 0 and self.active[mt["ep"]])):
+                continue
             nm = int(self.n[mt["em"]])
             npl = int(self.n[mt["ep"]]) if mt["ep"] >= 0 else 0
             key = (nm, npl, self.q_mortar(mt), mt["fm"], mt["fp"], mt["o"], mt["sub"], mt["bc"])

@@ -1,0 +1,278 @@
+"""hpdg: MI355X-native matrix-free SIPG hp-DG operator and multigrid-preconditioned solve.
+
+Thin ctypes binding of the C ABI in ``include/hpdg.h`` (libhpdg.so, HIP kernels for
+gfx950).  The binding only marshals arguments: every step of the operator, smoother,
+V-cycle and Krylov solve runs in the library's kernels.  Device vectors are torch CUDA
+(ROCm) tensors; streams are torch streams.  Importing this package fails loudly when
+the library has not been built (``python -m paper_1907_01572_amd.build``).
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhpdg.so")
+
+OK = 0
+ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_HIP, ERR_UNSUPPORTED = \
+    -1, -2, -3, -4, -5, -6, -7
+F64, F32 = 0, 1
+PREC_F64, PREC_MIXED = 0, 1
+SOLVER_FCG, SOLVER_PCG = 0, 1
+COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
+RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4}
+
+EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload", "hpdg_mesh_info_get",
+            "hpdg_level_cells", "hpdg_mesh_free", "hpdg_assemble_rhs", "hpdg_apply",
+            "hpdg_setup_smoother", "hpdg_smooth", "hpdg_vcycle", "hpdg_solve",
+            "hpdg_apply_timing_enable", "hpdg_apply_timing"]
+
+
+class HpdgError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("hpdg error %d: %s" % (code, msg))
+        self.code = code
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("n_macro", ctypes.c_int32), ("macro_kind", ctypes.c_void_p),
+                ("macro_params", ctypes.c_void_p), ("macro_nbr", ctypes.c_void_p),
+                ("macro_nbr_face", ctypes.c_void_p), ("macro_nbr_orient", ctypes.c_void_p),
+                ("macro_bc", ctypes.c_void_p), ("n_elem", ctypes.c_int64),
+                ("elem_macro", ctypes.c_void_p), ("elem_level", ctypes.c_void_p),
+                ("elem_anchor", ctypes.c_void_p), ("elem_p", ctypes.c_void_p)]
+
+
+class DiscParams(ctypes.Structure):
+    _fields_ = [("penalty_C", ctypes.c_double), ("quad_extra", ctypes.c_int32),
+                ("coef_kind", ctypes.c_int32), ("coef_params", ctypes.c_double * 4),
+                ("max_levels", ctypes.c_int32), ("build_f32", ctypes.c_int32)]
+
+
+class MeshInfo(ctypes.Structure):
+    _fields_ = [("n_levels", ctypes.c_int32), ("n_elem", ctypes.c_int64 * 32),
+                ("n_dof", ctypes.c_int64 * 32), ("n_mortar", ctypes.c_int64 * 32),
+                ("vgeo_scalars", ctypes.c_int64 * 32), ("mgeo_scalars", ctypes.c_int64 * 32),
+                ("table_bytes", ctypes.c_int64 * 32), ("device_bytes", ctypes.c_size_t)]
+
+
+class SmootherParams(ctypes.Structure):
+    _fields_ = [("n_cheb", ctypes.c_int32), ("n_eigs", ctypes.c_int32), ("Lambda", ctypes.c_double),
+                ("jacobi", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class SolveParams(ctypes.Structure):
+    _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
+class SolveStats(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("rel_residual", ctypes.c_double),
+                ("solve_ms", ctypes.c_double), ("status", ctypes.c_int32)]
+
+
+class RhsDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_params", ctypes.c_int32), ("params", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load_library(path=LIB_PATH):
+    """Load libhpdg.so; raises when it is missing (there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError("libhpdg.so not built: run `python -m paper_1907_01572_amd.build`")
+    lib = ctypes.CDLL(path)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    lib.hpdg_create.argtypes = [ctypes.POINTER(vp), i32, ctypes.c_size_t]
+    lib.hpdg_destroy.argtypes = [vp]
+    lib.hpdg_last_error.argtypes = [vp]
+    lib.hpdg_last_error.restype = ctypes.c_char_p
+    lib.hpdg_mesh_upload.argtypes = [vp, ctypes.POINTER(MeshDesc), ctypes.POINTER(DiscParams),
+                                     ctypes.POINTER(vp), vp]
+    lib.hpdg_mesh_info_get.argtypes = [vp, ctypes.POINTER(MeshInfo)]
+    lib.hpdg_level_cells.argtypes = [vp, i32, vp, vp, vp, vp]
+    lib.hpdg_mesh_free.argtypes = [vp]
+    lib.hpdg_assemble_rhs.argtypes = [vp, ctypes.POINTER(RhsDesc), vp, vp]
+    lib.hpdg_apply.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.hpdg_setup_smoother.argtypes = [vp, ctypes.POINTER(SmootherParams), vp, vp]
+    lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
+    lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
+    lib.hpdg_solve.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, ctypes.POINTER(SolveStats), vp]
+    lib.hpdg_apply_timing_enable.argtypes = [vp, i32]
+    lib.hpdg_apply_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+class Context:
+    """One library context on a HIP device (all device memory of its meshes)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0):
+        self.lib = load_library()
+        self.h = ctypes.c_void_p()
+        rc = self.lib.hpdg_create(ctypes.byref(self.h), int(device), int(hbm_budget_bytes))
+        if rc != OK:
+            raise HpdgError(rc, "hpdg_create failed")
+        self.meshes = []
+
+    def check(self, rc):
+        if rc != OK:
+            raise HpdgError(rc, self.lib.hpdg_last_error(self.h).decode())
+        return rc
+
+    def upload(self, mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False,
+               stream=None):
+        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream)
+
+    def close(self):
+        if self.h:
+            for m in list(self.meshes):
+                m.h = None
+            self.lib.hpdg_destroy(self.h)
+            self.h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def coef_from_problem(problem):
+    """Coefficient descriptor (kind, params) of a meshgen problem."""
+    if problem is not None and problem.get("kind") == "radial_step":
+        return COEF_RADIAL_STEP, list(problem["params"][:3]) + [0.0]
+    return COEF_CONSTANT, [0.0] * 4
+
+
+class Mesh:
+    """An uploaded mesh: level hierarchy, geometry and solver state on the device."""
+
+    def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream):
+        self.ctx, self.lib = ctx, ctx.lib
+        keep = dict(
+            macro_kind=np.ascontiguousarray(mesh["macro_kind"], np.int32),
+            macro_params=np.ascontiguousarray(mesh["macro_params"], np.float64),
+            macro_nbr=np.ascontiguousarray(mesh["macro_nbr"], np.int32),
+            macro_nbr_face=np.ascontiguousarray(mesh["macro_nbr_face"], np.int32),
+            macro_nbr_orient=np.ascontiguousarray(mesh["macro_nbr_orient"], np.int32),
+            macro_bc=np.ascontiguousarray(mesh["macro_bc"], np.int32),
+            elem_macro=np.ascontiguousarray(mesh["elem_macro"], np.int32),
+            elem_level=np.ascontiguousarray(mesh["elem_level"], np.int32),
+            elem_anchor=np.ascontiguousarray(mesh["elem_anchor"], np.int32),
+            elem_p=np.ascontiguousarray(mesh["elem_p"], np.int32))
+        d = MeshDesc()
+        d.n_macro = len(keep["macro_kind"])
+        d.n_elem = len(keep["elem_p"])
+        for k, v in keep.items():
+            setattr(d, k, v.ctypes.data)
+        dp = DiscParams()
+        dp.penalty_C = penalty_C
+        dp.quad_extra = quad_extra
+        kind, params = coef if coef is not None else (COEF_CONSTANT, [0.0] * 4)
+        dp.coef_kind = kind
+        for i in range(4):
+            dp.coef_params[i] = params[i]
+        dp.max_levels = max_levels
+        dp.build_f32 = 1 if build_f32 else 0
+        self.h = ctypes.c_void_p()
+        ctx.check(self.lib.hpdg_mesh_upload(ctx.h, ctypes.byref(d), ctypes.byref(dp),
+                                            ctypes.byref(self.h), _stream(stream)))
+        ctx.meshes.append(self)
+        info = MeshInfo()
+        ctx.check(self.lib.hpdg_mesh_info_get(self.h, ctypes.byref(info)))
+        self.n_levels = info.n_levels
+        self.n_dof = [int(info.n_dof[i]) for i in range(self.n_levels)]
+        self.n_elem = [int(info.n_elem[i]) for i in range(self.n_levels)]
+        self.n_mortar = [int(info.n_mortar[i]) for i in range(self.n_levels)]
+        self.vgeo_scalars = [int(info.vgeo_scalars[i]) for i in range(self.n_levels)]
+        self.mgeo_scalars = [int(info.mgeo_scalars[i]) for i in range(self.n_levels)]
+        self.table_bytes = [int(info.table_bytes[i]) for i in range(self.n_levels)]
+        self.device_bytes = int(info.device_bytes)
+
+    def algorithmic_bytes(self, level=0, scalar=8):
+        """Bytes one apply of ``level`` must move at least once: x read and y written, the
+        stored volume and mortar metric, and the element / mortar records."""
+        return (2 * scalar * self.n_dof[level] + scalar * (self.vgeo_scalars[level] + self.mgeo_scalars[level])
+                + self.table_bytes[level])
+
+    def level_cells(self, level):
+        E = self.n_elem[level]
+        macro, lvl, p = (np.zeros(E, np.int32) for _ in range(3))
+        anchor = np.zeros((E, 3), np.int32)
+        self.ctx.check(self.lib.hpdg_level_cells(self.h, level, macro.ctypes.data, lvl.ctypes.data,
+                                                 anchor.ctypes.data, p.ctypes.data))
+        return dict(elem_macro=macro, elem_level=lvl, elem_anchor=anchor, elem_p=p)
+
+    def assemble_rhs(self, problem, F, stream=None):
+        params = np.ascontiguousarray(problem["params"], np.float64).reshape(-1)
+        r = RhsDesc()
+        r.kind = RHS_IDS[problem["kind"]]
+        r.n_params = len(params)
+        r.params = params.ctypes.data if len(params) else None
+        self.ctx.check(self.lib.hpdg_assemble_rhs(self.h, ctypes.byref(r), _ptr(F), _stream(stream)))
+
+    def apply(self, x, y, level=0, stream=None):
+        prec = F32 if x.dtype.itemsize == 4 else F64
+        self.ctx.check(self.lib.hpdg_apply(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
+
+    def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
+                       stream=None):
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, 1 if jacobi else 0, seed)
+        lam = np.zeros(max(self.n_levels - 1, 1))
+        if lambda_max is not None:
+            lam[:len(lambda_max)] = lambda_max
+        self.ctx.check(self.lib.hpdg_setup_smoother(self.h, ctypes.byref(sp), lam.ctypes.data,
+                                                    _stream(stream)))
+        self.lambda_max = lam[: self.n_levels - 1].copy()
+        return self.lambda_max
+
+    def smooth(self, b, x, level=0, n_iter=4, stream=None):
+        prec = F32 if b.dtype.itemsize == 4 else F64
+        self.ctx.check(self.lib.hpdg_smooth(self.h, level, prec, _ptr(b), _ptr(x), n_iter, _stream(stream)))
+
+    def vcycle(self, r, z, stream=None):
+        prec = F32 if r.dtype.itemsize == 4 else F64
+        self.ctx.check(self.lib.hpdg_vcycle(self.h, prec, _ptr(r), _ptr(z), _stream(stream)))
+
+    def solve(self, b, u, tol=1e-10, max_iter=200, solver=SOLVER_FCG, precision=PREC_F64, stream=None,
+              raise_on_error=True):
+        p = SolveParams(solver, precision, tol, max_iter)
+        st = SolveStats()
+        rc = self.lib.hpdg_solve(self.h, ctypes.byref(p), _ptr(b), _ptr(u), ctypes.byref(st), _stream(stream))
+        if raise_on_error:
+            self.ctx.check(rc)
+        return dict(iterations=st.iterations, rel_residual=st.rel_residual, solve_ms=st.solve_ms,
+                    status=st.status)
+
+    def timing_enable(self, on=True):
+        self.ctx.check(self.lib.hpdg_apply_timing_enable(self.h, 1 if on else 0))
+
+    def timing(self):
+        ms = ctypes.c_double()
+        n = ctypes.c_int64()
+        self.ctx.check(self.lib.hpdg_apply_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+    def free(self):
+        if self.h:
+            self.lib.hpdg_mesh_free(self.h)
+            self.h = None
+            if self in self.ctx.meshes:
+                self.ctx.meshes.remove(self)

@@ -1,0 +1,807 @@
+// C ABI of the hpdg library: contexts, mesh upload, apply / smooth / V-cycle / solve.
+//
+// Solver structure (arXiv:1907.01572): flexible CG (Alg. 2) preconditioned by a V-cycle
+// (Alg. 3) over the stored level hierarchy, Chebyshev smoothing (Alg. 4) with spectral
+// bounds from CG (Alg. 5, computed once per level), exact FP64 coarse solve.  Every
+// step runs in the kernels of kernels.hip, stream-ordered; the host only sequences
+// launches and reads one residual norm per Krylov iteration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/hpdg.h"
+#include "device.hpp"
+#include "setup.hpp"
+
+using namespace hpdg;
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) throw Error(HPDG_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct hpdg_ctx {
+  int device = 0;
+  size_t budget = 0;
+  size_t used = 0;
+  std::string err;
+  std::vector<hpdg_mesh*> meshes;
+};
+
+namespace {
+
+template <typename T>
+struct DevLevel {
+  ElemInfo* einfo = nullptr;
+  MortarInfo* minfo = nullptr;
+  int* fmlist = nullptr;
+  T* vgeo = nullptr;
+  T* mgeo = nullptr;
+  T* dinv = nullptr;
+  TransferInfo* tinfo = nullptr;  // prolongation from level + 1 into this level
+  int* cstart = nullptr;
+  int* clist = nullptr;
+  T *f = nullptr, *v = nullptr, *t = nullptr, *p = nullptr;
+};
+
+}  // namespace
+
+struct hpdg_mesh {
+  hpdg_ctx* ctx = nullptr;
+  MacroMesh mm;
+  DiscParams dp;
+  OpTable tab;
+  std::vector<LevelHost> H;
+  bool has_f32 = false;
+  // device
+  std::vector<void*> allocs;
+  size_t bytes = 0;
+  int* tab_off = nullptr;
+  int *dg_off = nullptr, *w_off = nullptr, *dface_off = nullptr;
+  double* tab64 = nullptr;
+  float* tab32 = nullptr;
+  std::vector<DevLevel<double>> L64;
+  std::vector<DevLevel<float>> L32;
+  double* Ainv64 = nullptr;
+  float* Ainv32 = nullptr;
+  int ncoarse = 0;
+  // smoother
+  std::vector<double> lam;
+  hpdg_smoother_params sp{4, 15, 20.0, 1, 0};
+  bool smoother_ready = false;
+  // Krylov work
+  double *r = nullptr, *vv = nullptr, *w = nullptr, *d = nullptr, *q = nullptr;
+  double *partials = nullptr, *sc = nullptr;
+  double* host_sc = nullptr;  // pinned
+  // apply timing
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
+  double timed_ms = 0;
+  long long timed_calls = 0;
+
+  template <typename T>
+  T* alloc(size_t count) {
+    size_t b = count * sizeof(T);
+    if (b == 0) b = sizeof(T);
+    if (ctx->budget && ctx->used + b > ctx->budget) throw Error(HPDG_ERR_OOM, "HBM budget exceeded");
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, b) != hipSuccess) throw Error(HPDG_ERR_OOM, "hipMalloc failed");
+    allocs.push_back(ptr);
+    bytes += b;
+    ctx->used += b;
+    return static_cast<T*>(ptr);
+  }
+  template <typename T, typename S>
+  T* upload(const std::vector<S>& v, hipStream_t s) {
+    T* ptr = alloc<T>(v.size());
+    if (!v.empty()) {
+      std::vector<T> tmp(v.begin(), v.end());
+      HIPCHK(hipMemcpyAsync(ptr, tmp.data(), tmp.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    return ptr;
+  }
+  template <typename T>
+  T* upload_raw(const std::vector<T>& v, hipStream_t s) {
+    T* ptr = alloc<T>(v.size());
+    if (!v.empty()) {
+      HIPCHK(hipMemcpyAsync(ptr, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+      HIPCHK(hipStreamSynchronize(s));
+    }
+    return ptr;
+  }
+  ~hpdg_mesh() {
+    for (auto& ev : events) {
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    for (void* ptr : allocs) (void)hipFree(ptr);
+    if (host_sc) (void)hipHostFree(host_sc);
+    if (ctx) ctx->used -= std::min(ctx->used, bytes);
+  }
+
+  int nlevels() const { return int(H.size()); }
+
+  TabView tabview() const { return TabView{tab_off, dg_off, w_off, dface_off}; }
+
+  template <typename T>
+  LevelView<T> view(int l) const;
+  template <typename T>
+  TransferView<T> tview(int l) const;  // between level l (fine) and l + 1
+  template <typename T>
+  DevLevel<T>& lev(int l);
+  template <typename T>
+  const T* table() const;
+  template <typename T>
+  const T* ainv() const;
+};
+
+template <>
+DevLevel<double>& hpdg_mesh::lev<double>(int l) { return L64[l]; }
+template <>
+DevLevel<float>& hpdg_mesh::lev<float>(int l) { return L32[l]; }
+template <>
+const double* hpdg_mesh::table<double>() const { return tab64; }
+template <>
+const float* hpdg_mesh::table<float>() const { return tab32; }
+template <>
+const double* hpdg_mesh::ainv<double>() const { return Ainv64; }
+template <>
+const float* hpdg_mesh::ainv<float>() const { return Ainv32; }
+
+template <typename T>
+LevelView<T> hpdg_mesh::view(int l) const {
+  const LevelHost& h = H[l];
+  const DevLevel<T>& d = const_cast<hpdg_mesh*>(this)->lev<T>(l);
+  LevelView<T> v;
+  v.einfo = d.einfo;
+  v.minfo = d.minfo;
+  v.fmlist = d.fmlist;
+  v.vgeo = d.vgeo;
+  v.mgeo = d.mgeo;
+  v.tab = table<T>();
+  v.tv = tabview();
+  v.n_elem = (long long)h.cells.size();
+  v.nmax = h.nmax;
+  v.qmax = h.qmax;
+  v.qmmax = std::max(h.qmmax, 1);
+  return v;
+}
+
+template <typename T>
+TransferView<T> hpdg_mesh::tview(int l) const {
+  const DevLevel<T>& d = const_cast<hpdg_mesh*>(this)->lev<T>(l);
+  TransferView<T> v;
+  v.tinfo = d.tinfo;
+  v.cstart = d.cstart;
+  v.clist = d.clist;
+  v.tab = table<T>();
+  v.tv = tabview();
+  v.n_fine = (long long)H[l].cells.size();
+  v.n_coarse = (long long)H[l + 1].cells.size();
+  v.nmax = std::max(H[l].nmax, H[l + 1].nmax);
+  return v;
+}
+
+namespace {
+
+int fail(hpdg_ctx* ctx, int code, const std::string& msg) {
+  if (ctx) ctx->err = msg;
+  return code;
+}
+
+template <typename F>
+int guarded(hpdg_ctx* ctx, F&& f) {
+  try {
+    f();
+    return HPDG_OK;
+  } catch (const Error& e) {
+    return fail(ctx, e.code, e.what());
+  } catch (const std::bad_alloc&) {
+    return fail(ctx, HPDG_ERR_OOM, "host allocation failed");
+  } catch (const std::exception& e) {
+    return fail(ctx, HPDG_ERR_INVALID_ARG, e.what());
+  }
+}
+
+inline hipStream_t S(void* s) { return static_cast<hipStream_t>(s); }
+
+template <typename T>
+void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
+  LevelHost& h = M->H[l];
+  DevLevel<T>& d = M->lev<T>(l);
+  d.einfo = M->upload_raw(h.einfo, s);
+  d.minfo = M->upload_raw(h.minfo, s);
+  d.fmlist = M->upload_raw(h.fmlist, s);
+  d.vgeo = M->upload<T>(h.vgeo, s);
+  d.mgeo = M->upload<T>(h.mgeo, s);
+  std::vector<double> dinv(h.diag.size());
+  for (size_t i = 0; i < dinv.size(); ++i) dinv[i] = 1.0 / h.diag[i];
+  d.dinv = M->upload<T>(dinv, s);
+  if (l + 1 < M->nlevels()) {
+    d.tinfo = M->upload_raw(h.tinfo, s);
+    d.cstart = M->upload_raw(h.cstart, s);
+    d.clist = M->upload_raw(h.clist, s);
+  }
+  const size_t n = size_t(h.ndof);
+  d.f = M->alloc<T>(n);
+  d.v = M->alloc<T>(n);
+  d.t = M->alloc<T>(n);
+  d.p = M->alloc<T>(n);
+}
+
+template <typename T>
+void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
+  launch_apply<T>(M->view<T>(l), x, y, s);
+}
+
+// Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)
+template <typename T>
+void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, hipStream_t s) {
+  DevLevel<T>& d = M->lev<T>(l);
+  const long long n = M->H[l].ndof;
+  const double lmax = M->lam[l];
+  const double lmin = lmax / M->sp.Lambda;
+  const double c = 0.5 * (lmax - lmin), dd = 0.5 * (lmax + lmin);
+  double alpha = 0;
+  const T* dinv = M->sp.jacobi ? d.dinv : nullptr;
+  for (int k = 1; k <= n_iter; ++k) {
+    const T* Ax = nullptr;
+    if (!(zero && k == 1)) {
+      apply_level<T>(M, l, x, d.t, s);
+      Ax = d.t;
+    }
+    if (k == 1)
+      alpha = 1.0 / dd;
+    else if (k == 2)
+      alpha = 2.0 * dd / (2.0 * dd * dd - c * c);
+    else
+      alpha = 1.0 / (dd - alpha * c * c / 4.0);
+    const double beta = alpha * dd - 1.0;
+    launch_cheb_update<T>(n, b, Ax, dinv, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
+  }
+}
+
+// Alg. 3: z = V(r) on level-0 vectors of type T
+template <typename T>
+void vcycle(hpdg_mesh* M, const T* r0, T* z0, hipStream_t s) {
+  const int L = M->nlevels() - 1;
+  const int nc = M->sp.n_cheb;
+  std::vector<const T*> f(L + 1);
+  std::vector<T*> v(L + 1);
+  for (int l = 0; l <= L; ++l) {
+    f[l] = l == 0 ? r0 : M->lev<T>(l).f;
+    v[l] = l == 0 ? z0 : M->lev<T>(l).v;
+  }
+  for (int l = 0; l < L; ++l) {
+    DevLevel<T>& d = M->lev<T>(l);
+    const long long n = M->H[l].ndof;
+    launch_fill<T>(n, T(0), v[l], s);
+    smooth_level<T>(M, l, f[l], v[l], nc, true, s);
+    apply_level<T>(M, l, v[l], d.t, s);
+    launch_axpby<T>(n, T(1), f[l], T(-1), d.t, s);  // t = f - A v
+    launch_restrict<T>(M->tview<T>(l), d.t, M->lev<T>(l + 1).f, s);
+  }
+  if (L == 0) {
+    launch_dense_matvec<T>(M->ncoarse, M->ainv<T>(), f[0], v[0], s);
+    return;
+  }
+  launch_dense_matvec<T>(M->ncoarse, M->ainv<T>(), f[L], v[L], s);
+  for (int l = L - 1; l >= 0; --l) {
+    launch_prolong_add<T>(M->tview<T>(l), v[l + 1], v[l], s);
+    smooth_level<T>(M, l, f[l], v[l], nc, false, s);
+  }
+}
+
+// host-side dot (synchronising); used at setup and by PCG
+double dot_sync(hpdg_mesh* M, long long n, const double* a, const double* b, hipStream_t s) {
+  launch_dot(n, a, b, M->partials, M->sc + 12, s);
+  HIPCHK(hipMemcpyAsync(M->host_sc + 12, M->sc + 12, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return M->host_sc[12];
+}
+
+uint64_t splitmix64(uint64_t& state) {
+  uint64_t z = (state += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+// Alg. 5 on level l (FP64): returns the Gershgorin bound of the Lanczos tridiagonal
+double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
+  DevLevel<double>& d = M->lev<double>(l);
+  const long long n = M->H[l].ndof;
+  std::vector<double> b(n);
+  uint64_t st = seed;
+  for (long long i = 0; i < n; ++i) b[i] = double(splitmix64(st) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
+  // work vectors: r = f, p = p, Ap = t, x unused (x0 = 0); scaled operator uses v as temp
+  HIPCHK(hipMemcpyAsync(d.f, b.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  const bool jac = M->sp.jacobi != 0;
+  std::vector<double> sq;
+  double* sqrt_dinv = nullptr;
+  if (jac) {
+    sq = M->H[l].diag;
+    for (auto& x : sq) x = 1.0 / std::sqrt(x);
+    sqrt_dinv = M->alloc<double>(n);
+    HIPCHK(hipMemcpyAsync(sqrt_dinv, sq.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  auto op = [&](const double* in, double* out) {
+    if (jac) {
+      launch_scale<double>(n, sqrt_dinv, in, d.v, s);
+      apply_level<double>(M, l, d.v, out, s);
+      launch_scale<double>(n, sqrt_dinv, out, out, s);
+    } else {
+      apply_level<double>(M, l, in, out, s);
+    }
+  };
+  launch_copy<double>(n, d.f, d.p, s);
+  double rr = dot_sync(M, n, d.f, d.f, s);
+  std::vector<double> al, be;
+  for (int k = 0; k < n_eigs; ++k) {
+    op(d.p, d.t);
+    const double pAp = dot_sync(M, n, d.p, d.t, s);
+    const double alpha = rr / pAp;
+    launch_axpby<double>(n, -alpha, d.t, 1.0, d.f, s);  // r -= alpha A p
+    const double rr2 = dot_sync(M, n, d.f, d.f, s);
+    const double beta = rr2 / rr;
+    al.push_back(alpha);
+    be.push_back(beta);
+    launch_axpby<double>(n, 1.0, d.f, beta, d.p, s);  // p = r + beta p
+    rr = rr2;
+    if (!(rr > 0)) break;
+  }
+  const int k = int(al.size());
+  double bound = 0;
+  for (int i = 0; i < k; ++i) {
+    const double diag = 1.0 / al[i] + (i > 0 ? be[i - 1] / al[i - 1] : 0.0);
+    const double lo = i > 0 ? std::sqrt(be[i - 1]) / al[i - 1] : 0.0;
+    const double hi = i + 1 < k ? std::sqrt(be[i]) / al[i] : 0.0;
+    bound = std::max(bound, diag + lo + hi);
+  }
+  return bound;
+}
+
+// exact coarse solve: assemble the coarsest operator column by column, invert (Cholesky)
+void build_coarse(hpdg_mesh* M, hipStream_t s) {
+  const int L = M->nlevels() - 1;
+  const int n = int(M->H[L].ndof);
+  M->ncoarse = n;
+  DevLevel<double>& d = M->lev<double>(L);
+  std::vector<double> A(size_t(n) * n), col(n);
+  for (int j = 0; j < n; ++j) {
+    launch_fill<double>(n, 0.0, d.f, s);
+    const double one = 1.0;
+    HIPCHK(hipMemcpyAsync(d.f + j, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    apply_level<double>(M, L, d.f, d.t, s);
+    HIPCHK(hipMemcpyAsync(col.data(), d.t, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < n; ++i) A[size_t(i) * n + j] = col[i];
+  }
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < i; ++j) {
+      const double m = 0.5 * (A[size_t(i) * n + j] + A[size_t(j) * n + i]);
+      A[size_t(i) * n + j] = A[size_t(j) * n + i] = m;
+    }
+  // Cholesky A = C C^T (lower C), in place in the lower triangle
+  for (int j = 0; j < n; ++j) {
+    double dsum = A[size_t(j) * n + j];
+    for (int k = 0; k < j; ++k) dsum -= A[size_t(j) * n + k] * A[size_t(j) * n + k];
+    if (!(dsum > 0)) throw Error(HPDG_ERR_BREAKDOWN, "coarsest operator is not positive definite");
+    const double cjj = std::sqrt(dsum);
+    A[size_t(j) * n + j] = cjj;
+    for (int i = j + 1; i < n; ++i) {
+      double v = A[size_t(i) * n + j];
+      for (int k = 0; k < j; ++k) v -= A[size_t(i) * n + k] * A[size_t(j) * n + k];
+      A[size_t(i) * n + j] = v / cjj;
+    }
+  }
+  // Ci = C^-1 (lower), then A^-1 = Ci^T Ci
+  std::vector<double> Ci(size_t(n) * n, 0.0);
+  for (int j = 0; j < n; ++j) {
+    Ci[size_t(j) * n + j] = 1.0 / A[size_t(j) * n + j];
+    for (int i = j + 1; i < n; ++i) {
+      double v = 0;
+      for (int k = j; k < i; ++k) v -= A[size_t(i) * n + k] * Ci[size_t(k) * n + j];
+      Ci[size_t(i) * n + j] = v / A[size_t(i) * n + i];
+    }
+  }
+  std::vector<double> Ainv(size_t(n) * n, 0.0);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j <= i; ++j) {
+      double v = 0;
+      for (int k = i; k < n; ++k) v += Ci[size_t(k) * n + i] * Ci[size_t(k) * n + j];
+      Ainv[size_t(i) * n + j] = Ainv[size_t(j) * n + i] = v;
+    }
+  M->Ainv64 = M->upload_raw(Ainv, s);
+  if (M->has_f32) M->Ainv32 = M->upload<float>(Ainv, s);
+}
+
+void check_mesh(const hpdg_mesh_desc* D) {
+  if (!D || D->n_macro <= 0 || D->n_elem <= 0 || !D->macro_kind || !D->macro_params || !D->macro_nbr ||
+      !D->macro_nbr_face || !D->macro_nbr_orient || !D->macro_bc || !D->elem_macro || !D->elem_level ||
+      !D->elem_anchor || !D->elem_p)
+    throw Error(HPDG_ERR_INVALID_ARG, "incomplete mesh description");
+}
+
+}  // namespace
+
+extern "C" {
+
+int hpdg_create(hpdg_ctx** out, int hip_device, size_t hbm_budget_bytes) {
+  if (!out) return HPDG_ERR_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return HPDG_ERR_HIP;
+  if (hip_device < 0 || hip_device >= count) return HPDG_ERR_INVALID_ARG;
+  if (hipSetDevice(hip_device) != hipSuccess) return HPDG_ERR_HIP;
+  auto* c = new hpdg_ctx;
+  c->device = hip_device;
+  c->budget = hbm_budget_bytes;
+  *out = c;
+  return HPDG_OK;
+}
+
+int hpdg_destroy(hpdg_ctx* ctx) {
+  if (!ctx) return HPDG_ERR_INVALID_ARG;
+  (void)hipSetDevice(ctx->device);
+  for (hpdg_mesh* m : ctx->meshes) delete m;
+  delete ctx;
+  return HPDG_OK;
+}
+
+const char* hpdg_last_error(const hpdg_ctx* ctx) {
+  return ctx ? ctx->err.c_str() : "null context";
+}
+
+int hpdg_mesh_upload(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_params* disc,
+                     hpdg_mesh** out, void* stream) {
+  if (!ctx || !out) return fail(ctx, HPDG_ERR_INVALID_ARG, "null argument");
+  *out = nullptr;
+  auto M = std::make_unique<hpdg_mesh>();
+  M->ctx = ctx;
+  return guarded(ctx, [&] {
+    check_mesh(desc);
+    HIPCHK(hipSetDevice(ctx->device));
+    hipStream_t s = S(stream);
+    const int nm = desc->n_macro;
+    M->mm.macros.resize(nm);
+    for (int m = 0; m < nm; ++m) {
+      M->mm.macros[m].kind = desc->macro_kind[m];
+      if (desc->macro_kind[m] < 0 || desc->macro_kind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
+      std::memcpy(M->mm.macros[m].par, desc->macro_params + 16 * m, 16 * sizeof(double));
+    }
+    M->mm.nbr.assign(desc->macro_nbr, desc->macro_nbr + 6 * nm);
+    M->mm.nbr_face.assign(desc->macro_nbr_face, desc->macro_nbr_face + 6 * nm);
+    M->mm.nbr_orient.assign(desc->macro_nbr_orient, desc->macro_nbr_orient + 6 * nm);
+    M->mm.bc.assign(desc->macro_bc, desc->macro_bc + 6 * nm);
+    if (disc) {
+      M->dp.C = disc->penalty_C > 0 ? disc->penalty_C : 10.0;
+      M->dp.quad_extra = disc->quad_extra >= 0 ? disc->quad_extra : 1;
+      M->dp.coef_kind = disc->coef_kind;
+      for (int i = 0; i < 4; ++i) M->dp.coef[i] = disc->coef_params[i];
+      M->has_f32 = disc->build_f32 != 0;
+    }
+    const int max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
+    M->tab.build();
+    // hierarchy
+    LevelHost L0;
+    L0.cells.resize(desc->n_elem);
+    for (long long e = 0; e < desc->n_elem; ++e) {
+      Cell& c = L0.cells[e];
+      c.macro = desc->elem_macro[e];
+      c.level = desc->elem_level[e];
+      c.a[0] = desc->elem_anchor[3 * e];
+      c.a[1] = desc->elem_anchor[3 * e + 1];
+      c.a[2] = desc->elem_anchor[3 * e + 2];
+      c.p = desc->elem_p[e];
+    }
+    M->H.push_back(std::move(L0));
+    while (int(M->H.size()) < max_levels) {
+      LevelHost next;
+      if (!coarsen_cells(M->mm, M->H.back().cells, next.cells)) break;
+      M->H.push_back(std::move(next));
+    }
+    for (auto& h : M->H) {
+      build_level(M->mm, M->dp, M->tab, h);
+      build_diagonal(M->tab, h);
+      for (double dgv : h.diag)
+        if (!(dgv > 0)) throw Error(HPDG_ERR_INVALID_MESH, "non-positive operator diagonal");
+    }
+    for (int l = 0; l + 1 < M->nlevels(); ++l) build_transfer(M->H[l], M->H[l + 1]);
+    // device tables
+    M->tab_off = M->upload_raw(M->tab.off, s);
+    M->dg_off = M->upload_raw(M->tab.dg_off, s);
+    M->w_off = M->upload_raw(M->tab.w_off, s);
+    M->dface_off = M->upload_raw(M->tab.dface_off, s);
+    M->tab64 = M->upload_raw(M->tab.data, s);
+    if (M->has_f32) M->tab32 = M->upload<float>(M->tab.data, s);
+    M->L64.resize(M->nlevels());
+    if (M->has_f32) M->L32.resize(M->nlevels());
+    for (int l = 0; l < M->nlevels(); ++l) {
+      build_device_level<double>(M.get(), l, s);
+      if (M->has_f32) build_device_level<float>(M.get(), l, s);
+    }
+    const long long n0 = M->H[0].ndof;
+    M->r = M->alloc<double>(n0);
+    M->vv = M->alloc<double>(n0);
+    M->w = M->alloc<double>(n0);
+    M->d = M->alloc<double>(n0);
+    M->q = M->alloc<double>(n0);
+    M->partials = M->alloc<double>(3 * kRedBlocks);
+    M->sc = M->alloc<double>(16);
+    HIPCHK(hipHostMalloc((void**)&M->host_sc, 16 * sizeof(double), hipHostMallocDefault));
+    launch_fill<double>(16, 0.0, M->sc, s);
+    build_coarse(M.get(), s);
+    M->lam.assign(M->nlevels(), 0.0);
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    ctx->meshes.push_back(M.get());
+    *out = M.release();
+  });
+}
+
+int hpdg_mesh_info_get(const hpdg_mesh* mesh, hpdg_mesh_info* out) {
+  if (!mesh || !out) return HPDG_ERR_INVALID_ARG;
+  std::memset(out, 0, sizeof(*out));
+  out->n_levels = mesh->nlevels();
+  for (int l = 0; l < mesh->nlevels() && l < 32; ++l) {
+    out->n_elem[l] = (int64_t)mesh->H[l].cells.size();
+    out->n_dof[l] = mesh->H[l].ndof;
+    out->n_mortar[l] = (int64_t)mesh->H[l].mortars.size();
+    out->vgeo_scalars[l] = (int64_t)mesh->H[l].vgeo.size();
+    out->mgeo_scalars[l] = (int64_t)mesh->H[l].mgeo.size();
+    out->table_bytes[l] = (int64_t)(mesh->H[l].einfo.size() * sizeof(ElemInfo) +
+                                    mesh->H[l].minfo.size() * sizeof(MortarInfo) +
+                                    mesh->H[l].fmlist.size() * sizeof(int));
+  }
+  out->device_bytes = mesh->bytes;
+  return HPDG_OK;
+}
+
+int hpdg_level_cells(const hpdg_mesh* mesh, int level, int32_t* macro, int32_t* lvl, int32_t* anchor,
+                     int32_t* p) {
+  if (!mesh || level < 0 || level >= mesh->nlevels()) return HPDG_ERR_INVALID_ARG;
+  const auto& cells = mesh->H[level].cells;
+  for (size_t e = 0; e < cells.size(); ++e) {
+    if (macro) macro[e] = cells[e].macro;
+    if (lvl) lvl[e] = cells[e].level;
+    if (anchor)
+      for (int d = 0; d < 3; ++d) anchor[3 * e + d] = cells[e].a[d];
+    if (p) p[e] = cells[e].p;
+  }
+  return HPDG_OK;
+}
+
+int hpdg_mesh_free(hpdg_mesh* mesh) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  hpdg_ctx* ctx = mesh->ctx;
+  (void)hipSetDevice(ctx->device);
+  ctx->meshes.erase(std::remove(ctx->meshes.begin(), ctx->meshes.end(), mesh), ctx->meshes.end());
+  delete mesh;
+  return HPDG_OK;
+}
+
+int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream) {
+  if (!mesh || !rhs || !F_dev) return HPDG_ERR_INVALID_ARG;
+  return guarded(mesh->ctx, [&] {
+    std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
+    if (rhs->kind < 0 || rhs->kind > 4) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
+    std::vector<double> F;
+    assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);
+    HIPCHK(hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, S(stream)));
+    HIPCHK(hipStreamSynchronize(S(stream)));
+  });
+}
+
+int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream) {
+  if (!mesh || !x_dev || !y_dev || x_dev == y_dev || level < 0 || level >= mesh->nlevels())
+    return mesh ? fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "invalid apply arguments") : HPDG_ERR_INVALID_ARG;
+  if (prec == HPDG_F32 && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  return guarded(mesh->ctx, [&] {
+    hipStream_t s = S(stream);
+    hipEvent_t a = nullptr, b = nullptr;
+    if (mesh->timing) {
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&b));
+      HIPCHK(hipEventRecord(a, s));
+    }
+    if (prec == HPDG_F32)
+      apply_level<float>(mesh, level, static_cast<const float*>(x_dev), static_cast<float*>(y_dev), s);
+    else
+      apply_level<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), s);
+    HIPCHK(hipGetLastError());
+    if (mesh->timing) {
+      HIPCHK(hipEventRecord(b, s));
+      mesh->events.push_back({a, b});
+    }
+  });
+}
+
+int hpdg_apply_timing_enable(hpdg_mesh* mesh, int on) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  mesh->timing = on != 0;
+  return HPDG_OK;
+}
+
+int hpdg_apply_timing(hpdg_mesh* mesh, double* total_ms, int64_t* n_calls) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  return guarded(mesh->ctx, [&] {
+    for (auto& ev : mesh->events) {
+      HIPCHK(hipEventSynchronize(ev.second));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, ev.first, ev.second));
+      mesh->timed_ms += ms;
+      mesh->timed_calls += 1;
+      (void)hipEventDestroy(ev.first);
+      (void)hipEventDestroy(ev.second);
+    }
+    mesh->events.clear();
+    if (total_ms) *total_ms = mesh->timed_ms;
+    if (n_calls) *n_calls = mesh->timed_calls;
+    mesh->timed_ms = 0;
+    mesh->timed_calls = 0;
+  });
+}
+
+int hpdg_setup_smoother(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max,
+                        void* stream) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  return guarded(mesh->ctx, [&] {
+    if (params) {
+      mesh->sp = *params;
+      if (mesh->sp.n_cheb <= 0) mesh->sp.n_cheb = 4;
+      if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
+      if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
+    }
+    hipStream_t s = S(stream);
+    for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
+      if (lambda_max && lambda_max[l] > 0)
+        mesh->lam[l] = lambda_max[l];
+      else
+        mesh->lam[l] = cg_bound(mesh, l, mesh->sp.n_eigs, mesh->sp.seed, s);
+      if (lambda_max) lambda_max[l] = mesh->lam[l];
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    mesh->smoother_ready = true;
+  });
+}
+
+int hpdg_smooth(hpdg_mesh* mesh, int level, int prec, const void* b_dev, void* x_dev, int n_iter,
+                void* stream) {
+  if (!mesh || !b_dev || !x_dev || level < 0 || level >= mesh->nlevels() - 1 || n_iter < 0)
+    return mesh ? fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "invalid smooth arguments") : HPDG_ERR_INVALID_ARG;
+  if (!mesh->smoother_ready) return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
+  if (prec == HPDG_F32 && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  return guarded(mesh->ctx, [&] {
+    if (prec == HPDG_F32)
+      smooth_level<float>(mesh, level, static_cast<const float*>(b_dev), static_cast<float*>(x_dev), n_iter,
+                          false, S(stream));
+    else
+      smooth_level<double>(mesh, level, static_cast<const double*>(b_dev), static_cast<double*>(x_dev),
+                           n_iter, false, S(stream));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int hpdg_vcycle(hpdg_mesh* mesh, int prec, const void* r_dev, void* z_dev, void* stream) {
+  if (!mesh || !r_dev || !z_dev || r_dev == z_dev)
+    return mesh ? fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "invalid vcycle arguments") : HPDG_ERR_INVALID_ARG;
+  if (!mesh->smoother_ready) return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
+  if (prec == HPDG_F32 && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  return guarded(mesh->ctx, [&] {
+    if (prec == HPDG_F32)
+      vcycle<float>(mesh, static_cast<const float*>(r_dev), static_cast<float*>(z_dev), S(stream));
+    else
+      vcycle<double>(mesh, static_cast<const double*>(r_dev), static_cast<double*>(z_dev), S(stream));
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b_dev, double* u_dev,
+               hpdg_solve_stats* stats, void* stream) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!mesh || !params || !b_dev || !u_dev) return HPDG_ERR_INVALID_ARG;
+  if (!mesh->smoother_ready) return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
+  const bool mixed = params->precision == HPDG_PREC_MIXED;
+  if (mixed && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  int status = HPDG_OK;
+  int iters = 0;
+  double rel = 0;
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = guarded(mesh->ctx, [&] {
+    hipStream_t s = S(stream);
+    const long long n = mesh->H[0].ndof;
+    const double nb = std::sqrt(dot_sync(mesh, n, b_dev, b_dev, s));
+    if (!std::isfinite(nb)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite right-hand side");
+    double* r = mesh->r;
+    apply_level<double>(mesh, 0, u_dev, mesh->w, s);
+    launch_copy<double>(n, b_dev, r, s);
+    launch_axpby<double>(n, -1.0, mesh->w, 1.0, r, s);  // r0 = b - A u0
+    if (nb == 0.0) {
+      launch_fill<double>(n, 0.0, u_dev, s);
+      rel = 0.0;
+      return;
+    }
+    double rr = dot_sync(mesh, n, r, r, s);
+    rel = std::sqrt(rr) / nb;
+    auto precond = [&](const double* in, double* out) {
+      if (mixed) {
+        DevLevel<float>& d32 = mesh->L32[0];
+        // level-0 FP32 f / v buffers are free (the V-cycle takes f_0, v_0 as arguments)
+        launch_convert_d2f(n, in, d32.f, s);
+        vcycle<float>(mesh, d32.f, d32.v, s);
+        launch_convert_f2d(n, d32.v, out, s);
+      } else {
+        vcycle<double>(mesh, in, out, s);
+      }
+    };
+    if (params->solver == HPDG_SOLVER_PCG) {
+      // textbook PCG: z = M r, p = z + beta p, alpha = r.z / p.Ap
+      double* z = mesh->vv;
+      double* p = mesh->d;
+      double* Ap = mesh->w;
+      precond(r, z);
+      launch_copy<double>(n, z, p, s);
+      double rz = dot_sync(mesh, n, r, z, s);
+      while (rel > params->tol_rel && iters < params->max_iter) {
+        apply_level<double>(mesh, 0, p, Ap, s);
+        const double pAp = dot_sync(mesh, n, p, Ap, s);
+        if (!(pAp > 0) || !std::isfinite(pAp)) throw Error(HPDG_ERR_BREAKDOWN, "PCG breakdown");
+        const double alpha = rz / pAp;
+        launch_axpby<double>(n, alpha, p, 1.0, u_dev, s);
+        launch_axpby<double>(n, -alpha, Ap, 1.0, r, s);
+        precond(r, z);
+        const double rz2 = dot_sync(mesh, n, r, z, s);
+        launch_axpby<double>(n, 1.0, z, rz2 / rz, p, s);
+        rz = rz2;
+        rr = dot_sync(mesh, n, r, r, s);
+        rel = std::sqrt(rr) / nb;
+        ++iters;
+      }
+    } else {
+      // Alg. 2 with device-resident scalars; one host read of |r|^2 per iteration
+      launch_fill<double>(16, 0.0, mesh->sc, s);
+      while (rel > params->tol_rel && iters < params->max_iter) {
+        const int first = iters == 0 ? 1 : 0;
+        precond(r, mesh->vv);
+        apply_level<double>(mesh, 0, mesh->vv, mesh->w, s);
+        launch_dot3(n, mesh->vv, r, mesh->w, first ? nullptr : mesh->q, mesh->partials, mesh->sc, s);
+        launch_fcg_scalars(mesh->sc, first, s);
+        launch_fcg_update(n, mesh->vv, mesh->w, mesh->d, mesh->q, u_dev, r, mesh->sc, mesh->partials,
+                          first, s);
+        HIPCHK(hipMemcpyAsync(mesh->host_sc, mesh->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        ++iters;
+        if (mesh->host_sc[8] != 0.0) throw Error(HPDG_ERR_BREAKDOWN, "FCG breakdown (rho <= 0 or non-finite)");
+        rr = mesh->host_sc[7];
+        if (!std::isfinite(rr)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite residual");
+        rel = std::sqrt(rr) / nb;
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    HIPCHK(hipGetLastError());
+    if (rel > params->tol_rel) status = HPDG_ERR_NOT_CONVERGED;
+  });
+  auto t1 = std::chrono::steady_clock::now();
+  if (rc == HPDG_OK && status != HPDG_OK) {
+    rc = status;
+    mesh->ctx->err = "iteration cap reached";
+  }
+  if (stats) {
+    stats->iterations = iters;
+    stats->rel_residual = rel;
+    stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    stats->status = rc;
+  }
+  return rc;
+}
+
+}  // extern "C"

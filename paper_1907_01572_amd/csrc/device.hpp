@@ -1,0 +1,84 @@
+// Device-side views of a level and the kernel launchers (kernels.hip).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "host.hpp"
+
+namespace hpdg {
+
+// 1-D table offsets mirrored from OpTable (ints in device memory)
+struct TabView {
+  const int* off;        // [9][kMaxN + 1][kMaxQ + 1]
+  const int* dg_off;     // [kMaxQ + 1]
+  const int* w_off;      // [kMaxQ + 1]
+  const int* dface_off;  // [kMaxN + 1]
+};
+
+template <typename T>
+struct LevelView {
+  const ElemInfo* einfo;
+  const MortarInfo* minfo;
+  const int* fmlist;
+  const T* vgeo;
+  const T* mgeo;
+  const T* tab;
+  TabView tv;
+  long long n_elem;
+  int nmax, qmax, qmmax;
+};
+
+template <typename T>
+struct TransferView {
+  const TransferInfo* tinfo;   // per fine element
+  const int* cstart;           // per coarse element
+  const int* clist;
+  const T* tab;
+  TabView tv;
+  long long n_fine, n_coarse;
+  int nmax;
+};
+
+size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar);
+
+template <typename T>
+void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
+template <typename T>
+void launch_prolong_add(const TransferView<T>& V, const T* uc, T* uf, hipStream_t s);
+template <typename T>
+void launch_restrict(const TransferView<T>& V, const T* rf, T* rc, hipStream_t s);
+
+// vectors
+template <typename T>
+void launch_fill(long long n, T value, T* x, hipStream_t s);
+template <typename T>
+void launch_copy(long long n, const T* x, T* y, hipStream_t s);
+// y = a x + b y
+template <typename T>
+void launch_axpby(long long n, T a, const T* x, T b, T* y, hipStream_t s);
+// r = dinv (b - Ax) (dinv may be null; Ax null means x = 0); p = alpha r + beta p (first: p = alpha r); x += p
+template <typename T>
+void launch_cheb_update(long long n, const T* b, const T* Ax, const T* dinv, T* p, T* x, T alpha,
+                        T beta, int first, hipStream_t s);
+// y = a .* x
+template <typename T>
+void launch_scale(long long n, const T* a, const T* x, T* y, hipStream_t s);
+void launch_convert_d2f(long long n, const double* x, float* y, hipStream_t s);
+void launch_convert_f2d(long long n, const float* x, double* y, hipStream_t s);
+// dense y = A x (row-major n x n)
+template <typename T>
+void launch_dense_matvec(int n, const T* A, const T* x, T* y, hipStream_t s);
+
+// deterministic reductions: out[0..k) = dots, via partials (kRedBlocks * k doubles)
+constexpr int kRedBlocks = 512;
+void launch_dot(long long n, const double* a, const double* b, double* partials, double* out,
+                hipStream_t s);
+// FCG (Alg. 2): dots v.r, v.w, v.q into out[0..3)
+void launch_dot3(long long n, const double* v, const double* r, const double* w, const double* q,
+                 double* partials, double* out, hipStream_t s);
+// FCG scalars and updates; sc = device scalars (see kernels.hip); r.r partials -> sc
+void launch_fcg_scalars(double* sc, int first, hipStream_t s);
+void launch_fcg_update(long long n, const double* v, const double* w, double* d, double* q,
+                       double* u, double* r, double* sc, double* partials, int first, hipStream_t s);
+
+}  // namespace hpdg

@@ -1,0 +1,83 @@
+// Host-side data structures of the hpdg library: 1-D rules, analytic maps, octree
+// topology (mortars, multigrid hierarchy) and the per-level tables that are uploaded.
+#pragma once
+
+#include <cstdint>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+namespace hpdg {
+
+constexpr int kMaxN = 16;        // p <= 15
+constexpr int kMaxQ = 20;        // GL points per axis
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+// ---- 1-D rules (basis.cpp) ------------------------------------------------------
+void gauss_legendre(int q, double* x, double* w);
+void gauss_lobatto(int n, double* x, double* w);
+// L[a*n + i] = l_i(y_a), D[a*n + i] = l_i'(y_a) for Lagrange polynomials on nodes x[n]
+void lagrange_eval(int n, const double* x, int m, const double* y, double* L, double* D);
+
+// ---- macro maps (geom.cpp) ------------------------------------------------------
+struct Macro {
+  int kind;
+  double par[16];
+};
+// x(xi) and J[i][j] = dx_i/dxi_j of a macro at macro coordinates xi; zc picks the branch
+// of a piecewise radial map (the cell centre's xi2)
+void macro_eval(const Macro& M, const double xi[3], double zc, double x[3], double J[3][3]);
+
+// ---- octree topology (topo.cpp) ----------------------------------------------------
+struct Cell {
+  int macro, level, a[3], p;
+};
+
+struct MacroMesh {
+  std::vector<Macro> macros;
+  std::vector<int> nbr, nbr_face, nbr_orient, bc;  // [6 m + f]
+};
+
+struct Mortar {
+  int em, fm, ep, fp;   // minus (finer / lower index) side; ep = -1 on the boundary
+  int orient;           // minus face coordinates -> plus face coordinates
+  int sub;              // -1, or ia + 2 ib: minus face inside the coarser plus face
+  int bc;               // boundary kind (0 interior)
+};
+
+std::vector<Mortar> find_mortars(const MacroMesh& mm, const std::vector<Cell>& cells);
+// one coarsening step: false when nothing coarsens
+bool coarsen_cells(const MacroMesh& mm, const std::vector<Cell>& fine, std::vector<Cell>& coarse);
+// for each fine cell: coarse cell index and child bits (-1 when the cell is identical)
+void parent_cells(const std::vector<Cell>& fine, const std::vector<Cell>& coarse,
+                  std::vector<int>& parent, std::vector<int>& bits);
+
+// ---- element / mortar records shared with the device -----------------------------
+struct ElemInfo {
+  long long off;     // dof offset
+  long long vgeo;    // offset of the volume metric (in scalars)
+  int n, q;          // LGL nodes and GL points per axis
+  int vmode;         // 0: constant metric (affine, 6 values), 1: per GL point (6 q^3 values)
+  int mass;          // 1: a mass coefficient follows the metric (q^3 values)
+  int fstart[6];     // first entry of face f in the face-mortar list
+  int fcnt[6];       // mortars on face f (0: no operator term)
+};
+
+struct MortarInfo {
+  int em, fm, ep, fp;
+  int orient, sub, q, gmode;  // gmode 0: constant per mortar (8 values), 1: per point (8 q^2)
+  int bc, pad;
+  long long geo;              // offset of the mortar metric (in scalars)
+};
+
+struct TransferInfo {         // one per fine element
+  long long foff, coff;       // dof offsets in the fine and coarse level
+  int nf, nc, bits;           // bits: -1 same cell, else child bits (x | y<<1 | z<<2)
+  int pad;
+};
+
+}  // namespace hpdg

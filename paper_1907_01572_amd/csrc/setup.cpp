@@ -1,0 +1,567 @@
+// Host-side setup of a level: FP64 geometry at GL points (Sec. II.A.5, Eqs. Jacobian and
+// Surface-Jacobian), mortar metric and penalty (Eq. penaltyparameter), transfer records
+// (Sec. II.D.6), the operator diagonal and the right-hand side (Eq. Fh2).
+#include "setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+
+namespace hpdg {
+
+// ---------------------------------------------------------------------------------
+void OpTable::build() {
+  off.assign(NKIND * (kMaxN + 1) * (kMaxQ + 1), -1);
+  dg_off.assign(kMaxQ + 1, -1);
+  w_off.assign(kMaxQ + 1, -1);
+  gl_off.assign(kMaxQ + 1, -1);
+  dface_off.assign(kMaxN + 1, -1);
+  data.clear();
+  double xn[kMaxQ + 1], wn[kMaxQ + 1], eta[kMaxQ + 1], wq[kMaxQ + 1], pts[kMaxQ + 1];
+  std::vector<double> L(kMaxQ * kMaxQ), D(kMaxQ * kMaxQ);
+  auto push = [&](int kind, int n, int q, const double* M) {
+    off[(kind * (kMaxN + 1) + n) * (kMaxQ + 1) + q] = int(data.size());
+    data.insert(data.end(), M, M + q * n);
+  };
+  for (int n = 2; n <= kMaxN; ++n) {
+    gauss_lobatto(n, xn, wn);
+    for (int q = 1; q <= kMaxQ; ++q) {
+      gauss_legendre(q, eta, wq);
+      for (int half = 0; half < 3; ++half) {
+        for (int a = 0; a < q; ++a)
+          pts[a] = half == 0 ? eta[a] : 0.5 * (eta[a] + (half == 1 ? -1.0 : 1.0));
+        lagrange_eval(n, xn, q, pts, L.data(), D.data());
+        push(GL_VAL + 2 * half, n, q, L.data());
+        push(GL_DER + 2 * half, n, q, D.data());
+      }
+      if (q >= 2 && q <= kMaxN) {  // prolongation: rows at the LGL nodes of q points
+        double xf[kMaxN + 1], wf[kMaxN + 1];
+        gauss_lobatto(q, xf, wf);
+        for (int half = 0; half < 3; ++half) {
+          for (int a = 0; a < q; ++a)
+            pts[a] = half == 0 ? xf[a] : 0.5 * (xf[a] + (half == 1 ? -1.0 : 1.0));
+          lagrange_eval(n, xn, q, pts, L.data(), D.data());
+          push(PR_FULL + half, n, q, L.data());
+        }
+      }
+    }
+    double ends[2] = {-1.0, 1.0};
+    lagrange_eval(n, xn, 2, ends, L.data(), D.data());
+    dface_off[n] = int(data.size());
+    data.insert(data.end(), D.data(), D.data() + 2 * n);
+  }
+  for (int q = 1; q <= kMaxQ; ++q) {
+    gauss_legendre(q, eta, wq);
+    w_off[q] = int(data.size());
+    data.insert(data.end(), wq, wq + q);
+    gl_off[q] = int(data.size());
+    data.insert(data.end(), eta, eta + q);
+    if (q >= 2) {
+      lagrange_eval(q, eta, q, eta, L.data(), D.data());
+      dg_off[q] = int(data.size());
+      data.insert(data.end(), D.data(), D.data() + q * q);
+    } else {
+      dg_off[q] = int(data.size());
+      data.push_back(0.0);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+bool kconst(const DiscParams& dp) { return dp.coef_kind == 0; }
+
+double coef_k(const DiscParams& dp, const double x[3]) {
+  if (dp.coef_kind == 1) {
+    double r = std::sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+    return r < dp.coef[0] ? dp.coef[1] : dp.coef[2];
+  }
+  return 1.0;
+}
+
+double det3(const double J[3][3]) {
+  return J[0][0] * (J[1][1] * J[2][2] - J[1][2] * J[2][1]) -
+         J[0][1] * (J[1][0] * J[2][2] - J[1][2] * J[2][0]) +
+         J[0][2] * (J[1][0] * J[2][1] - J[1][1] * J[2][0]);
+}
+
+void inv3(const double J[3][3], double Ji[3][3]) {
+  const double d = det3(J);
+  Ji[0][0] = (J[1][1] * J[2][2] - J[1][2] * J[2][1]) / d;
+  Ji[0][1] = (J[0][2] * J[2][1] - J[0][1] * J[2][2]) / d;
+  Ji[0][2] = (J[0][1] * J[1][2] - J[0][2] * J[1][1]) / d;
+  Ji[1][0] = (J[1][2] * J[2][0] - J[1][0] * J[2][2]) / d;
+  Ji[1][1] = (J[0][0] * J[2][2] - J[0][2] * J[2][0]) / d;
+  Ji[1][2] = (J[0][2] * J[1][0] - J[0][0] * J[1][2]) / d;
+  Ji[2][0] = (J[1][0] * J[2][1] - J[1][1] * J[2][0]) / d;
+  Ji[2][1] = (J[0][1] * J[2][0] - J[0][0] * J[2][1]) / d;
+  Ji[2][2] = (J[0][0] * J[1][1] - J[0][1] * J[1][0]) / d;
+}
+
+void cell_eval(const MacroMesh& mm, const Cell& c, const double xi[3], double x[3], double J[3][3]) {
+  const double h = 1.0 / double(1 << c.level);
+  double xm[3];
+  for (int d = 0; d < 3; ++d) xm[d] = -1.0 + (2.0 * c.a[d] + 1.0 + xi[d]) * h;
+  const double zc = -1.0 + (2.0 * c.a[2] + 1.0) * h;
+  double Jm[3][3];
+  macro_eval(mm.macros[c.macro], xm, zc, x, Jm);
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) J[i][j] = Jm[i][j] * h;
+}
+
+namespace {
+
+void face_ref(int f, double a, double b, double xi[3]) {
+  const int d = f >> 1;
+  const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+  xi[d] = (f & 1) ? 1.0 : -1.0;
+  xi[t0] = a;
+  xi[t1] = b;
+}
+
+void plus_coords(int orient, int sub, double s, double t, double& a, double& b) {
+  a = (orient & 1) ? t : s;
+  b = (orient & 1) ? s : t;
+  if (orient & 2) a = -a;
+  if (orient & 4) b = -b;
+  if (sub >= 0) {
+    a = 0.5 * (a + 2.0 * (sub & 1) - 1.0);
+    b = 0.5 * (b + 2.0 * ((sub >> 1) & 1) - 1.0);
+  }
+}
+
+}  // namespace
+
+SideMap side_map(const MortarInfo& M, int side) {
+  SideMap s{0, 0, 0, 0, 0};
+  if (side == 1) {
+    s.swap = M.orient & 1;
+    s.flipA = (M.orient >> 1) & 1;
+    s.flipB = (M.orient >> 2) & 1;
+    s.halfA = M.sub < 0 ? 0 : 1 + (M.sub & 1);
+    s.halfB = M.sub < 0 ? 0 : 1 + ((M.sub >> 1) & 1);
+  }
+  return s;
+}
+
+// ---------------------------------------------------------------------------------
+void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, LevelHost& L) {
+  const size_t E = L.cells.size();
+  L.mortars = find_mortars(mm, L.cells);
+  const bool kc = kconst(dp);
+  L.einfo.assign(E, ElemInfo{});
+  L.vgeo.clear();
+  L.nmax = L.qmax = L.qmmax = 0;
+  long long off = 0;
+  double eta[kMaxQ + 1], wq[kMaxQ + 1];
+  for (size_t e = 0; e < E; ++e) {
+    const Cell& c = L.cells[e];
+    if (c.p < 1 || c.p > kMaxN - 1) throw Error(-2, "degree outside [1, 15]");
+    ElemInfo& I = L.einfo[e];
+    const bool affine = mm.macros[c.macro].kind == 0;
+    I.n = c.p + 1;
+    I.q = I.n + ((affine && kc) ? 0 : dp.quad_extra);
+    if (I.q > kMaxQ) throw Error(-2, "too many quadrature points");
+    I.off = off;
+    off += (long long)I.n * I.n * I.n;
+    I.vmode = (affine && kc) ? 0 : 1;
+    I.mass = 0;
+    I.vgeo = (long long)L.vgeo.size();
+    L.nmax = std::max(L.nmax, I.n);
+    L.qmax = std::max(L.qmax, I.q);
+    double x[3], J[3][3], Ji[3][3];
+    if (I.vmode == 0) {
+      double xi[3] = {0, 0, 0};
+      cell_eval(mm, c, xi, x, J);
+      const double dj = det3(J);
+      if (!(dj > 0)) throw Error(-2, "non-positive Jacobian determinant");
+      inv3(J, Ji);
+      const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+      for (int m = 0; m < 6; ++m) {
+        double g = 0;
+        for (int i = 0; i < 3; ++i) g += Ji[pr[m][0]][i] * Ji[pr[m][1]][i];
+        L.vgeo.push_back(dj * g);
+      }
+    } else {
+      const int q = I.q, q3 = q * q * q;
+      gauss_legendre(q, eta, wq);
+      const size_t base = L.vgeo.size();
+      L.vgeo.resize(base + 6 * size_t(q3));
+      for (int cc = 0; cc < q; ++cc)
+        for (int b = 0; b < q; ++b)
+          for (int a = 0; a < q; ++a) {
+            double xi[3] = {eta[a], eta[b], eta[cc]};
+            cell_eval(mm, c, xi, x, J);
+            const double dj = det3(J);
+            if (!(dj > 0)) throw Error(-2, "non-positive Jacobian determinant");
+            inv3(J, Ji);
+            const double s = wq[a] * wq[b] * wq[cc] * dj * coef_k(dp, x);
+            const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+            const int idx = a + q * (b + q * cc);
+            for (int m = 0; m < 6; ++m) {
+              double g = 0;
+              for (int i = 0; i < 3; ++i) g += Ji[pr[m][0]][i] * Ji[pr[m][1]][i];
+              L.vgeo[base + size_t(m) * q3 + idx] = s * g;
+            }
+          }
+    }
+  }
+  L.ndof = off;
+
+  // mortars
+  const size_t M = L.mortars.size();
+  L.minfo.assign(M, MortarInfo{});
+  L.mgeo.clear();
+  std::vector<std::vector<int>> lists(E * 6);
+  for (size_t mi = 0; mi < M; ++mi) {
+    const Mortar& mt = L.mortars[mi];
+    MortarInfo& I = L.minfo[mi];
+    I.em = mt.em; I.fm = mt.fm; I.ep = mt.ep; I.fp = mt.fp;
+    I.orient = mt.orient; I.sub = mt.sub; I.bc = mt.bc; I.pad = 0;
+    const Cell& cm = L.cells[mt.em];
+    const bool interior = mt.ep >= 0;
+    if (!interior && mt.bc != 1) {  // Neumann: no operator term
+      I.q = 0; I.gmode = 0; I.geo = -1;
+      continue;
+    }
+    const int nm = cm.p + 1;
+    const int np = interior ? L.cells[mt.ep].p + 1 : 0;
+    const bool curved = mm.macros[cm.macro].kind != 0 ||
+                        (interior && mm.macros[L.cells[mt.ep].macro].kind != 0);
+    const int pm = std::max(nm, np) - 1;
+    I.q = std::max(nm, np) + ((curved || !kc) ? dp.quad_extra : 0);
+    if (I.q > kMaxQ) throw Error(-2, "too many mortar quadrature points");
+    I.gmode = (curved || !kc) ? 1 : 0;
+    I.geo = (long long)L.mgeo.size();
+    L.qmmax = std::max(L.qmmax, I.q);
+    lists[size_t(mt.em) * 6 + mt.fm].push_back(int(mi) << 1);
+    if (interior) lists[size_t(mt.ep) * 6 + mt.fp].push_back((int(mi) << 1) | 1);
+    const int q = I.q;
+    gauss_legendre(q, eta, wq);
+    const int npts = I.gmode ? q * q : 1;
+    const size_t base = L.mgeo.size();
+    L.mgeo.resize(base + 8 * size_t(npts));
+    const int dmn = mt.fm >> 1;
+    const double sgn = (mt.fm & 1) ? 1.0 : -1.0;
+    for (int pidx = 0; pidx < npts; ++pidx) {
+      const int c = pidx % q, d = pidx / q;
+      const double s = I.gmode ? eta[c] : 0.0, t = I.gmode ? eta[d] : 0.0;
+      double xim[3], x[3], J[3][3], Ji[3][3];
+      face_ref(mt.fm, s, t, xim);
+      cell_eval(mm, cm, xim, x, J);
+      inv3(J, Ji);
+      const double dj = det3(J);
+      double nr = std::sqrt(Ji[dmn][0] * Ji[dmn][0] + Ji[dmn][1] * Ji[dmn][1] + Ji[dmn][2] * Ji[dmn][2]);
+      double nh[3] = {sgn * Ji[dmn][0] / nr, sgn * Ji[dmn][1] / nr, sgn * Ji[dmn][2] / nr};
+      const double S = dj * nr;
+      double h = 2.0 / nr;
+      const double kx = I.gmode ? coef_k(dp, x) : 1.0;
+      double mminus[3], mplus[3] = {0, 0, 0};
+      for (int r = 0; r < 3; ++r)
+        mminus[r] = kx * (Ji[r][0] * nh[0] + Ji[r][1] * nh[1] + Ji[r][2] * nh[2]);
+      if (interior) {
+        double a, b, xip[3], xp[3], Jp[3][3], Jpi[3][3];
+        plus_coords(mt.orient, mt.sub, s, t, a, b);
+        face_ref(mt.fp, a, b, xip);
+        cell_eval(mm, L.cells[mt.ep], xip, xp, Jp);
+        inv3(Jp, Jpi);
+        const int dp_ = mt.fp >> 1;
+        const double nrp = std::sqrt(Jpi[dp_][0] * Jpi[dp_][0] + Jpi[dp_][1] * Jpi[dp_][1] +
+                                     Jpi[dp_][2] * Jpi[dp_][2]);
+        h = std::min(h, 2.0 / nrp);
+        for (int r = 0; r < 3; ++r)
+          mplus[r] = -kx * (Jpi[r][0] * nh[0] + Jpi[r][1] * nh[1] + Jpi[r][2] * nh[2]);
+      }
+      const double sigma = dp.C * pm * pm / h * kx;
+      const double wS = I.gmode ? wq[c] * wq[d] * S : S;
+      double vals[8] = {mminus[0], mminus[1], mminus[2], mplus[0], mplus[1], mplus[2], wS, sigma};
+      for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
+    }
+  }
+  L.fmlist.clear();
+  for (size_t e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      auto& l = lists[e * 6 + f];
+      L.einfo[e].fstart[f] = int(L.fmlist.size());
+      L.einfo[e].fcnt[f] = int(l.size());
+      L.fmlist.insert(L.fmlist.end(), l.begin(), l.end());
+    }
+  (void)T;
+}
+
+void build_transfer(LevelHost& fine, const LevelHost& coarse) {
+  std::vector<int> parent, bits;
+  parent_cells(fine.cells, coarse.cells, parent, bits);
+  const size_t E = fine.cells.size();
+  fine.tinfo.resize(E);
+  std::vector<int> cnt(coarse.cells.size() + 1, 0);
+  for (size_t e = 0; e < E; ++e) {
+    TransferInfo& t = fine.tinfo[e];
+    t.foff = fine.einfo[e].off;
+    t.coff = coarse.einfo[parent[e]].off;
+    t.nf = fine.einfo[e].n;
+    t.nc = coarse.einfo[parent[e]].n;
+    t.bits = bits[e];
+    t.pad = 0;
+    if (t.nc > t.nf) throw Error(-2, "coarse degree above the fine degree");
+    cnt[parent[e] + 1]++;
+  }
+  fine.cstart.assign(coarse.cells.size() + 1, 0);
+  for (size_t K = 0; K < coarse.cells.size(); ++K) fine.cstart[K + 1] = fine.cstart[K] + cnt[K + 1];
+  fine.clist.assign(E, 0);
+  std::vector<int> fill(fine.cstart.begin(), fine.cstart.end() - 1);
+  for (size_t e = 0; e < E; ++e) fine.clist[fill[parent[e]]++] = int(e);
+}
+
+// ---------------------------------------------------------------------------------
+void build_diagonal(const OpTable& T, LevelHost& L) {
+  L.diag.assign(size_t(L.ndof), 0.0);
+  const double* td = T.data.data();
+  std::vector<double> t1, t2;
+  for (size_t e = 0; e < L.einfo.size(); ++e) {
+    const ElemInfo& I = L.einfo[e];
+    const int n = I.n, q = I.q, q3 = q * q * q;
+    const double* B = td + T.index(OpTable::GL_VAL, n, q);
+    const double* Dt = td + T.index(OpTable::GL_DER, n, q);
+    const double* w = td + T.w_off[q];
+    const double* G = L.vgeo.data() + I.vgeo;
+    double* out = L.diag.data() + I.off;
+    const double* fac[2] = {B, Dt};
+    const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+    t1.assign(size_t(q) * q * n, 0.0);
+    t2.assign(size_t(q) * n * n, 0.0);
+    for (int m = 0; m < 6; ++m) {
+      const int d0 = pr[m][0], d1 = pr[m][1];
+      const double mult = d0 == d1 ? 1.0 : 2.0;
+      // factor along axis x of phi_d phi_d' : derivative where the axis is d or d'
+      const double* X0 = fac[d0 == 0]; const double* X1 = fac[d1 == 0];
+      const double* Y0 = fac[d0 == 1]; const double* Y1 = fac[d1 == 1];
+      const double* Z0 = fac[d0 == 2]; const double* Z1 = fac[d1 == 2];
+      auto g = [&](int idx) {
+        if (I.vmode == 0) {
+          const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
+          return G[m] * w[a] * w[b] * w[c];
+        }
+        return G[size_t(m) * q3 + idx];
+      };
+      // t1[c][b][i] = sum_a X0[a][i] X1[a][i] g[c][b][a]
+      for (int cb = 0; cb < q * q; ++cb)
+        for (int i = 0; i < n; ++i) {
+          double s = 0;
+          for (int a = 0; a < q; ++a) s += X0[a * n + i] * X1[a * n + i] * g(cb * q + a);
+          t1[size_t(cb) * n + i] = s;
+        }
+      // t2[c][j][i] = sum_b Y0[b][j] Y1[b][j] t1[c][b][i]
+      for (int c = 0; c < q; ++c)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            double s = 0;
+            for (int b = 0; b < q; ++b) s += Y0[b * n + j] * Y1[b * n + j] * t1[(size_t(c) * q + b) * n + i];
+            t2[(size_t(c) * n + j) * n + i] = s;
+          }
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            double s = 0;
+            for (int c = 0; c < q; ++c) s += Z0[c * n + k] * Z1[c * n + k] * t2[(size_t(c) * n + j) * n + i];
+            out[(k * n + j) * n + i] += mult * s;
+          }
+    }
+  }
+  // faces: psi^2 sigma and the consistency/symmetry self terms, face nodes only
+  for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
+    const MortarInfo& M = L.minfo[mi];
+    if (M.q == 0) continue;
+    const int q = M.q;
+    const bool interior = M.ep >= 0;
+    const double factor = interior ? 1.0 : 2.0;
+    const double* wq = td + T.w_off[q];
+    const double* mg = L.mgeo.data() + M.geo;
+    const int npts = M.gmode ? q * q : 1;
+    for (int side = 0; side < (interior ? 2 : 1); ++side) {
+      const int e = side ? M.ep : M.em, f = side ? M.fp : M.fm;
+      const ElemInfo& I = L.einfo[e];
+      const int n = I.n, d = f >> 1, t0 = d == 0 ? 1 : 0, t1_ = d == 2 ? 1 : 2;
+      const SideMap sm = side_map(M, side);
+      const double* La = td + T.index(OpTable::GL_VAL + 2 * sm.halfA, n, q);
+      const double* Da = td + T.index(OpTable::GL_DER + 2 * sm.halfA, n, q);
+      const double* Lb = td + T.index(OpTable::GL_VAL + 2 * sm.halfB, n, q);
+      const double* Db = td + T.index(OpTable::GL_DER + 2 * sm.halfB, n, q);
+      const double* dface = td + T.dface_off[n] + ((f & 1) ? n : 0);
+      const int kf = (f & 1) ? n - 1 : 0;
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0;
+          for (int y = 0; y < q; ++y)
+            for (int x = 0; x < q; ++x) {
+              const int c = sm.swap ? y : x, dd = sm.swap ? x : y;
+              const int rho = c + q * dd;
+              const int ra = sm.flipA ? q - 1 - x : x, rb = sm.flipB ? q - 1 - y : y;
+              const int p = M.gmode ? rho : 0;
+              const double wS = M.gmode ? mg[6 * npts + p] : wq[c] * wq[dd] * mg[6];
+              const double sig = mg[7 * npts + p];
+              const double ma = mg[(3 * side + t0) * npts + p];
+              const double mb = mg[(3 * side + t1_) * npts + p];
+              const double mn = mg[(3 * side + d) * npts + p];
+              const double la = La[ra * n + i], lb = Lb[rb * n + j];
+              const double psi = la * lb;
+              const double gn = ma * Da[ra * n + i] * lb + mb * la * Db[rb * n + j] + mn * psi * dface[kf];
+              s += wS * (sig * psi * psi - factor * psi * gn);
+            }
+          int idx[3];
+          idx[d] = kf; idx[t0] = i; idx[t1_] = j;
+          L.diag[size_t(I.off) + (idx[2] * n + idx[1]) * n + idx[0]] += s;
+        }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------
+namespace {
+
+double exact_u(int kind, const std::vector<double>& P, const double x[3]) {
+  const double X = x[0], Y = x[1], Z = x[2];
+  switch (kind) {
+    case 0: return std::sin(M_PI * X) * std::sin(M_PI * Y) * std::sin(M_PI * Z);
+    case 1: {
+      const double r = std::sqrt(X * X + Y * Y + Z * Z);
+      return 1.0 / r + P[0] * X * Z / (r * r * r * r * r);
+    }
+    case 2: {
+      const double r2 = X * X + Y * Y + Z * Z;
+      if (std::sqrt(r2) < P[0]) return r2 / P[1] + P[0] * P[0] * (1.0 / P[2] - 1.0 / P[1]);
+      return r2 / P[2];
+    }
+    case 3: {
+      const int K = int(std::lround(std::cbrt(double(P.size()))));
+      double u = 0;
+      for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b)
+          for (int c = 0; c < K; ++c)
+            u += P[(a * K + b) * K + c] * std::pow(X, a) * std::pow(Y, b) * std::pow(Z, c);
+      return u;
+    }
+    default: return 0.0;
+  }
+}
+
+double source(int kind, const std::vector<double>& P, const double x[3]) {
+  const double X = x[0], Y = x[1], Z = x[2];
+  switch (kind) {
+    case 0: return 3.0 * M_PI * M_PI * exact_u(0, P, x);
+    case 1: return 0.0;
+    case 2: return -6.0;
+    case 3: {
+      const int K = int(std::lround(std::cbrt(double(P.size()))));
+      double g = 0;
+      for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b)
+          for (int c = 0; c < K; ++c) {
+            const double C = P[(a * K + b) * K + c];
+            if (a >= 2) g -= C * a * (a - 1) * std::pow(X, a - 2) * std::pow(Y, b) * std::pow(Z, c);
+            if (b >= 2) g -= C * b * (b - 1) * std::pow(X, a) * std::pow(Y, b - 2) * std::pow(Z, c);
+            if (c >= 2) g -= C * c * (c - 1) * std::pow(X, a) * std::pow(Y, b) * std::pow(Z, c - 2);
+          }
+      return g;
+    }
+    case 4: {
+      double g = 0;
+      for (size_t r = 0; r + 4 < P.size(); r += 5) {
+        const double dx = X - P[r + 1], dy = Y - P[r + 2], dz = Z - P[r + 3], s = P[r + 4];
+        g += P[r] * std::exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s * s));
+      }
+      return g;
+    }
+    default: return 0.0;
+  }
+}
+
+}  // namespace
+
+void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
+                  int kind, const std::vector<double>& P, std::vector<double>& F) {
+  F.assign(size_t(L.ndof), 0.0);
+  const double* td = T.data.data();
+  std::vector<double> gq, t1, t2;
+  for (size_t e = 0; e < L.einfo.size(); ++e) {
+    const ElemInfo& I = L.einfo[e];
+    const int n = I.n, q = I.q;
+    const double* B = td + T.index(OpTable::GL_VAL, n, q);
+    const double* w = td + T.w_off[q];
+    const double* eta = td + T.gl_off[q];
+    gq.assign(size_t(q) * q * q, 0.0);
+    for (int c = 0; c < q; ++c)
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          double xi[3] = {eta[a], eta[b], eta[c]}, x[3], J[3][3];
+          cell_eval(mm, L.cells[e], xi, x, J);
+          gq[(c * q + b) * q + a] = w[a] * w[b] * w[c] * det3(J) * source(kind, P, x);
+        }
+    t1.assign(size_t(q) * q * n, 0.0);
+    t2.assign(size_t(q) * n * n, 0.0);
+    for (int cb = 0; cb < q * q; ++cb)
+      for (int i = 0; i < n; ++i) {
+        double s = 0;
+        for (int a = 0; a < q; ++a) s += B[a * n + i] * gq[cb * q + a];
+        t1[size_t(cb) * n + i] = s;
+      }
+    for (int c = 0; c < q; ++c)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0;
+          for (int b = 0; b < q; ++b) s += B[b * n + j] * t1[(size_t(c) * q + b) * n + i];
+          t2[(size_t(c) * n + j) * n + i] = s;
+        }
+    for (int k = 0; k < n; ++k)
+      for (int j = 0; j < n; ++j)
+        for (int i = 0; i < n; ++i) {
+          double s = 0;
+          for (int c = 0; c < q; ++c) s += B[c * n + k] * t2[(size_t(c) * n + j) * n + i];
+          F[size_t(I.off) + (k * n + j) * n + i] += s;
+        }
+  }
+  // Dirichlet faces: int g_D (sigma psi - k n.grad psi)
+  for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
+    const MortarInfo& M = L.minfo[mi];
+    if (M.q == 0 || M.ep >= 0) continue;
+    const int q = M.q;
+    const ElemInfo& I = L.einfo[M.em];
+    const int n = I.n, f = M.fm, d = f >> 1, t0 = d == 0 ? 1 : 0, t1_ = d == 2 ? 1 : 2;
+    const double* La = td + T.index(OpTable::GL_VAL, n, q);
+    const double* Da = td + T.index(OpTable::GL_DER, n, q);
+    const double* wq = td + T.w_off[q];
+    const double* eta = td + T.gl_off[q];
+    const double* dface = td + T.dface_off[n] + ((f & 1) ? n : 0);
+    const double* mg = L.mgeo.data() + M.geo;
+    const int npts = M.gmode ? q * q : 1;
+    const int kf = (f & 1) ? n - 1 : 0;
+    for (int y = 0; y < q; ++y)
+      for (int x = 0; x < q; ++x) {
+        const int rho = x + q * y, p = M.gmode ? rho : 0;
+        double xi[3], xx[3], J[3][3];
+        xi[d] = (f & 1) ? 1.0 : -1.0;
+        xi[t0] = eta[x];
+        xi[t1_] = eta[y];
+        cell_eval(mm, L.cells[M.em], xi, xx, J);
+        const double gd = exact_u(kind, P, xx);
+        const double wS = M.gmode ? mg[6 * npts + p] : wq[x] * wq[y] * mg[6];
+        const double A = wS * mg[7 * npts + p] * gd;
+        const double Bc = -wS * gd;
+        const double ma = mg[t0 * npts + p], mb = mg[t1_ * npts + p], mn = mg[d * npts + p];
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            const double la = La[x * n + i], lb = La[y * n + j];
+            const double face = A * la * lb + Bc * (ma * Da[x * n + i] * lb + mb * la * Da[y * n + j]);
+            int idx[3];
+            idx[t0] = i; idx[t1_] = j;
+            for (int k = 0; k < n; ++k) {
+              idx[d] = k;
+              double v = Bc * mn * la * lb * dface[k];
+              if (k == kf) v += face;
+              F[size_t(I.off) + (idx[2] * n + idx[1]) * n + idx[0]] += v;
+            }
+          }
+      }
+  }
+  (void)dp;
+}
+
+}  // namespace hpdg

@@ -1,0 +1,72 @@
+// Per-level host tables (geometry, mortars, transfers, diagonal) built at upload time.
+#pragma once
+
+#include <vector>
+
+#include "host.hpp"
+
+namespace hpdg {
+
+struct DiscParams {
+  double C = 10.0;
+  int quad_extra = 1;
+  int coef_kind = 0;
+  double coef[4] = {0, 0, 0, 0};
+};
+
+// 1-D operator tables, indexed by (kind, n, q); every matrix is row-major [q][n].
+struct OpTable {
+  enum Kind { GL_VAL = 0, GL_DER = 1, GLLO_VAL = 2, GLLO_DER = 3, GLHI_VAL = 4, GLHI_DER = 5,
+              PR_FULL = 6, PR_LO = 7, PR_HI = 8, NKIND = 9 };
+  std::vector<double> data;
+  std::vector<int> off;        // [NKIND][kMaxN + 1][kMaxQ + 1]
+  std::vector<int> dg_off;     // GL collocation derivative [q][q], by q
+  std::vector<int> w_off;      // GL weights, by q
+  std::vector<int> gl_off;     // GL nodes, by q
+  std::vector<int> dface_off;  // l_i'(-1) then l_i'(+1), by n
+  int index(int kind, int n, int q) const { return off[(kind * (kMaxN + 1) + n) * (kMaxQ + 1) + q]; }
+  void build();
+};
+
+struct LevelHost {
+  std::vector<Cell> cells;
+  std::vector<Mortar> mortars;
+  std::vector<ElemInfo> einfo;
+  std::vector<MortarInfo> minfo;
+  std::vector<int> fmlist;       // (mortar << 1) | side, grouped per element face
+  std::vector<double> vgeo, mgeo;
+  std::vector<double> diag;
+  long long ndof = 0;
+  int nmax = 0, qmax = 0, qmmax = 0;
+  // prolongation from the next coarser level: one record per element of this level
+  std::vector<TransferInfo> tinfo;
+  // restriction gathers: for each coarser element, the elements of this level inside it
+  std::vector<int> cstart, clist;
+};
+
+bool kconst(const DiscParams& dp);
+double coef_k(const DiscParams& dp, const double x[3]);
+
+// element map: x, J at element reference point xi
+void cell_eval(const MacroMesh& mm, const Cell& c, const double xi[3], double x[3], double J[3][3]);
+double det3(const double J[3][3]);
+void inv3(const double J[3][3], double Ji[3][3]);
+
+// fill einfo / minfo / fmlist / vgeo / mgeo for a level (cells set)
+void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, LevelHost& L);
+// transfer records between a fine level and the next coarser one
+void build_transfer(LevelHost& fine, const LevelHost& coarse);
+// diagonal of the level operator (Jacobi smoothing)
+void build_diagonal(const OpTable& T, LevelHost& L);
+
+// right-hand side F_h (Eq. Fh2) on level 0
+void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
+                  int kind, const std::vector<double>& params, std::vector<double>& F);
+
+// one-side mortar map: rows of the 1-D matrices along the own face axes
+struct SideMap {
+  int swap, flipA, flipB, halfA, halfB;  // half: 0 full, 1 lower, 2 upper
+};
+SideMap side_map(const MortarInfo& M, int side);
+
+}  // namespace hpdg

@@ -1,0 +1,50 @@
+"""Helpers shared by the GPU parity tests: contexts, level matching, tolerances."""
+import numpy as np
+
+import meshgen
+import paper_1907_01572_amd as hp
+
+# FP64 apply parity (relative L2 over the output vector) on well-conditioned geometry.
+TOL_APPLY = 1e-12
+# Compactified shell layers (radial stretch dr/dzeta : r up to ~2e8 at r_out = 1e9): the
+# tangential components of J^-1 n are rounding noise of relative size eps * (dr/dzeta)/r
+# in both implementations; the bound below is that noise (2e-8) diluted by the share
+# of those faces in the output, measured at 1e-12 .. 1e-11.
+TOL_APPLY_COMPACTIFIED = 1e-10
+
+
+def coef_of(problem):
+    return hp.coef_from_problem(problem)
+
+
+def dof_perm(lib_cells, oracle_mesh):
+    """Index array: library dof i of a level corresponds to oracle dof perm[i]."""
+    key = {(int(oracle_mesh["elem_macro"][e]), int(oracle_mesh["elem_level"][e]),
+            *map(int, oracle_mesh["elem_anchor"][e])): e for e in range(len(oracle_mesh["elem_p"]))}
+    n = oracle_mesh["elem_p"].astype(np.int64) + 1
+    off = np.concatenate([[0], np.cumsum(n ** 3)])
+    out = []
+    for e in range(len(lib_cells["elem_p"])):
+        k = (int(lib_cells["elem_macro"][e]), int(lib_cells["elem_level"][e]),
+             *map(int, lib_cells["elem_anchor"][e]))
+        eo = key[k]
+        assert oracle_mesh["elem_p"][eo] == lib_cells["elem_p"][e]
+        out.append(np.arange(off[eo], off[eo + 1]))
+    return np.concatenate(out)
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+MESHES = {
+    "cube_l2_p3": (lambda: meshgen.unit_cube(2, 3), meshgen.problem_config1()),
+    "box_2to1_p3": (lambda: meshgen.box_grid((2, 1, 1), 1, 3,
+                                             refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+                    meshgen.problem_config1()),
+    "hp_k": (lambda: meshgen.hp_sphere_cube(level=2, p_lo=1, p_hi=5, seed=2, r_cut=0.6),
+             meshgen.problem_config3(r0=0.6)),
+    "shell_l2_p3_r1e3": (lambda: meshgen.cubed_sphere_shell(level=2, p=3, r_out=1e3),
+                         meshgen.problem_config2()),
+    "shell_l2_p4_r1e9": (lambda: meshgen.cubed_sphere_shell(level=2, p=4), meshgen.problem_config2()),
+}
