@@ -130,12 +130,20 @@ typedef struct {
   size_t device_bytes;   /* resident device memory of this mesh */
 } hpdg_mesh_info;
 
-/* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters. */
+/* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters.
+ * ``scaling`` preconditions the smoother's residual, r = M^-1 (b - A x):
+ *   HPDG_SMOOTH_NONE   M = I (the printed form of Alg. 4);
+ *   HPDG_SMOOTH_POINT  M = diag(A) (point Jacobi);
+ *   HPDG_SMOOTH_BLOCK  M = the element-diagonal blocks A_ee (element-block Jacobi; their
+ *                      inverses are formed on the device at setup, (p+1)^6 values per
+ *                      element and level).
+ * The bound of Alg. 5 is then taken for M^-1 A (preconditioned CG with the same M). */
+enum { HPDG_SMOOTH_NONE = 0, HPDG_SMOOTH_POINT = 1, HPDG_SMOOTH_BLOCK = 2 };
 typedef struct {
   int32_t n_cheb;        /* Chebyshev steps per smoothing call (default 4) */
   int32_t n_eigs;        /* CG steps for the bound (default 15) */
   double Lambda;         /* lambda_min = lambda_max / Lambda (default 20) */
-  int32_t jacobi;        /* 1: recurrence on D^-1 A (default); 0: the printed form on A */
+  int32_t scaling;       /* HPDG_SMOOTH_* (default HPDG_SMOOTH_POINT) */
   uint64_t seed;         /* SplitMix64 seed of the CG start vector */
 } hpdg_smoother_params;
 

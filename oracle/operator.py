@@ -328,6 +328,44 @@ class SIPG:
         return np.sqrt(err2)
 
 
+def element_blocks(op):
+    """Diagonal blocks A_ee (element with itself) of the operator, one dense matrix per element.
+
+    The volume term of the element plus, for every mortar it touches, its own-side block
+    (the four-block face term of ``assemble_dense`` restricted to trial = test = this side).
+    """
+    blocks = [np.zeros((int(n) ** 3, int(n) ** 3)) for n in op.n]
+    for g in op.vgroups:
+        n, q = g["n"], g["q"]
+        eta, w = rules.gl(q)
+        xi = np.stack(np.meshgrid(eta, eta, eta, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+        V, D = _basis_at(n, xi)
+        W = np.einsum("c,b,a->cba", w, w, w).reshape(-1)
+        for e in g["elems"]:
+            x, J = geometry.element_map(op.mesh, np.full(len(xi), e), xi)
+            Ji = np.linalg.inv(J)
+            grad = np.einsum("pdi,dpa->pai", Ji, D)
+            blocks[e] += np.einsum("p,pai,pbi->ba", W * np.linalg.det(J) * op.k(x), grad, grad)
+            if op.mass is not None:
+                blocks[e] += np.einsum("p,pa,pb->ba", W * np.linalg.det(J) * op.mass(x), V, V)
+    for g in op.fgroups:
+        wS, kx, sig = g["wS"], g["kx"], g["sigma"]
+        sides = [("Vm", "Dm", "mvec_m", "em")]
+        if "ep" in g:
+            sides.append(("Vp", "Dp", "mvec_p", "ep"))
+        half = 0.5 if "ep" in g else 1.0
+        for V, D, mv, el in sides:
+            psi = g[V]
+            for i, e in enumerate(g[el]):
+                gn = np.einsum("pd,dpa->pa", g[mv][i], g[D])   # n.grad psi at the points
+                wk = wS[i] * kx[i]
+                blk = (np.einsum("p,pa,pb->ba", wS[i] * sig[i], psi, psi)
+                       - half * np.einsum("p,pa,pb->ba", wk, psi, gn)
+                       - half * np.einsum("p,pa,pb->ba", wk, gn, psi))
+                blocks[e] += blk
+    return blocks
+
+
 def assemble_dense(op):
     """Brute-force dense matrix A[beta, alpha] = L(psi_alpha, psi_beta) for tiny meshes.
 

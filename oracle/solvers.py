@@ -5,9 +5,10 @@
   transpose (Eq. temp-G).
 * Chebyshev smoother (Alg. 4) with the update p <- alpha r + beta p (the sign that
   reproduces the Chebyshev polynomial; the printed minus sign diverges).
-  Optionally (the default here) the residual is scaled by the inverse diagonal of A,
-  i.e. the same recurrence on D^-1 A; the printed, unscaled form is jacobi=False.
-* CG spectral bound (Alg. 5): CG steps give the Lanczos tridiagonal of Eq. tridiag
+  Optionally the residual is preconditioned by the inverse diagonal (point Jacobi) or
+  the inverse element-diagonal blocks (block Jacobi) of A, i.e. the same recurrence on
+  M^-1 A; the printed, unpreconditioned form is smoother="none".
+* CG spectral bound (Alg. 5; preconditioned CG with the smoother's M): CG steps give the Lanczos tridiagonal of Eq. tridiag
   (diagonal 1/alpha_k + beta_{k-1}/alpha_{k-1}, off-diagonal -sqrt(beta_k)/alpha_k);
   lambda_max is the Gershgorin bound of the full tridiagonal.  It is computed once per
   level and frozen (the V-cycle is then a fixed symmetric operator).
@@ -21,7 +22,7 @@ import scipy.linalg
 
 from . import rules
 from .mesh import hierarchy, parent_map
-from .operator import SIPG
+from .operator import SIPG, element_blocks
 
 
 class Transfer:
@@ -68,12 +69,12 @@ class Transfer:
         return rc
 
 
-def chebyshev(apply, b, x, lam_max, Lambda, n_iter, dinv=None):
+def chebyshev(apply, b, x, lam_max, Lambda, n_iter, minv=None):
     """Alg. 4 with frozen lambda_max: n_iter Chebyshev steps on [lam_max/Lambda, lam_max].
 
-    With ``dinv`` (inverse diagonal of A) the residual is scaled, r = D^-1 (b - A x): the
-    same Chebyshev recurrence applied to D^-1 A (point-Jacobi-preconditioned Chebyshev);
-    lam_max is then a bound of the spectrum of D^-1 A.
+    With ``minv`` (the inverse of a diagonal or element-block-diagonal part M of A, as a
+    callable) the residual is preconditioned, r = M^-1 (b - A x): the same Chebyshev
+    recurrence applied to M^-1 A; lam_max is then a bound of the spectrum of M^-1 A.
     """
     lam_min = lam_max / Lambda
     c = 0.5 * (lam_max - lam_min)
@@ -83,8 +84,8 @@ def chebyshev(apply, b, x, lam_max, Lambda, n_iter, dinv=None):
     alpha = 0.0
     for k in range(1, n_iter + 1):
         r = b - apply(x)
-        if dinv is not None:
-            r = dinv * r
+        if minv is not None:
+            r = minv(r)
         if k == 1:
             alpha = 1.0 / d
         elif k == 2:
@@ -97,24 +98,30 @@ def chebyshev(apply, b, x, lam_max, Lambda, n_iter, dinv=None):
     return x
 
 
-def cg_lanczos(apply, b, n_iter, x=None):
-    """Alg. 5: n_iter CG steps; returns (x, T) with the Lanczos tridiagonal T of Eq. tridiag."""
+def cg_lanczos(apply, b, n_iter, x=None, minv=None):
+    """Alg. 5: n_iter CG steps; returns (x, T) with the Lanczos tridiagonal T of Eq. tridiag.
+
+    With ``minv`` the steps are preconditioned CG (z = M^-1 r, r.z in place of r.r), whose
+    coefficients give the Lanczos tridiagonal of M^-1 A.
+    """
     x = np.zeros_like(b) if x is None else x.copy()
     r = b - apply(x)
-    p = r.copy()
-    rr = r @ r
+    z = r if minv is None else minv(r)
+    p = z.copy()
+    rz = r @ z
     alphas, betas = [], []
     for _ in range(n_iter):
         Ap = apply(p)
-        alpha = rr / (p @ Ap)
+        alpha = rz / (p @ Ap)
         x = x + alpha * p
         r = r - alpha * Ap
-        rr_new = r @ r
-        beta = rr_new / rr
+        z = r if minv is None else minv(r)
+        rz_new = r @ z
+        beta = rz_new / rz
         alphas.append(alpha)
         betas.append(beta)
-        p = r + beta * p
-        rr = rr_new
+        p = z + beta * p
+        rz = rz_new
     k = len(alphas)
     T = np.zeros((k, k))
     for i in range(k):
@@ -145,26 +152,41 @@ class Multigrid:
     """Stored multigrid hierarchy with frozen Chebyshev bounds and an exact coarse solve."""
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
-                 n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True):
+                 n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None):
+        """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi) or "block"
+        (element-block Jacobi); ``jacobi`` selects "point" / "none" when it is not given."""
         meshes = hierarchy(mesh) if levels is None else levels
         self.ops = [SIPG(m, problem, C=C, quad_extra=quad_extra, mass=mass) for m in meshes]
         self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
         self.n_cheb, self.Lambda = n_cheb, Lambda
-        self.dinv = [1.0 / op.diagonal() if jacobi else None for op in self.ops[:-1]]
+        self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")
+        self.minv = [self._make_minv(op) for op in self.ops[:-1]]
         A0 = np.column_stack([self.ops[-1].apply(e) for e in np.eye(self.ops[-1].ndof)])
         self.A0 = 0.5 * (A0 + A0.T)
         self.chol = scipy.linalg.cho_factor(self.A0)
         if lam is None:
             lam = []
-            for op, dinv in zip(self.ops[:-1], self.dinv):
+            for op, minv in zip(self.ops[:-1], self.minv):
                 b = np.random.default_rng(seed).uniform(-1.0, 1.0, op.ndof)
-                if dinv is None:
-                    _, T = cg_lanczos(op.apply, b, n_eigs)
-                else:  # D^-1 A is similar to the symmetric D^-1/2 A D^-1/2
-                    s = np.sqrt(dinv)
-                    _, T = cg_lanczos(lambda v, op=op, s=s: s * op.apply(s * v), b, n_eigs)
+                _, T = cg_lanczos(op.apply, b, n_eigs, minv=minv)
                 lam.append(gershgorin_max(T))
         self.lam = list(lam)
+
+    def _make_minv(self, op):
+        if self.smoother == "point":
+            dinv = 1.0 / op.diagonal()
+            return lambda r: dinv * r
+        if self.smoother == "block":
+            inv = [np.linalg.inv(B) for B in element_blocks(op)]
+            off = op.offsets
+
+            def apply_blocks(r):
+                z = np.empty_like(r)
+                for e, Bi in enumerate(inv):
+                    z[off[e]:off[e + 1]] = Bi @ r[off[e]:off[e + 1]]
+                return z
+            return apply_blocks
+        return None
 
     @property
     def nlevels(self):
@@ -172,7 +194,7 @@ class Multigrid:
 
     def smooth(self, level, b, x):
         return chebyshev(self.ops[level].apply, b, x, self.lam[level], self.Lambda, self.n_cheb,
-                         self.dinv[level])
+                         self.minv[level])
 
     def coarse_solve(self, f):
         return scipy.linalg.cho_solve(self.chol, f)

@@ -21,6 +21,7 @@ F64, F32 = 0, 1
 PREC_F64, PREC_MIXED = 0, 1
 SOLVER_FCG, SOLVER_PCG = 0, 1
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
+SMOOTHERS = {"none": 0, "point": 1, "block": 2}
 RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4}
 
 EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload", "hpdg_mesh_info_get",
@@ -59,7 +60,7 @@ class MeshInfo(ctypes.Structure):
 
 class SmootherParams(ctypes.Structure):
     _fields_ = [("n_cheb", ctypes.c_int32), ("n_eigs", ctypes.c_int32), ("Lambda", ctypes.c_double),
-                ("jacobi", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("scaling", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class SolveParams(ctypes.Structure):
@@ -233,8 +234,10 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_apply(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
 
     def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
-                       stream=None):
-        sp = SmootherParams(n_cheb, n_eigs, Lambda, 1 if jacobi else 0, seed)
+                       smoother=None, stream=None):
+        """``smoother``: "none", "point" or "block" (default: "point" if jacobi else "none")."""
+        kind = smoother if smoother is not None else ("point" if jacobi else "none")
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed)
         lam = np.zeros(max(self.n_levels - 1, 1))
         if lambda_max is not None:
             lam[:len(lambda_max)] = lambda_max

@@ -32,7 +32,8 @@ def build(verbose=False, jobs=6):
             _wait(procs)
             procs = []
     _wait(procs)
-    cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", OUT + ".tmp"] + objs
+    cmd = [HIPCC, "-shared", "--offload-arch=gfx950", "-o", OUT + ".tmp"] + objs + \
+        ["-L/opt/rocm/lib", "-lrocsolver", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     r = subprocess.run(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout.decode())

@@ -6,6 +6,8 @@
 // step runs in the kernels of kernels.hip, stream-ordered; the host only sequences
 // launches and reads one residual norm per Krylov iteration.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <algorithm>
 #include <chrono>
@@ -49,6 +51,8 @@ struct DevLevel {
   int* cstart = nullptr;
   int* clist = nullptr;
   T *f = nullptr, *v = nullptr, *t = nullptr, *p = nullptr;
+  long long* boff = nullptr;  // element-block Jacobi: offsets of the inverse blocks
+  T* binv = nullptr;
 };
 
 }  // namespace
@@ -74,8 +78,9 @@ struct hpdg_mesh {
   int ncoarse = 0;
   // smoother
   std::vector<double> lam;
-  hpdg_smoother_params sp{4, 15, 20.0, 1, 0};
+  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0};
   bool smoother_ready = false;
+  rocblas_handle blas = nullptr;  // batched Cholesky of the element blocks (setup only)
   // Krylov work
   double *r = nullptr, *vv = nullptr, *w = nullptr, *d = nullptr, *q = nullptr;
   double *partials = nullptr, *sc = nullptr;
@@ -124,6 +129,7 @@ struct hpdg_mesh {
     }
     for (void* ptr : allocs) (void)hipFree(ptr);
     if (host_sc) (void)hipHostFree(host_sc);
+    if (blas) rocblas_destroy_handle(blas);
     if (ctx) ctx->used -= std::min(ctx->used, bytes);
   }
 
@@ -172,6 +178,7 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.nmax = h.nmax;
   v.qmax = h.qmax;
   v.qmmax = std::max(h.qmmax, 1);
+  v.self_only = 0;
   return v;
 }
 
@@ -251,7 +258,8 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   const double lmin = lmax / M->sp.Lambda;
   const double c = 0.5 * (lmax - lmin), dd = 0.5 * (lmax + lmin);
   double alpha = 0;
-  const T* dinv = M->sp.jacobi ? d.dinv : nullptr;
+  const T* dinv = M->sp.scaling == HPDG_SMOOTH_POINT ? d.dinv : nullptr;
+  const bool block = M->sp.scaling == HPDG_SMOOTH_BLOCK;
   for (int k = 1; k <= n_iter; ++k) {
     const T* Ax = nullptr;
     if (!(zero && k == 1)) {
@@ -265,7 +273,10 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
     else
       alpha = 1.0 / (dd - alpha * c * c / 4.0);
     const double beta = alpha * dd - 1.0;
-    launch_cheb_update<T>(n, b, Ax, dinv, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
+    if (block)
+      launch_block_cheb<T>(M->view<T>(l), d.boff, d.binv, b, Ax, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
+    else
+      launch_cheb_update<T>(n, b, Ax, dinv, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
   }
 }
 
@@ -322,41 +333,33 @@ double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
   std::vector<double> b(n);
   uint64_t st = seed;
   for (long long i = 0; i < n; ++i) b[i] = double(splitmix64(st) >> 11) * 0x1.0p-53 * 2.0 - 1.0;
-  // work vectors: r = f, p = p, Ap = t, x unused (x0 = 0); scaled operator uses v as temp
+  // preconditioned CG with the smoother's M (x0 = 0): r = f, z = v, p = p, A p = t
   HIPCHK(hipMemcpyAsync(d.f, b.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
-  const bool jac = M->sp.jacobi != 0;
-  std::vector<double> sq;
-  double* sqrt_dinv = nullptr;
-  if (jac) {
-    sq = M->H[l].diag;
-    for (auto& x : sq) x = 1.0 / std::sqrt(x);
-    sqrt_dinv = M->alloc<double>(n);
-    HIPCHK(hipMemcpyAsync(sqrt_dinv, sq.data(), n * sizeof(double), hipMemcpyHostToDevice, s));
-  }
-  auto op = [&](const double* in, double* out) {
-    if (jac) {
-      launch_scale<double>(n, sqrt_dinv, in, d.v, s);
-      apply_level<double>(M, l, d.v, out, s);
-      launch_scale<double>(n, sqrt_dinv, out, out, s);
-    } else {
-      apply_level<double>(M, l, in, out, s);
-    }
+  auto precond = [&](const double* r, double* z) {
+    if (M->sp.scaling == HPDG_SMOOTH_POINT)
+      launch_scale<double>(n, d.dinv, r, z, s);
+    else if (M->sp.scaling == HPDG_SMOOTH_BLOCK)
+      launch_block_apply<double>(M->view<double>(l), d.boff, d.binv, r, z, s);
+    else
+      launch_copy<double>(n, r, z, s);
   };
-  launch_copy<double>(n, d.f, d.p, s);
-  double rr = dot_sync(M, n, d.f, d.f, s);
+  precond(d.f, d.v);
+  launch_copy<double>(n, d.v, d.p, s);
+  double rz = dot_sync(M, n, d.f, d.v, s);
   std::vector<double> al, be;
   for (int k = 0; k < n_eigs; ++k) {
-    op(d.p, d.t);
+    apply_level<double>(M, l, d.p, d.t, s);
     const double pAp = dot_sync(M, n, d.p, d.t, s);
-    const double alpha = rr / pAp;
+    const double alpha = rz / pAp;
     launch_axpby<double>(n, -alpha, d.t, 1.0, d.f, s);  // r -= alpha A p
-    const double rr2 = dot_sync(M, n, d.f, d.f, s);
-    const double beta = rr2 / rr;
+    precond(d.f, d.v);
+    const double rz2 = dot_sync(M, n, d.f, d.v, s);
+    const double beta = rz2 / rz;
     al.push_back(alpha);
     be.push_back(beta);
-    launch_axpby<double>(n, 1.0, d.f, beta, d.p, s);  // p = r + beta p
-    rr = rr2;
-    if (!(rr > 0)) break;
+    launch_axpby<double>(n, 1.0, d.v, beta, d.p, s);  // p = z + beta p
+    rz = rz2;
+    if (!(rz > 0)) break;
   }
   const int k = int(al.size());
   double bound = 0;
@@ -367,6 +370,79 @@ double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
     bound = std::max(bound, diag + lo + hi);
   }
   return bound;
+}
+
+// element-block Jacobi: A_ee of every element of level l (column j of all blocks from one
+// apply with neighbours taken as zero), then their inverses by batched Cholesky (rocSOLVER)
+void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
+  DevLevel<double>& d = M->lev<double>(l);
+  if (d.binv) return;
+  const LevelHost& h = M->H[l];
+  const size_t E = h.cells.size();
+  std::vector<long long> boff(E + 1, 0);
+  for (size_t e = 0; e < E; ++e) {
+    const long long N = (long long)h.einfo[e].n * h.einfo[e].n * h.einfo[e].n;
+    boff[e + 1] = boff[e] + N * N;
+  }
+  d.boff = M->upload_raw(boff, s);
+  double* B = M->alloc<double>(size_t(boff[E]));
+  LevelView<double> V = M->view<double>(l);
+  V.self_only = 1;
+  launch_fill<double>(h.ndof, 0.0, d.f, s);
+  const int nmax3 = h.nmax * h.nmax * h.nmax;
+  for (int j = 0; j < nmax3; ++j) {
+    launch_set_unit<double>(V, j, 1.0, d.f, s);
+    launch_apply<double>(V, d.f, d.t, s);
+    launch_gather_column<double>(V, j, d.t, d.boff, B, s);
+    launch_set_unit<double>(V, j, 0.0, d.f, s);
+  }
+  if (!M->blas) {
+    if (rocblas_create_handle(&M->blas) != rocblas_status_success) throw Error(HPDG_ERR_HIP, "rocblas handle");
+  }
+  rocblas_set_stream(M->blas, s);
+  // batched Cholesky + inverse, one call per block size
+  std::vector<int> sizes;
+  for (size_t e = 0; e < E; ++e) sizes.push_back(h.einfo[e].n);
+  std::sort(sizes.begin(), sizes.end());
+  sizes.erase(std::unique(sizes.begin(), sizes.end()), sizes.end());
+  for (int n : sizes) {
+    const int N = n * n * n;
+    std::vector<double*> ptrs;
+    for (size_t e = 0; e < E; ++e)
+      if (h.einfo[e].n == n) ptrs.push_back(B + boff[e]);
+    const int cnt = int(ptrs.size());
+    double** dptrs = nullptr;
+    rocblas_int* info = nullptr;
+    HIPCHK(hipMalloc(&dptrs, cnt * sizeof(double*)));
+    HIPCHK(hipMalloc(&info, cnt * sizeof(rocblas_int)));
+    HIPCHK(hipMemcpyAsync(dptrs, ptrs.data(), cnt * sizeof(double*), hipMemcpyHostToDevice, s));
+    rocblas_status st1 = rocsolver_dpotrf_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt);
+    std::vector<rocblas_int> hinfo(cnt);
+    HIPCHK(hipMemcpyAsync(hinfo.data(), info, cnt * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    bool ok = st1 == rocblas_status_success;
+    for (int v : hinfo) ok = ok && v == 0;
+    rocblas_status st2 = ok ? rocsolver_dpotri_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt)
+                            : rocblas_status_internal_error;
+    if (ok) {
+      HIPCHK(hipMemcpyAsync(hinfo.data(), info, cnt * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      ok = st2 == rocblas_status_success;
+      for (int v : hinfo) ok = ok && v == 0;
+    }
+    (void)hipFree(dptrs);
+    (void)hipFree(info);
+    if (!ok) throw Error(HPDG_ERR_BREAKDOWN, "an element block is not positive definite");
+  }
+  launch_symmetrize_blocks<double>(V, d.boff, B, s);
+  d.binv = B;
+  if (M->has_f32) {
+    DevLevel<float>& d32 = M->lev<float>(l);
+    d32.boff = d.boff;
+    d32.binv = M->alloc<float>(size_t(boff[E]));
+    launch_blocks_d2f(V, d.boff, B, d32.binv, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
 }
 
 // exact coarse solve: assemble the coarsest operator column by column, invert (Cholesky)
@@ -660,8 +736,12 @@ int hpdg_setup_smoother(hpdg_mesh* mesh, const hpdg_smoother_params* params, dou
       if (mesh->sp.n_cheb <= 0) mesh->sp.n_cheb = 4;
       if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
       if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
+      if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)
+        throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
     }
     hipStream_t s = S(stream);
+    if (mesh->sp.scaling == HPDG_SMOOTH_BLOCK)
+      for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
     for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
       if (lambda_max && lambda_max[l] > 0)
         mesh->lam[l] = lambda_max[l];

@@ -26,6 +26,7 @@ struct LevelView {
   TabView tv;
   long long n_elem;
   int nmax, qmax, qmmax;
+  int self_only;  // 1: neighbour traces taken as zero (the element-diagonal blocks A_ee)
 };
 
 template <typename T>
@@ -68,6 +69,27 @@ void launch_convert_f2d(long long n, const float* x, double* y, hipStream_t s);
 // dense y = A x (row-major n x n)
 template <typename T>
 void launch_dense_matvec(int n, const T* A, const T* x, T* y, hipStream_t s);
+
+// element-block Jacobi: blocks of element e stored row-major at boff[e], size (n_e^3)^2
+// column j of every block at once: x holds e_j in every element (n^3 > j)
+template <typename T>
+void launch_set_unit(const LevelView<T>& L, int j, T value, T* x, hipStream_t s);
+template <typename T>
+void launch_gather_column(const LevelView<T>& L, int j, const T* y, const long long* boff, T* B,
+                          hipStream_t s);
+// copy the lower triangle (column-major) of every block to its upper triangle
+template <typename T>
+void launch_symmetrize_blocks(const LevelView<T>& L, const long long* boff, T* B, hipStream_t s);
+void launch_blocks_d2f(const LevelView<double>& L, const long long* boff, const double* B, float* Bf,
+                       hipStream_t s);
+// z = Binv r per element
+template <typename T>
+void launch_block_apply(const LevelView<T>& L, const long long* boff, const T* Binv, const T* r, T* z,
+                        hipStream_t s);
+// r = Binv (b - Ax) per element (Ax null: x = 0); p = alpha r + beta p (first: alpha r); x += p
+template <typename T>
+void launch_block_cheb(const LevelView<T>& L, const long long* boff, const T* Binv, const T* b,
+                       const T* Ax, T* p, T* x, T alpha, T beta, int first, hipStream_t s);
 
 // deterministic reductions: out[0..k) = dots, via partials (kRedBlocks * k doubles)
 constexpr int kRedBlocks = 512;

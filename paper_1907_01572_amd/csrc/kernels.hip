@@ -266,7 +266,15 @@ __global__ void __launch_bounds__(kBS) apply_kernel(LevelView<T> L, const T* __r
       const bool interior = M.ep >= 0;
       SideMapD ot{0, 0, 0, 0, 0};
       int od = 0, ot0 = 0, ot1 = 0;
-      if (interior) {
+      if (interior && L.self_only) {
+        // neighbour taken as zero: its traces vanish (the element's own diagonal block)
+        for (int idx = threadIdx.x; idx < 4 * qq; idx += blockDim.x) s.Go[idx] = 0;
+        ot = side_map_d(M, 1 - side);
+        od = (side ? M.fm : M.fp) >> 1;
+        ot0 = od == 0 ? 1 : 0;
+        ot1 = od == 2 ? 1 : 2;
+        __syncthreads();
+      } else if (interior) {
         const int oe = side ? M.em : M.ep, of = side ? M.fm : M.fp;
         const ElemInfo& O = L.einfo[oe];
         const int no = O.n;
@@ -367,6 +375,79 @@ __global__ void __launch_bounds__(kBS) apply_kernel(LevelView<T> L, const T* __r
     __syncthreads();
   }
   for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) y[I.off + idx] = s.sy[idx];
+}
+
+// ---- element-block Jacobi -------------------------------------------------------------
+template <typename T>
+__global__ void set_unit_kernel(LevelView<T> L, int j, T value, T* x) {
+  for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < L.n_elem;
+       e += (long long)gridDim.x * blockDim.x) {
+    const ElemInfo& I = L.einfo[e];
+    if (j < I.n * I.n * I.n) x[I.off + j] = value;
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBS) gather_column_kernel(LevelView<T> L, int j, const T* y,
+                                                            const long long* boff, T* B) {
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int N = I.n * I.n * I.n;
+  if (j >= N) return;
+  // the block is symmetric: column j is stored as row j (contiguous)
+  for (int i = threadIdx.x; i < N; i += blockDim.x) B[boff[e] + (long long)j * N + i] = y[I.off + i];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBS) symmetrize_kernel(LevelView<T> L, const long long* boff, T* B) {
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int N = I.n * I.n * I.n;
+  T* b = B + boff[e];
+  // column-major lower triangle (row >= col) holds the result: b[c * N + r], r >= c
+  for (long long idx = threadIdx.x; idx < (long long)N * N; idx += blockDim.x) {
+    const int r = int(idx % N), c = int(idx / N);
+    if (r < c) b[c * (long long)N + r] = b[r * (long long)N + c];
+  }
+}
+
+__global__ void __launch_bounds__(kBS) blocks_d2f_kernel(LevelView<double> L, const long long* boff,
+                                                         const double* B, float* Bf) {
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const long long N = (long long)I.n * I.n * I.n;
+  for (long long idx = threadIdx.x; idx < N * N; idx += blockDim.x) Bf[boff[e] + idx] = float(B[boff[e] + idx]);
+}
+
+// per element: z = Binv r (block_cheb: r = b - Ax first, then the Chebyshev update)
+template <typename T, bool CHEB>
+__global__ void __launch_bounds__(kBS) block_kernel(LevelView<T> L, const long long* boff, const T* Binv,
+                                                    const T* b, const T* Ax, T* p, T* x, T alpha, T beta,
+                                                    int first) {
+  extern __shared__ unsigned char smem_raw[];
+  T* r = reinterpret_cast<T*>(smem_raw);
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int N = I.n * I.n * I.n;
+  for (int i = threadIdx.x; i < N; i += blockDim.x)
+    r[i] = (CHEB && Ax) ? b[I.off + i] - Ax[I.off + i] : b[I.off + i];
+  __syncthreads();
+  const T* B = Binv + boff[e];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    T z = 0;
+    for (int j = 0; j < N; ++j) z += B[(long long)j * N + i] * r[j];  // symmetric: row j, col i
+    if (CHEB) {
+      const T pn = first ? alpha * z : alpha * z + beta * p[I.off + i];
+      p[I.off + i] = pn;
+      x[I.off + i] += pn;
+    } else {
+      x[I.off + i] = z;
+    }
+  }
 }
 
 // ---- transfers (Eqs. psi-interpolation, temp-G) -------------------------------------
@@ -654,6 +735,38 @@ void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
 }
 
 template <typename T>
+void launch_set_unit(const LevelView<T>& L, int j, T value, T* x, hipStream_t s) {
+  hipLaunchKernelGGL(set_unit_kernel<T>, dim3(grid_for(L.n_elem)), dim3(256), 0, s, L, j, value, x);
+}
+template <typename T>
+void launch_gather_column(const LevelView<T>& L, int j, const T* y, const long long* boff, T* B,
+                          hipStream_t s) {
+  hipLaunchKernelGGL(gather_column_kernel<T>, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, j, y, boff, B);
+}
+template <typename T>
+void launch_symmetrize_blocks(const LevelView<T>& L, const long long* boff, T* B, hipStream_t s) {
+  hipLaunchKernelGGL(symmetrize_kernel<T>, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B);
+}
+void launch_blocks_d2f(const LevelView<double>& L, const long long* boff, const double* B, float* Bf,
+                       hipStream_t s) {
+  hipLaunchKernelGGL(blocks_d2f_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, Bf);
+}
+template <typename T>
+void launch_block_apply(const LevelView<T>& L, const long long* boff, const T* Binv, const T* r, T* z,
+                        hipStream_t s) {
+  const size_t lds = sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
+  hipLaunchKernelGGL((block_kernel<T, false>), dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv,
+                     r, (const T*)nullptr, (T*)nullptr, z, T(0), T(0), 0);
+}
+template <typename T>
+void launch_block_cheb(const LevelView<T>& L, const long long* boff, const T* Binv, const T* b,
+                       const T* Ax, T* p, T* x, T alpha, T beta, int first, hipStream_t s) {
+  const size_t lds = sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
+  hipLaunchKernelGGL((block_kernel<T, true>), dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv,
+                     b, Ax, p, x, alpha, beta, first);
+}
+
+template <typename T>
 void launch_prolong_add(const TransferView<T>& V, const T* uc, T* uf, hipStream_t s) {
   const size_t lds = sizeof(T) * 2 * size_t(V.nmax) * V.nmax * V.nmax;
   hipLaunchKernelGGL(prolong_kernel<T>, dim3(unsigned(V.n_fine)), dim3(kBS), lds, s, V, uc, uf);
@@ -727,7 +840,15 @@ void launch_fcg_update(long long n, const double* v, const double* w, double* d,
   template void launch_cheb_update<T>(long long, const T*, const T*, const T*, T*, T*, T, T, int, \
                                       hipStream_t);                                             \
   template void launch_dense_matvec<T>(int, const T*, const T*, T*, hipStream_t);           \
-  template void launch_scale<T>(long long, const T*, const T*, T*, hipStream_t);
+  template void launch_scale<T>(long long, const T*, const T*, T*, hipStream_t);               \
+  template void launch_set_unit<T>(const LevelView<T>&, int, T, T*, hipStream_t);              \
+  template void launch_gather_column<T>(const LevelView<T>&, int, const T*, const long long*, T*, \
+                                        hipStream_t);                                           \
+  template void launch_symmetrize_blocks<T>(const LevelView<T>&, const long long*, T*, hipStream_t); \
+  template void launch_block_apply<T>(const LevelView<T>&, const long long*, const T*, const T*, T*, \
+                                      hipStream_t);                                             \
+  template void launch_block_cheb<T>(const LevelView<T>&, const long long*, const T*, const T*,   \
+                                     const T*, T*, T*, T, T, int, hipStream_t);
 HPDG_INST(double)
 HPDG_INST(float)
 #undef HPDG_INST

@@ -96,18 +96,20 @@ def test_rhs_parity(ctx):
         M.free()
 
 
-@pytest.mark.parametrize("name,jacobi", [("cube_l2_p3", False), ("hp_k", True), ("shell_l2_p3_r1e3", True)])
-def test_smoother_and_vcycle_parity(ctx, name, jacobi):
+@pytest.mark.parametrize("name,smoother", [("cube_l2_p3", "none"), ("hp_k", "point"),
+                                           ("shell_l2_p3_r1e3", "point"), ("hp_k", "block"),
+                                           ("shell_l2_p3_r1e3", "block")])
+def test_smoother_and_vcycle_parity(ctx, name, smoother):
     maker, prob = MESHES[name]
     m = maker()
-    mg = Multigrid(m, prob, n_cheb=3, jacobi=jacobi)
+    mg = Multigrid(m, prob, n_cheb=3, smoother=smoother)
     M = ctx.upload(m, coef=coef_of(prob))
-    lam = M.setup_smoother(n_cheb=3, jacobi=jacobi, lambda_max=mg.lam)
+    lam = M.setup_smoother(n_cheb=3, smoother=smoother, lambda_max=mg.lam)
     np.testing.assert_allclose(lam, mg.lam)
     rng = np.random.default_rng(2)
     op = mg.ops[0]
     b, x0 = rng.standard_normal((2, op.ndof))
-    xs = chebyshev(op.apply, b, x0, mg.lam[0], mg.Lambda, 5, mg.dinv[0])
+    xs = chebyshev(op.apply, b, x0, mg.lam[0], mg.Lambda, 5, mg.minv[0])
     xd = dev(x0)
     M.smooth(dev(b), xd, level=0, n_iter=5)
     e1 = rel(host(xd), xs)
@@ -120,14 +122,15 @@ def test_smoother_and_vcycle_parity(ctx, name, jacobi):
     M.free()
 
 
-def test_cg_spectral_bound_close_to_oracle(ctx):
-    maker, prob = MESHES["cube_l2_p3"]
+@pytest.mark.parametrize("smoother", ["point", "block"])
+def test_cg_spectral_bound_close_to_oracle(ctx, smoother):
+    maker, prob = MESHES["hp_k"]
     m = maker()
-    mg = Multigrid(m, prob, n_cheb=3, jacobi=True)
+    mg = Multigrid(m, prob, n_cheb=3, smoother=smoother)
     M = ctx.upload(m, coef=coef_of(prob))
-    lam = M.setup_smoother(n_cheb=3, jacobi=True)
-    # different (seeded) start vectors: the bounds agree to a few percent and both
-    # exceed the largest Ritz value scale of D^-1 A
+    lam = M.setup_smoother(n_cheb=3, smoother=smoother)
+    # different (seeded) start vectors: the Gershgorin bounds of the two Lanczos
+    # tridiagonals of M^-1 A agree to a few percent
     print("lambda gpu", lam, "oracle", mg.lam, flush=True)
     np.testing.assert_allclose(lam, mg.lam, rtol=0.15)
     M.free()
@@ -140,12 +143,13 @@ def test_cg_spectral_bound_close_to_oracle(ctx):
     ("hp_k", hp.SOLVER_FCG, hp.PREC_MIXED),
     ("shell_l2_p3_r1e3", hp.SOLVER_FCG, hp.PREC_F64),
     ("shell_l2_p3_r1e3", hp.SOLVER_FCG, hp.PREC_MIXED),
+    ("shell_l2_p4_r1e9", hp.SOLVER_FCG, hp.PREC_F64),
 ])
 def test_solve_reaches_oracle_residual(ctx, name, solver, prec):
     maker, prob = MESHES[name]
     m = maker()
     M = ctx.upload(m, coef=coef_of(prob), build_f32=(prec == hp.PREC_MIXED))
-    M.setup_smoother(n_cheb=8 if name.startswith("shell") else 4, jacobi=True)
+    M.setup_smoother(n_cheb=4, smoother="block" if name.startswith("shell") else "point")
     F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
     M.assemble_rhs(prob, F)
     u = torch.zeros_like(F)
