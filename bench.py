@@ -37,6 +37,8 @@ def main():
     ap.add_argument("--p", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--profile-apply", action="store_true",
+                    help="only upload the mesh and run --apply-reps FP64 and FP32 applies (for rocprofv3)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported" % args.gpus}))
@@ -53,6 +55,17 @@ def main():
     ctx = hp.Context(0)
     t0 = time.time()
     M = ctx.upload(mesh, build_f32=True)
+    if args.profile_apply:
+        x64 = torch.randn(M.n_dof[0], dtype=torch.float64, device=dev)
+        y64 = torch.zeros_like(x64)
+        x32, y32 = x64.float(), torch.zeros_like(x64, dtype=torch.float32)
+        for _ in range(args.apply_reps):
+            M.apply(x64, y64)
+        for _ in range(args.apply_reps):
+            M.apply(x32, y32)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_apply": True, "dof": M.n_dof[0], "reps": args.apply_reps}))
+        return
     lam = M.setup_smoother(n_cheb=args.n_cheb, smoother=args.smoother, Lambda=args.Lambda)
     setup_s = time.time() - t0
     N = M.n_dof[0]

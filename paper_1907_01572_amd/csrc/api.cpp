@@ -53,6 +53,7 @@ struct DevLevel {
   T *f = nullptr, *v = nullptr, *t = nullptr, *p = nullptr;
   long long* boff = nullptr;  // element-block Jacobi: offsets of the inverse blocks
   T* binv = nullptr;
+  int* belems = nullptr;      // element ids grouped by (n, q)
 };
 
 }  // namespace
@@ -227,6 +228,7 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
   d.einfo = M->upload_raw(h.einfo, s);
   d.minfo = M->upload_raw(h.minfo, s);
   d.fmlist = M->upload_raw(h.fmlist, s);
+  d.belems = M->upload_raw(h.bucket_elems, s);
   d.vgeo = M->upload<T>(h.vgeo, s);
   d.mgeo = M->upload<T>(h.mgeo, s);
   std::vector<double> dinv(h.diag.size());
@@ -246,7 +248,12 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
 
 template <typename T>
 void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
-  launch_apply<T>(M->view<T>(l), x, y, s);
+  const LevelHost& h = M->H[l];
+  const LevelView<T> V = M->view<T>(l);
+  const int* be = M->lev<T>(l).belems;
+  for (size_t b = 0; b < h.bucket_n.size(); ++b)
+    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
+                           h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
 }
 
 // Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)

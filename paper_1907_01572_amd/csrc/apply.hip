@@ -1,0 +1,775 @@
+// gfx950 operator kernel of the hpdg library: y = A x on one multigrid level.
+//
+// One workgroup per element computes y_e = (A x)_e completely, so every output is written
+// once, without atomics, and the result is bitwise reproducible:
+//   * volume: the stiffness term by sum factorisation through the GL points
+//     (Eq. harald-stiff): three 1-D passes to the GL points, the reference gradient by the
+//     GL collocation derivative, the metric contraction G (Eq. stiffness-3, with w J and k
+//     folded in), and the transposed passes back to the LGL test functions;
+//   * faces: the SIPG terms of Eq. lh2 on every mortar of the element (Eq. temp-E), both
+//     sides' traces interpolated onto the mortar's GL points through the hp projections of
+//     Fig. mortar (1-D matrices for the sub-face halves and the degree change), the flux
+//     formed for the own side only and lifted back through the transposed interpolation.
+//     The six faces are processed together, one mortar per face per round (a face of a
+//     coarse element facing four finer elements takes four rounds).
+// Each mortar is therefore evaluated once from each side.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace hpdg {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kFaces = 6;
+
+// how the mortar's point grid maps onto one side's face axes (a, b)
+struct Map {
+  int swap, flipA, flipB, halfA, halfB;
+};
+
+__device__ inline Map mortar_map(const MortarInfo& M, int side) {
+  Map s{0, 0, 0, 0, 0};
+  if (side) {
+    s.swap = M.orient & 1;
+    s.flipA = (M.orient >> 1) & 1;
+    s.flipB = (M.orient >> 2) & 1;
+    s.halfA = M.sub < 0 ? 0 : 1 + (M.sub & 1);
+    s.halfB = M.sub < 0 ? 0 : 1 + ((M.sub >> 1) & 1);
+  }
+  return s;
+}
+
+// one (face, mortar) pair of the element in the current round
+struct Task {
+  int valid, f, side, interior, other, qm, gmode, no, of;
+  Map me, ot;
+  long long ooff, geo;
+};
+
+// volume index of the node with index k along axis d and (i, j) along the face axes t0 < t1
+// (arithmetic only: indexed private arrays would live in scratch memory)
+__device__ inline int vidx(int n, int d, int t0, int t1, int k, int i, int j) {
+  const int s0 = t0 == 0 ? 1 : n;            // t0 is axis 0 or 1
+  const int s1 = t1 == 1 ? n : n * n;        // t1 is axis 1 or 2
+  const int sd = d == 0 ? 1 : (d == 1 ? n : n * n);
+  return k * sd + i * s0 + j * s1;
+}
+
+template <typename T>
+__device__ inline const T* tab(const LevelView<T>& L, int kind, int n, int q) {
+  return L.tab + L.tv.off[(kind * (kMaxN + 1) + n) * (kMaxQ + 1) + q];
+}
+
+// flattened loop over the items of the six tasks: cnt[t] items of task t
+// (counts passed as scalars and the task found by unrolled compares, so that nothing is an
+// indexed private array)
+template <typename F>
+__device__ inline void for_items(int c0, int c1, int c2, int c3, int c4, int c5, F&& body) {
+  const int p1 = c0, p2 = p1 + c1, p3 = p2 + c2, p4 = p3 + c3, p5 = p4 + c4, total = p5 + c5;
+  for (int g = threadIdx.x; g < total; g += blockDim.x) {
+    int t = 0, base = 0;
+    if (g >= p1) { t = 1; base = p1; }
+    if (g >= p2) { t = 2; base = p2; }
+    if (g >= p3) { t = 3; base = p3; }
+    if (g >= p4) { t = 4; base = p4; }
+    if (g >= p5) { t = 5; base = p5; }
+    body(t, g - base);
+  }
+}
+
+#define HPDG_COUNTS(expr) expr(0), expr(1), expr(2), expr(3), expr(4), expr(5)
+
+struct Layout {
+  int NM, QM, QMM;
+  size_t fixed, vol, ra, rb, y, tasks;
+  __host__ __device__ Layout(int nm, int qm, int qmm) : NM(nm), QM(qm), QMM(qmm) {
+    fixed = 2 * size_t(NM) * NM * NM + size_t(QM) * NM + size_t(QM) * QM + QM + 2 * NM;
+    const size_t tsz = size_t(NM) * QM * (NM > QM ? NM : QM);
+    vol = 4 * size_t(QM) * QM * QM + 2 * tsz;
+    ra = kFaces * mx3(size_t(NM) * NM * NM, 6 * size_t(NM) * QMM, 4 * size_t(QMM) * QMM);
+    rb = kFaces * mx3(4 * size_t(NM) * NM, 8 * size_t(QMM) * QMM, 3 * size_t(QMM) * NM);
+    y = 2 * kFaces * size_t(NM) * NM;
+    tasks = (kFaces * sizeof(Task) + 15) / 16 * 16;
+  }
+  __host__ __device__ static size_t mx3(size_t a, size_t b, size_t c) {
+    return a > b ? (a > c ? a : c) : (b > c ? b : c);
+  }
+  // the face phases also stage the six 1-D mortar matrices of a uniform level
+  __host__ __device__ size_t faces() const { return ra + rb + y + 6 * size_t(QMM) * NM; }
+  __host__ __device__ size_t region() const { return vol > faces() ? vol : faces(); }
+  __host__ __device__ size_t bytes(size_t scalar) const { return tasks + scalar * (fixed + region()); }
+};
+
+// Task metadata for face f in round r (shared by both face paths)
+template <typename T>
+__device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int r) {
+  // (read through memory: indexing a private copy of the element record with a per-thread
+  // face would place it in scratch)
+  const ElemInfo& Ig = L.einfo[e];
+  Task tk;
+  tk.valid = r < Ig.fcnt[f];
+  tk.f = f;
+  tk.side = tk.interior = tk.other = tk.qm = tk.gmode = tk.no = tk.of = 0;
+  tk.me = tk.ot = Map{0, 0, 0, 0, 0};
+  tk.ooff = tk.geo = 0;
+  if (tk.valid) {
+    const int ent = L.fmlist[Ig.fstart[f] + r];
+    const MortarInfo M = L.minfo[ent >> 1];
+    tk.side = ent & 1;
+    tk.interior = M.ep >= 0;
+    tk.other = tk.interior && !L.self_only;
+    tk.qm = M.q;
+    tk.gmode = M.gmode;
+    tk.geo = M.geo;
+    tk.me = mortar_map(M, tk.side);
+    tk.ot = mortar_map(M, 1 - tk.side);
+    tk.of = tk.side ? M.fm : M.fp;
+    if (tk.other) {
+      const ElemInfo& O = L.einfo[tk.side ? M.em : M.ep];
+      tk.no = O.n;
+      tk.ooff = O.off;
+    }
+  }
+  return tk;
+}
+
+// Face terms of a level whose elements all have N nodes and whose mortars all have Q GL
+// points per axis (uniform degree): every size is a compile-time constant, the six 1-D
+// matrices (values / derivatives at the full, lower-half and upper-half point sets) are
+// staged in LDS once, and each phase maps threads to (task, item) with constant strides.
+// Adds the face terms to sy and writes y.
+template <typename T, int N, int Q>
+__device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, const T* __restrict__ x,
+                              T* __restrict__ y, const T* su, const T* sy, const T* dfo, T* region, Task* tasks,
+                              const Layout& lay) {
+  constexpr int N2 = N * N, N3 = N2 * N, QQ = Q * Q, NQ = N * Q;
+  const int NM = lay.NM, QMM = lay.QMM;
+  const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
+  T* mats = region;  // [kind 0..5][Q][N]
+  T* RA = mats + 6 * QMM * NM;
+  T* RB = RA + lay.ra;
+  T* Yf = RB + lay.rb;
+  T* Yn = Yf + kFaces * NM * NM;
+  for (int i = threadIdx.x; i < 6 * NQ; i += blockDim.x) mats[i] = tab(L, i / NQ, N, Q)[i % NQ];
+  for (int i = threadIdx.x; i < 2 * kFaces * NM * NM; i += blockDim.x) Yf[i] = 0;
+  int rounds = 0;
+#pragma unroll
+  for (int f = 0; f < kFaces; ++f) rounds = I.fcnt[f] > rounds ? I.fcnt[f] : rounds;
+  for (int r = 0; r < rounds; ++r) {
+    for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
+    __syncthreads();
+    // P0: neighbour coefficients
+    for (int g = threadIdx.x; g < kFaces * N3; g += blockDim.x) {
+      const int t = g / N3, i = g % N3;
+      if (tasks[t].other) RA[t * raS + i] = x[tasks[t].ooff + i];
+    }
+    __syncthreads();
+    // P1: traces (values, reference normal derivative) of the own face and the neighbour's
+    for (int g = threadIdx.x; g < kFaces * 2 * N2; g += blockDim.x) {
+      const int t = g / (2 * N2), li = g % (2 * N2);
+      const Task& tk = tasks[t];
+      if (!tk.valid) continue;
+      const bool own = li < N2;
+      if (!own && !tk.other) continue;
+      const int l2 = own ? li : li - N2;
+      const int f = own ? tk.f : tk.of, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const int kf = (f & 1) ? N - 1 : 0;
+      const T* u = own ? su : RA + t * raS;
+      const T* df = dfo + (f & 1) * NM;
+      const int i = l2 % N, j = l2 / N;
+      T* tr = RB + t * rbS + (own ? 0 : 2 * NM * NM);
+      tr[l2] = u[vidx(N, d, t0, t1, kf, i, j)];
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += df[k] * u[vidx(N, d, t0, t1, k, i, j)];
+      tr[NM * NM + l2] = s;
+    }
+    __syncthreads();
+    // P2: first interpolation pass (along face axis a): u, du/da, du/dn
+    for (int g = threadIdx.x; g < kFaces * 2 * NQ; g += blockDim.x) {
+      const int t = g / (2 * NQ), li = g % (2 * NQ);
+      const Task& tk = tasks[t];
+      if (!tk.valid) continue;
+      const bool own = li < NQ;
+      if (!own && !tk.other) continue;
+      const int l2 = own ? li : li - NQ;
+      const Map m = own ? tk.me : tk.ot;
+      const T* F = RB + t * rbS + (own ? 0 : 2 * NM * NM);
+      const T* Nd = F + NM * NM;
+      const T* Ma = mats + (2 * m.halfA) * NQ;
+      const T* Da = Ma + NQ;
+      const int xg = l2 % Q, j = l2 / Q;
+      const int ra = m.flipA ? Q - 1 - xg : xg;
+      T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const T fv = F[j * N + i], ma = Ma[ra * N + i];
+        s0 += ma * fv;
+        s1 += Da[ra * N + i] * fv;
+        s2 += ma * Nd[j * N + i];
+      }
+      T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
+      T1[j * Q + xg] = s0;
+      T1[NM * QMM + j * Q + xg] = s1;
+      T1[2 * NM * QMM + j * Q + xg] = s2;
+    }
+    __syncthreads();
+    // P3: second pass (along face axis b): u, du/da, du/db, du/dn at the points
+    for (int g = threadIdx.x; g < kFaces * 2 * QQ; g += blockDim.x) {
+      const int t = g / (2 * QQ), li = g % (2 * QQ);
+      const Task& tk = tasks[t];
+      if (!tk.valid) continue;
+      const bool own = li < QQ;
+      if (!own && !tk.other) continue;
+      const int l2 = own ? li : li - QQ;
+      const Map m = own ? tk.me : tk.ot;
+      const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
+      const T* Mb = mats + (2 * m.halfB) * NQ;
+      const T* Db = Mb + NQ;
+      const int xg = l2 % Q, yg = l2 / Q;
+      const int rb = m.flipB ? Q - 1 - yg : yg;
+      T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) {
+        const T mb = Mb[rb * N + j];
+        const T a0 = T1[j * Q + xg];
+        g0 += mb * a0;
+        g1 += mb * T1[NM * QMM + j * Q + xg];
+        g2 += Db[rb * N + j] * a0;
+        g3 += mb * T1[2 * NM * QMM + j * Q + xg];
+      }
+      T* Gs = RB + t * rbS + (own ? 0 : 4 * QMM * QMM);
+      Gs[l2] = g0;
+      Gs[QMM * QMM + l2] = g1;
+      Gs[2 * QMM * QMM + l2] = g2;
+      Gs[3 * QMM * QMM + l2] = g3;
+    }
+    __syncthreads();
+    // P4: SIPG flux at the mortar points, own side, own frame
+    for (int g = threadIdx.x; g < kFaces * QQ; g += blockDim.x) {
+      const int t = g / QQ, li = g % QQ;
+      const Task& tk = tasks[t];
+      if (!tk.valid) continue;
+      const int side = tk.side;
+      const int npts = tk.gmode ? QQ : 1;
+      const T* mg = L.mgeo + tk.geo;
+      const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const int xg = li % Q, yg = li / Q;
+      const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
+      const int pp = tk.gmode ? cc + Q * dd : 0;
+      T wS;
+      if (tk.gmode) {
+        wS = mg[6 * npts + pp];
+      } else {
+        const T* wm = L.tab + L.tv.w_off[Q];
+        wS = wm[cc] * wm[dd] * mg[6];
+      }
+      const T sig = mg[7 * npts + pp];
+      const T ma = mg[(3 * side + t0) * npts + pp];
+      const T mb = mg[(3 * side + t1) * npts + pp];
+      const T mn = mg[(3 * side + d) * npts + pp];
+      const T* Gm = RB + t * rbS;
+      const T u_me = Gm[li];
+      const T g_me = ma * Gm[QMM * QMM + li] + mb * Gm[2 * QMM * QMM + li] + mn * Gm[3 * QMM * QMM + li];
+      T Af, Bc;
+      if (tk.interior) {
+        T u_o = 0, g_o = 0;
+        if (tk.other) {
+          const int os = 1 - side, od = tk.of >> 1;
+          const int ot0 = od == 0 ? 1 : 0, ot1 = od == 2 ? 1 : 2;
+          const int oi = tk.ot.swap ? dd + Q * cc : cc + Q * dd;
+          const T* Go = Gm + 4 * QMM * QMM;
+          u_o = Go[oi];
+          g_o = mg[(3 * os + ot0) * npts + pp] * Go[QMM * QMM + oi] +
+                mg[(3 * os + ot1) * npts + pp] * Go[2 * QMM * QMM + oi] +
+                mg[(3 * os + od) * npts + pp] * Go[3 * QMM * QMM + oi];
+        }
+        const T jmp = u_me - u_o;
+        Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
+        Bc = T(-0.5) * wS * jmp;
+      } else {
+        Af = wS * (sig * u_me - g_me);
+        Bc = -wS * u_me;
+      }
+      T* CF = RA + t * raS;
+      CF[li] = Af;
+      CF[QMM * QMM + li] = Bc * ma;
+      CF[2 * QMM * QMM + li] = Bc * mb;
+      CF[3 * QMM * QMM + li] = Bc * mn;
+    }
+    __syncthreads();
+    // P5: first transposed pass (along the own face axis a)
+    for (int g = threadIdx.x; g < kFaces * NQ; g += blockDim.x) {
+      const int t = g / NQ, li = g % NQ;
+      const Task& tk = tasks[t];
+      if (!tk.valid) continue;
+      const T* Ma = mats + (2 * tk.me.halfA) * NQ;
+      const T* Da = Ma + NQ;
+      const T* CF = RA + t * raS;
+      const int i = li % N, yg = li / N;
+      T s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll
+      for (int xg = 0; xg < Q; ++xg) {
+        const int ra = tk.me.flipA ? Q - 1 - xg : xg;
+        const T ma = Ma[ra * N + i];
+        const int gi = yg * Q + xg;
+        s1 += ma * CF[gi] + Da[ra * N + i] * CF[QMM * QMM + gi];
+        s2 += ma * CF[2 * QMM * QMM + gi];
+        s3 += ma * CF[3 * QMM * QMM + gi];
+      }
+      T* S = RB + t * rbS;
+      S[li] = s1;
+      S[QMM * NM + li] = s2;
+      S[2 * QMM * NM + li] = s3;
+    }
+    __syncthreads();
+    // P6: second transposed pass (along b) into the per-face sums
+    for (int g = threadIdx.x; g < kFaces * N2; g += blockDim.x) {
+      const int t = g / N2, li = g % N2;
+      const Task& tk = tasks[t];
+      if (!tk.valid) continue;
+      const T* Mb = mats + (2 * tk.me.halfB) * NQ;
+      const T* Db = Mb + NQ;
+      const T* S = RB + t * rbS;
+      const int i = li % N, j = li / N;
+      T yf = 0, yn = 0;
+#pragma unroll
+      for (int yg = 0; yg < Q; ++yg) {
+        const int rb = tk.me.flipB ? Q - 1 - yg : yg;
+        const T mb = Mb[rb * N + j];
+        yf += mb * S[yg * N + i] + Db[rb * N + j] * S[QMM * NM + yg * N + i];
+        yn += mb * S[2 * QMM * NM + yg * N + i];
+      }
+      Yf[tk.f * NM * NM + li] += yf;
+      Yn[tk.f * NM * NM + li] += yn;
+    }
+    __syncthreads();
+  }
+  // face sums -> element
+  for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) {
+    const int c0 = idx % N, c1 = (idx / N) % N, c2 = idx / N2;
+    T acc = sy[idx];
+#pragma unroll
+    for (int f = 0; f < kFaces; ++f) {
+      if (I.fcnt[f] == 0) continue;
+      const int d = f >> 1;
+      const int kd = d == 0 ? c0 : (d == 1 ? c1 : c2);
+      const int li = d == 0 ? c2 * N + c1 : (d == 1 ? c2 * N + c0 : c1 * N + c0);
+      acc += dfo[(f & 1) * NM + kd] * Yn[f * NM * NM + li];
+      if (kd == ((f & 1) ? N - 1 : 0)) acc += Yf[f * NM * NM + li];
+    }
+    y[I.off + idx] = acc;
+  }
+}
+
+// NT, QT > 0: element degree + 1 and volume GL points fixed at compile time (the bucket's
+// elements); 0: read from the element record.  UNI: uniform-degree level (faces_uniform).
+template <typename T, int NT, int QT, bool UNI>
+__global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const int* __restrict__ elems,
+                                                         long long count, const T* __restrict__ x,
+                                                         T* __restrict__ y) {
+  extern __shared__ unsigned char smem_raw[];
+  if ((long long)blockIdx.x >= count) return;
+  const long long e = elems ? elems[blockIdx.x] : (long long)blockIdx.x;
+  const ElemInfo I = L.einfo[e];
+  const int n = NT ? NT : I.n, q = QT ? QT : I.q;
+  const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
+  const Layout lay(L.nmax, L.qmax, L.qmmax);
+  const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
+
+  Task* tasks = reinterpret_cast<Task*>(smem_raw);
+  T* p = reinterpret_cast<T*>(smem_raw + lay.tasks);
+  T* su = p; p += NM * NM * NM;
+  T* sy = p; p += NM * NM * NM;
+  T* Bm = p; p += QM * NM;        // LGL -> GL interpolation [q][n]
+  T* Dg = p; p += QM * QM;        // GL collocation derivative [q][q]
+  T* w = p; p += QM;              // GL weights
+  T* dfo = p; p += 2 * NM;        // l_k'(-1), l_k'(+1) of the own basis
+  T* region = p;
+  T* A0 = region;
+  T* A1 = A0 + QM * QM * QM;
+  T* A2 = A1 + QM * QM * QM;
+  T* A3 = A2 + QM * QM * QM;
+  const int tsz = NM * QM * (NM > QM ? NM : QM);
+  T* tA = A3 + QM * QM * QM;
+  T* tB = tA + tsz;
+  // face phases (alias the volume buffers): ping-pong regions RA / RB and the face sums
+  T* RA = region;
+  T* RB = RA + lay.ra;
+  T* Yf = RB + lay.rb;
+  T* Yn = Yf + kFaces * NM * NM;
+  const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
+
+  {
+    const T* B = tab(L, 0, n, q);
+    const T* Dgg = L.tab + L.tv.dg_off[q];
+    const T* wg = L.tab + L.tv.w_off[q];
+    const T* dfg = L.tab + L.tv.dface_off[n];
+    for (int i = threadIdx.x; i < n3; i += blockDim.x) su[i] = x[I.off + i];
+    for (int i = threadIdx.x; i < q * n; i += blockDim.x) Bm[i] = B[i];
+    for (int i = threadIdx.x; i < q * q; i += blockDim.x) Dg[i] = Dgg[i];
+    for (int i = threadIdx.x; i < q; i += blockDim.x) w[i] = wg[i];
+    for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) dfo[(i / n) * NM + i % n] = dfg[i];
+  }
+  __syncthreads();
+
+  // ---- volume: u -> GL values (three 1-D passes) ----
+  for (int idx = threadIdx.x; idx < n2 * q; idx += blockDim.x) {
+    const int a = idx % q, kj = idx / q;
+    T acc = 0;
+#pragma unroll
+    for (int i = 0; i < n; ++i) acc += Bm[a * n + i] * su[kj * n + i];
+    tA[idx] = acc;  // [k][j][a]
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * q * q; idx += blockDim.x) {
+    const int a = idx % q, b = (idx / q) % q, k = idx / (q * q);
+    T acc = 0;
+#pragma unroll
+    for (int j = 0; j < n; ++j) acc += Bm[b * n + j] * tA[(k * n + j) * q + a];
+    tB[idx] = acc;  // [k][b][a]
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
+    const int ba = idx % (q * q), c = idx / (q * q);
+    T acc = 0;
+#pragma unroll
+    for (int k = 0; k < n; ++k) acc += Bm[c * n + k] * tB[k * q * q + ba];
+    A0[idx] = acc;  // [c][b][a]
+  }
+  __syncthreads();
+  // ---- reference gradient at the GL points and the metric contraction ----
+  const T* G = L.vgeo + I.vgeo;
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
+    const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
+    T g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+    for (int t = 0; t < q; ++t) {
+      g0 += Dg[a * q + t] * A0[(c * q + b) * q + t];
+      g1 += Dg[b * q + t] * A0[(c * q + t) * q + a];
+      g2 += Dg[c * q + t] * A0[(t * q + b) * q + a];
+    }
+    T G00, G01, G02, G11, G12, G22;
+    if (I.vmode == 0) {
+      const T ww = w[a] * w[b] * w[c];
+      G00 = G[0] * ww; G01 = G[1] * ww; G02 = G[2] * ww;
+      G11 = G[3] * ww; G12 = G[4] * ww; G22 = G[5] * ww;
+    } else {
+      G00 = G[idx]; G01 = G[q3 + idx]; G02 = G[2 * q3 + idx];
+      G11 = G[3 * q3 + idx]; G12 = G[4 * q3 + idx]; G22 = G[5 * q3 + idx];
+    }
+    A1[idx] = G00 * g0 + G01 * g1 + G02 * g2;
+    A2[idx] = G01 * g0 + G11 * g1 + G12 * g2;
+    A3[idx] = G02 * g0 + G12 * g1 + G22 * g2;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
+    const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
+    T r = 0;
+#pragma unroll
+    for (int t = 0; t < q; ++t) {
+      r += Dg[t * q + a] * A1[(c * q + b) * q + t];
+      r += Dg[t * q + b] * A2[(c * q + t) * q + a];
+      r += Dg[t * q + c] * A3[(t * q + b) * q + a];
+    }
+    if (I.mass) r += G[6 * q3 + idx] * A0[idx];
+    A0[idx] = r;
+  }
+  __syncthreads();
+  // ---- back to the LGL test functions (transposed passes) ----
+  for (int idx = threadIdx.x; idx < n * q * q; idx += blockDim.x) {
+    const int ba = idx % (q * q), k = idx / (q * q);
+    T acc = 0;
+#pragma unroll
+    for (int c = 0; c < q; ++c) acc += Bm[c * n + k] * A0[c * q * q + ba];
+    tB[idx] = acc;  // [k][b][a]
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n2 * q; idx += blockDim.x) {
+    const int a = idx % q, j = (idx / q) % n, k = idx / (n * q);
+    T acc = 0;
+#pragma unroll
+    for (int b = 0; b < q; ++b) acc += Bm[b * n + j] * tB[(k * q + b) * q + a];
+    tA[idx] = acc;  // [k][j][a]
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) {
+    const int i = idx % n, kj = idx / n;
+    T acc = 0;
+#pragma unroll
+    for (int a = 0; a < q; ++a) acc += Bm[a * n + i] * tA[kj * q + a];
+    sy[idx] = acc;
+  }
+  __syncthreads();  // the face phases reuse the volume buffers
+
+  // ---- faces ----
+  if constexpr (UNI) {
+    faces_uniform<T, NT, QT>(L, I, e, x, y, su, sy, dfo, region, tasks, lay);
+    return;
+  }
+  int rounds = 0;
+#pragma unroll
+  for (int f = 0; f < kFaces; ++f) rounds = I.fcnt[f] > rounds ? I.fcnt[f] : rounds;
+  for (int i = threadIdx.x; i < 2 * kFaces * NM * NM; i += blockDim.x) Yf[i] = 0;  // Yf and Yn
+  for (int r = 0; r < rounds; ++r) {
+    for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
+    __syncthreads();
+    // P0: neighbour coefficients
+#define C0(t) (tasks[t].valid && tasks[t].other ? tasks[t].no * tasks[t].no * tasks[t].no : 0)
+    for_items(HPDG_COUNTS(C0), [&](int t, int i) { RA[t * raS + i] = x[tasks[t].ooff + i]; });
+#undef C0
+    __syncthreads();
+    // P1: traces (values and reference normal derivative) of the own face and the neighbour's
+#define C1(t) (tasks[t].valid ? n2 + (tasks[t].other ? tasks[t].no * tasks[t].no : 0) : 0)
+    for_items(HPDG_COUNTS(C1), [&](int t, int li) {
+      const Task& tk = tasks[t];
+      T* tr = RB + t * rbS;  // Fm, Nm, Fo, No at strides NM^2
+      if (li < n2) {
+        const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const int kf = (f & 1) ? n - 1 : 0;
+        const T* df = dfo + (f & 1) * NM;
+        const int i = li % n, j = li / n;
+        tr[li] = su[vidx(n, d, t0, t1, kf, i, j)];
+        T s = 0;
+#pragma unroll
+        for (int k = 0; k < n; ++k) s += df[k] * su[vidx(n, d, t0, t1, k, i, j)];
+        tr[NM * NM + li] = s;
+      } else {
+        const int lo = li - n2, no = tk.no, f = tk.of, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const int kf = (f & 1) ? no - 1 : 0;
+        const T* df = L.tab + L.tv.dface_off[no] + ((f & 1) ? no : 0);
+        const T* so = RA + t * raS;
+        const int i = lo % no, j = lo / no;
+        tr[2 * NM * NM + lo] = so[vidx(no, d, t0, t1, kf, i, j)];
+        T s = 0;
+        for (int k = 0; k < no; ++k) s += df[k] * so[vidx(no, d, t0, t1, k, i, j)];
+        tr[3 * NM * NM + lo] = s;
+      }
+    });
+    __syncthreads();
+    // P2: first interpolation pass (along face axis a) of u, du/da, du/dn, both sides
+#define C2(t) (tasks[t].valid ? tasks[t].qm * (n + (tasks[t].other ? tasks[t].no : 0)) : 0)
+    for_items(HPDG_COUNTS(C2), [&](int t, int li) {
+      const Task& tk = tasks[t];
+      const int qm = tk.qm;
+      const bool own = li < n * qm;
+      const int ns = own ? n : tk.no;
+      const int l2 = own ? li : li - n * qm;
+      const Map m = own ? tk.me : tk.ot;
+      const T* F = RB + t * rbS + (own ? 0 : 2 * NM * NM);
+      const T* N = F + NM * NM;
+      const T* Ma = tab(L, 0 + 2 * m.halfA, ns, qm);
+      const T* Da = tab(L, 1 + 2 * m.halfA, ns, qm);
+      const int xg = l2 % qm, j = l2 / qm;
+      const int ra = m.flipA ? qm - 1 - xg : xg;
+      T s0 = 0, s1 = 0, s2 = 0;
+      for (int i = 0; i < ns; ++i) {
+        const T fv = F[j * ns + i], ma = Ma[ra * ns + i];
+        s0 += ma * fv;
+        s1 += Da[ra * ns + i] * fv;
+        s2 += ma * N[j * ns + i];
+      }
+      T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
+      T1[j * qm + xg] = s0;
+      T1[NM * QMM + j * qm + xg] = s1;
+      T1[2 * NM * QMM + j * qm + xg] = s2;
+    });
+    __syncthreads();
+    // P3: second pass (along face axis b): G = u, du/da, du/db, du/dn at the points
+#define C3(t) (tasks[t].valid ? tasks[t].qm * tasks[t].qm * (tasks[t].other ? 2 : 1) : 0)
+    for_items(HPDG_COUNTS(C3), [&](int t, int li) {
+      const Task& tk = tasks[t];
+      const int qm = tk.qm, qq = qm * qm;
+      const bool own = li < qq;
+      const int ns = own ? n : tk.no;
+      const int l2 = own ? li : li - qq;
+      const Map m = own ? tk.me : tk.ot;
+      const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
+      const T* Mb = tab(L, 0 + 2 * m.halfB, ns, qm);
+      const T* Db = tab(L, 1 + 2 * m.halfB, ns, qm);
+      const int xg = l2 % qm, yg = l2 / qm;
+      const int rb = m.flipB ? qm - 1 - yg : yg;
+      T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+      for (int j = 0; j < ns; ++j) {
+        const T mb = Mb[rb * ns + j];
+        const T a0 = T1[j * qm + xg];
+        g0 += mb * a0;
+        g1 += mb * T1[NM * QMM + j * qm + xg];
+        g2 += Db[rb * ns + j] * a0;
+        g3 += mb * T1[2 * NM * QMM + j * qm + xg];
+      }
+      T* Gs = RB + t * rbS + (own ? 0 : 4 * QMM * QMM);
+      Gs[l2] = g0;
+      Gs[QMM * QMM + l2] = g1;
+      Gs[2 * QMM * QMM + l2] = g2;
+      Gs[3 * QMM * QMM + l2] = g3;
+    });
+    __syncthreads();
+    // P4: SIPG flux at the mortar points for the own side (in the own frame)
+#define C4(t) (tasks[t].valid ? tasks[t].qm * tasks[t].qm : 0)
+    for_items(HPDG_COUNTS(C4), [&](int t, int li) {
+      const Task& tk = tasks[t];
+      const int qm = tk.qm, qq = qm * qm, side = tk.side;
+      const int npts = tk.gmode ? qq : 1;
+      const T* mg = L.mgeo + tk.geo;
+      const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const int xg = li % qm, yg = li / qm;
+      const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
+      const int rho = cc + qm * dd, pp = tk.gmode ? rho : 0;
+      T wS;
+      if (tk.gmode) {
+        wS = mg[6 * npts + pp];
+      } else {
+        const T* wm = L.tab + L.tv.w_off[qm];
+        wS = wm[cc] * wm[dd] * mg[6];
+      }
+      const T sig = mg[7 * npts + pp];
+      const T ma = mg[(3 * side + t0) * npts + pp];
+      const T mb = mg[(3 * side + t1) * npts + pp];
+      const T mn = mg[(3 * side + d) * npts + pp];
+      const T* Gm = RB + t * rbS;
+      const T u_me = Gm[li];
+      const T g_me = ma * Gm[QMM * QMM + li] + mb * Gm[2 * QMM * QMM + li] + mn * Gm[3 * QMM * QMM + li];
+      T Af, Bc;
+      if (tk.interior) {
+        T u_o = 0, g_o = 0;
+        if (tk.other) {
+          const int os = 1 - side, od = tk.of >> 1;
+          const int ot0 = od == 0 ? 1 : 0, ot1 = od == 2 ? 1 : 2;
+          const int xo = tk.ot.swap ? dd : cc, yo = tk.ot.swap ? cc : dd;
+          const int oi = xo + qm * yo;
+          const T* Go = Gm + 4 * QMM * QMM;
+          u_o = Go[oi];
+          g_o = mg[(3 * os + ot0) * npts + pp] * Go[QMM * QMM + oi] +
+                mg[(3 * os + ot1) * npts + pp] * Go[2 * QMM * QMM + oi] +
+                mg[(3 * os + od) * npts + pp] * Go[3 * QMM * QMM + oi];
+        }
+        const T jmp = u_me - u_o;
+        Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
+        Bc = T(-0.5) * wS * jmp;
+      } else {
+        Af = wS * (sig * u_me - g_me);
+        Bc = -wS * u_me;
+      }
+      T* CF = RA + t * raS;
+      CF[li] = Af;
+      CF[QMM * QMM + li] = Bc * ma;
+      CF[2 * QMM * QMM + li] = Bc * mb;
+      CF[3 * QMM * QMM + li] = Bc * mn;
+    });
+    __syncthreads();
+    // P5: first transposed pass (along the own face axis a)
+#define C5(t) (tasks[t].valid ? tasks[t].qm * n : 0)
+    for_items(HPDG_COUNTS(C5), [&](int t, int li) {
+      const Task& tk = tasks[t];
+      const int qm = tk.qm;
+      const T* Ma = tab(L, 0 + 2 * tk.me.halfA, n, qm);
+      const T* Da = tab(L, 1 + 2 * tk.me.halfA, n, qm);
+      const T* CF = RA + t * raS;
+      const int i = li % n, yg = li / n;
+      T s1 = 0, s2 = 0, s3 = 0;
+      for (int xg = 0; xg < qm; ++xg) {
+        const int ra = tk.me.flipA ? qm - 1 - xg : xg;
+        const T ma = Ma[ra * n + i];
+        const int g = yg * qm + xg;
+        s1 += ma * CF[g] + Da[ra * n + i] * CF[QMM * QMM + g];
+        s2 += ma * CF[2 * QMM * QMM + g];
+        s3 += ma * CF[3 * QMM * QMM + g];
+      }
+      T* S = RB + t * rbS;
+      S[li] = s1;  // [y][i]
+      S[QMM * NM + li] = s2;
+      S[2 * QMM * NM + li] = s3;
+    });
+    __syncthreads();
+    // P6: second transposed pass (along b) into the per-face sums
+#define C6(t) (tasks[t].valid ? n2 : 0)
+    for_items(HPDG_COUNTS(C6), [&](int t, int li) {
+      const Task& tk = tasks[t];
+      const int qm = tk.qm;
+      const T* Mb = tab(L, 0 + 2 * tk.me.halfB, n, qm);
+      const T* Db = tab(L, 1 + 2 * tk.me.halfB, n, qm);
+      const T* S = RB + t * rbS;
+      const int i = li % n, j = li / n;
+      T yf = 0, yn = 0;
+      for (int yg = 0; yg < qm; ++yg) {
+        const int rb = tk.me.flipB ? qm - 1 - yg : yg;
+        const T mb = Mb[rb * n + j];
+        yf += mb * S[yg * n + i] + Db[rb * n + j] * S[QMM * NM + yg * n + i];
+        yn += mb * S[2 * QMM * NM + yg * n + i];
+      }
+      Yf[tk.f * NM * NM + li] += yf;
+      Yn[tk.f * NM * NM + li] += yn;
+    });
+    __syncthreads();
+  }
+  // face sums -> element: values on the face layer, normal-derivative part along the lines
+#undef C1
+#undef C2
+#undef C3
+#undef C4
+#undef C5
+#undef C6
+  for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) {
+    const int c0 = idx % n, c1 = (idx / n) % n, c2 = idx / n2;
+    T acc = sy[idx];
+#pragma unroll
+    for (int f = 0; f < kFaces; ++f) {
+      if (I.fcnt[f] == 0) continue;
+      const int d = f >> 1;
+      // node index along the normal axis and its (t0, t1) position on the face
+      const int kd = d == 0 ? c0 : (d == 1 ? c1 : c2);
+      const int li = d == 0 ? c2 * n + c1 : (d == 1 ? c2 * n + c0 : c1 * n + c0);
+      acc += dfo[(f & 1) * NM + kd] * Yn[f * NM * NM + li];
+      if (kd == ((f & 1) ? n - 1 : 0)) acc += Yf[f * NM * NM + li];
+    }
+    y[I.off + idx] = acc;
+  }
+}
+
+template <typename T, int N, int Q, bool UNI>
+void launch_fixed(const LevelView<T>& L, const int* elems, long long count, const T* x, T* y, size_t lds,
+                  hipStream_t s) {
+  hipLaunchKernelGGL((apply_kernel<T, N, Q, UNI>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
+                     count, x, y);
+}
+
+}  // namespace
+
+size_t apply_lds_bytes(int NM, int QM, int QMM, size_t scalar) { return Layout(NM, QM, QMM).bytes(scalar); }
+
+template <typename T>
+void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
+  if (L.n_elem == 0) return;
+  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T));
+  hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
+                     (const int*)nullptr, L.n_elem, x, y);
+}
+
+template <typename T>
+void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
+                         const T* x, T* y, hipStream_t s) {
+  if (count == 0) return;
+  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T));
+#define HPDG_CASE(NN, QQ)                                                                      \
+  if (n == NN && q == QQ)                                                                       \
+    return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds, s)               \
+                   : launch_fixed<T, NN, QQ, false>(L, elems, count, x, y, lds, s);
+  HPDG_CASE(2, 2) HPDG_CASE(2, 3) HPDG_CASE(3, 3) HPDG_CASE(3, 4) HPDG_CASE(4, 4) HPDG_CASE(4, 5)
+  HPDG_CASE(5, 5) HPDG_CASE(5, 6) HPDG_CASE(6, 6) HPDG_CASE(6, 7) HPDG_CASE(7, 7) HPDG_CASE(7, 8)
+  HPDG_CASE(8, 8) HPDG_CASE(8, 9)
+#undef HPDG_CASE
+  hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
+                     count, x, y);
+}
+
+template void launch_apply<double>(const LevelView<double>&, const double*, double*, hipStream_t);
+template void launch_apply<float>(const LevelView<float>&, const float*, float*, hipStream_t);
+template void launch_apply_bucket<double>(const LevelView<double>&, int, int, int, const int*, long long,
+                                          const double*, double*, hipStream_t);
+template void launch_apply_bucket<float>(const LevelView<float>&, int, int, int, const int*, long long,
+                                         const float*, float*, hipStream_t);
+
+}  // namespace hpdg

@@ -44,6 +44,11 @@ size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar);
 
 template <typename T>
 void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
+// apply restricted to the elements elems[0..count) that share degree n - 1 and q GL points;
+// uniform: every element of the level has (n, q) and every mortar q points per axis
+template <typename T>
+void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
+                         const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const TransferView<T>& V, const T* uc, T* uf, hipStream_t s);
 template <typename T>

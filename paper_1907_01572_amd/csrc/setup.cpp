@@ -205,6 +205,22 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     }
   }
   L.ndof = off;
+  {
+    std::vector<std::pair<std::pair<int, int>, int>> keyed;
+    for (size_t e = 0; e < E; ++e) keyed.push_back({{L.einfo[e].n, L.einfo[e].q}, int(e)});
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    L.bucket_n.clear(); L.bucket_q.clear(); L.bucket_start.clear(); L.bucket_elems.clear();
+    for (size_t i = 0; i < keyed.size(); ++i) {
+      if (i == 0 || keyed[i].first != keyed[i - 1].first) {
+        L.bucket_n.push_back(keyed[i].first.first);
+        L.bucket_q.push_back(keyed[i].first.second);
+        L.bucket_start.push_back((long long)i);
+      }
+      L.bucket_elems.push_back(keyed[i].second);
+    }
+    L.bucket_start.push_back((long long)keyed.size());
+  }
 
   // mortars
   const size_t M = L.mortars.size();
@@ -276,6 +292,9 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
     }
   }
+  L.uniform = L.bucket_n.size() == 1 ? 1 : 0;
+  for (const MortarInfo& I : L.minfo)
+    if (I.q != 0 && !L.bucket_q.empty() && I.q != L.bucket_q[0]) L.uniform = 0;
   L.fmlist.clear();
   for (size_t e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f) {

@@ -38,6 +38,11 @@ struct LevelHost {
   std::vector<double> diag;
   long long ndof = 0;
   int nmax = 0, qmax = 0, qmmax = 0;
+  // elements grouped by (n, q): kernels are specialised per group
+  std::vector<int> bucket_n, bucket_q;
+  std::vector<long long> bucket_start;
+  std::vector<int> bucket_elems;
+  int uniform = 0;  // one (n, q) for every element, q points per axis on every mortar
   // prolongation from the next coarser level: one record per element of this level
   std::vector<TransferInfo> tinfo;
   // restriction gathers: for each coarser element, the elements of this level inside it
