@@ -27,10 +27,10 @@ HBM_PEAK_GBS = 8000.0
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--n-cheb", type=int, default=6)
-    ap.add_argument("--Lambda", type=float, default=20.0)
+    ap.add_argument("--n-cheb", type=int, default=8)
+    ap.add_argument("--Lambda", type=float, default=100.0)
     ap.add_argument("--smoother", default="block", choices=["none", "point", "block"])
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--level", type=int, default=3)

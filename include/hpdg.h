@@ -103,7 +103,7 @@ typedef struct {
  * Discretisation parameters.
  *   penalty_C   C of Eq. penaltyparameter: sigma = C p_m^2 / h_m (default 10).
  *   quad_extra  extra GL points per axis on curved elements or with a variable
- *               coefficient (Sec. II.A.5 "higher order GL grids"; default 1).
+ *               coefficient (Sec. II.A.5 leaves the GL grid size open; default 1).
  *   coef_kind   HPDG_COEF_*: k = 1, or k = coef_params[1] for |x| < coef_params[0]
  *               and coef_params[2] otherwise.
  *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh).

@@ -423,23 +423,31 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
     HIPCHK(hipMalloc(&dptrs, cnt * sizeof(double*)));
     HIPCHK(hipMalloc(&info, cnt * sizeof(rocblas_int)));
     HIPCHK(hipMemcpyAsync(dptrs, ptrs.data(), cnt * sizeof(double*), hipMemcpyHostToDevice, s));
-    rocblas_status st1 = rocsolver_dpotrf_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt);
     std::vector<rocblas_int> hinfo(cnt);
-    HIPCHK(hipMemcpyAsync(hinfo.data(), info, cnt * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    bool ok = st1 == rocblas_status_success;
-    for (int v : hinfo) ok = ok && v == 0;
-    rocblas_status st2 = ok ? rocsolver_dpotri_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt)
-                            : rocblas_status_internal_error;
-    if (ok) {
+    // status of a batched call and its per-block info: the first failing block is reported
+    auto check = [&](rocblas_status st, const char* what) {
       HIPCHK(hipMemcpyAsync(hinfo.data(), info, cnt * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
-      ok = st2 == rocblas_status_success;
-      for (int v : hinfo) ok = ok && v == 0;
-    }
+      if (st != rocblas_status_success) {
+        (void)hipFree(dptrs);
+        (void)hipFree(info);
+        throw Error(HPDG_ERR_HIP, std::string(what) + " failed with rocblas status " + std::to_string(int(st)) +
+                                      " (level " + std::to_string(l) + ", block size " + std::to_string(N) +
+                                      ", " + std::to_string(cnt) + " blocks)");
+      }
+      for (int b = 0; b < cnt; ++b)
+        if (hinfo[b] != 0) {
+          (void)hipFree(dptrs);
+          (void)hipFree(info);
+          throw Error(HPDG_ERR_BREAKDOWN, std::string(what) + ": element block " + std::to_string(b) +
+                                              " of size " + std::to_string(N) + " on level " + std::to_string(l) +
+                                              " is not positive definite (info " + std::to_string(hinfo[b]) + ")");
+        }
+    };
+    check(rocsolver_dpotrf_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt), "Cholesky");
+    check(rocsolver_dpotri_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt), "inverse");
     (void)hipFree(dptrs);
     (void)hipFree(info);
-    if (!ok) throw Error(HPDG_ERR_BREAKDOWN, "an element block is not positive definite");
   }
   launch_symmetrize_blocks<double>(V, d.boff, B, s);
   d.binv = B;
