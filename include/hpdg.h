@@ -57,7 +57,8 @@ enum { HPDG_MAP_AFFINE = 0, HPDG_MAP_SHELL = 1, HPDG_MAP_CUBE_SPHERE = 2 };
 enum { HPDG_BC_INTERIOR = 0, HPDG_BC_DIRICHLET = 1, HPDG_BC_NEUMANN = 2 };
 enum { HPDG_COEF_CONSTANT = 0, HPDG_COEF_RADIAL_STEP = 1 };
 enum { HPDG_RHS_SINSINSIN = 0, HPDG_RHS_SHELL_HARMONIC = 1, HPDG_RHS_RADIAL_STEP = 2,
-       HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4 };
+       HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4, HPDG_RHS_POLYNOMIAL_DIRICHLET = 5 };
+enum { HPDG_NL_PUNCTURE = 0, HPDG_NL_QUADRATIC = 1 };
 enum { HPDG_SOLVER_FCG = 0, HPDG_SOLVER_PCG = 1 };
 
 typedef struct hpdg_ctx hpdg_ctx;
@@ -109,6 +110,10 @@ typedef struct {
  *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh).
  *   build_f32   also build FP32 copies of every level (needed by HPDG_F32 calls and
  *               mixed-precision solves).
+ *   mass_term   1: every level carries a mass form  sum_sigma w det J c u v  with c set per
+ *               volume GL point by hpdg_nonlinear_linearize / hpdg_newton_solve (zero
+ *               until then); the volume rule then has p + 1 + quad_extra points on every
+ *               element.  Needed by the nonlinear calls.
  */
 typedef struct {
   double penalty_C;
@@ -117,6 +122,7 @@ typedef struct {
   double coef_params[4];
   int32_t max_levels;
   int32_t build_f32;
+  int32_t mass_term;
 } hpdg_disc_params;
 
 typedef struct {
@@ -168,6 +174,38 @@ typedef struct {
   const double* params;
 } hpdg_rhs_desc;
 
+/* Semilinear source of  -lap u = beta(x) (1 + alpha(x) u)^-7  (the puncture equation of
+ * Sec. III.D, Eq. Two_Punctures_PDE, for the regular part u, with psi = (1 + alpha u) /
+ * alpha).  Parameters (copied):
+ *   HPDG_NL_PUNCTURE   [s, then rows (cx, cy, cz, m, a)]:
+ *                      alpha = 1 / (1 + sum_I m_I / (2 |x - c_I|)),
+ *                      beta = sum_I a_I exp(-|x - c_I|^2 / (2 s^2)) / (1 + |x|^2)^2;
+ *   HPDG_NL_QUADRATIC  [alpha, C[a][b][c] (27 values, x^a y^b z^c, a, b, c <= 2)]:
+ *                      constant alpha, beta = (-lap u*) (1 + alpha u*)^7 for the quadratic
+ *                      u* (a manufactured problem whose exact solution is u*). */
+typedef struct {
+  int32_t kind;
+  int32_t n_params;
+  const double* params;
+} hpdg_nonlinear_desc;
+
+/* Newton-Krylov parameters (Alg. 1 with FCG, Alg. 2, as the linear solver). */
+typedef struct {
+  double tol_rel;        /* stop when |R(u_k)|_2 <= tol_rel |R(u_0)|_2 */
+  double lin_tol_rel;    /* FCG tolerance of each correction, relative to |R(u_k)|_2 */
+  int32_t max_newton;
+  int32_t max_lin_iter;  /* FCG iteration cap per Newton step */
+  int32_t precision;     /* HPDG_PREC_F64 or HPDG_PREC_MIXED V-cycle */
+} hpdg_newton_params;
+
+typedef struct {
+  int32_t newton_steps;
+  int32_t linear_iterations;  /* FCG iterations summed over the Newton steps */
+  double rel_residual;        /* |R(u)| / |R(u_0)| at exit */
+  double solve_ms;            /* wall time (host clock, synchronised) */
+  int32_t status;             /* the return code */
+} hpdg_newton_stats;
+
 /* Create a context on HIP device ``hip_device``; device memory of all its meshes is
  * limited to ``hbm_budget_bytes`` (0 = no limit). */
 int hpdg_create(hpdg_ctx** out, int hip_device, size_t hbm_budget_bytes);
@@ -215,10 +253,44 @@ int hpdg_vcycle(hpdg_mesh* mesh, int prec, const void* r_dev, void* z_dev, void*
 int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b_dev,
                double* u_dev, hpdg_solve_stats* stats, void* stream);
 
-/* Sum of the kernel time of the last ``hpdg_apply`` calls measured with HIP events on
- * their stream: enable with on = 1, read and reset with hpdg_apply_timing(). */
-int hpdg_apply_timing_enable(hpdg_mesh* mesh, int on);
-int hpdg_apply_timing(hpdg_mesh* mesh, double* total_ms, int64_t* n_calls);
+/* Nonlinear residual R(u) = A u - N(u) - F (Eq. Ru=0 discretised):
+ * N(u)_psi = sum_sigma w det J beta (1 + alpha u)^-7 psi at the volume GL points; F_dev may
+ * be NULL (F = 0), else the level-0 F (e.g. from hpdg_assemble_rhs).  FP64 level-0
+ * vectors; R_dev must differ from u_dev and F_dev.  Needs a mesh uploaded with
+ * mass_term = 1.  Returns HPDG_ERR_BREAKDOWN when 1 + alpha u <= 0 at a GL point. */
+int hpdg_nonlinear_residual(hpdg_mesh* mesh, const hpdg_nonlinear_desc* nl, const double* F_dev,
+                            const double* u_dev, double* R_dev, void* stream);
+/* Linearise at u (Eq. newtoncorrectionsystem): every level's mass coefficient becomes
+ * w det J 7 alpha beta (1 + alpha u_l)^-8 with u_0 = u and u_{l+1} injected from u_l (each
+ * coarse LGL node takes the value of the finer child containing it; nodes on the cut
+ * belong to the lower child); then the point-Jacobi scaling, the spectral bounds (Alg. 5)
+ * and the coarsest inverse are recomputed.  Afterwards hpdg_apply on level l applies the
+ * Jacobian J_l = A_l + M_l(u_l).  Needs hpdg_setup_smoother first (scaling NONE or POINT;
+ * BLOCK returns HPDG_ERR_UNSUPPORTED).  Synchronises ``stream``. */
+int hpdg_nonlinear_linearize(hpdg_mesh* mesh, const hpdg_nonlinear_desc* nl, const double* u_dev,
+                             void* stream);
+/* Newton-Krylov (Alg. 1): u_{k+1} = u_k + delta, J(u_k) delta = -R(u_k) solved by FCG
+ * with the V-cycle of the linearised levels, until |R(u_k)| <= tol_rel |R(u_0)| or
+ * max_newton steps.  u_dev: initial guess on entry, solution on exit (FP64 level 0).
+ * ``stats`` is filled even on failure; HPDG_ERR_NOT_CONVERGED leaves the last iterate. */
+int hpdg_newton_solve(hpdg_mesh* mesh, const hpdg_newton_params* params, const hpdg_nonlinear_desc* nl,
+                      const double* F_dev, double* u_dev, hpdg_newton_stats* stats, void* stream);
+
+/* Kernel timing for measurement.  While enabled (every = k > 0), every k-th operator
+ * application of each (kind, level, precision) (HPDG_TIMING_APPLY: hpdg_apply and the
+ * applies inside hpdg_smooth, hpdg_vcycle and hpdg_solve) and every k-th block-Jacobi
+ * Chebyshev step (HPDG_TIMING_BLOCK) is bracketed by two HIP events on its stream, and
+ * the algorithmic bytes of the launch are recorded (every = 0 disables):
+ *   apply: 2 s N (x read, y written) + s (volume + mortar metric scalars) + record bytes;
+ *   block step: s (sum_e (n_e^3)^2) (inverse blocks) + s N per vector read or written.
+ * (s = 8 for HPDG_F64, 4 for HPDG_F32; N = level DOF.)  hpdg_kernel_timing() waits for
+ * the recorded events and returns, for one (kind, level, prec), the summed event time in
+ * ms, the number of launches and the summed algorithmic bytes since the previous read of
+ * that entry, then resets the entry.  Recording costs two event records per launch. */
+enum { HPDG_TIMING_APPLY = 0, HPDG_TIMING_BLOCK = 1, HPDG_TIMING_KINDS = 2 };
+int hpdg_timing_enable(hpdg_mesh* mesh, int every);
+int hpdg_kernel_timing(hpdg_mesh* mesh, int kind, int level, int prec, double* total_ms, int64_t* launches,
+                       double* alg_bytes);
 
 #ifdef __cplusplus
 }

@@ -40,5 +40,6 @@ from .meshes import (  # noqa: F401
 )
 from .problems import (  # noqa: F401
     problem_config1, problem_config2, problem_config3, random_vector,
-    dof_count,
+    dof_count, polynomial_problem, gaussian_problem, polynomial_dirichlet_problem,
+    puncture_problem, quadratic_nonlinear_problem,
 )

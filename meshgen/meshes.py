@@ -152,8 +152,65 @@ def hp_sphere_cube(level=5, p_lo=2, p_hi=7, seed=0, r_cut=0.5):
     return mesh
 
 
-def puncture_mesh(*args, **kwargs):
-    raise NotImplementedError("the puncture macro-mesh is not generated yet")
+def puncture_mesh(level=2, p=6, punctures=None, n_ref=5, reach=3.0, r_cube=10.0, r_sphere=20.0, r_out=1e11):
+    """Cube with a compactified exterior (13 macros) refined around punctures (config 4).
+
+    Macros: the central cube [-r_cube, r_cube]^3 (affine), six cube-to-sphere wedges from
+    its faces to the sphere r_sphere, six shell wedges from r_sphere to r_out with the
+    inverse-radius (compactified) radial map.  Every macro is refined to ``level``; then,
+    ``n_ref`` times, every cell of the central cube whose centre lies within ``reach`` cell
+    diameters of a puncture centre is refined, each pass followed by 2:1 balance.
+    ``punctures``: array of centres [K, 3] (e.g. the rows of ``puncture_problem``).
+    Dirichlet data on r = r_out.
+    """
+    hexes, kinds, params = [], [], []
+    # central cube
+    hexes.append([(tuple(int(2 * ((c >> d) & 1) - 1) for d in range(3)), 0) for c in range(8)])
+    par = np.zeros(16)
+    par[0:3] = -r_cube
+    par[3], par[7], par[11] = 2 * r_cube, 2 * r_cube, 2 * r_cube
+    kinds.append(AFFINE)
+    params.append(par)
+    for layer in (0, 1):
+        for R in SHELL_FRAMES:
+            v = []
+            for c in range(8):
+                c0, c1, c2 = c & 1, (c >> 1) & 1, (c >> 2) & 1
+                d = R @ np.array([2 * c0 - 1, 2 * c1 - 1, 1])
+                v.append((tuple(int(x) for x in d), layer + c2))
+            hexes.append(v)
+            par = np.zeros(16)
+            par[0:9] = R.reshape(-1)
+            if layer == 0:
+                par[10], par[11] = r_cube, r_sphere
+                kinds.append(CUBE_SPHERE)
+            else:
+                par[9], par[10], par[11] = 1, r_sphere, r_out
+                par[12], par[13] = 0.0, r_sphere  # (break of the piecewise map: unused here)
+                kinds.append(SHELL)
+            params.append(par)
+    forest = _forest_for(hexes)
+    for _ in range(level):
+        forest.refine_where(lambda key: True)
+    centres = np.zeros((0, 3)) if punctures is None else np.asarray(punctures, float).reshape(-1, 3)
+
+    def near(key):
+        m, l, i, j, k = key
+        if m != 0 or len(centres) == 0:
+            return False
+        h = 2.0 * r_cube / (1 << l)
+        ctr = -r_cube + h * (np.array([i, j, k]) + 0.5)
+        return np.min(np.linalg.norm(centres - ctr, axis=1)) <= reach * h * np.sqrt(3.0)
+
+    for _ in range(n_ref):
+        forest.refine_where(near)
+        forest.balance()
+
+    def bc(m, f):
+        return BC_DIRICHLET
+
+    return _finish(kinds, params, hexes, bc, forest, lambda key: p,
+                   dict(name="puncture_l%d_p%d_r%d" % (level, p, n_ref)))
 
 
 def mesh_summary(mesh):

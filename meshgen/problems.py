@@ -57,6 +57,53 @@ def gaussian_problem(n=8, lo=(-1, -1, -1), hi=(1, 1, 1), seed=0):
     return dict(kind="gaussians", params=np.array(rows, float).reshape(-1))
 
 
+def polynomial_dirichlet_problem(C):
+    """Dirichlet data u = sum C[a,b,c] x^a y^b z^c with no volume source (g = 0)."""
+    C = np.asarray(C, float)
+    return dict(kind="polynomial_dirichlet", params=C.reshape(-1), shape=C.shape)
+
+
+def puncture_problem(n_punctures=3, seed=0, r_ball=8.0, m_range=(0.3, 1.0), p_max=0.2, s=2.0):
+    """Nonlinear source of the puncture-type problem  -lap u = beta (1 + alpha u)^-7.
+
+    Seeded punctures: centres c_I uniform in the ball |x| < r_ball, masses m_I uniform in
+    ``m_range``, momenta P_I with uniform direction and |P_I| uniform in [0, p_max].  Then
+    alpha = 1 / (1 + sum_I m_I / (2 |x - c_I|)) and
+    beta = sum_I |P_I|^2 exp(-|x - c_I|^2 / (2 s^2)) / (1 + |x|^2)^2 (a smooth decaying
+    field standing in for the extrinsic-curvature term).
+    params = [s, then rows (cx, cy, cz, m, a = |P|^2)].
+    """
+    rng = np.random.default_rng(seed)
+    rows = []
+    while len(rows) < n_punctures:
+        c = rng.uniform(-r_ball, r_ball, 3)
+        if np.linalg.norm(c) >= r_ball:
+            continue
+        m = rng.uniform(*m_range)
+        d = rng.standard_normal(3)
+        P = d / np.linalg.norm(d) * rng.uniform(0.0, p_max)
+        rows.append([c[0], c[1], c[2], m, float(P @ P)])
+    return dict(kind="puncture", params=np.concatenate([[s], np.array(rows).reshape(-1)]))
+
+
+def quadratic_nonlinear_problem(alpha=0.5, seed=0):
+    """Manufactured nonlinear problem with a quadratic exact solution.
+
+    u* = 0.5 - 0.3 |x|^2 + (seeded linear terms, |b_i| <= 0.05); alpha constant; the source
+    is chosen so that u* solves -lap u = beta (1 + alpha u)^-7, i.e.
+    beta = (-lap u*) (1 + alpha u*)^7 with -lap u* = 1.8.
+    params = [alpha, then the 27 coefficients C[a, b, c] of x^a y^b z^c (a, b, c <= 2)].
+    Use with Dirichlet data u* (``polynomial_dirichlet_problem(C)``).
+    """
+    rng = np.random.default_rng(seed)
+    C = np.zeros((3, 3, 3))
+    C[0, 0, 0] = 0.5
+    C[2, 0, 0] = C[0, 2, 0] = C[0, 0, 2] = -0.3
+    b = rng.uniform(-0.05, 0.05, 3)
+    C[1, 0, 0], C[0, 1, 0], C[0, 0, 1] = b
+    return dict(kind="nl_quadratic", params=np.concatenate([[alpha], C.reshape(-1)])), C
+
+
 def dof_count(mesh):
     return int(np.sum((mesh["elem_p"].astype(np.int64) + 1) ** 3))
 

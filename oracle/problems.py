@@ -47,6 +47,8 @@ def exact_u(problem, x):
         return u
     if kind == "gaussians":
         return np.zeros(x.shape[:-1])  # only used as Dirichlet data (g_D = 0)
+    if kind == "polynomial_dirichlet":
+        return exact_u(dict(kind="polynomial", params=problem["params"]), x)
     raise ValueError(kind)
 
 
@@ -84,6 +86,8 @@ def source_g(problem, x):
             d2 = (X - cx) ** 2 + (Y - cy) ** 2 + (Z - cz) ** 2
             g += a * np.exp(-d2 / (2.0 * s * s))
         return g
+    if kind == "polynomial_dirichlet":
+        return np.zeros(x.shape[:-1])  # Dirichlet data only
     raise ValueError(kind)
 
 
@@ -95,3 +99,33 @@ def _poly_coeffs(problem):
     C = np.asarray(problem["params"], float)
     P = int(round(len(C) ** (1.0 / 3.0)))
     return C.reshape(P, P, P)
+
+
+def nl_alpha_beta(nl, x):
+    """alpha(x), beta(x) of the nonlinear source  -lap u = beta (1 + alpha u)^-7.
+
+    ``puncture``: alpha = 1 / (1 + sum_I m_I / (2 r_I)), r_I = |x - c_I| (the puncture sum
+    of Sec. III.D written as psi = (1 + alpha u) / alpha), and a smooth decaying
+    beta = sum_I a_I exp(-r_I^2 / (2 s^2)) / (1 + |x|^2)^2; params = [s, rows (c, m, a)].
+    ``nl_quadratic``: alpha constant, beta = (-lap u*) (1 + alpha u*)^7 for the quadratic
+    u* of params[1:] (so that u* is an exact solution); params = [alpha, C (27)].
+    """
+    kind = nl["kind"]
+    P = np.asarray(nl["params"], float)
+    if kind == "puncture":
+        s = P[0]
+        rows = P[1:].reshape(-1, 5)
+        psum = np.zeros(x.shape[:-1])
+        beta = np.zeros(x.shape[:-1])
+        for cx, cy, cz, m, a in rows:
+            r2 = (x[..., 0] - cx) ** 2 + (x[..., 1] - cy) ** 2 + (x[..., 2] - cz) ** 2
+            psum += m / (2.0 * np.sqrt(r2))
+            beta += a * np.exp(-r2 / (2.0 * s * s))
+        beta /= (1.0 + np.sum(x * x, axis=-1)) ** 2
+        return 1.0 / (1.0 + psum), beta
+    if kind == "nl_quadratic":
+        alpha = P[0]
+        poly = dict(kind="polynomial", params=P[1:])
+        u = exact_u(poly, x)
+        return np.full(x.shape[:-1], alpha), source_g(poly, x) * (1.0 + alpha * u) ** 7
+    raise ValueError(kind)

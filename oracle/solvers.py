@@ -160,6 +160,12 @@ class Multigrid:
         self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
         self.n_cheb, self.Lambda = n_cheb, Lambda
         self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")
+        self.refresh(n_eigs, seed, lam)
+
+    def refresh(self, n_eigs=15, seed=0, lam=None):
+        """(Re)compute what depends on the level operators: the smoother scaling, the
+        coarsest factorisation and the frozen spectral bounds (given ``lam`` or by Alg. 5
+        from a seeded uniform start vector)."""
         self.minv = [self._make_minv(op) for op in self.ops[:-1]]
         A0 = np.column_stack([self.ops[-1].apply(e) for e in np.eye(self.ops[-1].ndof)])
         self.A0 = 0.5 * (A0 + A0.T)

@@ -22,12 +22,16 @@ PREC_F64, PREC_MIXED = 0, 1
 SOLVER_FCG, SOLVER_PCG = 0, 1
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 SMOOTHERS = {"none": 0, "point": 1, "block": 2}
-RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4}
+TIMING_KINDS = {"apply": 0, "block": 1}
+RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4,
+           "polynomial_dirichlet": 5}
+NL_IDS = {"puncture": 0, "nl_quadratic": 1}
 
 EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload", "hpdg_mesh_info_get",
             "hpdg_level_cells", "hpdg_mesh_free", "hpdg_assemble_rhs", "hpdg_apply",
             "hpdg_setup_smoother", "hpdg_smooth", "hpdg_vcycle", "hpdg_solve",
-            "hpdg_apply_timing_enable", "hpdg_apply_timing"]
+            "hpdg_nonlinear_residual", "hpdg_nonlinear_linearize", "hpdg_newton_solve",
+            "hpdg_timing_enable", "hpdg_kernel_timing"]
 
 
 class HpdgError(RuntimeError):
@@ -48,7 +52,7 @@ class MeshDesc(ctypes.Structure):
 class DiscParams(ctypes.Structure):
     _fields_ = [("penalty_C", ctypes.c_double), ("quad_extra", ctypes.c_int32),
                 ("coef_kind", ctypes.c_int32), ("coef_params", ctypes.c_double * 4),
-                ("max_levels", ctypes.c_int32), ("build_f32", ctypes.c_int32)]
+                ("max_levels", ctypes.c_int32), ("build_f32", ctypes.c_int32), ("mass_term", ctypes.c_int32)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -75,6 +79,20 @@ class SolveStats(ctypes.Structure):
 
 class RhsDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_params", ctypes.c_int32), ("params", ctypes.c_void_p)]
+
+
+class NonlinearDesc(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("n_params", ctypes.c_int32), ("params", ctypes.c_void_p)]
+
+
+class NewtonParams(ctypes.Structure):
+    _fields_ = [("tol_rel", ctypes.c_double), ("lin_tol_rel", ctypes.c_double), ("max_newton", ctypes.c_int32),
+                ("max_lin_iter", ctypes.c_int32), ("precision", ctypes.c_int32)]
+
+
+class NewtonStats(ctypes.Structure):
+    _fields_ = [("newton_steps", ctypes.c_int32), ("linear_iterations", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("solve_ms", ctypes.c_double), ("status", ctypes.c_int32)]
 
 
 _lib = None
@@ -104,8 +122,13 @@ def load_library(path=LIB_PATH):
     lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
     lib.hpdg_solve.argtypes = [vp, ctypes.POINTER(SolveParams), vp, vp, ctypes.POINTER(SolveStats), vp]
-    lib.hpdg_apply_timing_enable.argtypes = [vp, i32]
-    lib.hpdg_apply_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    lib.hpdg_nonlinear_residual.argtypes = [vp, ctypes.POINTER(NonlinearDesc), vp, vp, vp, vp]
+    lib.hpdg_nonlinear_linearize.argtypes = [vp, ctypes.POINTER(NonlinearDesc), vp, vp]
+    lib.hpdg_newton_solve.argtypes = [vp, ctypes.POINTER(NewtonParams), ctypes.POINTER(NonlinearDesc), vp, vp,
+                                      ctypes.POINTER(NewtonStats), vp]
+    lib.hpdg_timing_enable.argtypes = [vp, i32]
+    lib.hpdg_kernel_timing.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
+                                       ctypes.POINTER(ctypes.c_double)]
     _lib = lib
     return lib
 
@@ -138,8 +161,9 @@ class Context:
         return rc
 
     def upload(self, mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False,
-               stream=None):
-        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream)
+               stream=None, mass_term=False):
+        """``mass_term``: levels carry the Newton mass form (needed by the nonlinear calls)."""
+        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term)
 
     def close(self):
         if self.h:
@@ -165,7 +189,7 @@ def coef_from_problem(problem):
 class Mesh:
     """An uploaded mesh: level hierarchy, geometry and solver state on the device."""
 
-    def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream):
+    def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term=False):
         self.ctx, self.lib = ctx, ctx.lib
         keep = dict(
             macro_kind=np.ascontiguousarray(mesh["macro_kind"], np.int32),
@@ -192,6 +216,7 @@ class Mesh:
             dp.coef_params[i] = params[i]
         dp.max_levels = max_levels
         dp.build_f32 = 1 if build_f32 else 0
+        dp.mass_term = 1 if mass_term else 0
         self.h = ctypes.c_void_p()
         ctx.check(self.lib.hpdg_mesh_upload(ctx.h, ctypes.byref(d), ctypes.byref(dp),
                                             ctypes.byref(self.h), _stream(stream)))
@@ -264,14 +289,52 @@ class Mesh:
         return dict(iterations=st.iterations, rel_residual=st.rel_residual, solve_ms=st.solve_ms,
                     status=st.status)
 
-    def timing_enable(self, on=True):
-        self.ctx.check(self.lib.hpdg_apply_timing_enable(self.h, 1 if on else 0))
+    def _nl(self, nl):
+        params = np.ascontiguousarray(nl["params"], np.float64).reshape(-1)
+        d = NonlinearDesc()
+        d.kind = NL_IDS[nl["kind"]]
+        d.n_params = len(params)
+        d.params = params.ctypes.data
+        return d, params
 
-    def timing(self):
+    def nonlinear_residual(self, nl, u, R, F=None, stream=None):
+        """R = A u - N(u) - F (F None: zero)."""
+        d, keep = self._nl(nl)
+        self.ctx.check(self.lib.hpdg_nonlinear_residual(self.h, ctypes.byref(d), _ptr(F) if F is not None else None,
+                                                        _ptr(u), _ptr(R), _stream(stream)))
+
+    def linearize(self, nl, u, stream=None):
+        """Set every level's Jacobian mass term from u; afterwards ``apply`` applies J."""
+        d, keep = self._nl(nl)
+        self.ctx.check(self.lib.hpdg_nonlinear_linearize(self.h, ctypes.byref(d), _ptr(u), _stream(stream)))
+
+    def newton_solve(self, nl, u, F=None, tol=1e-10, lin_tol=1e-6, max_newton=30, max_lin_iter=500,
+                     precision=PREC_F64, stream=None, raise_on_error=True):
+        d, keep = self._nl(nl)
+        p = NewtonParams(tol, lin_tol, max_newton, max_lin_iter, precision)
+        st = NewtonStats()
+        rc = self.lib.hpdg_newton_solve(self.h, ctypes.byref(p), ctypes.byref(d),
+                                        _ptr(F) if F is not None else None, _ptr(u), ctypes.byref(st),
+                                        _stream(stream))
+        if raise_on_error:
+            self.ctx.check(rc)
+        return dict(newton_steps=st.newton_steps, linear_iterations=st.linear_iterations,
+                    rel_residual=st.rel_residual, solve_ms=st.solve_ms, status=st.status)
+
+    def timing_enable(self, every=1):
+        """Time every ``every``-th launch of each kernel kind / level / precision (0: off)."""
+        self.ctx.check(self.lib.hpdg_timing_enable(self.h, int(every)))
+
+    def kernel_timing(self, kind="apply", level=0, prec=F64):
+        """(total ms, launches, algorithmic bytes) recorded for one kernel kind, level and
+        precision since the previous read of that entry; the entry is then reset."""
         ms = ctypes.c_double()
         n = ctypes.c_int64()
-        self.ctx.check(self.lib.hpdg_apply_timing(self.h, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value, n.value
+        b = ctypes.c_double()
+        k = TIMING_KINDS[kind]
+        self.ctx.check(self.lib.hpdg_kernel_timing(self.h, k, level, prec, ctypes.byref(ms), ctypes.byref(n),
+                                                   ctypes.byref(b)))
+        return ms.value, n.value, b.value
 
     def free(self):
         if self.h:

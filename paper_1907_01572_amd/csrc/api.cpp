@@ -54,6 +54,11 @@ struct DevLevel {
   long long* boff = nullptr;  // element-block Jacobi: offsets of the inverse blocks
   T* binv = nullptr;
   int* belems = nullptr;      // element ids grouped by (n, q)
+  // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
+  T* mcoef = nullptr;
+  T* diag = nullptr;
+  double* nl_alpha = nullptr;  // alpha and w det J beta at the GL points (FP64 levels only)
+  double* nl_wbeta = nullptr;
 };
 
 }  // namespace
@@ -82,15 +87,34 @@ struct hpdg_mesh {
   hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0};
   bool smoother_ready = false;
   rocblas_handle blas = nullptr;  // batched Cholesky of the element blocks (setup only)
+  // nonlinear source (Newton)
+  bool mass_on = true;            // false: applies leave out the mass term (the residual's A u)
+  std::vector<double> nl_key;     // kind and parameters of the source the GL tables hold
+  int* bad = nullptr;             // device flag: 1 + alpha u <= 0 somewhere
+  int* host_bad = nullptr;        // pinned
+  double *nl_b = nullptr, *nl_rhs = nullptr, *nl_delta = nullptr;  // Newton: R, -R, correction
   // Krylov work
   double *r = nullptr, *vv = nullptr, *w = nullptr, *d = nullptr, *q = nullptr;
   double *partials = nullptr, *sc = nullptr;
   double* host_sc = nullptr;  // pinned
-  // apply timing
+  // kernel timing: HIP events around every timing_every-th operator apply and block-smoother
+  // step of each (kind, level, precision)
   bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> events;
-  double timed_ms = 0;
-  long long timed_calls = 0;
+  int timing_every = 1;
+  long long timing_count[HPDG_TIMING_KINDS][32][2] = {};
+  struct Timed {
+    hipEvent_t a, b;
+    int kind, level, prec;
+    double bytes;
+  };
+  struct Acc {
+    double ms = 0, bytes = 0;
+    long long calls = 0;
+  };
+  std::vector<long long> block_scalars = std::vector<long long>(32, 0);  // inverse-block scalars per level
+  std::vector<Timed> pending;
+  std::vector<hipEvent_t> event_pool;
+  Acc acc[HPDG_TIMING_KINDS][32][2];
 
   template <typename T>
   T* alloc(size_t count) {
@@ -124,12 +148,14 @@ struct hpdg_mesh {
     return ptr;
   }
   ~hpdg_mesh() {
-    for (auto& ev : events) {
-      (void)hipEventDestroy(ev.first);
-      (void)hipEventDestroy(ev.second);
+    for (auto& ev : pending) {
+      (void)hipEventDestroy(ev.a);
+      (void)hipEventDestroy(ev.b);
     }
+    for (auto ev : event_pool) (void)hipEventDestroy(ev);
     for (void* ptr : allocs) (void)hipFree(ptr);
     if (host_sc) (void)hipHostFree(host_sc);
+    if (host_bad) (void)hipHostFree(host_bad);
     if (blas) rocblas_destroy_handle(blas);
     if (ctx) ctx->used -= std::min(ctx->used, bytes);
   }
@@ -173,6 +199,7 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.fmlist = d.fmlist;
   v.vgeo = d.vgeo;
   v.mgeo = d.mgeo;
+  v.mcoef = mass_on ? d.mcoef : nullptr;
   v.tab = table<T>();
   v.tv = tabview();
   v.n_elem = (long long)h.cells.size();
@@ -239,6 +266,11 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
     d.cstart = M->upload_raw(h.cstart, s);
     d.clist = M->upload_raw(h.clist, s);
   }
+  if (h.nmq > 0) {
+    d.mcoef = M->alloc<T>(size_t(h.nmq));
+    launch_fill<T>(h.nmq, T(0), d.mcoef, s);
+    d.diag = M->upload<T>(h.diag, s);
+  }
   const size_t n = size_t(h.ndof);
   d.f = M->alloc<T>(n);
   d.v = M->alloc<T>(n);
@@ -246,14 +278,68 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
   d.p = M->alloc<T>(n);
 }
 
+// ---- kernel timing ----------------------------------------------------------------
+hipEvent_t take_event(hpdg_mesh* M) {
+  if (!M->event_pool.empty()) {
+    hipEvent_t e = M->event_pool.back();
+    M->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  HIPCHK(hipEventCreate(&e));
+  return e;
+}
+
+// run f() between two events on s when timing is enabled
+template <typename F>
+void timed(hpdg_mesh* M, int kind, int level, int prec, double bytes, hipStream_t s, F&& f) {
+  if (!M->timing || level >= 32 || (M->timing_count[kind][level][prec]++ % M->timing_every) != 0) {
+    f();
+    return;
+  }
+  hipEvent_t a = take_event(M);
+  HIPCHK(hipEventRecord(a, s));
+  f();
+  hipEvent_t b = take_event(M);
+  HIPCHK(hipEventRecord(b, s));
+  M->pending.push_back({a, b, kind, level, prec, bytes});
+}
+
+void collect_timing(hpdg_mesh* M) {
+  for (auto& t : M->pending) {
+    HIPCHK(hipEventSynchronize(t.b));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, t.a, t.b));
+    hpdg_mesh::Acc& a = M->acc[t.kind][t.level][t.prec];
+    a.ms += ms;
+    a.bytes += t.bytes;
+    a.calls += 1;
+    M->event_pool.push_back(t.a);
+    M->event_pool.push_back(t.b);
+  }
+  M->pending.clear();
+}
+
+// algorithmic bytes of one apply of level l: x read and y written once, the stored
+// metric once, the element / mortar / face-list records once
+double apply_bytes(const hpdg_mesh* M, int l, size_t scalar) {
+  const LevelHost& h = M->H[l];
+  return double(scalar) * (2.0 * double(h.ndof) + double(h.vgeo.size()) + double(h.mgeo.size())) +
+         double(h.einfo.size() * sizeof(ElemInfo) + h.minfo.size() * sizeof(MortarInfo) +
+                h.fmlist.size() * sizeof(int));
+}
+
 template <typename T>
 void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
   const LevelHost& h = M->H[l];
   const LevelView<T> V = M->view<T>(l);
   const int* be = M->lev<T>(l).belems;
-  for (size_t b = 0; b < h.bucket_n.size(); ++b)
-    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
-                           h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
+  const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
+  timed(M, HPDG_TIMING_APPLY, l, prec, M->timing ? apply_bytes(M, l, sizeof(T)) : 0.0, s, [&] {
+    for (size_t b = 0; b < h.bucket_n.size(); ++b)
+      launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
+                             h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
+  });
 }
 
 // Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)
@@ -280,9 +366,14 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
     else
       alpha = 1.0 / (dd - alpha * c * c / 4.0);
     const double beta = alpha * dd - 1.0;
-    if (block)
-      launch_block_cheb<T>(M->view<T>(l), d.boff, d.binv, b, Ax, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
-    else
+    if (block) {
+      // inverse blocks, b, Ax (when given), p (read after the first step, written), x (read, written)
+      const double vec = double(n) * (1 + (Ax ? 1 : 0) + (k == 1 ? 1 : 2) + 2);
+      const double bytes = M->timing ? double(sizeof(T)) * (double(M->block_scalars[l]) + vec) : 0.0;
+      timed(M, HPDG_TIMING_BLOCK, l, sizeof(T) == 4 ? HPDG_F32 : HPDG_F64, bytes, s, [&] {
+        launch_block_cheb<T>(M->view<T>(l), d.boff, d.binv, b, Ax, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
+      });
+    } else
       launch_cheb_update<T>(n, b, Ax, dinv, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
   }
 }
@@ -391,6 +482,7 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
     const long long N = (long long)h.einfo[e].n * h.einfo[e].n * h.einfo[e].n;
     boff[e + 1] = boff[e] + N * N;
   }
+  M->block_scalars[l] = boff[E];
   d.boff = M->upload_raw(boff, s);
   double* B = M->alloc<double>(size_t(boff[E]));
   LevelView<double> V = M->view<double>(l);
@@ -460,59 +552,227 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
-// exact coarse solve: assemble the coarsest operator column by column, invert (Cholesky)
+// exact coarse solve: the coarsest operator assembled column by column on the device (one
+// apply per unit vector), symmetrised, factorised (Cholesky) and inverted with rocSOLVER;
+// the explicit inverse is applied as a dense mat-vec in the V-cycle
 void build_coarse(hpdg_mesh* M, hipStream_t s) {
   const int L = M->nlevels() - 1;
   const int n = int(M->H[L].ndof);
   M->ncoarse = n;
   DevLevel<double>& d = M->lev<double>(L);
-  std::vector<double> A(size_t(n) * n), col(n);
+  if (!M->Ainv64) M->Ainv64 = M->alloc<double>(size_t(n) * n);
+  if (M->has_f32 && !M->Ainv32) M->Ainv32 = M->alloc<float>(size_t(n) * n);
+  double* A = M->Ainv64;
+  launch_fill<double>(n, 0.0, d.f, s);
   for (int j = 0; j < n; ++j) {
-    launch_fill<double>(n, 0.0, d.f, s);
-    const double one = 1.0;
-    HIPCHK(hipMemcpyAsync(d.f + j, &one, sizeof(double), hipMemcpyHostToDevice, s));
+    launch_fill<double>(1, 1.0, d.f + j, s);
     apply_level<double>(M, L, d.f, d.t, s);
-    HIPCHK(hipMemcpyAsync(col.data(), d.t, n * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(A + size_t(j) * n, d.t, n * sizeof(double), hipMemcpyDeviceToDevice, s));
+    launch_fill<double>(1, 0.0, d.f + j, s);
+  }
+  launch_symmetrize_dense<double>(n, A, 0, s);
+  if (!M->blas) {
+    if (rocblas_create_handle(&M->blas) != rocblas_status_success) throw Error(HPDG_ERR_HIP, "rocblas handle");
+  }
+  rocblas_set_stream(M->blas, s);
+  rocblas_int* info = nullptr;
+  HIPCHK(hipMalloc(&info, sizeof(rocblas_int)));
+  rocblas_int hinfo = 0;
+  auto check = [&](rocblas_status st, const char* what) {
+    HIPCHK(hipMemcpyAsync(&hinfo, info, sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (int i = 0; i < n; ++i) A[size_t(i) * n + j] = col[i];
+    if (st != rocblas_status_success || hinfo != 0) {
+      (void)hipFree(info);
+      if (st != rocblas_status_success)
+        throw Error(HPDG_ERR_HIP, std::string(what) + " of the coarsest operator failed with rocblas status " +
+                                      std::to_string(int(st)));
+      throw Error(HPDG_ERR_BREAKDOWN, std::string(what) + ": the coarsest operator is not positive definite (info " +
+                                          std::to_string(hinfo) + ")");
+    }
+  };
+  check(rocsolver_dpotrf(M->blas, rocblas_fill_lower, n, A, n, info), "Cholesky");
+  check(rocsolver_dpotri(M->blas, rocblas_fill_lower, n, A, n, info), "inverse");
+  (void)hipFree(info);
+  launch_symmetrize_dense<double>(n, A, 1, s);
+  if (M->has_f32) launch_convert_d2f((long long)n * n, A, M->Ainv32, s);
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// FCG (Alg. 2, device-resident scalars, one host read per iteration) or PCG, from the initial
+// guess in u; returns false when the iteration cap is reached
+bool krylov_solve(hpdg_mesh* mesh, const hpdg_solve_params& params, const double* b_dev, double* u_dev, int& iters,
+                  double& rel, hipStream_t s) {
+  const bool mixed = params.precision == HPDG_PREC_MIXED;
+  iters = 0;
+  rel = 0;
+  const long long n = mesh->H[0].ndof;
+  const double nb = std::sqrt(dot_sync(mesh, n, b_dev, b_dev, s));
+  if (!std::isfinite(nb)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite right-hand side");
+  double* r = mesh->r;
+  apply_level<double>(mesh, 0, u_dev, mesh->w, s);
+  launch_copy<double>(n, b_dev, r, s);
+  launch_axpby<double>(n, -1.0, mesh->w, 1.0, r, s);  // r0 = b - A u0
+  if (nb == 0.0) {
+    launch_fill<double>(n, 0.0, u_dev, s);
+    HIPCHK(hipStreamSynchronize(s));
+    return true;
   }
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j < i; ++j) {
-      const double m = 0.5 * (A[size_t(i) * n + j] + A[size_t(j) * n + i]);
-      A[size_t(i) * n + j] = A[size_t(j) * n + i] = m;
+  double rr = dot_sync(mesh, n, r, r, s);
+  rel = std::sqrt(rr) / nb;
+  auto precond = [&](const double* in, double* out) {
+    if (mixed) {
+      DevLevel<float>& d32 = mesh->L32[0];
+      // level-0 FP32 f / v buffers are free (the V-cycle takes f_0, v_0 as arguments)
+      launch_convert_d2f(n, in, d32.f, s);
+      vcycle<float>(mesh, d32.f, d32.v, s);
+      launch_convert_f2d(n, d32.v, out, s);
+    } else {
+      vcycle<double>(mesh, in, out, s);
     }
-  // Cholesky A = C C^T (lower C), in place in the lower triangle
-  for (int j = 0; j < n; ++j) {
-    double dsum = A[size_t(j) * n + j];
-    for (int k = 0; k < j; ++k) dsum -= A[size_t(j) * n + k] * A[size_t(j) * n + k];
-    if (!(dsum > 0)) throw Error(HPDG_ERR_BREAKDOWN, "coarsest operator is not positive definite");
-    const double cjj = std::sqrt(dsum);
-    A[size_t(j) * n + j] = cjj;
-    for (int i = j + 1; i < n; ++i) {
-      double v = A[size_t(i) * n + j];
-      for (int k = 0; k < j; ++k) v -= A[size_t(i) * n + k] * A[size_t(j) * n + k];
-      A[size_t(i) * n + j] = v / cjj;
+  };
+  if (params.solver == HPDG_SOLVER_PCG) {
+    // textbook PCG: z = M r, p = z + beta p, alpha = r.z / p.Ap
+    double* z = mesh->vv;
+    double* p = mesh->d;
+    double* Ap = mesh->w;
+    precond(r, z);
+    launch_copy<double>(n, z, p, s);
+    double rz = dot_sync(mesh, n, r, z, s);
+    while (rel > params.tol_rel && iters < params.max_iter) {
+      apply_level<double>(mesh, 0, p, Ap, s);
+      const double pAp = dot_sync(mesh, n, p, Ap, s);
+      if (!(pAp > 0) || !std::isfinite(pAp)) throw Error(HPDG_ERR_BREAKDOWN, "PCG breakdown");
+      const double alpha = rz / pAp;
+      launch_axpby<double>(n, alpha, p, 1.0, u_dev, s);
+      launch_axpby<double>(n, -alpha, Ap, 1.0, r, s);
+      precond(r, z);
+      const double rz2 = dot_sync(mesh, n, r, z, s);
+      launch_axpby<double>(n, 1.0, z, rz2 / rz, p, s);
+      rz = rz2;
+      rr = dot_sync(mesh, n, r, r, s);
+      rel = std::sqrt(rr) / nb;
+      ++iters;
+    }
+  } else {
+    // Alg. 2 with device-resident scalars; one host read of |r|^2 per iteration
+    launch_fill<double>(16, 0.0, mesh->sc, s);
+    while (rel > params.tol_rel && iters < params.max_iter) {
+      const int first = iters == 0 ? 1 : 0;
+      precond(r, mesh->vv);
+      apply_level<double>(mesh, 0, mesh->vv, mesh->w, s);
+      launch_dot3(n, mesh->vv, r, mesh->w, first ? nullptr : mesh->q, mesh->partials, mesh->sc, s);
+      launch_fcg_scalars(mesh->sc, first, s);
+      launch_fcg_update(n, mesh->vv, mesh->w, mesh->d, mesh->q, u_dev, r, mesh->sc, mesh->partials, first, s);
+      HIPCHK(hipMemcpyAsync(mesh->host_sc, mesh->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      ++iters;
+      if (mesh->host_sc[8] != 0.0) throw Error(HPDG_ERR_BREAKDOWN, "FCG breakdown (rho <= 0 or non-finite)");
+      rr = mesh->host_sc[7];
+      if (!std::isfinite(rr)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite residual");
+      rel = std::sqrt(rr) / nb;
     }
   }
-  // Ci = C^-1 (lower), then A^-1 = Ci^T Ci
-  std::vector<double> Ci(size_t(n) * n, 0.0);
-  for (int j = 0; j < n; ++j) {
-    Ci[size_t(j) * n + j] = 1.0 / A[size_t(j) * n + j];
-    for (int i = j + 1; i < n; ++i) {
-      double v = 0;
-      for (int k = j; k < i; ++k) v -= A[size_t(i) * n + k] * Ci[size_t(k) * n + j];
-      Ci[size_t(i) * n + j] = v / A[size_t(i) * n + i];
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+  return rel <= params.tol_rel;
+}
+
+// alpha and w det J beta at the GL points of every level for the source ``nl`` (host, FP64)
+void set_nonlinear(hpdg_mesh* M, const hpdg_nonlinear_desc* nl, hipStream_t s) {
+  if (M->H[0].nmq == 0) throw Error(HPDG_ERR_UNSUPPORTED, "mesh uploaded without mass_term");
+  if (nl->kind != HPDG_NL_PUNCTURE && nl->kind != HPDG_NL_QUADRATIC)
+    throw Error(HPDG_ERR_INVALID_ARG, "unknown nonlinear source kind");
+  if (nl->n_params < 0 || (nl->n_params > 0 && !nl->params)) throw Error(HPDG_ERR_INVALID_ARG, "bad parameters");
+  const std::vector<double> P(nl->params, nl->params + nl->n_params);
+  if (nl->kind == HPDG_NL_PUNCTURE && (P.empty() || (P.size() - 1) % 5 != 0 || !(P[0] > 0)))
+    throw Error(HPDG_ERR_INVALID_ARG, "puncture parameters are [s > 0, rows of 5]");
+  if (nl->kind == HPDG_NL_QUADRATIC && P.size() != 28)
+    throw Error(HPDG_ERR_INVALID_ARG, "quadratic parameters are [alpha, 27 coefficients]");
+  std::vector<double> key(1, double(nl->kind));
+  key.insert(key.end(), P.begin(), P.end());
+  if (key == M->nl_key) return;
+  if (!M->bad) {
+    M->bad = M->alloc<int>(1);
+    HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&M->host_bad), sizeof(int)));
+  }
+  std::vector<double> x, wdet, al, wb;
+  for (int l = 0; l < M->nlevels(); ++l) {
+    const LevelHost& h = M->H[l];
+    mass_points(M->mm, h, x, wdet);
+    al.resize(wdet.size());
+    wb.resize(wdet.size());
+    for (size_t k = 0; k < wdet.size(); ++k) {
+      double a, b;
+      nl_coefficients(nl->kind, P, &x[3 * k], a, b);
+      al[k] = a;
+      wb[k] = wdet[k] * b;
+    }
+    DevLevel<double>& d = M->lev<double>(l);
+    if (!d.nl_alpha) {
+      d.nl_alpha = M->alloc<double>(al.size());
+      d.nl_wbeta = M->alloc<double>(wb.size());
+    }
+    HIPCHK(hipMemcpyAsync(d.nl_alpha, al.data(), al.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(d.nl_wbeta, wb.data(), wb.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  M->nl_key = key;
+}
+
+void clear_bad(hpdg_mesh* M, hipStream_t s) {
+  *M->host_bad = 0;
+  HIPCHK(hipMemcpyAsync(M->bad, M->host_bad, sizeof(int), hipMemcpyHostToDevice, s));
+}
+
+void check_bad(hpdg_mesh* M, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(M->host_bad, M->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (*M->host_bad) throw Error(HPDG_ERR_BREAKDOWN, "1 + alpha u <= 0 at a quadrature point");
+}
+
+// R = A u - N(u) - F on level 0 (F may be null)
+void nl_residual(hpdg_mesh* M, const double* F, const double* u, double* R, hipStream_t s) {
+  const long long n = M->H[0].ndof;
+  DevLevel<double>& d = M->lev<double>(0);
+  M->mass_on = false;
+  apply_level<double>(M, 0, u, R, s);
+  M->mass_on = true;
+  clear_bad(M, s);
+  launch_nl_eval(M->view<double>(0), u, d.nl_alpha, d.nl_wbeta, d.t, nullptr, M->bad, s);
+  launch_axpby<double>(n, -1.0, d.t, 1.0, R, s);
+  if (F) launch_axpby<double>(n, -1.0, F, 1.0, R, s);
+  check_bad(M, s);
+}
+
+// Jacobian mass terms on every level from the state u (injected downwards), then the
+// point-Jacobi scaling, the spectral bounds and the coarsest inverse of the new operators
+void linearize(hpdg_mesh* M, const double* u, hipStream_t s) {
+  if (!M->smoother_ready) throw Error(HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
+  if (M->sp.scaling == HPDG_SMOOTH_BLOCK)
+    throw Error(HPDG_ERR_UNSUPPORTED, "block-Jacobi smoothing is not rebuilt for Newton linearisations");
+  const int L = M->nlevels();
+  clear_bad(M, s);
+  const double* ul = u;
+  for (int l = 0; l < L; ++l) {
+    DevLevel<double>& d = M->lev<double>(l);
+    if (l > 0) {
+      launch_inject<double>(M->tview<double>(l - 1), ul, d.p, s);
+      ul = d.p;
+    }
+    launch_nl_eval(M->view<double>(l), ul, d.nl_alpha, d.nl_wbeta, nullptr, d.mcoef, M->bad, s);
+  }
+  check_bad(M, s);
+  for (int l = 0; l < L; ++l) {
+    DevLevel<double>& d = M->lev<double>(l);
+    launch_diag_mass<double>(M->view<double>(l), d.diag, d.dinv, s);
+    if (M->has_f32) {
+      DevLevel<float>& f = M->lev<float>(l);
+      launch_convert_d2f(M->H[l].nmq, d.mcoef, f.mcoef, s);
+      launch_convert_d2f(M->H[l].ndof, d.dinv, f.dinv, s);
     }
   }
-  std::vector<double> Ainv(size_t(n) * n, 0.0);
-  for (int i = 0; i < n; ++i)
-    for (int j = 0; j <= i; ++j) {
-      double v = 0;
-      for (int k = i; k < n; ++k) v += Ci[size_t(k) * n + i] * Ci[size_t(k) * n + j];
-      Ainv[size_t(i) * n + j] = Ainv[size_t(j) * n + i] = v;
-    }
-  M->Ainv64 = M->upload_raw(Ainv, s);
-  if (M->has_f32) M->Ainv32 = M->upload<float>(Ainv, s);
+  for (int l = 0; l + 1 < L; ++l) M->lam[l] = cg_bound(M, l, M->sp.n_eigs, M->sp.seed, s);
+  build_coarse(M, s);
 }
 
 void check_mesh(const hpdg_mesh_desc* D) {
@@ -579,6 +839,7 @@ int hpdg_mesh_upload(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_
       M->dp.coef_kind = disc->coef_kind;
       for (int i = 0; i < 4; ++i) M->dp.coef[i] = disc->coef_params[i];
       M->has_f32 = disc->build_f32 != 0;
+      M->dp.mass_term = disc->mass_term != 0 ? 1 : 0;
     }
     const int max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
     M->tab.build();
@@ -684,7 +945,7 @@ int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, 
   if (!mesh || !rhs || !F_dev) return HPDG_ERR_INVALID_ARG;
   return guarded(mesh->ctx, [&] {
     std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
-    if (rhs->kind < 0 || rhs->kind > 4) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
+    if (rhs->kind < 0 || rhs->kind > 5) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
     std::vector<double> F;
     assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);
     HIPCHK(hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, S(stream)));
@@ -698,47 +959,35 @@ int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_
   if (prec == HPDG_F32 && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
   return guarded(mesh->ctx, [&] {
     hipStream_t s = S(stream);
-    hipEvent_t a = nullptr, b = nullptr;
-    if (mesh->timing) {
-      HIPCHK(hipEventCreate(&a));
-      HIPCHK(hipEventCreate(&b));
-      HIPCHK(hipEventRecord(a, s));
-    }
     if (prec == HPDG_F32)
       apply_level<float>(mesh, level, static_cast<const float*>(x_dev), static_cast<float*>(y_dev), s);
     else
       apply_level<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), s);
     HIPCHK(hipGetLastError());
-    if (mesh->timing) {
-      HIPCHK(hipEventRecord(b, s));
-      mesh->events.push_back({a, b});
-    }
   });
 }
 
-int hpdg_apply_timing_enable(hpdg_mesh* mesh, int on) {
-  if (!mesh) return HPDG_ERR_INVALID_ARG;
-  mesh->timing = on != 0;
+int hpdg_timing_enable(hpdg_mesh* mesh, int every) {
+  if (!mesh || every < 0) return HPDG_ERR_INVALID_ARG;
+  mesh->timing = every > 0;
+  mesh->timing_every = std::max(every, 1);
+  std::memset(mesh->timing_count, 0, sizeof(mesh->timing_count));
   return HPDG_OK;
 }
 
-int hpdg_apply_timing(hpdg_mesh* mesh, double* total_ms, int64_t* n_calls) {
+int hpdg_kernel_timing(hpdg_mesh* mesh, int kind, int level, int prec, double* total_ms, int64_t* launches,
+                       double* alg_bytes) {
   if (!mesh) return HPDG_ERR_INVALID_ARG;
+  if (kind < 0 || kind >= HPDG_TIMING_KINDS || level < 0 || level >= mesh->nlevels() || level >= 32 ||
+      (prec != HPDG_F64 && prec != HPDG_F32))
+    return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "invalid timing entry");
   return guarded(mesh->ctx, [&] {
-    for (auto& ev : mesh->events) {
-      HIPCHK(hipEventSynchronize(ev.second));
-      float ms = 0;
-      HIPCHK(hipEventElapsedTime(&ms, ev.first, ev.second));
-      mesh->timed_ms += ms;
-      mesh->timed_calls += 1;
-      (void)hipEventDestroy(ev.first);
-      (void)hipEventDestroy(ev.second);
-    }
-    mesh->events.clear();
-    if (total_ms) *total_ms = mesh->timed_ms;
-    if (n_calls) *n_calls = mesh->timed_calls;
-    mesh->timed_ms = 0;
-    mesh->timed_calls = 0;
+    collect_timing(mesh);
+    hpdg_mesh::Acc& a = mesh->acc[kind][level][prec];
+    if (total_ms) *total_ms = a.ms;
+    if (launches) *launches = a.calls;
+    if (alg_bytes) *alg_bytes = a.bytes;
+    a = hpdg_mesh::Acc();
   });
 }
 
@@ -805,93 +1054,94 @@ int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (!mesh || !params || !b_dev || !u_dev) return HPDG_ERR_INVALID_ARG;
   if (!mesh->smoother_ready) return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
-  const bool mixed = params->precision == HPDG_PREC_MIXED;
-  if (mixed && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
-  int status = HPDG_OK;
+  if (params->precision == HPDG_PREC_MIXED && !mesh->has_f32)
+    return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
   int iters = 0;
   double rel = 0;
+  bool converged = true;
+  auto t0 = std::chrono::steady_clock::now();
+  int rc = guarded(mesh->ctx, [&] {
+    converged = krylov_solve(mesh, *params, b_dev, u_dev, iters, rel, S(stream));
+  });
+  auto t1 = std::chrono::steady_clock::now();
+  if (rc == HPDG_OK && !converged) rc = fail(mesh->ctx, HPDG_ERR_NOT_CONVERGED, "iteration cap reached");
+  if (stats) {
+    stats->iterations = iters;
+    stats->rel_residual = rel;
+    stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    stats->status = rc;
+  }
+  return rc;
+}
+
+int hpdg_nonlinear_residual(hpdg_mesh* mesh, const hpdg_nonlinear_desc* nl, const double* F_dev,
+                            const double* u_dev, double* R_dev, void* stream) {
+  if (!mesh || !nl || !u_dev || !R_dev || R_dev == u_dev || R_dev == F_dev) return HPDG_ERR_INVALID_ARG;
+  return guarded(mesh->ctx, [&] {
+    hipStream_t s = S(stream);
+    set_nonlinear(mesh, nl, s);
+    nl_residual(mesh, F_dev, u_dev, R_dev, s);
+    HIPCHK(hipStreamSynchronize(s));
+  });
+}
+
+int hpdg_nonlinear_linearize(hpdg_mesh* mesh, const hpdg_nonlinear_desc* nl, const double* u_dev,
+                             void* stream) {
+  if (!mesh || !nl || !u_dev) return HPDG_ERR_INVALID_ARG;
+  return guarded(mesh->ctx, [&] {
+    hipStream_t s = S(stream);
+    set_nonlinear(mesh, nl, s);
+    linearize(mesh, u_dev, s);
+  });
+}
+
+int hpdg_newton_solve(hpdg_mesh* mesh, const hpdg_newton_params* params, const hpdg_nonlinear_desc* nl,
+                      const double* F_dev, double* u_dev, hpdg_newton_stats* stats, void* stream) {
+  if (stats) std::memset(stats, 0, sizeof(*stats));
+  if (!mesh || !params || !nl || !u_dev || F_dev == u_dev) return HPDG_ERR_INVALID_ARG;
+  if (params->precision == HPDG_PREC_MIXED && !mesh->has_f32)
+    return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  int steps = 0, lin = 0;
+  double rel = 1.0;
   auto t0 = std::chrono::steady_clock::now();
   int rc = guarded(mesh->ctx, [&] {
     hipStream_t s = S(stream);
+    set_nonlinear(mesh, nl, s);
     const long long n = mesh->H[0].ndof;
-    const double nb = std::sqrt(dot_sync(mesh, n, b_dev, b_dev, s));
-    if (!std::isfinite(nb)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite right-hand side");
-    double* r = mesh->r;
-    apply_level<double>(mesh, 0, u_dev, mesh->w, s);
-    launch_copy<double>(n, b_dev, r, s);
-    launch_axpby<double>(n, -1.0, mesh->w, 1.0, r, s);  // r0 = b - A u0
-    if (nb == 0.0) {
-      launch_fill<double>(n, 0.0, u_dev, s);
-      rel = 0.0;
-      return;
+    if (!mesh->nl_b) {
+      mesh->nl_b = mesh->alloc<double>(size_t(n));
+      mesh->nl_rhs = mesh->alloc<double>(size_t(n));
+      mesh->nl_delta = mesh->alloc<double>(size_t(n));
     }
-    double rr = dot_sync(mesh, n, r, r, s);
-    rel = std::sqrt(rr) / nb;
-    auto precond = [&](const double* in, double* out) {
-      if (mixed) {
-        DevLevel<float>& d32 = mesh->L32[0];
-        // level-0 FP32 f / v buffers are free (the V-cycle takes f_0, v_0 as arguments)
-        launch_convert_d2f(n, in, d32.f, s);
-        vcycle<float>(mesh, d32.f, d32.v, s);
-        launch_convert_f2d(n, d32.v, out, s);
-      } else {
-        vcycle<double>(mesh, in, out, s);
-      }
-    };
-    if (params->solver == HPDG_SOLVER_PCG) {
-      // textbook PCG: z = M r, p = z + beta p, alpha = r.z / p.Ap
-      double* z = mesh->vv;
-      double* p = mesh->d;
-      double* Ap = mesh->w;
-      precond(r, z);
-      launch_copy<double>(n, z, p, s);
-      double rz = dot_sync(mesh, n, r, z, s);
-      while (rel > params->tol_rel && iters < params->max_iter) {
-        apply_level<double>(mesh, 0, p, Ap, s);
-        const double pAp = dot_sync(mesh, n, p, Ap, s);
-        if (!(pAp > 0) || !std::isfinite(pAp)) throw Error(HPDG_ERR_BREAKDOWN, "PCG breakdown");
-        const double alpha = rz / pAp;
-        launch_axpby<double>(n, alpha, p, 1.0, u_dev, s);
-        launch_axpby<double>(n, -alpha, Ap, 1.0, r, s);
-        precond(r, z);
-        const double rz2 = dot_sync(mesh, n, r, z, s);
-        launch_axpby<double>(n, 1.0, z, rz2 / rz, p, s);
-        rz = rz2;
-        rr = dot_sync(mesh, n, r, r, s);
-        rel = std::sqrt(rr) / nb;
-        ++iters;
-      }
-    } else {
-      // Alg. 2 with device-resident scalars; one host read of |r|^2 per iteration
-      launch_fill<double>(16, 0.0, mesh->sc, s);
-      while (rel > params->tol_rel && iters < params->max_iter) {
-        const int first = iters == 0 ? 1 : 0;
-        precond(r, mesh->vv);
-        apply_level<double>(mesh, 0, mesh->vv, mesh->w, s);
-        launch_dot3(n, mesh->vv, r, mesh->w, first ? nullptr : mesh->q, mesh->partials, mesh->sc, s);
-        launch_fcg_scalars(mesh->sc, first, s);
-        launch_fcg_update(n, mesh->vv, mesh->w, mesh->d, mesh->q, u_dev, r, mesh->sc, mesh->partials,
-                          first, s);
-        HIPCHK(hipMemcpyAsync(mesh->host_sc, mesh->sc, 9 * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        ++iters;
-        if (mesh->host_sc[8] != 0.0) throw Error(HPDG_ERR_BREAKDOWN, "FCG breakdown (rho <= 0 or non-finite)");
-        rr = mesh->host_sc[7];
-        if (!std::isfinite(rr)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite residual");
-        rel = std::sqrt(rr) / nb;
-      }
+    double* R = mesh->nl_b;
+    nl_residual(mesh, F_dev, u_dev, R, s);
+    const double r0 = std::sqrt(dot_sync(mesh, n, R, R, s));
+    if (!std::isfinite(r0)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite initial residual");
+    rel = r0 > 0 ? 1.0 : 0.0;
+    hpdg_solve_params lp{HPDG_SOLVER_FCG, params->precision, params->lin_tol_rel, params->max_lin_iter};
+    while (rel > params->tol_rel && steps < params->max_newton) {
+      linearize(mesh, u_dev, s);
+      launch_fill<double>(n, 0.0, mesh->nl_rhs, s);
+      launch_axpby<double>(n, -1.0, R, 1.0, mesh->nl_rhs, s);  // b = -R
+      launch_fill<double>(n, 0.0, mesh->nl_delta, s);
+      int its = 0;
+      double lrel = 0;
+      krylov_solve(mesh, lp, mesh->nl_rhs, mesh->nl_delta, its, lrel, s);  // an inexact correction is still taken
+      lin += its;
+      launch_axpby<double>(n, 1.0, mesh->nl_delta, 1.0, u_dev, s);
+      nl_residual(mesh, F_dev, u_dev, R, s);
+      const double rn = std::sqrt(dot_sync(mesh, n, R, R, s));
+      if (!std::isfinite(rn)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite Newton residual");
+      rel = rn / r0;
+      ++steps;
     }
     HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipGetLastError());
-    if (rel > params->tol_rel) status = HPDG_ERR_NOT_CONVERGED;
   });
   auto t1 = std::chrono::steady_clock::now();
-  if (rc == HPDG_OK && status != HPDG_OK) {
-    rc = status;
-    mesh->ctx->err = "iteration cap reached";
-  }
+  if (rc == HPDG_OK && rel > params->tol_rel) rc = fail(mesh->ctx, HPDG_ERR_NOT_CONVERGED, "Newton step cap reached");
   if (stats) {
-    stats->iterations = iters;
+    stats->newton_steps = steps;
+    stats->linear_iterations = lin;
     stats->rel_residual = rel;
     stats->solve_ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
     stats->status = rc;

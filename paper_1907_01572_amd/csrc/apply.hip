@@ -474,7 +474,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       r += Dg[t * q + b] * A2[(c * q + t) * q + a];
       r += Dg[t * q + c] * A3[(t * q + b) * q + a];
     }
-    if (I.mass) r += G[6 * q3 + idx] * A0[idx];
+    if (I.mass && L.mcoef) r += L.mcoef[I.mq + idx] * A0[idx];
     A0[idx] = r;
   }
   __syncthreads();

@@ -9,7 +9,7 @@ namespace hpdg {
 
 // 1-D table offsets mirrored from OpTable (ints in device memory)
 struct TabView {
-  const int* off;        // [9][kMaxN + 1][kMaxQ + 1]
+  const int* off;        // [12][kMaxN + 1][kMaxQ + 1]
   const int* dg_off;     // [kMaxQ + 1]
   const int* w_off;      // [kMaxQ + 1]
   const int* dface_off;  // [kMaxN + 1]
@@ -22,6 +22,7 @@ struct LevelView {
   const int* fmlist;
   const T* vgeo;
   const T* mgeo;
+  const T* mcoef;  // w det J c at the GL points of elements with a mass term (null: no mass term)
   const T* tab;
   TabView tv;
   long long n_elem;
@@ -107,5 +108,20 @@ void launch_dot3(long long n, const double* v, const double* r, const double* w,
 void launch_fcg_scalars(double* sc, int first, hipStream_t s);
 void launch_fcg_update(long long n, const double* v, const double* w, double* d, double* q,
                        double* u, double* r, double* sc, double* partials, int first, hipStream_t s);
+
+// Newton linearisation (newton.hip): per element, u at the volume GL points; N(u) (LGL test
+// functions, may be null) and / or the mass coefficient w det J 7 alpha beta (1 + alpha u)^-8
+// (may be null); *bad = 1 when 1 + alpha u <= 0 somewhere
+void launch_nl_eval(const LevelView<double>& L, const double* u, const double* alpha, const double* wbeta,
+                    double* N, double* mcoef, int* bad, hipStream_t s);
+// dinv = 1 / (diag(A) + diag(mass form with L.mcoef))
+template <typename T>
+void launch_diag_mass(const LevelView<T>& L, const T* diagA, T* dinv, hipStream_t s);
+// coarse state from the fine one: fine polynomial of the containing child at each coarse node
+template <typename T>
+void launch_inject(const TransferView<T>& V, const T* uf, T* uc, hipStream_t s);
+// dense column-major n x n: lower_to_upper = 0: A = (A + A^T) / 2; 1: copy the lower triangle up
+template <typename T>
+void launch_symmetrize_dense(int n, T* A, int lower_to_upper, hipStream_t s);
 
 }  // namespace hpdg

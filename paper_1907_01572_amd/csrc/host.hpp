@@ -60,9 +60,10 @@ void parent_cells(const std::vector<Cell>& fine, const std::vector<Cell>& coarse
 struct ElemInfo {
   long long off;     // dof offset
   long long vgeo;    // offset of the volume metric (in scalars)
+  long long mq;      // offset of the mass coefficient w det J c at the GL points (q^3 values)
   int n, q;          // LGL nodes and GL points per axis
   int vmode;         // 0: constant metric (affine, 6 values), 1: per GL point (6 q^3 values)
-  int mass;          // 1: a mass coefficient follows the metric (q^3 values)
+  int mass;          // 1: the level carries a mass term c u v
   int fstart[6];     // first entry of face f in the face-mortar list
   int fcnt[6];       // mortars on face f (0: no operator term)
 };

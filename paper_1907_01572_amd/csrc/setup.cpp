@@ -42,6 +42,11 @@ void OpTable::build() {
           lagrange_eval(n, xn, q, pts, L.data(), D.data());
           push(PR_FULL + half, n, q, L.data());
         }
+        for (int half = 0; half < 3; ++half) {  // injection: child coordinate of a coarse node
+          for (int a = 0; a < q; ++a) pts[a] = half == 0 ? xf[a] : 2.0 * xf[a] + (half == 1 ? 1.0 : -1.0);
+          lagrange_eval(n, xn, q, pts, L.data(), D.data());
+          push(IN_FULL + half, n, q, L.data());
+        }
       }
     }
     double ends[2] = {-1.0, 1.0};
@@ -149,6 +154,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
   const bool kc = kconst(dp);
   L.einfo.assign(E, ElemInfo{});
   L.vgeo.clear();
+  L.nmq = 0;
   L.nmax = L.qmax = L.qmmax = 0;
   long long off = 0;
   double eta[kMaxQ + 1], wq[kMaxQ + 1];
@@ -158,12 +164,15 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     ElemInfo& I = L.einfo[e];
     const bool affine = mm.macros[c.macro].kind == 0;
     I.n = c.p + 1;
-    I.q = I.n + ((affine && kc) ? 0 : dp.quad_extra);
+    // affine, constant k and no mass term: every volume integrand is integrated exactly by n points
+    I.q = I.n + ((affine && kc && !dp.mass_term) ? 0 : dp.quad_extra);
     if (I.q > kMaxQ) throw Error(-2, "too many quadrature points");
     I.off = off;
     off += (long long)I.n * I.n * I.n;
     I.vmode = (affine && kc) ? 0 : 1;
-    I.mass = 0;
+    I.mass = dp.mass_term ? 1 : 0;
+    I.mq = L.nmq;
+    if (I.mass) L.nmq += (long long)I.q * I.q * I.q;
     I.vgeo = (long long)L.vgeo.size();
     L.nmax = std::max(L.nmax, I.n);
     L.qmax = std::max(L.qmax, I.q);
@@ -449,7 +458,8 @@ double exact_u(int kind, const std::vector<double>& P, const double x[3]) {
       if (std::sqrt(r2) < P[0]) return r2 / P[1] + P[0] * P[0] * (1.0 / P[2] - 1.0 / P[1]);
       return r2 / P[2];
     }
-    case 3: {
+    case 3:
+    case 5: {  // polynomial (5: Dirichlet data only, no source)
       const int K = int(std::lround(std::cbrt(double(P.size()))));
       double u = 0;
       for (int a = 0; a < K; ++a)
@@ -494,6 +504,51 @@ double source(int kind, const std::vector<double>& P, const double x[3]) {
 }
 
 }  // namespace
+
+void nl_coefficients(int kind, const std::vector<double>& P, const double x[3], double& alpha, double& beta) {
+  const double X = x[0], Y = x[1], Z = x[2];
+  if (kind == 0) {  // puncture: P = [s, rows (cx, cy, cz, m, a)]
+    const double s = P[0];
+    double psum = 0, b = 0;
+    for (size_t r = 1; r + 4 < P.size(); r += 5) {
+      const double dx = X - P[r], dy = Y - P[r + 1], dz = Z - P[r + 2];
+      const double r2 = dx * dx + dy * dy + dz * dz;
+      psum += P[r + 3] / (2.0 * std::sqrt(r2));
+      b += P[r + 4] * std::exp(-r2 / (2.0 * s * s));
+    }
+    const double q = 1.0 + X * X + Y * Y + Z * Z;
+    alpha = 1.0 / (1.0 + psum);
+    beta = b / (q * q);
+  } else {  // quadratic manufactured: P = [alpha, C (27)], beta = (-lap u*) (1 + alpha u*)^7
+    alpha = P[0];
+    const std::vector<double> C(P.begin() + 1, P.end());
+    const double u = exact_u(3, C, x), g = source(3, C, x), s = 1.0 + alpha * u;
+    const double s2 = s * s, s4 = s2 * s2;
+    beta = g * s4 * s2 * s;
+  }
+}
+
+void mass_points(const MacroMesh& mm, const LevelHost& L, std::vector<double>& x, std::vector<double>& wdet) {
+  x.assign(3 * size_t(L.nmq), 0.0);
+  wdet.assign(size_t(L.nmq), 0.0);
+  double eta[kMaxQ + 1], wq[kMaxQ + 1];
+  for (size_t e = 0; e < L.cells.size(); ++e) {
+    const ElemInfo& I = L.einfo[e];
+    if (!I.mass) continue;
+    const int q = I.q;
+    gauss_legendre(q, eta, wq);
+    for (int c = 0; c < q; ++c)
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          const double xi[3] = {eta[a], eta[b], eta[c]};
+          double xp[3], J[3][3];
+          cell_eval(mm, L.cells[e], xi, xp, J);
+          const size_t k = size_t(I.mq) + a + size_t(q) * (b + size_t(q) * c);
+          for (int d = 0; d < 3; ++d) x[3 * k + d] = xp[d];
+          wdet[k] = wq[a] * wq[b] * wq[c] * det3(J);
+        }
+  }
+}
 
 void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
                   int kind, const std::vector<double>& P, std::vector<double>& F) {

@@ -12,12 +12,16 @@ struct DiscParams {
   int quad_extra = 1;
   int coef_kind = 0;
   double coef[4] = {0, 0, 0, 0};
+  int mass_term = 0;  // levels carry a mass term c u v with c set per GL point (Newton)
 };
 
 // 1-D operator tables, indexed by (kind, n, q); every matrix is row-major [q][n].
 struct OpTable {
+  // GL_*: LGL basis of n nodes at q GL points (full interval, lower half, upper half);
+  // PR_*: coarse basis of n nodes at the q fine LGL nodes (prolongation, same cell / child);
+  // IN_*: fine basis of n nodes at the q coarse LGL nodes mapped into the child (injection)
   enum Kind { GL_VAL = 0, GL_DER = 1, GLLO_VAL = 2, GLLO_DER = 3, GLHI_VAL = 4, GLHI_DER = 5,
-              PR_FULL = 6, PR_LO = 7, PR_HI = 8, NKIND = 9 };
+              PR_FULL = 6, PR_LO = 7, PR_HI = 8, IN_FULL = 9, IN_LO = 10, IN_HI = 11, NKIND = 12 };
   std::vector<double> data;
   std::vector<int> off;        // [NKIND][kMaxN + 1][kMaxQ + 1]
   std::vector<int> dg_off;     // GL collocation derivative [q][q], by q
@@ -37,6 +41,7 @@ struct LevelHost {
   std::vector<double> vgeo, mgeo;
   std::vector<double> diag;
   long long ndof = 0;
+  long long nmq = 0;  // mass-coefficient scalars (sum of q^3 over elements with a mass term)
   int nmax = 0, qmax = 0, qmmax = 0;
   // elements grouped by (n, q): kernels are specialised per group
   std::vector<int> bucket_n, bucket_q;
@@ -63,6 +68,14 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
 void build_transfer(LevelHost& fine, const LevelHost& coarse);
 // diagonal of the level operator (Jacobi smoothing)
 void build_diagonal(const OpTable& T, LevelHost& L);
+
+// physical points and w det J at the volume GL points of every element with a mass term,
+// in the mass-coefficient layout (element mq offset, points a + q (b + q c))
+void mass_points(const MacroMesh& mm, const LevelHost& L, std::vector<double>& x, std::vector<double>& wdet);
+
+// alpha(x), beta(x) of the source beta (1 + alpha u)^-7: kind 0 puncture
+// (P = [s, rows (cx, cy, cz, m, a)]), kind 1 quadratic manufactured (P = [alpha, C (27)])
+void nl_coefficients(int kind, const std::vector<double>& P, const double x[3], double& alpha, double& beta);
 
 // right-hand side F_h (Eq. Fh2) on level 0
 void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
