@@ -52,7 +52,9 @@ enum {
 };
 
 enum { HPDG_F64 = 0, HPDG_F32 = 1 };                 /* vector precision of a call */
-enum { HPDG_PREC_F64 = 0, HPDG_PREC_MIXED = 1 };       /* solve precision: FP64 or FP32 V-cycle */
+/* solve precision: FP64 throughout; FP32 V-cycle; FP32 V-cycle whose block-Jacobi smoother
+ * reads bf16 inverse blocks (FP32 arithmetic; the outer FCG stays FP64 in every mode) */
+enum { HPDG_PREC_F64 = 0, HPDG_PREC_MIXED = 1, HPDG_PREC_MIXED_BF16 = 2 };
 enum { HPDG_MAP_AFFINE = 0, HPDG_MAP_SHELL = 1, HPDG_MAP_CUBE_SPHERE = 2 };
 enum { HPDG_BC_INTERIOR = 0, HPDG_BC_DIRICHLET = 1, HPDG_BC_NEUMANN = 2 };
 enum { HPDG_COEF_CONSTANT = 0, HPDG_COEF_RADIAL_STEP = 1 };
@@ -275,6 +277,57 @@ int hpdg_nonlinear_linearize(hpdg_mesh* mesh, const hpdg_nonlinear_desc* nl, con
  * ``stats`` is filled even on failure; HPDG_ERR_NOT_CONVERGED leaves the last iterate. */
 int hpdg_newton_solve(hpdg_mesh* mesh, const hpdg_newton_params* params, const hpdg_nonlinear_desc* nl,
                       const double* F_dev, double* u_dev, hpdg_newton_stats* stats, void* stream);
+
+/* ---- solve server: continuous batching of independent linear solves ----------------
+ * Requests (mesh + discretisation + analytic right-hand side) are queued on submit.  Up to
+ * ``max_active`` worker threads, each with its own HIP stream, take requests as slots and
+ * device memory free up: a request is admitted when its device footprint (its level
+ * tables, Krylov state and smoother data, computed from its host-side tables before any
+ * device allocation) fits in ``hbm_budget_bytes`` minus the footprint of the requests in
+ * flight; the first queued request that fits is taken, and the head of the queue is not
+ * passed over more than 2 max_active times.  Each request's element data and solver
+ * state stay on the device from upload to its last iteration; requests in flight share
+ * the GPU concurrently.  The result is copied to the caller's host buffer, then the
+ * request's device memory is released.  Results do not depend on the mix: every kernel
+ * and reduction of a solve is deterministic and private to its request. */
+typedef struct hpdg_server hpdg_server;
+typedef struct {
+  int32_t max_active;          /* requests in flight (worker threads / streams), >= 1 */
+  size_t hbm_budget_bytes;     /* device memory for requests in flight (0: no limit) */
+  int32_t precision;           /* HPDG_PREC_F64 or HPDG_PREC_MIXED */
+  hpdg_smoother_params smoother;
+  double tol_rel;              /* |b - A u| <= tol_rel |b| */
+  int32_t max_iter;
+} hpdg_server_params;
+
+typedef struct {
+  hpdg_mesh_desc mesh;         /* copied at submit */
+  hpdg_disc_params disc;       /* build_f32 is set by the server for mixed precision */
+  hpdg_rhs_desc rhs;           /* copied at submit */
+  double* u_out;               /* host buffer of n_dof doubles, written before DONE; the caller
+                                  keeps it alive until the request is DONE or FAILED */
+} hpdg_request;
+
+enum { HPDG_REQ_QUEUED = 0, HPDG_REQ_RUNNING = 1, HPDG_REQ_DONE = 2, HPDG_REQ_FAILED = 3 };
+typedef struct {
+  int32_t state;               /* HPDG_REQ_* */
+  int32_t status;              /* return code of the solve (HPDG_OK when DONE) */
+  int32_t iterations;
+  double rel_residual;
+  double submit_ms, start_ms, end_ms;  /* host clock, ms since the server was created */
+  size_t device_bytes;         /* admitted footprint */
+  int64_t n_dof;
+} hpdg_request_status;
+
+int hpdg_server_create(hpdg_ctx* ctx, const hpdg_server_params* params, hpdg_server** out);
+/* Queue a request; its ticket (> 0) identifies it in poll / wait. */
+int hpdg_server_submit(hpdg_server* server, const hpdg_request* request, uint64_t* ticket);
+int hpdg_server_poll(hpdg_server* server, uint64_t ticket, hpdg_request_status* status);
+/* Wait until the request is DONE or FAILED, or timeout_ms passes (< 0: no limit; the
+ * status is returned either way). */
+int hpdg_server_wait(hpdg_server* server, uint64_t ticket, int64_t timeout_ms, hpdg_request_status* status);
+/* Stop taking requests, finish those in flight, mark the queued ones FAILED, free. */
+int hpdg_server_destroy(hpdg_server* server);
 
 /* Kernel timing for measurement.  While enabled (every = k > 0), every k-th operator
  * application of each (kind, level, precision) (HPDG_TIMING_APPLY: hpdg_apply and the

@@ -18,7 +18,7 @@ OK = 0
 ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ERR_HIP, ERR_UNSUPPORTED = \
     -1, -2, -3, -4, -5, -6, -7
 F64, F32 = 0, 1
-PREC_F64, PREC_MIXED = 0, 1
+PREC_F64, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2
 SOLVER_FCG, SOLVER_PCG = 0, 1
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 SMOOTHERS = {"none": 0, "point": 1, "block": 2}
@@ -31,7 +31,8 @@ EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload"
             "hpdg_level_cells", "hpdg_mesh_free", "hpdg_assemble_rhs", "hpdg_apply",
             "hpdg_setup_smoother", "hpdg_smooth", "hpdg_vcycle", "hpdg_solve",
             "hpdg_nonlinear_residual", "hpdg_nonlinear_linearize", "hpdg_newton_solve",
-            "hpdg_timing_enable", "hpdg_kernel_timing"]
+            "hpdg_server_create", "hpdg_server_submit", "hpdg_server_poll", "hpdg_server_wait",
+            "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing"]
 
 
 class HpdgError(RuntimeError):
@@ -81,6 +82,21 @@ class RhsDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_params", ctypes.c_int32), ("params", ctypes.c_void_p)]
 
 
+class ServerParams(ctypes.Structure):
+    _fields_ = [("max_active", ctypes.c_int32), ("hbm_budget_bytes", ctypes.c_size_t), ("precision", ctypes.c_int32),
+                ("smoother", SmootherParams), ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("mesh", MeshDesc), ("disc", DiscParams), ("rhs", RhsDesc), ("u_out", ctypes.c_void_p)]
+
+
+class RequestStatus(ctypes.Structure):
+    _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("rel_residual", ctypes.c_double), ("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("end_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t), ("n_dof", ctypes.c_int64)]
+
+
 class NonlinearDesc(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("n_params", ctypes.c_int32), ("params", ctypes.c_void_p)]
 
@@ -126,6 +142,11 @@ def load_library(path=LIB_PATH):
     lib.hpdg_nonlinear_linearize.argtypes = [vp, ctypes.POINTER(NonlinearDesc), vp, vp]
     lib.hpdg_newton_solve.argtypes = [vp, ctypes.POINTER(NewtonParams), ctypes.POINTER(NonlinearDesc), vp, vp,
                                       ctypes.POINTER(NewtonStats), vp]
+    lib.hpdg_server_create.argtypes = [vp, ctypes.POINTER(ServerParams), ctypes.POINTER(vp)]
+    lib.hpdg_server_submit.argtypes = [vp, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]
+    lib.hpdg_server_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(RequestStatus)]
+    lib.hpdg_server_wait.argtypes = [vp, ctypes.c_uint64, i64, ctypes.POINTER(RequestStatus)]
+    lib.hpdg_server_destroy.argtypes = [vp]
     lib.hpdg_timing_enable.argtypes = [vp, i32]
     lib.hpdg_kernel_timing.argtypes = [vp, i32, i32, i32, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64),
                                        ctypes.POINTER(ctypes.c_double)]
@@ -186,40 +207,110 @@ def coef_from_problem(problem):
     return COEF_CONSTANT, [0.0] * 4
 
 
+def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False, mass_term=False):
+    """C descriptors of a meshgen mesh; returns (MeshDesc, DiscParams, arrays to keep alive)."""
+    keep = dict(
+        macro_kind=np.ascontiguousarray(mesh["macro_kind"], np.int32),
+        macro_params=np.ascontiguousarray(mesh["macro_params"], np.float64),
+        macro_nbr=np.ascontiguousarray(mesh["macro_nbr"], np.int32),
+        macro_nbr_face=np.ascontiguousarray(mesh["macro_nbr_face"], np.int32),
+        macro_nbr_orient=np.ascontiguousarray(mesh["macro_nbr_orient"], np.int32),
+        macro_bc=np.ascontiguousarray(mesh["macro_bc"], np.int32),
+        elem_macro=np.ascontiguousarray(mesh["elem_macro"], np.int32),
+        elem_level=np.ascontiguousarray(mesh["elem_level"], np.int32),
+        elem_anchor=np.ascontiguousarray(mesh["elem_anchor"], np.int32),
+        elem_p=np.ascontiguousarray(mesh["elem_p"], np.int32))
+    d = MeshDesc()
+    d.n_macro = len(keep["macro_kind"])
+    d.n_elem = len(keep["elem_p"])
+    for k, v in keep.items():
+        setattr(d, k, v.ctypes.data)
+    dp = DiscParams()
+    dp.penalty_C = penalty_C
+    dp.quad_extra = quad_extra
+    kind, params = coef if coef is not None else (COEF_CONSTANT, [0.0] * 4)
+    dp.coef_kind = kind
+    for i in range(4):
+        dp.coef_params[i] = params[i]
+    dp.max_levels = max_levels
+    dp.build_f32 = 1 if build_f32 else 0
+    dp.mass_term = 1 if mass_term else 0
+    return d, dp, keep
+
+
+REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
+
+
+class Server:
+    """Continuous-batching solve server (hpdg_server_*): independent linear solves admitted
+    by device footprint, ``max_active`` in flight on their own streams."""
+
+    def __init__(self, ctx, max_active=4, hbm_budget_bytes=0, precision=PREC_F64, n_cheb=4, Lambda=20.0,
+                 n_eigs=15, smoother="point", seed=0, tol=1e-10, max_iter=1000):
+        self.ctx, self.lib = ctx, ctx.lib
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[smoother], seed)
+        p = ServerParams(max_active, hbm_budget_bytes, precision, sp, tol, max_iter)
+        self.h = ctypes.c_void_p()
+        ctx.check(self.lib.hpdg_server_create(ctx.h, ctypes.byref(p), ctypes.byref(self.h)))
+        self._keep = {}
+
+    def submit(self, mesh, problem, out, coef=None):
+        """Queue a solve of the mesh with the problem's RHS; ``out`` (float64 numpy array of
+        the mesh's DOF count) receives the solution.  Returns the ticket."""
+        assert out.dtype == np.float64 and out.flags["C_CONTIGUOUS"]
+        d, dp, keep = _descriptors(mesh, coef=coef if coef is not None else coef_from_problem(problem))
+        params = np.ascontiguousarray(problem["params"], np.float64).reshape(-1)
+        r = Request()
+        r.mesh = d
+        r.disc = dp
+        r.rhs.kind = RHS_IDS[problem["kind"]]
+        r.rhs.n_params = len(params)
+        r.rhs.params = params.ctypes.data if len(params) else None
+        r.u_out = out.ctypes.data
+        t = ctypes.c_uint64()
+        self.ctx.check(self.lib.hpdg_server_submit(self.h, ctypes.byref(r), ctypes.byref(t)))
+        self._keep[t.value] = out  # the descriptors were copied; the output buffer must stay alive
+        return t.value
+
+    @staticmethod
+    def _status(st):
+        return dict(state=REQ_STATES[st.state], status=st.status, iterations=st.iterations,
+                    rel_residual=st.rel_residual, submit_ms=st.submit_ms, start_ms=st.start_ms,
+                    end_ms=st.end_ms, device_bytes=int(st.device_bytes), n_dof=int(st.n_dof))
+
+    def poll(self, ticket):
+        st = RequestStatus()
+        self.ctx.check(self.lib.hpdg_server_poll(self.h, ticket, ctypes.byref(st)))
+        return self._status(st)
+
+    def wait(self, ticket, timeout_ms=-1):
+        st = RequestStatus()
+        self.ctx.check(self.lib.hpdg_server_wait(self.h, ticket, int(timeout_ms), ctypes.byref(st)))
+        out = self._status(st)
+        if out["state"] in ("done", "failed"):
+            self._keep.pop(ticket, None)
+        return out
+
+    def close(self):
+        if self.h:
+            self.lib.hpdg_server_destroy(self.h)
+            self.h = None
+            self._keep.clear()
+
+
 class Mesh:
     """An uploaded mesh: level hierarchy, geometry and solver state on the device."""
 
     def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term=False):
         self.ctx, self.lib = ctx, ctx.lib
-        keep = dict(
-            macro_kind=np.ascontiguousarray(mesh["macro_kind"], np.int32),
-            macro_params=np.ascontiguousarray(mesh["macro_params"], np.float64),
-            macro_nbr=np.ascontiguousarray(mesh["macro_nbr"], np.int32),
-            macro_nbr_face=np.ascontiguousarray(mesh["macro_nbr_face"], np.int32),
-            macro_nbr_orient=np.ascontiguousarray(mesh["macro_nbr_orient"], np.int32),
-            macro_bc=np.ascontiguousarray(mesh["macro_bc"], np.int32),
-            elem_macro=np.ascontiguousarray(mesh["elem_macro"], np.int32),
-            elem_level=np.ascontiguousarray(mesh["elem_level"], np.int32),
-            elem_anchor=np.ascontiguousarray(mesh["elem_anchor"], np.int32),
-            elem_p=np.ascontiguousarray(mesh["elem_p"], np.int32))
-        d = MeshDesc()
-        d.n_macro = len(keep["macro_kind"])
-        d.n_elem = len(keep["elem_p"])
-        for k, v in keep.items():
-            setattr(d, k, v.ctypes.data)
-        dp = DiscParams()
-        dp.penalty_C = penalty_C
-        dp.quad_extra = quad_extra
-        kind, params = coef if coef is not None else (COEF_CONSTANT, [0.0] * 4)
-        dp.coef_kind = kind
-        for i in range(4):
-            dp.coef_params[i] = params[i]
-        dp.max_levels = max_levels
-        dp.build_f32 = 1 if build_f32 else 0
-        dp.mass_term = 1 if mass_term else 0
+        d, dp, self._keep = _descriptors(mesh, penalty_C, quad_extra, coef, max_levels, build_f32, mass_term)
         self.h = ctypes.c_void_p()
         ctx.check(self.lib.hpdg_mesh_upload(ctx.h, ctypes.byref(d), ctypes.byref(dp),
                                             ctypes.byref(self.h), _stream(stream)))
+        self._after_upload()
+
+    def _after_upload(self):
+        ctx = self.ctx
         ctx.meshes.append(self)
         info = MeshInfo()
         ctx.check(self.lib.hpdg_mesh_info_get(self.h, ctypes.byref(info)))

@@ -13,8 +13,14 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <condition_variable>
+#include <deque>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <string>
+#include <thread>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/hpdg.h"
@@ -35,6 +41,7 @@ struct hpdg_ctx {
   size_t used = 0;
   std::string err;
   std::vector<hpdg_mesh*> meshes;
+  std::mutex mu;  // guards used and meshes (a solve server uploads from several threads)
 };
 
 namespace {
@@ -53,6 +60,7 @@ struct DevLevel {
   T *f = nullptr, *v = nullptr, *t = nullptr, *p = nullptr;
   long long* boff = nullptr;  // element-block Jacobi: offsets of the inverse blocks
   T* binv = nullptr;
+  uint16_t* binv16 = nullptr;  // bf16 copy of the inverse blocks (FP32 levels)
   int* belems = nullptr;      // element ids grouped by (n, q)
   // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
   T* mcoef = nullptr;
@@ -89,6 +97,7 @@ struct hpdg_mesh {
   rocblas_handle blas = nullptr;  // batched Cholesky of the element blocks (setup only)
   // nonlinear source (Newton)
   bool mass_on = true;            // false: applies leave out the mass term (the residual's A u)
+  bool bf16_blocks = false;       // FP32 V-cycle reads the bf16 inverse blocks (HPDG_PREC_MIXED_BF16)
   std::vector<double> nl_key;     // kind and parameters of the source the GL tables hold
   int* bad = nullptr;             // device flag: 1 + alpha u <= 0 somewhere
   int* host_bad = nullptr;        // pinned
@@ -120,12 +129,19 @@ struct hpdg_mesh {
   T* alloc(size_t count) {
     size_t b = count * sizeof(T);
     if (b == 0) b = sizeof(T);
-    if (ctx->budget && ctx->used + b > ctx->budget) throw Error(HPDG_ERR_OOM, "HBM budget exceeded");
+    {
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      if (ctx->budget && ctx->used + b > ctx->budget) throw Error(HPDG_ERR_OOM, "HBM budget exceeded");
+      ctx->used += b;
+    }
     void* ptr = nullptr;
-    if (hipMalloc(&ptr, b) != hipSuccess) throw Error(HPDG_ERR_OOM, "hipMalloc failed");
+    if (hipMalloc(&ptr, b) != hipSuccess) {
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      ctx->used -= b;
+      throw Error(HPDG_ERR_OOM, "hipMalloc failed");
+    }
     allocs.push_back(ptr);
     bytes += b;
-    ctx->used += b;
     return static_cast<T*>(ptr);
   }
   template <typename T, typename S>
@@ -157,7 +173,10 @@ struct hpdg_mesh {
     if (host_sc) (void)hipHostFree(host_sc);
     if (host_bad) (void)hipHostFree(host_bad);
     if (blas) rocblas_destroy_handle(blas);
-    if (ctx) ctx->used -= std::min(ctx->used, bytes);
+    if (ctx) {
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      ctx->used -= std::min(ctx->used, bytes);
+    }
   }
 
   int nlevels() const { return int(H.size()); }
@@ -371,6 +390,13 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
       const double vec = double(n) * (1 + (Ax ? 1 : 0) + (k == 1 ? 1 : 2) + 2);
       const double bytes = M->timing ? double(sizeof(T)) * (double(M->block_scalars[l]) + vec) : 0.0;
       timed(M, HPDG_TIMING_BLOCK, l, sizeof(T) == 4 ? HPDG_F32 : HPDG_F64, bytes, s, [&] {
+        if constexpr (std::is_same<T, float>::value) {
+          if (M->bf16_blocks && d.binv16) {
+            launch_block_cheb_bf16(M->view<float>(l), d.boff, d.binv16, b, Ax, d.p, x, float(alpha), float(beta),
+                                   k == 1 ? 1 : 0, s);
+            return;
+          }
+        }
         launch_block_cheb<T>(M->view<T>(l), d.boff, d.binv, b, Ax, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
       });
     } else
@@ -548,6 +574,8 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
     d32.boff = d.boff;
     d32.binv = M->alloc<float>(size_t(boff[E]));
     launch_blocks_d2f(V, d.boff, B, d32.binv, s);
+    d32.binv16 = M->alloc<uint16_t>(size_t(boff[E]));
+    launch_blocks_f2bf(M->view<float>(l), d.boff, d32.binv, d32.binv16, s);
   }
   HIPCHK(hipStreamSynchronize(s));
 }
@@ -598,11 +626,160 @@ void build_coarse(hpdg_mesh* M, hipStream_t s) {
   HIPCHK(hipStreamSynchronize(s));
 }
 
+void check_mesh(const hpdg_mesh_desc* D) {
+  if (!D || D->n_macro <= 0 || D->n_elem <= 0 || !D->macro_kind || !D->macro_params || !D->macro_nbr ||
+      !D->macro_nbr_face || !D->macro_nbr_orient || !D->macro_bc || !D->elem_macro || !D->elem_level ||
+      !D->elem_anchor || !D->elem_p)
+    throw Error(HPDG_ERR_INVALID_ARG, "incomplete mesh description");
+}
+
+// host side of an upload: macro mesh, level hierarchy, geometry / mortar / transfer tables
+std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_params* disc) {
+  check_mesh(desc);
+  auto M = std::make_unique<hpdg_mesh>();
+  M->ctx = ctx;
+  const int nm = desc->n_macro;
+  M->mm.macros.resize(nm);
+  for (int m = 0; m < nm; ++m) {
+    M->mm.macros[m].kind = desc->macro_kind[m];
+    if (desc->macro_kind[m] < 0 || desc->macro_kind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
+    std::memcpy(M->mm.macros[m].par, desc->macro_params + 16 * m, 16 * sizeof(double));
+  }
+  M->mm.nbr.assign(desc->macro_nbr, desc->macro_nbr + 6 * nm);
+  M->mm.nbr_face.assign(desc->macro_nbr_face, desc->macro_nbr_face + 6 * nm);
+  M->mm.nbr_orient.assign(desc->macro_nbr_orient, desc->macro_nbr_orient + 6 * nm);
+  M->mm.bc.assign(desc->macro_bc, desc->macro_bc + 6 * nm);
+  if (disc) {
+    M->dp.C = disc->penalty_C > 0 ? disc->penalty_C : 10.0;
+    M->dp.quad_extra = disc->quad_extra >= 0 ? disc->quad_extra : 1;
+    M->dp.coef_kind = disc->coef_kind;
+    for (int i = 0; i < 4; ++i) M->dp.coef[i] = disc->coef_params[i];
+    M->has_f32 = disc->build_f32 != 0;
+    M->dp.mass_term = disc->mass_term != 0 ? 1 : 0;
+  }
+  const int max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
+  M->tab.build();
+  // hierarchy
+  LevelHost L0;
+  L0.cells.resize(desc->n_elem);
+  for (long long e = 0; e < desc->n_elem; ++e) {
+    Cell& c = L0.cells[e];
+    c.macro = desc->elem_macro[e];
+    c.level = desc->elem_level[e];
+    c.a[0] = desc->elem_anchor[3 * e];
+    c.a[1] = desc->elem_anchor[3 * e + 1];
+    c.a[2] = desc->elem_anchor[3 * e + 2];
+    c.p = desc->elem_p[e];
+  }
+  M->H.push_back(std::move(L0));
+  while (int(M->H.size()) < max_levels) {
+    LevelHost next;
+    if (!coarsen_cells(M->mm, M->H.back().cells, next.cells)) break;
+    M->H.push_back(std::move(next));
+  }
+  for (auto& h : M->H) {
+    build_level(M->mm, M->dp, M->tab, h);
+    build_diagonal(M->tab, h);
+    for (double dgv : h.diag)
+      if (!(dgv > 0)) throw Error(HPDG_ERR_INVALID_MESH, "non-positive operator diagonal");
+  }
+  for (int l = 0; l + 1 < M->nlevels(); ++l) build_transfer(M->H[l], M->H[l + 1]);
+  return M;
+}
+
+// device side of an upload: tables, level data, Krylov work vectors, coarsest inverse
+void upload_mesh_device(hpdg_mesh* M, hipStream_t s) {
+  // device tables
+  M->tab_off = M->upload_raw(M->tab.off, s);
+  M->dg_off = M->upload_raw(M->tab.dg_off, s);
+  M->w_off = M->upload_raw(M->tab.w_off, s);
+  M->dface_off = M->upload_raw(M->tab.dface_off, s);
+  M->tab64 = M->upload_raw(M->tab.data, s);
+  if (M->has_f32) M->tab32 = M->upload<float>(M->tab.data, s);
+  M->L64.resize(M->nlevels());
+  if (M->has_f32) M->L32.resize(M->nlevels());
+  for (int l = 0; l < M->nlevels(); ++l) {
+    build_device_level<double>(M, l, s);
+    if (M->has_f32) build_device_level<float>(M, l, s);
+  }
+  const long long n0 = M->H[0].ndof;
+  M->r = M->alloc<double>(n0);
+  M->vv = M->alloc<double>(n0);
+  M->w = M->alloc<double>(n0);
+  M->d = M->alloc<double>(n0);
+  M->q = M->alloc<double>(n0);
+  M->partials = M->alloc<double>(3 * kRedBlocks);
+  M->sc = M->alloc<double>(16);
+  HIPCHK(hipHostMalloc((void**)&M->host_sc, 16 * sizeof(double), hipHostMallocDefault));
+  launch_fill<double>(16, 0.0, M->sc, s);
+  build_coarse(M, s);
+  M->lam.assign(M->nlevels(), 0.0);
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipGetLastError());
+}
+
+// device bytes an upload (and a smoother setup with ``scaling``) will allocate
+size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
+  const size_t prec = M->has_f32 ? 12 : 8;  // bytes per scalar over the FP64 (+ FP32) copies
+  size_t b = M->tab.data.size() * prec + M->tab.off.size() * 4 + 4096;
+  for (int l = 0; l < M->nlevels(); ++l) {
+    const LevelHost& h = M->H[l];
+    b += h.einfo.size() * sizeof(ElemInfo) * (M->has_f32 ? 2 : 1);
+    b += h.minfo.size() * sizeof(MortarInfo) * (M->has_f32 ? 2 : 1);
+    b += (h.fmlist.size() + h.bucket_elems.size()) * 4 * (M->has_f32 ? 2 : 1);
+    b += (h.vgeo.size() + h.mgeo.size()) * prec;
+    b += size_t(h.ndof) * prec * 5;  // dinv, f, v, t, p
+    b += size_t(h.nmq) * prec + (h.nmq ? size_t(h.ndof) * prec : 0);
+    b += (h.tinfo.size() * sizeof(TransferInfo) + (h.cstart.size() + h.clist.size()) * 4) * (M->has_f32 ? 2 : 1);
+    if (scaling == HPDG_SMOOTH_BLOCK && l + 1 < M->nlevels()) {
+      size_t blk = 0;
+      for (const ElemInfo& I : h.einfo) blk += size_t(I.n) * I.n * I.n * I.n * I.n * I.n;
+      b += blk * prec + h.einfo.size() * 8;
+    }
+  }
+  const size_t n0 = size_t(M->H[0].ndof), nc = size_t(M->H.back().ndof);
+  b += n0 * 8 * 5 + 3 * kRedBlocks * 8 + 128 + nc * nc * prec;
+  return b;
+}
+
+void assemble_rhs_impl(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, hipStream_t s) {
+  if (rhs->kind < 0 || rhs->kind > 5) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
+  if (rhs->n_params > 0 && !rhs->params) throw Error(HPDG_ERR_INVALID_ARG, "rhs parameters missing");
+  std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
+  std::vector<double> F;
+  assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);
+  HIPCHK(hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max, hipStream_t s) {
+  if (params) {
+    mesh->sp = *params;
+    if (mesh->sp.n_cheb <= 0) mesh->sp.n_cheb = 4;
+    if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
+    if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
+    if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)
+      throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
+  }
+  if (mesh->sp.scaling == HPDG_SMOOTH_BLOCK)
+    for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
+  for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
+    if (lambda_max && lambda_max[l] > 0)
+      mesh->lam[l] = lambda_max[l];
+    else
+      mesh->lam[l] = cg_bound(mesh, l, mesh->sp.n_eigs, mesh->sp.seed, s);
+    if (lambda_max) lambda_max[l] = mesh->lam[l];
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  mesh->smoother_ready = true;
+}
+
 // FCG (Alg. 2, device-resident scalars, one host read per iteration) or PCG, from the initial
 // guess in u; returns false when the iteration cap is reached
 bool krylov_solve(hpdg_mesh* mesh, const hpdg_solve_params& params, const double* b_dev, double* u_dev, int& iters,
                   double& rel, hipStream_t s) {
-  const bool mixed = params.precision == HPDG_PREC_MIXED;
+  const bool mixed = params.precision == HPDG_PREC_MIXED || params.precision == HPDG_PREC_MIXED_BF16;
+  mesh->bf16_blocks = params.precision == HPDG_PREC_MIXED_BF16;
   iters = 0;
   rel = 0;
   const long long n = mesh->H[0].ndof;
@@ -775,14 +952,198 @@ void linearize(hpdg_mesh* M, const double* u, hipStream_t s) {
   build_coarse(M, s);
 }
 
-void check_mesh(const hpdg_mesh_desc* D) {
-  if (!D || D->n_macro <= 0 || D->n_elem <= 0 || !D->macro_kind || !D->macro_params || !D->macro_nbr ||
-      !D->macro_nbr_face || !D->macro_nbr_orient || !D->macro_bc || !D->elem_macro || !D->elem_level ||
-      !D->elem_anchor || !D->elem_p)
-    throw Error(HPDG_ERR_INVALID_ARG, "incomplete mesh description");
+
+}  // namespace
+
+// ---- solve server ------------------------------------------------------------------
+namespace {
+
+struct ServerRequest {
+  uint64_t ticket = 0;
+  std::string key;       // bytes of the mesh description and discretisation (host-table cache key)
+  std::vector<int32_t> mkind, mnbr, mnface, mnor, mbc, emacro, elevel, eanchor, ep;
+  std::vector<double> mparams, rhs_params;
+  hpdg_mesh_desc desc{};
+  hpdg_disc_params disc{};
+  hpdg_rhs_desc rhs{};
+  double* u_out = nullptr;
+  size_t estimate = 0;   // footprint used for admission (upper estimate from the description)
+  int bypassed = 0;      // times passed over while at the head of the queue
+  hpdg_request_status st{};
+};
+
+// device footprint from the description alone (before any table is built): vectors and
+// tables of every level, metric at GL points, smoother data, FP32 copies; an upper estimate
+size_t estimate_from_desc(const hpdg_mesh_desc& d, const hpdg_disc_params& disc, int scaling) {
+  double dof = 0, geo = 0, blocks = 0;
+  int pmin = 16;
+  for (int64_t e = 0; e < d.n_elem; ++e) {
+    const double n = d.elem_p[e] + 1.0, q = n + 1.0;
+    pmin = std::min(pmin, d.elem_p[e]);
+    const bool affine = d.macro_kind[d.elem_macro[e]] == HPDG_MAP_AFFINE && disc.coef_kind == HPDG_COEF_CONSTANT;
+    dof += n * n * n;
+    geo += (affine ? 6.0 : 6.0 * q * q * q) + 3.0 * 8.0 * q * q + (disc.mass_term ? q * q * q : 0.0);
+    if (scaling == HPDG_SMOOTH_BLOCK) blocks += n * n * n * n * n * n;
+  }
+  const double prec = disc.build_f32 ? 12.0 : 8.0;
+  const double levels = 8.0 / 7.0;  // coarser levels: a geometric series in the element count
+  const double coarse = double(d.n_macro) * std::pow(pmin + 1.0, 3);
+  const double b = levels * (prec * (6.0 * dof + geo + blocks) + 250.0 * d.n_elem) + 8.0 * 5.0 * dof +
+                   prec * coarse * coarse + (1 << 20);
+  return size_t(1.25 * b);
 }
 
 }  // namespace
+
+struct hpdg_server {
+  hpdg_ctx* ctx = nullptr;
+  hpdg_server_params p{};
+  std::mutex mu;
+  // host tables (hierarchy, geometry, mortars, transfers) of recently served meshes: a request
+  // on a mesh seen before copies them instead of rebuilding; least recently used evicted
+  // beyond kHostCacheBytes
+  static constexpr size_t kHostCacheBytes = size_t(16) << 30;
+  struct Cached {
+    std::shared_ptr<const hpdg_mesh> host;
+    size_t bytes = 0;
+    uint64_t last_use = 0;
+  };
+  std::mutex cache_mu;
+  std::map<std::string, Cached> cache;
+  size_t cache_bytes = 0;
+  uint64_t cache_clock = 0;
+  std::condition_variable cv_work, cv_done;
+  std::deque<uint64_t> queue;
+  std::map<uint64_t, std::unique_ptr<ServerRequest>> reqs;
+  size_t in_flight_bytes = 0;
+  bool stop = false;
+  uint64_t next_ticket = 1;
+  std::vector<std::thread> workers;
+  std::chrono::steady_clock::time_point t0;
+
+  double now_ms() const {
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  // the first queued request that fits (the head is not passed over more than 2 max_active
+  // times); caller holds mu
+  ServerRequest* pick() {
+    const size_t budget = p.hbm_budget_bytes;
+    const size_t free_b = budget ? (budget > in_flight_bytes ? budget - in_flight_bytes : 0) : SIZE_MAX;
+    for (size_t k = 0; k < queue.size(); ++k) {
+      ServerRequest* r = reqs[queue[k]].get();
+      const bool fits = !budget || r->estimate <= free_b || (in_flight_bytes == 0 && k == 0);
+      if (fits) {
+        if (k > 0) reqs[queue[0]]->bypassed += 1;
+        queue.erase(queue.begin() + k);
+        return r;
+      }
+      if (k == 0 && reqs[queue[0]]->bypassed >= 2 * p.max_active) return nullptr;
+    }
+    return nullptr;
+  }
+  void run(ServerRequest* r, hipStream_t s) {
+    int iters = 0;
+    double rel = 0;
+    int rc = HPDG_OK;
+    try {
+      std::unique_ptr<hpdg_mesh> M = host_tables(r);
+      upload_mesh_device(M.get(), s);
+      setup_smoother_impl(M.get(), &p.smoother, nullptr, s);
+      const long long n = M->H[0].ndof;
+      double* F = M->alloc<double>(size_t(n));
+      double* u = M->alloc<double>(size_t(n));
+      assemble_rhs_impl(M.get(), &r->rhs, F, s);
+      launch_fill<double>(n, 0.0, u, s);
+      hpdg_solve_params sp{HPDG_SOLVER_FCG, p.precision, p.tol_rel, p.max_iter};
+      const bool ok = krylov_solve(M.get(), sp, F, u, iters, rel, s);
+      if (!ok) rc = HPDG_ERR_NOT_CONVERGED;
+      HIPCHK(hipMemcpyAsync(r->u_out, u, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      std::lock_guard<std::mutex> lock(mu);
+      r->st.n_dof = n;
+    } catch (const Error& e) {
+      rc = e.code;
+    } catch (...) {
+      rc = HPDG_ERR_INVALID_ARG;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    r->st.iterations = iters;
+    r->st.rel_residual = rel;
+    r->st.status = rc;
+    r->st.state = rc == HPDG_OK ? HPDG_REQ_DONE : HPDG_REQ_FAILED;
+    r->st.end_ms = now_ms();
+  }
+  std::unique_ptr<hpdg_mesh> host_tables(const ServerRequest* r) {
+    std::shared_ptr<const hpdg_mesh> C;
+    {
+      std::lock_guard<std::mutex> lock(cache_mu);
+      auto it = cache.find(r->key);
+      if (it != cache.end()) {
+        it->second.last_use = ++cache_clock;
+        C = it->second.host;
+      }
+    }
+    if (!C) {
+      std::shared_ptr<hpdg_mesh> built(build_mesh_host(ctx, &r->desc, &r->disc).release());
+      const size_t bytes = host_bytes(*built);
+      std::lock_guard<std::mutex> lock(cache_mu);
+      if (bytes <= kHostCacheBytes && !cache.count(r->key)) {
+        while (cache_bytes + bytes > kHostCacheBytes && !cache.empty()) {
+          auto lru = cache.begin();
+          for (auto it = cache.begin(); it != cache.end(); ++it)
+            if (it->second.last_use < lru->second.last_use) lru = it;
+          cache_bytes -= lru->second.bytes;
+          cache.erase(lru);
+        }
+        cache[r->key] = Cached{built, bytes, ++cache_clock};
+        cache_bytes += bytes;
+      }
+      C = built;
+    }
+    auto M = std::make_unique<hpdg_mesh>();
+    M->ctx = ctx;
+    M->mm = C->mm;
+    M->dp = C->dp;
+    M->tab = C->tab;
+    M->H = C->H;
+    M->has_f32 = C->has_f32;
+    return M;
+  }
+  static size_t host_bytes(const hpdg_mesh& M) {
+    size_t b = M.tab.data.size() * 8;
+    for (const LevelHost& h : M.H)
+      b += (h.vgeo.size() + h.mgeo.size() + h.diag.size()) * 8 + h.einfo.size() * sizeof(ElemInfo) +
+           h.minfo.size() * sizeof(MortarInfo) + h.mortars.size() * sizeof(Mortar) + h.cells.size() * sizeof(Cell) +
+           (h.fmlist.size() + h.bucket_elems.size() + h.cstart.size() + h.clist.size()) * 4 +
+           h.tinfo.size() * sizeof(TransferInfo);
+    return b;
+  }
+  void worker() {
+    (void)hipSetDevice(ctx->device);
+    hipStream_t s = nullptr;
+    if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+    for (;;) {
+      ServerRequest* r = nullptr;
+      {
+        std::unique_lock<std::mutex> lock(mu);
+        cv_work.wait(lock, [&] { return stop || (!queue.empty() && (r = pick()) != nullptr); });
+        if (!r) break;  // stop with nothing admissible
+        in_flight_bytes += r->estimate;
+        r->st.state = HPDG_REQ_RUNNING;
+        r->st.start_ms = now_ms();
+        r->st.device_bytes = r->estimate;
+      }
+      run(r, s);
+      {
+        std::lock_guard<std::mutex> lock(mu);
+        in_flight_bytes -= r->estimate;
+      }
+      cv_done.notify_all();
+      cv_work.notify_all();
+    }
+    if (s) (void)hipStreamDestroy(s);
+  }
+};
 
 extern "C" {
 
@@ -816,85 +1177,11 @@ int hpdg_mesh_upload(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_
                      hpdg_mesh** out, void* stream) {
   if (!ctx || !out) return fail(ctx, HPDG_ERR_INVALID_ARG, "null argument");
   *out = nullptr;
-  auto M = std::make_unique<hpdg_mesh>();
-  M->ctx = ctx;
   return guarded(ctx, [&] {
-    check_mesh(desc);
     HIPCHK(hipSetDevice(ctx->device));
-    hipStream_t s = S(stream);
-    const int nm = desc->n_macro;
-    M->mm.macros.resize(nm);
-    for (int m = 0; m < nm; ++m) {
-      M->mm.macros[m].kind = desc->macro_kind[m];
-      if (desc->macro_kind[m] < 0 || desc->macro_kind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
-      std::memcpy(M->mm.macros[m].par, desc->macro_params + 16 * m, 16 * sizeof(double));
-    }
-    M->mm.nbr.assign(desc->macro_nbr, desc->macro_nbr + 6 * nm);
-    M->mm.nbr_face.assign(desc->macro_nbr_face, desc->macro_nbr_face + 6 * nm);
-    M->mm.nbr_orient.assign(desc->macro_nbr_orient, desc->macro_nbr_orient + 6 * nm);
-    M->mm.bc.assign(desc->macro_bc, desc->macro_bc + 6 * nm);
-    if (disc) {
-      M->dp.C = disc->penalty_C > 0 ? disc->penalty_C : 10.0;
-      M->dp.quad_extra = disc->quad_extra >= 0 ? disc->quad_extra : 1;
-      M->dp.coef_kind = disc->coef_kind;
-      for (int i = 0; i < 4; ++i) M->dp.coef[i] = disc->coef_params[i];
-      M->has_f32 = disc->build_f32 != 0;
-      M->dp.mass_term = disc->mass_term != 0 ? 1 : 0;
-    }
-    const int max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
-    M->tab.build();
-    // hierarchy
-    LevelHost L0;
-    L0.cells.resize(desc->n_elem);
-    for (long long e = 0; e < desc->n_elem; ++e) {
-      Cell& c = L0.cells[e];
-      c.macro = desc->elem_macro[e];
-      c.level = desc->elem_level[e];
-      c.a[0] = desc->elem_anchor[3 * e];
-      c.a[1] = desc->elem_anchor[3 * e + 1];
-      c.a[2] = desc->elem_anchor[3 * e + 2];
-      c.p = desc->elem_p[e];
-    }
-    M->H.push_back(std::move(L0));
-    while (int(M->H.size()) < max_levels) {
-      LevelHost next;
-      if (!coarsen_cells(M->mm, M->H.back().cells, next.cells)) break;
-      M->H.push_back(std::move(next));
-    }
-    for (auto& h : M->H) {
-      build_level(M->mm, M->dp, M->tab, h);
-      build_diagonal(M->tab, h);
-      for (double dgv : h.diag)
-        if (!(dgv > 0)) throw Error(HPDG_ERR_INVALID_MESH, "non-positive operator diagonal");
-    }
-    for (int l = 0; l + 1 < M->nlevels(); ++l) build_transfer(M->H[l], M->H[l + 1]);
-    // device tables
-    M->tab_off = M->upload_raw(M->tab.off, s);
-    M->dg_off = M->upload_raw(M->tab.dg_off, s);
-    M->w_off = M->upload_raw(M->tab.w_off, s);
-    M->dface_off = M->upload_raw(M->tab.dface_off, s);
-    M->tab64 = M->upload_raw(M->tab.data, s);
-    if (M->has_f32) M->tab32 = M->upload<float>(M->tab.data, s);
-    M->L64.resize(M->nlevels());
-    if (M->has_f32) M->L32.resize(M->nlevels());
-    for (int l = 0; l < M->nlevels(); ++l) {
-      build_device_level<double>(M.get(), l, s);
-      if (M->has_f32) build_device_level<float>(M.get(), l, s);
-    }
-    const long long n0 = M->H[0].ndof;
-    M->r = M->alloc<double>(n0);
-    M->vv = M->alloc<double>(n0);
-    M->w = M->alloc<double>(n0);
-    M->d = M->alloc<double>(n0);
-    M->q = M->alloc<double>(n0);
-    M->partials = M->alloc<double>(3 * kRedBlocks);
-    M->sc = M->alloc<double>(16);
-    HIPCHK(hipHostMalloc((void**)&M->host_sc, 16 * sizeof(double), hipHostMallocDefault));
-    launch_fill<double>(16, 0.0, M->sc, s);
-    build_coarse(M.get(), s);
-    M->lam.assign(M->nlevels(), 0.0);
-    HIPCHK(hipStreamSynchronize(s));
-    HIPCHK(hipGetLastError());
+    std::unique_ptr<hpdg_mesh> M = build_mesh_host(ctx, desc, disc);
+    upload_mesh_device(M.get(), S(stream));
+    std::lock_guard<std::mutex> lock(ctx->mu);
     ctx->meshes.push_back(M.get());
     *out = M.release();
   });
@@ -936,21 +1223,17 @@ int hpdg_mesh_free(hpdg_mesh* mesh) {
   if (!mesh) return HPDG_ERR_INVALID_ARG;
   hpdg_ctx* ctx = mesh->ctx;
   (void)hipSetDevice(ctx->device);
-  ctx->meshes.erase(std::remove(ctx->meshes.begin(), ctx->meshes.end(), mesh), ctx->meshes.end());
+  {
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    ctx->meshes.erase(std::remove(ctx->meshes.begin(), ctx->meshes.end(), mesh), ctx->meshes.end());
+  }
   delete mesh;
   return HPDG_OK;
 }
 
 int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream) {
   if (!mesh || !rhs || !F_dev) return HPDG_ERR_INVALID_ARG;
-  return guarded(mesh->ctx, [&] {
-    std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
-    if (rhs->kind < 0 || rhs->kind > 5) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
-    std::vector<double> F;
-    assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);
-    HIPCHK(hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, S(stream)));
-    HIPCHK(hipStreamSynchronize(S(stream)));
-  });
+  return guarded(mesh->ctx, [&] { assemble_rhs_impl(mesh, rhs, F_dev, S(stream)); });
 }
 
 int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream) {
@@ -994,28 +1277,7 @@ int hpdg_kernel_timing(hpdg_mesh* mesh, int kind, int level, int prec, double* t
 int hpdg_setup_smoother(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max,
                         void* stream) {
   if (!mesh) return HPDG_ERR_INVALID_ARG;
-  return guarded(mesh->ctx, [&] {
-    if (params) {
-      mesh->sp = *params;
-      if (mesh->sp.n_cheb <= 0) mesh->sp.n_cheb = 4;
-      if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
-      if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
-      if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)
-        throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
-    }
-    hipStream_t s = S(stream);
-    if (mesh->sp.scaling == HPDG_SMOOTH_BLOCK)
-      for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
-    for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
-      if (lambda_max && lambda_max[l] > 0)
-        mesh->lam[l] = lambda_max[l];
-      else
-        mesh->lam[l] = cg_bound(mesh, l, mesh->sp.n_eigs, mesh->sp.seed, s);
-      if (lambda_max) lambda_max[l] = mesh->lam[l];
-    }
-    HIPCHK(hipStreamSynchronize(s));
-    mesh->smoother_ready = true;
-  });
+  return guarded(mesh->ctx, [&] { setup_smoother_impl(mesh, params, lambda_max, S(stream)); });
 }
 
 int hpdg_smooth(hpdg_mesh* mesh, int level, int prec, const void* b_dev, void* x_dev, int n_iter,
@@ -1054,7 +1316,7 @@ int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (!mesh || !params || !b_dev || !u_dev) return HPDG_ERR_INVALID_ARG;
   if (!mesh->smoother_ready) return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
-  if (params->precision == HPDG_PREC_MIXED && !mesh->has_f32)
+  if (params->precision != HPDG_PREC_F64 && !mesh->has_f32)
     return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
   int iters = 0;
   double rel = 0;
@@ -1099,7 +1361,7 @@ int hpdg_newton_solve(hpdg_mesh* mesh, const hpdg_newton_params* params, const h
                       const double* F_dev, double* u_dev, hpdg_newton_stats* stats, void* stream) {
   if (stats) std::memset(stats, 0, sizeof(*stats));
   if (!mesh || !params || !nl || !u_dev || F_dev == u_dev) return HPDG_ERR_INVALID_ARG;
-  if (params->precision == HPDG_PREC_MIXED && !mesh->has_f32)
+  if (params->precision != HPDG_PREC_F64 && !mesh->has_f32)
     return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
   int steps = 0, lin = 0;
   double rel = 1.0;
@@ -1147,6 +1409,128 @@ int hpdg_newton_solve(hpdg_mesh* mesh, const hpdg_newton_params* params, const h
     stats->status = rc;
   }
   return rc;
+}
+
+int hpdg_server_create(hpdg_ctx* ctx, const hpdg_server_params* params, hpdg_server** out) {
+  if (!ctx || !params || !out || params->max_active < 1 || params->max_active > 64)
+    return fail(ctx, HPDG_ERR_INVALID_ARG, "invalid server parameters");
+  auto* sv = new hpdg_server;
+  sv->ctx = ctx;
+  sv->p = *params;
+  if (sv->p.max_iter <= 0) sv->p.max_iter = 1000;
+  if (!(sv->p.tol_rel > 0)) sv->p.tol_rel = 1e-10;
+  sv->t0 = std::chrono::steady_clock::now();
+  for (int w = 0; w < sv->p.max_active; ++w) sv->workers.emplace_back([sv] { sv->worker(); });
+  *out = sv;
+  return HPDG_OK;
+}
+
+int hpdg_server_submit(hpdg_server* sv, const hpdg_request* rq, uint64_t* ticket) {
+  if (!sv || !rq || !ticket || !rq->u_out) return HPDG_ERR_INVALID_ARG;
+  return guarded(sv->ctx, [&] {
+    check_mesh(&rq->mesh);
+    auto r = std::make_unique<ServerRequest>();
+    const hpdg_mesh_desc& d = rq->mesh;
+    const int nm = d.n_macro;
+    const int64_t E = d.n_elem;
+    r->mkind.assign(d.macro_kind, d.macro_kind + nm);
+    r->mparams.assign(d.macro_params, d.macro_params + 16 * nm);
+    r->mnbr.assign(d.macro_nbr, d.macro_nbr + 6 * nm);
+    r->mnface.assign(d.macro_nbr_face, d.macro_nbr_face + 6 * nm);
+    r->mnor.assign(d.macro_nbr_orient, d.macro_nbr_orient + 6 * nm);
+    r->mbc.assign(d.macro_bc, d.macro_bc + 6 * nm);
+    r->emacro.assign(d.elem_macro, d.elem_macro + E);
+    r->elevel.assign(d.elem_level, d.elem_level + E);
+    r->eanchor.assign(d.elem_anchor, d.elem_anchor + 3 * E);
+    r->ep.assign(d.elem_p, d.elem_p + E);
+    for (int m = 0; m < nm; ++m)
+      if (r->mkind[m] < 0 || r->mkind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
+    for (int64_t e = 0; e < E; ++e)
+      if (r->emacro[e] < 0 || r->emacro[e] >= nm) throw Error(HPDG_ERR_INVALID_MESH, "element macro out of range");
+    r->desc = hpdg_mesh_desc{nm, r->mkind.data(), r->mparams.data(), r->mnbr.data(), r->mnface.data(),
+                             r->mnor.data(), r->mbc.data(), E, r->emacro.data(), r->elevel.data(),
+                             r->eanchor.data(), r->ep.data()};
+    r->disc = rq->disc;
+    r->disc.build_f32 = sv->p.precision != HPDG_PREC_F64 ? 1 : r->disc.build_f32;
+    if (rq->rhs.n_params > 0) {
+      if (!rq->rhs.params) throw Error(HPDG_ERR_INVALID_ARG, "rhs parameters missing");
+      r->rhs_params.assign(rq->rhs.params, rq->rhs.params + rq->rhs.n_params);
+    }
+    r->rhs = hpdg_rhs_desc{rq->rhs.kind, int32_t(r->rhs_params.size()), r->rhs_params.data()};
+    r->u_out = rq->u_out;
+    r->estimate = estimate_from_desc(r->desc, r->disc, sv->p.smoother.scaling);
+    auto put = [&](const void* ptr, size_t bytes) { r->key.append(static_cast<const char*>(ptr), bytes); };
+    const hpdg_disc_params& dc = r->disc;  // field by field (the struct has padding)
+    put(&dc.penalty_C, 8);
+    put(&dc.quad_extra, 4);
+    put(&dc.coef_kind, 4);
+    put(dc.coef_params, 32);
+    put(&dc.max_levels, 4);
+    put(&dc.build_f32, 4);
+    put(&dc.mass_term, 4);
+    put(r->mkind.data(), 4 * r->mkind.size());
+    put(r->mparams.data(), 8 * r->mparams.size());
+    put(r->mnbr.data(), 4 * r->mnbr.size());
+    put(r->mnface.data(), 4 * r->mnface.size());
+    put(r->mnor.data(), 4 * r->mnor.size());
+    put(r->mbc.data(), 4 * r->mbc.size());
+    put(r->emacro.data(), 4 * r->emacro.size());
+    put(r->elevel.data(), 4 * r->elevel.size());
+    put(r->eanchor.data(), 4 * r->eanchor.size());
+    put(r->ep.data(), 4 * r->ep.size());
+    std::lock_guard<std::mutex> lock(sv->mu);
+    if (sv->stop) throw Error(HPDG_ERR_INVALID_ARG, "server is shutting down");
+    r->ticket = sv->next_ticket++;
+    r->st.state = HPDG_REQ_QUEUED;
+    r->st.submit_ms = sv->now_ms();
+    *ticket = r->ticket;
+    sv->queue.push_back(r->ticket);
+    sv->reqs[r->ticket] = std::move(r);
+    sv->cv_work.notify_one();
+  });
+}
+
+int hpdg_server_poll(hpdg_server* sv, uint64_t ticket, hpdg_request_status* status) {
+  if (!sv || !status) return HPDG_ERR_INVALID_ARG;
+  std::lock_guard<std::mutex> lock(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return HPDG_ERR_INVALID_ARG;
+  *status = it->second->st;
+  return HPDG_OK;
+}
+
+int hpdg_server_wait(hpdg_server* sv, uint64_t ticket, int64_t timeout_ms, hpdg_request_status* status) {
+  if (!sv || !status) return HPDG_ERR_INVALID_ARG;
+  std::unique_lock<std::mutex> lock(sv->mu);
+  auto it = sv->reqs.find(ticket);
+  if (it == sv->reqs.end()) return HPDG_ERR_INVALID_ARG;
+  ServerRequest* r = it->second.get();
+  auto done = [&] { return r->st.state == HPDG_REQ_DONE || r->st.state == HPDG_REQ_FAILED; };
+  if (timeout_ms < 0)
+    sv->cv_done.wait(lock, done);
+  else
+    sv->cv_done.wait_for(lock, std::chrono::milliseconds(timeout_ms), done);
+  *status = r->st;
+  return HPDG_OK;
+}
+
+int hpdg_server_destroy(hpdg_server* sv) {
+  if (!sv) return HPDG_ERR_INVALID_ARG;
+  {
+    std::lock_guard<std::mutex> lock(sv->mu);
+    sv->stop = true;
+    for (uint64_t t : sv->queue) {
+      ServerRequest* r = sv->reqs[t].get();
+      r->st.state = HPDG_REQ_FAILED;
+      r->st.status = HPDG_ERR_INVALID_ARG;
+    }
+    sv->queue.clear();
+  }
+  sv->cv_work.notify_all();
+  for (auto& w : sv->workers) w.join();
+  sv->cv_done.notify_all();
+  delete sv;
+  return HPDG_OK;
 }
 
 }  // extern "C"

@@ -88,6 +88,12 @@ template <typename T>
 void launch_symmetrize_blocks(const LevelView<T>& L, const long long* boff, T* B, hipStream_t s);
 void launch_blocks_d2f(const LevelView<double>& L, const long long* boff, const double* B, float* Bf,
                        hipStream_t s);
+// bf16 copies of the FP32 inverse blocks (round to nearest even) and the Chebyshev step that
+// reads them (FP32 arithmetic)
+void launch_blocks_f2bf(const LevelView<float>& L, const long long* boff, const float* B, uint16_t* Bh,
+                        hipStream_t s);
+void launch_block_cheb_bf16(const LevelView<float>& L, const long long* boff, const uint16_t* Binv, const float* b,
+                            const float* Ax, float* p, float* x, float alpha, float beta, int first, hipStream_t s);
 // z = Binv r per element
 template <typename T>
 void launch_block_apply(const LevelView<T>& L, const long long* boff, const T* Binv, const T* r, T* z,

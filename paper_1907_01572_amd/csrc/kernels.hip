@@ -56,6 +56,45 @@ __global__ void __launch_bounds__(kBS) blocks_d2f_kernel(LevelView<double> L, co
   for (long long idx = threadIdx.x; idx < N * N; idx += blockDim.x) Bf[boff[e] + idx] = float(B[boff[e] + idx]);
 }
 
+// bf16 storage of the FP32 inverse blocks: round to nearest even on the upper 16 bits
+__device__ inline uint16_t f2bf(float v) {
+  const uint32_t u = __float_as_uint(v);
+  return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
+
+__global__ void __launch_bounds__(kBS) blocks_f2bf_kernel(LevelView<float> L, const long long* boff,
+                                                          const float* B, uint16_t* Bh) {
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const long long N = (long long)I.n * I.n * I.n;
+  for (long long idx = threadIdx.x; idx < N * N; idx += blockDim.x) Bh[boff[e] + idx] = f2bf(B[boff[e] + idx]);
+}
+
+// Chebyshev step with bf16 inverse blocks: operands widened to FP32, FP32 accumulation
+__global__ void __launch_bounds__(kBS) block_cheb_bf16_kernel(LevelView<float> L, const long long* boff,
+                                                              const uint16_t* Binv, const float* b, const float* Ax,
+                                                              float* p, float* x, float alpha, float beta,
+                                                              int first) {
+  extern __shared__ unsigned char smem_raw[];
+  float* r = reinterpret_cast<float*>(smem_raw);
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int N = I.n * I.n * I.n;
+  for (int i = threadIdx.x; i < N; i += blockDim.x) r[i] = Ax ? b[I.off + i] - Ax[I.off + i] : b[I.off + i];
+  __syncthreads();
+  const uint16_t* B = Binv + boff[e];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    float z = 0;
+    for (int j = 0; j < N; ++j) z += bf2f(B[(long long)j * N + i]) * r[j];
+    const float pn = first ? alpha * z : alpha * z + beta * p[I.off + i];
+    p[I.off + i] = pn;
+    x[I.off + i] += pn;
+  }
+}
+
 // per element: z = Binv r (block_cheb: r = b - Ax first, then the Chebyshev update)
 template <typename T, bool CHEB>
 __global__ void __launch_bounds__(kBS) block_kernel(LevelView<T> L, const long long* boff, const T* Binv,
@@ -382,6 +421,17 @@ void launch_block_cheb(const LevelView<T>& L, const long long* boff, const T* Bi
   const size_t lds = sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
   hipLaunchKernelGGL((block_kernel<T, true>), dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv,
                      b, Ax, p, x, alpha, beta, first);
+}
+
+void launch_blocks_f2bf(const LevelView<float>& L, const long long* boff, const float* B, uint16_t* Bh,
+                        hipStream_t s) {
+  hipLaunchKernelGGL(blocks_f2bf_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, Bh);
+}
+void launch_block_cheb_bf16(const LevelView<float>& L, const long long* boff, const uint16_t* Binv, const float* b,
+                            const float* Ax, float* p, float* x, float alpha, float beta, int first, hipStream_t s) {
+  const size_t lds = sizeof(float) * size_t(L.nmax) * L.nmax * L.nmax;
+  hipLaunchKernelGGL(block_cheb_bf16_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv, b, Ax, p,
+                     x, alpha, beta, first);
 }
 
 template <typename T>

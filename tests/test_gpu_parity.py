@@ -144,11 +144,13 @@ def test_cg_spectral_bound_close_to_oracle(ctx, smoother):
     ("shell_l2_p3_r1e3", hp.SOLVER_FCG, hp.PREC_F64),
     ("shell_l2_p3_r1e3", hp.SOLVER_FCG, hp.PREC_MIXED),
     ("shell_l2_p4_r1e9", hp.SOLVER_FCG, hp.PREC_F64),
+    ("shell_l2_p3_r1e3", hp.SOLVER_FCG, hp.PREC_MIXED_BF16),
+    ("shell_l2_p4_r1e9", hp.SOLVER_FCG, hp.PREC_MIXED_BF16),
 ])
 def test_solve_reaches_oracle_residual(ctx, name, solver, prec):
     maker, prob = MESHES[name]
     m = maker()
-    M = ctx.upload(m, coef=coef_of(prob), build_f32=(prec == hp.PREC_MIXED))
+    M = ctx.upload(m, coef=coef_of(prob), build_f32=(prec != hp.PREC_F64))
     M.setup_smoother(n_cheb=4, smoother="block" if name.startswith("shell") else "point")
     F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
     M.assemble_rhs(prob, F)
