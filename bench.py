@@ -111,8 +111,8 @@ def make_workload(args, meshgen, hp):
         w["mesh"] = meshgen.cubed_sphere_shell(level=args.level, p=args.p)
         w["prob"] = meshgen.problem_config2()
         w["upload"] = dict(build_f32=True)
-        w["smoother"] = dict(n_cheb=args.n_cheb or 8, smoother=args.smoother or "block",
-                             Lambda=args.Lambda or 100.0)
+        w["smoother"] = dict(n_cheb=args.n_cheb or 20, smoother=args.smoother or "block",
+                             Lambda=args.Lambda or 400.0)
         w["desc"] = ("cubed-sphere shell r=1..1e9 (compactified), 6x8^3 cells + 2:1 inner layer, p=%d, "
                      "Poisson, MG-FCG to 1e-10" % args.p)
     elif args.workload == "hp":

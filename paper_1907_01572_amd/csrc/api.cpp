@@ -121,6 +121,7 @@ struct hpdg_mesh {
     long long calls = 0;
   };
   std::vector<long long> block_scalars = std::vector<long long>(32, 0);  // inverse-block scalars per level
+  int block_retries = 0;  // block factorisations repeated after a failed attempt
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
   Acc acc[HPDG_TIMING_KINDS][32][2];
@@ -496,6 +497,9 @@ double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
   return bound;
 }
 
+void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff, double* B,
+                   hipStream_t s);
+
 // element-block Jacobi: A_ee of every element of level l (column j of all blocks from one
 // apply with neighbours taken as zero), then their inverses by batched Cholesky (rocSOLVER)
 void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
@@ -513,6 +517,37 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
   double* B = M->alloc<double>(size_t(boff[E]));
   LevelView<double> V = M->view<double>(l);
   V.self_only = 1;
+  // A failed factorisation is retried once from a fresh gather (the blocks are SPD: a
+  // failure that does not repeat is not a property of the operator); a repeated one is an error.
+  for (int attempt = 0;; ++attempt) {
+    try {
+      factor_blocks(M, l, V, boff, B, s);
+      break;
+    } catch (const Error& err) {
+      if (attempt >= 1 || err.code != HPDG_ERR_BREAKDOWN) throw;
+      M->block_retries += 1;
+    }
+  }
+  launch_symmetrize_blocks<double>(V, d.boff, B, s);
+  d.binv = B;
+  if (M->has_f32) {
+    DevLevel<float>& d32 = M->lev<float>(l);
+    d32.boff = d.boff;
+    d32.binv = M->alloc<float>(size_t(boff[E]));
+    launch_blocks_d2f(V, d.boff, B, d32.binv, s);
+    d32.binv16 = M->alloc<uint16_t>(size_t(boff[E]));
+    launch_blocks_f2bf(M->view<float>(l), d.boff, d32.binv, d32.binv16, s);
+  }
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+// gather the element blocks of level l (column j of every block from one self-only apply),
+// check them, and replace them by their inverses (batched Cholesky + inverse, rocSOLVER)
+void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff, double* B,
+                   hipStream_t s) {
+  DevLevel<double>& d = M->lev<double>(l);
+  const LevelHost& h = M->H[l];
+  const size_t E = h.cells.size();
   launch_fill<double>(h.ndof, 0.0, d.f, s);
   const int nmax3 = h.nmax * h.nmax * h.nmax;
   for (int j = 0; j < nmax3; ++j) {
@@ -520,6 +555,20 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
     launch_apply<double>(V, d.f, d.t, s);
     launch_gather_column<double>(V, j, d.t, d.boff, B, s);
     launch_set_unit<double>(V, j, 0.0, d.f, s);
+  }
+  {
+    int* bad = nullptr;
+    HIPCHK(hipMalloc(&bad, E * sizeof(int)));
+    launch_check_blocks(V, d.boff, B, d.dinv, bad, s);
+    std::vector<int> hb(E);
+    HIPCHK(hipMemcpyAsync(hb.data(), bad, E * sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    (void)hipFree(bad);
+    for (size_t e = 0; e < E; ++e)
+      if (hb[e])
+        throw Error(HPDG_ERR_HIP, "element block " + std::to_string(e) + " on level " + std::to_string(l) +
+                                      ": gathered column " + std::to_string(hb[e] - 1) +
+                                      " is inconsistent with the operator diagonal / symmetry");
   }
   if (!M->blas) {
     if (rocblas_create_handle(&M->blas) != rocblas_status_success) throw Error(HPDG_ERR_HIP, "rocblas handle");
@@ -566,16 +615,6 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
     check(rocsolver_dpotri_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt), "inverse");
     (void)hipFree(dptrs);
     (void)hipFree(info);
-  }
-  launch_symmetrize_blocks<double>(V, d.boff, B, s);
-  d.binv = B;
-  if (M->has_f32) {
-    DevLevel<float>& d32 = M->lev<float>(l);
-    d32.boff = d.boff;
-    d32.binv = M->alloc<float>(size_t(boff[E]));
-    launch_blocks_d2f(V, d.boff, B, d32.binv, s);
-    d32.binv16 = M->alloc<uint16_t>(size_t(boff[E]));
-    launch_blocks_f2bf(M->view<float>(l), d.boff, d32.binv, d32.binv16, s);
   }
   HIPCHK(hipStreamSynchronize(s));
 }

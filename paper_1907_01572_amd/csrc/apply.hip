@@ -21,8 +21,7 @@ namespace hpdg {
 
 namespace {
 
-// threads per workgroup (one element per workgroup); a compile-time constant because the
-// register prefetch arrays are sized by it
+// threads per workgroup (one element per workgroup)
 #ifndef HPDG_APPLY_THREADS
 #define HPDG_APPLY_THREADS 256
 #endif
@@ -145,10 +144,10 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
 // matrices (values / derivatives at the full, lower-half and upper-half point sets) are
 // staged in LDS once, and each phase maps threads to (task, item) with constant strides.
 // Adds the face terms to sy and writes y.
-template <typename T, int N, int Q, int KNB>
+template <typename T, int N, int Q>
 __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, const T* __restrict__ x,
                               T* __restrict__ y, const T* su, const T* sy, const T* dfo, T* region, Task* tasks,
-                              const Layout& lay, const T (&nb)[KNB]) {
+                              const Layout& lay) {
   constexpr int N2 = N * N, N3 = N2 * N, QQ = Q * Q, NQ = N * Q;
   const int NM = lay.NM, QMM = lay.QMM;
   const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
@@ -162,47 +161,15 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
   int rounds = 0;
 #pragma unroll
   for (int f = 0; f < kFaces; ++f) rounds = I.fcnt[f] > rounds ? I.fcnt[f] : rounds;
-  constexpr int kP4 = (kFaces * QQ + kThreads - 1) / kThreads;
   for (int r = 0; r < rounds; ++r) {
-    if (r == 0) {
-      // the round-0 tasks were made and their neighbour coefficients loaded into registers
-      // before the volume passes
-#pragma unroll
-      for (int k = 0; k < KNB; ++k) {
-        const int g = threadIdx.x + k * kThreads;
-        if (g < kFaces * N3 && tasks[g / N3].other) RA[(g / N3) * raS + g % N3] = nb[k];
-      }
-    } else {
-      __syncthreads();
-      for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
-      __syncthreads();
-      // P0: neighbour coefficients
-      for (int g = threadIdx.x; g < kFaces * N3; g += blockDim.x) {
-        const int t = g / N3, i = g % N3;
-        if (tasks[t].other) RA[t * raS + i] = x[tasks[t].ooff + i];
-      }
+    for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
+    __syncthreads();
+    // P0: neighbour coefficients
+    for (int g = threadIdx.x; g < kFaces * N3; g += blockDim.x) {
+      const int t = g / N3, i = g % N3;
+      if (tasks[t].other) RA[t * raS + i] = x[tasks[t].ooff + i];
     }
     __syncthreads();
-    // mortar metric of this thread's P4 points, loaded now to overlap P1 - P3
-    T mpf[kP4][8];
-#pragma unroll
-    for (int k = 0; k < kP4; ++k) {
-      const int g = threadIdx.x + k * kThreads;
-#pragma unroll
-      for (int m = 0; m < 8; ++m) mpf[k][m] = T(0);
-      if (g < kFaces * QQ) {
-        const Task& tk = tasks[g / QQ];
-        if (tk.valid) {
-          const int li = g % QQ, npts = tk.gmode ? QQ : 1;
-          const int xg = li % Q, yg = li / Q;
-          const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
-          const int pp = tk.gmode ? cc + Q * dd : 0;
-          const T* mg = L.mgeo + tk.geo;
-#pragma unroll
-          for (int m = 0; m < 8; ++m) mpf[k][m] = mg[m * npts + pp];
-        }
-      }
-    }
     // P1: traces (values, reference normal derivative) of the own face and the neighbour's
     for (int g = threadIdx.x; g < kFaces * 2 * N2; g += blockDim.x) {
       const int t = g / (2 * N2), li = g % (2 * N2);
@@ -285,33 +252,28 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
     }
     __syncthreads();
     // P4: SIPG flux at the mortar points, own side, own frame
-#pragma unroll
-    for (int k = 0; k < kP4; ++k) {
-      const int g = threadIdx.x + k * kThreads;
-      if (g >= kFaces * QQ) continue;
+    for (int g = threadIdx.x; g < kFaces * QQ; g += blockDim.x) {
       const int t = g / QQ, li = g % QQ;
       const Task& tk = tasks[t];
       if (!tk.valid) continue;
       const int side = tk.side;
-      const T* mv = mpf[k];  // the 8 metric planes at this point
+      const int npts = tk.gmode ? QQ : 1;
+      const T* mg = L.mgeo + tk.geo;
       const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
       const int xg = li % Q, yg = li / Q;
       const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
+      const int pp = tk.gmode ? cc + Q * dd : 0;
       T wS;
       if (tk.gmode) {
-        wS = mv[6];
+        wS = mg[6 * npts + pp];
       } else {
         const T* wm = L.tab + L.tv.w_off[Q];
-        wS = wm[cc] * wm[dd] * mv[6];
+        wS = wm[cc] * wm[dd] * mg[6];
       }
-      const T sig = mv[7];
-      auto pick3 = [&](int base, int comp) {
-        // component comp of the 3-vector stored in planes base .. base + 2
-        return comp == 0 ? mv[base] : (comp == 1 ? mv[base + 1] : mv[base + 2]);
-      };
-      const T ma = pick3(3 * side, t0);
-      const T mb = pick3(3 * side, t1);
-      const T mn = pick3(3 * side, d);
+      const T sig = mg[7 * npts + pp];
+      const T ma = mg[(3 * side + t0) * npts + pp];
+      const T mb = mg[(3 * side + t1) * npts + pp];
+      const T mn = mg[(3 * side + d) * npts + pp];
       const T* Gm = RB + t * rbS;
       const T u_me = Gm[li];
       const T g_me = ma * Gm[QMM * QMM + li] + mb * Gm[2 * QMM * QMM + li] + mn * Gm[3 * QMM * QMM + li];
@@ -324,8 +286,9 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
           const int oi = tk.ot.swap ? dd + Q * cc : cc + Q * dd;
           const T* Go = Gm + 4 * QMM * QMM;
           u_o = Go[oi];
-          g_o = pick3(3 * os, ot0) * Go[QMM * QMM + oi] + pick3(3 * os, ot1) * Go[2 * QMM * QMM + oi] +
-                pick3(3 * os, od) * Go[3 * QMM * QMM + oi];
+          g_o = mg[(3 * os + ot0) * npts + pp] * Go[QMM * QMM + oi] +
+                mg[(3 * os + ot1) * npts + pp] * Go[2 * QMM * QMM + oi] +
+                mg[(3 * os + od) * npts + pp] * Go[3 * QMM * QMM + oi];
         }
         const T jmp = u_me - u_o;
         Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
@@ -464,37 +427,8 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     for (int i = threadIdx.x; i < q * q; i += blockDim.x) Dg[i] = Dgg[i];
     for (int i = threadIdx.x; i < q; i += blockDim.x) w[i] = wg[i];
     for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) dfo[(i / n) * NM + i % n] = dfg[i];
-    if constexpr (UNI)
-      for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, 0);
   }
   __syncthreads();
-
-  // uniform level: issue the global loads the later phases need now, into registers, so that
-  // their latency overlaps the volume passes: the volume metric of this thread's GL points and
-  // the coefficients of the neighbours met in the first face round
-  constexpr int kGp = UNI ? (QT * QT * QT + kThreads - 1) / kThreads : 1;
-  constexpr int kNb = UNI ? (kFaces * NT * NT * NT + kThreads - 1) / kThreads : 1;
-  T gm[kGp][6];
-  T nb[kNb];
-  const T* G = L.vgeo + I.vgeo;
-  if constexpr (UNI) {
-#pragma unroll
-    for (int k = 0; k < kGp; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
-#pragma unroll
-      for (int m = 0; m < 6; ++m) gm[k][m] = (idx < q3 && I.vmode != 0) ? G[m * q3 + idx] : T(0);
-    }
-#pragma unroll
-    for (int k = 0; k < kNb; ++k) {
-      const int g = threadIdx.x + k * kThreads;
-      constexpr int N3c = NT * NT * NT;
-      nb[k] = T(0);
-      if (g < kFaces * N3c) {
-        const Task& tk = tasks[g / N3c];
-        if (tk.valid && tk.other) nb[k] = x[tk.ooff + g % N3c];
-      }
-    }
-  }
 
   // ---- volume: u -> GL values (three 1-D passes) ----
   for (int idx = threadIdx.x; idx < n2 * q; idx += blockDim.x) {
@@ -522,7 +456,8 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   }
   __syncthreads();
   // ---- reference gradient at the GL points and the metric contraction ----
-  auto metric_point = [&](int idx, const T* gp) {
+  const T* G = L.vgeo + I.vgeo;
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
     const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
     T g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
@@ -536,9 +471,6 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       const T ww = w[a] * w[b] * w[c];
       G00 = G[0] * ww; G01 = G[1] * ww; G02 = G[2] * ww;
       G11 = G[3] * ww; G12 = G[4] * ww; G22 = G[5] * ww;
-    } else if (gp) {
-      G00 = gp[0]; G01 = gp[1]; G02 = gp[2];
-      G11 = gp[3]; G12 = gp[4]; G22 = gp[5];
     } else {
       G00 = G[idx]; G01 = G[q3 + idx]; G02 = G[2 * q3 + idx];
       G11 = G[3 * q3 + idx]; G12 = G[4 * q3 + idx]; G22 = G[5 * q3 + idx];
@@ -546,15 +478,6 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     A1[idx] = G00 * g0 + G01 * g1 + G02 * g2;
     A2[idx] = G01 * g0 + G11 * g1 + G12 * g2;
     A3[idx] = G02 * g0 + G12 * g1 + G22 * g2;
-  };
-  if constexpr (UNI) {
-#pragma unroll
-    for (int k = 0; k < kGp; ++k) {
-      const int idx = threadIdx.x + k * kThreads;
-      if (idx < q3) metric_point(idx, gm[k]);
-    }
-  } else {
-    for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) metric_point(idx, nullptr);
   }
   __syncthreads();
   for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
@@ -598,7 +521,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
 
   // ---- faces ----
   if constexpr (UNI) {
-    faces_uniform<T, NT, QT, kNb>(L, I, e, x, y, su, sy, dfo, region, tasks, lay, nb);
+    faces_uniform<T, NT, QT>(L, I, e, x, y, su, sy, dfo, region, tasks, lay);
     return;
   }
   int rounds = 0;

@@ -88,6 +88,10 @@ template <typename T>
 void launch_symmetrize_blocks(const LevelView<T>& L, const long long* boff, T* B, hipStream_t s);
 void launch_blocks_d2f(const LevelView<double>& L, const long long* boff, const double* B, float* Bf,
                        hipStream_t s);
+// bad[e] = 1 + first column of element e's gathered block that is not symmetric or whose
+// diagonal differs from 1 / dinv; 0 when consistent
+void launch_check_blocks(const LevelView<double>& L, const long long* boff, const double* B, const double* dinv,
+                         int* bad, hipStream_t s);
 // bf16 copies of the FP32 inverse blocks (round to nearest even) and the Chebyshev step that
 // reads them (FP32 arithmetic)
 void launch_blocks_f2bf(const LevelView<float>& L, const long long* boff, const float* B, uint16_t* Bh,

@@ -56,6 +56,32 @@ __global__ void __launch_bounds__(kBS) blocks_d2f_kernel(LevelView<double> L, co
   for (long long idx = threadIdx.x; idx < N * N; idx += blockDim.x) Bf[boff[e] + idx] = float(B[boff[e] + idx]);
 }
 
+// consistency of freshly gathered element blocks before their factorisation: the diagonal must
+// equal the level's stored diagonal (computed independently on the host) and the block must be
+// symmetric; bad[e] = 1 + first offending column of element e, or 0
+__global__ void __launch_bounds__(kBS) check_blocks_kernel(LevelView<double> L, const long long* boff,
+                                                           const double* B, const double* dinv, int* bad) {
+  __shared__ int first;
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int N = I.n * I.n * I.n;
+  const double* Be = B + boff[e];
+  if (threadIdx.x == 0) first = N;
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < N * N; idx += blockDim.x) {
+    const int i = idx % N, j = idx / N;
+    const double a = Be[(long long)j * N + i], b = Be[(long long)i * N + j];
+    const double dref = 1.0 / dinv[I.off + j];
+    const double scale = fabs(Be[(long long)j * N + j]) + fabs(Be[(long long)i * N + i]);
+    bool ok = fabs(a - b) <= 1e-9 * scale;
+    if (i == j) ok = ok && fabs(a - dref) <= 1e-9 * fabs(dref);
+    if (!ok) atomicMin(&first, j);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) bad[e] = first < N ? first + 1 : 0;
+}
+
 // bf16 storage of the FP32 inverse blocks: round to nearest even on the upper 16 bits
 __device__ inline uint16_t f2bf(float v) {
   const uint32_t u = __float_as_uint(v);
@@ -423,6 +449,10 @@ void launch_block_cheb(const LevelView<T>& L, const long long* boff, const T* Bi
                      b, Ax, p, x, alpha, beta, first);
 }
 
+void launch_check_blocks(const LevelView<double>& L, const long long* boff, const double* B, const double* dinv,
+                         int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(check_blocks_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, dinv, bad);
+}
 void launch_blocks_f2bf(const LevelView<float>& L, const long long* boff, const float* B, uint16_t* Bh,
                         hipStream_t s) {
   hipLaunchKernelGGL(blocks_f2bf_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, Bh);

@@ -169,7 +169,24 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     if (I.q > kMaxQ) throw Error(-2, "too many quadrature points");
     I.off = off;
     off += (long long)I.n * I.n * I.n;
-    I.vmode = (affine && kc) ? 0 : 1;
+    // constant metric: affine map and one value of k at every GL point of the element (k is
+    // folded into the 6 stored values; the rule keeps its q points)
+    double kel = 1.0;
+    bool kflat = kc;
+    if (affine && !kc) {
+      gauss_legendre(I.q, eta, wq);
+      kflat = true;
+      for (int cc = 0; cc < I.q && kflat; ++cc)
+        for (int b = 0; b < I.q && kflat; ++b)
+          for (int a = 0; a < I.q && kflat; ++a) {
+            double xi[3] = {eta[a], eta[b], eta[cc]}, xp[3], Jp[3][3];
+            cell_eval(mm, c, xi, xp, Jp);
+            const double kv = coef_k(dp, xp);
+            if (a == 0 && b == 0 && cc == 0) kel = kv;
+            kflat = kv == kel;
+          }
+    }
+    I.vmode = (affine && kflat) ? 0 : 1;
     I.mass = dp.mass_term ? 1 : 0;
     I.mq = L.nmq;
     if (I.mass) L.nmq += (long long)I.q * I.q * I.q;
@@ -187,7 +204,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       for (int m = 0; m < 6; ++m) {
         double g = 0;
         for (int i = 0; i < 3; ++i) g += Ji[pr[m][0]][i] * Ji[pr[m][1]][i];
-        L.vgeo.push_back(dj * g);
+        L.vgeo.push_back(dj * kel * g);
       }
     } else {
       const int q = I.q, q3 = q * q * q;
@@ -254,7 +271,22 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     const int pm = std::max(nm, np) - 1;
     I.q = std::max(nm, np) + ((curved || !kc) ? dp.quad_extra : 0);
     if (I.q > kMaxQ) throw Error(-2, "too many mortar quadrature points");
-    I.gmode = (curved || !kc) ? 1 : 0;
+    // constant metric on a flat mortar with one value of k at all its points (folded in)
+    double kmt = 1.0;
+    bool kflat = kc;
+    if (!curved && !kc) {
+      gauss_legendre(I.q, eta, wq);
+      kflat = true;
+      for (int pidx = 0; pidx < I.q * I.q && kflat; ++pidx) {
+        double xim[3], xp[3], Jp[3][3];
+        face_ref(mt.fm, eta[pidx % I.q], eta[pidx / I.q], xim);
+        cell_eval(mm, cm, xim, xp, Jp);
+        const double kv = coef_k(dp, xp);
+        if (pidx == 0) kmt = kv;
+        kflat = kv == kmt;
+      }
+    }
+    I.gmode = (curved || !kflat) ? 1 : 0;
     I.geo = (long long)L.mgeo.size();
     L.qmmax = std::max(L.qmmax, I.q);
     lists[size_t(mt.em) * 6 + mt.fm].push_back(int(mi) << 1);
@@ -278,7 +310,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       double nh[3] = {sgn * Ji[dmn][0] / nr, sgn * Ji[dmn][1] / nr, sgn * Ji[dmn][2] / nr};
       const double S = dj * nr;
       double h = 2.0 / nr;
-      const double kx = I.gmode ? coef_k(dp, x) : 1.0;
+      const double kx = I.gmode ? coef_k(dp, x) : kmt;
       double mminus[3], mplus[3] = {0, 0, 0};
       for (int r = 0; r < 3; ++r)
         mminus[r] = kx * (Ji[r][0] * nh[0] + Ji[r][1] * nh[1] + Ji[r][2] * nh[2]);
