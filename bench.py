@@ -65,6 +65,27 @@ def measured_traffic(kernel, alg_bytes):
     return None if v is None else float(v)
 
 
+def summarize_trace(stats_csv, out_md, command):
+    """Top kernels of a rocprofv3 kernel-stats table as markdown (name, calls, total, mean)."""
+    import csv
+
+    with open(stats_csv) as fh:
+        rows = list(csv.DictReader(fh))
+    total = sum(float(r["TotalDurationNs"]) for r in rows)
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = ["# rocprofv3 kernel trace", "", "Command (from the repository root, on one MI355X):", "",
+             "    " + command, "", "Total kernel time: %.1f ms." % (total / 1e6), "",
+             "| kernel | calls | total ms | share | mean us | min us | max us |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:20]:
+        name = r["Name"].split("(hpdg::")[0].replace("void hpdg::(anonymous namespace)::", "").replace("|", "/")
+        lines.append("| `%s` | %s | %.2f | %.1f%% | %.1f | %.1f | %.1f |" % (
+            name[:90], r["Calls"], float(r["TotalDurationNs"]) / 1e6, 100 * float(r["TotalDurationNs"]) / total,
+            float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    with open(out_md, "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, kernels, out):
     """Mean FETCH_SIZE + WRITE_SIZE per dispatch of each kernel (rocprofv3 --pmc CSVs, KiB),
     each scaled by the same counter on a 1 GiB device copy, written as a text summary."""
@@ -128,7 +149,7 @@ def make_workload(args, meshgen, hp):
         w["mesh"] = meshgen.puncture_mesh(punctures=nl["params"][1:].reshape(-1, 5)[:, :3])
         w["prob"] = None
         w["upload"] = dict(mass_term=True, build_f32=True)
-        w["smoother"] = dict(n_cheb=args.n_cheb or 4, smoother=args.smoother or "point", Lambda=args.Lambda or 20.0)
+        w["smoother"] = dict(n_cheb=args.n_cheb or 16, smoother=args.smoother or "point", Lambda=args.Lambda or 400.0)
         w["desc"] = ("cube [-10,10]^3 + cube-to-sphere + compactified shell to 1e11 (13 macros), refined 5x "
                      "around 3 seeded punctures, p=6, -lap u = beta (1 + alpha u)^-7, Newton-Krylov to 1e-10")
     return w
@@ -156,7 +177,12 @@ def main():
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH", "CAL_WRITE"),
                     help="write the HBM traffic summary from rocprofv3 --pmc counter CSVs")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_STATS_CSV", "OUT_MD", "COMMAND"),
+                    help="write a markdown summary of a rocprofv3 --kernel-trace --stats table")
     args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic,
                           kernels=["apply_kernel<double, 6, 7, true>", "block_kernel<double, true>",

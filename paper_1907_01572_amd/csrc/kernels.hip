@@ -114,6 +114,7 @@ __global__ void __launch_bounds__(kBS) block_cheb_bf16_kernel(LevelView<float> L
   const uint16_t* B = Binv + boff[e];
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     float z = 0;
+#pragma unroll 8
     for (int j = 0; j < N; ++j) z += bf2f(B[(long long)j * N + i]) * r[j];
     const float pn = first ? alpha * z : alpha * z + beta * p[I.off + i];
     p[I.off + i] = pn;
@@ -138,6 +139,8 @@ __global__ void __launch_bounds__(kBS) block_kernel(LevelView<T> L, const long l
   const T* B = Binv + boff[e];
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     T z = 0;
+    // unrolled so that several independent block loads are in flight per thread
+#pragma unroll 8
     for (int j = 0; j < N; ++j) z += B[(long long)j * N + i] * r[j];  // symmetric: row j, col i
     if (CHEB) {
       const T pn = first ? alpha * z : alpha * z + beta * p[I.off + i];
