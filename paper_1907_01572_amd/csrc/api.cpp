@@ -65,6 +65,7 @@ struct DevLevel {
   // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
   T* mcoef = nullptr;
   T* diag = nullptr;
+  T* trace = nullptr;  // face traces (written before each apply)
   double* nl_alpha = nullptr;  // alpha and w det J beta at the GL points (FP64 levels only)
   double* nl_wbeta = nullptr;
 };
@@ -220,6 +221,7 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.vgeo = d.vgeo;
   v.mgeo = d.mgeo;
   v.mcoef = mass_on ? d.mcoef : nullptr;
+  v.trace = d.trace;
   v.tab = table<T>();
   v.tv = tabview();
   v.n_elem = (long long)h.cells.size();
@@ -291,6 +293,7 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
     launch_fill<T>(h.nmq, T(0), d.mcoef, s);
     d.diag = M->upload<T>(h.diag, s);
   }
+  d.trace = M->alloc<T>(size_t(h.ntrace));
   const size_t n = size_t(h.ndof);
   d.f = M->alloc<T>(n);
   d.v = M->alloc<T>(n);
@@ -356,6 +359,7 @@ void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
   const int* be = M->lev<T>(l).belems;
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   timed(M, HPDG_TIMING_APPLY, l, prec, M->timing ? apply_bytes(M, l, sizeof(T)) : 0.0, s, [&] {
+    launch_traces<T>(V, x, s);
     for (size_t b = 0; b < h.bucket_n.size(); ++b)
       launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
                              h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
@@ -768,6 +772,7 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
     b += (h.fmlist.size() + h.bucket_elems.size()) * 4 * (M->has_f32 ? 2 : 1);
     b += (h.vgeo.size() + h.mgeo.size()) * prec;
     b += size_t(h.ndof) * prec * 5;  // dinv, f, v, t, p
+    b += size_t(h.ntrace) * prec;      // face traces
     b += size_t(h.nmq) * prec + (h.nmq ? size_t(h.ndof) * prec : 0);
     b += (h.tinfo.size() * sizeof(TransferInfo) + (h.cstart.size() + h.clist.size()) * 4) * (M->has_f32 ? 2 : 1);
     if (scaling == HPDG_SMOOTH_BLOCK && l + 1 < M->nlevels()) {
@@ -1021,7 +1026,7 @@ size_t estimate_from_desc(const hpdg_mesh_desc& d, const hpdg_disc_params& disc,
     pmin = std::min(pmin, d.elem_p[e]);
     const bool affine = d.macro_kind[d.elem_macro[e]] == HPDG_MAP_AFFINE && disc.coef_kind == HPDG_COEF_CONSTANT;
     dof += n * n * n;
-    geo += (affine ? 6.0 : 6.0 * q * q * q) + 3.0 * 8.0 * q * q + (disc.mass_term ? q * q * q : 0.0);
+    geo += (affine ? 6.0 : 6.0 * q * q * q) + 3.0 * 8.0 * q * q + (disc.mass_term ? q * q * q : 0.0) + 12.0 * n * n;
     if (scaling == HPDG_SMOOTH_BLOCK) blocks += n * n * n * n * n * n;
   }
   const double prec = disc.build_f32 ? 12.0 : 8.0;

@@ -49,7 +49,7 @@ __device__ inline Map mortar_map(const MortarInfo& M, int side) {
 struct Task {
   int valid, f, side, interior, other, qm, gmode, no, of;
   Map me, ot;
-  long long ooff, geo;
+  long long ooff, geo;  // neighbour trace offset, mortar metric offset
 };
 
 // volume index of the node with index k along axis d and (i, j) along the face axes t0 < t1
@@ -131,9 +131,10 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
     tk.ot = mortar_map(M, 1 - tk.side);
     tk.of = tk.side ? M.fm : M.fp;
     if (tk.other) {
+      // the neighbour's traces on the face it shares (values, then normal derivatives)
       const ElemInfo& O = L.einfo[tk.side ? M.em : M.ep];
       tk.no = O.n;
-      tk.ooff = O.off;
+      tk.ooff = O.toff + 2LL * tk.of * O.n * O.n;
     }
   }
   return tk;
@@ -164,31 +165,30 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
   for (int r = 0; r < rounds; ++r) {
     for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
     __syncthreads();
-    // P0: neighbour coefficients
-    for (int g = threadIdx.x; g < kFaces * N3; g += blockDim.x) {
-      const int t = g / N3, i = g % N3;
-      if (tasks[t].other) RA[t * raS + i] = x[tasks[t].ooff + i];
-    }
-    __syncthreads();
-    // P1: traces (values, reference normal derivative) of the own face and the neighbour's
+    // P1: traces (values, reference normal derivative) of the own face from the element's
+    // coefficients; the neighbour's from its stored traces
     for (int g = threadIdx.x; g < kFaces * 2 * N2; g += blockDim.x) {
       const int t = g / (2 * N2), li = g % (2 * N2);
       const Task& tk = tasks[t];
       if (!tk.valid) continue;
-      const bool own = li < N2;
-      if (!own && !tk.other) continue;
-      const int l2 = own ? li : li - N2;
-      const int f = own ? tk.f : tk.of, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      if (li >= N2) {
+        if (!tk.other) continue;
+        const int l2 = li - N2;
+        T* tr = RB + t * rbS + 2 * NM * NM;
+        tr[l2] = L.trace[tk.ooff + l2];
+        tr[NM * NM + l2] = L.trace[tk.ooff + N2 + l2];
+        continue;
+      }
+      const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
       const int kf = (f & 1) ? N - 1 : 0;
-      const T* u = own ? su : RA + t * raS;
       const T* df = dfo + (f & 1) * NM;
-      const int i = l2 % N, j = l2 / N;
-      T* tr = RB + t * rbS + (own ? 0 : 2 * NM * NM);
-      tr[l2] = u[vidx(N, d, t0, t1, kf, i, j)];
+      const int i = li % N, j = li / N;
+      T* tr = RB + t * rbS;
+      tr[li] = su[vidx(N, d, t0, t1, kf, i, j)];
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < N; ++k) s += df[k] * u[vidx(N, d, t0, t1, k, i, j)];
-      tr[NM * NM + l2] = s;
+      for (int k = 0; k < N; ++k) s += df[k] * su[vidx(N, d, t0, t1, k, i, j)];
+      tr[NM * NM + li] = s;
     }
     __syncthreads();
     // P2: first interpolation pass (along face axis a): u, du/da, du/dn
@@ -531,12 +531,8 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   for (int r = 0; r < rounds; ++r) {
     for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
     __syncthreads();
-    // P0: neighbour coefficients
-#define C0(t) (tasks[t].valid && tasks[t].other ? tasks[t].no * tasks[t].no * tasks[t].no : 0)
-    for_items(HPDG_COUNTS(C0), [&](int t, int i) { RA[t * raS + i] = x[tasks[t].ooff + i]; });
-#undef C0
-    __syncthreads();
-    // P1: traces (values and reference normal derivative) of the own face and the neighbour's
+    // P1: traces (values and reference normal derivative) of the own face; the neighbour's
+    // from its stored traces
 #define C1(t) (tasks[t].valid ? n2 + (tasks[t].other ? tasks[t].no * tasks[t].no : 0) : 0)
     for_items(HPDG_COUNTS(C1), [&](int t, int li) {
       const Task& tk = tasks[t];
@@ -552,15 +548,9 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
         for (int k = 0; k < n; ++k) s += df[k] * su[vidx(n, d, t0, t1, k, i, j)];
         tr[NM * NM + li] = s;
       } else {
-        const int lo = li - n2, no = tk.no, f = tk.of, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-        const int kf = (f & 1) ? no - 1 : 0;
-        const T* df = L.tab + L.tv.dface_off[no] + ((f & 1) ? no : 0);
-        const T* so = RA + t * raS;
-        const int i = lo % no, j = lo / no;
-        tr[2 * NM * NM + lo] = so[vidx(no, d, t0, t1, kf, i, j)];
-        T s = 0;
-        for (int k = 0; k < no; ++k) s += df[k] * so[vidx(no, d, t0, t1, k, i, j)];
-        tr[3 * NM * NM + lo] = s;
+        const int lo = li - n2, no2 = tk.no * tk.no;
+        tr[2 * NM * NM + lo] = L.trace[tk.ooff + lo];
+        tr[3 * NM * NM + lo] = L.trace[tk.ooff + no2 + lo];
       }
     });
     __syncthreads();
@@ -744,6 +734,30 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   }
 }
 
+template <typename T>
+__global__ void __launch_bounds__(kThreads) trace_kernel(LevelView<T> L, const T* __restrict__ x) {
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int n = I.n, n2 = n * n;
+  const T* u = x + I.off;
+  const T* dfg = L.tab + L.tv.dface_off[n];  // l_k'(-1), then l_k'(+1)
+  for (int g = threadIdx.x; g < 12 * n2; g += blockDim.x) {
+    const int f = g / (2 * n2), r = g % (2 * n2), li = r % n2;
+    const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+    const int i = li % n, j = li / n;
+    T v;
+    if (r < n2) {
+      v = u[vidx(n, d, t0, t1, (f & 1) ? n - 1 : 0, i, j)];
+    } else {
+      const T* df = dfg + ((f & 1) ? n : 0);
+      v = 0;
+      for (int k = 0; k < n; ++k) v += df[k] * u[vidx(n, d, t0, t1, k, i, j)];
+    }
+    L.trace[I.toff + g] = v;
+  }
+}
+
 template <typename T, int N, int Q, bool UNI>
 void launch_fixed(const LevelView<T>& L, const int* elems, long long count, const T* x, T* y, size_t lds,
                   hipStream_t s) {
@@ -756,8 +770,15 @@ void launch_fixed(const LevelView<T>& L, const int* elems, long long count, cons
 size_t apply_lds_bytes(int NM, int QM, int QMM, size_t scalar) { return Layout(NM, QM, QMM).bytes(scalar); }
 
 template <typename T>
+void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s) {
+  if (L.n_elem == 0 || L.self_only) return;
+  hipLaunchKernelGGL((trace_kernel<T>), dim3(unsigned(L.n_elem)), dim3(kThreads), 0, s, L, x);
+}
+
+template <typename T>
 void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
   if (L.n_elem == 0) return;
+  launch_traces<T>(L, x, s);
   const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T));
   hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
                      (const int*)nullptr, L.n_elem, x, y);
@@ -780,6 +801,8 @@ void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const
                      count, x, y);
 }
 
+template void launch_traces<double>(const LevelView<double>&, const double*, hipStream_t);
+template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t);
 template void launch_apply<double>(const LevelView<double>&, const double*, double*, hipStream_t);
 template void launch_apply<float>(const LevelView<float>&, const float*, float*, hipStream_t);
 template void launch_apply_bucket<double>(const LevelView<double>&, int, int, int, const int*, long long,

@@ -23,6 +23,7 @@ struct LevelView {
   const T* vgeo;
   const T* mgeo;
   const T* mcoef;  // w det J c at the GL points of elements with a mass term (null: no mass term)
+  T* trace;        // face traces of every element (written by launch_traces before an apply)
   const T* tab;
   TabView tv;
   long long n_elem;
@@ -43,6 +44,10 @@ struct TransferView {
 
 size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar);
 
+// face traces of every element of the level: for each face, the values at its n^2 LGL nodes
+// and the reference normal derivative there (read by the neighbours' face terms)
+template <typename T>
+void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s);
 template <typename T>
 void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
 // apply restricted to the elements elems[0..count) that share degree n - 1 and q GL points;

@@ -61,6 +61,7 @@ struct ElemInfo {
   long long off;     // dof offset
   long long vgeo;    // offset of the volume metric (in scalars)
   long long mq;      // offset of the mass coefficient w det J c at the GL points (q^3 values)
+  long long toff;    // offset of the element's face traces (6 faces x [values n^2, normal derivatives n^2])
   int n, q;          // LGL nodes and GL points per axis
   int vmode;         // 0: constant metric (affine, 6 values), 1: per GL point (6 q^3 values)
   int mass;          // 1: the level carries a mass term c u v

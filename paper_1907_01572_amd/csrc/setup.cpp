@@ -155,6 +155,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
   L.einfo.assign(E, ElemInfo{});
   L.vgeo.clear();
   L.nmq = 0;
+  L.ntrace = 0;
   L.nmax = L.qmax = L.qmmax = 0;
   long long off = 0;
   double eta[kMaxQ + 1], wq[kMaxQ + 1];
@@ -190,6 +191,8 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     I.mass = dp.mass_term ? 1 : 0;
     I.mq = L.nmq;
     if (I.mass) L.nmq += (long long)I.q * I.q * I.q;
+    I.toff = L.ntrace;
+    L.ntrace += 12LL * I.n * I.n;
     I.vgeo = (long long)L.vgeo.size();
     L.nmax = std::max(L.nmax, I.n);
     L.qmax = std::max(L.qmax, I.q);

@@ -42,6 +42,7 @@ struct LevelHost {
   std::vector<double> diag;
   long long ndof = 0;
   long long nmq = 0;  // mass-coefficient scalars (sum of q^3 over elements with a mass term)
+  long long ntrace = 0;  // face-trace scalars (12 n^2 per element)
   int nmax = 0, qmax = 0, qmmax = 0;
   // elements grouped by (n, q): kernels are specialised per group
   std::vector<int> bucket_n, bucket_q;
