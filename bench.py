@@ -430,6 +430,9 @@ def run_serving(args, meshgen, hp):
     arrivals = np.cumsum(np.random.default_rng(1).exponential(1.0 / rate, len(reqs)))
     f64 = run(hp.PREC_F64, args.max_active, arrivals)
     mixed = run(hp.PREC_MIXED, args.max_active, arrivals)
+    # saturated: every request queued at once, max_active in flight (throughput of the server)
+    sat64 = run(hp.PREC_F64, args.max_active, [0.0] * len(reqs))
+    satmx = run(hp.PREC_MIXED, args.max_active, [0.0] * len(reqs))
     dofs = [r["dof"] for r in reqs]
     out = {
         "metric": METRIC, "value": round(f64["solves_per_s"], 4), "unit": "solves/s", "n_gpus": 1,
@@ -440,6 +443,7 @@ def run_serving(args, meshgen, hp):
                                "p 2..7, 8-Gaussian sources, to 1e-10" % (len(reqs), rate, np.mean(dofs)),
                    "name": "serving", "max_active": args.max_active, "distinct_meshes": len({r["key"] for r in reqs})},
         "sequential_f64": seq, "served_f64": f64, "served_mixed": mixed,
+        "saturated_f64": sat64, "saturated_mixed": satmx,
         "p50_ms": f64["p50_ms"], "p99_ms": f64["p99_ms"],
     }
     print(json.dumps(out))

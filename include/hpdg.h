@@ -326,7 +326,8 @@ int hpdg_server_poll(hpdg_server* server, uint64_t ticket, hpdg_request_status* 
 /* Wait until the request is DONE or FAILED, or timeout_ms passes (< 0: no limit; the
  * status is returned either way). */
 int hpdg_server_wait(hpdg_server* server, uint64_t ticket, int64_t timeout_ms, hpdg_request_status* status);
-/* Stop taking requests, finish those in flight, mark the queued ones FAILED, free. */
+/* Stop taking requests, finish those in flight, mark the queued ones FAILED, free.  No other
+ * thread may be inside a call on this server (e.g. hpdg_server_wait) when it is destroyed. */
 int hpdg_server_destroy(hpdg_server* server);
 
 /* Kernel timing for measurement.  While enabled (every = k > 0), every k-th operator

@@ -336,9 +336,23 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
     }
   }
+  // One degree and one volume rule on the level: flat constant-coefficient mortars, whose
+  // n-point rule is already exact, take the volume rule's q >= n points too (the same integrals
+  // up to rounding), so that a level mixing flat and curved faces (or a mass term) still runs
+  // the uniform fast path.
   L.uniform = L.bucket_n.size() == 1 ? 1 : 0;
-  for (const MortarInfo& I : L.minfo)
-    if (I.q != 0 && !L.bucket_q.empty() && I.q != L.bucket_q[0]) L.uniform = 0;
+  if (L.uniform) {
+    const int q0 = L.bucket_q[0];
+    for (MortarInfo& I : L.minfo) {
+      if (I.q == 0 || I.q == q0) continue;
+      if (I.gmode == 0 && I.q == L.bucket_n[0] && I.q < q0) {
+        I.q = q0;
+        L.qmmax = std::max(L.qmmax, q0);
+      } else {
+        L.uniform = 0;
+      }
+    }
+  }
   L.fmlist.clear();
   for (size_t e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f) {
