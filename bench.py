@@ -185,8 +185,8 @@ def main():
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic,
-                          kernels=["apply_kernel<double, 6, 7, true>", "block_kernel<double, true>",
-                                   "apply_kernel<float, 6, 7, true>", "block_kernel<float, true>"],
+                          kernels=["apply_kernel<double, 6, 7, true>", "block_sym_kernel<double, double, true>",
+                                   "apply_kernel<float, 6, 7, true>", "block_sym_kernel<float, float, true>"],
                           out=os.path.join(ROOT, TRAFFIC_FILE))
         return
     if args.gpus != 1:
@@ -290,15 +290,16 @@ def main():
         return (sum(e[0] for e in entries), sum(e[1] for e in entries), sum(e[2] for e in entries))
 
     kernels = {}
-    names = ({"apply": "apply_kernel<double, 6, 7, true>", "block": "block_kernel<double, true>"}
+    names = ({"apply": "apply_kernel<double, 6, 7, true>", "block": "block_sym_kernel<double, double, true>"}
              if args.workload == "shell" else
-             {"apply": "apply_kernel<double, *> (all buckets)", "block": "block_kernel<double, true>"})
+             {"apply": "apply_kernel<double, *> (all buckets)", "block": "block_sym_kernel<double, double, true>"})
     for kind in ("apply", "block"):
         ms, n, b = totals(t64[kind])
         if n:
             kernels[kind] = {"kernel": names[kind], "total_ms": ms, "launches": n, "avg_launch_us": 1e3 * ms / n,
                              "alg_bytes_per_launch": b / n, "gbs": b / (ms * 1e-3) / 1e9,
-                             "per_level_launches": [e[1] for e in t64[kind]]}
+                             "per_level_launches": [e[1] for e in t64[kind]],
+                             "per_level_avg_us": [round(1e3 * e[0] / e[1], 2) if e[1] else None for e in t64[kind]]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     K = kernels[dom]
     ms0, n0, b0 = t64["apply"][0]

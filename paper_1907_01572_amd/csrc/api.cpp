@@ -58,9 +58,10 @@ struct DevLevel {
   int* cstart = nullptr;
   int* clist = nullptr;
   T *f = nullptr, *v = nullptr, *t = nullptr, *p = nullptr;
-  long long* boff = nullptr;  // element-block Jacobi: offsets of the inverse blocks
-  T* binv = nullptr;
-  uint16_t* binv16 = nullptr;  // bf16 copy of the inverse blocks (FP32 levels)
+  long long* poff = nullptr;  // element-block Jacobi: offsets of the packed inverse blocks
+  T* binv = nullptr;           // packed lower triangles of the inverse blocks
+  long long* boff16 = nullptr;  // offsets of the full bf16 blocks (FP32 levels)
+  uint16_t* binv16 = nullptr;   // full bf16 copies of the inverse blocks (FP32 levels)
   int* belems = nullptr;      // element ids grouped by (n, q)
   // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
   T* mcoef = nullptr;
@@ -81,6 +82,7 @@ struct hpdg_mesh {
   bool has_f32 = false;
   // device
   std::vector<void*> allocs;
+  std::vector<size_t> alloc_bytes;
   size_t bytes = 0;
   int* tab_off = nullptr;
   int *dg_off = nullptr, *w_off = nullptr, *dface_off = nullptr;
@@ -121,7 +123,8 @@ struct hpdg_mesh {
     double ms = 0, bytes = 0;
     long long calls = 0;
   };
-  std::vector<long long> block_scalars = std::vector<long long>(32, 0);  // inverse-block scalars per level
+  std::vector<long long> block_scalars = std::vector<long long>(32, 0);  // packed inverse-block scalars per level
+  std::vector<long long> block_full_scalars = std::vector<long long>(32, 0);  // full-block scalars per level
   int block_retries = 0;  // block factorisations repeated after a failed attempt
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
@@ -143,8 +146,23 @@ struct hpdg_mesh {
       throw Error(HPDG_ERR_OOM, "hipMalloc failed");
     }
     allocs.push_back(ptr);
+    alloc_bytes.push_back(b);
     bytes += b;
     return static_cast<T*>(ptr);
+  }
+  // free one allocation made by alloc() before the mesh is destroyed (setup temporaries)
+  void release(void* ptr) {
+    for (size_t i = 0; i < allocs.size(); ++i) {
+      if (allocs[i] != ptr) continue;
+      (void)hipFree(ptr);
+      const size_t b = alloc_bytes[i];
+      allocs.erase(allocs.begin() + i);
+      alloc_bytes.erase(alloc_bytes.begin() + i);
+      bytes -= b;
+      std::lock_guard<std::mutex> lock(ctx->mu);
+      ctx->used -= std::min(ctx->used, b);
+      return;
+    }
   }
   template <typename T, typename S>
   T* upload(const std::vector<S>& v, hipStream_t s) {
@@ -393,16 +411,19 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
     if (block) {
       // inverse blocks, b, Ax (when given), p (read after the first step, written), x (read, written)
       const double vec = double(n) * (1 + (Ax ? 1 : 0) + (k == 1 ? 1 : 2) + 2);
-      const double bytes = M->timing ? double(sizeof(T)) * (double(M->block_scalars[l]) + vec) : 0.0;
+      const bool bf16 = std::is_same<T, float>::value && M->bf16_blocks && d.binv16;
+      const double stored = bf16 ? 2.0 * double(M->block_full_scalars[l]) : double(sizeof(T)) * double(M->block_scalars[l]);
+      const double bytes = M->timing ? stored + double(sizeof(T)) * vec : 0.0;
       timed(M, HPDG_TIMING_BLOCK, l, sizeof(T) == 4 ? HPDG_F32 : HPDG_F64, bytes, s, [&] {
         if constexpr (std::is_same<T, float>::value) {
-          if (M->bf16_blocks && d.binv16) {
-            launch_block_cheb_bf16(M->view<float>(l), d.boff, d.binv16, b, Ax, d.p, x, float(alpha), float(beta),
+          if (bf16) {
+            launch_block_cheb_bf16(M->view<float>(l), d.boff16, d.binv16, b, Ax, d.p, x, float(alpha), float(beta),
                                    k == 1 ? 1 : 0, s);
             return;
           }
         }
-        launch_block_cheb<T>(M->view<T>(l), d.boff, d.binv, b, Ax, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
+        launch_block_cheb<T, T>(M->view<T>(l), d.poff, d.binv, b, Ax, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0,
+                                s);
       });
     } else
       launch_cheb_update<T>(n, b, Ax, dinv, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0, s);
@@ -468,7 +489,7 @@ double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
     if (M->sp.scaling == HPDG_SMOOTH_POINT)
       launch_scale<double>(n, d.dinv, r, z, s);
     else if (M->sp.scaling == HPDG_SMOOTH_BLOCK)
-      launch_block_apply<double>(M->view<double>(l), d.boff, d.binv, r, z, s);
+      launch_block_apply<double, double>(M->view<double>(l), d.poff, d.binv, r, z, s);
     else
       launch_copy<double>(n, r, z, s);
   };
@@ -501,23 +522,28 @@ double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
   return bound;
 }
 
-void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff, double* B,
-                   hipStream_t s);
+void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
+                   const long long* dboff, double* B, hipStream_t s);
 
 // element-block Jacobi: A_ee of every element of level l (column j of all blocks from one
-// apply with neighbours taken as zero), then their inverses by batched Cholesky (rocSOLVER)
+// apply with neighbours taken as zero), their inverses by batched Cholesky (rocSOLVER), and
+// the lower triangles of the inverses packed (FP64, and FP32 for FP32 levels; the bf16 copies
+// for FP32 levels are full blocks, read row per thread). The full FP64 blocks exist during
+// setup only.
 void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
   DevLevel<double>& d = M->lev<double>(l);
   if (d.binv) return;
   const LevelHost& h = M->H[l];
   const size_t E = h.cells.size();
-  std::vector<long long> boff(E + 1, 0);
+  std::vector<long long> boff(E + 1, 0), poff(E + 1, 0);
   for (size_t e = 0; e < E; ++e) {
     const long long N = (long long)h.einfo[e].n * h.einfo[e].n * h.einfo[e].n;
     boff[e + 1] = boff[e] + N * N;
+    poff[e + 1] = poff[e] + N * (N + 1) / 2;
   }
-  M->block_scalars[l] = boff[E];
-  d.boff = M->upload_raw(boff, s);
+  M->block_scalars[l] = poff[E];
+  M->block_full_scalars[l] = boff[E];
+  long long* dboff = M->upload_raw(boff, s);
   double* B = M->alloc<double>(size_t(boff[E]));
   LevelView<double> V = M->view<double>(l);
   V.self_only = 1;
@@ -525,30 +551,34 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
   // failure that does not repeat is not a property of the operator); a repeated one is an error.
   for (int attempt = 0;; ++attempt) {
     try {
-      factor_blocks(M, l, V, boff, B, s);
+      factor_blocks(M, l, V, boff, dboff, B, s);
       break;
     } catch (const Error& err) {
       if (attempt >= 1 || err.code != HPDG_ERR_BREAKDOWN) throw;
       M->block_retries += 1;
     }
   }
-  launch_symmetrize_blocks<double>(V, d.boff, B, s);
-  d.binv = B;
+  d.poff = M->upload_raw(poff, s);
+  d.binv = M->alloc<double>(size_t(poff[E]));
+  launch_pack_blocks<double>(V, dboff, B, d.poff, d.binv, s);
   if (M->has_f32) {
     DevLevel<float>& d32 = M->lev<float>(l);
-    d32.boff = d.boff;
-    d32.binv = M->alloc<float>(size_t(boff[E]));
-    launch_blocks_d2f(V, d.boff, B, d32.binv, s);
+    d32.poff = d.poff;
+    d32.binv = M->alloc<float>(size_t(poff[E]));
+    launch_pack_blocks<float>(V, dboff, B, d.poff, d32.binv, s);
+    d32.boff16 = dboff;
     d32.binv16 = M->alloc<uint16_t>(size_t(boff[E]));
-    launch_blocks_f2bf(M->view<float>(l), d.boff, d32.binv, d32.binv16, s);
+    launch_blocks_bf16_full(V, dboff, B, d32.binv16, s);
   }
   HIPCHK(hipStreamSynchronize(s));
+  M->release(B);
+  if (!M->has_f32) M->release(dboff);
 }
 
 // gather the element blocks of level l (column j of every block from one self-only apply),
 // check them, and replace them by their inverses (batched Cholesky + inverse, rocSOLVER)
-void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff, double* B,
-                   hipStream_t s) {
+void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
+                   const long long* dboff, double* B, hipStream_t s) {
   DevLevel<double>& d = M->lev<double>(l);
   const LevelHost& h = M->H[l];
   const size_t E = h.cells.size();
@@ -557,13 +587,13 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
   for (int j = 0; j < nmax3; ++j) {
     launch_set_unit<double>(V, j, 1.0, d.f, s);
     launch_apply<double>(V, d.f, d.t, s);
-    launch_gather_column<double>(V, j, d.t, d.boff, B, s);
+    launch_gather_column<double>(V, j, d.t, dboff, B, s);
     launch_set_unit<double>(V, j, 0.0, d.f, s);
   }
   {
     int* bad = nullptr;
     HIPCHK(hipMalloc(&bad, E * sizeof(int)));
-    launch_check_blocks(V, d.boff, B, d.dinv, bad, s);
+    launch_check_blocks(V, dboff, B, d.dinv, bad, s);
     std::vector<int> hb(E);
     HIPCHK(hipMemcpyAsync(hb.data(), bad, E * sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
@@ -765,6 +795,7 @@ void upload_mesh_device(hpdg_mesh* M, hipStream_t s) {
 size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
   const size_t prec = M->has_f32 ? 12 : 8;  // bytes per scalar over the FP64 (+ FP32) copies
   size_t b = M->tab.data.size() * prec + M->tab.off.size() * 4 + 4096;
+  size_t full_max = 0;  // the full FP64 blocks of one level, alive while that level is set up
   for (int l = 0; l < M->nlevels(); ++l) {
     const LevelHost& h = M->H[l];
     b += h.einfo.size() * sizeof(ElemInfo) * (M->has_f32 ? 2 : 1);
@@ -776,13 +807,18 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
     b += size_t(h.nmq) * prec + (h.nmq ? size_t(h.ndof) * prec : 0);
     b += (h.tinfo.size() * sizeof(TransferInfo) + (h.cstart.size() + h.clist.size()) * 4) * (M->has_f32 ? 2 : 1);
     if (scaling == HPDG_SMOOTH_BLOCK && l + 1 < M->nlevels()) {
-      size_t blk = 0;
-      for (const ElemInfo& I : h.einfo) blk += size_t(I.n) * I.n * I.n * I.n * I.n * I.n;
-      b += blk * prec + h.einfo.size() * 8;
+      size_t packed = 0, full = 0;
+      for (const ElemInfo& I : h.einfo) {
+        const size_t N = size_t(I.n) * I.n * I.n;
+        packed += N * (N + 1) / 2;
+        full += N * N;
+      }
+      b += packed * (M->has_f32 ? 12 : 8) + (M->has_f32 ? full * 2 : 0) + h.einfo.size() * 8;  // FP64 (+ FP32, bf16)
+      full_max = std::max(full_max, full * 8 + h.einfo.size() * 8);
     }
   }
   const size_t n0 = size_t(M->H[0].ndof), nc = size_t(M->H.back().ndof);
-  b += n0 * 8 * 5 + 3 * kRedBlocks * 8 + 128 + nc * nc * prec;
+  b += full_max + n0 * 8 * 5 + 3 * kRedBlocks * 8 + 128 + nc * nc * prec;
   return b;
 }
 
@@ -1027,13 +1063,16 @@ size_t estimate_from_desc(const hpdg_mesh_desc& d, const hpdg_disc_params& disc,
     const bool affine = d.macro_kind[d.elem_macro[e]] == HPDG_MAP_AFFINE && disc.coef_kind == HPDG_COEF_CONSTANT;
     dof += n * n * n;
     geo += (affine ? 6.0 : 6.0 * q * q * q) + 3.0 * 8.0 * q * q + (disc.mass_term ? q * q * q : 0.0) + 12.0 * n * n;
-    if (scaling == HPDG_SMOOTH_BLOCK) blocks += n * n * n * n * n * n;
+    if (scaling == HPDG_SMOOTH_BLOCK) blocks += n * n * n * (n * n * n + 1.0) / 2.0;
   }
   const double prec = disc.build_f32 ? 12.0 : 8.0;
+  // packed inverse blocks: FP64, plus FP32 and full bf16 copies (as many bytes as packed FP32);
+  // the full FP64 blocks of the finest level exist while it is set up (twice the packed count)
+  const double bprec = disc.build_f32 ? 16.0 : 8.0;
   const double levels = 8.0 / 7.0;  // coarser levels: a geometric series in the element count
   const double coarse = double(d.n_macro) * std::pow(pmin + 1.0, 3);
-  const double b = levels * (prec * (6.0 * dof + geo + blocks) + 250.0 * d.n_elem) + 8.0 * 5.0 * dof +
-                   prec * coarse * coarse + (1 << 20);
+  const double b = levels * (prec * (6.0 * dof + geo) + bprec * blocks + 250.0 * d.n_elem) + 8.0 * 5.0 * dof +
+                   16.0 * blocks + prec * coarse * coarse + (1 << 20);
   return size_t(1.25 * b);
 }
 

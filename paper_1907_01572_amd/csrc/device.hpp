@@ -81,36 +81,38 @@ void launch_convert_f2d(long long n, const float* x, double* y, hipStream_t s);
 template <typename T>
 void launch_dense_matvec(int n, const T* A, const T* x, T* y, hipStream_t s);
 
-// element-block Jacobi: blocks of element e stored row-major at boff[e], size (n_e^3)^2
-// column j of every block at once: x holds e_j in every element (n^3 > j)
+// element-block Jacobi. Setup: the FP64 blocks of element e, column-major at boff[e], size
+// (n_e^3)^2; column j of every block at once from an apply to e_j in every element (n^3 > j)
 template <typename T>
 void launch_set_unit(const LevelView<T>& L, int j, T value, T* x, hipStream_t s);
 template <typename T>
 void launch_gather_column(const LevelView<T>& L, int j, const T* y, const long long* boff, T* B,
                           hipStream_t s);
-// copy the lower triangle (column-major) of every block to its upper triangle
-template <typename T>
-void launch_symmetrize_blocks(const LevelView<T>& L, const long long* boff, T* B, hipStream_t s);
-void launch_blocks_d2f(const LevelView<double>& L, const long long* boff, const double* B, float* Bf,
-                       hipStream_t s);
 // bad[e] = 1 + first column of element e's gathered block that is not symmetric or whose
 // diagonal differs from 1 / dinv; 0 when consistent
 void launch_check_blocks(const LevelView<double>& L, const long long* boff, const double* B, const double* dinv,
                          int* bad, hipStream_t s);
-// bf16 copies of the FP32 inverse blocks (round to nearest even) and the Chebyshev step that
-// reads them (FP32 arithmetic)
-void launch_blocks_f2bf(const LevelView<float>& L, const long long* boff, const float* B, uint16_t* Bh,
-                        hipStream_t s);
+// the lower triangles of the inverted blocks (column-major, B[c N + r], r >= c) packed at
+// poff[e] (N (N + 1) / 2 scalars, panels of 64 rows, see kernels.hip) in storage type S
+// (double or float)
+template <typename S>
+void launch_pack_blocks(const LevelView<double>& L, const long long* boff, const double* B, const long long* poff,
+                        S* P, hipStream_t s);
+// full bf16 copies of the inverted blocks (both triangles, column-major at boff[e]; bf16 held
+// as uint16_t, rounded to nearest even from the FP32 value) and the FP32 Chebyshev step that
+// reads them (same update as launch_block_cheb)
+void launch_blocks_bf16_full(const LevelView<double>& L, const long long* boff, const double* B, uint16_t* Bh,
+                             hipStream_t s);
 void launch_block_cheb_bf16(const LevelView<float>& L, const long long* boff, const uint16_t* Binv, const float* b,
                             const float* Ax, float* p, float* x, float alpha, float beta, int first, hipStream_t s);
-// z = Binv r per element
-template <typename T>
-void launch_block_apply(const LevelView<T>& L, const long long* boff, const T* Binv, const T* r, T* z,
+// z = Binv r per element (packed blocks, storage S, arithmetic T)
+template <typename T, typename S>
+void launch_block_apply(const LevelView<T>& L, const long long* poff, const S* P, const T* r, T* z,
                         hipStream_t s);
 // r = Binv (b - Ax) per element (Ax null: x = 0); p = alpha r + beta p (first: alpha r); x += p
-template <typename T>
-void launch_block_cheb(const LevelView<T>& L, const long long* boff, const T* Binv, const T* b,
-                       const T* Ax, T* p, T* x, T alpha, T beta, int first, hipStream_t s);
+template <typename T, typename S>
+void launch_block_cheb(const LevelView<T>& L, const long long* poff, const S* P, const T* b, const T* Ax, T* p,
+                       T* x, T alpha, T beta, int first, hipStream_t s);
 
 // deterministic reductions: out[0..k) = dots, via partials (kRedBlocks * k doubles)
 constexpr int kRedBlocks = 512;

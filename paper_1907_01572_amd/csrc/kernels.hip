@@ -33,29 +33,6 @@ __global__ void __launch_bounds__(kBS) gather_column_kernel(LevelView<T> L, int 
   for (int i = threadIdx.x; i < N; i += blockDim.x) B[boff[e] + (long long)j * N + i] = y[I.off + i];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kBS) symmetrize_kernel(LevelView<T> L, const long long* boff, T* B) {
-  const long long e = blockIdx.x;
-  if (e >= L.n_elem) return;
-  const ElemInfo I = L.einfo[e];
-  const int N = I.n * I.n * I.n;
-  T* b = B + boff[e];
-  // column-major lower triangle (row >= col) holds the result: b[c * N + r], r >= c
-  for (long long idx = threadIdx.x; idx < (long long)N * N; idx += blockDim.x) {
-    const int r = int(idx % N), c = int(idx / N);
-    if (r < c) b[c * (long long)N + r] = b[r * (long long)N + c];
-  }
-}
-
-__global__ void __launch_bounds__(kBS) blocks_d2f_kernel(LevelView<double> L, const long long* boff,
-                                                         const double* B, float* Bf) {
-  const long long e = blockIdx.x;
-  if (e >= L.n_elem) return;
-  const ElemInfo I = L.einfo[e];
-  const long long N = (long long)I.n * I.n * I.n;
-  for (long long idx = threadIdx.x; idx < N * N; idx += blockDim.x) Bf[boff[e] + idx] = float(B[boff[e] + idx]);
-}
-
 // consistency of freshly gathered element blocks before their factorisation: the diagonal must
 // equal the level's stored diagonal (computed independently on the host) and the block must be
 // symmetric; bad[e] = 1 + first offending column of element e, or 0
@@ -82,23 +59,66 @@ __global__ void __launch_bounds__(kBS) check_blocks_kernel(LevelView<double> L, 
   if (threadIdx.x == 0) bad[e] = first < N ? first + 1 : 0;
 }
 
-// bf16 storage of the FP32 inverse blocks: round to nearest even on the upper 16 bits
+// ---- packed symmetric inverse blocks ----------------------------------------------------
+// Only the lower triangle of each inverse block is stored (N (N + 1) / 2 scalars for N = n^3),
+// in panels of 64 rows: panel rows r0 = 64 P .. r0 + m - 1 (m = min(64, N - r0)) start at
+// r0 (r0 + 1) / 2 and hold first the r0 full columns of these rows (column c: m scalars in row
+// order), then the panel's diagonal tile column by column (tile column j: rows j .. m - 1).
+// A wave reading one column of a panel reads consecutive addresses.
+__device__ inline long long packed_index(int N, int r, int c) {  // r >= c
+  const int r0 = r & ~63, m = min(64, N - r0), l = r - r0;
+  const long long base = (long long)r0 * (r0 + 1) / 2;
+  if (c < r0) return base + (long long)c * m + l;
+  const int j = c - r0;
+  return base + (long long)r0 * m + (long long)j * m - (long long)j * (j - 1) / 2 + (l - j);
+}
+
+// bf16: round to nearest even on the upper 16 bits of the FP32 value
 __device__ inline uint16_t f2bf(float v) {
   const uint32_t u = __float_as_uint(v);
   return uint16_t((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
 }
 __device__ inline float bf2f(uint16_t h) { return __uint_as_float(uint32_t(h) << 16); }
 
-__global__ void __launch_bounds__(kBS) blocks_f2bf_kernel(LevelView<float> L, const long long* boff,
-                                                          const float* B, uint16_t* Bh) {
+template <typename S>
+__device__ inline S to_storage(double v) { return S(v); }
+template <typename T, typename S>
+__device__ inline T from_storage(S v) { return T(v); }
+
+// pack the FP64 inverse blocks (column-major, lower triangle valid: B[c N + r], r >= c)
+template <typename S>
+__global__ void __launch_bounds__(kBS) pack_blocks_kernel(LevelView<double> L, const long long* boff,
+                                                          const double* B, const long long* poff, S* P) {
   const long long e = blockIdx.x;
   if (e >= L.n_elem) return;
   const ElemInfo I = L.einfo[e];
-  const long long N = (long long)I.n * I.n * I.n;
-  for (long long idx = threadIdx.x; idx < N * N; idx += blockDim.x) Bh[boff[e] + idx] = f2bf(B[boff[e] + idx]);
+  const int N = I.n * I.n * I.n;
+  const double* Be = B + boff[e];
+  S* Pe = P + poff[e];
+  for (long long idx = threadIdx.x; idx < (long long)N * N; idx += blockDim.x) {
+    const int r = int(idx % N), c = int(idx / N);
+    if (r >= c) Pe[packed_index(N, r, c)] = to_storage<S>(Be[idx]);
+  }
 }
 
-// Chebyshev step with bf16 inverse blocks: operands widened to FP32, FP32 accumulation
+// bf16 copies of the symmetric inverse blocks, full (column-major, both triangles): the FP32
+// V-cycle's bf16 mode reads these with the row-per-thread kernel below
+__global__ void __launch_bounds__(kBS) blocks_bf16_full_kernel(LevelView<double> L, const long long* boff,
+                                                               const double* B, uint16_t* Bh) {
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int N = I.n * I.n * I.n;
+  const double* Be = B + boff[e];
+  for (long long idx = threadIdx.x; idx < (long long)N * N; idx += blockDim.x) {
+    const int r = int(idx % N), c = int(idx / N);
+    const double v = r >= c ? Be[idx] : Be[(long long)r * N + c];  // lower triangle valid
+    Bh[boff[e] + idx] = f2bf(float(v));
+  }
+}
+
+// Chebyshev step with the full bf16 blocks: one thread per row, operands widened to FP32, FP32
+// accumulation (the blocks are symmetric, so row i is read as column i: coalesced over i)
 __global__ void __launch_bounds__(kBS) block_cheb_bf16_kernel(LevelView<float> L, const long long* boff,
                                                               const uint16_t* Binv, const float* b, const float* Ax,
                                                               float* p, float* x, float alpha, float beta,
@@ -122,26 +142,157 @@ __global__ void __launch_bounds__(kBS) block_cheb_bf16_kernel(LevelView<float> L
   }
 }
 
-// per element: z = Binv r (block_cheb: r = b - Ax first, then the Chebyshev update)
-template <typename T, bool CHEB>
-__global__ void __launch_bounds__(kBS) block_kernel(LevelView<T> L, const long long* boff, const T* Binv,
-                                                    const T* b, const T* Ax, T* p, T* x, T alpha, T beta,
-                                                    int first) {
+// ---- the packed mat-vec: one wave per element ----
+// The lower triangle is visited in groups of G columns of one panel: first the panel's full
+// columns (c0 = 0, G, .. < r0), then its diagonal tile (tile columns j0 = 0, G, .. < m).
+constexpr int kGroup = 16;
+
+// G per-lane values w[t] (partial sums of columns c0 + t) summed over the wave; returns, in
+// every lane, the total of column c0 + (lane % G): halving exchange steps (each lane keeps the
+// half selected by one lane bit, adding its partner's copy of that half), then all-reduce
+// steps over the lane groups of G. The order of additions is fixed.
+template <int G, typename T>
+__device__ __forceinline__ T wave_column_sums(T (&w)[G], int lane) {
+#pragma unroll
+  for (int step = 0; (G >> (step + 1)) >= 1; ++step) {  // an affine counter, so that it unrolls
+    const int s = G >> (step + 1);
+    const bool hi = (lane & s) != 0;
+#pragma unroll
+    for (int k = 0; k < s; ++k) {
+      // both halves are exchanged and the select acts on the sums: a select between two array
+      // elements would be turned into a per-lane array index (a chain of selects over w)
+      const T lo = w[k] + __shfl_xor(w[k], s, 64);
+      const T up = w[k + s] + __shfl_xor(w[k + s], s, 64);
+      w[k] = hi ? up : lo;
+    }
+  }
+  T v = w[0];
+#pragma unroll
+  for (int s = G; s < 64; s *= 2) v += __shfl_xor(v, s, 64);
+  return v;
+}
+
+struct PanelGroup {
+  int r0, m, c0;  // panel rows r0 .. r0 + m - 1; first column of the group (tile column if diag)
+  bool diag;
+};
+
+// group gi of an element's sequence (panels in order; per panel its full columns, then its
+// diagonal tile); false past the end
+template <int G>
+__device__ __forceinline__ bool group_at(int gi, int N, PanelGroup& g) {
+  for (int r0 = 0; r0 < N; r0 += 64) {
+    const int m = min(64, N - r0);
+    const int nf = r0 / G, nd = (m + G - 1) / G;
+    if (gi < nf) {
+      g = PanelGroup{r0, m, gi * G, false};
+      return true;
+    }
+    gi -= nf;
+    if (gi < nd) {
+      g = PanelGroup{r0, m, gi * G, true};
+      return true;
+    }
+    gi -= nd;
+  }
+  return false;
+}
+
+// every lane loads (lanes outside the panel or the triangle read a clamped address inside the
+// same column, and the value is discarded), so that no load sits behind a per-lane branch
+template <int G, typename S, typename T>
+__device__ __forceinline__ void load_group(const S* Pe, const PanelGroup& g, int lane, T (&v)[G]) {
+  const S* Pp = Pe + (long long)g.r0 * (g.r0 + 1) / 2;
+  const int m = g.m;
+  if (!g.diag) {
+    const S* q = Pp + (long long)g.c0 * m + min(lane, m - 1);
+#pragma unroll
+    for (int t = 0; t < G; ++t) v[t] = from_storage<T, S>(q[t * m]);
+  } else {
+    const S* Pd = Pp + (long long)g.r0 * m;
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const int j = min(g.c0 + t, m - 1);
+      const int st = j * m - j * (j - 1) / 2;
+      v[t] = from_storage<T, S>(Pd[st + min(max(lane - j, 0), m - 1 - j)]);
+    }
+  }
+}
+
+// one group: lane l accumulates row r0 + l in acc (xr = r[r0 + l]); the group's column sums go
+// to zs, index i by lane i % 64; the diagonal entry counts for its row only
+template <int G, typename T>
+__device__ __forceinline__ void group_products(const PanelGroup& g, T (&v)[G], int lane, const T* rs, T* zs,
+                                               T& acc, T xr) {
+  const int m = g.m, r0 = g.r0;
+  const bool act = lane < m;
+  T w[G];
+  if (!g.diag) {
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const T vv = act ? v[t] : T(0);
+      acc += vv * rs[g.c0 + t];
+      w[t] = vv * xr;
+    }
+    const T cs = wave_column_sums<G>(w, lane);
+    if (lane / G == ((g.c0 / G) & (64 / G - 1))) zs[g.c0 + (lane & (G - 1))] += cs;  // lane == index % 64
+  } else {
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+      const int j = g.c0 + t;
+      const bool in = act && j < m && lane >= j;
+      const T vv = in ? v[t] : T(0);
+      acc += vv * rs[r0 + min(j, m - 1)];
+      w[t] = lane > j ? vv * xr : T(0);
+    }
+    const T cs = wave_column_sums<G>(w, lane);
+    if (lane / G == g.c0 / G && (lane & (G - 1)) + g.c0 < m) zs[r0 + g.c0 + (lane & (G - 1))] += cs;
+  }
+}
+
+// per element, blockDim.x / 64 waves (group gi taken by wave gi % waves): z = Binv r with Binv
+// symmetric and packed (each stored off-diagonal entry is used twice: for its row and, via the
+// wave column sums, for its column); CHEB: r = b - Ax (Ax null: r = b), p = alpha z + beta p
+// (first: alpha z), x += p; else x = z. S is the storage type (double or float), T the
+// arithmetic type. LDS: r (broadcast reads), then per wave the accumulators of z (index i only
+// touched by lane i % 64 of that wave), summed over the waves in a fixed order at the end.
+template <typename S, typename T, bool CHEB>
+__global__ void __launch_bounds__(512) block_sym_kernel(LevelView<T> L, const long long* poff, const S* P,
+                                                        const T* b, const T* Ax, T* p, T* x, T alpha, T beta,
+                                                        int first) {
   extern __shared__ unsigned char smem_raw[];
-  T* r = reinterpret_cast<T*>(smem_raw);
   const long long e = blockIdx.x;
   if (e >= L.n_elem) return;
   const ElemInfo I = L.einfo[e];
   const int N = I.n * I.n * I.n;
+  const int waves = int(blockDim.x >> 6), lane = int(threadIdx.x & 63), wv = int(threadIdx.x >> 6);
+  T* rs = reinterpret_cast<T*>(smem_raw);
+  T* zs = rs + N + wv * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x)
-    r[i] = (CHEB && Ax) ? b[I.off + i] - Ax[I.off + i] : b[I.off + i];
+    rs[i] = (CHEB && Ax) ? b[I.off + i] - Ax[I.off + i] : b[I.off + i];
+  for (int i = lane; i < N; i += 64) zs[i] = 0;
   __syncthreads();
-  const T* B = Binv + boff[e];
+  const S* Pe = P + poff[e];
+  T acc = 0, xr = 0;
+  int cur = -1, cur_m = 0;  // panel of the row sums in acc
+  PanelGroup g;
+  for (int gi = wv; group_at<kGroup>(gi, N, g); gi += waves) {
+    if (g.r0 != cur) {
+      if (cur >= 0 && lane < cur_m) zs[cur + lane] += acc;
+      cur = g.r0;
+      cur_m = g.m;
+      acc = 0;
+      xr = lane < g.m ? rs[g.r0 + lane] : T(0);
+    }
+    T v[kGroup];
+    load_group<kGroup>(Pe, g, lane, v);
+    group_products<kGroup>(g, v, lane, rs, zs, acc, xr);
+  }
+  if (cur >= 0 && lane < cur_m) zs[cur + lane] += acc;
+  __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     T z = 0;
-    // unrolled so that several independent block loads are in flight per thread
-#pragma unroll 8
-    for (int j = 0; j < N; ++j) z += B[(long long)j * N + i] * r[j];  // symmetric: row j, col i
+    for (int w = 0; w < waves; ++w) z += rs[N + w * N + i];
     if (CHEB) {
       const T pn = first ? alpha * z : alpha * z + beta * p[I.off + i];
       p[I.off + i] = pn;
@@ -429,42 +580,61 @@ void launch_gather_column(const LevelView<T>& L, int j, const T* y, const long l
                           hipStream_t s) {
   hipLaunchKernelGGL(gather_column_kernel<T>, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, j, y, boff, B);
 }
-template <typename T>
-void launch_symmetrize_blocks(const LevelView<T>& L, const long long* boff, T* B, hipStream_t s) {
-  hipLaunchKernelGGL(symmetrize_kernel<T>, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B);
+template <typename S>
+void launch_pack_blocks(const LevelView<double>& L, const long long* boff, const double* B, const long long* poff,
+                        S* P, hipStream_t s) {
+  hipLaunchKernelGGL(pack_blocks_kernel<S>, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, poff, P);
 }
-void launch_blocks_d2f(const LevelView<double>& L, const long long* boff, const double* B, float* Bf,
-                       hipStream_t s) {
-  hipLaunchKernelGGL(blocks_d2f_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, Bf);
-}
-template <typename T>
-void launch_block_apply(const LevelView<T>& L, const long long* boff, const T* Binv, const T* r, T* z,
-                        hipStream_t s) {
-  const size_t lds = sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
-  hipLaunchKernelGGL((block_kernel<T, false>), dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv,
-                     r, (const T*)nullptr, (T*)nullptr, z, T(0), T(0), 0);
-}
-template <typename T>
-void launch_block_cheb(const LevelView<T>& L, const long long* boff, const T* Binv, const T* b,
-                       const T* Ax, T* p, T* x, T alpha, T beta, int first, hipStream_t s) {
-  const size_t lds = sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
-  hipLaunchKernelGGL((block_kernel<T, true>), dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv,
-                     b, Ax, p, x, alpha, beta, first);
-}
-
-void launch_check_blocks(const LevelView<double>& L, const long long* boff, const double* B, const double* dinv,
-                         int* bad, hipStream_t s) {
-  hipLaunchKernelGGL(check_blocks_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, dinv, bad);
-}
-void launch_blocks_f2bf(const LevelView<float>& L, const long long* boff, const float* B, uint16_t* Bh,
-                        hipStream_t s) {
-  hipLaunchKernelGGL(blocks_f2bf_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, Bh);
+template void launch_pack_blocks<double>(const LevelView<double>&, const long long*, const double*,
+                                         const long long*, double*, hipStream_t);
+template void launch_pack_blocks<float>(const LevelView<double>&, const long long*, const double*,
+                                        const long long*, float*, hipStream_t);
+void launch_blocks_bf16_full(const LevelView<double>& L, const long long* boff, const double* B, uint16_t* Bh,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(blocks_bf16_full_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, Bh);
 }
 void launch_block_cheb_bf16(const LevelView<float>& L, const long long* boff, const uint16_t* Binv, const float* b,
                             const float* Ax, float* p, float* x, float alpha, float beta, int first, hipStream_t s) {
   const size_t lds = sizeof(float) * size_t(L.nmax) * L.nmax * L.nmax;
   hipLaunchKernelGGL(block_cheb_bf16_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), lds, s, L, boff, Binv, b, Ax, p,
                      x, alpha, beta, first);
+}
+
+// waves per element: one on levels with enough elements to fill the chip, more (up to 8) on
+// small levels, where each wave's sequence of groups would otherwise set the time
+inline int block_waves(long long n_elem) {
+  int w = 1;
+  while (w < 8 && n_elem * w < 4096) w *= 2;
+  return w;
+}
+template <typename T, typename S>
+void launch_block_apply(const LevelView<T>& L, const long long* poff, const S* P, const T* r, T* z,
+                        hipStream_t s) {
+  const int w = block_waves(L.n_elem);
+  const size_t lds = (1 + w) * sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
+  hipLaunchKernelGGL((block_sym_kernel<S, T, false>), dim3(unsigned(L.n_elem)), dim3(64 * w), lds, s, L, poff, P,
+                     r, (const T*)nullptr, (T*)nullptr, z, T(0), T(0), 0);
+}
+template <typename T, typename S>
+void launch_block_cheb(const LevelView<T>& L, const long long* poff, const S* P, const T* b, const T* Ax, T* p,
+                       T* x, T alpha, T beta, int first, hipStream_t s) {
+  const int w = block_waves(L.n_elem);
+  const size_t lds = (1 + w) * sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
+  hipLaunchKernelGGL((block_sym_kernel<S, T, true>), dim3(unsigned(L.n_elem)), dim3(64 * w), lds, s, L, poff, P,
+                     b, Ax, p, x, alpha, beta, first);
+}
+#define HPDG_BLOCK_INST(T, S)                                                                             \
+  template void launch_block_apply<T, S>(const LevelView<T>&, const long long*, const S*, const T*, T*,  \
+                                         hipStream_t);                                                    \
+  template void launch_block_cheb<T, S>(const LevelView<T>&, const long long*, const S*, const T*,       \
+                                        const T*, T*, T*, T, T, int, hipStream_t);
+HPDG_BLOCK_INST(double, double)
+HPDG_BLOCK_INST(float, float)
+#undef HPDG_BLOCK_INST
+
+void launch_check_blocks(const LevelView<double>& L, const long long* boff, const double* B, const double* dinv,
+                         int* bad, hipStream_t s) {
+  hipLaunchKernelGGL(check_blocks_kernel, dim3(unsigned(L.n_elem)), dim3(kBS), 0, s, L, boff, B, dinv, bad);
 }
 
 template <typename T>
@@ -543,12 +713,7 @@ void launch_fcg_update(long long n, const double* v, const double* w, double* d,
   template void launch_scale<T>(long long, const T*, const T*, T*, hipStream_t);               \
   template void launch_set_unit<T>(const LevelView<T>&, int, T, T*, hipStream_t);              \
   template void launch_gather_column<T>(const LevelView<T>&, int, const T*, const long long*, T*, \
-                                        hipStream_t);                                           \
-  template void launch_symmetrize_blocks<T>(const LevelView<T>&, const long long*, T*, hipStream_t); \
-  template void launch_block_apply<T>(const LevelView<T>&, const long long*, const T*, const T*, T*, \
-                                      hipStream_t);                                             \
-  template void launch_block_cheb<T>(const LevelView<T>&, const long long*, const T*, const T*,   \
-                                     const T*, T*, T*, T, T, int, hipStream_t);
+                                        hipStream_t);
 HPDG_INST(double)
 HPDG_INST(float)
 #undef HPDG_INST

@@ -39,6 +39,9 @@ def rel(a, b):
 
 MESHES = {
     "cube_l2_p3": (lambda: meshgen.unit_cube(2, 3), meshgen.problem_config1()),
+    # element blocks of 343 and 512 rows (several 64-row panels of the packed inverse blocks)
+    "cube_l1_p6": (lambda: meshgen.unit_cube(1, 6), meshgen.problem_config1()),
+    "cube_l1_p7": (lambda: meshgen.unit_cube(1, 7), meshgen.problem_config1()),
     "box_2to1_p3": (lambda: meshgen.box_grid((2, 1, 1), 1, 3,
                                              refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
                     meshgen.problem_config1()),

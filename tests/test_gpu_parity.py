@@ -98,7 +98,8 @@ def test_rhs_parity(ctx):
 
 @pytest.mark.parametrize("name,smoother", [("cube_l2_p3", "none"), ("hp_k", "point"),
                                            ("shell_l2_p3_r1e3", "point"), ("hp_k", "block"),
-                                           ("shell_l2_p3_r1e3", "block")])
+                                           ("shell_l2_p3_r1e3", "block"), ("cube_l1_p6", "block"),
+                                           ("cube_l1_p7", "block")])
 def test_smoother_and_vcycle_parity(ctx, name, smoother):
     maker, prob = MESHES[name]
     m = maker()
