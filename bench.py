@@ -131,7 +131,8 @@ def make_workload(args, meshgen, hp):
     if args.workload == "shell":
         w["mesh"] = meshgen.cubed_sphere_shell(level=args.level, p=args.p)
         w["prob"] = meshgen.problem_config2()
-        w["upload"] = dict(build_f32=True)
+        # four levels: the coarsest (10,368 DOF, 48 cells at p = 5) is solved exactly
+        w["upload"] = dict(build_f32=True, max_levels=4)
         w["smoother"] = dict(n_cheb=args.n_cheb or 20, smoother=args.smoother or "block",
                              Lambda=args.Lambda or 400.0)
         w["desc"] = ("cubed-sphere shell r=1..1e9 (compactified), 6x8^3 cells + 2:1 inner layer, p=%d, "
@@ -165,6 +166,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--n-cheb", type=int, default=0, help="0: the workload's default")
     ap.add_argument("--Lambda", type=float, default=0.0, help="0: the workload's default")
+    ap.add_argument("--max-levels", type=int, default=-1,
+                    help="multigrid levels (the last one solved exactly); -1: the workload's default, 0: all")
     ap.add_argument("--smoother", default=None, choices=["none", "point", "block"])
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--level", type=int, default=3)
@@ -214,7 +217,10 @@ def main():
     newton = "nl" in W
     ctx = hp.Context(0)
     t0 = time.time()
-    M = ctx.upload(mesh, **W["upload"])
+    up = dict(W["upload"])
+    if args.max_levels >= 0:
+        up["max_levels"] = args.max_levels
+    M = ctx.upload(mesh, **up)
     if args.profile_apply:
         x64 = torch.randn(M.n_dof[0], dtype=torch.float64, device=dev)
         y64 = torch.zeros_like(x64)

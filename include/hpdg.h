@@ -109,7 +109,10 @@ typedef struct {
  *               coefficient (Sec. II.A.5 leaves the GL grid size open; default 1).
  *   coef_kind   HPDG_COEF_*: k = 1, or k = coef_params[1] for |x| < coef_params[0]
  *               and coef_params[2] otherwise.
- *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh).
+ *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh). The last
+ *               level is solved exactly through a dense inverse (N_c^2 scalars, FP64 and
+ *               FP32): N_c^2 must stay below 2^31, else the smoother setup fails with
+ *               HPDG_ERR_UNSUPPORTED.
  *   build_f32   also build FP32 copies of every level (needed by HPDG_F32 calls and
  *               mixed-precision solves).
  *   mass_term   1: every level carries a mass form  sum_sigma w det J c u v  with c set per

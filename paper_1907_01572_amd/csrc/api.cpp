@@ -10,6 +10,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <limits>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -658,6 +659,10 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
 // the explicit inverse is applied as a dense mat-vec in the V-cycle
 void build_coarse(hpdg_mesh* M, hipStream_t s) {
   const int L = M->nlevels() - 1;
+  if (M->H[L].ndof * M->H[L].ndof > (long long)std::numeric_limits<rocblas_int>::max())
+    throw Error(HPDG_ERR_UNSUPPORTED, "the coarsest level has " + std::to_string(M->H[L].ndof) +
+                                          " DOF: its dense matrix exceeds the 32-bit indexing of the dense "
+                                          "Cholesky; allow more multigrid levels");
   const int n = int(M->H[L].ndof);
   M->ncoarse = n;
   DevLevel<double>& d = M->lev<double>(L);
