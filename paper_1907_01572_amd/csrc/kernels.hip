@@ -142,9 +142,11 @@ __global__ void __launch_bounds__(kBS) block_cheb_bf16_kernel(LevelView<float> L
   }
 }
 
-// ---- the packed mat-vec: one wave per element ----
-// The lower triangle is visited in groups of G columns of one panel: first the panel's full
-// columns (c0 = 0, G, .. < r0), then its diagonal tile (tile columns j0 = 0, G, .. < m).
+// ---- the packed mat-vec ----
+// The lower triangle is visited by column blocks of G columns; in a block, by the 64-row panels
+// at and below it: the diagonal panel's tile (tile columns j0 .. j0 + G - 1 of its diagonal
+// tile) and then the full columns c0 .. c0 + G - 1 of every lower panel. The column part is
+// accumulated per lane across the panels and reduced over the wave once per column block.
 constexpr int kGroup = 16;
 
 // G per-lane values w[t] (partial sums of columns c0 + t) summed over the wave; returns, in
@@ -172,100 +174,79 @@ __device__ __forceinline__ T wave_column_sums(T (&w)[G], int lane) {
   return v;
 }
 
-struct PanelGroup {
-  int r0, m, c0;  // panel rows r0 .. r0 + m - 1; first column of the group (tile column if diag)
-  bool diag;
-};
-
-// group gi of an element's sequence (panels in order; per panel its full columns, then its
-// diagonal tile); false past the end
-template <int G>
-__device__ __forceinline__ bool group_at(int gi, int N, PanelGroup& g) {
-  for (int r0 = 0; r0 < N; r0 += 64) {
-    const int m = min(64, N - r0);
-    const int nf = r0 / G, nd = (m + G - 1) / G;
-    if (gi < nf) {
-      g = PanelGroup{r0, m, gi * G, false};
-      return true;
-    }
-    gi -= nf;
-    if (gi < nd) {
-      g = PanelGroup{r0, m, gi * G, true};
-      return true;
-    }
-    gi -= nd;
-  }
-  return false;
-}
-
-// every lane loads (lanes outside the panel or the triangle read a clamped address inside the
-// same column, and the value is discarded), so that no load sits behind a per-lane branch
+// the G values of columns c0 .. c0 + G - 1 in the rows of panel r0 (lane l: row r0 + l). Every
+// lane loads: lanes outside the panel or the triangle read a clamped address inside the same
+// column and their value is discarded later, so that no load sits behind a per-lane branch.
 template <int G, typename S, typename T>
-__device__ __forceinline__ void load_group(const S* Pe, const PanelGroup& g, int lane, T (&v)[G]) {
-  const S* Pp = Pe + (long long)g.r0 * (g.r0 + 1) / 2;
-  const int m = g.m;
-  if (!g.diag) {
-    const S* q = Pp + (long long)g.c0 * m + min(lane, m - 1);
+__device__ __forceinline__ void load_tile(const S* Pe, int N, int c0, int r0, int lane, T (&v)[G]) {
+  const int m = min(64, N - r0);
+  const S* Pp = Pe + (long long)r0 * (r0 + 1) / 2;
+  if (c0 < r0) {  // full columns (c0 + G <= r0: c0 and r0 are multiples of G and 64)
+    const S* q = Pp + (long long)c0 * m + min(lane, m - 1);
 #pragma unroll
     for (int t = 0; t < G; ++t) v[t] = from_storage<T, S>(q[t * m]);
-  } else {
-    const S* Pd = Pp + (long long)g.r0 * m;
+  } else {  // diagonal tile columns j0 .. j0 + G - 1 (column j holds rows j .. m - 1)
+    const S* Pd = Pp + (long long)r0 * m;
+    const int j0 = c0 - r0;
 #pragma unroll
     for (int t = 0; t < G; ++t) {
-      const int j = min(g.c0 + t, m - 1);
+      const int j = min(j0 + t, m - 1);
       const int st = j * m - j * (j - 1) / 2;
       v[t] = from_storage<T, S>(Pd[st + min(max(lane - j, 0), m - 1 - j)]);
     }
   }
 }
 
-// one group: lane l accumulates row r0 + l in acc (xr = r[r0 + l]); the group's column sums go
-// to zs, index i by lane i % 64; the diagonal entry counts for its row only
+// one tile: lane l adds its row's products to z[r0 + l] (LDS, index i only touched by lane
+// i % 64) and its column partials (times r[r0 + l]) to w; the diagonal entry counts once
 template <int G, typename T>
-__device__ __forceinline__ void group_products(const PanelGroup& g, T (&v)[G], int lane, const T* rs, T* zs,
-                                               T& acc, T xr) {
-  const int m = g.m, r0 = g.r0;
+__device__ __forceinline__ void tile_products(int N, int c0, int r0, int lane, const T* rs, T* zs, T (&w)[G],
+                                              const T (&v)[G]) {
+  const int m = min(64, N - r0);
   const bool act = lane < m;
-  T w[G];
-  if (!g.diag) {
+  const T xr = act ? rs[r0 + lane] : T(0);
+  T acc = 0;
+  if (c0 < r0) {
 #pragma unroll
     for (int t = 0; t < G; ++t) {
       const T vv = act ? v[t] : T(0);
-      acc += vv * rs[g.c0 + t];
-      w[t] = vv * xr;
+      acc += vv * rs[c0 + t];
+      w[t] += vv * xr;
     }
-    const T cs = wave_column_sums<G>(w, lane);
-    if (lane / G == ((g.c0 / G) & (64 / G - 1))) zs[g.c0 + (lane & (G - 1))] += cs;  // lane == index % 64
   } else {
+    const int j0 = c0 - r0;
 #pragma unroll
     for (int t = 0; t < G; ++t) {
-      const int j = g.c0 + t;
+      const int j = j0 + t;
       const bool in = act && j < m && lane >= j;
       const T vv = in ? v[t] : T(0);
       acc += vv * rs[r0 + min(j, m - 1)];
-      w[t] = lane > j ? vv * xr : T(0);
+      w[t] += lane > j ? vv * xr : T(0);
     }
-    const T cs = wave_column_sums<G>(w, lane);
-    if (lane / G == g.c0 / G && (lane & (G - 1)) + g.c0 < m) zs[r0 + g.c0 + (lane & (G - 1))] += cs;
   }
+  if (act) zs[r0 + lane] += acc;
 }
 
-// per element, blockDim.x / 64 waves (group gi taken by wave gi % waves): z = Binv r with Binv
-// symmetric and packed (each stored off-diagonal entry is used twice: for its row and, via the
-// wave column sums, for its column); CHEB: r = b - Ax (Ax null: r = b), p = alpha z + beta p
-// (first: alpha z), x += p; else x = z. S is the storage type (double or float), T the
-// arithmetic type. LDS: r (broadcast reads), then per wave the accumulators of z (index i only
-// touched by lane i % 64 of that wave), summed over the waves in a fixed order at the end.
+// per element, blockDim.x / 64 waves (column block k taken by wave k % waves): z = Binv r with
+// Binv symmetric and packed (each stored off-diagonal entry is used twice: for its row and,
+// via the wave column sums, for its column); CHEB: r = b - Ax (Ax null: r = b),
+// p = alpha z + beta p (first: alpha z), x += p; else x = z. S is the storage type (double or
+// float), T the arithmetic type. LDS: r (broadcast reads), then per wave the accumulators of z
+// (index i only touched by lane i % 64 of that wave), summed over the waves in a fixed order.
 template <typename S, typename T, bool CHEB>
 __global__ void __launch_bounds__(512) block_sym_kernel(LevelView<T> L, const long long* poff, const S* P,
                                                         const T* b, const T* Ax, T* p, T* x, T alpha, T beta,
                                                         int first) {
+  constexpr int G = kGroup;
   extern __shared__ unsigned char smem_raw[];
   const long long e = blockIdx.x;
   if (e >= L.n_elem) return;
   const ElemInfo I = L.einfo[e];
   const int N = I.n * I.n * I.n;
-  const int waves = int(blockDim.x >> 6), lane = int(threadIdx.x & 63), wv = int(threadIdx.x >> 6);
+  // the wave index is uniform over the wave: taken into a scalar register, so that the loop
+  // control and the block addresses stay scalar
+  const int waves = int(blockDim.x >> 6), lane = int(threadIdx.x & 63);
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
   T* rs = reinterpret_cast<T*>(smem_raw);
   T* zs = rs + N + wv * N;
   for (int i = threadIdx.x; i < N; i += blockDim.x)
@@ -273,22 +254,22 @@ __global__ void __launch_bounds__(512) block_sym_kernel(LevelView<T> L, const lo
   for (int i = lane; i < N; i += 64) zs[i] = 0;
   __syncthreads();
   const S* Pe = P + poff[e];
-  T acc = 0, xr = 0;
-  int cur = -1, cur_m = 0;  // panel of the row sums in acc
-  PanelGroup g;
-  for (int gi = wv; group_at<kGroup>(gi, N, g); gi += waves) {
-    if (g.r0 != cur) {
-      if (cur >= 0 && lane < cur_m) zs[cur + lane] += acc;
-      cur = g.r0;
-      cur_m = g.m;
-      acc = 0;
-      xr = lane < g.m ? rs[g.r0 + lane] : T(0);
+#pragma unroll 1
+  for (int kb = wv; kb * G < N; kb += waves) {
+    const int c0 = kb * G;  // a multiple of G by construction (lets the compiler simplify the indexing)
+    T w[G];
+#pragma unroll
+    for (int t = 0; t < G; ++t) w[t] = 0;
+#pragma unroll 1
+    for (int r0 = c0 & ~63; r0 < N; r0 += 64) {
+      T v[G];
+      load_tile<G>(Pe, N, c0, r0, lane, v);
+      tile_products<G>(N, c0, r0, lane, rs, zs, w, v);
     }
-    T v[kGroup];
-    load_group<kGroup>(Pe, g, lane, v);
-    group_products<kGroup>(g, v, lane, rs, zs, acc, xr);
+    const T cs = wave_column_sums<G>(w, lane);
+    // lane == (c0 + lane % G) % 64 owns that index
+    if (lane / G == ((c0 / G) & (64 / G - 1)) && c0 + (lane & (G - 1)) < N) zs[c0 + (lane & (G - 1))] += cs;
   }
-  if (cur >= 0 && lane < cur_m) zs[cur + lane] += acc;
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     T z = 0;
