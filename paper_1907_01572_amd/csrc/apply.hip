@@ -85,13 +85,19 @@ __device__ inline void for_items(int c0, int c1, int c2, int c3, int c4, int c5,
 
 #define HPDG_COUNTS(expr) expr(0), expr(1), expr(2), expr(3), expr(4), expr(5)
 
+// compact: uniform-degree levels with at most one volume node per thread; the element's
+// coefficients sit at the start of the shared region (dead once the volume phase has read
+// them: the face phases take both sides' traces from the trace buffer) and each thread keeps
+// its volume result in a register, so the workgroup needs less LDS
 struct Layout {
   int NM, QM, QMM;
+  bool compact;
   size_t fixed, vol, ra, rb, y, tasks;
-  __host__ __device__ Layout(int nm, int qm, int qmm) : NM(nm), QM(qm), QMM(qmm) {
-    fixed = 2 * size_t(NM) * NM * NM + size_t(QM) * NM + size_t(QM) * QM + QM + 2 * NM;
+  __host__ __device__ Layout(int nm, int qm, int qmm, bool cmp = false) : NM(nm), QM(qm), QMM(qmm), compact(cmp) {
+    const size_t n3 = size_t(NM) * NM * NM;
+    fixed = (compact ? 0 : 2 * n3) + size_t(QM) * NM + size_t(QM) * QM + QM + 2 * NM;
     const size_t tsz = size_t(NM) * QM * (NM > QM ? NM : QM);
-    vol = 4 * size_t(QM) * QM * QM + 2 * tsz;
+    vol = (compact ? n3 : 0) + 4 * size_t(QM) * QM * QM + 2 * tsz;
     ra = kFaces * mx3(size_t(NM) * NM * NM, 6 * size_t(NM) * QMM, 4 * size_t(QMM) * QMM);
     rb = kFaces * mx3(4 * size_t(NM) * NM, 8 * size_t(QMM) * QMM, 3 * size_t(QMM) * NM);
     y = 2 * kFaces * size_t(NM) * NM;
@@ -145,9 +151,9 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
 // matrices (values / derivatives at the full, lower-half and upper-half point sets) are
 // staged in LDS once, and each phase maps threads to (task, item) with constant strides.
 // Adds the face terms to sy and writes y.
-template <typename T, int N, int Q>
+template <typename T, int N, int Q, bool COMPACT>
 __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, const T* __restrict__ x,
-                              T* __restrict__ y, const T* su, const T* sy, const T* dfo, T* region, Task* tasks,
+                              T* __restrict__ y, const T* sy, T syr, const T* dfo, T* region, Task* tasks,
                               const Layout& lay) {
   constexpr int N2 = N * N, N3 = N2 * N, QQ = Q * Q, NQ = N * Q;
   const int NM = lay.NM, QMM = lay.QMM;
@@ -165,30 +171,18 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
   for (int r = 0; r < rounds; ++r) {
     for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
     __syncthreads();
-    // P1: traces (values, reference normal derivative) of the own face from the element's
-    // coefficients; the neighbour's from its stored traces
+    // P1: traces (values, reference normal derivative) of both sides from the trace buffer
     for (int g = threadIdx.x; g < kFaces * 2 * N2; g += blockDim.x) {
       const int t = g / (2 * N2), li = g % (2 * N2);
       const Task& tk = tasks[t];
       if (!tk.valid) continue;
-      if (li >= N2) {
-        if (!tk.other) continue;
-        const int l2 = li - N2;
-        T* tr = RB + t * rbS + 2 * NM * NM;
-        tr[l2] = L.trace[tk.ooff + l2];
-        tr[NM * NM + l2] = L.trace[tk.ooff + N2 + l2];
-        continue;
-      }
-      const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      const int kf = (f & 1) ? N - 1 : 0;
-      const T* df = dfo + (f & 1) * NM;
-      const int i = li % N, j = li / N;
-      T* tr = RB + t * rbS;
-      tr[li] = su[vidx(N, d, t0, t1, kf, i, j)];
-      T s = 0;
-#pragma unroll
-      for (int k = 0; k < N; ++k) s += df[k] * su[vidx(N, d, t0, t1, k, i, j)];
-      tr[NM * NM + li] = s;
+      const bool own = li < N2;
+      if (!own && !tk.other) continue;
+      const int l2 = own ? li : li - N2;
+      const long long off = own ? I.toff + 2LL * tk.f * N2 : tk.ooff;
+      T* tr = RB + t * rbS + (own ? 0 : 2 * NM * NM);
+      tr[l2] = L.trace[off + l2];
+      tr[NM * NM + l2] = L.trace[off + N2 + l2];
     }
     __syncthreads();
     // P2: first interpolation pass (along face axis a): u, du/da, du/dn
@@ -354,7 +348,7 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
   // face sums -> element
   for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) {
     const int c0 = idx % N, c1 = (idx / N) % N, c2 = idx / N2;
-    T acc = sy[idx];
+    T acc = COMPACT ? syr : sy[idx];
 #pragma unroll
     for (int f = 0; f < kFaces; ++f) {
       if (I.fcnt[f] == 0) continue;
@@ -391,19 +385,25 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const ElemInfo I = L.einfo[e];
   const int n = NT ? NT : I.n, q = QT ? QT : I.q;
   const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
-  const Layout lay(L.nmax, L.qmax, L.qmmax);
+  constexpr bool COMPACT = UNI && NT > 0 && NT * NT * NT <= kThreads;
+  const Layout lay(L.nmax, L.qmax, L.qmmax, COMPACT);
   const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
 
   Task* tasks = reinterpret_cast<Task*>(smem_raw);
   T* p = reinterpret_cast<T*>(smem_raw + lay.tasks);
-  T* su = p; p += NM * NM * NM;
-  T* sy = p; p += NM * NM * NM;
+  T* su = p;
+  T* sy = p + NM * NM * NM;
+  if (!COMPACT) p += 2 * NM * NM * NM;
   T* Bm = p; p += QM * NM;        // LGL -> GL interpolation [q][n]
   T* Dg = p; p += QM * QM;        // GL collocation derivative [q][q]
   T* w = p; p += QM;              // GL weights
   T* dfo = p; p += 2 * NM;        // l_k'(-1), l_k'(+1) of the own basis
   T* region = p;
-  T* A0 = region;
+  if (COMPACT) {
+    su = region;  // the coefficients open the region; the volume buffers follow
+    sy = nullptr;
+  }
+  T* A0 = region + (COMPACT ? NM * NM * NM : 0);
   T* A1 = A0 + QM * QM * QM;
   T* A2 = A1 + QM * QM * QM;
   T* A3 = A2 + QM * QM * QM;
@@ -510,18 +510,22 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     tA[idx] = acc;  // [k][j][a]
   }
   __syncthreads();
+  T syr = 0;  // COMPACT: this thread's volume result (at most one node per thread)
   for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) {
     const int i = idx % n, kj = idx / n;
     T acc = 0;
 #pragma unroll
     for (int a = 0; a < q; ++a) acc += Bm[a * n + i] * tA[kj * q + a];
-    sy[idx] = acc;
+    if (COMPACT)
+      syr = acc;
+    else
+      sy[idx] = acc;
   }
   __syncthreads();  // the face phases reuse the volume buffers
 
   // ---- faces ----
   if constexpr (UNI) {
-    faces_uniform<T, NT, QT>(L, I, e, x, y, su, sy, dfo, region, tasks, lay);
+    faces_uniform<T, NT, QT, COMPACT>(L, I, e, x, y, sy, syr, dfo, region, tasks, lay);
     return;
   }
   int rounds = 0;
@@ -767,11 +771,13 @@ void launch_fixed(const LevelView<T>& L, const int* elems, long long count, cons
 
 }  // namespace
 
-size_t apply_lds_bytes(int NM, int QM, int QMM, size_t scalar) { return Layout(NM, QM, QMM).bytes(scalar); }
+size_t apply_lds_bytes(int NM, int QM, int QMM, size_t scalar, bool compact) {
+  return Layout(NM, QM, QMM, compact).bytes(scalar);
+}
 
 template <typename T>
 void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s) {
-  if (L.n_elem == 0 || L.self_only) return;
+  if (L.n_elem == 0) return;  // also with self_only: the uniform face path reads the own traces
   hipLaunchKernelGGL((trace_kernel<T>), dim3(unsigned(L.n_elem)), dim3(kThreads), 0, s, L, x);
 }
 
@@ -779,7 +785,7 @@ template <typename T>
 void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
   if (L.n_elem == 0) return;
   launch_traces<T>(L, x, s);
-  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T));
+  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
   hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
                      (const int*)nullptr, L.n_elem, x, y);
 }
@@ -788,10 +794,12 @@ template <typename T>
 void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
                          const T* x, T* y, hipStream_t s) {
   if (count == 0) return;
-  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T));
+  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
+  // the uniform kernels of degree n with n^3 <= kThreads use the compact layout
+  const size_t lds_u = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), n * n * n <= kThreads);
 #define HPDG_CASE(NN, QQ)                                                                      \
   if (n == NN && q == QQ)                                                                       \
-    return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds, s)               \
+    return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds_u, s)             \
                    : launch_fixed<T, NN, QQ, false>(L, elems, count, x, y, lds, s);
   HPDG_CASE(2, 2) HPDG_CASE(2, 3) HPDG_CASE(3, 3) HPDG_CASE(3, 4) HPDG_CASE(4, 4) HPDG_CASE(4, 5)
   HPDG_CASE(5, 5) HPDG_CASE(5, 6) HPDG_CASE(6, 6) HPDG_CASE(6, 7) HPDG_CASE(7, 7) HPDG_CASE(7, 8)

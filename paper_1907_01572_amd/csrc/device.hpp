@@ -42,10 +42,11 @@ struct TransferView {
   int nmax;
 };
 
-size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar);
+size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar, bool compact);
 
 // face traces of every element of the level: for each face, the values at its n^2 LGL nodes
-// and the reference normal derivative there (read by the neighbours' face terms)
+// and the reference normal derivative there (read by the face terms: the neighbours' traces,
+// and on uniform-degree levels the own ones too)
 template <typename T>
 void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s);
 template <typename T>
