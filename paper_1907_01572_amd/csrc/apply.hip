@@ -98,8 +98,13 @@ struct Layout {
     fixed = (compact ? 0 : 2 * n3) + size_t(QM) * NM + size_t(QM) * QM + QM + 2 * NM;
     const size_t tsz = size_t(NM) * QM * (NM > QM ? NM : QM);
     vol = (compact ? n3 : 0) + 4 * size_t(QM) * QM * QM + 2 * tsz;
-    ra = kFaces * mx3(size_t(NM) * NM * NM, 6 * size_t(NM) * QMM, 4 * size_t(QMM) * QMM);
-    rb = kFaces * mx3(4 * size_t(NM) * NM, 8 * size_t(QMM) * QMM, 3 * size_t(QMM) * NM);
+    if (compact) {  // the uniform face phases only (see faces_uniform)
+      ra = kFaces * mx3(6 * size_t(NM) * QMM, 3 * size_t(QMM) * NM, 0);
+      rb = kFaces * mx3(4 * size_t(NM) * NM, 4 * size_t(QMM) * QMM, 0);
+    } else {  // large enough for both face paths
+      ra = kFaces * mx3(size_t(NM) * NM * NM, 6 * size_t(NM) * QMM, 4 * size_t(QMM) * QMM);
+      rb = kFaces * mx3(4 * size_t(NM) * NM, 8 * size_t(QMM) * QMM, 3 * size_t(QMM) * NM);
+    }
     y = 2 * kFaces * size_t(NM) * NM;
     tasks = (kFaces * sizeof(Task) + 15) / 16 * 16;
   }
@@ -159,6 +164,8 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
   const int NM = lay.NM, QMM = lay.QMM;
   const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
   T* mats = region;  // [kind 0..5][Q][N]
+  // RB: traces (4 NM^2), then the flux coefficients (4 QMM^2); RA: first-pass values of both
+  // sides (6 NM QMM), then the first transposed pass (3 QMM NM)
   T* RA = mats + 6 * QMM * NM;
   T* RB = RA + lay.ra;
   T* Yf = RB + lay.rb;
@@ -214,42 +221,35 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       T1[2 * NM * QMM + j * Q + xg] = s2;
     }
     __syncthreads();
-    // P3: second pass (along face axis b): u, du/da, du/db, du/dn at the points
-    for (int g = threadIdx.x; g < kFaces * 2 * QQ; g += blockDim.x) {
-      const int t = g / (2 * QQ), li = g % (2 * QQ);
-      const Task& tk = tasks[t];
-      if (!tk.valid) continue;
-      const bool own = li < QQ;
-      if (!own && !tk.other) continue;
-      const int l2 = own ? li : li - QQ;
-      const Map m = own ? tk.me : tk.ot;
-      const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-      const T* Mb = mats + (2 * m.halfB) * NQ;
-      const T* Db = Mb + NQ;
-      const int xg = l2 % Q, yg = l2 / Q;
-      const int rb = m.flipB ? Q - 1 - yg : yg;
-      T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-#pragma unroll
-      for (int j = 0; j < N; ++j) {
-        const T mb = Mb[rb * N + j];
-        const T a0 = T1[j * Q + xg];
-        g0 += mb * a0;
-        g1 += mb * T1[NM * QMM + j * Q + xg];
-        g2 += Db[rb * N + j] * a0;
-        g3 += mb * T1[2 * NM * QMM + j * Q + xg];
-      }
-      T* Gs = RB + t * rbS + (own ? 0 : 4 * QMM * QMM);
-      Gs[l2] = g0;
-      Gs[QMM * QMM + l2] = g1;
-      Gs[2 * QMM * QMM + l2] = g2;
-      Gs[3 * QMM * QMM + l2] = g3;
-    }
-    __syncthreads();
-    // P4: SIPG flux at the mortar points, own side, own frame
+    // P3+P4: second pass (along face axis b) of both sides at one mortar point: u, du/da,
+    // du/db, du/dn; then the SIPG flux there (own side, own frame) into RB
     for (int g = threadIdx.x; g < kFaces * QQ; g += blockDim.x) {
       const int t = g / QQ, li = g % QQ;
       const Task& tk = tasks[t];
       if (!tk.valid) continue;
+      // side values at the point with index l2 of that side's frame
+      auto at_point = [&](bool own, int l2, T& v0, T& v1, T& v2, T& v3) {
+        const Map m = own ? tk.me : tk.ot;
+        const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
+        const T* Mb = mats + (2 * m.halfB) * NQ;
+        const T* Db = Mb + NQ;
+        const int xg = l2 % Q, yg = l2 / Q;
+        const int rb = m.flipB ? Q - 1 - yg : yg;
+        T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) {
+          const T mb = Mb[rb * N + j];
+          const T a0 = T1[j * Q + xg];
+          g0 += mb * a0;
+          g1 += mb * T1[NM * QMM + j * Q + xg];
+          g2 += Db[rb * N + j] * a0;
+          g3 += mb * T1[2 * NM * QMM + j * Q + xg];
+        }
+        v0 = g0;
+        v1 = g1;
+        v2 = g2;
+        v3 = g3;
+      };
       const int side = tk.side;
       const int npts = tk.gmode ? QQ : 1;
       const T* mg = L.mgeo + tk.geo;
@@ -268,9 +268,9 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       const T ma = mg[(3 * side + t0) * npts + pp];
       const T mb = mg[(3 * side + t1) * npts + pp];
       const T mn = mg[(3 * side + d) * npts + pp];
-      const T* Gm = RB + t * rbS;
-      const T u_me = Gm[li];
-      const T g_me = ma * Gm[QMM * QMM + li] + mb * Gm[2 * QMM * QMM + li] + mn * Gm[3 * QMM * QMM + li];
+      T u_me, ga, gb, gn;
+      at_point(true, li, u_me, ga, gb, gn);
+      const T g_me = ma * ga + mb * gb + mn * gn;
       T Af, Bc;
       if (tk.interior) {
         T u_o = 0, g_o = 0;
@@ -278,11 +278,10 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
           const int os = 1 - side, od = tk.of >> 1;
           const int ot0 = od == 0 ? 1 : 0, ot1 = od == 2 ? 1 : 2;
           const int oi = tk.ot.swap ? dd + Q * cc : cc + Q * dd;
-          const T* Go = Gm + 4 * QMM * QMM;
-          u_o = Go[oi];
-          g_o = mg[(3 * os + ot0) * npts + pp] * Go[QMM * QMM + oi] +
-                mg[(3 * os + ot1) * npts + pp] * Go[2 * QMM * QMM + oi] +
-                mg[(3 * os + od) * npts + pp] * Go[3 * QMM * QMM + oi];
+          T oa, ob, on;
+          at_point(false, oi, u_o, oa, ob, on);
+          g_o = mg[(3 * os + ot0) * npts + pp] * oa + mg[(3 * os + ot1) * npts + pp] * ob +
+                mg[(3 * os + od) * npts + pp] * on;
         }
         const T jmp = u_me - u_o;
         Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
@@ -291,7 +290,7 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
         Af = wS * (sig * u_me - g_me);
         Bc = -wS * u_me;
       }
-      T* CF = RA + t * raS;
+      T* CF = RB + t * rbS;
       CF[li] = Af;
       CF[QMM * QMM + li] = Bc * ma;
       CF[2 * QMM * QMM + li] = Bc * mb;
@@ -305,7 +304,7 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       if (!tk.valid) continue;
       const T* Ma = mats + (2 * tk.me.halfA) * NQ;
       const T* Da = Ma + NQ;
-      const T* CF = RA + t * raS;
+      const T* CF = RB + t * rbS;
       const int i = li % N, yg = li / N;
       T s1 = 0, s2 = 0, s3 = 0;
 #pragma unroll
@@ -317,7 +316,7 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
         s2 += ma * CF[2 * QMM * QMM + gi];
         s3 += ma * CF[3 * QMM * QMM + gi];
       }
-      T* S = RB + t * rbS;
+      T* S = RA + t * raS;
       S[li] = s1;
       S[QMM * NM + li] = s2;
       S[2 * QMM * NM + li] = s3;
@@ -330,7 +329,7 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       if (!tk.valid) continue;
       const T* Mb = mats + (2 * tk.me.halfB) * NQ;
       const T* Db = Mb + NQ;
-      const T* S = RB + t * rbS;
+      const T* S = RA + t * raS;
       const int i = li % N, j = li / N;
       T yf = 0, yn = 0;
 #pragma unroll
