@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
     ap.add_argument("--max-active", type=int, default=4, help="serving: requests in flight")
     ap.add_argument("--n-cheb", type=int, default=0, help="0: the workload's default")
+    ap.add_argument("--n-cheb-coarse", type=int, default=-1,
+                    help="Chebyshev steps on the levels below the finest; -1: the workload's default")
     ap.add_argument("--Lambda", type=float, default=0.0, help="0: the workload's default")
     ap.add_argument("--max-levels", type=int, default=-1,
                     help="multigrid levels (the last one solved exactly); -1: the workload's default, 0: all")
@@ -232,6 +234,8 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"profile_apply": True, "dof": M.n_dof[0], "reps": args.apply_reps}))
         return
+    if args.n_cheb_coarse >= 0:
+        W["smoother"]["n_cheb_coarse"] = args.n_cheb_coarse
     lam = M.setup_smoother(**W["smoother"])
     setup_s = time.time() - t0
     N = M.n_dof[0]
@@ -337,7 +341,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": W["desc"] + " (%d DOF)" % N, "name": args.workload,
                    "elements": M.n_elem[0], "dof": N, "levels": M.n_levels, "level_dof": list(M.n_dof),
-                   "n_cheb": W["smoother"]["n_cheb"], "Lambda": W["smoother"]["Lambda"],
+                   "n_cheb": W["smoother"]["n_cheb"], "n_cheb_coarse": W["smoother"].get("n_cheb_coarse", 0),
+                   "Lambda": W["smoother"]["Lambda"],
                    "smoother": W["smoother"]["smoother"]},
         "solve": solve_info,
         "mixed": mixed_info,
@@ -360,7 +365,8 @@ def main():
     if not args.no_cpu:
         n_lin = float(np.mean(iters))
         n_newton = float(np.mean(solve_info.get("newton_steps", [0])))
-        out["cpu_baseline"] = cpu_baseline(mesh, prob, M, W["smoother"]["n_cheb"], n_lin, n_newton,
+        out["cpu_baseline"] = cpu_baseline(mesh, prob, M, W["smoother"]["n_cheb"],
+                                           W["smoother"].get("n_cheb_coarse", 0), n_lin, n_newton,
                                            mass=newton)
     print(json.dumps(out))
     M.free()
@@ -457,7 +463,7 @@ def run_serving(args, meshgen, hp):
     ctx.close()
 
 
-def cpu_baseline(mesh, prob, M, n_cheb, n_lin, n_newton, mass=False):
+def cpu_baseline(mesh, prob, M, n_cheb, n_cheb_coarse, n_lin, n_newton, mass=False):
     """The oracle's matrix-free apply on a bounded sample of the same mesh, on the host."""
     from threadpoolctl import threadpool_limits
 
@@ -487,7 +493,8 @@ def cpu_baseline(mesh, prob, M, n_cheb, n_lin, n_newton, mass=False):
     # per Newton step two residuals and 15 CG-bound applies per smoothed level.  The oracle's
     # rate divided by this count bounds its solves/s from above (smoother block solves,
     # transfers, vector work and the coarse factorisations are not charged to it).
-    per_iter = M.n_dof[0] + sum(2 * n_cheb * M.n_dof[lv] for lv in range(M.n_levels - 1))
+    steps = [n_cheb if lv == 0 or n_cheb_coarse <= 0 else n_cheb_coarse for lv in range(M.n_levels - 1)]
+    per_iter = M.n_dof[0] + sum(2 * steps[lv] * M.n_dof[lv] for lv in range(M.n_levels - 1))
     per_newton = 2 * M.n_dof[0] + sum(15 * M.n_dof[lv] for lv in range(M.n_levels - 1))
     dof_applies = M.n_dof[0] + n_lin * per_iter + n_newton * per_newton
     return {"value": dof_apply_per_s / dof_applies, "unit": "solves/s", "cores": 1, "kind": "oracle",

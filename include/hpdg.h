@@ -146,8 +146,8 @@ typedef struct {
  *   HPDG_SMOOTH_NONE   M = I (the printed form of Alg. 4);
  *   HPDG_SMOOTH_POINT  M = diag(A) (point Jacobi);
  *   HPDG_SMOOTH_BLOCK  M = the element-diagonal blocks A_ee (element-block Jacobi; their
- *                      inverses are formed on the device at setup, (p+1)^6 values per
- *                      element and level).
+ *                      inverses are formed on the device at setup and kept as packed lower
+ *                      triangles, N (N + 1) / 2 values per element and level, N = (p+1)^3).
  * The bound of Alg. 5 is then taken for M^-1 A (preconditioned CG with the same M). */
 enum { HPDG_SMOOTH_NONE = 0, HPDG_SMOOTH_POINT = 1, HPDG_SMOOTH_BLOCK = 2 };
 typedef struct {
@@ -156,6 +156,8 @@ typedef struct {
   double Lambda;         /* lambda_min = lambda_max / Lambda (default 20) */
   int32_t scaling;       /* HPDG_SMOOTH_* (default HPDG_SMOOTH_POINT) */
   uint64_t seed;         /* SplitMix64 seed of the CG start vector */
+  int32_t n_cheb_coarse; /* Chebyshev steps per smoothing call on the levels below the finest
+                            (0: n_cheb) */
 } hpdg_smoother_params;
 
 typedef struct {

@@ -65,7 +65,7 @@ class MeshInfo(ctypes.Structure):
 
 class SmootherParams(ctypes.Structure):
     _fields_ = [("n_cheb", ctypes.c_int32), ("n_eigs", ctypes.c_int32), ("Lambda", ctypes.c_double),
-                ("scaling", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+                ("scaling", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_cheb_coarse", ctypes.c_int32)]
 
 
 class SolveParams(ctypes.Structure):
@@ -350,10 +350,11 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_apply(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
 
     def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
-                       smoother=None, stream=None):
-        """``smoother``: "none", "point" or "block" (default: "point" if jacobi else "none")."""
+                       smoother=None, stream=None, n_cheb_coarse=0):
+        """``smoother``: "none", "point" or "block" (default: "point" if jacobi else "none").
+        ``n_cheb_coarse``: Chebyshev steps on the levels below the finest (0: ``n_cheb``)."""
         kind = smoother if smoother is not None else ("point" if jacobi else "none")
-        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed)
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed, n_cheb_coarse)
         lam = np.zeros(max(self.n_levels - 1, 1))
         if lambda_max is not None:
             lam[:len(lambda_max)] = lambda_max

@@ -96,7 +96,7 @@ struct hpdg_mesh {
   int ncoarse = 0;
   // smoother
   std::vector<double> lam;
-  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0};
+  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0, 0};
   bool smoother_ready = false;
   rocblas_handle blas = nullptr;  // batched Cholesky of the element blocks (setup only)
   // nonlinear source (Newton)
@@ -435,7 +435,7 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
 template <typename T>
 void vcycle(hpdg_mesh* M, const T* r0, T* z0, hipStream_t s) {
   const int L = M->nlevels() - 1;
-  const int nc = M->sp.n_cheb;
+  auto nc = [&](int l) { return l > 0 && M->sp.n_cheb_coarse > 0 ? M->sp.n_cheb_coarse : M->sp.n_cheb; };
   std::vector<const T*> f(L + 1);
   std::vector<T*> v(L + 1);
   for (int l = 0; l <= L; ++l) {
@@ -446,7 +446,7 @@ void vcycle(hpdg_mesh* M, const T* r0, T* z0, hipStream_t s) {
     DevLevel<T>& d = M->lev<T>(l);
     const long long n = M->H[l].ndof;
     launch_fill<T>(n, T(0), v[l], s);
-    smooth_level<T>(M, l, f[l], v[l], nc, true, s);
+    smooth_level<T>(M, l, f[l], v[l], nc(l), true, s);
     apply_level<T>(M, l, v[l], d.t, s);
     launch_axpby<T>(n, T(1), f[l], T(-1), d.t, s);  // t = f - A v
     launch_restrict<T>(M->tview<T>(l), d.t, M->lev<T>(l + 1).f, s);
@@ -458,7 +458,7 @@ void vcycle(hpdg_mesh* M, const T* r0, T* z0, hipStream_t s) {
   launch_dense_matvec<T>(M->ncoarse, M->ainv<T>(), f[L], v[L], s);
   for (int l = L - 1; l >= 0; --l) {
     launch_prolong_add<T>(M->tview<T>(l), v[l + 1], v[l], s);
-    smooth_level<T>(M, l, f[l], v[l], nc, false, s);
+    smooth_level<T>(M, l, f[l], v[l], nc(l), false, s);
   }
 }
 
@@ -841,6 +841,7 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
   if (params) {
     mesh->sp = *params;
     if (mesh->sp.n_cheb <= 0) mesh->sp.n_cheb = 4;
+    if (mesh->sp.n_cheb_coarse < 0) mesh->sp.n_cheb_coarse = 0;
     if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
     if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
     if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)
