@@ -85,10 +85,10 @@ __device__ inline void for_items(int c0, int c1, int c2, int c3, int c4, int c5,
 
 #define HPDG_COUNTS(expr) expr(0), expr(1), expr(2), expr(3), expr(4), expr(5)
 
-// compact: uniform-degree levels with at most one volume node per thread; the element's
+// compact: uniform-degree levels with at most two volume nodes per thread; the element's
 // coefficients sit at the start of the shared region (dead once the volume phase has read
 // them: the face phases take both sides' traces from the trace buffer) and each thread keeps
-// its volume result in a register, so the workgroup needs less LDS
+// its volume results in registers, so the workgroup needs less LDS
 struct Layout {
   int NM, QM, QMM;
   bool compact;
@@ -158,7 +158,7 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
 // Adds the face terms to sy and writes y.
 template <typename T, int N, int Q, bool COMPACT>
 __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, const T* __restrict__ x,
-                              T* __restrict__ y, const T* sy, T syr, const T* dfo, T* region, Task* tasks,
+                              T* __restrict__ y, const T* sy, const T (&syr)[2], const T* dfo, T* region, Task* tasks,
                               const Layout& lay) {
   constexpr int N2 = N * N, N3 = N2 * N, QQ = Q * Q, NQ = N * Q;
   const int NM = lay.NM, QMM = lay.QMM;
@@ -345,9 +345,8 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
     __syncthreads();
   }
   // face sums -> element
-  for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) {
+  auto finish = [&](int idx, T acc) {
     const int c0 = idx % N, c1 = (idx / N) % N, c2 = idx / N2;
-    T acc = COMPACT ? syr : sy[idx];
 #pragma unroll
     for (int f = 0; f < kFaces; ++f) {
       if (I.fcnt[f] == 0) continue;
@@ -358,6 +357,13 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       if (kd == ((f & 1) ? N - 1 : 0)) acc += Yf[f * NM * NM + li];
     }
     y[I.off + idx] = acc;
+  };
+  if constexpr (COMPACT) {  // node threadIdx.x + it kThreads of this thread
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      if (int(threadIdx.x) + it * kThreads < N3) finish(int(threadIdx.x) + it * kThreads, syr[it]);
+  } else {
+    for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) finish(idx, sy[idx]);
   }
 }
 
@@ -384,7 +390,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const ElemInfo I = L.einfo[e];
   const int n = NT ? NT : I.n, q = QT ? QT : I.q;
   const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
-  constexpr bool COMPACT = UNI && NT > 0 && NT * NT * NT <= kThreads;
+  constexpr bool COMPACT = UNI && NT > 0 && NT * NT * NT <= 2 * kThreads;
   const Layout lay(L.nmax, L.qmax, L.qmmax, COMPACT);
   const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
 
@@ -509,16 +515,21 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     tA[idx] = acc;  // [k][j][a]
   }
   __syncthreads();
-  T syr = 0;  // COMPACT: this thread's volume result (at most one node per thread)
-  for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) {
+  // COMPACT: this thread's volume results (nodes threadIdx.x and threadIdx.x + kThreads)
+  T syr[2] = {0, 0};
+  auto back_a = [&](int idx) {
     const int i = idx % n, kj = idx / n;
     T acc = 0;
 #pragma unroll
     for (int a = 0; a < q; ++a) acc += Bm[a * n + i] * tA[kj * q + a];
-    if (COMPACT)
-      syr = acc;
-    else
-      sy[idx] = acc;
+    return acc;
+  };
+  if constexpr (COMPACT) {
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      if (int(threadIdx.x) + it * kThreads < n3) syr[it] = back_a(int(threadIdx.x) + it * kThreads);
+  } else {
+    for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) sy[idx] = back_a(idx);
   }
   __syncthreads();  // the face phases reuse the volume buffers
 
@@ -794,8 +805,8 @@ void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const
                          const T* x, T* y, hipStream_t s) {
   if (count == 0) return;
   const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
-  // the uniform kernels of degree n with n^3 <= kThreads use the compact layout
-  const size_t lds_u = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), n * n * n <= kThreads);
+  // the uniform kernels of degree n with n^3 <= 2 kThreads use the compact layout
+  const size_t lds_u = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), n * n * n <= 2 * kThreads);
 #define HPDG_CASE(NN, QQ)                                                                      \
   if (n == NN && q == QQ)                                                                       \
     return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds_u, s)             \
