@@ -85,7 +85,7 @@ __device__ inline void for_items(int c0, int c1, int c2, int c3, int c4, int c5,
 
 #define HPDG_COUNTS(expr) expr(0), expr(1), expr(2), expr(3), expr(4), expr(5)
 
-// compact: uniform-degree levels with at most two volume nodes per thread; the element's
+// compact: kernels of a fixed degree with at most two volume nodes per thread; the element's
 // coefficients sit at the start of the shared region (dead once the volume phase has read
 // them: the face phases take both sides' traces from the trace buffer) and each thread keeps
 // its volume results in registers, so the workgroup needs less LDS
@@ -98,7 +98,7 @@ struct Layout {
     fixed = (compact ? 0 : 2 * n3) + size_t(QM) * NM + size_t(QM) * QM + QM + 2 * NM;
     const size_t tsz = size_t(NM) * QM * (NM > QM ? NM : QM);
     vol = (compact ? n3 : 0) + 4 * size_t(QM) * QM * QM + 2 * tsz;
-    if (compact) {  // the uniform face phases only (see faces_uniform)
+    if (compact) {  // fused face phases: RA holds T1, then S; RB the traces, then the fluxes
       ra = kFaces * mx3(6 * size_t(NM) * QMM, 3 * size_t(QMM) * NM, 0);
       rb = kFaces * mx3(4 * size_t(NM) * NM, 4 * size_t(QMM) * QMM, 0);
     } else {  // large enough for both face paths
@@ -390,7 +390,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const ElemInfo I = L.einfo[e];
   const int n = NT ? NT : I.n, q = QT ? QT : I.q;
   const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
-  constexpr bool COMPACT = UNI && NT > 0 && NT * NT * NT <= 2 * kThreads;
+  constexpr bool COMPACT = NT > 0 && NT * NT * NT <= 2 * kThreads;
   const Layout lay(L.nmax, L.qmax, L.qmmax, COMPACT);
   const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
 
@@ -545,22 +545,15 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   for (int r = 0; r < rounds; ++r) {
     for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
     __syncthreads();
-    // P1: traces (values and reference normal derivative) of the own face; the neighbour's
-    // from its stored traces
+    // P1: traces (values and reference normal derivative) of both sides from the trace buffer
 #define C1(t) (tasks[t].valid ? n2 + (tasks[t].other ? tasks[t].no * tasks[t].no : 0) : 0)
     for_items(HPDG_COUNTS(C1), [&](int t, int li) {
       const Task& tk = tasks[t];
       T* tr = RB + t * rbS;  // Fm, Nm, Fo, No at strides NM^2
       if (li < n2) {
-        const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-        const int kf = (f & 1) ? n - 1 : 0;
-        const T* df = dfo + (f & 1) * NM;
-        const int i = li % n, j = li / n;
-        tr[li] = su[vidx(n, d, t0, t1, kf, i, j)];
-        T s = 0;
-#pragma unroll
-        for (int k = 0; k < n; ++k) s += df[k] * su[vidx(n, d, t0, t1, k, i, j)];
-        tr[NM * NM + li] = s;
+        const long long off = I.toff + 2LL * tk.f * n2;
+        tr[li] = L.trace[off + li];
+        tr[NM * NM + li] = L.trace[off + n2 + li];
       } else {
         const int lo = li - n2, no2 = tk.no * tk.no;
         tr[2 * NM * NM + lo] = L.trace[tk.ooff + lo];
@@ -596,41 +589,35 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       T1[2 * NM * QMM + j * qm + xg] = s2;
     });
     __syncthreads();
-    // P3: second pass (along face axis b): G = u, du/da, du/db, du/dn at the points
-#define C3(t) (tasks[t].valid ? tasks[t].qm * tasks[t].qm * (tasks[t].other ? 2 : 1) : 0)
-    for_items(HPDG_COUNTS(C3), [&](int t, int li) {
-      const Task& tk = tasks[t];
-      const int qm = tk.qm, qq = qm * qm;
-      const bool own = li < qq;
-      const int ns = own ? n : tk.no;
-      const int l2 = own ? li : li - qq;
-      const Map m = own ? tk.me : tk.ot;
-      const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-      const T* Mb = tab(L, 0 + 2 * m.halfB, ns, qm);
-      const T* Db = tab(L, 1 + 2 * m.halfB, ns, qm);
-      const int xg = l2 % qm, yg = l2 / qm;
-      const int rb = m.flipB ? qm - 1 - yg : yg;
-      T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-      for (int j = 0; j < ns; ++j) {
-        const T mb = Mb[rb * ns + j];
-        const T a0 = T1[j * qm + xg];
-        g0 += mb * a0;
-        g1 += mb * T1[NM * QMM + j * qm + xg];
-        g2 += Db[rb * ns + j] * a0;
-        g3 += mb * T1[2 * NM * QMM + j * qm + xg];
-      }
-      T* Gs = RB + t * rbS + (own ? 0 : 4 * QMM * QMM);
-      Gs[l2] = g0;
-      Gs[QMM * QMM + l2] = g1;
-      Gs[2 * QMM * QMM + l2] = g2;
-      Gs[3 * QMM * QMM + l2] = g3;
-    });
-    __syncthreads();
-    // P4: SIPG flux at the mortar points for the own side (in the own frame)
+    // P3+P4: second pass (along face axis b) of both sides at one mortar point: u, du/da,
+    // du/db, du/dn; then the SIPG flux there (own side, own frame) into RB
 #define C4(t) (tasks[t].valid ? tasks[t].qm * tasks[t].qm : 0)
     for_items(HPDG_COUNTS(C4), [&](int t, int li) {
       const Task& tk = tasks[t];
       const int qm = tk.qm, qq = qm * qm, side = tk.side;
+      // side values at the point with index l2 of that side's frame
+      auto at_point = [&](bool own, int l2, T& v0, T& v1, T& v2, T& v3) {
+        const int ns = own ? n : tk.no;
+        const Map m = own ? tk.me : tk.ot;
+        const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
+        const T* Mb = tab(L, 0 + 2 * m.halfB, ns, qm);
+        const T* Db = tab(L, 1 + 2 * m.halfB, ns, qm);
+        const int xg = l2 % qm, yg = l2 / qm;
+        const int rb = m.flipB ? qm - 1 - yg : yg;
+        T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+        for (int j = 0; j < ns; ++j) {
+          const T mb = Mb[rb * ns + j];
+          const T a0 = T1[j * qm + xg];
+          g0 += mb * a0;
+          g1 += mb * T1[NM * QMM + j * qm + xg];
+          g2 += Db[rb * ns + j] * a0;
+          g3 += mb * T1[2 * NM * QMM + j * qm + xg];
+        }
+        v0 = g0;
+        v1 = g1;
+        v2 = g2;
+        v3 = g3;
+      };
       const int npts = tk.gmode ? qq : 1;
       const T* mg = L.mgeo + tk.geo;
       const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
@@ -648,9 +635,9 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       const T ma = mg[(3 * side + t0) * npts + pp];
       const T mb = mg[(3 * side + t1) * npts + pp];
       const T mn = mg[(3 * side + d) * npts + pp];
-      const T* Gm = RB + t * rbS;
-      const T u_me = Gm[li];
-      const T g_me = ma * Gm[QMM * QMM + li] + mb * Gm[2 * QMM * QMM + li] + mn * Gm[3 * QMM * QMM + li];
+      T u_me, ga, gb, gn;
+      at_point(true, li, u_me, ga, gb, gn);
+      const T g_me = ma * ga + mb * gb + mn * gn;
       T Af, Bc;
       if (tk.interior) {
         T u_o = 0, g_o = 0;
@@ -658,12 +645,10 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
           const int os = 1 - side, od = tk.of >> 1;
           const int ot0 = od == 0 ? 1 : 0, ot1 = od == 2 ? 1 : 2;
           const int xo = tk.ot.swap ? dd : cc, yo = tk.ot.swap ? cc : dd;
-          const int oi = xo + qm * yo;
-          const T* Go = Gm + 4 * QMM * QMM;
-          u_o = Go[oi];
-          g_o = mg[(3 * os + ot0) * npts + pp] * Go[QMM * QMM + oi] +
-                mg[(3 * os + ot1) * npts + pp] * Go[2 * QMM * QMM + oi] +
-                mg[(3 * os + od) * npts + pp] * Go[3 * QMM * QMM + oi];
+          T oa, ob, on;
+          at_point(false, xo + qm * yo, u_o, oa, ob, on);
+          g_o = mg[(3 * os + ot0) * npts + pp] * oa + mg[(3 * os + ot1) * npts + pp] * ob +
+                mg[(3 * os + od) * npts + pp] * on;
         }
         const T jmp = u_me - u_o;
         Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
@@ -672,7 +657,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
         Af = wS * (sig * u_me - g_me);
         Bc = -wS * u_me;
       }
-      T* CF = RA + t * raS;
+      T* CF = RB + t * rbS;
       CF[li] = Af;
       CF[QMM * QMM + li] = Bc * ma;
       CF[2 * QMM * QMM + li] = Bc * mb;
@@ -686,7 +671,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       const int qm = tk.qm;
       const T* Ma = tab(L, 0 + 2 * tk.me.halfA, n, qm);
       const T* Da = tab(L, 1 + 2 * tk.me.halfA, n, qm);
-      const T* CF = RA + t * raS;
+      const T* CF = RB + t * rbS;
       const int i = li % n, yg = li / n;
       T s1 = 0, s2 = 0, s3 = 0;
       for (int xg = 0; xg < qm; ++xg) {
@@ -697,7 +682,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
         s2 += ma * CF[2 * QMM * QMM + g];
         s3 += ma * CF[3 * QMM * QMM + g];
       }
-      T* S = RB + t * rbS;
+      T* S = RA + t * raS;
       S[li] = s1;  // [y][i]
       S[QMM * NM + li] = s2;
       S[2 * QMM * NM + li] = s3;
@@ -710,7 +695,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       const int qm = tk.qm;
       const T* Mb = tab(L, 0 + 2 * tk.me.halfB, n, qm);
       const T* Db = tab(L, 1 + 2 * tk.me.halfB, n, qm);
-      const T* S = RB + t * rbS;
+      const T* S = RA + t * raS;
       const int i = li % n, j = li / n;
       T yf = 0, yn = 0;
       for (int yg = 0; yg < qm; ++yg) {
@@ -727,13 +712,11 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   // face sums -> element: values on the face layer, normal-derivative part along the lines
 #undef C1
 #undef C2
-#undef C3
 #undef C4
 #undef C5
 #undef C6
-  for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) {
+  auto finish = [&](int idx, T acc) {
     const int c0 = idx % n, c1 = (idx / n) % n, c2 = idx / n2;
-    T acc = sy[idx];
 #pragma unroll
     for (int f = 0; f < kFaces; ++f) {
       if (I.fcnt[f] == 0) continue;
@@ -745,6 +728,13 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       if (kd == ((f & 1) ? n - 1 : 0)) acc += Yf[f * NM * NM + li];
     }
     y[I.off + idx] = acc;
+  };
+  if constexpr (COMPACT) {  // node threadIdx.x + it kThreads of this thread
+#pragma unroll
+    for (int it = 0; it < 2; ++it)
+      if (int(threadIdx.x) + it * kThreads < n3) finish(int(threadIdx.x) + it * kThreads, syr[it]);
+  } else {
+    for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) finish(idx, sy[idx]);
   }
 }
 
@@ -805,12 +795,12 @@ void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const
                          const T* x, T* y, hipStream_t s) {
   if (count == 0) return;
   const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
-  // the uniform kernels of degree n with n^3 <= 2 kThreads use the compact layout
-  const size_t lds_u = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), n * n * n <= 2 * kThreads);
+  // the fixed-degree kernels of degree n with n^3 <= 2 kThreads use the compact layout
+  const size_t lds_c = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), n * n * n <= 2 * kThreads);
 #define HPDG_CASE(NN, QQ)                                                                      \
   if (n == NN && q == QQ)                                                                       \
-    return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds_u, s)             \
-                   : launch_fixed<T, NN, QQ, false>(L, elems, count, x, y, lds, s);
+    return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds_c, s)             \
+                   : launch_fixed<T, NN, QQ, false>(L, elems, count, x, y, lds_c, s);
   HPDG_CASE(2, 2) HPDG_CASE(2, 3) HPDG_CASE(3, 3) HPDG_CASE(3, 4) HPDG_CASE(4, 4) HPDG_CASE(4, 5)
   HPDG_CASE(5, 5) HPDG_CASE(5, 6) HPDG_CASE(6, 6) HPDG_CASE(6, 7) HPDG_CASE(7, 7) HPDG_CASE(7, 8)
   HPDG_CASE(8, 8) HPDG_CASE(8, 9)
