@@ -65,12 +65,26 @@ def measured_traffic(kernel, alg_bytes):
     return None if v is None else float(v)
 
 
-def summarize_trace(stats_csv, out_md, command):
-    """Top kernels of a rocprofv3 kernel-stats table as markdown (name, calls, total, mean)."""
+def summarize_trace(stats_csv, out_md, command, trace_csv=None):
+    """Top kernels of a rocprofv3 kernel-stats table as markdown (name, calls, total, mean), and
+    from the per-dispatch trace (optional) the mean duration of each kernel's fine-level
+    dispatches (those with its largest grid)."""
     import csv
 
     with open(stats_csv) as fh:
         rows = list(csv.DictReader(fh))
+    fine = {}
+    if trace_csv:
+        per = {}
+        with open(trace_csv) as fh:
+            for r in csv.DictReader(fh):
+                g = (int(r["Grid_Size"]) if r.get("Grid_Size") else
+                     int(r["Grid_Size_X"]) * int(r["Grid_Size_Y"]) * int(r["Grid_Size_Z"]))
+                per.setdefault(r["Kernel_Name"], []).append((g, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])))
+        for name, v in per.items():
+            g = max(x[0] for x in v)
+            d = [x[1] for x in v if x[0] == g]
+            fine[name] = (g, len(d), float(np.mean(d)))
     total = sum(float(r["TotalDurationNs"]) for r in rows)
     rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
     lines = ["# rocprofv3 kernel trace", "", "Command (from the repository root, on one MI355X):", "",
@@ -81,6 +95,15 @@ def summarize_trace(stats_csv, out_md, command):
         lines.append("| `%s` | %s | %.2f | %.1f%% | %.1f | %.1f | %.1f |" % (
             name[:90], r["Calls"], float(r["TotalDurationNs"]) / 1e6, 100 * float(r["TotalDurationNs"]) / total,
             float(r["AverageNs"]) / 1e3, float(r["MinNs"]) / 1e3, float(r["MaxNs"]) / 1e3))
+    if fine:
+        lines += ["", "Fine-level dispatches (each kernel's largest grid, from the per-dispatch trace):", "",
+                  "| kernel | grid (threads) | dispatches | mean us |", "|---|---|---|---|"]
+        top = [r["Name"] for r in rows[:8]]
+        for nm in top:
+            if nm in fine:
+                g, c, m = fine[nm]
+                name = nm.split("(hpdg::")[0].replace("void hpdg::(anonymous namespace)::", "").replace("|", "/")
+                lines.append("| `%s` | %d | %d | %.1f |" % (name[:90], g, c, m / 1e3))
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -91,12 +114,16 @@ def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, kernel
     each scaled by the same counter on a 1 GiB device copy, written as a text summary."""
     import csv
 
-    def per_kernel(path):
-        acc = {}
+    def per_kernel(path, fine_only=False):
+        # fine_only: only the dispatches with the kernel's largest grid (the finest level)
+        rows = {}
         with open(path) as fh:
             for r in csv.DictReader(fh):
-                name = r["Kernel_Name"]
-                acc.setdefault(name, []).append(float(r["Counter_Value"]) * 1024.0)
+                rows.setdefault(r["Kernel_Name"], []).append((int(r["Grid_Size"]), float(r["Counter_Value"]) * 1024.0))
+        acc = {}
+        for name, v in rows.items():
+            g = max(x[0] for x in v)
+            acc[name] = [x[1] for x in v if x[0] == g or not fine_only]
         return acc
 
     def copy_value(path):
@@ -105,9 +132,10 @@ def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, kernel
 
     sf = COPY_BYTES / copy_value(cal_fetch_csv)
     sw = COPY_BYTES / copy_value(cal_write_csv)
-    fa, wa = per_kernel(fetch_csv), per_kernel(write_csv)
-    lines = ["# HBM traffic per launch: rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch),",
-             "# scaled by the counters read on a 1 GiB device-to-device copy",
+    fa, wa = per_kernel(fetch_csv, True), per_kernel(write_csv, True)
+    lines = ["# HBM traffic per fine-level launch (the kernel's dispatches with the largest grid):",
+             "# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the counters read",
+             "# on a 1 GiB device-to-device copy",
              "fetch_scale: %.6f" % sf, "write_scale: %.6f" % sw,
              "sources_sha256: %s" % kernel_sources_sha256()]
     for k in kernels:
@@ -182,8 +210,9 @@ def main():
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH", "CAL_WRITE"),
                     help="write the HBM traffic summary from rocprofv3 --pmc counter CSVs")
-    ap.add_argument("--summarize-trace", nargs=3, metavar=("KERNEL_STATS_CSV", "OUT_MD", "COMMAND"),
-                    help="write a markdown summary of a rocprofv3 --kernel-trace --stats table")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
+                    help="KERNEL_STATS_CSV OUT_MD COMMAND [KERNEL_TRACE_CSV]: write a markdown summary of a "
+                         "rocprofv3 --kernel-trace --stats run")
     args = ap.parse_args()
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
@@ -312,6 +341,10 @@ def main():
                              "per_level_avg_us": [round(1e3 * e[0] / e[1], 2) if e[1] else None for e in t64[kind]]}
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
     K = kernels[dom]
+    # roofline of the dominant kernel on the finest level (its largest launches)
+    msR, nR, bR = t64[dom][0]
+    R_us, R_bytes = 1e3 * msR / nR, bR / nR
+    R_gbs = R_bytes / (R_us * 1e-6) / 1e9
     ms0, n0, b0 = t64["apply"][0]
     ms0_32, n0_32, b0_32 = t32["apply"][0]
     apply_ms64 = ms0 / n0
@@ -355,12 +388,11 @@ def main():
                   "gbs_f64": b0 / (ms0 * 1e-3) / 1e9,
                   "gbs_f32": b0_32 / (ms0_32 * 1e-3) / 1e9 if n0_32 else None},
         "kernels_f64_solve": kernels,
-        "roofline": {"bound": "hbm", "achieved": round(K["gbs"], 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(K["gbs"] / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(K["kernel"], K["alg_bytes_per_launch"])
-                     if args.workload == "shell" else None,
-                     "kernel": K["kernel"], "avg_launch_us": round(K["avg_launch_us"], 2),
-                     "alg_bytes_per_launch": round(K["alg_bytes_per_launch"])},
+        "roofline": {"bound": "hbm", "achieved": round(R_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(R_gbs / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic(K["kernel"], R_bytes) if args.workload == "shell" else None,
+                     "kernel": K["kernel"], "level": "finest", "avg_launch_us": round(R_us, 2),
+                     "alg_bytes_per_launch": round(R_bytes)},
     }
     if not args.no_cpu:
         n_lin = float(np.mean(iters))
