@@ -230,3 +230,34 @@ def test_budget_admission(ctx):
         small.upload(maker())
     assert ei.value.code == hp.ERR_OOM
     small.close()
+
+
+def test_coarse_level_too_large_for_dense_solve(ctx):
+    # one level of 82,944 DOF: its dense matrix has more than 2^31 entries
+    with pytest.raises(hp.HpdgError) as ei:
+        ctx.upload(meshgen.cubed_sphere_shell(level=2, p=5), max_levels=1)
+    assert ei.value.code == hp.ERR_UNSUPPORTED
+
+
+def test_coarse_chebyshev_degree(ctx):
+    # fewer Chebyshev steps below the finest level: a different V-cycle, same converged solution
+    maker, prob = MESHES["shell_l2_p3_r1e3"]
+    m = maker()
+    M = ctx.upload(m)
+    M.setup_smoother(n_cheb=4, smoother="block")
+    r = dev(np.random.default_rng(5).standard_normal(M.n_dof[0]))
+    z1, z2 = torch.zeros_like(r), torch.zeros_like(r)
+    M.vcycle(r, z1)
+    M.setup_smoother(n_cheb=4, smoother="block", n_cheb_coarse=2, lambda_max=M.lambda_max)
+    M.vcycle(r, z2)
+    assert not torch.equal(z1, z2)
+    F = torch.zeros_like(r)
+    M.assemble_rhs(prob, F)
+    u = torch.zeros_like(F)
+    st = M.solve(F, u, tol=5e-11, max_iter=400)
+    op = SIPG(m, prob)
+    Fo = op.rhs()
+    res = np.linalg.norm(Fo - op.apply(host(u))) / np.linalg.norm(Fo)
+    print("n_cheb_coarse=2", st, "oracle residual", res, flush=True)
+    assert res <= 1e-10
+    M.free()
