@@ -322,6 +322,7 @@ typedef struct {
   double submit_ms, start_ms, end_ms;  /* host clock, ms since the server was created */
   size_t device_bytes;         /* admitted footprint */
   int64_t n_dof;
+  char message[200];           /* FAILED: the error text (NUL-terminated, possibly cut) */
 } hpdg_request_status;
 
 int hpdg_server_create(hpdg_ctx* ctx, const hpdg_server_params* params, hpdg_server** out);

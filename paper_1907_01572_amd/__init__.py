@@ -94,7 +94,8 @@ class Request(ctypes.Structure):
 class RequestStatus(ctypes.Structure):
     _fields_ = [("state", ctypes.c_int32), ("status", ctypes.c_int32), ("iterations", ctypes.c_int32),
                 ("rel_residual", ctypes.c_double), ("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
-                ("end_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t), ("n_dof", ctypes.c_int64)]
+                ("end_ms", ctypes.c_double), ("device_bytes", ctypes.c_size_t), ("n_dof", ctypes.c_int64),
+                ("message", ctypes.c_char * 200)]
 
 
 class NonlinearDesc(ctypes.Structure):
@@ -276,7 +277,8 @@ class Server:
     def _status(st):
         return dict(state=REQ_STATES[st.state], status=st.status, iterations=st.iterations,
                     rel_residual=st.rel_residual, submit_ms=st.submit_ms, start_ms=st.start_ms,
-                    end_ms=st.end_ms, device_bytes=int(st.device_bytes), n_dof=int(st.n_dof))
+                    end_ms=st.end_ms, device_bytes=int(st.device_bytes), n_dof=int(st.n_dof),
+                    message=st.message.decode(errors="replace"))
 
     def poll(self, ticket):
         st = RequestStatus()

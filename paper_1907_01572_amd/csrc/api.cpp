@@ -10,6 +10,7 @@
 #include <rocsolver/rocsolver.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <limits>
 #include <chrono>
 #include <cmath>
@@ -126,7 +127,8 @@ struct hpdg_mesh {
   };
   std::vector<long long> block_scalars = std::vector<long long>(32, 0);  // packed inverse-block scalars per level
   std::vector<long long> block_full_scalars = std::vector<long long>(32, 0);  // full-block scalars per level
-  int block_retries = 0;  // block factorisations repeated after a failed attempt
+  int block_retries = 0;   // block factorisations repeated after a failed attempt
+  int coarse_retries = 0;  // coarse factorisations repeated after a failed attempt
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
   Acc acc[HPDG_TIMING_KINDS][32][2];
@@ -657,7 +659,21 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
 // exact coarse solve: the coarsest operator assembled column by column on the device (one
 // apply per unit vector), symmetrised, factorised (Cholesky) and inverted with rocSOLVER;
 // the explicit inverse is applied as a dense mat-vec in the V-cycle
+void build_coarse_once(hpdg_mesh* M, hipStream_t s);
 void build_coarse(hpdg_mesh* M, hipStream_t s) {
+  // the operator is SPD: a failed factorisation that does not repeat on a fresh assembly is not
+  // a property of the operator (as for the element blocks); a repeated one is an error
+  for (int attempt = 0;; ++attempt) {
+    try {
+      build_coarse_once(M, s);
+      return;
+    } catch (const Error& err) {
+      if (attempt >= 1 || err.code != HPDG_ERR_BREAKDOWN) throw;
+      M->coarse_retries += 1;
+    }
+  }
+}
+void build_coarse_once(hpdg_mesh* M, hipStream_t s) {
   const int L = M->nlevels() - 1;
   if (M->H[L].ndof * M->H[L].ndof > (long long)std::numeric_limits<rocblas_int>::max())
     throw Error(HPDG_ERR_UNSUPPORTED, "the coarsest level has " + std::to_string(M->H[L].ndof) +
@@ -1134,6 +1150,7 @@ struct hpdg_server {
     int iters = 0;
     double rel = 0;
     int rc = HPDG_OK;
+    std::string msg;
     try {
       std::unique_ptr<hpdg_mesh> M = host_tables(r);
       upload_mesh_device(M.get(), s);
@@ -1152,10 +1169,19 @@ struct hpdg_server {
       r->st.n_dof = n;
     } catch (const Error& e) {
       rc = e.code;
+      msg = e.what();
+    } catch (const std::exception& e) {
+      rc = HPDG_ERR_INVALID_ARG;
+      msg = e.what();
     } catch (...) {
       rc = HPDG_ERR_INVALID_ARG;
+      msg = "unknown error";
     }
     std::lock_guard<std::mutex> lock(mu);
+    if (rc != HPDG_OK) {
+      if (msg.empty()) msg = "error " + std::to_string(rc);
+      std::snprintf(r->st.message, sizeof(r->st.message), "%s", msg.c_str());
+    }
     r->st.iterations = iters;
     r->st.rel_residual = rel;
     r->st.status = rc;
@@ -1612,6 +1638,7 @@ int hpdg_server_destroy(hpdg_server* sv) {
       ServerRequest* r = sv->reqs[t].get();
       r->st.state = HPDG_REQ_FAILED;
       r->st.status = HPDG_ERR_INVALID_ARG;
+      std::snprintf(r->st.message, sizeof(r->st.message), "%s", "server destroyed before the request ran");
     }
     sv->queue.clear();
   }
