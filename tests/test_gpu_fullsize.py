@@ -10,7 +10,8 @@ benchmark (FP64 level 0, FP32 copies built).
   solve reaches 1e-10 (true residual by an FP64 apply) with its sampled residual rows
   matching the oracle's;
 * puncture mesh, p = 6, 12,739,363 DOF: nonlinear residual rows and, after
-  linearisation, Jacobian rows.
+  linearisation, Jacobian rows;
+* the shell's first coarse level (1,056 cells): operator rows.
 """
 import numpy as np
 import pytest
@@ -144,4 +145,27 @@ def test_fullsize_puncture_residual_and_jacobian_rows(ctx):
     e_jac = rel_rows(host(y), op.apply(v), rows)
     print("puncture sampled rows: residual", e_res, "Jacobian", e_jac, flush=True)
     assert e_res <= TOL_APPLY_R1E11 and e_jac <= TOL_APPLY_R1E11
+    M.free()
+
+
+def test_fullsize_shell_level1_apply_rows(ctx):
+    # level 1 of the shell (1,056 cells at p = 5), the first coarse level of the bench's V-cycle,
+    # against the oracle on the same coarse cells
+    m, prob = meshgen.cubed_sphere_shell(level=3, p=5), meshgen.problem_config2()
+    M = ctx.upload(m, coef=coef_of(prob), build_f32=True, max_levels=4)
+    cells = M.level_cells(1)
+    m1 = dict(m)
+    for k in ("elem_macro", "elem_level", "elem_anchor", "elem_p"):
+        m1[k] = np.ascontiguousarray(cells[k])
+    elems = _sample(len(m1["elem_p"]), 3)
+    op = SIPG(m1, prob, active=elems)
+    assert op.ndof == M.n_dof[1]
+    x = np.random.default_rng(4).standard_normal(op.ndof)
+    xd = torch.tensor(x, device="cuda")
+    y = torch.zeros_like(xd)
+    M.apply(xd, y, level=1)
+    rows = sample_rows(op, elems)
+    err = rel_rows(host(y), op.apply(x), rows)
+    print("shell level 1:", len(m1["elem_p"]), "cells, sampled rows FP64", err, flush=True)
+    assert err <= TOL_APPLY_COMPACTIFIED
     M.free()
