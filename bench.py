@@ -194,6 +194,8 @@ def main():
     ap.add_argument("--max-active", type=int, default=8, help="serving: requests in flight")
     ap.add_argument("--arrival-factor", type=float, default=2.0,
                     help="serving: Poisson arrival rate as a multiple of the FP64 sequential capacity")
+    ap.add_argument("--solver", choices=["fcg", "fgmres"], default="fcg",
+                    help="outer Krylov solver of the linear solves (fgmres: restarted flexible GMRES, 30)")
     ap.add_argument("--n-cheb", type=int, default=0, help="0: the workload's default")
     ap.add_argument("--n-cheb-coarse", type=int, default=-1,
                     help="Chebyshev steps on the levels below the finest; -1: the workload's default")
@@ -281,7 +283,8 @@ def main():
             st = M.newton_solve(W["nl"], u, tol=1e-10, lin_tol=1e-6, max_lin_iter=args.max_iter, precision=prec)
             st["iterations"] = st["linear_iterations"]
             return st
-        return M.solve(F, u, tol=1e-10, max_iter=args.max_iter, precision=prec)
+        return M.solve(F, u, tol=1e-10, max_iter=args.max_iter, precision=prec,
+                       solver=hp.SOLVER_FGMRES if args.solver == "fgmres" else hp.SOLVER_FCG)
 
     for _ in range(args.warmup):
         solve(hp.PREC_F64)
@@ -378,7 +381,7 @@ def main():
                    "elements": M.n_elem[0], "dof": N, "levels": M.n_levels, "level_dof": list(M.n_dof),
                    "n_cheb": W["smoother"]["n_cheb"], "n_cheb_coarse": W["smoother"].get("n_cheb_coarse", 0),
                    "Lambda": W["smoother"]["Lambda"],
-                   "smoother": W["smoother"]["smoother"]},
+                   "smoother": W["smoother"]["smoother"], "solver": args.solver},
         "solve": solve_info,
         "mixed": mixed_info,
         "mixed_bf16_blocks": bf16_info,

@@ -61,7 +61,12 @@ enum { HPDG_COEF_CONSTANT = 0, HPDG_COEF_RADIAL_STEP = 1 };
 enum { HPDG_RHS_SINSINSIN = 0, HPDG_RHS_SHELL_HARMONIC = 1, HPDG_RHS_RADIAL_STEP = 2,
        HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4, HPDG_RHS_POLYNOMIAL_DIRICHLET = 5 };
 enum { HPDG_NL_PUNCTURE = 0, HPDG_NL_QUADRATIC = 1 };
-enum { HPDG_SOLVER_FCG = 0, HPDG_SOLVER_PCG = 1 };
+/* Outer Krylov solvers, each preconditioned by one V-cycle per iteration: flexible CG
+ * (Alg. 2), textbook PCG, and restarted flexible GMRES (right preconditioned: the
+ * preconditioned directions are kept, so the V-cycle may vary between iterations, e.g. in
+ * FP32; modified Gram-Schmidt, Givens rotations; the residual is recomputed as b - A u at
+ * every restart and at exit). */
+enum { HPDG_SOLVER_FCG = 0, HPDG_SOLVER_PCG = 1, HPDG_SOLVER_FGMRES = 2 };
 
 typedef struct hpdg_ctx hpdg_ctx;
 typedef struct hpdg_mesh hpdg_mesh;
@@ -161,10 +166,12 @@ typedef struct {
 } hpdg_smoother_params;
 
 typedef struct {
-  int32_t solver;        /* HPDG_SOLVER_FCG (Alg. 2) or HPDG_SOLVER_PCG */
+  int32_t solver;        /* HPDG_SOLVER_FCG (Alg. 2), HPDG_SOLVER_PCG or HPDG_SOLVER_FGMRES */
   int32_t precision;     /* HPDG_PREC_F64 or HPDG_PREC_MIXED (FP32 V-cycle) */
   double tol_rel;        /* stop when |b - A u|_2 <= tol_rel |b|_2 */
-  int32_t max_iter;
+  int32_t max_iter;      /* iterations (one V-cycle and one apply each) */
+  int32_t restart;       /* FGMRES: Krylov vectors per cycle (0: 30); the 2 restart + 1
+                            level-0 vectors are allocated on the first FGMRES solve of a mesh */
 } hpdg_solve_params;
 
 typedef struct {

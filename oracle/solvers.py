@@ -16,6 +16,9 @@
   a dense FP64 Cholesky factorisation (instead of being smoothed).
 * Flexible CG (Alg. 2) with r0 = b - A u0, stopping when |r|/|b| <= tol or after
   max_iter iterations; plain preconditioned CG for comparison.
+* Restarted flexible GMRES (not in the paper; the method of Saad, SIAM J. Sci. Comput. 14,
+  1993): right preconditioning with the preconditioned directions kept, so the
+  preconditioner may change between iterations.
 """
 import numpy as np
 import scipy.linalg
@@ -270,4 +273,43 @@ def pcg(apply, b, precond, u0=None, tol=1e-10, max_iter=200):
         rz = rz_new
         k += 1
         hist.append(np.linalg.norm(r) / nb)
+    return u, k, hist
+
+
+def fgmres(apply, b, precond, u0=None, tol=1e-10, max_iter=200, restart=30):
+    """Restarted flexible GMRES (Saad 1993).  Each cycle builds, from r0 = b - A u0, an
+    orthonormal basis V by Arnoldi (modified Gram-Schmidt) on the preconditioned directions
+    z_j = M_j v_j, A Z = V Hbar, and takes u = u0 + Z y with y minimising |beta e1 - Hbar y|
+    (a least-squares solve); the cycle stops when that minimum is <= tol |b| or after
+    ``restart`` steps.  Returns (u, iterations, relative residuals: the least-squares value
+    after every step)."""
+    u = np.zeros_like(b) if u0 is None else u0.copy()
+    nb = np.linalg.norm(b)
+    r = b - apply(u)
+    hist = [np.linalg.norm(r) / nb]
+    k = 0
+    while hist[-1] > tol and k < max_iter:
+        beta = np.linalg.norm(r)
+        V = [r / beta]
+        Z = []
+        Hbar = np.zeros((restart + 1, restart))
+        y = np.zeros(0)
+        for j in range(restart):
+            Z.append(precond(V[j]))
+            w = apply(Z[j])
+            for i in range(j + 1):
+                Hbar[i, j] = w @ V[i]
+                w = w - Hbar[i, j] * V[i]
+            Hbar[j + 1, j] = np.linalg.norm(w)
+            V.append(w / Hbar[j + 1, j] if Hbar[j + 1, j] > 0 else w)
+            e1 = np.zeros(j + 2)
+            e1[0] = beta
+            y, *_ = np.linalg.lstsq(Hbar[:j + 2, :j + 1], e1, rcond=None)
+            k += 1
+            hist.append(np.linalg.norm(e1 - Hbar[:j + 2, :j + 1] @ y) / nb)
+            if hist[-1] <= tol or k >= max_iter or Hbar[j + 1, j] == 0:
+                break
+        u = u + np.array(Z).T @ y
+        r = b - apply(u)
+        hist[-1] = np.linalg.norm(r) / nb  # the true residual at the end of the cycle
     return u, k, hist

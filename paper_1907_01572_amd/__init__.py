@@ -19,7 +19,7 @@ ERR_INVALID_ARG, ERR_INVALID_MESH, ERR_OOM, ERR_NOT_CONVERGED, ERR_BREAKDOWN, ER
     -1, -2, -3, -4, -5, -6, -7
 F64, F32 = 0, 1
 PREC_F64, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2
-SOLVER_FCG, SOLVER_PCG = 0, 1
+SOLVER_FCG, SOLVER_PCG, SOLVER_FGMRES = 0, 1, 2
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 SMOOTHERS = {"none": 0, "point": 1, "block": 2}
 TIMING_KINDS = {"apply": 0, "block": 1}
@@ -70,7 +70,7 @@ class SmootherParams(ctypes.Structure):
 
 class SolveParams(ctypes.Structure):
     _fields_ = [("solver", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32)]
+                ("tol_rel", ctypes.c_double), ("max_iter", ctypes.c_int32), ("restart", ctypes.c_int32)]
 
 
 class SolveStats(ctypes.Structure):
@@ -374,8 +374,8 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_vcycle(self.h, prec, _ptr(r), _ptr(z), _stream(stream)))
 
     def solve(self, b, u, tol=1e-10, max_iter=200, solver=SOLVER_FCG, precision=PREC_F64, stream=None,
-              raise_on_error=True):
-        p = SolveParams(solver, precision, tol, max_iter)
+              raise_on_error=True, restart=0):
+        p = SolveParams(solver, precision, tol, max_iter, restart)
         st = SolveStats()
         rc = self.lib.hpdg_solve(self.h, ctypes.byref(p), _ptr(b), _ptr(u), ctypes.byref(st), _stream(stream))
         if raise_on_error:

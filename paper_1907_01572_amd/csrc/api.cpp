@@ -127,6 +127,9 @@ struct hpdg_mesh {
   };
   std::vector<long long> block_scalars = std::vector<long long>(32, 0);  // packed inverse-block scalars per level
   std::vector<long long> block_full_scalars = std::vector<long long>(32, 0);  // full-block scalars per level
+  double* gm_V = nullptr;  // FGMRES basis (gm_m + 1 level-0 vectors) and directions (gm_m)
+  double* gm_Z = nullptr;
+  int gm_m = 0;
   int block_retries = 0;   // block factorisations repeated after a failed attempt
   int coarse_retries = 0;  // coarse factorisations repeated after a failed attempt
   std::vector<Timed> pending;
@@ -932,6 +935,71 @@ bool krylov_solve(hpdg_mesh* mesh, const hpdg_solve_params& params, const double
       rel = std::sqrt(rr) / nb;
       ++iters;
     }
+  } else if (params.solver == HPDG_SOLVER_FGMRES) {
+    // restarted flexible GMRES: V[0..m] an orthonormal basis, Z[j] = M V[j] (kept, since
+    // the preconditioner may vary), H the (m+1) x m Hessenberg matrix reduced by Givens
+    // rotations on the host; u += Z y at the end of a cycle
+    const int m = params.restart > 0 ? params.restart : 30;
+    if (mesh->gm_m < m) {
+      if (mesh->gm_V) mesh->release(mesh->gm_V);
+      if (mesh->gm_Z) mesh->release(mesh->gm_Z);
+      mesh->gm_V = mesh->alloc<double>(size_t(m + 1) * size_t(n));
+      mesh->gm_Z = mesh->alloc<double>(size_t(m) * size_t(n));
+      mesh->gm_m = m;
+    }
+    auto V = [&](int j) { return mesh->gm_V + size_t(j) * size_t(n); };
+    auto Z = [&](int j) { return mesh->gm_Z + size_t(j) * size_t(n); };
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    auto h = [&](int i, int j) -> double& { return H[size_t(j) * (m + 1) + i]; };
+    while (rel > params.tol_rel && iters < params.max_iter) {
+      const double beta = std::sqrt(rr);
+      launch_fill<double>(n, 0.0, V(0), s);
+      launch_axpby<double>(n, 1.0 / beta, r, 0.0, V(0), s);
+      std::fill(g.begin(), g.end(), 0.0);
+      g[0] = beta;
+      int k = 0;  // columns of this cycle
+      while (k < m && iters < params.max_iter) {
+        const int j = k;
+        precond(V(j), Z(j));
+        apply_level<double>(mesh, 0, Z(j), V(j + 1), s);
+        for (int i = 0; i <= j; ++i) {  // modified Gram-Schmidt
+          h(i, j) = dot_sync(mesh, n, V(j + 1), V(i), s);
+          launch_axpby<double>(n, -h(i, j), V(i), 1.0, V(j + 1), s);
+        }
+        const double hn = std::sqrt(dot_sync(mesh, n, V(j + 1), V(j + 1), s));
+        if (!std::isfinite(hn)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite FGMRES basis vector");
+        h(j + 1, j) = hn;
+        if (hn > 0) launch_axpby<double>(n, 0.0, V(j + 1), 1.0 / hn, V(j + 1), s);
+        for (int i = 0; i < j; ++i) {  // earlier rotations on column j
+          const double a = h(i, j), b2 = h(i + 1, j);
+          h(i, j) = cs[i] * a + sn[i] * b2;
+          h(i + 1, j) = -sn[i] * a + cs[i] * b2;
+        }
+        const double den = std::hypot(h(j, j), h(j + 1, j));
+        if (!(den > 0)) throw Error(HPDG_ERR_BREAKDOWN, "FGMRES breakdown (zero column)");
+        cs[j] = h(j, j) / den;
+        sn[j] = h(j + 1, j) / den;
+        h(j, j) = den;
+        h(j + 1, j) = 0.0;
+        g[j + 1] = -sn[j] * g[j];
+        g[j] = cs[j] * g[j];
+        ++k;
+        ++iters;
+        if (std::fabs(g[j + 1]) / nb <= params.tol_rel || hn == 0.0) break;
+      }
+      for (int i = k - 1; i >= 0; --i) {  // y = R^-1 g (back substitution)
+        double t = g[i];
+        for (int l = i + 1; l < k; ++l) t -= h(i, l) * y[l];
+        y[i] = t / h(i, i);
+      }
+      for (int i = 0; i < k; ++i) launch_axpby<double>(n, y[i], Z(i), 1.0, u_dev, s);
+      apply_level<double>(mesh, 0, u_dev, mesh->w, s);  // true residual
+      launch_copy<double>(n, b_dev, r, s);
+      launch_axpby<double>(n, -1.0, mesh->w, 1.0, r, s);
+      rr = dot_sync(mesh, n, r, r, s);
+      if (!std::isfinite(rr)) throw Error(HPDG_ERR_BREAKDOWN, "non-finite residual");
+      rel = std::sqrt(rr) / nb;
+    }
   } else {
     // Alg. 2 with device-resident scalars; one host read of |r|^2 per iteration
     launch_fill<double>(16, 0.0, mesh->sc, s);
@@ -1160,7 +1228,7 @@ struct hpdg_server {
       double* u = M->alloc<double>(size_t(n));
       assemble_rhs_impl(M.get(), &r->rhs, F, s);
       launch_fill<double>(n, 0.0, u, s);
-      hpdg_solve_params sp{HPDG_SOLVER_FCG, p.precision, p.tol_rel, p.max_iter};
+      hpdg_solve_params sp{HPDG_SOLVER_FCG, p.precision, p.tol_rel, p.max_iter, 0};
       const bool ok = krylov_solve(M.get(), sp, F, u, iters, rel, s);
       if (!ok) rc = HPDG_ERR_NOT_CONVERGED;
       HIPCHK(hipMemcpyAsync(r->u_out, u, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1433,6 +1501,9 @@ int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b
   if (!mesh->smoother_ready) return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
   if (params->precision != HPDG_PREC_F64 && !mesh->has_f32)
     return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  if (params->solver < HPDG_SOLVER_FCG || params->solver > HPDG_SOLVER_FGMRES || params->restart < 0 ||
+      params->restart > 1000)
+    return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "unknown solver or restart length out of [0, 1000]");
   int iters = 0;
   double rel = 0;
   bool converged = true;

@@ -12,7 +12,7 @@ import pytest
 
 import meshgen
 from oracle.operator import SIPG
-from oracle.solvers import Multigrid, chebyshev
+from oracle.solvers import Multigrid, chebyshev, fgmres
 from tests.gpu_common import MESHES, TOL_APPLY, TOL_APPLY_COMPACTIFIED, coef_of, dof_perm, rel
 
 torch = pytest.importorskip("torch")
@@ -260,4 +260,36 @@ def test_coarse_chebyshev_degree(ctx):
     res = np.linalg.norm(Fo - op.apply(host(u))) / np.linalg.norm(Fo)
     print("n_cheb_coarse=2", st, "oracle residual", res, flush=True)
     assert res <= 1e-10
+    M.free()
+
+
+@pytest.mark.parametrize("name,prec,restart", [
+    ("shell_l2_p3_r1e3", hp.PREC_F64, 30),
+    ("cube_l2_p3", hp.PREC_F64, 3),
+    ("hp_k", hp.PREC_MIXED, 30),
+])
+def test_fgmres_reaches_oracle_residual(ctx, name, prec, restart):
+    # restarted flexible GMRES: the solution's residual recomputed by the oracle, and (FP64,
+    # the oracle's V-cycle with the same frozen bounds) the iteration count of the oracle's
+    # flexible GMRES
+    maker, prob = MESHES[name]
+    m = maker()
+    smoother = "block" if name.startswith("shell") else "point"
+    mg = Multigrid(m, prob, n_cheb=4, smoother=smoother)
+    M = ctx.upload(m, coef=coef_of(prob), build_f32=(prec != hp.PREC_F64))
+    M.setup_smoother(n_cheb=4, smoother=smoother, lambda_max=mg.lam)
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    M.assemble_rhs(prob, F)
+    u = torch.zeros_like(F)
+    st = M.solve(F, u, tol=5e-11, max_iter=400, solver=hp.SOLVER_FGMRES, precision=prec, restart=restart)
+    op = mg.ops[0]
+    Fo = op.rhs()
+    res = np.linalg.norm(Fo - op.apply(host(u))) / np.linalg.norm(Fo)
+    msg = "%s restart %d prec %d: %s, oracle residual %.3e" % (name, restart, prec, st, res)
+    if prec == hp.PREC_F64:
+        uo, ko, hist = fgmres(op.apply, Fo, mg.vcycle, tol=5e-11, max_iter=400, restart=restart)
+        msg += ", oracle FGMRES %d iterations" % ko
+        assert abs(st["iterations"] - ko) <= 2, msg
+    print(msg, flush=True)
+    assert res <= 1e-10, msg
     M.free()

@@ -5,7 +5,7 @@ import pytest
 import meshgen
 from oracle import problems as P
 from oracle.operator import SIPG
-from oracle.solvers import (Multigrid, Transfer, cg_lanczos, chebyshev, fcg, gershgorin_max,
+from oracle.solvers import (Multigrid, Transfer, cg_lanczos, chebyshev, fcg, fgmres, gershgorin_max,
                             pcg, splitmix64_uniform)
 
 
@@ -114,3 +114,44 @@ def test_paper_literal_smoother_also_solves():
     ua, ka, _ = fcg(a.ops[0].apply, F, a.vcycle, tol=1e-11)
     ub, kb, _ = fcg(b.ops[0].apply, F, b.vcycle, tol=1e-11)
     np.testing.assert_allclose(ua, ub, atol=1e-9 * np.abs(ua).max())
+
+
+def test_fgmres_pins():
+    # flexible GMRES, pinned against properties that do not depend on its code:
+    rng = np.random.default_rng(11)
+    n = 40
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    A = Q @ np.diag(np.linspace(1.0, 50.0, n)) @ Q.T
+    b = rng.standard_normal(n)
+    exact = np.linalg.solve(A, b)
+    # (1) with a fixed preconditioner it solves the system (up to rounding)
+    Minv = np.linalg.inv(A + 0.3 * np.diag(rng.uniform(0.5, 1.5, n)))
+    u, k, hist = fgmres(lambda x: A @ x, b, lambda r: Minv @ r, tol=1e-13, max_iter=200, restart=10)
+    assert np.linalg.norm(u - exact) <= 1e-11 * np.linalg.norm(exact)
+    # (2) finite termination: without preconditioning and without restart, a matrix with 5
+    # distinct eigenvalues is solved in at most 5 steps
+    D = np.diag(np.repeat([1.0, 2.0, 3.0, 5.0, 8.0], 8))
+    u, k, hist = fgmres(lambda x: D @ x, b, lambda r: r, tol=1e-12, max_iter=100, restart=50)
+    assert k <= 5 and np.allclose(u, b / np.diag(D), rtol=1e-10, atol=0)
+    # (3) within a cycle the minimised residual does not grow
+    u, k, hist = fgmres(lambda x: A @ x, b, lambda r: r, tol=1e-12, max_iter=30, restart=30)
+    assert all(hist[i + 1] <= hist[i] * (1 + 1e-12) for i in range(len(hist) - 2))
+    # (4) flexible: a preconditioner that changes at every call (two alternating SPD
+    # approximate inverses) still converges to the solution
+    M1, M2 = np.diag(1.0 / np.diag(A)), Minv
+    calls = [0]
+
+    def varying(r):
+        calls[0] += 1
+        return (M1 if calls[0] % 2 else M2) @ r
+    u, k, hist = fgmres(lambda x: A @ x, b, varying, tol=1e-12, max_iter=200, restart=8)
+    assert np.linalg.norm(A @ u - b) <= 1e-11 * np.linalg.norm(b)
+    # (5) a planted error in a copy of the oracle (a Gram-Schmidt sign flipped) fails (1)
+    import inspect
+
+    import oracle.solvers as solvers
+    src = inspect.getsource(solvers.fgmres).replace("w = w - Hbar[i, j] * V[i]", "w = w + Hbar[i, j] * V[i]")
+    ns = {"np": np}
+    exec(src, ns)
+    u, k, hist = ns["fgmres"](lambda x: A @ x, b, lambda r: Minv @ r, tol=1e-13, max_iter=200, restart=10)
+    assert np.linalg.norm(u - exact) > 1e-6 * np.linalg.norm(exact)
