@@ -35,11 +35,11 @@ Conventions (the neutral mesh format, documented once here):
 """
 from .forest import Forest, orient_map_int, face_corner_orientation  # noqa: F401
 from .meshes import (  # noqa: F401
-    unit_cube, box_grid, cubed_sphere_shell, hp_sphere_cube, puncture_mesh,
+    unit_cube, box_grid, cubed_sphere_shell, hp_sphere_cube, puncture_mesh, star_mesh,
     mesh_summary,
 )
 from .problems import (  # noqa: F401
     problem_config1, problem_config2, problem_config3, random_vector,
     dof_count, polynomial_problem, gaussian_problem, polynomial_dirichlet_problem,
-    puncture_problem, quadratic_nonlinear_problem,
+    puncture_problem, quadratic_nonlinear_problem, star_problem,
 )

@@ -88,6 +88,16 @@ def box_grid(macros=(1, 1, 1), level=0, p=3, lo=(0.0, 0.0, 0.0), hi=(1.0, 1.0, 1
                    dict(name="box", cell_bounds=None))
 
 
+def star_mesh(level=2, p=4, r0=1.0, refine_near=1):
+    """The constant-density star's domain (Sec. III.B): the cube [-8 r0, 8 r0]^3, one affine
+    macro refined uniformly to ``level``, then ``refine_near`` times more in the cells that
+    come within 1.5 r0 of the centre while wider than r0 / 2 (2:1 balanced); degree p,
+    Dirichlet faces."""
+    def near(key, c0, c1):
+        return np.linalg.norm(np.clip(0.0, c0, c1)) <= 1.5 * r0 and (c1 - c0).max() > 0.5 * r0
+    return box_grid((1, 1, 1), level, p, lo=(-8.0 * r0,) * 3, hi=(8.0 * r0,) * 3, refine=[near] * refine_near)
+
+
 def unit_cube(level=2, p=3):
     """Unit cube, one affine macro refined uniformly to ``level`` (config 1 at level 2, p 3)."""
     m = box_grid((1, 1, 1), level, p)

@@ -104,6 +104,14 @@ def quadratic_nonlinear_problem(alpha=0.5, seed=0):
     return dict(kind="nl_quadratic", params=np.concatenate([[alpha], C.reshape(-1)])), C
 
 
+def star_problem(rho0=0.001, r0=1.0):
+    """Constant-density star (Sec. III.B): -lap psi = 2 pi rho psi^5 with rho = rho0 inside
+    r <= r0 and 0 outside; Dirichlet data from the closed-form psi.  Returns the nonlinear
+    source and the Dirichlet-data descriptors (both kind "star", params [rho0, r0])."""
+    p = np.array([rho0, r0], float)
+    return dict(kind="star", params=p.copy()), dict(kind="star", params=p.copy())
+
+
 def dof_count(mesh):
     return int(np.sum((mesh["elem_p"].astype(np.int64) + 1) ** 3))
 

@@ -19,6 +19,10 @@ the coefficient c is evaluated at each level's own GL points, and the smoother s
 spectral bounds and coarse factorisation are recomputed for every Newton step.
 
 Each level's volume rule uses q = p + 1 + quad_extra points (a mass term is present).
+
+The constant-density star (Sec. III.B, Eq. Constant_Density_Star_PDE) is the same solve with
+N(psi)_v = sum_sigma w det J 2 pi rho psi^5 v (rho = rho0 inside r0, 0 outside) and the
+Jacobian mass coefficient c = -5 (2 pi rho) psi^4 (problems.nl_terms).
 """
 import numpy as np
 
@@ -94,9 +98,8 @@ class NewtonSolver:
         op = self.ops[0]
         N = np.zeros(op.ndof)
         for g in op.vgroups:
-            s = 1.0 + g["alpha"] * _gl_values(g, u)
-            self._check(s)
-            N[g["idx"]] += _project(g, g["W"] * g["det"] * g["beta"] * s ** -7)
+            val, _ = problems.nl_terms(self.nl, g["alpha"], g["beta"], _gl_values(g, u))
+            N[g["idx"]] += _project(g, g["W"] * g["det"] * val)
         return N
 
     def apply_A(self, u):
@@ -120,9 +123,7 @@ class NewtonSolver:
             if lvl > 0:
                 ul = inject(self.ops[lvl - 1], op, ul)
             for g in op.vgroups:
-                s = 1.0 + g["alpha"] * _gl_values(g, ul)
-                self._check(s)
-                c = 7.0 * g["alpha"] * g["beta"] * s ** -8
+                _, c = problems.nl_terms(self.nl, g["alpha"], g["beta"], _gl_values(g, ul))
                 g["M"] = g["W"] * g["det"] * c
         self.mg.refresh(self.n_eigs, self.seed)
 

@@ -49,7 +49,47 @@ def exact_u(problem, x):
         return np.zeros(x.shape[:-1])  # only used as Dirichlet data (g_D = 0)
     if kind == "polynomial_dirichlet":
         return exact_u(dict(kind="polynomial", params=problem["params"]), x)
+    if kind == "star":
+        rho0, r0 = problem["params"][:2]
+        return star_psi(rho0, r0, np.linalg.norm(x, axis=-1))
     raise ValueError(kind)
+
+
+def star_parameters(rho0, r0):
+    """Constant-density star (Sec. III.B): C = (2 pi rho0 / 3)^(-1/4), beta = r0 (C u_alpha(r0) - 1),
+    and alpha from the continuity of psi and dpsi/dr at r0, which gives
+    rho0 r0^2 = (3 / (2 pi)) alpha^10 / (1 + alpha^2)^6 (the printed exponent 3 does not make
+    dpsi/dr continuous).  The right side rises to its maximum at alpha^2 = 5 and then falls;
+    the root taken is the one on the falling branch, alpha >= sqrt(5), where psi -> 1 as
+    rho0 -> 0 (the weak-field star), found by bisection."""
+    C = (2.0 * np.pi * rho0 / 3.0) ** -0.25
+    target = rho0 * r0 * r0
+
+    def f(a):
+        return 3.0 / (2.0 * np.pi) * a ** 10 / (1.0 + a * a) ** 6 - target
+
+    lo = np.sqrt(5.0)
+    if f(lo) < 0:
+        raise ValueError("rho0 r0^2 above the largest value a static star allows")
+    hi = 2.0 * lo
+    while f(hi) > 0:
+        hi *= 2.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        lo, hi = (mid, hi) if f(mid) > 0 else (lo, mid)
+    alpha = 0.5 * (lo + hi)
+    u_r0 = np.sqrt(alpha * r0) / np.sqrt(r0 * r0 + (alpha * r0) ** 2)
+    return C, alpha, r0 * (C * u_r0 - 1.0)
+
+
+def star_psi(rho0, r0, r):
+    """psi(r) of the constant-density star: C u_alpha(r) inside r0, beta / r + 1 outside."""
+    C, alpha, beta = star_parameters(rho0, r0)
+    r = np.asarray(r, float)
+    inside = C * np.sqrt(alpha * r0) / np.sqrt(r * r + (alpha * r0) ** 2)
+    with np.errstate(divide="ignore"):
+        outside = beta / r + 1.0
+    return np.where(r <= r0, inside, outside)
 
 
 def source_g(problem, x):
@@ -79,6 +119,9 @@ def source_g(problem, x):
                     if c >= 2:
                         g -= C[a, b, c] * c * (c - 1) * X ** a * Y ** b * Z ** (c - 2)
         return g
+    if kind == "star":
+        # the density term is the nonlinear source of the Newton solve; no linear source
+        return np.zeros(x.shape[:-1])
     if kind == "gaussians":
         rows = np.asarray(problem["params"]).reshape(-1, 5)
         g = np.zeros(x.shape[:-1])
@@ -128,4 +171,21 @@ def nl_alpha_beta(nl, x):
         poly = dict(kind="polynomial", params=P[1:])
         u = exact_u(poly, x)
         return np.full(x.shape[:-1], alpha), source_g(poly, x) * (1.0 + alpha * u) ** 7
+    if kind == "star":
+        # -lap psi = 2 pi rho psi^5 (Sec. III.B): alpha is unused, beta = 2 pi rho(x)
+        rho0, r0 = P[:2]
+        r = np.linalg.norm(x, axis=-1)
+        return np.zeros(x.shape[:-1]), np.where(r <= r0, 2.0 * np.pi * rho0, 0.0)
     raise ValueError(kind)
+
+
+def nl_terms(nl, alpha, beta, u):
+    """Integrand factor of N(u) and the Jacobian's mass coefficient -dN/du at GL points:
+    puncture-type sources beta (1 + alpha u)^-7 and 7 alpha beta (1 + alpha u)^-8; the star
+    beta u^5 and -5 beta u^4."""
+    if nl["kind"] == "star":
+        return beta * u ** 5, -5.0 * beta * u ** 4
+    s = 1.0 + alpha * u
+    if np.any(s <= 0.0):
+        raise FloatingPointError("1 + alpha u <= 0 at a quadrature point")
+    return beta * s ** -7, 7.0 * alpha * beta * s ** -8

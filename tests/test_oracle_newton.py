@@ -86,3 +86,50 @@ def test_puncture_coefficients_limits():
     a, b = problems.nl_alpha_beta(nl, near)
     # alpha ~ 2 r / m next to a puncture
     assert abs(a[0] / (2e-7 / mI) - 1.0) < 1e-3 and b[0] >= 0
+
+
+def test_star_closed_form():
+    # constant-density star (Sec. III.B): psi and dpsi/dr continuous at r0, psi -> 1 far
+    # away, and psi solves psi'' + 2 psi' / r + 2 pi rho psi^5 = 0 inside and outside
+    rho0, r0 = 0.001, 4.0
+    C, alpha, beta = problems.star_parameters(rho0, r0)
+    assert alpha >= np.sqrt(5.0)
+    assert abs(3.0 / (2.0 * np.pi) * alpha ** 10 / (1.0 + alpha ** 2) ** 6 - rho0 * r0 * r0) <= 1e-12
+    psi = lambda r: problems.star_psi(rho0, r0, r)  # noqa: E731
+    h = 1e-5
+    d_in = (psi(r0) - psi(r0 - h)) / h
+    d_out = (psi(r0 + 2 * h) - psi(r0 + h)) / h
+    assert abs(psi(r0) - (beta / r0 + 1.0)) <= 1e-14
+    assert abs(d_in - d_out) <= 1e-4 * abs(d_in)  # one-sided differences: O(h) each
+    assert abs(psi(1e6) - 1.0) <= 1e-6
+    for r in (0.5, 2.0, 3.5, 5.0, 9.0):
+        rho = rho0 if r <= r0 else 0.0
+        hh = 1e-3
+        lap = (psi(r + hh) - 2 * psi(r) + psi(r - hh)) / hh ** 2 + (psi(r + hh) - psi(r - hh)) / (r * hh)
+        assert abs(lap + 2 * np.pi * rho * psi(r) ** 5) <= 1e-6
+
+
+def test_star_newton_jacobian_and_convergence():
+    rho0, r0 = 0.001, 4.0
+    nl, dirichlet = meshgen.star_problem(rho0, r0)
+    errs = []
+    for nref in (1, 2):
+        m = meshgen.star_mesh(level=2, p=2, r0=r0, refine_near=nref)
+        ns = NewtonSolver(m, nl, n_cheb=3)
+        F = ns.ops[0].rhs(dirichlet)
+        if nref == 1:
+            # the Jacobian (mass coefficient -5 (2 pi rho) psi^4) is the derivative of R
+            rng = np.random.default_rng(0)
+            u = 1.0 + 0.1 * rng.standard_normal(ns.ops[0].ndof)
+            v = rng.standard_normal(ns.ops[0].ndof)
+            ns.set_state(u)
+            Jv = ns.jacobian_apply(v)
+            eps = 1e-4
+            fd = (ns.residual(u + eps * v, F) - ns.residual(u - eps * v, F)) / (2 * eps)
+            assert np.linalg.norm(fd - Jv) <= 1e-6 * np.linalg.norm(Jv)
+        u, k, hist, _ = ns.solve(F, tol=1e-11, lin_tol=1e-8)
+        assert hist[-1] <= 1e-11
+        exact = ns.ops[0].interpolate(lambda x: problems.star_psi(rho0, r0, np.linalg.norm(x, axis=-1)))
+        errs.append(np.abs(u - exact).max())
+    # the discrete solution approaches the closed form as the cells at the star shrink
+    assert errs[1] < 0.5 * errs[0], errs
