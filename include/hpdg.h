@@ -59,8 +59,9 @@ enum { HPDG_MAP_AFFINE = 0, HPDG_MAP_SHELL = 1, HPDG_MAP_CUBE_SPHERE = 2 };
 enum { HPDG_BC_INTERIOR = 0, HPDG_BC_DIRICHLET = 1, HPDG_BC_NEUMANN = 2 };
 enum { HPDG_COEF_CONSTANT = 0, HPDG_COEF_RADIAL_STEP = 1 };
 enum { HPDG_RHS_SINSINSIN = 0, HPDG_RHS_SHELL_HARMONIC = 1, HPDG_RHS_RADIAL_STEP = 2,
-       HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4, HPDG_RHS_POLYNOMIAL_DIRICHLET = 5 };
-enum { HPDG_NL_PUNCTURE = 0, HPDG_NL_QUADRATIC = 1 };
+       HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4, HPDG_RHS_POLYNOMIAL_DIRICHLET = 5,
+       HPDG_RHS_STAR = 6 };
+enum { HPDG_NL_PUNCTURE = 0, HPDG_NL_QUADRATIC = 1, HPDG_NL_STAR = 2 };
 /* Outer Krylov solvers, each preconditioned by one V-cycle per iteration: flexible CG
  * (Alg. 2), textbook PCG, and restarted flexible GMRES (right preconditioned: the
  * preconditioned directions are kept, so the V-cycle may vary between iterations, e.g. in
@@ -181,22 +182,30 @@ typedef struct {
   int32_t status;        /* the return code */
 } hpdg_solve_stats;
 
-/* RHS descriptor: analytic source / Dirichlet data (ids as HPDG_RHS_*). */
+/* RHS descriptor: analytic source / Dirichlet data (ids as HPDG_RHS_*).  HPDG_RHS_STAR
+ * [rho0, r0]: no source, Dirichlet data the closed-form conformal factor of the
+ * constant-density star (Sec. III.B): psi = C u_alpha(r) inside r0, beta / r + 1 outside,
+ * C = (2 pi rho0 / 3)^(-1/4), alpha >= sqrt(5) from
+ * rho0 r0^2 = (3 / (2 pi)) alpha^10 / (1 + alpha^2)^6 (the continuity of psi and its slope),
+ * beta = r0 (C u_alpha(r0) - 1). */
 typedef struct {
   int32_t kind;
   int32_t n_params;
   const double* params;
 } hpdg_rhs_desc;
 
-/* Semilinear source of  -lap u = beta(x) (1 + alpha(x) u)^-7  (the puncture equation of
+/* Semilinear source N: -lap u = beta(x) (1 + alpha(x) u)^-7  (the puncture equation of
  * Sec. III.D, Eq. Two_Punctures_PDE, for the regular part u, with psi = (1 + alpha u) /
- * alpha).  Parameters (copied):
+ * alpha), or -lap psi = 2 pi rho psi^5 (the constant-density star of Sec. III.B,
+ * Eq. Constant_Density_Star_PDE).  Parameters (copied):
  *   HPDG_NL_PUNCTURE   [s, then rows (cx, cy, cz, m, a)]:
  *                      alpha = 1 / (1 + sum_I m_I / (2 |x - c_I|)),
  *                      beta = sum_I a_I exp(-|x - c_I|^2 / (2 s^2)) / (1 + |x|^2)^2;
  *   HPDG_NL_QUADRATIC  [alpha, C[a][b][c] (27 values, x^a y^b z^c, a, b, c <= 2)]:
  *                      constant alpha, beta = (-lap u*) (1 + alpha u*)^7 for the quadratic
- *                      u* (a manufactured problem whose exact solution is u*). */
+ *                      u* (a manufactured problem whose exact solution is u*);
+ *   HPDG_NL_STAR       [rho0, r0]: N(psi) = 2 pi rho psi^5, rho = rho0 for |x| <= r0 and 0
+ *                      outside (with HPDG_RHS_STAR Dirichlet data). */
 typedef struct {
   int32_t kind;
   int32_t n_params;
@@ -268,14 +277,17 @@ int hpdg_solve(hpdg_mesh* mesh, const hpdg_solve_params* params, const double* b
                double* u_dev, hpdg_solve_stats* stats, void* stream);
 
 /* Nonlinear residual R(u) = A u - N(u) - F (Eq. Ru=0 discretised):
- * N(u)_psi = sum_sigma w det J beta (1 + alpha u)^-7 psi at the volume GL points; F_dev may
+ * N(u)_psi = sum_sigma w det J beta (1 + alpha u)^-7 psi at the volume GL points (star:
+ * w det J 2 pi rho u^5 psi); F_dev may
  * be NULL (F = 0), else the level-0 F (e.g. from hpdg_assemble_rhs).  FP64 level-0
  * vectors; R_dev must differ from u_dev and F_dev.  Needs a mesh uploaded with
  * mass_term = 1.  Returns HPDG_ERR_BREAKDOWN when 1 + alpha u <= 0 at a GL point. */
 int hpdg_nonlinear_residual(hpdg_mesh* mesh, const hpdg_nonlinear_desc* nl, const double* F_dev,
                             const double* u_dev, double* R_dev, void* stream);
 /* Linearise at u (Eq. newtoncorrectionsystem): every level's mass coefficient becomes
- * w det J 7 alpha beta (1 + alpha u_l)^-8 with u_0 = u and u_{l+1} injected from u_l (each
+ * w det J 7 alpha beta (1 + alpha u_l)^-8 (star: -5 w det J 2 pi rho u_l^4; the Jacobian
+ * must stay positive definite, which holds on the weak-field branch) with u_0 = u and
+ * u_{l+1} injected from u_l (each
  * coarse LGL node takes the value of the finer child containing it; nodes on the cut
  * belong to the lower child); then the point-Jacobi scaling, the spectral bounds (Alg. 5)
  * and the coarsest inverse are recomputed.  Afterwards hpdg_apply on level l applies the

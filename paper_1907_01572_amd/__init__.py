@@ -24,8 +24,8 @@ COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 SMOOTHERS = {"none": 0, "point": 1, "block": 2}
 TIMING_KINDS = {"apply": 0, "block": 1}
 RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4,
-           "polynomial_dirichlet": 5}
-NL_IDS = {"puncture": 0, "nl_quadratic": 1}
+           "polynomial_dirichlet": 5, "star": 6}
+NL_IDS = {"puncture": 0, "nl_quadratic": 1, "star": 2}
 
 EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload", "hpdg_mesh_info_get",
             "hpdg_level_cells", "hpdg_mesh_free", "hpdg_assemble_rhs", "hpdg_apply",

@@ -104,6 +104,7 @@ struct hpdg_mesh {
   bool mass_on = true;            // false: applies leave out the mass term (the residual's A u)
   bool bf16_blocks = false;       // FP32 V-cycle reads the bf16 inverse blocks (HPDG_PREC_MIXED_BF16)
   std::vector<double> nl_key;     // kind and parameters of the source the GL tables hold
+  int nl_kind = 0;                // HPDG_NL_* of that source
   int* bad = nullptr;             // device flag: 1 + alpha u <= 0 somewhere
   int* host_bad = nullptr;        // pinned
   double *nl_b = nullptr, *nl_rhs = nullptr, *nl_delta = nullptr;  // Newton: R, -R, correction
@@ -847,7 +848,7 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
 }
 
 void assemble_rhs_impl(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, hipStream_t s) {
-  if (rhs->kind < 0 || rhs->kind > 5) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
+  if (rhs->kind < 0 || rhs->kind > 6) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
   if (rhs->n_params > 0 && !rhs->params) throw Error(HPDG_ERR_INVALID_ARG, "rhs parameters missing");
   std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
   std::vector<double> F;
@@ -1027,7 +1028,7 @@ bool krylov_solve(hpdg_mesh* mesh, const hpdg_solve_params& params, const double
 // alpha and w det J beta at the GL points of every level for the source ``nl`` (host, FP64)
 void set_nonlinear(hpdg_mesh* M, const hpdg_nonlinear_desc* nl, hipStream_t s) {
   if (M->H[0].nmq == 0) throw Error(HPDG_ERR_UNSUPPORTED, "mesh uploaded without mass_term");
-  if (nl->kind != HPDG_NL_PUNCTURE && nl->kind != HPDG_NL_QUADRATIC)
+  if (nl->kind != HPDG_NL_PUNCTURE && nl->kind != HPDG_NL_QUADRATIC && nl->kind != HPDG_NL_STAR)
     throw Error(HPDG_ERR_INVALID_ARG, "unknown nonlinear source kind");
   if (nl->n_params < 0 || (nl->n_params > 0 && !nl->params)) throw Error(HPDG_ERR_INVALID_ARG, "bad parameters");
   const std::vector<double> P(nl->params, nl->params + nl->n_params);
@@ -1035,6 +1036,8 @@ void set_nonlinear(hpdg_mesh* M, const hpdg_nonlinear_desc* nl, hipStream_t s) {
     throw Error(HPDG_ERR_INVALID_ARG, "puncture parameters are [s > 0, rows of 5]");
   if (nl->kind == HPDG_NL_QUADRATIC && P.size() != 28)
     throw Error(HPDG_ERR_INVALID_ARG, "quadratic parameters are [alpha, 27 coefficients]");
+  if (nl->kind == HPDG_NL_STAR && (P.size() != 2 || !(P[0] > 0) || !(P[1] > 0)))
+    throw Error(HPDG_ERR_INVALID_ARG, "star parameters are [rho0 > 0, r0 > 0]");
   std::vector<double> key(1, double(nl->kind));
   key.insert(key.end(), P.begin(), P.end());
   if (key == M->nl_key) return;
@@ -1064,6 +1067,7 @@ void set_nonlinear(hpdg_mesh* M, const hpdg_nonlinear_desc* nl, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
   }
   M->nl_key = key;
+  M->nl_kind = nl->kind;
 }
 
 void clear_bad(hpdg_mesh* M, hipStream_t s) {
@@ -1085,7 +1089,7 @@ void nl_residual(hpdg_mesh* M, const double* F, const double* u, double* R, hipS
   apply_level<double>(M, 0, u, R, s);
   M->mass_on = true;
   clear_bad(M, s);
-  launch_nl_eval(M->view<double>(0), u, d.nl_alpha, d.nl_wbeta, d.t, nullptr, M->bad, s);
+  launch_nl_eval(M->view<double>(0), M->nl_kind, u, d.nl_alpha, d.nl_wbeta, d.t, nullptr, M->bad, s);
   launch_axpby<double>(n, -1.0, d.t, 1.0, R, s);
   if (F) launch_axpby<double>(n, -1.0, F, 1.0, R, s);
   check_bad(M, s);
@@ -1106,7 +1110,7 @@ void linearize(hpdg_mesh* M, const double* u, hipStream_t s) {
       launch_inject<double>(M->tview<double>(l - 1), ul, d.p, s);
       ul = d.p;
     }
-    launch_nl_eval(M->view<double>(l), ul, d.nl_alpha, d.nl_wbeta, nullptr, d.mcoef, M->bad, s);
+    launch_nl_eval(M->view<double>(l), M->nl_kind, ul, d.nl_alpha, d.nl_wbeta, nullptr, d.mcoef, M->bad, s);
   }
   check_bad(M, s);
   for (int l = 0; l < L; ++l) {

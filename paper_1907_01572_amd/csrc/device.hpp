@@ -128,10 +128,12 @@ void launch_fcg_update(long long n, const double* v, const double* w, double* d,
                        double* u, double* r, double* sc, double* partials, int first, hipStream_t s);
 
 // Newton linearisation (newton.hip): per element, u at the volume GL points; N(u) (LGL test
-// functions, may be null) and / or the mass coefficient w det J 7 alpha beta (1 + alpha u)^-8
-// (may be null); *bad = 1 when 1 + alpha u <= 0 somewhere
-void launch_nl_eval(const LevelView<double>& L, const double* u, const double* alpha, const double* wbeta,
-                    double* N, double* mcoef, int* bad, hipStream_t s);
+// functions, may be null) and / or the Jacobian's mass coefficient (may be null). kind 0, 1:
+// N integrand w det J beta (1 + alpha u)^-7, mass w det J 7 alpha beta (1 + alpha u)^-8, and
+// *bad = 1 when 1 + alpha u <= 0 somewhere; kind 2 (star): w det J beta u^5, mass
+// -5 w det J beta u^4 (wbeta = w det J beta)
+void launch_nl_eval(const LevelView<double>& L, int kind, const double* u, const double* alpha,
+                    const double* wbeta, double* N, double* mcoef, int* bad, hipStream_t s);
 // dinv = 1 / (diag(A) + diag(mass form with L.mcoef))
 template <typename T>
 void launch_diag_mass(const LevelView<T>& L, const T* diagA, T* dinv, hipStream_t s);

@@ -72,7 +72,9 @@ struct ElemInfo {
 struct MortarInfo {
   int em, fm, ep, fp;
   int orient, sub, q, gmode;  // gmode 0: constant per mortar (8 values), 1: per point (8 q^2)
-  int bc, pad;
+  int bc;
+  int rq;                     // the face's own rule (before any raise to the volume rule's q);
+                              // Dirichlet data are integrated with it
   long long geo;              // offset of the mortar metric (in scalars)
 };
 

@@ -82,7 +82,9 @@ size_t lds_elem(int NM, int QM) {
   return n * n * n + q * n + n * n * q + n * q * q + q * q * q;
 }
 
-__global__ void __launch_bounds__(kNT) nl_eval_kernel(LevelView<double> L, const double* __restrict__ u,
+// kind 0, 1 (puncture-type): wbeta (1 + alpha u)^-7, mass 7 alpha wbeta (1 + alpha u)^-8;
+// kind 2 (constant-density star, Sec. III.B): wbeta u^5, mass -5 wbeta u^4
+__global__ void __launch_bounds__(kNT) nl_eval_kernel(LevelView<double> L, int kind, const double* __restrict__ u,
                                                       const double* __restrict__ alpha,
                                                       const double* __restrict__ wbeta, double* N,
                                                       double* mcoef, int* bad) {
@@ -103,6 +105,12 @@ __global__ void __launch_bounds__(kNT) nl_eval_kernel(LevelView<double> L, const
   lgl_to_gl(B, n, q, su, t1, t2, g);
   for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
     const long long k = I.mq + idx;
+    if (kind == 2) {
+      const double v = g[idx], v2 = v * v, v4 = v2 * v2;
+      if (mcoef) mcoef[k] = -5.0 * wbeta[k] * v4;
+      g[idx] = wbeta[k] * v4 * v;
+      continue;
+    }
     const double s = 1.0 + alpha[k] * g[idx];
     if (!(s > 0.0)) bad[0] = 1;
     const double s2 = s * s, s4 = s2 * s2;
@@ -204,12 +212,12 @@ unsigned grid_of(long long n) {
 
 }  // namespace
 
-void launch_nl_eval(const LevelView<double>& L, const double* u, const double* alpha, const double* wbeta,
+void launch_nl_eval(const LevelView<double>& L, int kind, const double* u, const double* alpha, const double* wbeta,
                     double* N, double* mcoef, int* bad, hipStream_t s) {
   if (L.n_elem == 0) return;
   const size_t lds = sizeof(double) * lds_elem(L.nmax, L.qmax);
-  hipLaunchKernelGGL(nl_eval_kernel, dim3(unsigned(L.n_elem)), dim3(kNT), lds, s, L, u, alpha, wbeta, N, mcoef,
-                     bad);
+  hipLaunchKernelGGL(nl_eval_kernel, dim3(unsigned(L.n_elem)), dim3(kNT), lds, s, L, kind, u, alpha, wbeta, N,
+                     mcoef, bad);
 }
 
 template <typename T>

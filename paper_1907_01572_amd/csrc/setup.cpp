@@ -260,7 +260,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     const Mortar& mt = L.mortars[mi];
     MortarInfo& I = L.minfo[mi];
     I.em = mt.em; I.fm = mt.fm; I.ep = mt.ep; I.fp = mt.fp;
-    I.orient = mt.orient; I.sub = mt.sub; I.bc = mt.bc; I.pad = 0;
+    I.orient = mt.orient; I.sub = mt.sub; I.bc = mt.bc; I.rq = 0;
     const Cell& cm = L.cells[mt.em];
     const bool interior = mt.ep >= 0;
     if (!interior && mt.bc != 1) {  // Neumann: no operator term
@@ -274,6 +274,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     const int pm = std::max(nm, np) - 1;
     I.q = std::max(nm, np) + ((curved || !kc) ? dp.quad_extra : 0);
     if (I.q > kMaxQ) throw Error(-2, "too many mortar quadrature points");
+    I.rq = I.q;
     // constant metric on a flat mortar with one value of k at all its points (folded in)
     double kmt = 1.0;
     bool kflat = kc;
@@ -494,6 +495,27 @@ void build_diagonal(const OpTable& T, LevelHost& L) {
 // ---------------------------------------------------------------------------------
 namespace {
 
+// constant-density star (Sec. III.B): C = (2 pi rho0 / 3)^(-1/4); alpha from the continuity
+// of psi and dpsi/dr at r0, rho0 r0^2 = (3 / (2 pi)) alpha^10 / (1 + alpha^2)^6, on the
+// weak-field branch alpha >= sqrt(5) (bisection; the right side falls there);
+// beta = r0 (C u_alpha(r0) - 1); psi = C u_alpha(r) inside r0, beta / r + 1 outside
+double star_psi(double rho0, double r0, double r) {
+  const double C = std::pow(2.0 * M_PI * rho0 / 3.0, -0.25);
+  const double target = rho0 * r0 * r0;
+  auto f = [&](double a) { return 3.0 / (2.0 * M_PI) * std::pow(a, 10) / std::pow(1.0 + a * a, 6) - target; };
+  double lo = std::sqrt(5.0), hi = 2.0 * lo;
+  if (f(lo) < 0) return std::nan("");
+  while (f(hi) > 0) hi *= 2.0;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    (f(mid) > 0 ? lo : hi) = mid;
+  }
+  const double alpha = 0.5 * (lo + hi), ar = alpha * r0;
+  if (r <= r0) return C * std::sqrt(ar) / std::sqrt(r * r + ar * ar);
+  const double beta = r0 * (C * std::sqrt(ar) / std::sqrt(r0 * r0 + ar * ar) - 1.0);
+  return beta / r + 1.0;
+}
+
 double exact_u(int kind, const std::vector<double>& P, const double x[3]) {
   const double X = x[0], Y = x[1], Z = x[2];
   switch (kind) {
@@ -517,6 +539,7 @@ double exact_u(int kind, const std::vector<double>& P, const double x[3]) {
             u += P[(a * K + b) * K + c] * std::pow(X, a) * std::pow(Y, b) * std::pow(Z, c);
       return u;
     }
+    case 6: return star_psi(P[0], P[1], std::sqrt(X * X + Y * Y + Z * Z));
     default: return 0.0;
   }
 }
@@ -568,6 +591,9 @@ void nl_coefficients(int kind, const std::vector<double>& P, const double x[3], 
     const double q = 1.0 + X * X + Y * Y + Z * Z;
     alpha = 1.0 / (1.0 + psum);
     beta = b / (q * q);
+  } else if (kind == 2) {  // constant-density star: P = [rho0, r0], beta = 2 pi rho (alpha unused)
+    alpha = 0.0;
+    beta = std::sqrt(X * X + Y * Y + Z * Z) <= P[1] ? 2.0 * M_PI * P[0] : 0.0;
   } else {  // quadratic manufactured: P = [alpha, C (27)], beta = (-lap u*) (1 + alpha u*)^7
     alpha = P[0];
     const std::vector<double> C(P.begin() + 1, P.end());
@@ -641,11 +667,12 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
           F[size_t(I.off) + (k * n + j) * n + i] += s;
         }
   }
-  // Dirichlet faces: int g_D (sigma psi - k n.grad psi)
+  // Dirichlet faces: int g_D (sigma psi - k n.grad psi), with the face's own rule (a flat face
+  // whose rule was raised to the volume rule's keeps its constant metric, valid at any q)
   for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
     const MortarInfo& M = L.minfo[mi];
     if (M.q == 0 || M.ep >= 0) continue;
-    const int q = M.q;
+    const int q = M.rq;
     const ElemInfo& I = L.einfo[M.em];
     const int n = I.n, f = M.fm, d = f >> 1, t0 = d == 0 ? 1 : 0, t1_ = d == 2 ? 1 : 2;
     const double* La = td + T.index(OpTable::GL_VAL, n, q);

@@ -5,6 +5,8 @@
 * Newton solves: the manufactured quadratic problem returns the interpolant of the exact
   solution; the puncture source on a curved shell reaches |R| <= 1e-10 |R(0)| recomputed
   by the oracle, in FP64 and with the FP32 V-cycle;
+* the constant-density star (Sec. III.B, psi^5 source): residual, Jacobian and boundary
+  data match the oracle, and the Newton solution matches the oracle's Newton solution;
 * block-Jacobi smoothing is refused for Newton (its blocks are not rebuilt).
 """
 import numpy as np
@@ -24,7 +26,11 @@ CASES = {
                      lambda: meshgen.quadratic_nonlinear_problem(0.5)[0]),
     "shell_puncture": (lambda: meshgen.cubed_sphere_shell(level=1, p=3, r_out=30.0, zeta_break=0.0, r_break=4.0),
                        lambda: _strong_puncture()),
+    "star": (lambda: meshgen.star_mesh(level=2, p=2, r0=4.0, refine_near=1),
+             lambda: meshgen.star_problem(0.001, 4.0)[0]),
 }
+# states near which each case is linearised (the star's psi is about 1)
+OFFSET = {"star": 1.0}
 
 
 def _strong_puncture():
@@ -59,7 +65,7 @@ def test_residual_and_jacobian_parity(ctx, name):
     M = ctx.upload(m, mass_term=True)
     M.setup_smoother(smoother="point")
     rng = np.random.default_rng(0)
-    u = 0.05 * rng.standard_normal(ns.ops[0].ndof)
+    u = OFFSET.get(name, 0.0) + 0.05 * rng.standard_normal(ns.ops[0].ndof)
     F = rng.standard_normal(ns.ops[0].ndof)
     R = torch.zeros(len(u), dtype=torch.float64, device="cuda")
     M.nonlinear_residual(nl, dev(u), R, F=dev(F))
@@ -115,6 +121,30 @@ def test_newton_puncture_reaches_oracle_residual(ctx, prec):
     r = np.linalg.norm(ns.residual(host(u), F)) / np.linalg.norm(ns.residual(np.zeros_like(F), F))
     print("puncture prec", prec, st, "oracle |R|/|R0|", r, flush=True)
     assert st["newton_steps"] >= 2 and r <= 1e-10
+    M.free()
+
+
+def test_newton_star_matches_oracle_solution(ctx):
+    rho0, r0 = 0.001, 4.0
+    nl, dirichlet = meshgen.star_problem(rho0, r0)
+    m = meshgen.star_mesh(level=2, p=2, r0=r0, refine_near=1)
+    ns = NewtonSolver(m, nl, n_cheb=3)
+    Fo = ns.ops[0].rhs(dirichlet)
+    M = ctx.upload(m, mass_term=True)
+    M.setup_smoother(smoother="point", n_cheb=3)
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    M.assemble_rhs(dirichlet, F)
+    e_rhs = rel(host(F), Fo)
+    u = torch.zeros_like(F)
+    st = M.newton_solve(nl, u, F=F, tol=1e-11, lin_tol=1e-8)
+    uo, k, hist, _ = ns.solve(Fo, tol=1e-11, lin_tol=1e-8)
+    ug = host(u)
+    r = np.linalg.norm(ns.residual(ug, Fo)) / np.linalg.norm(ns.residual(np.zeros_like(Fo), Fo))
+    d = np.abs(ug - uo).max()
+    print("star rhs", e_rhs, st, "oracle |R|/|R0|", r, "max |u - u_oracle|", d, flush=True)
+    assert e_rhs <= 1e-12 and st["newton_steps"] >= 2 and r <= 1e-10
+    # both solutions solve the same discrete system to 1e-11 relative; psi is about 1
+    assert d <= 1e-8
     M.free()
 
 
