@@ -31,11 +31,13 @@ HBM_PEAK_GBS = 8000.0
 # --summarize-traffic; valid only while the kernel sources hash to the recorded value
 TRAFFIC_FILE = os.path.join("profiles", "solve_shell_p5_hbm_traffic.txt")
 KERNEL_SOURCES = [os.path.join("paper_1907_01572_amd", "csrc", f)
-                  for f in ("apply.hip", "kernels.hip", "device.hpp", "host.hpp")]
+                  for f in ("apply.hip", "kernels.hip", "blocks.hpp", "device.hpp", "host.hpp")]
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read, 1 GiB written
 # kernel timing inside the timed solves: HIP events around every 8th launch of each kernel
 # kind and level (two event records per sampled launch)
 TIMING_EVERY = 8
+# library timing kinds: the apply, the block-Jacobi step and the two fused in one kernel
+TIMED_KINDS = ("apply", "block", "smooth")
 
 
 def kernel_sources_sha256():
@@ -210,6 +212,8 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--profile-apply", action="store_true",
                     help="only upload the mesh and run --apply-reps FP64 and FP32 applies (for rocprofv3)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="block smoothing with the apply and the block step in separate kernels")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH", "CAL_WRITE"),
@@ -223,8 +227,10 @@ def main():
         return
     if args.summarize_traffic:
         summarize_traffic(*args.summarize_traffic,
-                          kernels=["apply_kernel<double, 6, 7, true>", "block_sym_kernel<double, double, true>",
-                                   "apply_kernel<float, 6, 7, true>", "block_sym_kernel<float, float, true>"],
+                          kernels=["apply_kernel<double, 6, 7, true, true>", "apply_kernel<double, 6, 7, true, false>",
+                                   "block_sym_kernel<double, double, true>",
+                                   "apply_kernel<float, 6, 7, true, true>", "apply_kernel<float, 6, 7, true, false>",
+                                   "block_sym_kernel<float, float, true>"],
                           out=os.path.join(ROOT, TRAFFIC_FILE))
         return
     if args.gpus != 1:
@@ -269,6 +275,8 @@ def main():
         return
     if args.n_cheb_coarse >= 0:
         W["smoother"]["n_cheb_coarse"] = args.n_cheb_coarse
+    if args.unfused:
+        W["smoother"]["fused"] = False
     lam = M.setup_smoother(**W["smoother"])
     setup_s = time.time() - t0
     N = M.n_dof[0]
@@ -293,7 +301,7 @@ def main():
 
     def read_timing(prec):
         # per kernel kind: level -> (ms, launches, algorithmic bytes) recorded by the library
-        return {kind: [M.kernel_timing(kind, lv, prec) for lv in range(L)] for kind in ("apply", "block")}
+        return {kind: [M.kernel_timing(kind, lv, prec) for lv in range(L)] for kind in TIMED_KINDS}
 
     def timed_solves(prec):
         read_timing(hp.F64), read_timing(hp.F32)  # reset
@@ -334,10 +342,12 @@ def main():
         return (sum(e[0] for e in entries), sum(e[1] for e in entries), sum(e[2] for e in entries))
 
     kernels = {}
-    names = ({"apply": "apply_kernel<double, 6, 7, true>", "block": "block_sym_kernel<double, double, true>"}
+    names = ({"apply": "apply_kernel<double, 6, 7, true, false>", "block": "block_sym_kernel<double, double, true>",
+              "smooth": "apply_kernel<double, 6, 7, true, true>"}
              if args.workload == "shell" else
-             {"apply": "apply_kernel<double, *> (all buckets)", "block": "block_sym_kernel<double, double, true>"})
-    for kind in ("apply", "block"):
+             {"apply": "apply_kernel<double, *> (all buckets)", "block": "block_sym_kernel<double, double, true>",
+              "smooth": "apply_kernel<double, *, *, true, true>"})
+    for kind in TIMED_KINDS:
         ms, n, b = totals(t64[kind])
         if n:
             kernels[kind] = {"kernel": names[kind], "total_ms": ms, "launches": n, "avg_launch_us": 1e3 * ms / n,

@@ -22,7 +22,7 @@ PREC_F64, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2
 SOLVER_FCG, SOLVER_PCG, SOLVER_FGMRES = 0, 1, 2
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 SMOOTHERS = {"none": 0, "point": 1, "block": 2}
-TIMING_KINDS = {"apply": 0, "block": 1}
+TIMING_KINDS = {"apply": 0, "block": 1, "smooth": 2}
 RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4,
            "polynomial_dirichlet": 5, "star": 6}
 NL_IDS = {"puncture": 0, "nl_quadratic": 1, "star": 2}
@@ -65,7 +65,8 @@ class MeshInfo(ctypes.Structure):
 
 class SmootherParams(ctypes.Structure):
     _fields_ = [("n_cheb", ctypes.c_int32), ("n_eigs", ctypes.c_int32), ("Lambda", ctypes.c_double),
-                ("scaling", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_cheb_coarse", ctypes.c_int32)]
+                ("scaling", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_cheb_coarse", ctypes.c_int32),
+                ("unfused", ctypes.c_int32)]
 
 
 class SolveParams(ctypes.Structure):
@@ -352,11 +353,13 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_apply(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
 
     def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
-                       smoother=None, stream=None, n_cheb_coarse=0):
+                       smoother=None, stream=None, n_cheb_coarse=0, fused=True):
         """``smoother``: "none", "point" or "block" (default: "point" if jacobi else "none").
-        ``n_cheb_coarse``: Chebyshev steps on the levels below the finest (0: ``n_cheb``)."""
+        ``n_cheb_coarse``: Chebyshev steps on the levels below the finest (0: ``n_cheb``).
+        ``fused``: block smoothing on one-degree levels runs the apply and the block step as one
+        kernel (False: separate kernels)."""
         kind = smoother if smoother is not None else ("point" if jacobi else "none")
-        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed, n_cheb_coarse)
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed, n_cheb_coarse, 0 if fused else 1)
         lam = np.zeros(max(self.n_levels - 1, 1))
         if lambda_max is not None:
             lam[:len(lambda_max)] = lambda_max

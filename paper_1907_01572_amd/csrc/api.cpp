@@ -97,7 +97,7 @@ struct hpdg_mesh {
   int ncoarse = 0;
   // smoother
   std::vector<double> lam;
-  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0, 0};
+  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0, 0, 0};
   bool smoother_ready = false;
   rocblas_handle blas = nullptr;  // batched Cholesky of the element blocks (setup only)
   // nonlinear source (Newton)
@@ -402,12 +402,12 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   double alpha = 0;
   const T* dinv = M->sp.scaling == HPDG_SMOOTH_POINT ? d.dinv : nullptr;
   const bool block = M->sp.scaling == HPDG_SMOOTH_BLOCK;
+  const bool bf16 = std::is_same<T, float>::value && M->bf16_blocks && d.binv16;
+  const LevelHost& h = M->H[l];
+  const bool fuse = block && !bf16 && !M->sp.unfused && h.bucket_n.size() == 1 &&
+                    apply_block_fusable(h.nmax, h.qmax, h.qmmax, h.bucket_n[0], h.bucket_q[0], h.uniform);
+  const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   for (int k = 1; k <= n_iter; ++k) {
-    const T* Ax = nullptr;
-    if (!(zero && k == 1)) {
-      apply_level<T>(M, l, x, d.t, s);
-      Ax = d.t;
-    }
     if (k == 1)
       alpha = 1.0 / dd;
     else if (k == 2)
@@ -415,13 +415,32 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
     else
       alpha = 1.0 / (dd - alpha * c * c / 4.0);
     const double beta = alpha * dd - 1.0;
+    if (fuse && !(zero && k == 1)) {
+      // the apply without its y write; packed blocks, b, p (read after the first step, written), x written
+      const double bytes = M->timing ? apply_bytes(M, l, sizeof(T)) - double(sizeof(T)) * double(n) +
+                                           double(sizeof(T)) * double(M->block_scalars[l]) +
+                                           double(sizeof(T)) * double(n) * (1 + (k == 1 ? 1 : 2) + 1)
+                                     : 0.0;
+      const BlockStep<T> bs{d.poff, d.binv, b, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0};
+      const LevelView<T> V = M->view<T>(l);
+      launch_traces<T>(V, x, s);
+      timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
+        launch_apply_block_cheb<T>(V, h.bucket_n[0], h.bucket_q[0], M->lev<T>(l).belems + h.bucket_start[0],
+                                   h.bucket_start[1] - h.bucket_start[0], x, bs, s);
+      });
+      continue;
+    }
+    const T* Ax = nullptr;
+    if (!(zero && k == 1)) {
+      apply_level<T>(M, l, x, d.t, s);
+      Ax = d.t;
+    }
     if (block) {
       // inverse blocks, b, Ax (when given), p (read after the first step, written), x (read, written)
       const double vec = double(n) * (1 + (Ax ? 1 : 0) + (k == 1 ? 1 : 2) + 2);
-      const bool bf16 = std::is_same<T, float>::value && M->bf16_blocks && d.binv16;
       const double stored = bf16 ? 2.0 * double(M->block_full_scalars[l]) : double(sizeof(T)) * double(M->block_scalars[l]);
       const double bytes = M->timing ? stored + double(sizeof(T)) * vec : 0.0;
-      timed(M, HPDG_TIMING_BLOCK, l, sizeof(T) == 4 ? HPDG_F32 : HPDG_F64, bytes, s, [&] {
+      timed(M, HPDG_TIMING_BLOCK, l, prec, bytes, s, [&] {
         if constexpr (std::is_same<T, float>::value) {
           if (bf16) {
             launch_block_cheb_bf16(M->view<float>(l), d.boff16, d.binv16, b, Ax, d.p, x, float(alpha), float(beta),
@@ -862,6 +881,7 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
     mesh->sp = *params;
     if (mesh->sp.n_cheb <= 0) mesh->sp.n_cheb = 4;
     if (mesh->sp.n_cheb_coarse < 0) mesh->sp.n_cheb_coarse = 0;
+    mesh->sp.unfused = mesh->sp.unfused ? 1 : 0;
     if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
     if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
     if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)

@@ -15,6 +15,7 @@
 // Each mortar is therefore evaluated once from each side.
 #include <hip/hip_runtime.h>
 
+#include "blocks.hpp"
 #include "device.hpp"
 
 namespace hpdg {
@@ -155,11 +156,12 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
 // points per axis (uniform degree): every size is a compile-time constant, the six 1-D
 // matrices (values / derivatives at the full, lower-half and upper-half point sets) are
 // staged in LDS once, and each phase maps threads to (task, item) with constant strides.
-// Adds the face terms to sy and writes y.
-template <typename T, int N, int Q, bool COMPACT>
-__device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, const T* __restrict__ x,
-                              T* __restrict__ y, const T* sy, const T (&syr)[2], const T* dfo, T* region, Task* tasks,
-                              const Layout& lay) {
+// Adds the face terms to sy and writes y (FUSE: runs the block-Jacobi Chebyshev step bs on
+// the result instead, in the same workgroup).
+template <typename T, int N, int Q, bool COMPACT, bool FUSE>
+__device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, T* __restrict__ y,
+                              const T* sy, const T (&syr)[2], const T* dfo, T* region, Task* tasks,
+                              const Layout& lay, const BlockStep<T>& bs) {
   constexpr int N2 = N * N, N3 = N2 * N, QQ = Q * Q, NQ = N * Q;
   const int NM = lay.NM, QMM = lay.QMM;
   const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
@@ -356,7 +358,10 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       acc += dfo[(f & 1) * NM + kd] * Yn[f * NM * NM + li];
       if (kd == ((f & 1) ? N - 1 : 0)) acc += Yf[f * NM * NM + li];
     }
-    y[I.off + idx] = acc;
+    if constexpr (FUSE)
+      region[idx] = bs.b[I.off + idx] - acc;  // r = b - A x (the face buffers before Yf are free now)
+    else
+      y[I.off + idx] = acc;
   };
   if constexpr (COMPACT) {  // node threadIdx.x + it kThreads of this thread
 #pragma unroll
@@ -364,6 +369,27 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       if (int(threadIdx.x) + it * kThreads < N3) finish(int(threadIdx.x) + it * kThreads, syr[it]);
   } else {
     for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) finish(idx, sy[idx]);
+  }
+  if constexpr (FUSE) {
+    // z = Binv r over the four waves (column blocks taken in turn), partial z per wave after r
+    constexpr int kWaves = kThreads / 64;
+    static_assert(kWaves >= 1, "the fused step needs whole waves");
+    const T* rs = region;
+    const int lane = int(threadIdx.x & 63);
+    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+    T* zs = region + N3 + wv * N3;
+    for (int i = lane; i < N3; i += 64) zs[i] = 0;
+    __syncthreads();
+    packed_block_partial<T, T>(bs.P + bs.poff[e], N3, rs, zs, kWaves, wv, lane);
+    __syncthreads();
+    for (int i = threadIdx.x; i < N3; i += kThreads) {
+      T z = 0;
+#pragma unroll
+      for (int k = 0; k < kWaves; ++k) z += rs[N3 + k * N3 + i];
+      const T pn = bs.first ? bs.alpha * z : bs.alpha * z + bs.beta * bs.p[I.off + i];
+      bs.p[I.off + i] = pn;
+      bs.x[I.off + i] += pn;
+    }
   }
 }
 
@@ -379,10 +405,10 @@ __device__ inline unsigned xcd_remap(unsigned b, unsigned G) {
 
 // NT, QT > 0: element degree + 1 and volume GL points fixed at compile time (the bucket's
 // elements); 0: read from the element record.  UNI: uniform-degree level (faces_uniform).
-template <typename T, int NT, int QT, bool UNI>
+template <typename T, int NT, int QT, bool UNI, bool FUSE = false>
 __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const int* __restrict__ elems,
-                                                         long long count, const T* __restrict__ x,
-                                                         T* __restrict__ y) {
+                                                         long long count, const T* x, T* __restrict__ y,
+                                                         BlockStep<T> bs) {
   extern __shared__ unsigned char smem_raw[];
   if ((long long)blockIdx.x >= count) return;
   const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);  // gridDim.x == count
@@ -535,7 +561,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
 
   // ---- faces ----
   if constexpr (UNI) {
-    faces_uniform<T, NT, QT, COMPACT>(L, I, e, x, y, sy, syr, dfo, region, tasks, lay);
+    faces_uniform<T, NT, QT, COMPACT, FUSE>(L, I, e, y, sy, syr, dfo, region, tasks, lay, bs);
     return;
   }
   int rounds = 0;
@@ -762,11 +788,11 @@ __global__ void __launch_bounds__(kThreads) trace_kernel(LevelView<T> L, const T
   }
 }
 
-template <typename T, int N, int Q, bool UNI>
+template <typename T, int N, int Q, bool UNI, bool FUSE = false>
 void launch_fixed(const LevelView<T>& L, const int* elems, long long count, const T* x, T* y, size_t lds,
-                  hipStream_t s) {
-  hipLaunchKernelGGL((apply_kernel<T, N, Q, UNI>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
-                     count, x, y);
+                  hipStream_t s, const BlockStep<T>& bs = BlockStep<T>{}) {
+  hipLaunchKernelGGL((apply_kernel<T, N, Q, UNI, FUSE>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
+                     count, x, y, bs);
 }
 
 }  // namespace
@@ -787,7 +813,7 @@ void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
   launch_traces<T>(L, x, s);
   const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
   hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
-                     (const int*)nullptr, L.n_elem, x, y);
+                     (const int*)nullptr, L.n_elem, x, y, BlockStep<T>{});
 }
 
 template <typename T>
@@ -806,9 +832,36 @@ void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const
   HPDG_CASE(8, 8) HPDG_CASE(8, 9)
 #undef HPDG_CASE
   hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
-                     count, x, y);
+                     count, x, y, BlockStep<T>{});
 }
 
+bool apply_block_fusable(int nmax, int qmax, int qmmax, int n, int q, int uniform) {
+  if (!uniform || n * n * n > 2 * kThreads || kThreads % 64 != 0 || n > 8 || q > 9) return false;
+  const Layout lay(nmax, qmax, qmmax, true);
+  // r and one partial z per wave in the face buffers before the face sums (mats, RA, RB)
+  return 6LL * lay.QMM * lay.NM + lay.ra + lay.rb >= (1LL + kThreads / 64) * n * n * n;
+}
+
+template <typename T>
+void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x,
+                             const BlockStep<T>& bs, hipStream_t s) {
+  if (count == 0) return;
+  if (!apply_block_fusable(L.nmax, L.qmax, L.qmmax, n, q, 1))
+    throw Error(-7, "fused block step: level not uniform or degree outside the compact layout");
+  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), true);
+#define HPDG_CASE(NN, QQ) \
+  if (n == NN && q == QQ) return launch_fixed<T, NN, QQ, true, true>(L, elems, count, x, nullptr, lds, s, bs);
+  HPDG_CASE(2, 2) HPDG_CASE(2, 3) HPDG_CASE(3, 3) HPDG_CASE(3, 4) HPDG_CASE(4, 4) HPDG_CASE(4, 5)
+  HPDG_CASE(5, 5) HPDG_CASE(5, 6) HPDG_CASE(6, 6) HPDG_CASE(6, 7) HPDG_CASE(7, 7) HPDG_CASE(7, 8)
+  HPDG_CASE(8, 8) HPDG_CASE(8, 9)
+#undef HPDG_CASE
+  throw Error(-7, "fused block step: no kernel for this (n, q)");
+}
+
+template void launch_apply_block_cheb<double>(const LevelView<double>&, int, int, const int*, long long,
+                                              const double*, const BlockStep<double>&, hipStream_t);
+template void launch_apply_block_cheb<float>(const LevelView<float>&, int, int, const int*, long long,
+                                             const float*, const BlockStep<float>&, hipStream_t);
 template void launch_traces<double>(const LevelView<double>&, const double*, hipStream_t);
 template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t);
 template void launch_apply<double>(const LevelView<double>&, const double*, double*, hipStream_t);

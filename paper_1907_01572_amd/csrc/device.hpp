@@ -56,6 +56,27 @@ void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
                          const T* x, T* y, hipStream_t s);
+// One block-Jacobi Chebyshev step fused behind the apply (Alg. 4 with M the element blocks):
+// with r = b - A x, z = Binv r (packed FP64 / FP32 blocks), p = alpha z + beta p (first:
+// alpha z), x += p, per element in the workgroup that computed (A x)_e. Every element's apply
+// reads only its own x and the face traces written before the launch, so x is updated in place.
+template <typename T>
+struct BlockStep {
+  const long long* poff;  // packed block offset of each element (scalars)
+  const T* P;             // packed inverse blocks
+  const T* b;
+  T* p;
+  T* x;
+  T alpha, beta;
+  int first;
+};
+// whether the level's elements (one bucket of degree n - 1, q GL points) can take the fused step:
+// a uniform level, the compact apply layout (n^3 <= 512) and LDS room for r and 4 partial z
+bool apply_block_fusable(int nmax, int qmax, int qmmax, int n, int q, int uniform);
+// launch_traces first; then the apply and the step for the elements elems[0..count)
+template <typename T>
+void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* elems, long long count,
+                             const T* x, const BlockStep<T>& bs, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const TransferView<T>& V, const T* uc, T* uf, hipStream_t s);
 template <typename T>

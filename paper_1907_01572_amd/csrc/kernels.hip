@@ -3,6 +3,7 @@
 // and the dense coarse solve.
 #include <hip/hip_runtime.h>
 
+#include "blocks.hpp"
 #include "device.hpp"
 
 namespace hpdg {
@@ -142,91 +143,6 @@ __global__ void __launch_bounds__(kBS) block_cheb_bf16_kernel(LevelView<float> L
   }
 }
 
-// ---- the packed mat-vec ----
-// The lower triangle is visited by column blocks of G columns; in a block, by the 64-row panels
-// at and below it: the diagonal panel's tile (tile columns j0 .. j0 + G - 1 of its diagonal
-// tile) and then the full columns c0 .. c0 + G - 1 of every lower panel. The column part is
-// accumulated per lane across the panels and reduced over the wave once per column block.
-constexpr int kGroup = 16;
-
-// G per-lane values w[t] (partial sums of columns c0 + t) summed over the wave; returns, in
-// every lane, the total of column c0 + (lane % G): halving exchange steps (each lane keeps the
-// half selected by one lane bit, adding its partner's copy of that half), then all-reduce
-// steps over the lane groups of G. The order of additions is fixed.
-template <int G, typename T>
-__device__ __forceinline__ T wave_column_sums(T (&w)[G], int lane) {
-#pragma unroll
-  for (int step = 0; (G >> (step + 1)) >= 1; ++step) {  // an affine counter, so that it unrolls
-    const int s = G >> (step + 1);
-    const bool hi = (lane & s) != 0;
-#pragma unroll
-    for (int k = 0; k < s; ++k) {
-      // both halves are exchanged and the select acts on the sums: a select between two array
-      // elements would be turned into a per-lane array index (a chain of selects over w)
-      const T lo = w[k] + __shfl_xor(w[k], s, 64);
-      const T up = w[k + s] + __shfl_xor(w[k + s], s, 64);
-      w[k] = hi ? up : lo;
-    }
-  }
-  T v = w[0];
-#pragma unroll
-  for (int s = G; s < 64; s *= 2) v += __shfl_xor(v, s, 64);
-  return v;
-}
-
-// the G values of columns c0 .. c0 + G - 1 in the rows of panel r0 (lane l: row r0 + l). Every
-// lane loads: lanes outside the panel or the triangle read a clamped address inside the same
-// column and their value is discarded later, so that no load sits behind a per-lane branch.
-template <int G, typename S, typename T>
-__device__ __forceinline__ void load_tile(const S* Pe, int N, int c0, int r0, int lane, T (&v)[G]) {
-  const int m = min(64, N - r0);
-  const S* Pp = Pe + (long long)r0 * (r0 + 1) / 2;
-  if (c0 < r0) {  // full columns (c0 + G <= r0: c0 and r0 are multiples of G and 64)
-    const S* q = Pp + (long long)c0 * m + min(lane, m - 1);
-#pragma unroll
-    for (int t = 0; t < G; ++t) v[t] = from_storage<T, S>(q[t * m]);
-  } else {  // diagonal tile columns j0 .. j0 + G - 1 (column j holds rows j .. m - 1)
-    const S* Pd = Pp + (long long)r0 * m;
-    const int j0 = c0 - r0;
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const int j = min(j0 + t, m - 1);
-      const int st = j * m - j * (j - 1) / 2;
-      v[t] = from_storage<T, S>(Pd[st + min(max(lane - j, 0), m - 1 - j)]);
-    }
-  }
-}
-
-// one tile: lane l adds its row's products to z[r0 + l] (LDS, index i only touched by lane
-// i % 64) and its column partials (times r[r0 + l]) to w; the diagonal entry counts once
-template <int G, typename T>
-__device__ __forceinline__ void tile_products(int N, int c0, int r0, int lane, const T* rs, T* zs, T (&w)[G],
-                                              const T (&v)[G]) {
-  const int m = min(64, N - r0);
-  const bool act = lane < m;
-  const T xr = act ? rs[r0 + lane] : T(0);
-  T acc = 0;
-  if (c0 < r0) {
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const T vv = act ? v[t] : T(0);
-      acc += vv * rs[c0 + t];
-      w[t] += vv * xr;
-    }
-  } else {
-    const int j0 = c0 - r0;
-#pragma unroll
-    for (int t = 0; t < G; ++t) {
-      const int j = j0 + t;
-      const bool in = act && j < m && lane >= j;
-      const T vv = in ? v[t] : T(0);
-      acc += vv * rs[r0 + min(j, m - 1)];
-      w[t] += lane > j ? vv * xr : T(0);
-    }
-  }
-  if (act) zs[r0 + lane] += acc;
-}
-
 // per element, blockDim.x / 64 waves (column block k taken by wave k % waves): z = Binv r with
 // Binv symmetric and packed (each stored off-diagonal entry is used twice: for its row and,
 // via the wave column sums, for its column); CHEB: r = b - Ax (Ax null: r = b),
@@ -237,7 +153,6 @@ template <typename S, typename T, bool CHEB>
 __global__ void __launch_bounds__(512) block_sym_kernel(LevelView<T> L, const long long* poff, const S* P,
                                                         const T* b, const T* Ax, T* p, T* x, T alpha, T beta,
                                                         int first) {
-  constexpr int G = kGroup;
   extern __shared__ unsigned char smem_raw[];
   const long long e = blockIdx.x;
   if (e >= L.n_elem) return;
@@ -253,23 +168,7 @@ __global__ void __launch_bounds__(512) block_sym_kernel(LevelView<T> L, const lo
     rs[i] = (CHEB && Ax) ? b[I.off + i] - Ax[I.off + i] : b[I.off + i];
   for (int i = lane; i < N; i += 64) zs[i] = 0;
   __syncthreads();
-  const S* Pe = P + poff[e];
-#pragma unroll 1
-  for (int kb = wv; kb * G < N; kb += waves) {
-    const int c0 = kb * G;  // a multiple of G by construction (lets the compiler simplify the indexing)
-    T w[G];
-#pragma unroll
-    for (int t = 0; t < G; ++t) w[t] = 0;
-#pragma unroll 1
-    for (int r0 = c0 & ~63; r0 < N; r0 += 64) {
-      T v[G];
-      load_tile<G>(Pe, N, c0, r0, lane, v);
-      tile_products<G>(N, c0, r0, lane, rs, zs, w, v);
-    }
-    const T cs = wave_column_sums<G>(w, lane);
-    // lane == (c0 + lane % G) % 64 owns that index
-    if (lane / G == ((c0 / G) & (64 / G - 1)) && c0 + (lane & (G - 1)) < N) zs[c0 + (lane & (G - 1))] += cs;
-  }
+  packed_block_partial<S, T>(P + poff[e], N, rs, zs, waves, wv, lane);
   __syncthreads();
   for (int i = threadIdx.x; i < N; i += blockDim.x) {
     T z = 0;
@@ -583,15 +482,19 @@ void launch_block_cheb_bf16(const LevelView<float>& L, const long long* boff, co
 
 // waves per element: one on levels with enough elements to fill the chip, more (up to 8) on
 // small levels, where each wave's sequence of groups would otherwise set the time
-inline int block_waves(long long n_elem) {
+// waves per element: doubled while every wave keeps at least 3 of the element's column blocks,
+// or while the grid holds fewer than 8192 waves (small levels), never past 8 waves or half the
+// column blocks (measured on blocks of 64, 125, 216 and 343 rows)
+inline int block_waves(long long n_elem, int nmax) {
+  const int ncb = (nmax * nmax * nmax + kGroup - 1) / kGroup;
   int w = 1;
-  while (w < 8 && n_elem * w < 4096) w *= 2;
+  while (w < 8 && 2 * w <= ncb && (n_elem * w < 8192 || 6 * w <= ncb)) w *= 2;
   return w;
 }
 template <typename T, typename S>
 void launch_block_apply(const LevelView<T>& L, const long long* poff, const S* P, const T* r, T* z,
                         hipStream_t s) {
-  const int w = block_waves(L.n_elem);
+  const int w = block_waves(L.n_elem, L.nmax);
   const size_t lds = (1 + w) * sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
   hipLaunchKernelGGL((block_sym_kernel<S, T, false>), dim3(unsigned(L.n_elem)), dim3(64 * w), lds, s, L, poff, P,
                      r, (const T*)nullptr, (T*)nullptr, z, T(0), T(0), 0);
@@ -599,7 +502,7 @@ void launch_block_apply(const LevelView<T>& L, const long long* poff, const S* P
 template <typename T, typename S>
 void launch_block_cheb(const LevelView<T>& L, const long long* poff, const S* P, const T* b, const T* Ax, T* p,
                        T* x, T alpha, T beta, int first, hipStream_t s) {
-  const int w = block_waves(L.n_elem);
+  const int w = block_waves(L.n_elem, L.nmax);
   const size_t lds = (1 + w) * sizeof(T) * size_t(L.nmax) * L.nmax * L.nmax;
   hipLaunchKernelGGL((block_sym_kernel<S, T, true>), dim3(unsigned(L.n_elem)), dim3(64 * w), lds, s, L, poff, P,
                      b, Ax, p, x, alpha, beta, first);
