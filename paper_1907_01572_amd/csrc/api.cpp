@@ -69,6 +69,7 @@ struct DevLevel {
   T* mcoef = nullptr;
   T* diag = nullptr;
   T* trace = nullptr;  // face traces (written before each apply)
+  T* trace2 = nullptr;  // block smoothing: the next step's traces, written by the fused step
   double* nl_alpha = nullptr;  // alpha and w det J beta at the GL points (FP64 levels only)
   double* nl_wbeta = nullptr;
 };
@@ -407,6 +408,10 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   const bool fuse = block && !bf16 && !M->sp.unfused && h.bucket_n.size() == 1 &&
                     apply_block_fusable(h.nmax, h.qmax, h.qmmax, h.bucket_n[0], h.bucket_q[0], h.uniform);
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
+  // fused steps write the traces of their result for the next fused step, alternating between
+  // the level's two trace buffers (a step reads one while its neighbours' new traces go to the
+  // other); ``cur`` holds the traces of x when they are current, else null
+  T* cur = nullptr;
   for (int k = 1; k <= n_iter; ++k) {
     if (k == 1)
       alpha = 1.0 / dd;
@@ -421,15 +426,22 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
                                            double(sizeof(T)) * double(M->block_scalars[l]) +
                                            double(sizeof(T)) * double(n) * (1 + (k == 1 ? 1 : 2) + 1)
                                      : 0.0;
-      const BlockStep<T> bs{d.poff, d.binv, b, d.p, x, T(alpha), T(beta), k == 1 ? 1 : 0};
-      const LevelView<T> V = M->view<T>(l);
-      launch_traces<T>(V, x, s);
+      LevelView<T> V = M->view<T>(l);
+      if (!cur) {
+        launch_traces<T>(V, x, s);
+        cur = d.trace;
+      }
+      V.trace = cur;
+      T* next = k < n_iter ? (cur == d.trace ? d.trace2 : d.trace) : nullptr;
+      const BlockStep<T> bs{d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0};
       timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
         launch_apply_block_cheb<T>(V, h.bucket_n[0], h.bucket_q[0], M->lev<T>(l).belems + h.bucket_start[0],
                                    h.bucket_start[1] - h.bucket_start[0], x, bs, s);
       });
+      cur = next;
       continue;
     }
+    cur = nullptr;
     const T* Ax = nullptr;
     if (!(zero && k == 1)) {
       apply_level<T>(M, l, x, d.t, s);
@@ -858,6 +870,7 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
         full += N * N;
       }
       b += packed * (M->has_f32 ? 12 : 8) + (M->has_f32 ? full * 2 : 0) + h.einfo.size() * 8;  // FP64 (+ FP32, bf16)
+      b += size_t(h.ntrace) * prec;  // the second face-trace buffer of the fused step
       full_max = std::max(full_max, full * 8 + h.einfo.size() * 8);
     }
   }
@@ -888,7 +901,12 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
       throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
   }
   if (mesh->sp.scaling == HPDG_SMOOTH_BLOCK)
-    for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
+    for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
+      build_blocks(mesh, l, s);
+      const size_t nt = size_t(mesh->H[l].ntrace);
+      if (!mesh->lev<double>(l).trace2) mesh->lev<double>(l).trace2 = mesh->alloc<double>(nt);
+      if (mesh->has_f32 && !mesh->lev<float>(l).trace2) mesh->lev<float>(l).trace2 = mesh->alloc<float>(nt);
+    }
   for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
     if (lambda_max && lambda_max[l] > 0)
       mesh->lam[l] = lambda_max[l];

@@ -388,7 +388,28 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
       for (int k = 0; k < kWaves; ++k) z += rs[N3 + k * N3 + i];
       const T pn = bs.first ? bs.alpha * z : bs.alpha * z + bs.beta * bs.p[I.off + i];
       bs.p[I.off + i] = pn;
-      bs.x[I.off + i] += pn;
+      const T xn = bs.x[I.off + i] + pn;
+      bs.x[I.off + i] = xn;
+      region[i] = xn;  // r is no longer read (each thread reads only its own partials after it)
+    }
+    if (bs.trace_out) {
+      // the next step's traces (as trace_kernel): values on each face and the reference
+      // normal derivative there
+      __syncthreads();
+      for (int g = threadIdx.x; g < 12 * N2; g += kThreads) {
+        const int f = g / (2 * N2), r = g % (2 * N2), li = r % N2;
+        const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const int i = li % N, j = li / N;
+        T v;
+        if (r < N2) {
+          v = region[vidx(N, d, t0, t1, (f & 1) ? N - 1 : 0, i, j)];
+        } else {
+          v = 0;
+#pragma unroll
+          for (int k = 0; k < N; ++k) v += dfo[(f & 1) * NM + k] * region[vidx(N, d, t0, t1, k, i, j)];
+        }
+        bs.trace_out[I.toff + g] = v;
+      }
     }
   }
 }

@@ -67,6 +67,8 @@ struct BlockStep {
   const T* b;
   T* p;
   T* x;
+  T* trace_out;  // non-null: the face traces of the updated x are written here (the launch reads
+                 // L.trace, so the two must differ)
   T alpha, beta;
   int first;
 };
