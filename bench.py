@@ -163,8 +163,8 @@ def make_workload(args, meshgen, hp):
         w["prob"] = meshgen.problem_config2()
         # four levels: the coarsest (10,368 DOF, 48 cells at p = 5) is solved exactly
         w["upload"] = dict(build_f32=True, max_levels=4)
-        w["smoother"] = dict(n_cheb=args.n_cheb or 20, smoother=args.smoother or "block",
-                             Lambda=args.Lambda or 400.0)
+        w["smoother"] = dict(n_cheb=args.n_cheb or 26, smoother=args.smoother or "block",
+                             Lambda=args.Lambda or 600.0)
         w["desc"] = ("cubed-sphere shell r=1..1e9 (compactified), 6x8^3 cells + 2:1 inner layer, p=%d, "
                      "Poisson, MG-FCG to 1e-10" % args.p)
     elif args.workload == "hp":
