@@ -164,10 +164,11 @@ typedef struct {
   uint64_t seed;         /* SplitMix64 seed of the CG start vector */
   int32_t n_cheb_coarse; /* Chebyshev steps per smoothing call on the levels below the finest
                             (0: n_cheb) */
-  int32_t unfused;       /* HPDG_SMOOTH_BLOCK with FP64 / FP32 blocks on a level of one degree
-                            (p <= 7): 0 runs each Chebyshev step that needs A x as one fused
-                            kernel per element (apply, r = b - A x, z = M^-1 r and the update;
-                            the same arithmetic); 1 keeps the apply and the block step apart */
+  int32_t unfused;       /* HPDG_SMOOTH_POINT, or HPDG_SMOOTH_BLOCK with FP64 / FP32 blocks,
+                            on a level of one degree (p <= 7): 0 runs each Chebyshev step that
+                            needs A x as one fused kernel per element (apply, r = b - A x,
+                            z = M^-1 r and the update; the same arithmetic); 1 keeps the apply
+                            and the scaling step apart */
 } hpdg_smoother_params;
 
 typedef struct {
@@ -362,15 +363,15 @@ int hpdg_server_destroy(hpdg_server* server);
 /* Kernel timing for measurement.  While enabled (every = k > 0), every k-th operator
  * application of each (kind, level, precision) (HPDG_TIMING_APPLY: hpdg_apply and the
  * applies inside hpdg_smooth, hpdg_vcycle and hpdg_solve), every k-th block-Jacobi
- * Chebyshev step (HPDG_TIMING_BLOCK) and every k-th fused apply + block-Jacobi step
+ * Chebyshev step (HPDG_TIMING_BLOCK) and every k-th fused apply + Jacobi-scaled Chebyshev step
  * (HPDG_TIMING_SMOOTH, see hpdg_smoother_params.unfused) is bracketed by two HIP events on
  * its stream, and the algorithmic bytes of the launch are recorded (every = 0 disables):
  *   apply: 2 s N (x read, y written) + s (volume + mortar metric scalars) + record bytes;
  *   block step: s sum_e N_e (N_e + 1) / 2 (packed inverse blocks, N_e = n_e^3) + s N per
  *   vector read or written;
  *   fused step (the one fused kernel; the face-trace launch before it is not timed): the
- *   apply's bytes without the y write, plus the block step's without the A x read (b, p, x
- *   written, p read after the first step).
+ *   apply's bytes without the y write, plus the packed blocks (point Jacobi: s N, the inverse
+ *   diagonal) and s N per vector (b, p, x written, p read after the first step).
  * (s = 8 for HPDG_F64, 4 for HPDG_F32; N = level DOF.)  hpdg_kernel_timing() waits for
  * the recorded events and returns, for one (kind, level, prec), the summed event time in
  * ms, the number of launches and the summed algorithmic bytes since the previous read of

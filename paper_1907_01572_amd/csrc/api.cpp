@@ -405,7 +405,7 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   const bool block = M->sp.scaling == HPDG_SMOOTH_BLOCK;
   const bool bf16 = std::is_same<T, float>::value && M->bf16_blocks && d.binv16;
   const LevelHost& h = M->H[l];
-  const bool fuse = block && !bf16 && !M->sp.unfused && h.bucket_n.size() == 1 &&
+  const bool fuse = ((block && !bf16) || dinv) && !M->sp.unfused && h.bucket_n.size() == 1 &&
                     apply_block_fusable(h.nmax, h.qmax, h.qmmax, h.bucket_n[0], h.bucket_q[0], h.uniform);
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   // fused steps write the traces of their result for the next fused step, alternating between
@@ -421,9 +421,10 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
       alpha = 1.0 / (dd - alpha * c * c / 4.0);
     const double beta = alpha * dd - 1.0;
     if (fuse && !(zero && k == 1)) {
-      // the apply without its y write; packed blocks, b, p (read after the first step, written), x written
-      const double bytes = M->timing ? apply_bytes(M, l, sizeof(T)) - double(sizeof(T)) * double(n) +
-                                           double(sizeof(T)) * double(M->block_scalars[l]) +
+      // the apply without its y write; packed blocks (or the inverse diagonal), b, p (read after the
+      // first step, written), x written
+      const double scaling = double(sizeof(T)) * (dinv ? double(n) : double(M->block_scalars[l]));
+      const double bytes = M->timing ? apply_bytes(M, l, sizeof(T)) - double(sizeof(T)) * double(n) + scaling +
                                            double(sizeof(T)) * double(n) * (1 + (k == 1 ? 1 : 2) + 1)
                                      : 0.0;
       LevelView<T> V = M->view<T>(l);
@@ -433,7 +434,7 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
       }
       V.trace = cur;
       T* next = k < n_iter ? (cur == d.trace ? d.trace2 : d.trace) : nullptr;
-      const BlockStep<T> bs{d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0};
+      const BlockStep<T> bs{dinv, d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0};
       timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
         launch_apply_block_cheb<T>(V, h.bucket_n[0], h.bucket_q[0], M->lev<T>(l).belems + h.bucket_start[0],
                                    h.bucket_start[1] - h.bucket_start[0], x, bs, s);

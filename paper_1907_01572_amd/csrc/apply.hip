@@ -378,14 +378,20 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
     const int lane = int(threadIdx.x & 63);
     const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
     T* zs = region + N3 + wv * N3;
-    for (int i = lane; i < N3; i += 64) zs[i] = 0;
-    __syncthreads();
-    packed_block_partial<T, T>(bs.P + bs.poff[e], N3, rs, zs, kWaves, wv, lane);
+    if (!bs.dinv) {
+      for (int i = lane; i < N3; i += 64) zs[i] = 0;
+      __syncthreads();
+      packed_block_partial<T, T>(bs.P + bs.poff[e], N3, rs, zs, kWaves, wv, lane);
+    }
     __syncthreads();
     for (int i = threadIdx.x; i < N3; i += kThreads) {
       T z = 0;
+      if (bs.dinv) {
+        z = bs.dinv[I.off + i] * rs[i];
+      } else {
 #pragma unroll
-      for (int k = 0; k < kWaves; ++k) z += rs[N3 + k * N3 + i];
+        for (int k = 0; k < kWaves; ++k) z += rs[N3 + k * N3 + i];
+      }
       const T pn = bs.first ? bs.alpha * z : bs.alpha * z + bs.beta * bs.p[I.off + i];
       bs.p[I.off + i] = pn;
       const T xn = bs.x[I.off + i] + pn;

@@ -56,12 +56,14 @@ void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
                          const T* x, T* y, hipStream_t s);
-// One block-Jacobi Chebyshev step fused behind the apply (Alg. 4 with M the element blocks):
-// with r = b - A x, z = Binv r (packed FP64 / FP32 blocks), p = alpha z + beta p (first:
+// One Jacobi-scaled Chebyshev step fused behind the apply (Alg. 4 with M the element blocks or
+// diag A): with r = b - A x, z = M^-1 r (packed FP64 / FP32 blocks, or the inverse diagonal),
+// p = alpha z + beta p (first:
 // alpha z), x += p, per element in the workgroup that computed (A x)_e. Every element's apply
 // reads only its own x and the face traces written before the launch, so x is updated in place.
 template <typename T>
 struct BlockStep {
+  const T* dinv;          // non-null: point Jacobi (z = dinv r) instead of the element blocks
   const long long* poff;  // packed block offset of each element (scalars)
   const T* P;             // packed inverse blocks
   const T* b;
