@@ -863,6 +863,8 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
     b += size_t(h.ntrace) * prec;      // face traces
     b += size_t(h.nmq) * prec + (h.nmq ? size_t(h.ndof) * prec : 0);
     b += (h.tinfo.size() * sizeof(TransferInfo) + (h.cstart.size() + h.clist.size()) * 4) * (M->has_f32 ? 2 : 1);
+    if (scaling != HPDG_SMOOTH_NONE && l + 1 < M->nlevels())
+      b += size_t(h.ntrace) * prec;  // the second face-trace buffer of the fused steps
     if (scaling == HPDG_SMOOTH_BLOCK && l + 1 < M->nlevels()) {
       size_t packed = 0, full = 0;
       for (const ElemInfo& I : h.einfo) {
@@ -871,7 +873,6 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
         full += N * N;
       }
       b += packed * (M->has_f32 ? 12 : 8) + (M->has_f32 ? full * 2 : 0) + h.einfo.size() * 8;  // FP64 (+ FP32, bf16)
-      b += size_t(h.ntrace) * prec;  // the second face-trace buffer of the fused step
       full_max = std::max(full_max, full * 8 + h.einfo.size() * 8);
     }
   }
@@ -902,8 +903,9 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
       throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
   }
   if (mesh->sp.scaling == HPDG_SMOOTH_BLOCK)
+    for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
+  if (mesh->sp.scaling != HPDG_SMOOTH_NONE)  // the fused Jacobi-scaled steps' second trace buffer
     for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
-      build_blocks(mesh, l, s);
       const size_t nt = size_t(mesh->H[l].ntrace);
       if (!mesh->lev<double>(l).trace2) mesh->lev<double>(l).trace2 = mesh->alloc<double>(nt);
       if (mesh->has_f32 && !mesh->lev<float>(l).trace2) mesh->lev<float>(l).trace2 = mesh->alloc<float>(nt);

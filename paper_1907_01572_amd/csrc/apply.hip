@@ -436,6 +436,7 @@ template <typename T, int NT, int QT, bool UNI, bool FUSE = false>
 __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const int* __restrict__ elems,
                                                          long long count, const T* x, T* __restrict__ y,
                                                          BlockStep<T> bs) {
+  static_assert(!FUSE || UNI, "the fused smoother step runs on one-degree levels only");
   extern __shared__ unsigned char smem_raw[];
   if ((long long)blockIdx.x >= count) return;
   const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);  // gridDim.x == count
