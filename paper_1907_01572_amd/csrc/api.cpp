@@ -405,8 +405,9 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   const bool block = M->sp.scaling == HPDG_SMOOTH_BLOCK;
   const bool bf16 = std::is_same<T, float>::value && M->bf16_blocks && d.binv16;
   const LevelHost& h = M->H[l];
-  const bool fuse = ((block && !bf16) || dinv) && !M->sp.unfused && h.bucket_n.size() == 1 &&
-                    apply_block_fusable(h.nmax, h.qmax, h.qmmax, h.bucket_n[0], h.bucket_q[0], h.uniform);
+  bool fuse = ((block && !bf16) || dinv) && !M->sp.unfused && !h.bucket_n.empty();
+  for (size_t bk = 0; fuse && bk < h.bucket_n.size(); ++bk)
+    fuse = apply_block_fusable(h.nmax, h.qmax, h.qmmax, h.bucket_n[bk], h.bucket_q[bk], h.uniform);
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   // fused steps write the traces of their result for the next fused step, alternating between
   // the level's two trace buffers (a step reads one while its neighbours' new traces go to the
@@ -436,8 +437,10 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
       T* next = k < n_iter ? (cur == d.trace ? d.trace2 : d.trace) : nullptr;
       const BlockStep<T> bs{dinv, d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0};
       timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
-        launch_apply_block_cheb<T>(V, h.bucket_n[0], h.bucket_q[0], M->lev<T>(l).belems + h.bucket_start[0],
-                                   h.bucket_start[1] - h.bucket_start[0], x, bs, s);
+        for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
+          launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], h.uniform,
+                                     M->lev<T>(l).belems + h.bucket_start[bk],
+                                     h.bucket_start[bk + 1] - h.bucket_start[bk], x, bs, s);
       });
       cur = next;
       continue;

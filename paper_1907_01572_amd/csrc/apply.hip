@@ -152,11 +152,67 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
   return tk;
 }
 
+// The Jacobi-scaled Chebyshev step behind a fused apply: region[0 .. n^3) holds r = b - A x of
+// element e (the face buffers are free by then). z = M^-1 r (the packed block over the
+// workgroup's waves, partial z per wave after r; or z = dinv r), p and x are updated, and with
+// bs.trace_out the face traces of the new x are written as trace_kernel writes them. NC: n
+// when fixed at compile time, else 0.
+template <typename T, int NC>
+__device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* region, const T* dfo, int NM,
+                                const BlockStep<T>& bs) {
+  const int N = NC ? NC : n_rt, N2 = N * N, N3 = N2 * N;
+  constexpr int kWaves = kThreads / 64;
+  static_assert(kWaves >= 1, "the fused step needs whole waves");
+  const T* rs = region;
+  const int lane = int(threadIdx.x & 63);
+  const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
+  T* zs = region + N3 + wv * N3;
+  if (!bs.dinv) {
+    for (int i = lane; i < N3; i += 64) zs[i] = 0;
+    __syncthreads();
+    packed_block_partial<T, T>(bs.P + bs.poff[e], N3, rs, zs, kWaves, wv, lane);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < N3; i += kThreads) {
+    T z = 0;
+    if (bs.dinv) {
+      z = bs.dinv[I.off + i] * rs[i];
+    } else {
+#pragma unroll
+      for (int k = 0; k < kWaves; ++k) z += rs[N3 + k * N3 + i];
+    }
+    const T pn = bs.first ? bs.alpha * z : bs.alpha * z + bs.beta * bs.p[I.off + i];
+    bs.p[I.off + i] = pn;
+    const T xn = bs.x[I.off + i] + pn;
+    bs.x[I.off + i] = xn;
+    region[i] = xn;  // r is no longer read (each thread reads only its own partials after it)
+  }
+  if (bs.trace_out) {
+    // the next step's traces (as trace_kernel): values on each face and the reference normal
+    // derivative there
+    __syncthreads();
+    for (int g = threadIdx.x; g < 12 * N2; g += kThreads) {
+      const int f = g / (2 * N2), r = g % (2 * N2), li = r % N2;
+      const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const int i = li % N, j = li / N;
+      T v;
+      if (r < N2) {
+        v = region[vidx(N, d, t0, t1, (f & 1) ? N - 1 : 0, i, j)];
+      } else {
+        v = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) v += dfo[(f & 1) * NM + k] * region[vidx(N, d, t0, t1, k, i, j)];
+      }
+      bs.trace_out[I.toff + g] = v;
+    }
+  }
+}
+
 // Face terms of a level whose elements all have N nodes and whose mortars all have Q GL
 // points per axis (uniform degree): every size is a compile-time constant, the six 1-D
 // matrices (values / derivatives at the full, lower-half and upper-half point sets) are
 // staged in LDS once, and each phase maps threads to (task, item) with constant strides.
-// Adds the face terms to sy and writes y (FUSE: runs the block-Jacobi Chebyshev step bs on
+// Adds the face terms to sy and writes y (FUSE: runs the Jacobi-scaled Chebyshev step bs on
 // the result instead, in the same workgroup).
 template <typename T, int N, int Q, bool COMPACT, bool FUSE>
 __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, T* __restrict__ y,
@@ -370,54 +426,7 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
   } else {
     for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) finish(idx, sy[idx]);
   }
-  if constexpr (FUSE) {
-    // z = Binv r over the four waves (column blocks taken in turn), partial z per wave after r
-    constexpr int kWaves = kThreads / 64;
-    static_assert(kWaves >= 1, "the fused step needs whole waves");
-    const T* rs = region;
-    const int lane = int(threadIdx.x & 63);
-    const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
-    T* zs = region + N3 + wv * N3;
-    if (!bs.dinv) {
-      for (int i = lane; i < N3; i += 64) zs[i] = 0;
-      __syncthreads();
-      packed_block_partial<T, T>(bs.P + bs.poff[e], N3, rs, zs, kWaves, wv, lane);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < N3; i += kThreads) {
-      T z = 0;
-      if (bs.dinv) {
-        z = bs.dinv[I.off + i] * rs[i];
-      } else {
-#pragma unroll
-        for (int k = 0; k < kWaves; ++k) z += rs[N3 + k * N3 + i];
-      }
-      const T pn = bs.first ? bs.alpha * z : bs.alpha * z + bs.beta * bs.p[I.off + i];
-      bs.p[I.off + i] = pn;
-      const T xn = bs.x[I.off + i] + pn;
-      bs.x[I.off + i] = xn;
-      region[i] = xn;  // r is no longer read (each thread reads only its own partials after it)
-    }
-    if (bs.trace_out) {
-      // the next step's traces (as trace_kernel): values on each face and the reference
-      // normal derivative there
-      __syncthreads();
-      for (int g = threadIdx.x; g < 12 * N2; g += kThreads) {
-        const int f = g / (2 * N2), r = g % (2 * N2), li = r % N2;
-        const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-        const int i = li % N, j = li / N;
-        T v;
-        if (r < N2) {
-          v = region[vidx(N, d, t0, t1, (f & 1) ? N - 1 : 0, i, j)];
-        } else {
-          v = 0;
-#pragma unroll
-          for (int k = 0; k < N; ++k) v += dfo[(f & 1) * NM + k] * region[vidx(N, d, t0, t1, k, i, j)];
-        }
-        bs.trace_out[I.toff + g] = v;
-      }
-    }
-  }
+  if constexpr (FUSE) fused_step_tail<T, N>(N, I, e, region, dfo, NM, bs);
 }
 
 // Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD b % 8), each with
@@ -436,7 +445,6 @@ template <typename T, int NT, int QT, bool UNI, bool FUSE = false>
 __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const int* __restrict__ elems,
                                                          long long count, const T* x, T* __restrict__ y,
                                                          BlockStep<T> bs) {
-  static_assert(!FUSE || UNI, "the fused smoother step runs on one-degree levels only");
   extern __shared__ unsigned char smem_raw[];
   if ((long long)blockIdx.x >= count) return;
   const unsigned bid = xcd_remap(blockIdx.x, gridDim.x);  // gridDim.x == count
@@ -445,6 +453,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const int n = NT ? NT : I.n, q = QT ? QT : I.q;
   const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
   constexpr bool COMPACT = NT > 0 && NT * NT * NT <= 2 * kThreads;
+  static_assert(!FUSE || (UNI && COMPACT), "the fused smoother step runs on one-degree levels (compact layout)");
   const Layout lay(L.nmax, L.qmax, L.qmmax, COMPACT);
   const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
 
@@ -864,18 +873,20 @@ void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const
 }
 
 bool apply_block_fusable(int nmax, int qmax, int qmmax, int n, int q, int uniform) {
-  if (!uniform || n * n * n > 2 * kThreads || kThreads % 64 != 0 || n > 8 || q > 9) return false;
+  // mixed-degree levels keep the separate kernels: fused per degree bucket they measured slower
+  if (!uniform || n * n * n > 2 * kThreads || kThreads % 64 != 0 || n < 2 || n > 8 || q < n || q > n + 1)
+    return false;
   const Layout lay(nmax, qmax, qmmax, true);
-  // r and one partial z per wave in the face buffers before the face sums (mats, RA, RB)
-  return 6LL * lay.QMM * lay.NM + lay.ra + lay.rb >= (1LL + kThreads / 64) * n * n * n;
+  // r and one partial z per wave in the face buffers before the face sums (RA, RB)
+  return lay.ra + lay.rb >= (1LL + kThreads / 64) * n * n * n;
 }
 
 template <typename T>
-void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x,
-                             const BlockStep<T>& bs, hipStream_t s) {
+void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
+                             const T* x, const BlockStep<T>& bs, hipStream_t s) {
   if (count == 0) return;
-  if (!apply_block_fusable(L.nmax, L.qmax, L.qmmax, n, q, 1))
-    throw Error(-7, "fused block step: level not uniform or degree outside the compact layout");
+  if (!apply_block_fusable(L.nmax, L.qmax, L.qmmax, n, q, uniform))
+    throw Error(-7, "fused smoother step: level of several degrees, or degree outside the compact layout");
   const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), true);
 #define HPDG_CASE(NN, QQ) \
   if (n == NN && q == QQ) return launch_fixed<T, NN, QQ, true, true>(L, elems, count, x, nullptr, lds, s, bs);
@@ -886,9 +897,9 @@ void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* ele
   throw Error(-7, "fused block step: no kernel for this (n, q)");
 }
 
-template void launch_apply_block_cheb<double>(const LevelView<double>&, int, int, const int*, long long,
+template void launch_apply_block_cheb<double>(const LevelView<double>&, int, int, int, const int*, long long,
                                               const double*, const BlockStep<double>&, hipStream_t);
-template void launch_apply_block_cheb<float>(const LevelView<float>&, int, int, const int*, long long,
+template void launch_apply_block_cheb<float>(const LevelView<float>&, int, int, int, const int*, long long,
                                              const float*, const BlockStep<float>&, hipStream_t);
 template void launch_traces<double>(const LevelView<double>&, const double*, hipStream_t);
 template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t);

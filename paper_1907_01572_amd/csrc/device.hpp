@@ -74,12 +74,14 @@ struct BlockStep {
   T alpha, beta;
   int first;
 };
-// whether the level's elements (one bucket of degree n - 1, q GL points) can take the fused step:
-// a uniform level, the compact apply layout (n^3 <= 512) and LDS room for r and 4 partial z
+// whether the elements of one bucket (degree n - 1, q GL points) can take the fused step: a
+// uniform level, the compact apply layout (n^3 <= 512, q = n or n + 1) and LDS room for r and
+// 4 partial z
 bool apply_block_fusable(int nmax, int qmax, int qmmax, int n, int q, int uniform);
-// launch_traces first; then the apply and the step for the elements elems[0..count)
+// the apply and the step for the elements elems[0..count) of the level's one bucket (uniform
+// must be 1); L.trace must hold the traces of x
 template <typename T>
-void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* elems, long long count,
+void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
                              const T* x, const BlockStep<T>& bs, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const TransferView<T>& V, const T* uc, T* uf, hipStream_t s);

@@ -143,9 +143,9 @@ def test_smoother_and_vcycle_parity(ctx, name, smoother):
 @pytest.mark.parametrize("name,smoother", [("shell_l2_p3_r1e3", "block"), ("cube_l1_p7", "block"),
                                            ("shell_l2_p3_r1e3", "point")])
 def test_fused_block_step_matches_separate_kernels(ctx, name, smoother):
-    # one-degree levels run each Jacobi-scaled Chebyshev step that needs A x as one kernel per
-    # element; the arithmetic is the separate kernels' (the block partial sums may be taken
-    # by a different number of waves, so FP32 agrees to rounding)
+    # on one-degree levels each Jacobi-scaled Chebyshev step that needs A x runs as one kernel
+    # per element; the arithmetic is the separate kernels' (the block partial sums may be
+    # taken by a different number of waves, so FP32 agrees to rounding)
     maker, prob = MESHES[name]
     m = maker()
     out = {}
