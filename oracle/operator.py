@@ -269,7 +269,8 @@ class SIPG:
         return dg
 
     def rhs(self, problem=None):
-        """F(psi) = int g psi + sum_{Dirichlet} int g_D (-k n.grad psi + sigma psi)  (Eq. Fh2)."""
+        """F(psi) = int g psi + sum_{Dirichlet} int g_D (-k n.grad psi + sigma psi)  (Eq. Fh2)
+        + sum_{Neumann} int g_N psi (Eq. NeumannBC)."""
         problem = problem if problem is not None else self.problem
         F = np.zeros(self.ndof)
         for g in self.vgroups:
@@ -286,6 +287,23 @@ class SIPG:
             Bc = -g["wS"] * g["kx"] * gd
             ym = A @ g["Vm"] + np.einsum("mp,mpd,dpa->ma", Bc, g["mvec_m"], g["Dm"])
             np.add.at(F, g["idx_m"], ym)
+        # Neumann faces (Eq. NeumannBC): the boundary term int g_N psi of the integration by
+        # parts, with the face's own rule
+        for mt in self.mortars:
+            if mt["ep"] >= 0 or mt["bc"] != NEUMANN:
+                continue
+            em, fm, nm, qm = mt["em"], mt["fm"], int(self.n[mt["em"]]), self.q_mortar(mt)
+            eta, w = rules.gl(qm)
+            s_, t_ = np.meshgrid(eta, eta, indexing="xy")
+            xim = face_point(fm, s_.reshape(-1), t_.reshape(-1))
+            Vm, _ = _basis_at(nm, xim)
+            x, J = geometry.element_map(self.mesh, np.array([[em]]), xim[None])
+            row = np.linalg.inv(J)[0, :, fm // 2, :]
+            nrm = np.linalg.norm(row, axis=-1)
+            nhat = (1.0 if fm % 2 else -1.0) * row / nrm[:, None]
+            wS = np.outer(w, w).reshape(-1) * np.linalg.det(J)[0] * nrm
+            gN = problems.neumann_g(problem, x[0], nhat, self.k(x[0]))
+            F[self.offsets[em] + np.arange(nm ** 3)] += (wS * gN) @ Vm
         return F
 
     def interpolate(self, func):

@@ -138,6 +138,40 @@ def dirichlet_g(problem, x):
     return exact_u(problem, x)
 
 
+def grad_u(problem, x):
+    """grad u of the manufactured u, for the kinds that carry Neumann data."""
+    kind = problem["kind"]
+    X, Y, Z = x[..., 0], x[..., 1], x[..., 2]
+    if kind == "sinsinsin":
+        sx, sy, sz = np.sin(np.pi * X), np.sin(np.pi * Y), np.sin(np.pi * Z)
+        cx, cy, cz = np.cos(np.pi * X), np.cos(np.pi * Y), np.cos(np.pi * Z)
+        return np.pi * np.stack([cx * sy * sz, sx * cy * sz, sx * sy * cz], axis=-1)
+    if kind in ("polynomial", "polynomial_dirichlet"):
+        C = _poly_coeffs(problem)
+        P = C.shape[0]
+        gx, gy, gz = (np.zeros(x.shape[:-1]) for _ in range(3))
+        for a in range(P):
+            for b in range(P):
+                for c in range(P):
+                    if a >= 1:
+                        gx += C[a, b, c] * a * X ** (a - 1) * Y ** b * Z ** c
+                    if b >= 1:
+                        gy += C[a, b, c] * b * X ** a * Y ** (b - 1) * Z ** c
+                    if c >= 1:
+                        gz += C[a, b, c] * c * X ** a * Y ** b * Z ** (c - 1)
+        return np.stack([gx, gy, gz], axis=-1)
+    raise ValueError("no Neumann data for problem kind %s" % kind)
+
+
+def neumann_g(problem, x, nhat, kx):
+    """Neumann data (Eq. NeumannBC, as the flux k n.grad u of the form -div(k grad u) = g):
+    g_N = k grad u . n with n the outward unit normal; 0 for "gaussians" (a source with
+    homogeneous boundary data)."""
+    if problem["kind"] == "gaussians":
+        return np.zeros(x.shape[:-1])
+    return kx * np.einsum("...d,...d->...", grad_u(problem, x), nhat)
+
+
 def _poly_coeffs(problem):
     C = np.asarray(problem["params"], float)
     P = int(round(len(C) ** (1.0 / 3.0)))

@@ -7,7 +7,9 @@ Each pin is fixed by the mathematics, not by the oracle's own formulas:
 * A 1 = 0 with Neumann boundaries (constants are in the kernel of the broken
   gradient and have no jumps), on curved, 2:1 and variable-degree meshes;
 * polynomial consistency: on affine meshes all integrals are exact, SIPG is
-  consistent, so A u_I = F for u in Q_pmin with g = -lap u and g_D = u;
+  consistent, so A u_I = F for u in Q_pmin with g = -lap u and g_D = u, also with Neumann
+  data g_N = n.grad u on part of the boundary (Eq. NeumannBC); with Neumann data on all of
+  it, the data satisfy the divergence theorem (F . 1 = 0);
 * L2 convergence of order p + 1 for a smooth solution (the L2 rate of the
   adjoint-consistent SIPG method; Sec. II.E.1 states the energy-norm rate p).
 """
@@ -93,6 +95,58 @@ def test_polynomial_consistency_fails_with_planted_sign_error():
     u = op.interpolate(lambda X: P.exact_u(prob, X))
     F = op.rhs()
     assert np.linalg.norm(op.apply(u) - F) > 1e-6 * np.linalg.norm(F)
+
+
+def _neumann_faces(m, faces):
+    # the listed macro faces that lie on the boundary carry Neumann data (Eq. NeumannBC)
+    m = dict(m)
+    bc = np.array(m["macro_bc"], copy=True)
+    for f in faces:
+        bc[bc[:, f] == 1, f] = 2
+    m["macro_bc"] = bc
+    return m
+
+
+@pytest.mark.parametrize("name,deg", [("cube_p2", 2), ("box_2to1_p2", 2), ("hp_var_p", 1),
+                                      ("skew_affine", 2)])
+def test_polynomial_consistency_with_neumann_faces(name, deg):
+    # SIPG stays consistent with Neumann data g_N = n.grad u on part of the boundary: A u_I = F
+    prob = polynomial_problem(deg, seed=11, total=(name == "skew_affine"))
+    op = SIPG(_neumann_faces(MESHES[name](), (0, 3, 4)), prob)
+    u = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    assert np.linalg.norm(op.apply(u) - F) <= 1e-13 * np.linalg.norm(F)
+
+
+def test_neumann_consistency_fails_with_planted_sign_error(monkeypatch):
+    # outward normal taken inward in the Neumann data: the consistency pin above must fail
+    prob = polynomial_problem(2, seed=11)
+    good = P.neumann_g
+    monkeypatch.setattr(P, "neumann_g", lambda pr, x, n, k: good(pr, x, -n, k))
+    op = SIPG(_neumann_faces(MESHES["box_2to1_p2"](), (0, 3, 4)), prob)
+    u = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    assert np.linalg.norm(op.apply(u) - F) > 1e-6 * np.linalg.norm(F)
+
+
+@pytest.mark.parametrize("name", ["cube_p2", "box_2to1_p2", "skew_affine"])
+def test_pure_neumann_data_satisfy_divergence_theorem(name):
+    # all faces Neumann: the constant test function (all ones in the LGL basis) sees
+    # int g + int_boundary n.grad u = int (-lap u) + int n.grad u = 0 (exact quadrature)
+    prob = polynomial_problem(2, seed=3, total=True)
+    op = SIPG(_neumann_faces(MESHES[name](), range(6)), prob)
+    F = op.rhs()
+    src = SIPG(MESHES[name](), dict(prob, kind="polynomial")).rhs()  # scale: the source part alone
+    assert abs(F.sum()) <= 1e-12 * np.abs(src).sum()
+
+
+@pytest.mark.parametrize("prob", [dict(kind="sinsinsin", params=np.zeros(0)), polynomial_problem(3, seed=5)])
+def test_grad_u_matches_differences_of_u(prob):
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0.1, 0.9, (20, 3))
+    h = 1e-5
+    fd = np.stack([(P.exact_u(prob, x + h * e) - P.exact_u(prob, x - h * e)) / (2 * h) for e in np.eye(3)], -1)
+    assert np.abs(P.grad_u(prob, x) - fd).max() <= 1e-8 * max(1.0, np.abs(fd).max())
 
 
 def test_penalty_length_is_element_size():
