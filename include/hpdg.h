@@ -255,8 +255,12 @@ int hpdg_level_cells(const hpdg_mesh* mesh, int level, int32_t* macro, int32_t* 
 int hpdg_mesh_free(hpdg_mesh* mesh);
 
 /* F = F_h(psi) (Eq. Fh2) for an analytic source g and Dirichlet data g_D = u, written
- * to the device FP64 vector F_dev of level 0.  Computed on the host in FP64, then
- * copied (stream-ordered). */
+ * to the device FP64 vector F_dev of level 0.  Faces marked Neumann in the mesh (macro
+ * face kind 2) add int g_N psi with g_N = k n.grad u (Eq. NeumannBC, n the outward normal)
+ * for HPDG_RHS_SINSINSIN, HPDG_RHS_POLYNOMIAL and HPDG_RHS_POLYNOMIAL_DIRICHLET, and
+ * g_N = 0 for HPDG_RHS_GAUSSIANS; other kinds with Neumann faces return HPDG_ERR_UNSUPPORTED.
+ * Every face integral uses the face's own rule.  Computed on the host in FP64, then copied
+ * (stream-ordered). */
 int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream);
 
 /* y = A_level x (Eq. lh2 applied matrix-free): volume stiffness by sum factorisation,

@@ -161,8 +161,7 @@ template <typename T, int NC>
 __device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* region, const T* dfo, int NM,
                                 const BlockStep<T>& bs) {
   const int N = NC ? NC : n_rt, N2 = N * N, N3 = N2 * N;
-  constexpr int kWaves = kThreads / 64;
-  static_assert(kWaves >= 1, "the fused step needs whole waves");
+  constexpr int kWaves = kThreads >= 64 ? kThreads / 64 : 1;  // the launcher requires whole waves
   const T* rs = region;
   const int lane = int(threadIdx.x & 63);
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -453,7 +452,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const int n = NT ? NT : I.n, q = QT ? QT : I.q;
   const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
   constexpr bool COMPACT = NT > 0 && NT * NT * NT <= 2 * kThreads;
-  static_assert(!FUSE || (UNI && COMPACT), "the fused smoother step runs on one-degree levels (compact layout)");
+  static_assert(!FUSE || UNI, "the fused smoother step runs on one-degree levels");
   const Layout lay(L.nmax, L.qmax, L.qmmax, COMPACT);
   const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
 

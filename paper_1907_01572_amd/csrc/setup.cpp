@@ -544,6 +544,33 @@ double exact_u(int kind, const std::vector<double>& P, const double x[3]) {
   }
 }
 
+// grad u of the manufactured u for the kinds with Neumann data (sin sin sin, the polynomial
+// kinds); false for the others
+bool exact_grad(int kind, const std::vector<double>& P, const double x[3], double g[3]) {
+  const double X = x[0], Y = x[1], Z = x[2];
+  if (kind == 0) {
+    const double sx = std::sin(M_PI * X), sy = std::sin(M_PI * Y), sz = std::sin(M_PI * Z);
+    g[0] = M_PI * std::cos(M_PI * X) * sy * sz;
+    g[1] = M_PI * sx * std::cos(M_PI * Y) * sz;
+    g[2] = M_PI * sx * sy * std::cos(M_PI * Z);
+    return true;
+  }
+  if (kind == 3 || kind == 5) {
+    const int K = int(std::lround(std::cbrt(double(P.size()))));
+    g[0] = g[1] = g[2] = 0;
+    for (int a = 0; a < K; ++a)
+      for (int b = 0; b < K; ++b)
+        for (int c = 0; c < K; ++c) {
+          const double C = P[(a * K + b) * K + c];
+          if (a >= 1) g[0] += C * a * std::pow(X, a - 1) * std::pow(Y, b) * std::pow(Z, c);
+          if (b >= 1) g[1] += C * b * std::pow(X, a) * std::pow(Y, b - 1) * std::pow(Z, c);
+          if (c >= 1) g[2] += C * c * std::pow(X, a) * std::pow(Y, b) * std::pow(Z, c - 1);
+        }
+    return true;
+  }
+  return false;
+}
+
 double source(int kind, const std::vector<double>& P, const double x[3]) {
   const double X = x[0], Y = x[1], Z = x[2];
   switch (kind) {
@@ -711,7 +738,50 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
           }
       }
   }
-  (void)dp;
+  // Neumann faces (Eq. NeumannBC): int g_N psi, g_N = k grad u . n (outward n; 0 for the
+  // Gaussian sources), with the face's own rule (n points, n + quad_extra on curved faces or
+  // with variable k); only the face layer of the element's nodes is nonzero on the face
+  for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
+    const MortarInfo& M = L.minfo[mi];
+    if (M.ep >= 0 || M.bc != 2) continue;
+    if (kind != 4) {
+      double g0[3];
+      const double x0[3] = {0, 0, 0};
+      if (!exact_grad(kind, P, x0, g0)) throw Error(-7, "no Neumann data for this right-hand-side kind");
+    }
+    const ElemInfo& I = L.einfo[M.em];
+    const Cell& cell = L.cells[M.em];
+    const bool curved = mm.macros[cell.macro].kind != 0;
+    const int n = I.n, q = n + ((curved || !kconst(dp)) ? dp.quad_extra : 0);
+    if (q > kMaxQ) throw Error(-2, "too many quadrature points");
+    const int f = M.fm, d = f >> 1, t0 = d == 0 ? 1 : 0, t1_ = d == 2 ? 1 : 2;
+    const double sgn = (f & 1) ? 1.0 : -1.0;
+    const double* La = td + T.index(OpTable::GL_VAL, n, q);
+    const double* wq = td + T.w_off[q];
+    const double* eta = td + T.gl_off[q];
+    const int kf = (f & 1) ? n - 1 : 0;
+    for (int y = 0; y < q; ++y)
+      for (int x = 0; x < q; ++x) {
+        double xi[3], xx[3], J[3][3], Ji[3][3], g[3] = {0, 0, 0};
+        xi[d] = sgn;
+        xi[t0] = eta[x];
+        xi[t1_] = eta[y];
+        cell_eval(mm, cell, xi, xx, J);
+        inv3(J, Ji);
+        const double nr = std::sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
+        if (kind != 4) exact_grad(kind, P, xx, g);
+        const double gN = coef_k(dp, xx) * sgn * (Ji[d][0] * g[0] + Ji[d][1] * g[1] + Ji[d][2] * g[2]) / nr;
+        const double v = wq[x] * wq[y] * det3(J) * nr * gN;
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            int idx[3];
+            idx[d] = kf;
+            idx[t0] = i;
+            idx[t1_] = j;
+            F[size_t(I.off) + (idx[2] * n + idx[1]) * n + idx[0]] += v * La[x * n + i] * La[y * n + j];
+          }
+      }
+  }
 }
 
 }  // namespace hpdg

@@ -11,6 +11,7 @@ import numpy as np
 import pytest
 
 import meshgen
+from oracle import problems as P
 from oracle.operator import SIPG
 from oracle.solvers import Multigrid, chebyshev, fgmres
 from tests.gpu_common import MESHES, TOL_APPLY, TOL_APPLY_COMPACTIFIED, coef_of, dof_perm, rel
@@ -94,6 +95,61 @@ def test_rhs_parity(ctx):
         print("rhs", name, err, flush=True)
         assert err <= TOL_APPLY
         M.free()
+
+
+def _neumann_faces(m, faces):
+    m = dict(m)
+    bc = np.array(m["macro_bc"], copy=True)
+    for f in faces:
+        bc[bc[:, f] == 1, f] = 2
+    m["macro_bc"] = bc
+    return m
+
+
+def test_rhs_parity_with_neumann_faces(ctx):
+    # Neumann data g_N = k n.grad u (Eq. NeumannBC) on three of the six sides
+    probs = [meshgen.polynomial_problem(2, seed=11), dict(kind="sinsinsin", params=np.zeros(0)),
+             meshgen.gaussian_problem(n=4, seed=1)]
+    for name in ["box_2to1_p3", "shell_l2_p3_r1e3"]:
+        m = _neumann_faces(MESHES[name][0](), (0, 3, 4))
+        for prob in probs:
+            M = ctx.upload(m)
+            F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+            M.assemble_rhs(prob, F)
+            op = SIPG(m, prob)
+            err = rel(host(F), op.rhs()[dof_perm(M.level_cells(0), op.mesh)])
+            print("rhs with Neumann faces", name, prob["kind"], err, flush=True)
+            assert err <= TOL_APPLY
+            M.free()
+
+
+def test_rhs_neumann_faces_refuse_kinds_without_data(ctx):
+    m = _neumann_faces(MESHES["box_2to1_p3"][0](), (0,))
+    M = ctx.upload(m)
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    with pytest.raises(RuntimeError):
+        M.assemble_rhs(meshgen.problem_config2(), F)  # the shell harmonic has no Neumann data here
+    M.free()
+
+
+def test_solve_with_neumann_faces_reproduces_polynomial(ctx):
+    # affine 2:1 box, u in Q_2, Dirichlet on three sides and Neumann on the others: SIPG is
+    # consistent, so the discrete solution is the interpolant of u
+    m = _neumann_faces(meshgen.box_grid((1, 1, 1), 1, 2, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+                       (0, 3, 4))
+    prob = meshgen.polynomial_problem(2, seed=11)
+    M = ctx.upload(m)
+    M.setup_smoother(n_cheb=4, smoother="block")
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    M.assemble_rhs(prob, F)
+    u = torch.zeros_like(F)
+    st = M.solve(F, u, tol=1e-12, max_iter=300)
+    op = SIPG(m, prob)
+    ui = op.interpolate(lambda X: P.exact_u(prob, X))[dof_perm(M.level_cells(0), op.mesh)]
+    err = np.abs(host(u) - ui).max() / np.abs(ui).max()
+    print("Neumann solve", st, "max err vs interpolant", err, flush=True)
+    assert err <= 1e-9
+    M.free()
 
 
 def test_rhs_parity_with_mass_term(ctx):
