@@ -234,7 +234,7 @@ def main():
                           out=os.path.join(ROOT, TRAFFIC_FILE))
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus %d is not supported" % args.gpus}))
+        print(json.dumps({"error": "the benchmark runs on one GPU only (no multi-GPU path); --gpus %d is not supported" % args.gpus}))
         sys.exit(2)
 
     import torch
