@@ -11,7 +11,9 @@ benchmark (FP64 level 0, FP32 copies built).
   matching the oracle's;
 * puncture mesh, p = 6, 12,739,363 DOF: nonlinear residual rows and, after
   linearisation, Jacobian rows;
-* the shell's first coarse level (1,056 cells): operator rows.
+* the shell's first coarse level (1,056 cells): operator rows;
+* the shell's smoother as the benchmark runs it (the fused apply + block-Jacobi step)
+  against the separate kernels, FP64 and FP32, fine and first coarse level, and a V-cycle.
 """
 import numpy as np
 import pytest
@@ -168,4 +170,42 @@ def test_fullsize_shell_level1_apply_rows(ctx):
     err = rel_rows(host(y), op.apply(x), rows)
     print("shell level 1:", len(m1["elem_p"]), "cells, sampled rows FP64", err, flush=True)
     assert err <= TOL_APPLY_COMPACTIFIED
+    M.free()
+
+
+def test_fullsize_shell_fused_smoothing_matches_separate_kernels(ctx):
+    # the bench's smoother on the bench's mesh and hierarchy: block-Jacobi Chebyshev steps as
+    # one fused kernel per element (the timed path) against the separate apply and block
+    # kernels (whose apply rows are checked against the oracle above), on the fine level and
+    # the first coarse level, FP64 and FP32, and one V-cycle
+    m, prob = meshgen.cubed_sphere_shell(level=3, p=5), meshgen.problem_config2()
+    M = ctx.upload(m, coef=coef_of(prob), build_f32=True, max_levels=4)
+    rng = np.random.default_rng(5)
+    vecs = {l: rng.standard_normal((2, M.n_dof[l])) for l in (0, 1)}
+    r = rng.standard_normal(M.n_dof[0])
+    out, lam = {}, None
+    for fused in (True, False):
+        M.setup_smoother(n_cheb=26, Lambda=600.0, smoother="block", fused=fused, lambda_max=lam)
+        lam = M.lambda_max
+        M.timing_enable(1)
+        res = {}
+        for dt in (torch.float64, torch.float32):
+            for l in (0, 1):
+                b, x0 = vecs[l]
+                x = torch.tensor(x0, dtype=dt, device="cuda")
+                M.smooth(torch.tensor(b, dtype=dt, device="cuda"), x, level=l, n_iter=4)
+                res[(dt, l)] = host(x)
+            z = torch.zeros(M.n_dof[0], dtype=dt, device="cuda")
+            M.vcycle(torch.tensor(r, dtype=dt, device="cuda"), z)
+            res[(dt, "v")] = host(z)
+        fused_launches = M.kernel_timing("smooth", 0, hp.F64)[1]
+        M.timing_enable(0)
+        out[fused] = (res, fused_launches)
+    assert out[True][1] > 0 and out[False][1] == 0
+    for key, a in out[True][0].items():
+        b = out[False][0][key]
+        err = float(np.linalg.norm(a - b) / np.linalg.norm(b))
+        tol = 1e-13 if key[0] == torch.float64 else 1e-5
+        print("shell fused vs separate", key, err, flush=True)
+        assert err <= tol, key
     M.free()
