@@ -214,11 +214,15 @@ def test_fused_block_step_matches_separate_kernels(ctx, name, smoother):
         M.timing_enable(1)
         res = {}
         for dt in (torch.float64, torch.float32):
-            x = torch.tensor(x0, dtype=dt, device="cuda")
-            M.smooth(torch.tensor(b, dtype=dt, device="cuda"), x, level=0, n_iter=4)
+            # one fused step (no trace hand-off), two (one hand-off), four
+            xs = []
+            for n_iter in (1, 2, 4):
+                x = torch.tensor(x0, dtype=dt, device="cuda")
+                M.smooth(torch.tensor(b, dtype=dt, device="cuda"), x, level=0, n_iter=n_iter)
+                xs.append(host(x))
             z = torch.zeros(n, dtype=dt, device="cuda")
             M.vcycle(torch.tensor(r, dtype=dt, device="cuda"), z)
-            res[dt] = (host(x), host(z))
+            res[dt] = (np.concatenate(xs), host(z))
         launches = {k: M.kernel_timing(k, 0, hp.F64)[1] for k in ("smooth", "block")}
         M.timing_enable(0)
         out[fused] = (res, launches)
