@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <thread>
 
 namespace hpdg {
 
@@ -656,43 +657,57 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
                   int kind, const std::vector<double>& P, std::vector<double>& F) {
   F.assign(size_t(L.ndof), 0.0);
   const double* td = T.data.data();
-  std::vector<double> gq, t1, t2;
-  for (size_t e = 0; e < L.einfo.size(); ++e) {
-    const ElemInfo& I = L.einfo[e];
-    const int n = I.n, q = I.q;
-    const double* B = td + T.index(OpTable::GL_VAL, n, q);
-    const double* w = td + T.w_off[q];
-    const double* eta = td + T.gl_off[q];
-    gq.assign(size_t(q) * q * q, 0.0);
-    for (int c = 0; c < q; ++c)
-      for (int b = 0; b < q; ++b)
-        for (int a = 0; a < q; ++a) {
-          double xi[3] = {eta[a], eta[b], eta[c]}, x[3], J[3][3];
-          cell_eval(mm, L.cells[e], xi, x, J);
-          gq[(c * q + b) * q + a] = w[a] * w[b] * w[c] * det3(J) * source(kind, P, x);
-        }
-    t1.assign(size_t(q) * q * n, 0.0);
-    t2.assign(size_t(q) * n * n, 0.0);
-    for (int cb = 0; cb < q * q; ++cb)
-      for (int i = 0; i < n; ++i) {
-        double s = 0;
-        for (int a = 0; a < q; ++a) s += B[a * n + i] * gq[cb * q + a];
-        t1[size_t(cb) * n + i] = s;
-      }
-    for (int c = 0; c < q; ++c)
-      for (int j = 0; j < n; ++j)
+  // volume terms: each element writes only its own entries, so contiguous element ranges run
+  // on separate host threads (the result does not depend on the split)
+  auto volume = [&](size_t e_begin, size_t e_end) {
+    std::vector<double> gq, t1, t2;
+    for (size_t e = e_begin; e < e_end; ++e) {
+      const ElemInfo& I = L.einfo[e];
+      const int n = I.n, q = I.q;
+      const double* B = td + T.index(OpTable::GL_VAL, n, q);
+      const double* w = td + T.w_off[q];
+      const double* eta = td + T.gl_off[q];
+      gq.assign(size_t(q) * q * q, 0.0);
+      for (int c = 0; c < q; ++c)
+        for (int b = 0; b < q; ++b)
+          for (int a = 0; a < q; ++a) {
+            double xi[3] = {eta[a], eta[b], eta[c]}, x[3], J[3][3];
+            cell_eval(mm, L.cells[e], xi, x, J);
+            gq[(c * q + b) * q + a] = w[a] * w[b] * w[c] * det3(J) * source(kind, P, x);
+          }
+      t1.assign(size_t(q) * q * n, 0.0);
+      t2.assign(size_t(q) * n * n, 0.0);
+      for (int cb = 0; cb < q * q; ++cb)
         for (int i = 0; i < n; ++i) {
           double s = 0;
-          for (int b = 0; b < q; ++b) s += B[b * n + j] * t1[(size_t(c) * q + b) * n + i];
-          t2[(size_t(c) * n + j) * n + i] = s;
+          for (int a = 0; a < q; ++a) s += B[a * n + i] * gq[cb * q + a];
+          t1[size_t(cb) * n + i] = s;
         }
-    for (int k = 0; k < n; ++k)
-      for (int j = 0; j < n; ++j)
-        for (int i = 0; i < n; ++i) {
-          double s = 0;
-          for (int c = 0; c < q; ++c) s += B[c * n + k] * t2[(size_t(c) * n + j) * n + i];
-          F[size_t(I.off) + (k * n + j) * n + i] += s;
-        }
+      for (int c = 0; c < q; ++c)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            double s = 0;
+            for (int b = 0; b < q; ++b) s += B[b * n + j] * t1[(size_t(c) * q + b) * n + i];
+            t2[(size_t(c) * n + j) * n + i] = s;
+          }
+      for (int k = 0; k < n; ++k)
+        for (int j = 0; j < n; ++j)
+          for (int i = 0; i < n; ++i) {
+            double s = 0;
+            for (int c = 0; c < q; ++c) s += B[c * n + k] * t2[(size_t(c) * n + j) * n + i];
+            F[size_t(I.off) + (k * n + j) * n + i] += s;
+          }
+    }
+  };
+  const size_t E = L.einfo.size();
+  const size_t nt = std::min<size_t>(std::max(1u, std::thread::hardware_concurrency()), std::max<size_t>(1, E / 256));
+  const size_t nthreads = std::min<size_t>(nt, 8);
+  if (nthreads <= 1) {
+    volume(0, E);
+  } else {
+    std::vector<std::thread> pool;
+    for (size_t t = 0; t < nthreads; ++t) pool.emplace_back(volume, E * t / nthreads, E * (t + 1) / nthreads);
+    for (std::thread& th : pool) th.join();
   }
   // Dirichlet faces: int g_D (sigma psi - k n.grad psi), with the face's own rule (a flat face
   // whose rule was raised to the volume rule's keeps its constant metric, valid at any q)
