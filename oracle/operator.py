@@ -346,6 +346,65 @@ class SIPG:
         return np.sqrt(err2)
 
 
+    def energy_error(self, u, func, grad_func, extra=3):
+        """||func - u_h||_* of Eq. energynorm: the broken H1 seminorm of the error on every
+        element plus the penalty-weighted squared jumps on every mortar where the penalty
+        acts (interior and Dirichlet faces; on a Dirichlet face the jump of nu is nu n).
+        ``func`` and ``grad_func`` give the exact solution and its physical gradient at
+        points [..., 3].  Integrals use q = p + 1 + extra GL points per axis (volume) and
+        p_m + 1 + extra (mortars); sigma = C p_m^2 / h_m as in Eq. penaltyparameter, without
+        the coefficient k (the norm as printed)."""
+        u = np.asarray(u, float)
+        err2 = 0.0
+        for n in sorted(set(int(x) for x in self.n)):
+            elems = np.where(self.n == n)[0]
+            q = n + extra
+            eta, w = rules.gl(q)
+            xi = np.stack(np.meshgrid(eta, eta, eta, indexing="ij")[::-1], axis=-1).reshape(-1, 3)
+            W = np.einsum("c,b,a->cba", w, w, w).reshape(-1)
+            _, D = _basis_at(n, xi)                               # [3, P, n^3]
+            x, J = geometry.element_map(self.mesh, elems[:, None], xi[None])
+            Ji = np.linalg.inv(J)                                 # [E, P, d, i]
+            U = u[self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]]
+            gxi = np.einsum("dpa,ea->epd", D, U)                  # reference gradient
+            gx = np.einsum("epdi,epd->epi", Ji, gxi)              # physical gradient
+            diff = grad_func(x) - gx
+            err2 += float(np.sum(W * np.linalg.det(J) * np.sum(diff * diff, axis=-1)))
+        for mt in self.mortars:
+            if mt["ep"] < 0 and mt["bc"] != DIRICHLET:
+                continue
+            em, fm = mt["em"], mt["fm"]
+            nm = int(self.n[em])
+            pm = nm - 1
+            if mt["ep"] >= 0:
+                pm = max(pm, int(self.n[mt["ep"]]) - 1)
+            qm = pm + 1 + extra
+            eta, w = rules.gl(qm)
+            s, t = np.meshgrid(eta, eta, indexing="xy")
+            s, t = s.reshape(-1), t.reshape(-1)
+            xim = face_point(fm, s, t)
+            x, J = geometry.element_map(self.mesh, np.full(len(s), em), xim)
+            row = np.linalg.inv(J)[:, fm // 2, :]
+            nrm = np.linalg.norm(row, axis=-1)
+            dS = np.outer(w, w).reshape(-1) * np.linalg.det(J) * nrm
+            h = 2.0 / nrm
+            Vm, _ = _basis_at(nm, xim)
+            um = Vm @ u[self.offsets[em] + np.arange(nm ** 3)]
+            if mt["ep"] >= 0:
+                ep, fp = mt["ep"], mt["fp"]
+                npl = int(self.n[ep])
+                a, b = minus_to_plus(mt, s, t)
+                xip = face_point(fp, a, b)
+                _, Jp = geometry.element_map(self.mesh, np.full(len(s), ep), xip)
+                h = np.minimum(h, 2.0 / np.linalg.norm(np.linalg.inv(Jp)[:, fp // 2, :], axis=-1))
+                Vp, _ = _basis_at(npl, xip)
+                jump = Vp @ u[self.offsets[ep] + np.arange(npl ** 3)] - um  # (u - u_h-) - (u - u_h+)
+            else:
+                jump = func(x) - um
+            err2 += float(np.sum(dS * (self.C * pm * pm / h) * jump * jump))
+        return np.sqrt(err2)
+
+
 def element_blocks(op):
     """Diagonal blocks A_ee (element with itself) of the operator, one dense matrix per element.
 

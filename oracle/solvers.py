@@ -139,45 +139,53 @@ def gershgorin_max(T):
 
 
 def splitmix64_uniform(n, seed):
-    """Uniform [-1, 1) values from the SplitMix64 generator (Steele, Lea, Flood 2014), counter i."""
-    mask = (1 << 64) - 1
-    out = np.empty(n)
-    for i in range(n):
-        z = (seed + (i + 1) * 0x9E3779B97F4A7C15) & mask
-        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & mask
-        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & mask
-        z = z ^ (z >> 31)
-        out[i] = (z >> 11) * (2.0 ** -53) * 2.0 - 1.0
-    return out
+    """Uniform [-1, 1) values from the SplitMix64 generator (Steele, Lea, Flood 2014): output i
+    mixes the counter state seed + (i + 1) * 0x9E3779B97F4A7C15 (mod 2^64); its top 53 bits give
+    a value in [0, 1), mapped to [-1, 1).  Vectorised in uint64 arithmetic (wraps mod 2^64)."""
+    i = np.arange(1, int(n) + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        z = np.uint64(int(seed) & ((1 << 64) - 1)) + i * np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) * 2.0 - 1.0
 
 
 class Multigrid:
     """Stored multigrid hierarchy with frozen Chebyshev bounds and an exact coarse solve."""
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
-                 n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None):
+                 n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None,
+                 starts=None, max_levels=32):
         """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi) or "block"
-        (element-block Jacobi); ``jacobi`` selects "point" / "none" when it is not given."""
-        meshes = hierarchy(mesh) if levels is None else levels
+        (element-block Jacobi); ``jacobi`` selects "point" / "none" when it is not given.
+        ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``)."""
+        meshes = hierarchy(mesh, max_levels) if levels is None else levels
         self.ops = [SIPG(m, problem, C=C, quad_extra=quad_extra, mass=mass) for m in meshes]
         self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
         self.n_cheb, self.Lambda = n_cheb, Lambda
         self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")
-        self.refresh(n_eigs, seed, lam)
+        self.refresh(n_eigs, seed, lam, starts)
 
-    def refresh(self, n_eigs=15, seed=0, lam=None):
+    def refresh(self, n_eigs=15, seed=0, lam=None, starts=None):
         """(Re)compute what depends on the level operators: the smoother scaling, the
-        coarsest factorisation and the frozen spectral bounds (given ``lam`` or by Alg. 5
-        from a seeded uniform start vector)."""
+        coarsest factorisation and the frozen spectral bounds (given ``lam`` or by Alg. 5).
+
+        Alg. 5's start vector b of a level is ``starts[l]`` when given, else the SplitMix64
+        uniform values ``splitmix64_uniform(ndof, seed)`` in this level's DOF order (x0 = 0, so
+        the first residual is b).  A caller whose DOF order differs (a permutation of the same
+        elements) passes the permuted generator output to reproduce the same Krylov process."""
         self.minv = [self._make_minv(op) for op in self.ops[:-1]]
         A0 = np.column_stack([self.ops[-1].apply(e) for e in np.eye(self.ops[-1].ndof)])
         self.A0 = 0.5 * (A0 + A0.T)
         self.chol = scipy.linalg.cho_factor(self.A0)
+        self.lanczos = []
         if lam is None:
             lam = []
-            for op, minv in zip(self.ops[:-1], self.minv):
-                b = np.random.default_rng(seed).uniform(-1.0, 1.0, op.ndof)
+            for l, (op, minv) in enumerate(zip(self.ops[:-1], self.minv)):
+                b = starts[l] if starts is not None else splitmix64_uniform(op.ndof, seed)
                 _, T = cg_lanczos(op.apply, b, n_eigs, minv=minv)
+                self.lanczos.append(T)
                 lam.append(gershgorin_max(T))
         self.lam = list(lam)
 

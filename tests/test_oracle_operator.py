@@ -11,7 +11,12 @@ Each pin is fixed by the mathematics, not by the oracle's own formulas:
   data g_N = n.grad u on part of the boundary (Eq. NeumannBC); with Neumann data on all of
   it, the data satisfy the divergence theorem (F . 1 = 0);
 * L2 convergence of order p + 1 for a smooth solution (the L2 rate of the
-  adjoint-consistent SIPG method; Sec. II.E.1 states the energy-norm rate p).
+  adjoint-consistent SIPG method) and energy-norm convergence of order p (Eq. energynorm,
+  the rate stated with Eq. expectedconvergence);
+* the energy norm's closed forms: the H1 seminorm of sin(pi x) sin(pi y) sin(pi z) on the
+  unit cube is 3 pi^2 / 8, and a constant u_h = 1 with u = 0 has only the Dirichlet-face
+  penalty term 6 C p^2 N on N^3 cells;
+* the element-diagonal blocks equal the diagonal blocks of the brute-force assembled matrix.
 """
 import numpy as np
 import pytest
@@ -19,7 +24,7 @@ import pytest
 import meshgen
 from meshgen.problems import polynomial_problem
 from oracle import problems as P
-from oracle.operator import SIPG, assemble_dense
+from oracle.operator import SIPG, assemble_dense, element_blocks
 from oracle.solvers import Multigrid, fcg
 
 MESHES = {
@@ -158,11 +163,13 @@ def test_penalty_length_is_element_size():
         np.testing.assert_allclose(g["wS"].sum(axis=1), 1.0 / N ** 2, rtol=1e-14)
 
 
-def _solve_sin(level, p):
+def _solve_sin(level, p, norm="l2"):
     prob = meshgen.problem_config1()
     mg = Multigrid(meshgen.unit_cube(level, p), prob, n_cheb=4)
     op = mg.ops[0]
     u, it, hist = fcg(op.apply, op.rhs(), mg.vcycle, tol=1e-12)
+    if norm == "energy":
+        return op.energy_error(u, lambda X: P.exact_u(prob, X), lambda X: P.grad_u(prob, X))
     return op.l2_error(u, lambda X: P.exact_u(prob, X))
 
 
@@ -171,6 +178,50 @@ def test_l2_convergence_order(p):
     e1, e2 = _solve_sin(2, p), _solve_sin(3, p)
     rate = np.log2(e1 / e2)
     assert abs(rate - (p + 1)) < 0.35, rate
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_energy_convergence_order(p):
+    # Eq. expectedconvergence: |u - u_h|_* <= C h^p for a smooth solution
+    e1, e2 = _solve_sin(2, p, "energy"), _solve_sin(3, p, "energy")
+    rate = np.log2(e1 / e2)
+    print("energy rate p=%d: %.3f" % (p, rate))
+    assert abs(rate - p) < 0.2, rate
+
+
+def test_energy_norm_closed_forms():
+    prob = meshgen.problem_config1()
+    op = SIPG(meshgen.unit_cube(2, 3), prob)
+    u_ex = lambda X: P.exact_u(prob, X)
+    g_ex = lambda X: P.grad_u(prob, X)
+    # u_h = 0: only the broken H1 seminorm of u (u vanishes on the boundary): 3 pi^2 / 8
+    e = op.energy_error(np.zeros(op.ndof), u_ex, g_ex, extra=6)
+    assert abs(e * e - 3 * np.pi ** 2 / 8) <= 1e-10 * 3 * np.pi ** 2 / 8
+    # u_h = 1 and u = 0: no gradient and no interior jumps; each Dirichlet face has jump 1 and
+    # sigma = C p^2 / h with h = 1/N: 6 C p^2 N
+    zero = lambda X: np.zeros(X.shape[:-1])
+    e = op.energy_error(np.ones(op.ndof), zero, lambda X: np.zeros(X.shape), extra=1)
+    np.testing.assert_allclose(e * e, 6 * 10.0 * 9 * 4, rtol=1e-13)
+    # a Q2 solution on a 2:1 mesh is reproduced exactly (consistency): zero energy error
+    prob2 = meshgen.problems.polynomial_problem(2, seed=3)
+    m = meshgen.box_grid((1, 1, 1), 1, 2, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5])
+    op2 = SIPG(m, prob2)
+    uI = op2.interpolate(lambda X: P.exact_u(prob2, X))
+    e0 = op2.energy_error(uI, lambda X: P.exact_u(prob2, X), lambda X: P.grad_u(prob2, X))
+    e1 = op2.energy_error(uI + 1e-3 * np.random.default_rng(0).standard_normal(op2.ndof),
+                          lambda X: P.exact_u(prob2, X), lambda X: P.grad_u(prob2, X))
+    assert e0 <= 1e-12 and e1 > 1e-4
+
+
+@pytest.mark.parametrize("name", ["hp_var_p", "box_2to1_p2", "shell_l1_p2"])
+def test_element_blocks_equal_assembled_diagonal_blocks(name):
+    op = SIPG(MESHES[name](), meshgen.problem_config3(r0=0.7))
+    A = assemble_dense(op)
+    blocks = element_blocks(op)
+    scale = np.abs(A).max()
+    for e, B in enumerate(blocks):
+        sl = slice(op.offsets[e], op.offsets[e + 1])
+        np.testing.assert_allclose(B, A[sl, sl], rtol=0, atol=1e-13 * scale)
 
 
 @pytest.mark.parametrize("name", ["hp_var_p", "shell_l1_p1", "box_2to1_p2"])
