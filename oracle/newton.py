@@ -28,33 +28,7 @@ import numpy as np
 
 from . import problems, rules
 from .mesh import parent_map
-from .solvers import Multigrid, fcg
-
-
-def inject(fine_op, coarse_op, uf):
-    """Coarse nodal values from the fine-level field: the fine polynomial of the child that
-    contains each coarse LGL node (lower child on the cut), evaluated there."""
-    uc = np.zeros(coarse_op.ndof)
-    for k, (K, bits) in enumerate(parent_map(fine_op.mesh, coarse_op.mesh)):
-        nf, nc = int(fine_op.n[k]), int(coarse_op.n[K])
-        xf, _ = rules.lgl(nf)
-        xc, _ = rules.lgl(nc)
-        mats, owned = [], []
-        for d in range(3):
-            if bits is None:
-                pts, own = xc, np.ones(nc, bool)
-            else:
-                b = bits[d]
-                pts = 2.0 * xc - 2.0 * b + 1.0          # coarse node in the child's coordinates
-                own = xc <= 0.0 if b == 0 else xc > 0.0  # nodes on the cut go to the lower child
-            mats.append(rules.lagrange(xf, pts))        # [coarse node, fine node]
-            owned.append(own)
-        U = uf[fine_op.offsets[k]:fine_op.offsets[k + 1]].reshape(nf, nf, nf)
-        vals = np.einsum("zc,yb,xa,cba->zyx", mats[2], mats[1], mats[0], U)
-        mask = owned[2][:, None, None] & owned[1][None, :, None] & owned[0][None, None, :]
-        block = uc[coarse_op.offsets[K]:coarse_op.offsets[K + 1]].reshape(nc, nc, nc)
-        block[mask] = vals[mask]
-    return uc
+from .solvers import Multigrid, fcg, inject  # noqa: F401 (inject is part of this module's API)
 
 
 def _gl_values(g, u):

@@ -17,7 +17,13 @@ element index), whose face coordinates parametrise the mortar.
 
 Penalty (Eq. penaltyparameter): sigma = C p_m^2 / h_m, h_m = 2 min_side 1/|grad xi_j|
 (the thickness of the side normal to the face), evaluated at each mortar point,
-multiplied by k at the point.
+multiplied by max(k-, k+) at the point.
+
+Coefficients k (diffusion) and c (mass, the f u term of Eq. Laplacian read with the sign of
+Eq. lh) come from the problem (k analytic), from a mass callable c(x), or from tables: one
+value per element, or nodal values in the level-vector layout whose LGL interpolant on each
+element gives the value at any point of that element.  A tabulated k may jump across a
+mortar; each side then uses its own value: {{k grad u}} = (k- grad u- + k+ grad u+) / 2.
 """
 import numpy as np
 
@@ -47,21 +53,26 @@ class SIPG:
     """The discrete operator A (y = A u) and right-hand side F on one cell mesh."""
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, bc_override=None,
-                 mass=None, active=None):
+                 mass=None, active=None, kfield=None, cfield=None):
         """``active``: optional element subset; the operator is then formed only for the
         rows of those elements (their volume terms and the mortars touching them), so that
-        (A x) restricted to them is exact while the rest of the output stays zero."""
+        (A x) restricted to them is exact while the rest of the output stays zero.
+        ``kfield`` / ``cfield``: tabulated diffusion / mass coefficient, dict(where="element",
+        values=[E]) or dict(where="node", values=[ndof]) (replaces the problem's k / ``mass``)."""
         self.mesh = mesh
         self.problem = problem
         self.C = float(C)
         self.quad_extra = int(quad_extra)
         self.mass = mass  # callable c(x) >= 0 or None
+        self.kfield, self.cfield = kfield, cfield
+        if cfield is not None:
+            self.mass = self._mass_from_field
         p = mesh["elem_p"].astype(np.int64)
         self.E = len(p)
         self.n = p + 1
         self.offsets = np.concatenate([[0], np.cumsum(self.n ** 3)])
         self.ndof = int(self.offsets[-1])
-        self.kconst = problems.k_is_constant(problem)
+        self.kconst = problems.k_is_constant(problem) and kfield is None
         self.affine = geometry.is_affine_macro(mesh["macro_kind"][mesh["elem_macro"]])
         self.mortars = build_mortars(mesh)
         self.active = None
@@ -91,6 +102,35 @@ class SIPG:
     def k(self, x):
         return problems.k_of(self.problem, x)
 
+    def _field_at(self, field, elems, xi):
+        """A tabulated coefficient at reference points xi [..., 3] of elements ``elems``
+        (broadcast against xi[..., 0])."""
+        elems = np.broadcast_to(np.asarray(elems), xi.shape[:-1])
+        vals = np.asarray(field["values"], float)
+        if field["where"] == "element":
+            return vals[elems]
+        out = np.zeros(xi.shape[:-1])
+        for e in np.unique(elems):
+            sel = elems == e
+            V, _ = _basis_at(int(self.n[e]), xi[sel])
+            out[sel] = V @ vals[self.offsets[e]:self.offsets[e + 1]]
+        return out
+
+    def k_at(self, elems, xi, x):
+        """k at the physical points x = Phi_e(xi) of elements ``elems``."""
+        if self.kfield is None:
+            return self.k(x)
+        return self._field_at(self.kfield, elems, xi)
+
+    def _mass_from_field(self, x, elems=None, xi=None):
+        return self._field_at(self.cfield, elems, xi)
+
+    def c_at(self, elems, xi, x):
+        """Mass coefficient c at the points x = Phi_e(xi) of elements ``elems``."""
+        if self.cfield is not None:
+            return self._field_at(self.cfield, elems, xi)
+        return self.mass(x)
+
     # -- volume -------------------------------------------------------------------
     def _setup_volume(self):
         groups = {}
@@ -112,10 +152,11 @@ class SIPG:
             if np.any(det <= 0):
                 raise ValueError("non-positive Jacobian determinant")
             Ji = np.linalg.inv(J)  # Ji[d, i] = dxi_d / dx_i
-            G = np.einsum("epdi,epci->epdc", Ji, Ji) * (W * det * self.k(x))[:, :, None, None]
+            xie = np.broadcast_to(xi, x.shape)
+            G = np.einsum("epdi,epci->epdc", Ji, Ji) * (W * det * self.k_at(elems[:, None], xie, x))[:, :, None, None]
             M = None
             if self.mass is not None:
-                M = W * det * self.mass(x)
+                M = W * det * self.c_at(elems[:, None], xie, x)
             idx = self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]
             self.vgroups.append(dict(n=n, q=q, elems=elems, B=B, Dt=Dt, G=G, M=M, idx=idx,
                                      x=x, W=W, det=det))
@@ -174,6 +215,8 @@ class SIPG:
             wS = wst[None, :] * S
             hmin = 2.0 / nrm
             pm = nm - 1
+            km = self.k_at(em[:, None], np.broadcast_to(xim, x.shape), x)
+            kp = km
             g = dict(key=key, mis=np.array(mis), em=em, wS=wS, x=x, Vm=Vm, Dm=Dm,
                      mvec_m=np.einsum("mpdi,mpi->mpd", Jim, nhat), nhat=nhat,
                      idx_m=self.offsets[em][:, None] + np.arange(nm ** 3)[None, :])
@@ -188,12 +231,13 @@ class SIPG:
                 nrp = np.linalg.norm(Jip[:, :, dp_, :], axis=-1)
                 hmin = np.minimum(hmin, 2.0 / nrp)
                 pm = max(pm, npl - 1)
+                kp = self.k_at(ep[:, None], np.broadcast_to(xip, xp.shape), xp)
                 g.update(ep=ep, Vp=Vp, Dp=Dp, xp=xp,
                          mvec_p=np.einsum("mpdi,mpi->mpd", Jip, -nhat),
                          idx_p=self.offsets[ep][:, None] + np.arange(npl ** 3)[None, :])
-            kx = self.k(x)
-            g["kx"] = kx
-            g["sigma"] = self.C * pm * pm / hmin * kx
+            g["kx"] = km          # the minus side's k (its own side of the mortar)
+            g["kp"] = kp          # the plus side's k (= km where k is continuous)
+            g["sigma"] = self.C * pm * pm / hmin * np.maximum(km, kp)
             self.fgroups.append(g)
 
     def _faces(self, u, y):
@@ -207,11 +251,12 @@ class SIPG:
                 Up = u[g["idx_p"]]
                 up = Up @ g["Vp"].T
                 gp = np.einsum("mpd,dpa,ma->mp", g["mvec_p"], g["Dp"], Up)
-                # side -: jump j = u- - u+, n-.(grad u- + grad u+) = g- - g+
+                # side -: jump j = u- - u+, n-.({{k grad u}}) = (k- g- - k+ g+) / 2
+                kp = g["kp"]
                 jm = um - up
-                Am = wS * (sig * jm - 0.5 * kx * (gm - gp))
+                Am = wS * (sig * jm - 0.5 * (kx * gm - kp * gp))
                 Bm = -0.5 * wS * kx * jm
-                Ap, Bp = -Am, -Bm  # side +: j+ = -j-, n+ = -n-
+                Ap, Bp = -Am, 0.5 * wS * kp * jm  # side +: j+ = -j-, n+ = -n-, its own k
                 ym = Am @ g["Vm"] + np.einsum("mp,mpd,dpa->ma", Bm, g["mvec_m"], g["Dm"])
                 yp = Ap @ g["Vp"] + np.einsum("mp,mpd,dpa->ma", Bp, g["mvec_p"], g["Dp"])
                 np.add.at(y, g["idx_m"], ym)
@@ -257,14 +302,14 @@ class SIPG:
             dg[g["idx"]] += out.reshape(len(G), -1)
         for g in self.fgroups:
             wS, kx, sig = g["wS"], g["kx"], g["sigma"]
-            sides = [("Vm", "Dm", "mvec_m", "idx_m")]
+            sides = [("Vm", "Dm", "mvec_m", "idx_m", kx)]
             if "ep" in g:
-                sides.append(("Vp", "Dp", "mvec_p", "idx_p"))
+                sides.append(("Vp", "Dp", "mvec_p", "idx_p", g["kp"]))
             factor = 1.0 if "ep" in g else 2.0
-            for V, D, mv, idx in sides:
+            for V, D, mv, idx, ks in sides:
                 psi = g[V]                                      # [p, a]
                 gn = np.einsum("mpd,dpa->mpa", g[mv], g[D])     # n.grad psi per mortar
-                val = (wS * sig) @ (psi * psi) - factor * np.einsum("mp,pa,mpa->ma", wS * kx, psi, gn)
+                val = (wS * sig) @ (psi * psi) - factor * np.einsum("mp,pa,mpa->ma", wS * ks, psi, gn)
                 np.add.at(dg, g[idx], val)
         return dg
 
@@ -302,7 +347,7 @@ class SIPG:
             nrm = np.linalg.norm(row, axis=-1)
             nhat = (1.0 if fm % 2 else -1.0) * row / nrm[:, None]
             wS = np.outer(w, w).reshape(-1) * np.linalg.det(J)[0] * nrm
-            gN = problems.neumann_g(problem, x[0], nhat, self.k(x[0]))
+            gN = problems.neumann_g(problem, x[0], nhat, self.k_at(np.full(len(xim), em), xim, x[0]))
             F[self.offsets[em] + np.arange(nm ** 3)] += (wS * gN) @ Vm
         return F
 
@@ -422,20 +467,22 @@ def element_blocks(op):
             x, J = geometry.element_map(op.mesh, np.full(len(xi), e), xi)
             Ji = np.linalg.inv(J)
             grad = np.einsum("pdi,dpa->pai", Ji, D)
-            blocks[e] += np.einsum("p,pai,pbi->ba", W * np.linalg.det(J) * op.k(x), grad, grad)
+            kv = op.k_at(np.full(len(xi), e), xi, x)
+            blocks[e] += np.einsum("p,pai,pbi->ba", W * np.linalg.det(J) * kv, grad, grad)
             if op.mass is not None:
-                blocks[e] += np.einsum("p,pa,pb->ba", W * np.linalg.det(J) * op.mass(x), V, V)
+                cv = op.c_at(np.full(len(xi), e), xi, x)
+                blocks[e] += np.einsum("p,pa,pb->ba", W * np.linalg.det(J) * cv, V, V)
     for g in op.fgroups:
         wS, kx, sig = g["wS"], g["kx"], g["sigma"]
-        sides = [("Vm", "Dm", "mvec_m", "em")]
+        sides = [("Vm", "Dm", "mvec_m", "em", kx)]
         if "ep" in g:
-            sides.append(("Vp", "Dp", "mvec_p", "ep"))
+            sides.append(("Vp", "Dp", "mvec_p", "ep", g["kp"]))
         half = 0.5 if "ep" in g else 1.0
-        for V, D, mv, el in sides:
+        for V, D, mv, el, ks in sides:
             psi = g[V]
             for i, e in enumerate(g[el]):
                 gn = np.einsum("pd,dpa->pa", g[mv][i], g[D])   # n.grad psi at the points
-                wk = wS[i] * kx[i]
+                wk = wS[i] * ks[i]
                 blk = (np.einsum("p,pa,pb->ba", wS[i] * sig[i], psi, psi)
                        - half * np.einsum("p,pa,pb->ba", wk, psi, gn)
                        - half * np.einsum("p,pa,pb->ba", wk, gn, psi))
@@ -463,11 +510,11 @@ def assemble_dense(op):
             x, J = geometry.element_map(op.mesh, np.full(len(xi), e), xi)
             Ji = np.linalg.inv(J)
             det = np.linalg.det(J)
-            kx = op.k(x)
+            kx = op.k_at(np.full(len(xi), e), xi, x)
             grad = np.einsum("pdi,dpa->pai", Ji, D)  # physical gradient of every basis function
             Ke = np.einsum("p,pai,pbi->ba", W * det * kx, grad, grad)
             if op.mass is not None:
-                Ke += np.einsum("p,pa,pb->ba", W * det * op.mass(x), V, V)
+                Ke += np.einsum("p,pa,pb->ba", W * det * op.c_at(np.full(len(xi), e), xi, x), V, V)
             sl = slice(op.offsets[e], op.offsets[e + 1])
             A[sl, sl] += Ke
     for mt in op.mortars:
@@ -489,28 +536,31 @@ def assemble_dense(op):
         nvec = (1.0 if sd else -1.0) * row / nrm[:, None]
         dS = wst * np.linalg.det(J) * nrm
         V, D = _basis_at(int(op.n[em]), xim)
-        sides.append((em, V, np.einsum("pdi,dpa->pai", Ji, D), nvec))
+        km = op.k_at(np.full(len(s), em), xim, x)
+        sides.append((em, V, np.einsum("pdi,dpa->pai", Ji, D), nvec, km))
         h = 2.0 / nrm
         pm = int(op.n[em]) - 1
+        kmax = km
         if mt["ep"] >= 0:
             ep, fp = mt["ep"], mt["fp"]
             a, b = minus_to_plus(mt, s, t)
             xip = face_point(fp, a, b)
-            _, Jp = geometry.element_map(op.mesh, np.full(len(s), ep), xip)
+            xpp, Jp = geometry.element_map(op.mesh, np.full(len(s), ep), xip)
             Jip = np.linalg.inv(Jp)
             Vp, Dp = _basis_at(int(op.n[ep]), xip)
-            sides.append((ep, Vp, np.einsum("pdi,dpa->pai", Jip, Dp), -nvec))
+            kp = op.k_at(np.full(len(s), ep), xip, xpp)
+            sides.append((ep, Vp, np.einsum("pdi,dpa->pai", Jip, Dp), -nvec, kp))
             h = np.minimum(h, 2.0 / np.linalg.norm(Jip[:, fp // 2, :], axis=-1))
             pm = max(pm, int(op.n[ep]) - 1)
-        kx = op.k(x)
-        sigma = op.C * pm * pm / h * kx
+            kmax = np.maximum(km, kp)
+        sigma = op.C * pm * pm / h * kmax
         half = 0.5 if len(sides) == 2 else 1.0
-        for (eu, Vu, Gu, nu) in sides:        # trial side
-            for (ev, Vv, Gv, nv) in sides:    # test side
+        for (eu, Vu, Gu, nu, ku) in sides:        # trial side
+            for (ev, Vv, Gv, nv, kv) in sides:    # test side
                 jump_u = Vu[:, :, None] * nu[:, None, :]          # [[psi_u]]  (p, a, i)
                 jump_v = Vv[:, :, None] * nv[:, None, :]
-                avg_u = half * kx[:, None, None] * Gu               # {{k grad psi_u}}
-                avg_v = half * kx[:, None, None] * Gv
+                avg_u = half * ku[:, None, None] * Gu               # {{k grad psi_u}}
+                avg_v = half * kv[:, None, None] * Gv
                 blk = (-np.einsum("p,pai,pbi->ba", dS, jump_u, avg_v)
                        - np.einsum("p,pbi,pai->ba", dS, jump_v, avg_u)
                        + np.einsum("p,pai,pbi->ba", dS * sigma, jump_u, jump_v))

@@ -52,6 +52,11 @@ def exact_u(problem, x):
     if kind == "star":
         rho0, r0 = problem["params"][:2]
         return star_psi(rho0, r0, np.linalg.norm(x, axis=-1))
+    if kind == "layered_x":
+        # k = k1 for x < x0, k2 beyond: u = x / k1, then x0 / k1 + (x - x0) / k2 (continuous,
+        # flux k du/dx = 1 on both sides, so -div(k grad u) = 0)
+        x0, k1, k2 = problem["params"][:3]
+        return np.where(X < x0, X / k1, x0 / k1 + (X - x0) / k2)
     raise ValueError(kind)
 
 
@@ -131,6 +136,8 @@ def source_g(problem, x):
         return g
     if kind == "polynomial_dirichlet":
         return np.zeros(x.shape[:-1])  # Dirichlet data only
+    if kind == "layered_x":
+        return np.zeros(x.shape[:-1])  # k du/dx = 1 on both sides of x0
     raise ValueError(kind)
 
 

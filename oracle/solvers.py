@@ -151,17 +151,69 @@ def splitmix64_uniform(n, seed):
     return (z >> np.uint64(11)).astype(np.float64) * (2.0 ** -53) * 2.0 - 1.0
 
 
+def inject(fine_op, coarse_op, uf):
+    """Coarse nodal values from the fine-level field: the fine polynomial of the child that
+    contains each coarse LGL node (lower child on the cut), evaluated there."""
+    uc = np.zeros(coarse_op.ndof)
+    for k, (K, bits) in enumerate(parent_map(fine_op.mesh, coarse_op.mesh)):
+        nf, nc = int(fine_op.n[k]), int(coarse_op.n[K])
+        xf, _ = rules.lgl(nf)
+        xc, _ = rules.lgl(nc)
+        mats, owned = [], []
+        for d in range(3):
+            if bits is None:
+                pts, own = xc, np.ones(nc, bool)
+            else:
+                b = bits[d]
+                pts = 2.0 * xc - 2.0 * b + 1.0          # coarse node in the child's coordinates
+                own = xc <= 0.0 if b == 0 else xc > 0.0  # nodes on the cut go to the lower child
+            mats.append(rules.lagrange(xf, pts))        # [coarse node, fine node]
+            owned.append(own)
+        U = uf[fine_op.offsets[k]:fine_op.offsets[k + 1]].reshape(nf, nf, nf)
+        vals = np.einsum("zc,yb,xa,cba->zyx", mats[2], mats[1], mats[0], U)
+        mask = owned[2][:, None, None] & owned[1][None, :, None] & owned[0][None, None, :]
+        block = uc[coarse_op.offsets[K]:coarse_op.offsets[K + 1]].reshape(nc, nc, nc)
+        block[mask] = vals[mask]
+    return uc
+
+
+def coarsen_field(fine_op, coarse_mesh, field):
+    """A tabulated coefficient on the next coarser mesh: per element, the mean of the values of
+    the fine cells inside each coarse cell; per node, the injection of the fine field."""
+    if field is None:
+        return None
+    pm = parent_map(fine_op.mesh, coarse_mesh)
+    if field["where"] == "element":
+        vals = np.asarray(field["values"], float)
+        acc = np.zeros(len(coarse_mesh["elem_p"]))
+        cnt = np.zeros(len(coarse_mesh["elem_p"]))
+        for k, (K, _) in enumerate(pm):
+            acc[K] += vals[k]
+            cnt[K] += 1
+        return dict(where="element", values=acc / cnt)
+    coarse_op = SIPG(coarse_mesh, None)
+    return dict(where="node", values=inject(fine_op, coarse_op, np.asarray(field["values"], float)))
+
+
 class Multigrid:
     """Stored multigrid hierarchy with frozen Chebyshev bounds and an exact coarse solve."""
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
                  n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None,
-                 starts=None, max_levels=32):
+                 starts=None, max_levels=32, kfield=None, cfield=None):
         """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi) or "block"
         (element-block Jacobi); ``jacobi`` selects "point" / "none" when it is not given.
-        ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``)."""
+        ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``).
+        ``kfield`` / ``cfield``: tabulated coefficients of the finest level (SIPG), carried to
+        the coarser levels by ``coarsen_field``."""
         meshes = hierarchy(mesh, max_levels) if levels is None else levels
-        self.ops = [SIPG(m, problem, C=C, quad_extra=quad_extra, mass=mass) for m in meshes]
+        self.ops = []
+        for m in meshes:
+            if self.ops:
+                kfield = coarsen_field(self.ops[-1], m, kfield)
+                cfield = coarsen_field(self.ops[-1], m, cfield)
+            self.ops.append(SIPG(m, problem, C=C, quad_extra=quad_extra, mass=mass, kfield=kfield,
+                                 cfield=cfield))
         self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
         self.n_cheb, self.Lambda = n_cheb, Lambda
         self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")

@@ -129,3 +129,82 @@ def test_hierarchy_is_strictly_coarser_and_balanced():
         pm = om.parent_map(a, b)
         for k, (K, bits) in enumerate(pm):
             assert b["elem_p"][K] <= a["elem_p"][k]  # coarse degree is the min of the children
+
+
+def _shell_jacobian_ld(par, xi):
+    """Jacobian of a SHELL macro (radial kind 2, inverse branch) in extended precision
+    (np.longdouble): the same closed form as the macro map, evaluated independently."""
+    LD = np.longdouble
+    R = np.asarray(par[0:9]).astype(LD).reshape(3, 3)
+    r_out, zb, rb = (LD(par[i]) for i in (11, 12, 13))
+    pi = LD("3.14159265358979323846264338327950288")
+    X, Y, z = np.tan(pi / 4 * xi[:, 0]), np.tan(pi / 4 * xi[:, 1]), xi[:, 2]
+    dX, dY = pi / 4 * (1 + X * X), pi / 4 * (1 + Y * Y)
+    v = np.stack([X, Y, np.ones_like(X)], -1) @ R.T
+    nv = np.sqrt(X * X + Y * Y + 1)
+    u = v / nv[:, None]
+    du_dX = R[:, 0][None, :] / nv[:, None] - v * (X / nv ** 3)[:, None]
+    du_dY = R[:, 1][None, :] / nv[:, None] - v * (Y / nv ** 3)[:, None]
+    r = 1 / (((LD(1) - z) / rb + (z - zb) / r_out) / (LD(1) - zb))
+    dr = -r * r * (1 / r_out - 1 / rb) / (LD(1) - zb)
+    J = np.zeros((len(z), 3, 3), dtype=LD)
+    J[:, :, 0] = (r * dX)[:, None] * du_dX
+    J[:, :, 1] = (r * dY)[:, None] * du_dY
+    J[:, :, 2] = dr[:, None] * u
+    return J
+
+
+def _inv3_ld(a):
+    C = np.empty_like(a)
+    for i in range(3):
+        for j in range(3):
+            r0, r1 = [k for k in range(3) if k != j]
+            c0, c1 = [k for k in range(3) if k != i]
+            C[:, i, j] = (-1) ** (i + j) * (a[:, r0, c0] * a[:, r1, c1] - a[:, r0, c1] * a[:, r1, c0])
+    det = np.einsum("pj,pj->p", a[:, 0, :], C[:, :, 0])
+    return C / det[:, None, None]
+
+
+def test_compactified_face_metric_fp64_noise_against_extended_precision():
+    # The outer layer of the r_out = 1e9 shell: the face metric J^-1 n on its radial faces has
+    # an exact tangential part of zero (the angles do not depend on r) and a radial part of
+    # size 1/(dr/dzeta); an FP64 evaluation leaves rounding noise of relative size
+    # eps (dr/dzeta)/r there.  Against an extended-precision evaluation of the same closed form,
+    # FP64 (the oracle's path) is off by 1e-9 .. 1e-6 relative, while the volume metric G, scaled
+    # by sqrt(G_dd G_cc), stays at rounding level.  Two FP64 implementations of the operator
+    # therefore differ in the rows of that layer by up to this noise times the face terms'
+    # share of the row: the bound behind the compactified-mesh tolerances of the GPU tests.
+    from oracle import rules
+    m = meshgen.cubed_sphere_shell(level=2, p=4)
+    lev, anc = m["elem_level"], m["elem_anchor"]
+    outer = np.where(anc[:, 2] == (1 << lev) - 1)[0][:12]
+    eta, _ = rules.gl(6)
+    LD = np.longdouble
+    worst_face, worst_G = 0.0, 0.0
+    xi_v = np.stack(np.meshgrid(eta, eta, eta, indexing="ij")[::-1], -1).reshape(-1, 3)
+    for e in outer:
+        sc = LD(1) / LD(2) ** lev[e]
+        par = m["macro_params"][m["elem_macro"][e]]
+        for zf in (-1.0, 1.0):
+            s, t = np.meshgrid(eta, eta, indexing="xy")
+            xi_f = np.stack([s.reshape(-1), t.reshape(-1), np.full(s.size, zf)], -1)
+            _, J64 = geometry.element_map(m, np.full(len(xi_f), e), xi_f)
+            Ji = np.linalg.inv(J64)
+            nh = Ji[:, 2, :] / np.linalg.norm(Ji[:, 2, :], axis=-1)[:, None]
+            v64 = np.einsum("pri,pi->pr", Ji, nh)
+            Jil = _inv3_ld(_shell_jacobian_ld(par, -1 + (2 * anc[e].astype(LD) + 1 + xi_f.astype(LD)) * sc) * sc)
+            nl = Jil[:, 2, :] / np.sqrt(np.sum(Jil[:, 2, :] ** 2, -1))[:, None]
+            vl = np.einsum("pri,pi->pr", Jil, nl).astype(float)
+            worst_face = max(worst_face, float((np.abs(v64 - vl).max(-1) / np.abs(vl).max(-1)).max()))
+        _, J64 = geometry.element_map(m, np.full(len(xi_v), e), xi_v)
+        Ji = np.linalg.inv(J64)
+        G64 = np.einsum("pdi,pci->pdc", Ji, Ji) * np.linalg.det(J64)[:, None, None]
+        Jl = _shell_jacobian_ld(par, -1 + (2 * anc[e].astype(LD) + 1 + xi_v.astype(LD)) * sc) * sc
+        Jil = _inv3_ld(Jl)
+        detl = np.einsum("pj,pj->p", Jl[:, 0, :], np.cross(Jl[:, 1, :], Jl[:, 2, :]))
+        Gl = (np.einsum("pdi,pci->pdc", Jil, Jil) * detl[:, None, None]).astype(float)
+        dg = np.abs(np.einsum("pdd->pd", Gl))
+        worst_G = max(worst_G, float((np.abs(G64 - Gl) / np.sqrt(dg[:, :, None] * dg[:, None, :])).max()))
+    print("FP64 vs extended precision: face metric %.3e, volume metric %.3e" % (worst_face, worst_G))
+    assert 1e-9 < worst_face < 1e-6
+    assert worst_G < 1e-13

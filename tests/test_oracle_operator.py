@@ -229,3 +229,105 @@ def test_diagonal_equals_assembled_diagonal(name):
     op = SIPG(MESHES[name](), meshgen.problem_config3(r0=0.7))
     A = assemble_dense(op)
     np.testing.assert_allclose(op.diagonal(), np.diag(A), rtol=1e-13, atol=1e-14 * np.abs(A).max())
+
+
+# ---- tabulated coefficients (per element, per node; a k that jumps across mortars) ----------
+
+def _kfields(m, seed=0):
+    """A per-element k and a per-node k (smooth inside each element, jumping across faces)."""
+    rng = np.random.default_rng(seed)
+    E = len(m["elem_p"])
+    ke = rng.uniform(0.5, 4.0, E)
+    n = m["elem_p"].astype(np.int64) + 1
+    kn = np.concatenate([ke[e] * (1.0 + 0.3 * rng.uniform(-1, 1, n[e] ** 3)) for e in range(E)])
+    return dict(where="element", values=ke), dict(where="node", values=kn)
+
+
+@pytest.mark.parametrize("name", ["box_2to1_p2", "hp_var_p", "shell_l1_p1"])
+def test_tabulated_k_matrix_free_equals_assembled_symmetric_spd(name):
+    # per-side k on every mortar: the matrix-free apply, the brute-force assembly (vector jumps
+    # and averages of Eq. 20 with {{k grad u}} = (k- grad u- + k+ grad u+)/2), the diagonal and
+    # the element blocks agree; the form stays symmetric positive definite
+    m = MESHES[name]()
+    for kf in _kfields(m):
+        op = SIPG(m, None, kfield=kf)
+        A = assemble_dense(op)
+        x = np.random.default_rng(1).standard_normal(op.ndof)
+        np.testing.assert_allclose(op.apply(x), A @ x, rtol=1e-12, atol=1e-12 * np.abs(A @ x).max())
+        np.testing.assert_allclose(A, A.T, atol=1e-12 * np.abs(A).max())
+        assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+        np.testing.assert_allclose(op.diagonal(), np.diag(A), rtol=1e-12, atol=1e-14 * np.abs(A).max())
+        for e, B in enumerate(element_blocks(op)):
+            sl = slice(op.offsets[e], op.offsets[e + 1])
+            np.testing.assert_allclose(B, A[sl, sl], atol=1e-12 * np.abs(A).max())
+
+
+def test_tabulated_k_scaling_and_node_form():
+    # k = 2 everywhere scales the whole form by 2 (volume, consistency terms and penalty); a
+    # nodal field that is constant on each element equals the per-element field
+    m = MESHES["box_2to1_p2"]()
+    x = np.random.default_rng(2).standard_normal(meshgen.dof_count(m))
+    y1 = SIPG(m, None).apply(x)
+    E = len(m["elem_p"])
+    np.testing.assert_allclose(SIPG(m, None, kfield=dict(where="element", values=np.full(E, 2.0))).apply(x), 2 * y1,
+                               rtol=1e-13, atol=1e-13 * np.abs(y1).max())
+    ke = np.random.default_rng(3).uniform(0.5, 3.0, E)
+    n = m["elem_p"].astype(np.int64) + 1
+    kn = np.repeat(ke, n ** 3)
+    ya = SIPG(m, None, kfield=dict(where="element", values=ke)).apply(x)
+    yb = SIPG(m, None, kfield=dict(where="node", values=kn)).apply(x)
+    np.testing.assert_allclose(ya, yb, rtol=1e-13, atol=1e-13 * np.abs(ya).max())
+
+
+@pytest.mark.parametrize("where", ["element", "node"])
+def test_tabulated_k_constants_in_kernel_with_neumann(where):
+    m = MESHES["shell_l1_p2"]()
+    kf = _kfields(m)[0 if where == "element" else 1]
+    op = SIPG(m, None, bc_override=2, kfield=kf)
+    y = op.apply(np.ones(op.ndof))
+    assert np.abs(y).max() <= 1e-12 * np.abs(op.diagonal()).max()
+
+
+@pytest.mark.parametrize("maker", [
+    lambda: meshgen.box_grid((1, 1, 1), 1, 2),
+    lambda: meshgen.box_grid((1, 1, 1), 1, 1, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+    lambda: meshgen.hp_sphere_cube(level=1, p_lo=1, p_hi=3, seed=2, r_cut=2.0),
+])
+def test_layered_k_consistency(maker):
+    # k = 1 for x < 0.5 and 5 beyond (element-aligned jump): u piecewise linear in x with a
+    # continuous flux solves -div(k grad u) = 0; SIPG with per-side k is consistent, so
+    # A u_I = F exactly on affine meshes (every integral exact, u in Q_p on each element)
+    m = maker()
+    lo = np.min(m["macro_params"][:, 0:3], axis=0)
+    hi = lo + np.array([m["macro_params"][0, 3], m["macro_params"][0, 7], m["macro_params"][0, 11]])
+    x0 = 0.5 * (lo[0] + hi[0])
+    prob = dict(kind="layered_x", params=np.array([x0, 1.0, 5.0]))
+    cells = (m["elem_anchor"][:, 0] + 0.5) / (2.0 ** m["elem_level"])
+    kf = dict(where="element", values=np.where(lo[0] + cells * (hi[0] - lo[0]) < x0, 1.0, 5.0))
+    op = SIPG(m, prob, kfield=kf)
+    uI = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    r = op.apply(uI) - F
+    assert np.abs(r).max() <= 1e-12 * np.abs(F).max(), np.abs(r).max() / np.abs(F).max()
+    # a single k on both sides of the jump (the larger one) breaks consistency
+    bad = SIPG(m, prob, kfield=kf)
+    for g in bad.fgroups:
+        g["kp"] = g["kx"] = np.maximum(g["kx"], g["kp"]) if "ep" in g else g["kx"]
+    rb = bad.apply(uI) - bad.rhs()
+    assert np.abs(rb).max() > 1e-6 * np.abs(F).max()
+
+
+def test_tabulated_fields_coarsen_to_the_hierarchy():
+    # per element: mean over the cells inside; per node: injection, which reproduces a
+    # field that is a polynomial of the coarse degree
+    from oracle.solvers import Multigrid
+    m = meshgen.unit_cube(2, 2)
+    E = len(m["elem_p"])
+    ke = np.arange(E, dtype=float) + 1.0
+    mg = Multigrid(m, None, lam=[1.0] * 10, kfield=dict(where="element", values=ke))
+    assert abs(np.mean(mg.ops[1].kfield["values"]) - np.mean(ke)) <= 1e-13 * np.mean(ke)
+    f = lambda X: 1.0 + X[..., 0] + 2 * X[..., 1] * X[..., 2]
+    op0 = SIPG(m, None)
+    mg = Multigrid(m, None, lam=[1.0] * 10, kfield=dict(where="node", values=op0.interpolate(f)))
+    for op in mg.ops[1:]:
+        np.testing.assert_allclose(op.kfield["values"], SIPG(op.mesh, None).interpolate(f), atol=1e-13)
