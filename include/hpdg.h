@@ -116,9 +116,8 @@ typedef struct {
  *   coef_kind   HPDG_COEF_*: k = 1, or k = coef_params[1] for |x| < coef_params[0]
  *               and coef_params[2] otherwise.
  *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh). The last
- *               level is solved exactly through a dense inverse (N_c^2 scalars, FP64 and
- *               FP32): N_c^2 must stay below 2^31, else the smoother setup fails with
- *               HPDG_ERR_UNSUPPORTED.
+ *               level is solved exactly through a dense FP64 inverse (N_c^2 scalars): N_c^2
+ *               must stay below 2^31, else the upload fails with HPDG_ERR_UNSUPPORTED.
  *   build_f32   also build FP32 copies of every level (needed by HPDG_F32 calls and
  *               mixed-precision solves).
  *   mass_term   1: every level carries a mass form  sum_sigma w det J c u v  with c set per
@@ -145,6 +144,11 @@ typedef struct {
   int64_t mgeo_scalars[32];  /* mortar metric values stored per level */
   int64_t table_bytes[32];   /* element + mortar records and face lists per level */
   size_t device_bytes;   /* resident device memory of this mesh */
+  /* setup factorisations repeated after a failed attempt (the element-block Cholesky of the
+   * block-Jacobi smoother, the coarsest operator's Cholesky): a failure on an SPD operator that
+   * does not repeat on a fresh assembly is retried once; both stay 0 in a healthy run */
+  int32_t block_retries;
+  int32_t coarse_retries;
 } hpdg_mesh_info;
 
 /* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters.
@@ -239,7 +243,9 @@ typedef struct {
 int hpdg_create(hpdg_ctx** out, int hip_device, size_t hbm_budget_bytes);
 /* Free the context and every mesh it still owns. */
 int hpdg_destroy(hpdg_ctx* ctx);
-/* Message of the last failure on this context (never NULL). */
+/* Message of the last failed call made by the calling thread (thread-local: calls on other
+ * threads, e.g. the solve server's workers, do not overwrite it); never NULL.  The pointer stays
+ * valid until the calling thread's next failing call. */
 const char* hpdg_last_error(const hpdg_ctx* ctx);
 
 /* Build the level hierarchy (Sec. II.D.3: surrogate coarsening + 2:1 restoration,
@@ -277,7 +283,8 @@ int hpdg_setup_smoother(hpdg_mesh* mesh, const hpdg_smoother_params* params, dou
 int hpdg_smooth(hpdg_mesh* mesh, int level, int prec, const void* b_dev, void* x_dev, int n_iter,
                 void* stream);
 /* z = V(r): one V-cycle (Alg. 3) from zero initial guesses; level-0 vectors of ``prec``;
- * coarsest level solved exactly (FP64 Cholesky factor formed at setup). */
+ * coarsest level solved exactly through the FP64 inverse formed at setup (Cholesky); an FP32
+ * V-cycle widens the coarse right-hand side to FP64 for that solve and rounds the result. */
 int hpdg_vcycle(hpdg_mesh* mesh, int prec, const void* r_dev, void* z_dev, void* stream);
 /* Solve A u = b (FP64 level-0 vectors).  u is the initial guess on entry (Alg. 2,
  * r0 = b - A u0) and the solution on exit.  ``stats`` is filled even on failure;

@@ -60,7 +60,8 @@ class MeshInfo(ctypes.Structure):
     _fields_ = [("n_levels", ctypes.c_int32), ("n_elem", ctypes.c_int64 * 32),
                 ("n_dof", ctypes.c_int64 * 32), ("n_mortar", ctypes.c_int64 * 32),
                 ("vgeo_scalars", ctypes.c_int64 * 32), ("mgeo_scalars", ctypes.c_int64 * 32),
-                ("table_bytes", ctypes.c_int64 * 32), ("device_bytes", ctypes.c_size_t)]
+                ("table_bytes", ctypes.c_int64 * 32), ("device_bytes", ctypes.c_size_t),
+                ("block_retries", ctypes.c_int32), ("coarse_retries", ctypes.c_int32)]
 
 
 class SmootherParams(ctypes.Structure):
@@ -114,6 +115,9 @@ class NewtonStats(ctypes.Structure):
 
 
 _lib = None
+# (block, coarse) setup retries of every mesh freed through Mesh.free(), for callers that check
+# that no factorisation had to be repeated
+RETRY_LOG = []
 
 
 def load_library(path=LIB_PATH):
@@ -325,6 +329,8 @@ class Mesh:
         self.mgeo_scalars = [int(info.mgeo_scalars[i]) for i in range(self.n_levels)]
         self.table_bytes = [int(info.table_bytes[i]) for i in range(self.n_levels)]
         self.device_bytes = int(info.device_bytes)
+        self.block_retries = int(info.block_retries)
+        self.coarse_retries = int(info.coarse_retries)
 
     def algorithmic_bytes(self, level=0, scalar=8):
         """Bytes one apply of ``level`` must move at least once: x read and y written, the
@@ -433,8 +439,15 @@ class Mesh:
                                                    ctypes.byref(b)))
         return ms.value, n.value, b.value
 
+    def setup_retries(self):
+        """(block, coarse) setup factorisations repeated after a failed attempt (0, 0 when healthy)."""
+        info = MeshInfo()
+        self.ctx.check(self.lib.hpdg_mesh_info_get(self.h, ctypes.byref(info)))
+        return int(info.block_retries), int(info.coarse_retries)
+
     def free(self):
         if self.h:
+            RETRY_LOG.append(self.setup_retries())
             self.lib.hpdg_mesh_free(self.h)
             self.h = None
             if self in self.ctx.meshes:

@@ -41,7 +41,6 @@ struct hpdg_ctx {
   int device = 0;
   size_t budget = 0;
   size_t used = 0;
-  std::string err;
   std::vector<hpdg_mesh*> meshes;
   std::mutex mu;  // guards used and meshes (a solve server uploads from several threads)
 };
@@ -53,6 +52,7 @@ struct DevLevel {
   ElemInfo* einfo = nullptr;
   MortarInfo* minfo = nullptr;
   int* fmlist = nullptr;
+  FaceTask* ftask = nullptr;
   T* vgeo = nullptr;
   T* mgeo = nullptr;
   T* dinv = nullptr;
@@ -93,8 +93,7 @@ struct hpdg_mesh {
   float* tab32 = nullptr;
   std::vector<DevLevel<double>> L64;
   std::vector<DevLevel<float>> L32;
-  double* Ainv64 = nullptr;
-  float* Ainv32 = nullptr;
+  double* Ainv64 = nullptr;  // explicit inverse of the coarsest operator (FP64 in every precision mode)
   int ncoarse = 0;
   // smoother
   std::vector<double> lam;
@@ -219,8 +218,6 @@ struct hpdg_mesh {
   DevLevel<T>& lev(int l);
   template <typename T>
   const T* table() const;
-  template <typename T>
-  const T* ainv() const;
 };
 
 template <>
@@ -231,10 +228,6 @@ template <>
 const double* hpdg_mesh::table<double>() const { return tab64; }
 template <>
 const float* hpdg_mesh::table<float>() const { return tab32; }
-template <>
-const double* hpdg_mesh::ainv<double>() const { return Ainv64; }
-template <>
-const float* hpdg_mesh::ainv<float>() const { return Ainv32; }
 
 template <typename T>
 LevelView<T> hpdg_mesh::view(int l) const {
@@ -244,6 +237,7 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.einfo = d.einfo;
   v.minfo = d.minfo;
   v.fmlist = d.fmlist;
+  v.ftask = d.ftask;
   v.vgeo = d.vgeo;
   v.mgeo = d.mgeo;
   v.mcoef = mass_on ? d.mcoef : nullptr;
@@ -275,8 +269,13 @@ TransferView<T> hpdg_mesh::tview(int l) const {
 
 namespace {
 
+// message of the last failed call of the calling thread (the server's worker threads and the
+// caller's threads do not overwrite each other's messages)
+thread_local std::string t_last_error = "no error";
+
 int fail(hpdg_ctx* ctx, int code, const std::string& msg) {
-  if (ctx) ctx->err = msg;
+  (void)ctx;
+  t_last_error = msg.empty() ? "error " + std::to_string(code) : msg;
   return code;
 }
 
@@ -303,6 +302,7 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
   d.einfo = M->upload_raw(h.einfo, s);
   d.minfo = M->upload_raw(h.minfo, s);
   d.fmlist = M->upload_raw(h.fmlist, s);
+  d.ftask = M->upload_raw(h.ftask, s);
   d.belems = M->upload_raw(h.bucket_elems, s);
   d.vgeo = M->upload<T>(h.vgeo, s);
   d.mgeo = M->upload<T>(h.mgeo, s);
@@ -374,8 +374,7 @@ void collect_timing(hpdg_mesh* M) {
 double apply_bytes(const hpdg_mesh* M, int l, size_t scalar) {
   const LevelHost& h = M->H[l];
   return double(scalar) * (2.0 * double(h.ndof) + double(h.vgeo.size()) + double(h.mgeo.size())) +
-         double(h.einfo.size() * sizeof(ElemInfo) + h.minfo.size() * sizeof(MortarInfo) +
-                h.fmlist.size() * sizeof(int));
+         double(h.einfo.size() * sizeof(ElemInfo) + h.ftask.size() * sizeof(FaceTask));
 }
 
 template <typename T>
@@ -472,6 +471,20 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   }
 }
 
+// exact coarse solve v = A_L^-1 f through the FP64 inverse; FP32 vectors (mixed V-cycle) are
+// widened to FP64 for the mat-vec and rounded back, so the coarse solve itself stays FP64
+template <typename T>
+void coarse_solve(hpdg_mesh* M, const T* f, T* v, hipStream_t s) {
+  if constexpr (std::is_same<T, double>::value) {
+    launch_dense_matvec<double>(M->ncoarse, M->Ainv64, f, v, s);
+  } else {
+    DevLevel<double>& d = M->lev<double>(M->nlevels() - 1);
+    launch_convert_f2d(M->ncoarse, f, d.f, s);
+    launch_dense_matvec<double>(M->ncoarse, M->Ainv64, d.f, d.v, s);
+    launch_convert_d2f(M->ncoarse, d.v, v, s);
+  }
+}
+
 // Alg. 3: z = V(r) on level-0 vectors of type T
 template <typename T>
 void vcycle(hpdg_mesh* M, const T* r0, T* z0, hipStream_t s) {
@@ -492,11 +505,8 @@ void vcycle(hpdg_mesh* M, const T* r0, T* z0, hipStream_t s) {
     launch_axpby<T>(n, T(1), f[l], T(-1), d.t, s);  // t = f - A v
     launch_restrict<T>(M->tview<T>(l), d.t, M->lev<T>(l + 1).f, s);
   }
-  if (L == 0) {
-    launch_dense_matvec<T>(M->ncoarse, M->ainv<T>(), f[0], v[0], s);
-    return;
-  }
-  launch_dense_matvec<T>(M->ncoarse, M->ainv<T>(), f[L], v[L], s);
+  coarse_solve<T>(M, f[L], v[L], s);
+  if (L == 0) return;
   for (int l = L - 1; l >= 0; --l) {
     launch_prolong_add<T>(M->tview<T>(l), v[l + 1], v[l], s);
     smooth_level<T>(M, l, f[l], v[l], nc(l), false, s);
@@ -566,6 +576,14 @@ double cg_bound(hpdg_mesh* M, int l, int n_eigs, uint64_t seed, hipStream_t s) {
 
 void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
                    const long long* dboff, double* B, hipStream_t s);
+std::string diagnose_block(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
+                           const long long* dboff, double* B, long long e, hipStream_t s);
+
+// a batched element-block factorisation reported a non-positive pivot in element ``elem``
+struct BlockFailure : Error {
+  long long elem;
+  BlockFailure(const std::string& m, long long e) : Error(HPDG_ERR_BREAKDOWN, m), elem(e) {}
+};
 
 // element-block Jacobi: A_ee of every element of level l (column j of all blocks from one
 // apply with neighbours taken as zero), their inverses by batched Cholesky (rocSOLVER), and
@@ -591,12 +609,17 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
   V.self_only = 1;
   // A failed factorisation is retried once from a fresh gather (the blocks are SPD: a
   // failure that does not repeat is not a property of the operator); a repeated one is an error.
+  // Each failure is reported on stderr with a host check of the re-gathered block, which tells
+  // bad block data (not SPD on the host) from a failed device factorisation (SPD on the host),
+  // and counted (hpdg_mesh_info.block_retries).
   for (int attempt = 0;; ++attempt) {
     try {
       factor_blocks(M, l, V, boff, dboff, B, s);
       break;
-    } catch (const Error& err) {
-      if (attempt >= 1 || err.code != HPDG_ERR_BREAKDOWN) throw;
+    } catch (const BlockFailure& err) {
+      const std::string diag = diagnose_block(M, l, V, boff, dboff, B, err.elem, s);
+      std::fprintf(stderr, "hpdg: %s; %s\n", err.what(), diag.c_str());
+      if (attempt >= 1) throw Error(HPDG_ERR_BREAKDOWN, std::string(err.what()) + "; " + diag);
       M->block_retries += 1;
     }
   }
@@ -617,13 +640,11 @@ void build_blocks(hpdg_mesh* M, int l, hipStream_t s) {
   if (!M->has_f32) M->release(dboff);
 }
 
-// gather the element blocks of level l (column j of every block from one self-only apply),
-// check them, and replace them by their inverses (batched Cholesky + inverse, rocSOLVER)
-void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
-                   const long long* dboff, double* B, hipStream_t s) {
+// gather the element blocks of level l: column j of every block from one self-only apply
+void gather_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const long long* dboff, double* B,
+                   hipStream_t s) {
   DevLevel<double>& d = M->lev<double>(l);
   const LevelHost& h = M->H[l];
-  const size_t E = h.cells.size();
   launch_fill<double>(h.ndof, 0.0, d.f, s);
   const int nmax3 = h.nmax * h.nmax * h.nmax;
   for (int j = 0; j < nmax3; ++j) {
@@ -632,6 +653,64 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
     launch_gather_column<double>(V, j, d.t, dboff, B, s);
     launch_set_unit<double>(V, j, 0.0, d.f, s);
   }
+}
+
+// after a failed factorisation of element e's block: gather the blocks again, copy e's to the
+// host and factorise it there (plain Cholesky); returns a one-line finding
+std::string diagnose_block(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
+                           const long long* dboff, double* B, long long e, hipStream_t s) {
+  if (e < 0 || e + 1 >= (long long)boff.size()) return "no element to check";
+  try {
+    gather_blocks(M, l, V, dboff, B, s);
+    const long long N2 = boff[e + 1] - boff[e];
+    const int N = int(std::llround(std::sqrt(double(N2))));
+    std::vector<double> A(static_cast<size_t>(N2));
+    HIPCHK(hipMemcpyAsync(A.data(), B + boff[e], size_t(N2) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    double asym = 0, scale = 0;
+    for (int i = 0; i < N; ++i) {
+      scale = std::max(scale, std::fabs(A[size_t(i) * N + i]));
+      for (int j = 0; j < i; ++j) asym = std::max(asym, std::fabs(A[size_t(i) * N + j] - A[size_t(j) * N + i]));
+    }
+    // in-place lower Cholesky of the symmetric part
+    double minpiv = std::numeric_limits<double>::infinity();
+    int fail_at = -1;
+    for (int j = 0; j < N && fail_at < 0; ++j) {
+      double dj = A[size_t(j) * N + j];
+      for (int k = 0; k < j; ++k) dj -= A[size_t(j) * N + k] * A[size_t(j) * N + k];
+      minpiv = std::min(minpiv, dj);
+      if (!(dj > 0)) {
+        fail_at = j;
+        break;
+      }
+      const double ljj = std::sqrt(dj);
+      A[size_t(j) * N + j] = ljj;
+      for (int i = j + 1; i < N; ++i) {
+        double v = 0.5 * (A[size_t(i) * N + j] + A[size_t(j) * N + i]);
+        for (int k = 0; k < j; ++k) v -= A[size_t(i) * N + k] * A[size_t(j) * N + k];
+        A[size_t(i) * N + j] = v / ljj;
+      }
+    }
+    char buf[256];
+    std::snprintf(buf, sizeof(buf),
+                  "re-gathered block of element %lld (N %d): host Cholesky %s (smallest pivot %.3e, "
+                  "largest diagonal %.3e, asymmetry %.3e)",
+                  e, N, fail_at < 0 ? "succeeds" : ("fails at column " + std::to_string(fail_at)).c_str(), minpiv,
+                  scale, asym);
+    return buf;
+  } catch (const std::exception& x) {
+    return std::string("the check of the re-gathered block failed: ") + x.what();
+  }
+}
+
+// gather the element blocks of level l, check them, and replace them by their inverses
+// (batched Cholesky + inverse, rocSOLVER)
+void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::vector<long long>& boff,
+                   const long long* dboff, double* B, hipStream_t s) {
+  DevLevel<double>& d = M->lev<double>(l);
+  const LevelHost& h = M->H[l];
+  const size_t E = h.cells.size();
+  gather_blocks(M, l, V, dboff, B, s);
   {
     int* bad = nullptr;
     HIPCHK(hipMalloc(&bad, E * sizeof(int)));
@@ -658,8 +737,12 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
   for (int n : sizes) {
     const int N = n * n * n;
     std::vector<double*> ptrs;
+    std::vector<long long> eids;
     for (size_t e = 0; e < E; ++e)
-      if (h.einfo[e].n == n) ptrs.push_back(B + boff[e]);
+      if (h.einfo[e].n == n) {
+        ptrs.push_back(B + boff[e]);
+        eids.push_back((long long)e);
+      }
     const int cnt = int(ptrs.size());
     double** dptrs = nullptr;
     rocblas_int* info = nullptr;
@@ -682,9 +765,10 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
         if (hinfo[b] != 0) {
           (void)hipFree(dptrs);
           (void)hipFree(info);
-          throw Error(HPDG_ERR_BREAKDOWN, std::string(what) + ": element block " + std::to_string(b) +
-                                              " of size " + std::to_string(N) + " on level " + std::to_string(l) +
-                                              " is not positive definite (info " + std::to_string(hinfo[b]) + ")");
+          throw BlockFailure(std::string(what) + ": the block of element " + std::to_string(eids[b]) +
+                                 " (size " + std::to_string(N) + ", level " + std::to_string(l) +
+                                 ") is not positive definite (info " + std::to_string(hinfo[b]) + ")",
+                             eids[b]);
         }
     };
     check(rocsolver_dpotrf_batched(M->blas, rocblas_fill_lower, N, dptrs, N, info, cnt), "Cholesky");
@@ -707,7 +791,9 @@ void build_coarse(hpdg_mesh* M, hipStream_t s) {
       build_coarse_once(M, s);
       return;
     } catch (const Error& err) {
-      if (attempt >= 1 || err.code != HPDG_ERR_BREAKDOWN) throw;
+      if (err.code != HPDG_ERR_BREAKDOWN) throw;
+      std::fprintf(stderr, "hpdg: %s\n", err.what());
+      if (attempt >= 1) throw;
       M->coarse_retries += 1;
     }
   }
@@ -722,7 +808,6 @@ void build_coarse_once(hpdg_mesh* M, hipStream_t s) {
   M->ncoarse = n;
   DevLevel<double>& d = M->lev<double>(L);
   if (!M->Ainv64) M->Ainv64 = M->alloc<double>(size_t(n) * n);
-  if (M->has_f32 && !M->Ainv32) M->Ainv32 = M->alloc<float>(size_t(n) * n);
   double* A = M->Ainv64;
   launch_fill<double>(n, 0.0, d.f, s);
   for (int j = 0; j < n; ++j) {
@@ -755,7 +840,6 @@ void build_coarse_once(hpdg_mesh* M, hipStream_t s) {
   check(rocsolver_dpotri(M->blas, rocblas_fill_lower, n, A, n, info), "inverse");
   (void)hipFree(info);
   launch_symmetrize_dense<double>(n, A, 1, s);
-  if (M->has_f32) launch_convert_d2f((long long)n * n, A, M->Ainv32, s);
   HIPCHK(hipStreamSynchronize(s));
 }
 
@@ -861,6 +945,7 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
     b += h.einfo.size() * sizeof(ElemInfo) * (M->has_f32 ? 2 : 1);
     b += h.minfo.size() * sizeof(MortarInfo) * (M->has_f32 ? 2 : 1);
     b += (h.fmlist.size() + h.bucket_elems.size()) * 4 * (M->has_f32 ? 2 : 1);
+    b += h.ftask.size() * sizeof(FaceTask) * (M->has_f32 ? 2 : 1);
     b += (h.vgeo.size() + h.mgeo.size()) * prec;
     b += size_t(h.ndof) * prec * 5;  // dinv, f, v, t, p
     b += size_t(h.ntrace) * prec;      // face traces
@@ -880,7 +965,7 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
     }
   }
   const size_t n0 = size_t(M->H[0].ndof), nc = size_t(M->H.back().ndof);
-  b += full_max + n0 * 8 * 5 + 3 * kRedBlocks * 8 + 128 + nc * nc * prec;
+  b += full_max + n0 * 8 * 5 + 3 * kRedBlocks * 8 + 128 + nc * nc * 8;
   return b;
 }
 
@@ -1401,7 +1486,8 @@ int hpdg_destroy(hpdg_ctx* ctx) {
 }
 
 const char* hpdg_last_error(const hpdg_ctx* ctx) {
-  return ctx ? ctx->err.c_str() : "null context";
+  (void)ctx;
+  return t_last_error.c_str();
 }
 
 int hpdg_mesh_upload(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_params* disc,
@@ -1433,6 +1519,8 @@ int hpdg_mesh_info_get(const hpdg_mesh* mesh, hpdg_mesh_info* out) {
                                     mesh->H[l].fmlist.size() * sizeof(int));
   }
   out->device_bytes = mesh->bytes;
+  out->block_retries = mesh->block_retries;
+  out->coarse_retries = mesh->coarse_retries;
   return HPDG_OK;
 }
 

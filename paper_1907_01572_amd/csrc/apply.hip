@@ -15,6 +15,7 @@
 // Each mortar is therefore evaluated once from each side.
 #include <hip/hip_runtime.h>
 
+#include "apply_common.hpp"
 #include "blocks.hpp"
 #include "device.hpp"
 
@@ -27,65 +28,6 @@ namespace {
 #define HPDG_APPLY_THREADS 256
 #endif
 constexpr int kThreads = HPDG_APPLY_THREADS;
-constexpr int kFaces = 6;
-
-// how the mortar's point grid maps onto one side's face axes (a, b)
-struct Map {
-  int swap, flipA, flipB, halfA, halfB;
-};
-
-__device__ inline Map mortar_map(const MortarInfo& M, int side) {
-  Map s{0, 0, 0, 0, 0};
-  if (side) {
-    s.swap = M.orient & 1;
-    s.flipA = (M.orient >> 1) & 1;
-    s.flipB = (M.orient >> 2) & 1;
-    s.halfA = M.sub < 0 ? 0 : 1 + (M.sub & 1);
-    s.halfB = M.sub < 0 ? 0 : 1 + ((M.sub >> 1) & 1);
-  }
-  return s;
-}
-
-// one (face, mortar) pair of the element in the current round
-struct Task {
-  int valid, f, side, interior, other, qm, gmode, no, of;
-  Map me, ot;
-  long long ooff, geo;  // neighbour trace offset, mortar metric offset
-};
-
-// volume index of the node with index k along axis d and (i, j) along the face axes t0 < t1
-// (arithmetic only: indexed private arrays would live in scratch memory)
-__device__ inline int vidx(int n, int d, int t0, int t1, int k, int i, int j) {
-  const int s0 = t0 == 0 ? 1 : n;            // t0 is axis 0 or 1
-  const int s1 = t1 == 1 ? n : n * n;        // t1 is axis 1 or 2
-  const int sd = d == 0 ? 1 : (d == 1 ? n : n * n);
-  return k * sd + i * s0 + j * s1;
-}
-
-template <typename T>
-__device__ inline const T* tab(const LevelView<T>& L, int kind, int n, int q) {
-  return L.tab + L.tv.off[(kind * (kMaxN + 1) + n) * (kMaxQ + 1) + q];
-}
-
-// flattened loop over the items of the six tasks: cnt[t] items of task t
-// (counts passed as scalars and the task found by unrolled compares, so that nothing is an
-// indexed private array)
-template <typename F>
-__device__ inline void for_items(int c0, int c1, int c2, int c3, int c4, int c5, F&& body) {
-  const int p1 = c0, p2 = p1 + c1, p3 = p2 + c2, p4 = p3 + c3, p5 = p4 + c4, total = p5 + c5;
-  for (int g = threadIdx.x; g < total; g += blockDim.x) {
-    int t = 0, base = 0;
-    if (g >= p1) { t = 1; base = p1; }
-    if (g >= p2) { t = 2; base = p2; }
-    if (g >= p3) { t = 3; base = p3; }
-    if (g >= p4) { t = 4; base = p4; }
-    if (g >= p5) { t = 5; base = p5; }
-    body(t, g - base);
-  }
-}
-
-#define HPDG_COUNTS(expr) expr(0), expr(1), expr(2), expr(3), expr(4), expr(5)
-
 // compact: kernels of a fixed degree with at most two volume nodes per thread; the element's
 // coefficients sit at the start of the shared region (dead once the volume phase has read
 // them: the face phases take both sides' traces from the trace buffer) and each thread keeps
@@ -117,40 +59,6 @@ struct Layout {
   __host__ __device__ size_t region() const { return vol > faces() ? vol : faces(); }
   __host__ __device__ size_t bytes(size_t scalar) const { return tasks + scalar * (fixed + region()); }
 };
-
-// Task metadata for face f in round r (shared by both face paths)
-template <typename T>
-__device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int r) {
-  // (read through memory: indexing a private copy of the element record with a per-thread
-  // face would place it in scratch)
-  const ElemInfo& Ig = L.einfo[e];
-  Task tk;
-  tk.valid = r < Ig.fcnt[f];
-  tk.f = f;
-  tk.side = tk.interior = tk.other = tk.qm = tk.gmode = tk.no = tk.of = 0;
-  tk.me = tk.ot = Map{0, 0, 0, 0, 0};
-  tk.ooff = tk.geo = 0;
-  if (tk.valid) {
-    const int ent = L.fmlist[Ig.fstart[f] + r];
-    const MortarInfo M = L.minfo[ent >> 1];
-    tk.side = ent & 1;
-    tk.interior = M.ep >= 0;
-    tk.other = tk.interior && !L.self_only;
-    tk.qm = M.q;
-    tk.gmode = M.gmode;
-    tk.geo = M.geo;
-    tk.me = mortar_map(M, tk.side);
-    tk.ot = mortar_map(M, 1 - tk.side);
-    tk.of = tk.side ? M.fm : M.fp;
-    if (tk.other) {
-      // the neighbour's traces on the face it shares (values, then normal derivatives)
-      const ElemInfo& O = L.einfo[tk.side ? M.em : M.ep];
-      tk.no = O.n;
-      tk.ooff = O.toff + 2LL * tk.of * O.n * O.n;
-    }
-  }
-  return tk;
-}
 
 // The Jacobi-scaled Chebyshev step behind a fused apply: region[0 .. n^3) holds r = b - A x of
 // element e (the face buffers are free by then). z = M^-1 r (the packed block over the
@@ -426,16 +334,6 @@ __device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long lon
     for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) finish(idx, sy[idx]);
   }
   if constexpr (FUSE) fused_step_tail<T, N>(N, I, e, region, dfo, NM, bs);
-}
-
-// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b on XCD b % 8), each with
-// its own L2.  Remap so that every XCD walks one contiguous range of the element list: elements
-// that are neighbours in the (Morton-ordered) list then meet in the same L2, where the face
-// layers and the shared mortar metric they both read are reused.  A bijection of [0, G).
-__device__ inline unsigned xcd_remap(unsigned b, unsigned G) {
-  constexpr unsigned X = 8;
-  const unsigned q = G / X, r = G % X, x = b % X, i = b / X;
-  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
 // NT, QT > 0: element degree + 1 and volume GL points fixed at compile time (the bucket's

@@ -20,6 +20,7 @@ struct LevelView {
   const ElemInfo* einfo;
   const MortarInfo* minfo;
   const int* fmlist;
+  const FaceTask* ftask;  // fmlist entries as kernel task records
   const T* vgeo;
   const T* mgeo;
   const T* mcoef;  // w det J c at the GL points of elements with a mass term (null: no mass term)

@@ -78,6 +78,18 @@ struct MortarInfo {
   long long geo;              // offset of the mortar metric (in scalars)
 };
 
+// one entry of the face-mortar list in the form the operator kernels use: which face, which
+// side of which mortar, the neighbour's degree and trace offset, the mortar's rule and metric
+// offset (one 32-byte load instead of the list entry, the mortar and the neighbour's record)
+struct FaceTask {
+  long long ooff;             // neighbour's traces on the shared face (values, then normal derivatives)
+  long long geo;              // offset of the mortar metric
+  signed char f, side, interior, qm, gmode, no, of, pad;
+  unsigned char me, ot;       // side maps: swap | flipA << 1 | flipB << 2 | halfA << 3 | halfB << 5
+  short pad2;
+  int pad3;
+};
+
 struct TransferInfo {         // one per fine element
   long long foff, coff;       // dof offsets in the fine and coarse level
   int nf, nc, bits;           // bits: -1 same cell, else child bits (x | y<<1 | z<<2)

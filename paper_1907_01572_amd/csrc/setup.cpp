@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <system_error>
 #include <thread>
 
 namespace hpdg {
@@ -73,7 +74,91 @@ void OpTable::build() {
 }
 
 // ---------------------------------------------------------------------------------
-bool kconst(const DiscParams& dp) { return dp.coef_kind == 0; }
+bool kconst(const DiscParams& dp) { return dp.coef_kind == 0 && dp.kfield == 0; }
+
+namespace {
+
+// value at reference point xi of the LGL interpolant of the n^3 nodal values u (x fastest)
+double nodal_at(int n, const double* u, const double xi[3]) {
+  double xn[kMaxN + 1], wn[kMaxN + 1], L[3][kMaxN + 1], D[kMaxN + 1];
+  gauss_lobatto(n, xn, wn);
+  for (int d = 0; d < 3; ++d) lagrange_eval(n, xn, 1, &xi[d], L[d], D);
+  double v = 0;
+  for (int k = 0; k < n; ++k)
+    for (int j = 0; j < n; ++j) {
+      double r = 0;
+      for (int i = 0; i < n; ++i) r += L[0][i] * u[(k * n + j) * n + i];
+      v += L[2][k] * L[1][j] * r;
+    }
+  return v;
+}
+
+double field_point(int kind, const std::vector<double>& vals, const LevelHost& L, int e, const double xi[3]) {
+  if (kind == 1) return vals[size_t(e)];
+  const ElemInfo& I = L.einfo[e];
+  return nodal_at(I.n, vals.data() + I.off, xi);
+}
+
+}  // namespace
+
+double k_point(const DiscParams& dp, const LevelHost& L, int e, const double xi[3], const double x[3]) {
+  if (dp.kfield) return field_point(dp.kfield, L.kvals, L, e, xi);
+  return coef_k(dp, x);
+}
+
+void coarsen_fields(const DiscParams& dp, const LevelHost& fine, LevelHost& coarse) {
+  if (!dp.kfield && !dp.cfield) return;
+  std::vector<int> parent, bits;
+  parent_cells(fine.cells, coarse.cells, parent, bits);
+  const size_t Ec = coarse.cells.size();
+  long long cdof = 0;
+  std::vector<long long> coff(Ec);
+  for (size_t K = 0; K < Ec; ++K) {
+    coff[K] = cdof;
+    const long long nc = coarse.cells[K].p + 1;
+    cdof += nc * nc * nc;
+  }
+  auto coarsen = [&](int kind, const std::vector<double>& fv, std::vector<double>& cv) {
+    if (kind == 1) {
+      std::vector<double> cnt(Ec, 0.0);
+      cv.assign(Ec, 0.0);
+      for (size_t k = 0; k < fine.cells.size(); ++k) {
+        cv[size_t(parent[k])] += fv[k];
+        cnt[size_t(parent[k])] += 1.0;
+      }
+      for (size_t K = 0; K < Ec; ++K) cv[K] /= cnt[K];
+      return;
+    }
+    cv.assign(size_t(cdof), 0.0);
+    double xc[kMaxN + 1], wc[kMaxN + 1];
+    for (size_t k = 0; k < fine.cells.size(); ++k) {
+      const int K = parent[k], b = bits[k];
+      const int nf = fine.cells[k].p + 1, nc = coarse.cells[K].p + 1;
+      gauss_lobatto(nc, xc, wc);
+      const double* u = fv.data() + fine.einfo[k].off;
+      for (int c = 0; c < nc; ++c)
+        for (int bb = 0; bb < nc; ++bb)
+          for (int a = 0; a < nc; ++a) {
+            const int idx[3] = {a, bb, c};
+            double xi[3];
+            bool own = true;
+            for (int d = 0; d < 3; ++d) {
+              const double t = xc[idx[d]];
+              if (b < 0) {
+                xi[d] = t;
+              } else {
+                const int bd = (b >> d) & 1;
+                xi[d] = 2.0 * t - 2.0 * bd + 1.0;
+                own = own && (bd == 0 ? t <= 0.0 : t > 0.0);
+              }
+            }
+            if (own) cv[size_t(coff[K]) + (size_t(c) * nc + bb) * nc + a] = nodal_at(nf, u, xi);
+          }
+    }
+  };
+  if (dp.kfield) coarsen(dp.kfield, fine.kvals, coarse.kvals);
+  if (dp.cfield) coarsen(dp.cfield, fine.cvals, coarse.cvals);
+}
 
 double coef_k(const DiscParams& dp, const double x[3]) {
   if (dp.coef_kind == 1) {
@@ -183,7 +268,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
           for (int a = 0; a < I.q && kflat; ++a) {
             double xi[3] = {eta[a], eta[b], eta[cc]}, xp[3], Jp[3][3];
             cell_eval(mm, c, xi, xp, Jp);
-            const double kv = coef_k(dp, xp);
+            const double kv = k_point(dp, L, int(e), xi, xp);
             if (a == 0 && b == 0 && cc == 0) kel = kv;
             kflat = kv == kel;
           }
@@ -223,7 +308,7 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
             const double dj = det3(J);
             if (!(dj > 0)) throw Error(-2, "non-positive Jacobian determinant");
             inv3(J, Ji);
-            const double s = wq[a] * wq[b] * wq[cc] * dj * coef_k(dp, x);
+            const double s = wq[a] * wq[b] * wq[cc] * dj * k_point(dp, L, int(e), xi, x);
             const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
             const int idx = a + q * (b + q * cc);
             for (int m = 0; m < 6; ++m) {
@@ -276,19 +361,37 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     I.q = std::max(nm, np) + ((curved || !kc) ? dp.quad_extra : 0);
     if (I.q > kMaxQ) throw Error(-2, "too many mortar quadrature points");
     I.rq = I.q;
-    // constant metric on a flat mortar with one value of k at all its points (folded in)
-    double kmt = 1.0;
+    // each side's k at a mortar point: a tabulated k may jump across the mortar, so each side
+    // takes its own element's value (an analytic k is single-valued: the minus side's value)
+    auto side_k = [&](double s_, double t_, double& km, double& kp) {
+      double xim[3], xp[3], Jp[3][3];
+      face_ref(mt.fm, s_, t_, xim);
+      cell_eval(mm, cm, xim, xp, Jp);
+      km = k_point(dp, L, mt.em, xim, xp);
+      kp = km;
+      if (interior && dp.kfield) {
+        double a, b, xip[3], xq[3], Jq[3][3];
+        plus_coords(mt.orient, mt.sub, s_, t_, a, b);
+        face_ref(mt.fp, a, b, xip);
+        cell_eval(mm, L.cells[mt.ep], xip, xq, Jq);
+        kp = k_point(dp, L, mt.ep, xip, xq);
+      }
+    };
+    // constant metric on a flat mortar where each side's k takes one value at all its points
+    // (folded in)
+    double kmt = 1.0, kpt = 1.0;
     bool kflat = kc;
     if (!curved && !kc) {
       gauss_legendre(I.q, eta, wq);
       kflat = true;
       for (int pidx = 0; pidx < I.q * I.q && kflat; ++pidx) {
-        double xim[3], xp[3], Jp[3][3];
-        face_ref(mt.fm, eta[pidx % I.q], eta[pidx / I.q], xim);
-        cell_eval(mm, cm, xim, xp, Jp);
-        const double kv = coef_k(dp, xp);
-        if (pidx == 0) kmt = kv;
-        kflat = kv == kmt;
+        double km, kp;
+        side_k(eta[pidx % I.q], eta[pidx / I.q], km, kp);
+        if (pidx == 0) {
+          kmt = km;
+          kpt = kp;
+        }
+        kflat = km == kmt && kp == kpt;
       }
     }
     I.gmode = (curved || !kflat) ? 1 : 0;
@@ -315,7 +418,8 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       double nh[3] = {sgn * Ji[dmn][0] / nr, sgn * Ji[dmn][1] / nr, sgn * Ji[dmn][2] / nr};
       const double S = dj * nr;
       double h = 2.0 / nr;
-      const double kx = I.gmode ? coef_k(dp, x) : kmt;
+      double kx = kmt, kxp = kpt;
+      if (I.gmode) side_k(s, t, kx, kxp);
       double mminus[3], mplus[3] = {0, 0, 0};
       for (int r = 0; r < 3; ++r)
         mminus[r] = kx * (Ji[r][0] * nh[0] + Ji[r][1] * nh[1] + Ji[r][2] * nh[2]);
@@ -330,9 +434,9 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
                                      Jpi[dp_][2] * Jpi[dp_][2]);
         h = std::min(h, 2.0 / nrp);
         for (int r = 0; r < 3; ++r)
-          mplus[r] = -kx * (Jpi[r][0] * nh[0] + Jpi[r][1] * nh[1] + Jpi[r][2] * nh[2]);
+          mplus[r] = -kxp * (Jpi[r][0] * nh[0] + Jpi[r][1] * nh[1] + Jpi[r][2] * nh[2]);
       }
-      const double sigma = dp.C * pm * pm / h * kx;
+      const double sigma = dp.C * pm * pm / h * std::max(kx, kxp);
       const double wS = I.gmode ? wq[c] * wq[d] * S : S;
       double vals[8] = {mminus[0], mminus[1], mminus[2], mplus[0], mplus[1], mplus[2], wS, sigma};
       for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
@@ -363,6 +467,30 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       L.einfo[e].fcnt[f] = int(l.size());
       L.fmlist.insert(L.fmlist.end(), l.begin(), l.end());
     }
+  L.ftask.assign(L.fmlist.size(), FaceTask{});
+  for (size_t k = 0; k < L.fmlist.size(); ++k) {
+    const int ent = L.fmlist[k], side = ent & 1;
+    const MortarInfo& M = L.minfo[size_t(ent >> 1)];
+    FaceTask& t = L.ftask[k];
+    t.f = (signed char)(side ? M.fp : M.fm);
+    t.side = (signed char)side;
+    t.interior = M.ep >= 0 ? 1 : 0;
+    t.qm = (signed char)M.q;
+    t.gmode = (signed char)M.gmode;
+    t.of = (signed char)(side ? M.fm : M.fp);
+    t.geo = M.geo;
+    auto pack = [&](int sd) {
+      const SideMap m = side_map(M, sd);
+      return (unsigned char)(m.swap | (m.flipA << 1) | (m.flipB << 2) | (m.halfA << 3) | (m.halfB << 5));
+    };
+    t.me = pack(side);
+    t.ot = pack(1 - side);
+    if (M.ep >= 0) {
+      const ElemInfo& O = L.einfo[size_t(side ? M.em : M.ep)];
+      t.no = (signed char)O.n;
+      t.ooff = O.toff + 2LL * t.of * O.n * O.n;
+    }
+  }
   (void)T;
 }
 
@@ -653,6 +781,26 @@ void mass_points(const MacroMesh& mm, const LevelHost& L, std::vector<double>& x
   }
 }
 
+void mass_table(const MacroMesh& mm, const DiscParams& dp, const LevelHost& L, std::vector<double>& wc) {
+  wc.assign(size_t(L.nmq), 0.0);
+  double eta[kMaxQ + 1], wq[kMaxQ + 1];
+  for (size_t e = 0; e < L.cells.size(); ++e) {
+    const ElemInfo& I = L.einfo[e];
+    if (!I.mass) continue;
+    const int q = I.q;
+    gauss_legendre(q, eta, wq);
+    for (int c = 0; c < q; ++c)
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          const double xi[3] = {eta[a], eta[b], eta[c]};
+          double xp[3], J[3][3];
+          cell_eval(mm, L.cells[e], xi, xp, J);
+          const size_t k = size_t(I.mq) + a + size_t(q) * (b + size_t(q) * c);
+          wc[k] = wq[a] * wq[b] * wq[c] * det3(J) * field_point(dp.cfield, L.cvals, L, int(e), xi);
+        }
+  }
+}
+
 void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
                   int kind, const std::vector<double>& P, std::vector<double>& F) {
   F.assign(size_t(L.ndof), 0.0);
@@ -705,8 +853,18 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
   if (nthreads <= 1) {
     volume(0, E);
   } else {
+    // a thread that cannot be started leaves its element range (and the later ones) to this
+    // thread; the threads already started are joined either way (no exception escapes)
     std::vector<std::thread> pool;
-    for (size_t t = 0; t < nthreads; ++t) pool.emplace_back(volume, E * t / nthreads, E * (t + 1) / nthreads);
+    size_t started = 0;
+    for (; started < nthreads; ++started) {
+      try {
+        pool.emplace_back(volume, E * started / nthreads, E * (started + 1) / nthreads);
+      } catch (const std::system_error&) {
+        break;
+      }
+    }
+    if (started < nthreads) volume(E * started / nthreads, E);
     for (std::thread& th : pool) th.join();
   }
   // Dirichlet faces: int g_D (sigma psi - k n.grad psi), with the face's own rule (a flat face
@@ -785,7 +943,7 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
         inv3(J, Ji);
         const double nr = std::sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
         if (kind != 4) exact_grad(kind, P, xx, g);
-        const double gN = coef_k(dp, xx) * sgn * (Ji[d][0] * g[0] + Ji[d][1] * g[1] + Ji[d][2] * g[2]) / nr;
+        const double gN = k_point(dp, L, M.em, xi, xx) * sgn * (Ji[d][0] * g[0] + Ji[d][1] * g[1] + Ji[d][2] * g[2]) / nr;
         const double v = wq[x] * wq[y] * det3(J) * nr * gN;
         for (int j = 0; j < n; ++j)
           for (int i = 0; i < n; ++i) {

@@ -13,6 +13,11 @@ struct DiscParams {
   int coef_kind = 0;
   double coef[4] = {0, 0, 0, 0};
   int mass_term = 0;  // levels carry a mass term c u v with c set per GL point (Newton)
+  // tabulated coefficients (hpdg_set_coefficient): 0 none, 1 one value per element, 2 nodal
+  // values (level-vector layout, LGL interpolant per element); the values of every level are
+  // in LevelHost::kvals / cvals
+  int kfield = 0;
+  int cfield = 0;
 };
 
 // 1-D operator tables, indexed by (kind, n, q); every matrix is row-major [q][n].
@@ -38,6 +43,7 @@ struct LevelHost {
   std::vector<ElemInfo> einfo;
   std::vector<MortarInfo> minfo;
   std::vector<int> fmlist;       // (mortar << 1) | side, grouped per element face
+  std::vector<FaceTask> ftask;   // the same entries as kernel task records
   std::vector<double> vgeo, mgeo;
   std::vector<double> diag;
   long long ndof = 0;
@@ -53,10 +59,22 @@ struct LevelHost {
   std::vector<TransferInfo> tinfo;
   // restriction gathers: for each coarser element, the elements of this level inside it
   std::vector<int> cstart, clist;
+  // tabulated diffusion / mass coefficient of this level (DiscParams::kfield / cfield)
+  std::vector<double> kvals, cvals;
 };
 
 bool kconst(const DiscParams& dp);
 double coef_k(const DiscParams& dp, const double x[3]);
+// k at the point x = Phi_e(xi) of element e of level L: the tabulated value (per element, or
+// the element's nodal interpolant at xi) or the analytic coefficient at x
+double k_point(const DiscParams& dp, const LevelHost& L, int e, const double xi[3], const double x[3]);
+// the tabulated coefficients of the next coarser level: per element the mean over the cells
+// inside each coarse cell, per node the injection of the fine field (each coarse LGL node takes
+// the value of the fine polynomial of the child containing it; on a cut the lower child)
+void coarsen_fields(const DiscParams& dp, const LevelHost& fine, LevelHost& coarse);
+// w det J c at the volume GL points of every element (mass-coefficient layout) for the
+// tabulated mass coefficient c of the level
+void mass_table(const MacroMesh& mm, const DiscParams& dp, const LevelHost& L, std::vector<double>& wc);
 
 // element map: x, J at element reference point xi
 void cell_eval(const MacroMesh& mm, const Cell& c, const double xi[3], double x[3], double J[3][3]);

@@ -4,13 +4,12 @@ import numpy as np
 import meshgen
 import paper_1907_01572_amd as hp
 
-# FP64 apply parity (relative L2 over the output vector) on well-conditioned geometry.
+# FP64 apply parity (relative L2 over the output vector).
 TOL_APPLY = 1e-12
-# Compactified shell layers (radial stretch dr/dzeta : r up to ~2e8 at r_out = 1e9): the
-# tangential components of J^-1 n are rounding noise of relative size eps * (dr/dzeta)/r
-# in both implementations; the bound below is that noise (2e-8) diluted by the share
-# of those faces in the output, measured at 1e-12 .. 1e-11.
-TOL_APPLY_COMPACTIFIED = 1e-10
+# Compactified shells (r_out = 1e9): the face-metric noise described below; measured in L2
+# 7.7e-13 on the finest level, 3.0e-12 on the next and 1.2e-11 on the coarsest (one cell
+# spans r = 1 .. 1e9, so the outer faces are a larger share of its rows)
+TOL_APPLY_COMPACTIFIED = 5e-11
 
 
 def coef_of(problem):
@@ -35,6 +34,27 @@ def dof_perm(lib_cells, oracle_mesh):
 
 def rel(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def row_err(y, y_ref, diag, x, rows=None):
+    """Largest per-row error max_i |y_i - y_ref_i| / (diag(A)_i |x|_inf): each row against the
+    size of its own terms (the diagonal of the SIPG operator bounds its row to a modest factor),
+    so an error confined to a few faces is not diluted as in a norm over the whole vector."""
+    y, y_ref, diag = np.asarray(y), np.asarray(y_ref), np.asarray(diag)
+    if rows is not None:
+        y, y_ref, diag = y[rows], y_ref[rows], diag[rows]
+    return float(np.max(np.abs(y - y_ref) / (np.abs(diag) * np.abs(x).max())))
+
+
+# per-row FP64 apply parity (row_err): a row sums O(100) products of its own size
+TOL_ROW = 1e-12
+# per-row parity in the outer layer of a compactified shell (r_out = 1e9): there the FP64 face
+# metric J^-1 n itself carries relative rounding noise up to 1.2e-7 against an extended-precision
+# evaluation (tests/test_oracle_geometry.py, compactified face metric), so two FP64
+# implementations may differ by twice that times the face terms' share of a row; measured
+# 1.3e-11 on the finest level and 9.3e-11 on the coarsest, gated at 5e-10 (about 500x below
+# that bound)
+TOL_ROW_COMPACTIFIED = 5e-10
 
 
 MESHES = {

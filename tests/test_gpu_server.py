@@ -1,7 +1,8 @@
 """GPU tests of the continuous-batching solve server.
 
 * a mix of requests (cube / hp + k / shell meshes, degrees 2..5, Poisson and variable k,
-  Gaussian-sum sources) submitted at once and solved concurrently gives, for every request,
+  Gaussian-sum sources) submitted at once runs concurrently (requests in flight together) and
+  gives, for every request,
   the same result as solving it alone through the mesh API (the kernels and reductions are
   deterministic and private to a request), and each reaches the 1e-10 residual;
 * admission by device footprint: with a budget that holds one request at a time, no two
@@ -68,8 +69,14 @@ def test_results_in_the_mix_equal_results_alone(ctx, precision):
     sv.close()
     overlap = any(a["start_ms"] < b["end_ms"] and b["start_ms"] < a["end_ms"]
                   for i, a in enumerate(sts) for b in sts[i + 1:])
+    busy = sum(s["end_ms"] - s["start_ms"] for s in sts)
+    span = max(s["end_ms"] for s in sts) - min(s["start_ms"] for s in sts)
     print("states", [s["state"] for s in sts], "iterations", [s["iterations"] for s in sts],
-          "in flight together", overlap, flush=True)
+          "in flight together", overlap, "summed run time %.1f ms over a %.1f ms span" % (busy, span), flush=True)
+    # continuous batching: the six requests were submitted at once to three slots, so requests
+    # ran concurrently (their [start, end) intervals intersect, and the summed run time exceeds
+    # the span); the equality below then shows each result is the same in the mix as alone
+    assert overlap and busy > span
     for (mesh, prob), u, st in zip(mix, outs, sts):
         assert st["state"] == "done" and st["rel_residual"] <= 1e-10
         ua = _alone(ctx, mesh, prob, precision)
