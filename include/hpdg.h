@@ -274,6 +274,16 @@ int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, 
  * vectors of precision ``prec``; x != y. */
 int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream);
 
+/* y = A_level x as hpdg_apply, for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the face traces go to a
+ * fixed device array of the library (64 MiB per GPU, held until the process ends; its address
+ * is taken when the context is created) instead of the mesh's trace buffer, and the call makes
+ * no allocation of any kind.  Same kernels and result as hpdg_apply.  A level whose traces need
+ * more than 64 MiB (12 (p+1)^2 scalars per element) returns HPDG_ERR_INVALID_ARG.  Every call
+ * on a GPU shares that GPU's array: calls that overlap on one GPU (other streams, other
+ * threads, other contexts) race and must be serialised by the caller. */
+int hpdg_apply_noalloc(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream);
+
 /* Spectral bounds of every smoothed level.  With lambda_max[l] > 0 on entry the value
  * is used as given (frozen); otherwise it is computed by Alg. 5 and written back.
  * ``lambda_max`` is a host array of n_levels - 1 entries.  Synchronises ``stream``. */

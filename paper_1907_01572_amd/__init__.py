@@ -32,7 +32,7 @@ EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload"
             "hpdg_setup_smoother", "hpdg_smooth", "hpdg_vcycle", "hpdg_solve",
             "hpdg_nonlinear_residual", "hpdg_nonlinear_linearize", "hpdg_newton_solve",
             "hpdg_server_create", "hpdg_server_submit", "hpdg_server_poll", "hpdg_server_wait",
-            "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing"]
+            "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing", "hpdg_apply_noalloc"]
 
 
 class HpdgError(RuntimeError):
@@ -140,6 +140,7 @@ def load_library(path=LIB_PATH):
     lib.hpdg_mesh_free.argtypes = [vp]
     lib.hpdg_assemble_rhs.argtypes = [vp, ctypes.POINTER(RhsDesc), vp, vp]
     lib.hpdg_apply.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.hpdg_apply_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_setup_smoother.argtypes = [vp, ctypes.POINTER(SmootherParams), vp, vp]
     lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
@@ -357,6 +358,11 @@ class Mesh:
     def apply(self, x, y, level=0, stream=None):
         prec = F32 if x.dtype.itemsize == 4 else F64
         self.ctx.check(self.lib.hpdg_apply(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
+
+    def apply_noalloc(self, x, y, level=0, stream=None):
+        """y = A x with the face traces in the library's fixed scratch (no device allocation)."""
+        prec = F32 if x.dtype.itemsize == 4 else F64
+        self.ctx.check(self.lib.hpdg_apply_noalloc(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
 
     def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
                        smoother=None, stream=None, n_cheb_coarse=0, fused=True):

@@ -391,6 +391,20 @@ void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
   });
 }
 
+// the apply of level l with the face traces in the caller-free scratch ``trace`` (no timing,
+// no allocation)
+template <typename T>
+void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, hipStream_t s) {
+  const LevelHost& h = M->H[l];
+  LevelView<T> V = M->view<T>(l);
+  V.trace = trace;
+  const int* be = M->lev<T>(l).belems;
+  launch_traces<T>(V, x, s);
+  for (size_t b = 0; b < h.bucket_n.size(); ++b)
+    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
+                           h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
+}
+
 // Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)
 template <typename T>
 void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, hipStream_t s) {
@@ -1470,6 +1484,11 @@ int hpdg_create(hpdg_ctx** out, int hip_device, size_t hbm_budget_bytes) {
   if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return HPDG_ERR_HIP;
   if (hip_device < 0 || hip_device >= count) return HPDG_ERR_INVALID_ARG;
   if (hipSetDevice(hip_device) != hipSuccess) return HPDG_ERR_HIP;
+  try {
+    init_noalloc_scratch(hip_device);
+  } catch (const Error& e) {
+    return fail(nullptr, HPDG_ERR_HIP, e.what());
+  }
   auto* c = new hpdg_ctx;
   c->device = hip_device;
   c->budget = hbm_budget_bytes;
@@ -1565,6 +1584,29 @@ int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_
       apply_level<float>(mesh, level, static_cast<const float*>(x_dev), static_cast<float*>(y_dev), s);
     else
       apply_level<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), s);
+    HIPCHK(hipGetLastError());
+  });
+}
+
+int hpdg_apply_noalloc(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream) {
+  if (!mesh || !x_dev || !y_dev || x_dev == y_dev || level < 0 || level >= mesh->nlevels())
+    return mesh ? fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "invalid apply arguments") : HPDG_ERR_INVALID_ARG;
+  if (prec == HPDG_F32 && !mesh->has_f32) return fail(mesh->ctx, HPDG_ERR_UNSUPPORTED, "mesh built without FP32 levels");
+  return guarded(mesh->ctx, [&] {
+    void* scr = noalloc_scratch(mesh->ctx->device);
+    if (!scr) throw Error(HPDG_ERR_HIP, "the no-allocation scratch is not set up on this device");
+    const size_t need = size_t(mesh->H[level].ntrace) * (prec == HPDG_F32 ? sizeof(float) : sizeof(double));
+    if (need > noalloc_scratch_bytes())
+      throw Error(HPDG_ERR_INVALID_ARG, "level " + std::to_string(level) + " needs " + std::to_string(need) +
+                                            " bytes of face traces; the no-allocation apply holds at most " +
+                                            std::to_string(noalloc_scratch_bytes()) + " bytes");
+    hipStream_t s = S(stream);
+    if (prec == HPDG_F32)
+      apply_level_scratch<float>(mesh, level, static_cast<const float*>(x_dev), static_cast<float*>(y_dev),
+                                 static_cast<float*>(scr), s);
+    else
+      apply_level_scratch<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev),
+                                  static_cast<double*>(scr), s);
     HIPCHK(hipGetLastError());
   });
 }

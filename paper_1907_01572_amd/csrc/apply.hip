@@ -15,6 +15,10 @@
 // Each mortar is therefore evaluated once from each side.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+#include <string>
+#include <vector>
+
 #include "apply_common.hpp"
 #include "blocks.hpp"
 #include "device.hpp"
@@ -802,6 +806,35 @@ template void launch_traces<double>(const LevelView<double>&, const double*, hip
 template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t);
 template void launch_apply<double>(const LevelView<double>&, const double*, double*, hipStream_t);
 template void launch_apply<float>(const LevelView<float>&, const float*, float*, hipStream_t);
+// ---- face-trace scratch of the apply for callers that cannot allocate -------------------
+// The traces live in this fixed device array (each GPU the library runs on holds its own copy
+// until the process ends).  Host code never passes the array's name to a kernel: it uses the
+// device address that hipGetSymbolAddress returns for the current device, kept per device.
+namespace {
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_ptr;  // per HIP device: the address of that device's copy
+}  // namespace
+
+size_t noalloc_scratch_bytes() { return kNoAllocScratchBytes; }
+
+void init_noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < int(g_scratch_ptr.size()) && g_scratch_ptr[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !ptr)
+    throw Error(-6, std::string("hipGetSymbolAddress of the no-allocation scratch: ") + hipGetErrorString(e));
+  if (device >= int(g_scratch_ptr.size())) g_scratch_ptr.resize(device + 1, nullptr);
+  g_scratch_ptr[device] = ptr;
+}
+
+void* noalloc_scratch(int device) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return device >= 0 && device < int(g_scratch_ptr.size()) ? g_scratch_ptr[device] : nullptr;
+}
+
 template void launch_apply_bucket<double>(const LevelView<double>&, int, int, int, const int*, long long,
                                           const double*, double*, hipStream_t);
 template void launch_apply_bucket<float>(const LevelView<float>&, int, int, int, const int*, long long,

@@ -57,6 +57,12 @@ void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
                          const T* x, T* y, hipStream_t s);
+// the fixed face-trace scratch of the no-allocation apply: its capacity in bytes; set-up of the
+// current device's address (once per device, that device current; throws on failure); the
+// address kept for a device (null before set-up)
+size_t noalloc_scratch_bytes();
+void init_noalloc_scratch(int device);
+void* noalloc_scratch(int device);
 // One Jacobi-scaled Chebyshev step fused behind the apply (Alg. 4 with M the element blocks or
 // diag A): with r = b - A x, z = M^-1 r (packed FP64 / FP32 blocks, or the inverse diagonal),
 // p = alpha z + beta p (first:
