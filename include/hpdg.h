@@ -260,6 +260,30 @@ int hpdg_level_cells(const hpdg_mesh* mesh, int level, int32_t* macro, int32_t* 
                      int32_t* anchor, int32_t* p);
 int hpdg_mesh_free(hpdg_mesh* mesh);
 
+/* Coefficients of the model -div(k grad u) + c u = g (Sec. II.A.2, Eq. Laplacian: c is the
+ * f u term, read with the sign of the bilinear form of Eq. lh; k is this library's variable
+ * coefficient, folded into the metric as k J^-1 J^-T).  ``kind``: HPDG_COEF_DIFFUSION (k > 0)
+ * or HPDG_COEF_MASS (c; needs a mesh uploaded with mass_term = 1; replaced by the nonlinear
+ * calls' own mass terms when those are used).  ``where``:
+ *   HPDG_WHERE_ELEMENT   host_vals[n_elem[0]]: one value per level-0 element;
+ *   HPDG_WHERE_NODE      host_vals[n_dof[0]]: values at the LGL nodes in the level-vector layout;
+ *                        the coefficient at any point of an element is their interpolant there;
+ *   HPDG_WHERE_ANALYTIC  params: diffusion [HPDG_COEF_* kind, its 4 parameters] (as
+ *                        hpdg_disc_params); mass [c] (constant).
+ * Values are copied (FP64 master; the FP32 levels take its rounding).  Coarser levels take the
+ * mean over the level-0 cells inside each cell (per element) or the injection of the nodal
+ * field (each coarse node takes the value of the finer polynomial of the child containing it).
+ * A tabulated k may jump across a face: each side of a mortar uses its own value in
+ * {{k grad u}} and the penalty takes max(k-, k+).  The call rebuilds every level's tables and
+ * device data (the mesh handle stays valid; device vectors of the previous tables are not
+ * touched) and, when the smoother was set up, sets it up again (bounds recomputed by Alg. 5).
+ * Synchronises ``stream``.  Errors: HPDG_ERR_INVALID_ARG (unknown kind / placement, missing,
+ * non-finite or non-positive k values), HPDG_ERR_UNSUPPORTED (mass without mass_term). */
+enum { HPDG_COEF_DIFFUSION = 0, HPDG_COEF_MASS = 1 };
+enum { HPDG_WHERE_ELEMENT = 0, HPDG_WHERE_NODE = 1, HPDG_WHERE_ANALYTIC = 2 };
+int hpdg_set_coefficient(hpdg_mesh* mesh, int kind, int where, const double* host_vals, const double* params,
+                         void* stream);
+
 /* F = F_h(psi) (Eq. Fh2) for an analytic source g and Dirichlet data g_D = u, written
  * to the device FP64 vector F_dev of level 0.  Faces marked Neumann in the mesh (macro
  * face kind 2) add int g_N psi with g_N = k n.grad u (Eq. NeumannBC, n the outward normal)

@@ -21,6 +21,8 @@ F64, F32 = 0, 1
 PREC_F64, PREC_MIXED, PREC_MIXED_BF16 = 0, 1, 2
 SOLVER_FCG, SOLVER_PCG, SOLVER_FGMRES = 0, 1, 2
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
+COEF_KINDS = {"diffusion": 0, "mass": 1}
+COEF_WHERE = {"element": 0, "node": 1, "analytic": 2}
 SMOOTHERS = {"none": 0, "point": 1, "block": 2}
 TIMING_KINDS = {"apply": 0, "block": 1, "smooth": 2}
 RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4,
@@ -32,7 +34,8 @@ EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload"
             "hpdg_setup_smoother", "hpdg_smooth", "hpdg_vcycle", "hpdg_solve",
             "hpdg_nonlinear_residual", "hpdg_nonlinear_linearize", "hpdg_newton_solve",
             "hpdg_server_create", "hpdg_server_submit", "hpdg_server_poll", "hpdg_server_wait",
-            "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing", "hpdg_apply_noalloc"]
+            "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing", "hpdg_apply_noalloc",
+            "hpdg_set_coefficient"]
 
 
 class HpdgError(RuntimeError):
@@ -141,6 +144,7 @@ def load_library(path=LIB_PATH):
     lib.hpdg_assemble_rhs.argtypes = [vp, ctypes.POINTER(RhsDesc), vp, vp]
     lib.hpdg_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_apply_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.hpdg_set_coefficient.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_setup_smoother.argtypes = [vp, ctypes.POINTER(SmootherParams), vp, vp]
     lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
@@ -358,6 +362,25 @@ class Mesh:
     def apply(self, x, y, level=0, stream=None):
         prec = F32 if x.dtype.itemsize == 4 else F64
         self.ctx.check(self.lib.hpdg_apply(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
+
+    def set_coefficient(self, kind, where, values=None, params=None, stream=None):
+        """k ("diffusion") or c ("mass") per "element" (values[n_elem[0]]), per "node" (values[n_dof[0]],
+        level-vector layout) or "analytic" (params); rebuilds the level tables (and the smoother)."""
+        vals = None if values is None else np.ascontiguousarray(values, np.float64)
+        par = None if params is None else np.ascontiguousarray(params, np.float64)
+        self.ctx.check(self.lib.hpdg_set_coefficient(self.h, COEF_KINDS[kind], COEF_WHERE[where],
+                                                     vals.ctypes.data if vals is not None else None,
+                                                     par.ctypes.data if par is not None else None,
+                                                     _stream(stream)))
+        self._after_info()
+
+    def _after_info(self):
+        info = MeshInfo()
+        self.ctx.check(self.lib.hpdg_mesh_info_get(self.h, ctypes.byref(info)))
+        self.vgeo_scalars = [int(info.vgeo_scalars[i]) for i in range(self.n_levels)]
+        self.mgeo_scalars = [int(info.mgeo_scalars[i]) for i in range(self.n_levels)]
+        self.table_bytes = [int(info.table_bytes[i]) for i in range(self.n_levels)]
+        self.device_bytes = int(info.device_bytes)
 
     def apply_noalloc(self, x, y, level=0, stream=None):
         """y = A x with the face traces in the library's fixed scratch (no device allocation)."""

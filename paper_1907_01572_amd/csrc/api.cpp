@@ -131,6 +131,7 @@ struct hpdg_mesh {
   double* gm_V = nullptr;  // FGMRES basis (gm_m + 1 level-0 vectors) and directions (gm_m)
   double* gm_Z = nullptr;
   int gm_m = 0;
+  int max_levels = 32;     // cap on the hierarchy depth given at upload
   int block_retries = 0;   // block factorisations repeated after a failed attempt
   int coarse_retries = 0;  // coarse factorisations repeated after a failed attempt
   std::vector<Timed> pending;
@@ -864,6 +865,8 @@ void check_mesh(const hpdg_mesh_desc* D) {
     throw Error(HPDG_ERR_INVALID_ARG, "incomplete mesh description");
 }
 
+void build_levels(hpdg_mesh* M);
+
 // host side of an upload: macro mesh, level hierarchy, geometry / mortar / transfer tables
 std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_params* disc) {
   check_mesh(desc);
@@ -888,7 +891,7 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
     M->has_f32 = disc->build_f32 != 0;
     M->dp.mass_term = disc->mass_term != 0 ? 1 : 0;
   }
-  const int max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
+  M->max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
   M->tab.build();
   // hierarchy
   LevelHost L0;
@@ -903,19 +906,48 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
     c.p = desc->elem_p[e];
   }
   M->H.push_back(std::move(L0));
-  while (int(M->H.size()) < max_levels) {
+  build_levels(M.get());
+  return M;
+}
+
+// the level hierarchy below H[0] (surrogate coarsening, Sec. II.D.3) and every level's tables;
+// tabulated coefficients of H[0] are carried down level by level
+void build_levels(hpdg_mesh* M) {
+  M->H.resize(1);
+  while (int(M->H.size()) < M->max_levels) {
     LevelHost next;
     if (!coarsen_cells(M->mm, M->H.back().cells, next.cells)) break;
     M->H.push_back(std::move(next));
   }
-  for (auto& h : M->H) {
+  for (int l = 0; l < M->nlevels(); ++l) {
+    LevelHost& h = M->H[l];
+    if (l > 0) coarsen_fields(M->dp, M->H[l - 1], h);  // needs the finer level's records
     build_level(M->mm, M->dp, M->tab, h);
     build_diagonal(M->tab, h);
     for (double dgv : h.diag)
       if (!(dgv > 0)) throw Error(HPDG_ERR_INVALID_MESH, "non-positive operator diagonal");
   }
   for (int l = 0; l + 1 < M->nlevels(); ++l) build_transfer(M->H[l], M->H[l + 1]);
-  return M;
+}
+
+// a tabulated mass coefficient c (hpdg_set_coefficient): w det J c at every level's GL points,
+// and the point-Jacobi scaling of the operators with that mass term
+void set_mass_tables(hpdg_mesh* M, hipStream_t s) {
+  if (M->H[0].nmq == 0) throw Error(HPDG_ERR_UNSUPPORTED, "a mass coefficient needs a mesh uploaded with mass_term");
+  std::vector<double> wc;
+  for (int l = 0; l < M->nlevels(); ++l) {
+    const LevelHost& h = M->H[l];
+    mass_table(M->mm, M->dp, h, wc);
+    DevLevel<double>& d = M->lev<double>(l);
+    HIPCHK(hipMemcpyAsync(d.mcoef, wc.data(), wc.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    launch_diag_mass<double>(M->view<double>(l), d.diag, d.dinv, s);
+    if (M->has_f32) {
+      DevLevel<float>& f = M->lev<float>(l);
+      launch_convert_d2f(h.nmq, d.mcoef, f.mcoef, s);
+      launch_convert_d2f(h.ndof, d.dinv, f.dinv, s);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  }
 }
 
 // device side of an upload: tables, level data, Krylov work vectors, coarsest inverse
@@ -933,6 +965,7 @@ void upload_mesh_device(hpdg_mesh* M, hipStream_t s) {
     build_device_level<double>(M, l, s);
     if (M->has_f32) build_device_level<float>(M, l, s);
   }
+  if (M->dp.cfield) set_mass_tables(M, s);
   const long long n0 = M->H[0].ndof;
   M->r = M->alloc<double>(n0);
   M->vv = M->alloc<double>(n0);
@@ -981,6 +1014,68 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
   const size_t n0 = size_t(M->H[0].ndof), nc = size_t(M->H.back().ndof);
   b += full_max + n0 * 8 * 5 + 3 * kRedBlocks * 8 + 128 + nc * nc * 8;
   return b;
+}
+
+void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max, hipStream_t s);
+
+// rebuild every level's tables and device data after the discretisation changed (a new
+// coefficient): a fresh mesh object is built and uploaded, its device state is exchanged with
+// M's (so the caller's handle stays valid), and the old state is freed with the fresh object;
+// a smoother that was set up is set up again with its parameters (bounds recomputed)
+void rebuild_mesh(hpdg_mesh* M, hipStream_t s) {
+  HIPCHK(hipStreamSynchronize(s));
+  collect_timing(M);
+  auto F = std::make_unique<hpdg_mesh>();
+  F->ctx = M->ctx;
+  F->mm = M->mm;
+  F->dp = M->dp;
+  F->tab = M->tab;
+  F->has_f32 = M->has_f32;
+  F->max_levels = M->max_levels;
+  F->H.resize(1);
+  F->H[0].cells = M->H[0].cells;
+  F->H[0].kvals = M->H[0].kvals;
+  F->H[0].cvals = M->H[0].cvals;
+  build_levels(F.get());
+  upload_mesh_device(F.get(), s);
+  using std::swap;
+  swap(M->H, F->H);
+  swap(M->allocs, F->allocs);
+  swap(M->alloc_bytes, F->alloc_bytes);
+  swap(M->bytes, F->bytes);
+  swap(M->tab_off, F->tab_off);
+  swap(M->dg_off, F->dg_off);
+  swap(M->w_off, F->w_off);
+  swap(M->dface_off, F->dface_off);
+  swap(M->tab64, F->tab64);
+  swap(M->tab32, F->tab32);
+  swap(M->L64, F->L64);
+  swap(M->L32, F->L32);
+  swap(M->Ainv64, F->Ainv64);
+  swap(M->ncoarse, F->ncoarse);
+  swap(M->lam, F->lam);
+  swap(M->bad, F->bad);
+  swap(M->host_bad, F->host_bad);
+  swap(M->nl_b, F->nl_b);
+  swap(M->nl_rhs, F->nl_rhs);
+  swap(M->nl_delta, F->nl_delta);
+  swap(M->nl_key, F->nl_key);
+  swap(M->nl_kind, F->nl_kind);
+  swap(M->r, F->r);
+  swap(M->vv, F->vv);
+  swap(M->w, F->w);
+  swap(M->d, F->d);
+  swap(M->q, F->q);
+  swap(M->partials, F->partials);
+  swap(M->sc, F->sc);
+  swap(M->host_sc, F->host_sc);
+  swap(M->gm_V, F->gm_V);
+  swap(M->gm_Z, F->gm_Z);
+  swap(M->gm_m, F->gm_m);
+  swap(M->block_scalars, F->block_scalars);
+  swap(M->block_full_scalars, F->block_full_scalars);
+  F.reset();  // frees M's previous device state
+  if (M->smoother_ready) setup_smoother_impl(M, nullptr, nullptr, s);
 }
 
 void assemble_rhs_impl(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, hipStream_t s) {
@@ -1585,6 +1680,55 @@ int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_
     else
       apply_level<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), s);
     HIPCHK(hipGetLastError());
+  });
+}
+
+int hpdg_set_coefficient(hpdg_mesh* mesh, int kind, int where, const double* host_vals, const double* params,
+                         void* stream) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  if ((kind != HPDG_COEF_DIFFUSION && kind != HPDG_COEF_MASS) ||
+      (where != HPDG_WHERE_ELEMENT && where != HPDG_WHERE_NODE && where != HPDG_WHERE_ANALYTIC))
+    return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "unknown coefficient kind or placement");
+  if (where == HPDG_WHERE_ANALYTIC ? !params : !host_vals)
+    return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "coefficient values missing");
+  return guarded(mesh->ctx, [&] {
+    HIPCHK(hipSetDevice(mesh->ctx->device));
+    LevelHost& h0 = mesh->H[0];
+    std::vector<double> vals;
+    if (where == HPDG_WHERE_ELEMENT) vals.assign(host_vals, host_vals + h0.cells.size());
+    if (where == HPDG_WHERE_NODE) vals.assign(host_vals, host_vals + h0.ndof);
+    for (double v : vals) {
+      if (!std::isfinite(v)) throw Error(HPDG_ERR_INVALID_ARG, "non-finite coefficient value");
+      if (kind == HPDG_COEF_DIFFUSION && !(v > 0)) throw Error(HPDG_ERR_INVALID_ARG, "the diffusion coefficient must be positive");
+    }
+    if (kind == HPDG_COEF_MASS && !mesh->dp.mass_term)
+      throw Error(HPDG_ERR_UNSUPPORTED, "a mass coefficient needs a mesh uploaded with mass_term = 1");
+    if (kind == HPDG_COEF_DIFFUSION) {
+      if (where == HPDG_WHERE_ANALYTIC) {
+        const int ck = int(params[0]);
+        if (ck != HPDG_COEF_CONSTANT && ck != HPDG_COEF_RADIAL_STEP)
+          throw Error(HPDG_ERR_INVALID_ARG, "unknown analytic diffusion coefficient");
+        if (ck == HPDG_COEF_RADIAL_STEP && !(params[2] > 0 && params[3] > 0))
+          throw Error(HPDG_ERR_INVALID_ARG, "the diffusion coefficient must be positive");
+        mesh->dp.coef_kind = ck;
+        for (int i = 0; i < 4; ++i) mesh->dp.coef[i] = params[1 + i];
+        mesh->dp.kfield = 0;
+        h0.kvals.clear();
+      } else {
+        mesh->dp.kfield = where == HPDG_WHERE_ELEMENT ? 1 : 2;
+        h0.kvals = vals;
+      }
+    } else {
+      if (where == HPDG_WHERE_ANALYTIC) {
+        if (!std::isfinite(params[0])) throw Error(HPDG_ERR_INVALID_ARG, "non-finite coefficient value");
+        vals.assign(h0.cells.size(), params[0]);
+        mesh->dp.cfield = 1;
+      } else {
+        mesh->dp.cfield = where == HPDG_WHERE_ELEMENT ? 1 : 2;
+      }
+      h0.cvals = vals;
+    }
+    rebuild_mesh(mesh, S(stream));
   });
 }
 
