@@ -56,7 +56,9 @@ enum { HPDG_F64 = 0, HPDG_F32 = 1 };                 /* vector precision of a ca
  * reads bf16 inverse blocks (FP32 arithmetic; the outer FCG stays FP64 in every mode) */
 enum { HPDG_PREC_F64 = 0, HPDG_PREC_MIXED = 1, HPDG_PREC_MIXED_BF16 = 2 };
 enum { HPDG_MAP_AFFINE = 0, HPDG_MAP_SHELL = 1, HPDG_MAP_CUBE_SPHERE = 2 };
-enum { HPDG_BC_INTERIOR = 0, HPDG_BC_DIRICHLET = 1, HPDG_BC_NEUMANN = 2 };
+/* boundary kinds (Sec. II.A.1, Eqs. NeumannBC, RobinBC): Dirichlet u = g_D; Neumann
+ * k n.grad u = g_N; Robin k n.grad u + gamma u = g_R (gamma from hpdg_disc_params) */
+enum { HPDG_BC_INTERIOR = 0, HPDG_BC_DIRICHLET = 1, HPDG_BC_NEUMANN = 2, HPDG_BC_ROBIN = 3 };
 enum { HPDG_COEF_CONSTANT = 0, HPDG_COEF_RADIAL_STEP = 1 };
 enum { HPDG_RHS_SINSINSIN = 0, HPDG_RHS_SHELL_HARMONIC = 1, HPDG_RHS_RADIAL_STEP = 2,
        HPDG_RHS_POLYNOMIAL = 3, HPDG_RHS_GAUSSIANS = 4, HPDG_RHS_POLYNOMIAL_DIRICHLET = 5,
@@ -124,6 +126,8 @@ typedef struct {
  *               volume GL point by hpdg_nonlinear_linearize / hpdg_newton_solve (zero
  *               until then); the volume rule then has p + 1 + quad_extra points on every
  *               element.  Needed by the nonlinear calls.
+ *   robin_gamma gamma of the Robin faces (macro face kind HPDG_BC_ROBIN): the operator gains
+ *               int gamma u v on them (Eq. lh) and the right-hand side int g_R v.
  */
 typedef struct {
   double penalty_C;
@@ -133,6 +137,7 @@ typedef struct {
   int32_t max_levels;
   int32_t build_f32;
   int32_t mass_term;
+  double robin_gamma;
 } hpdg_disc_params;
 
 typedef struct {
@@ -288,7 +293,9 @@ int hpdg_set_coefficient(hpdg_mesh* mesh, int kind, int where, const double* hos
  * to the device FP64 vector F_dev of level 0.  Faces marked Neumann in the mesh (macro
  * face kind 2) add int g_N psi with g_N = k n.grad u (Eq. NeumannBC, n the outward normal)
  * for HPDG_RHS_SINSINSIN, HPDG_RHS_POLYNOMIAL and HPDG_RHS_POLYNOMIAL_DIRICHLET, and
- * g_N = 0 for HPDG_RHS_GAUSSIANS; other kinds with Neumann faces return HPDG_ERR_UNSUPPORTED.
+ * g_N = 0 for HPDG_RHS_GAUSSIANS; Robin faces (kind 3) add int g_R psi with
+ * g_R = k n.grad u + gamma u (Eq. RobinBC with the sign of Eq. lh; 0 for the Gaussians);
+ * other kinds with Neumann or Robin faces return HPDG_ERR_UNSUPPORTED.
  * Every face integral uses the face's own rule.  Computed on the host in FP64, then copied
  * (stream-ordered). */
 int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream);

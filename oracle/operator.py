@@ -53,7 +53,7 @@ class SIPG:
     """The discrete operator A (y = A u) and right-hand side F on one cell mesh."""
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, bc_override=None,
-                 mass=None, active=None, kfield=None, cfield=None):
+                 mass=None, active=None, kfield=None, cfield=None, robin_gamma=0.0):
         """``active``: optional element subset; the operator is then formed only for the
         rows of those elements (their volume terms and the mortars touching them), so that
         (A x) restricted to them is exact while the rest of the output stays zero.
@@ -62,6 +62,7 @@ class SIPG:
         self.mesh = mesh
         self.problem = problem
         self.C = float(C)
+        self.gamma = float(robin_gamma)  # Robin coefficient: k n.grad u + gamma u = g_R
         self.quad_extra = int(quad_extra)
         self.mass = mass  # callable c(x) >= 0 or None
         self.kfield, self.cfield = kfield, cfield
@@ -184,7 +185,7 @@ class SIPG:
     def _setup_faces(self):
         groups = {}
         for mi, mt in enumerate(self.mortars):
-            if mt["ep"] < 0 and mt["bc"] != DIRICHLET:
+            if mt["ep"] < 0 and mt["bc"] not in (DIRICHLET, ROBIN):
                 continue  # Neumann faces: no operator term
             if self.active is not None and not (self.active[mt["em"]] or
                                                 (mt["ep"] >= 0 and self.active[mt["ep"]])):
@@ -235,6 +236,7 @@ class SIPG:
                 g.update(ep=ep, Vp=Vp, Dp=Dp, xp=xp,
                          mvec_p=np.einsum("mpdi,mpi->mpd", Jip, -nhat),
                          idx_p=self.offsets[ep][:, None] + np.arange(npl ** 3)[None, :])
+            g["robin"] = bc == ROBIN
             g["kx"] = km          # the minus side's k (its own side of the mortar)
             g["kp"] = kp          # the plus side's k (= km where k is continuous)
             g["sigma"] = self.C * pm * pm / hmin * np.maximum(km, kp)
@@ -261,6 +263,8 @@ class SIPG:
                 yp = Ap @ g["Vp"] + np.einsum("mp,mpd,dpa->ma", Bp, g["mvec_p"], g["Dp"])
                 np.add.at(y, g["idx_m"], ym)
                 np.add.at(y, g["idx_p"], yp)
+            elif g["robin"]:  # Robin face: int gamma u v (the flux k n.grad u enters as data)
+                np.add.at(y, g["idx_m"], (wS * self.gamma * um) @ g["Vm"])
             else:  # Dirichlet face: [[u]] = u n, {{k grad u}} = k grad u
                 A = wS * (sig * um - kx * gm)
                 Bc = -wS * kx * um
@@ -302,6 +306,9 @@ class SIPG:
             dg[g["idx"]] += out.reshape(len(G), -1)
         for g in self.fgroups:
             wS, kx, sig = g["wS"], g["kx"], g["sigma"]
+            if g["robin"]:
+                np.add.at(dg, g["idx_m"], (wS * self.gamma) @ (g["Vm"] * g["Vm"]))
+                continue
             sides = [("Vm", "Dm", "mvec_m", "idx_m", kx)]
             if "ep" in g:
                 sides.append(("Vp", "Dp", "mvec_p", "idx_p", g["kp"]))
@@ -315,7 +322,8 @@ class SIPG:
 
     def rhs(self, problem=None):
         """F(psi) = int g psi + sum_{Dirichlet} int g_D (-k n.grad psi + sigma psi)  (Eq. Fh2)
-        + sum_{Neumann} int g_N psi (Eq. NeumannBC)."""
+        + sum_{Neumann} int g_N psi (Eq. NeumannBC) + sum_{Robin} int g_R psi (Eq. RobinBC with
+        the sign of Eq. lh: k n.grad u + gamma u = g_R, whose gamma u v enters the operator)."""
         problem = problem if problem is not None else self.problem
         F = np.zeros(self.ndof)
         for g in self.vgroups:
@@ -325,7 +333,7 @@ class SIPG:
             F[g["idx"]] += np.einsum("ck,bj,ai,ecba->ekji", B, B, B,
                                      gx.reshape(-1, q, q, q), optimize=True).reshape(len(gx), -1)
         for g in self.fgroups:
-            if "ep" in g:
+            if "ep" in g or g["robin"]:
                 continue
             gd = problems.dirichlet_g(problem, g["x"])
             A = g["wS"] * g["sigma"] * gd
@@ -335,7 +343,7 @@ class SIPG:
         # Neumann faces (Eq. NeumannBC): the boundary term int g_N psi of the integration by
         # parts, with the face's own rule
         for mt in self.mortars:
-            if mt["ep"] >= 0 or mt["bc"] != NEUMANN:
+            if mt["ep"] >= 0 or mt["bc"] not in (NEUMANN, ROBIN):
                 continue
             em, fm, nm, qm = mt["em"], mt["fm"], int(self.n[mt["em"]]), self.q_mortar(mt)
             eta, w = rules.gl(qm)
@@ -348,6 +356,8 @@ class SIPG:
             nhat = (1.0 if fm % 2 else -1.0) * row / nrm[:, None]
             wS = np.outer(w, w).reshape(-1) * np.linalg.det(J)[0] * nrm
             gN = problems.neumann_g(problem, x[0], nhat, self.k_at(np.full(len(xim), em), xim, x[0]))
+            if mt["bc"] == ROBIN:  # g_R = k n.grad u + gamma u (Eq. RobinBC, sign of Eq. lh)
+                gN = gN + self.gamma * problems.robin_u(problem, x[0])
             F[self.offsets[em] + np.arange(nm ** 3)] += (wS * gN) @ Vm
         return F
 
@@ -474,6 +484,10 @@ def element_blocks(op):
                 blocks[e] += np.einsum("p,pa,pb->ba", W * np.linalg.det(J) * cv, V, V)
     for g in op.fgroups:
         wS, kx, sig = g["wS"], g["kx"], g["sigma"]
+        if g["robin"]:
+            for i, e in enumerate(g["em"]):
+                blocks[e] += np.einsum("p,pa,pb->ba", wS[i] * op.gamma, g["Vm"], g["Vm"])
+            continue
         sides = [("Vm", "Dm", "mvec_m", "em", kx)]
         if "ep" in g:
             sides.append(("Vp", "Dp", "mvec_p", "ep", g["kp"]))
@@ -518,6 +532,19 @@ def assemble_dense(op):
             sl = slice(op.offsets[e], op.offsets[e + 1])
             A[sl, sl] += Ke
     for mt in op.mortars:
+        if mt["ep"] < 0 and mt["bc"] == ROBIN:
+            # Robin face: int gamma psi_a psi_b over the face (its own rule)
+            qm = op.q_mortar(mt)
+            eta, w = rules.gl(qm)
+            s, t = np.meshgrid(eta, eta, indexing="xy")
+            xim = face_point(mt["fm"], s.reshape(-1), t.reshape(-1))
+            _, J = geometry.element_map(op.mesh, np.full(len(xim), mt["em"]), xim)
+            rowv = np.linalg.inv(J)[:, mt["fm"] // 2, :]
+            dS = np.outer(w, w).reshape(-1) * np.linalg.det(J) * np.linalg.norm(rowv, axis=-1)
+            V, _ = _basis_at(int(op.n[mt["em"]]), xim)
+            sl = slice(op.offsets[mt["em"]], op.offsets[mt["em"] + 1])
+            A[sl, sl] += np.einsum("p,pa,pb->ba", dS * op.gamma, V, V)
+            continue
         if mt["ep"] < 0 and mt["bc"] != DIRICHLET:
             continue
         qm = op.q_mortar(mt)

@@ -170,6 +170,14 @@ def grad_u(problem, x):
     raise ValueError("no Neumann data for problem kind %s" % kind)
 
 
+def robin_u(problem, x):
+    """u on a Robin face for the Robin data g_R = k n.grad u + gamma u (0 for the Gaussian
+    sources, which carry homogeneous boundary data)."""
+    if problem["kind"] == "gaussians":
+        return np.zeros(x.shape[:-1])
+    return exact_u(problem, x)
+
+
 def neumann_g(problem, x, nhat, kx):
     """Neumann data (Eq. NeumannBC, as the flux k n.grad u of the form -div(k grad u) = g):
     g_N = k grad u . n with n the outward unit normal; 0 for "gaussians" (a source with

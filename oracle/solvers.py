@@ -200,7 +200,7 @@ class Multigrid:
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
                  n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None,
-                 starts=None, max_levels=32, kfield=None, cfield=None):
+                 starts=None, max_levels=32, kfield=None, cfield=None, robin_gamma=0.0):
         """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi) or "block"
         (element-block Jacobi); ``jacobi`` selects "point" / "none" when it is not given.
         ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``).
@@ -213,7 +213,7 @@ class Multigrid:
                 kfield = coarsen_field(self.ops[-1], m, kfield)
                 cfield = coarsen_field(self.ops[-1], m, cfield)
             self.ops.append(SIPG(m, problem, C=C, quad_extra=quad_extra, mass=mass, kfield=kfield,
-                                 cfield=cfield))
+                                 cfield=cfield, robin_gamma=robin_gamma))
         self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
         self.n_cheb, self.Lambda = n_cheb, Lambda
         self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")

@@ -56,7 +56,8 @@ class MeshDesc(ctypes.Structure):
 class DiscParams(ctypes.Structure):
     _fields_ = [("penalty_C", ctypes.c_double), ("quad_extra", ctypes.c_int32),
                 ("coef_kind", ctypes.c_int32), ("coef_params", ctypes.c_double * 4),
-                ("max_levels", ctypes.c_int32), ("build_f32", ctypes.c_int32), ("mass_term", ctypes.c_int32)]
+                ("max_levels", ctypes.c_int32), ("build_f32", ctypes.c_int32), ("mass_term", ctypes.c_int32),
+                ("robin_gamma", ctypes.c_double)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -193,9 +194,10 @@ class Context:
         return rc
 
     def upload(self, mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False,
-               stream=None, mass_term=False):
-        """``mass_term``: levels carry the Newton mass form (needed by the nonlinear calls)."""
-        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term)
+               stream=None, mass_term=False, robin_gamma=0.0):
+        """``mass_term``: levels carry the Newton mass form (needed by the nonlinear calls);
+        ``robin_gamma``: gamma of the Robin faces (macro face kind 3)."""
+        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term, robin_gamma)
 
     def close(self):
         if self.h:
@@ -218,7 +220,8 @@ def coef_from_problem(problem):
     return COEF_CONSTANT, [0.0] * 4
 
 
-def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False, mass_term=False):
+def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False, mass_term=False,
+                 robin_gamma=0.0):
     """C descriptors of a meshgen mesh; returns (MeshDesc, DiscParams, arrays to keep alive)."""
     keep = dict(
         macro_kind=np.ascontiguousarray(mesh["macro_kind"], np.int32),
@@ -246,6 +249,7 @@ def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, bu
     dp.max_levels = max_levels
     dp.build_f32 = 1 if build_f32 else 0
     dp.mass_term = 1 if mass_term else 0
+    dp.robin_gamma = robin_gamma
     return d, dp, keep
 
 
@@ -313,9 +317,11 @@ class Server:
 class Mesh:
     """An uploaded mesh: level hierarchy, geometry and solver state on the device."""
 
-    def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term=False):
+    def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term=False,
+                 robin_gamma=0.0):
         self.ctx, self.lib = ctx, ctx.lib
-        d, dp, self._keep = _descriptors(mesh, penalty_C, quad_extra, coef, max_levels, build_f32, mass_term)
+        d, dp, self._keep = _descriptors(mesh, penalty_C, quad_extra, coef, max_levels, build_f32, mass_term,
+                                         robin_gamma)
         self.h = ctypes.c_void_p()
         ctx.check(self.lib.hpdg_mesh_upload(ctx.h, ctypes.byref(d), ctypes.byref(dp),
                                             ctypes.byref(self.h), _stream(stream)))

@@ -877,6 +877,9 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
   for (int m = 0; m < nm; ++m) {
     M->mm.macros[m].kind = desc->macro_kind[m];
     if (desc->macro_kind[m] < 0 || desc->macro_kind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
+    for (int f = 0; f < 6; ++f)
+      if (desc->macro_bc[6 * m + f] < 0 || desc->macro_bc[6 * m + f] > 3)
+        throw Error(HPDG_ERR_INVALID_MESH, "unknown boundary kind");
     std::memcpy(M->mm.macros[m].par, desc->macro_params + 16 * m, 16 * sizeof(double));
   }
   M->mm.nbr.assign(desc->macro_nbr, desc->macro_nbr + 6 * nm);
@@ -890,6 +893,8 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
     for (int i = 0; i < 4; ++i) M->dp.coef[i] = disc->coef_params[i];
     M->has_f32 = disc->build_f32 != 0;
     M->dp.mass_term = disc->mass_term != 0 ? 1 : 0;
+    M->dp.robin_gamma = disc->robin_gamma;
+    if (!std::isfinite(M->dp.robin_gamma)) throw Error(HPDG_ERR_INVALID_ARG, "non-finite Robin coefficient");
   }
   M->max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
   M->tab.build();
@@ -1976,6 +1981,7 @@ int hpdg_server_submit(hpdg_server* sv, const hpdg_request* rq, uint64_t* ticket
     put(&dc.max_levels, 4);
     put(&dc.build_f32, 4);
     put(&dc.mass_term, 4);
+    put(&dc.robin_gamma, 8);
     put(r->mkind.data(), 4 * r->mkind.size());
     put(r->mparams.data(), 8 * r->mparams.size());
     put(r->mnbr.data(), 4 * r->mnbr.size());

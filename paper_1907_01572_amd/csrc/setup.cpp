@@ -349,7 +349,8 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     I.orient = mt.orient; I.sub = mt.sub; I.bc = mt.bc; I.rq = 0;
     const Cell& cm = L.cells[mt.em];
     const bool interior = mt.ep >= 0;
-    if (!interior && mt.bc != 1) {  // Neumann: no operator term
+    const bool robin = !interior && mt.bc == 3;
+    if (!interior && mt.bc != 1 && !robin) {  // Neumann: no operator term
       I.q = 0; I.gmode = 0; I.geo = -1;
       continue;
     }
@@ -436,7 +437,14 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
         for (int r = 0; r < 3; ++r)
           mplus[r] = -kxp * (Jpi[r][0] * nh[0] + Jpi[r][1] * nh[1] + Jpi[r][2] * nh[2]);
       }
-      const double sigma = dp.C * pm * pm / h * std::max(kx, kxp);
+      double sigma = dp.C * pm * pm / h * std::max(kx, kxp);
+      if (robin) {
+        // Robin face: the only operator term is int gamma u v; with zero normal-derivative
+        // coefficients the boundary flux w S (sigma u - n.grad u) of a Dirichlet face reduces to
+        // w S gamma u (and its lift has no derivative part)
+        for (int r = 0; r < 3; ++r) mminus[r] = 0.0;
+        sigma = dp.robin_gamma;
+      }
       const double wS = I.gmode ? wq[c] * wq[d] * S : S;
       double vals[8] = {mminus[0], mminus[1], mminus[2], mplus[0], mplus[1], mplus[2], wS, sigma};
       for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
@@ -871,7 +879,7 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
   // whose rule was raised to the volume rule's keeps its constant metric, valid at any q)
   for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
     const MortarInfo& M = L.minfo[mi];
-    if (M.q == 0 || M.ep >= 0) continue;
+    if (M.q == 0 || M.ep >= 0 || M.bc == 3) continue;
     const int q = M.rq;
     const ElemInfo& I = L.einfo[M.em];
     const int n = I.n, f = M.fm, d = f >> 1, t0 = d == 0 ? 1 : 0, t1_ = d == 2 ? 1 : 2;
@@ -913,10 +921,12 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
   }
   // Neumann faces (Eq. NeumannBC): int g_N psi, g_N = k grad u . n (outward n; 0 for the
   // Gaussian sources), with the face's own rule (n points, n + quad_extra on curved faces or
-  // with variable k); only the face layer of the element's nodes is nonzero on the face
+  // with variable k); only the face layer of the element's nodes is nonzero on the face.
+  // Robin faces (Eq. RobinBC, read with the sign of Eq. lh): int g_R psi with
+  // g_R = k n.grad u + gamma u (the gamma u v part is in the operator)
   for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
     const MortarInfo& M = L.minfo[mi];
-    if (M.ep >= 0 || M.bc != 2) continue;
+    if (M.ep >= 0 || (M.bc != 2 && M.bc != 3)) continue;
     if (kind != 4) {
       double g0[3];
       const double x0[3] = {0, 0, 0};
@@ -943,7 +953,8 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
         inv3(J, Ji);
         const double nr = std::sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
         if (kind != 4) exact_grad(kind, P, xx, g);
-        const double gN = k_point(dp, L, M.em, xi, xx) * sgn * (Ji[d][0] * g[0] + Ji[d][1] * g[1] + Ji[d][2] * g[2]) / nr;
+        double gN = k_point(dp, L, M.em, xi, xx) * sgn * (Ji[d][0] * g[0] + Ji[d][1] * g[1] + Ji[d][2] * g[2]) / nr;
+        if (M.bc == 3 && kind != 4) gN += dp.robin_gamma * exact_u(kind, P, xx);
         const double v = wq[x] * wq[y] * det3(J) * nr * gN;
         for (int j = 0; j < n; ++j)
           for (int i = 0; i < n; ++i) {

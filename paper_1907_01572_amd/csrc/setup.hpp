@@ -18,6 +18,7 @@ struct DiscParams {
   // in LevelHost::kvals / cvals
   int kfield = 0;
   int cfield = 0;
+  double robin_gamma = 0.0;  // k n.grad u + gamma u = g_R on Robin faces (macro face kind 3)
 };
 
 // 1-D operator tables, indexed by (kind, n, q); every matrix is row-major [q][n].

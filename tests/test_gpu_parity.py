@@ -165,6 +165,64 @@ def test_solve_with_neumann_faces_reproduces_polynomial(ctx):
     M.free()
 
 
+def _robin_faces(m, faces):
+    m = dict(m)
+    bc = np.array(m["macro_bc"], copy=True)
+    for f in faces:
+        bc[bc[:, f] == 1, f] = 3
+    m["macro_bc"] = bc
+    return m
+
+
+@pytest.mark.parametrize("name", ["box_2to1_p3", "shell_l2_p3_r1e3"])
+def test_robin_faces_apply_all_levels_and_rhs(ctx, name):
+    # Robin faces k n.grad u + gamma u = g_R (Eq. RobinBC): int gamma u v in the operator on every
+    # level, int g_R v in the right-hand side
+    m = _robin_faces(MESHES[name][0](), (1, 2, 5))
+    M = ctx.upload(m, robin_gamma=2.5)
+    mg = Multigrid(m, None, n_cheb=2, lam=[1.0] * 40, jacobi=False, robin_gamma=2.5)
+    rng = np.random.default_rng(4)
+    for l in range(M.n_levels):
+        op = mg.ops[l]
+        perm = dof_perm(M.level_cells(l), op.mesh)
+        x = rng.standard_normal(op.ndof)
+        y = torch.zeros(op.ndof, dtype=torch.float64, device="cuda")
+        M.apply(dev(x[perm]), y, level=l)
+        yo = op.apply(x)[perm]
+        err, erow = rel(host(y), yo), row_err(host(y), yo, op.diagonal()[perm], x)
+        print(name, "Robin level", l, "rel", err, "per-row", erow, flush=True)
+        assert err <= TOL_APPLY and erow <= TOL_ROW
+    for prob in [meshgen.polynomial_problem(2, seed=12), dict(kind="sinsinsin", params=np.zeros(0)),
+                 meshgen.gaussian_problem(n=4, seed=2)]:
+        F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+        M.assemble_rhs(prob, F)
+        op = SIPG(m, prob, robin_gamma=2.5)
+        err = rel(host(F), op.rhs()[dof_perm(M.level_cells(0), op.mesh)])
+        print(name, "Robin rhs", prob["kind"], err, flush=True)
+        assert err <= TOL_APPLY
+    M.free()
+
+
+def test_solve_with_robin_faces_reproduces_polynomial(ctx):
+    # affine 2:1 box, u in Q_2, Dirichlet on three sides and Robin on the others: the discrete
+    # solution is the interpolant (SIPG with Robin data is consistent)
+    m = _robin_faces(meshgen.box_grid((1, 1, 1), 1, 2, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+                     (1, 2, 5))
+    prob = meshgen.polynomial_problem(2, seed=12)
+    M = ctx.upload(m, robin_gamma=2.5)
+    M.setup_smoother(n_cheb=4, smoother="block")
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    M.assemble_rhs(prob, F)
+    u = torch.zeros_like(F)
+    st = M.solve(F, u, tol=1e-12, max_iter=300)
+    op = SIPG(m, prob, robin_gamma=2.5)
+    ui = op.interpolate(lambda X: P.exact_u(prob, X))[dof_perm(M.level_cells(0), op.mesh)]
+    err = np.abs(host(u) - ui).max() / np.abs(ui).max()
+    print("Robin solve", st, "max err vs interpolant", err, flush=True)
+    assert err <= 1e-9
+    M.free()
+
+
 def test_rhs_parity_with_mass_term(ctx):
     # a mass term raises the volume rule to n + 1 points; flat faces of a one-degree level
     # then run with that rule too, but Dirichlet data that are not polynomials must still be

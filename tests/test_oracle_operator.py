@@ -331,3 +331,56 @@ def test_tabulated_fields_coarsen_to_the_hierarchy():
     mg = Multigrid(m, None, lam=[1.0] * 10, kfield=dict(where="node", values=op0.interpolate(f)))
     for op in mg.ops[1:]:
         np.testing.assert_allclose(op.kfield["values"], SIPG(op.mesh, None).interpolate(f), atol=1e-13)
+
+
+# ---- Robin boundary data (Eq. RobinBC, read with the sign of Eq. lh) ----------------------
+
+def _robin_faces(m, faces):
+    m = dict(m)
+    bc = np.array(m["macro_bc"], copy=True)
+    for f in faces:
+        bc[bc[:, f] == 1, f] = 3
+    m["macro_bc"] = bc
+    return m
+
+
+@pytest.mark.parametrize("name,deg", [("cube_p2", 2), ("box_2to1_p2", 2), ("hp_var_p", 1), ("skew_affine", 2)])
+def test_polynomial_consistency_with_robin_faces(name, deg):
+    # k n.grad u + gamma u = g_R on some faces: the form gains int gamma u v there and F gains
+    # int g_R v; SIPG stays consistent, so A u_I = F for u in Q_p
+    prob = polynomial_problem(deg, seed=12, total=(name == "skew_affine"))
+    op = SIPG(_robin_faces(MESHES[name](), (1, 2, 5)), prob, robin_gamma=2.5)
+    u = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    assert np.linalg.norm(op.apply(u) - F) <= 1e-13 * np.linalg.norm(F)
+
+
+def test_robin_consistency_fails_with_planted_gamma_sign(monkeypatch):
+    # gamma u subtracted in the data: the consistency pin must fail
+    prob = polynomial_problem(2, seed=12)
+    good = P.robin_u
+    monkeypatch.setattr(P, "robin_u", lambda pr, x: -good(pr, x))
+    op = SIPG(_robin_faces(MESHES["box_2to1_p2"](), (1, 2, 5)), prob, robin_gamma=2.5)
+    u = op.interpolate(lambda X: P.exact_u(prob, X))
+    F = op.rhs()
+    assert np.linalg.norm(op.apply(u) - F) > 1e-6 * np.linalg.norm(F)
+
+
+@pytest.mark.parametrize("name", ["box_2to1_p2", "shell_l1_p2", "hp_var_p"])
+def test_robin_form_assembled_symmetric_spd(name):
+    # all faces Robin (gamma > 0): no Dirichlet face, the form is still SPD; matrix-free,
+    # brute-force assembly, diagonal and element blocks agree
+    m = _robin_faces(MESHES[name](), range(6))
+    op = SIPG(m, meshgen.problem_config3(r0=0.7), robin_gamma=1.5)
+    A = assemble_dense(op)
+    x = np.random.default_rng(3).standard_normal(op.ndof)
+    np.testing.assert_allclose(op.apply(x), A @ x, rtol=1e-12, atol=1e-12 * np.abs(A @ x).max())
+    np.testing.assert_allclose(A, A.T, atol=1e-12 * np.abs(A).max())
+    assert np.linalg.eigvalsh(0.5 * (A + A.T)).min() > 0
+    np.testing.assert_allclose(op.diagonal(), np.diag(A), rtol=1e-12, atol=1e-14 * np.abs(A).max())
+    for e, B in enumerate(element_blocks(op)):
+        sl = slice(op.offsets[e], op.offsets[e + 1])
+        np.testing.assert_allclose(B, A[sl, sl], atol=1e-12 * np.abs(A).max())
+    # with gamma = 0 the Robin faces are Neumann faces: A 1 = 0
+    op0 = SIPG(m, None, robin_gamma=0.0)
+    assert np.abs(op0.apply(np.ones(op0.ndof))).max() <= 1e-12 * np.abs(op0.diagonal()).max()
