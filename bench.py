@@ -1,18 +1,22 @@
 """Benchmark: MG-preconditioned FCG solves of the SIPG operator on one MI355X.
 
-Workload "shell" (default): Poisson on the six-patch cubed-sphere shell r in [1, 1e9]
-(linear radial map up to r = 10, inverse-radius compactification beyond), 8^3 cells per
-patch, innermost radial layer refined 2:1, degree p = 5 (1,244,160 DOF), manufactured
-harmonic solution u = 1/r + x z / r^5 with Dirichlet data.  One step = one solve from u = 0
-to a relative residual of 1e-10 (FP64 flexible CG, V-cycle with block-Jacobi Chebyshev
-smoothing, exact coarse solve): every row of the linear hot path runs inside it.
+Workload "hp" (default, the largest configuration whose timed solves fit about a minute):
+-div(k grad u) = g on [-1, 1]^3, 32^3 cells, degree p uniform in 2..7 per cell (seed 0),
+cells cut by r = 0.5 refined 2:1, k = 1 inside r = 0.5 and 5 outside, manufactured
+u = r^2 / k + c_k with Dirichlet data (8,649,651 DOF).  One step = one FP64 solve from u = 0
+to a relative residual of 1e-10 (flexible CG, V-cycle with point-Jacobi Chebyshev smoothing,
+exact coarse solve): every row of the linear hot path runs inside it.  The same line carries
+the mixed-precision solves (FP32 V-cycle inside FP64 FCG), the fine-level apply rate against
+the HBM and FP64 roofs, the compactified cubed-sphere shell (p = 5, 1,244,160 DOF, block-Jacobi
+smoothing with the fused apply + block step) as a sub-measurement, the committed out-of-cache
+apply sweep and the oracle's CPU rate.
 
-Other workloads (``--workload``): "hp" (the [-1,1]^3 cube, 32^3 cells, p uniform in 2..7,
-cells cut by r = 0.5 refined, k = 1 / 5 across r = 0.5; 8,649,651 DOF) and "newton" (the
-13-macro cube + compactified exterior refined around three seeded punctures, p = 6,
-12,739,363 DOF, Newton-Krylov to |R| <= 1e-10 |R_0|).  Printed: one JSON line.
+Other workloads (``--workload``): "shell" alone, "newton" (the 13-macro cube + compactified
+exterior refined around three seeded punctures, p = 6, 12,739,363 DOF, Newton-Krylov to
+|R| <= 1e-10 |R_0|), "serving" (the 512-request stream) and "sweep" (the out-of-cache apply
+rates of the uniform box, written to profiles/).  Printed: one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload shell|hp|newton]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hp|shell|newton|serving|sweep]
 """
 import argparse
 import json
@@ -27,11 +31,13 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DG operator DOF-applies/s (FP64 vs mixed); solves/s + p99 latency at 1e-10 residual"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, written by
 # --summarize-traffic; valid only while the kernel sources hash to the recorded value
-TRAFFIC_FILE = os.path.join("profiles", "solve_shell_p5_hbm_traffic.txt")
+TRAFFIC_FILE = os.path.join("profiles", "solve_hp_hbm_traffic.txt")
+APPLY_ALL_BUCKETS = "trace_kernel<double> + apply_kernel<double, n, q, false> (one launch per degree bucket)"
 KERNEL_SOURCES = [os.path.join("paper_1907_01572_amd", "csrc", f)
-                  for f in ("apply.hip", "kernels.hip", "blocks.hpp", "device.hpp", "host.hpp")]
+                  for f in ("apply.hip", "apply_common.hpp", "kernels.hip", "blocks.hpp", "device.hpp", "host.hpp")]
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read, 1 GiB written
 # kernel timing inside the timed solves: HIP events around every 8th launch of each kernel
 # kind and level (two event records per sampled launch)
@@ -111,9 +117,11 @@ def summarize_trace(stats_csv, out_md, command, trace_csv=None):
     print("\n".join(lines))
 
 
-def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, kernels, out):
+def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out, kernels=None):
     """Mean FETCH_SIZE + WRITE_SIZE per dispatch of each kernel (rocprofv3 --pmc CSVs, KiB),
-    each scaled by the same counter on a 1 GiB device copy, written as a text summary."""
+    each scaled by the same counter on a 1 GiB device copy, written as a text summary; for the
+    per-bucket FP64 apply (trace kernel + one apply_kernel launch per degree bucket) also the sum
+    over its kernels, the traffic of one finest-level apply."""
     import csv
 
     def per_kernel(path, fine_only=False):
@@ -135,6 +143,8 @@ def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, kernel
     sf = COPY_BYTES / copy_value(cal_fetch_csv)
     sw = COPY_BYTES / copy_value(cal_write_csv)
     fa, wa = per_kernel(fetch_csv, True), per_kernel(write_csv, True)
+    if kernels is None:
+        kernels = sorted(k for k in fa if "hpdg" in k)
     lines = ["# HBM traffic per fine-level launch (the kernel's dispatches with the largest grid):",
              "# rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB per dispatch), scaled by the counters read",
              "# on a 1 GiB device-to-device copy",
@@ -146,10 +156,17 @@ def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, kernel
             continue
         f = np.mean(fa[full[0]]) * sf
         w = np.mean(wa[full[0]]) * sw if full[0] in wa else float("nan")
-        lines += ["dispatches[%s]: %d" % (k, len(fa[full[0]])),
-                  "fetch_bytes_per_launch[%s]: %.0f" % (k, f),
-                  "write_bytes_per_launch[%s]: %.0f" % (k, w),
-                  "bytes_per_launch[%s]: %.0f" % (k, f + w)]
+        short = k.split("(hpdg::")[0].replace("void hpdg::(anonymous namespace)::", "")
+        lines += ["dispatches[%s]: %d" % (short, len(fa[full[0]])),
+                  "fetch_bytes_per_launch[%s]: %.0f" % (short, f),
+                  "write_bytes_per_launch[%s]: %.0f" % (short, w),
+                  "bytes_per_launch[%s]: %.0f" % (short, f + w)]
+    # one finest-level FP64 apply of a mixed-degree level: the trace kernel and every bucket's
+    # apply_kernel<double, n, q, false>
+    parts = [k for k in fa if ("apply_kernel<double," in k and "false>" in k) or "trace_kernel<double>" in k]
+    if parts:
+        tot = sum(np.mean(fa[k]) * sf + (np.mean(wa[k]) * sw if k in wa else 0.0) for k in parts)
+        lines.append("bytes_per_launch[%s]: %.0f" % (APPLY_ALL_BUCKETS, tot))
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -186,93 +203,37 @@ def make_workload(args, meshgen, hp):
     return w
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
-    ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="shell", choices=["shell", "hp", "newton", "serving"])
-    ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
-    ap.add_argument("--max-active", type=int, default=8, help="serving: requests in flight")
-    ap.add_argument("--arrival-factor", type=float, default=2.0,
-                    help="serving: Poisson arrival rate as a multiple of the FP64 sequential capacity")
-    ap.add_argument("--solver", choices=["fcg", "fgmres"], default="fcg",
-                    help="outer Krylov solver of the linear solves (fgmres: restarted flexible GMRES, 30)")
-    ap.add_argument("--n-cheb", type=int, default=0, help="0: the workload's default")
-    ap.add_argument("--n-cheb-coarse", type=int, default=-1,
-                    help="Chebyshev steps on the levels below the finest; -1: the workload's default")
-    ap.add_argument("--Lambda", type=float, default=0.0, help="0: the workload's default")
-    ap.add_argument("--max-levels", type=int, default=-1,
-                    help="multigrid levels (the last one solved exactly); -1: the workload's default, 0: all")
-    ap.add_argument("--smoother", default=None, choices=["none", "point", "block"])
-    ap.add_argument("--max-iter", type=int, default=1000)
-    ap.add_argument("--level", type=int, default=3)
-    ap.add_argument("--p", type=int, default=5)
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--apply-reps", type=int, default=50)
-    ap.add_argument("--profile-apply", action="store_true",
-                    help="only upload the mesh and run --apply-reps FP64 and FP32 applies (for rocprofv3)")
-    ap.add_argument("--unfused", action="store_true",
-                    help="block smoothing with the apply and the block step in separate kernels")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="only run one 1 GiB device-to-device copy (counter calibration)")
-    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH", "CAL_WRITE"),
-                    help="write the HBM traffic summary from rocprofv3 --pmc counter CSVs")
-    ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
-                    help="KERNEL_STATS_CSV OUT_MD COMMAND [KERNEL_TRACE_CSV]: write a markdown summary of a "
-                         "rocprofv3 --kernel-trace --stats run")
-    args = ap.parse_args()
-    if args.summarize_trace:
-        summarize_trace(*args.summarize_trace)
-        return
-    if args.summarize_traffic:
-        summarize_traffic(*args.summarize_traffic,
-                          kernels=["apply_kernel<double, 6, 7, true, true>", "apply_kernel<double, 6, 7, true, false>",
-                                   "block_sym_kernel<double, double, true>",
-                                   "apply_kernel<float, 6, 7, true, true>", "apply_kernel<float, 6, 7, true, false>",
-                                   "block_sym_kernel<float, float, true>"],
-                          out=os.path.join(ROOT, TRAFFIC_FILE))
-        return
-    if args.gpus != 1:
-        print(json.dumps({"error": "the benchmark runs on one GPU only (no multi-GPU path); --gpus %d is not supported" % args.gpus}))
-        sys.exit(2)
+def apply_flops(M, W, level=0):
+    """FP64 flops of one apply of ``level`` as the kernels compute it (an FMA is 2 flops): per
+    element the sum-factorised volume passes (three interpolations to the GL points, the GL
+    collocation derivative, the metric contraction and the transposed passes), and per face the
+    mortar interpolation of both sides, the flux and the transposed lift (neighbours taken of
+    the element's own degree, the mortar rule of the volume's).  q = n on affine elements with a
+    constant k and no mass term, n + 1 otherwise (the library's rule)."""
+    cells = M.level_cells(level)
+    n = cells["elem_p"].astype(np.float64) + 1.0
+    up = W["upload"]
+    kconst = up.get("coef") is None or up["coef"][0] == 0
+    affine = np.asarray(W["mesh"]["macro_kind"])[cells["elem_macro"]] == 0
+    q = n + np.where(affine & kconst & (not up.get("mass_term", False)), 0.0, 1.0)
+    vol = 2 * (n ** 3 * q + n ** 2 * q ** 2 + n * q ** 3) + 6 * q ** 4 + 9 * q ** 3
+    face = 6 * (9 * n ** 2 * q + 12 * n * q ** 2 + 20 * q ** 2)
+    return float(2.0 * np.sum(vol + face))
 
+
+def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
+    """Upload a workload, set up its smoother, time ``steps`` FP64 solves and as many mixed
+    (and mixed-bf16 with block smoothing) solves; returns the measurement dictionary."""
     import torch
 
-    import meshgen
-    import paper_1907_01572_amd as hp
-
-    dev = torch.device("cuda:0")
-    if args.copy_calibration:
-        x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
-        y = torch.empty_like(x)
-        torch.cuda.synchronize()
-        y.copy_(x)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_calibration_bytes": COPY_BYTES}))
-        return
-    if args.workload == "serving":
-        return run_serving(args, meshgen, hp)
-    W = make_workload(args, meshgen, hp)
     mesh, prob = W["mesh"], W["prob"]
     newton = "nl" in W
-    ctx = hp.Context(0)
+    dev = torch.device("cuda:0")
     t0 = time.time()
     up = dict(W["upload"])
     if args.max_levels >= 0:
         up["max_levels"] = args.max_levels
     M = ctx.upload(mesh, **up)
-    if args.profile_apply:
-        x64 = torch.randn(M.n_dof[0], dtype=torch.float64, device=dev)
-        y64 = torch.zeros_like(x64)
-        x32, y32 = x64.float(), torch.zeros_like(x64, dtype=torch.float32)
-        for _ in range(args.apply_reps):
-            M.apply(x64, y64)
-        for _ in range(args.apply_reps):
-            M.apply(x32, y32)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_apply": True, "dof": M.n_dof[0], "reps": args.apply_reps}))
-        return
     if args.n_cheb_coarse >= 0:
         W["smoother"]["n_cheb_coarse"] = args.n_cheb_coarse
     if args.unfused:
@@ -294,7 +255,7 @@ def main():
         return M.solve(F, u, tol=1e-10, max_iter=args.max_iter, precision=prec,
                        solver=hp.SOLVER_FGMRES if args.solver == "fgmres" else hp.SOLVER_FCG)
 
-    for _ in range(args.warmup):
+    for _ in range(warmup):
         solve(hp.PREC_F64)
     torch.cuda.synchronize()
     L = M.n_levels
@@ -308,7 +269,7 @@ def main():
         M.timing_enable(TIMING_EVERY)
         lat, its, sts = [], [], []
         t_start = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             a = time.perf_counter()
             st = solve(prec)
             torch.cuda.synchronize()
@@ -320,21 +281,18 @@ def main():
         return elapsed, lat, its, sts, read_timing(hp.F64), read_timing(hp.F32)
 
     elapsed, lat, iters, sts, t64, _ = timed_solves(hp.PREC_F64)
-    ms_per_step = elapsed * 1e3 / args.steps
-    solves_per_s = args.steps / elapsed
     st = sts[-1]
     solve(hp.PREC_MIXED)  # warm the FP32 path
     torch.cuda.synchronize()
     el_mx, lat_mx, it_mx, sts_mx, _, t32 = timed_solves(hp.PREC_MIXED)
     stm = sts_mx[-1]
-    mixed_solves_per_s = args.steps / el_mx
     bf16_info = None
     if W["smoother"]["smoother"] == "block":
         # FP32 V-cycle whose block-Jacobi smoother reads bf16 inverse blocks
         solve(hp.PREC_MIXED_BF16)
         torch.cuda.synchronize()
         el_bf, lat_bf, it_bf, sts_bf, _, _ = timed_solves(hp.PREC_MIXED_BF16)
-        bf16_info = {"solves_per_s": round(args.steps / el_bf, 4), "iterations": it_bf,
+        bf16_info = {"solves_per_s": round(steps / el_bf, 4), "iterations": it_bf,
                      "final_rel_residual": sts_bf[-1]["rel_residual"],
                      "p50_ms": float(np.percentile(lat_bf, 50)), "p99_ms": float(np.percentile(lat_bf, 99))}
 
@@ -342,46 +300,158 @@ def main():
         return (sum(e[0] for e in entries), sum(e[1] for e in entries), sum(e[2] for e in entries))
 
     kernels = {}
-    names = ({"apply": "apply_kernel<double, 6, 7, true, false>", "block": "block_sym_kernel<double, double, true>",
-              "smooth": "apply_kernel<double, 6, 7, true, true>"}
-             if args.workload == "shell" else
-             {"apply": "apply_kernel<double, *> (all buckets)", "block": "block_sym_kernel<double, double, true>",
-              "smooth": "apply_kernel<double, *, *, true, true>"})
     for kind in TIMED_KINDS:
         ms, n, b = totals(t64[kind])
         if n:
-            kernels[kind] = {"kernel": names[kind], "total_ms": ms, "launches": n, "avg_launch_us": 1e3 * ms / n,
+            kernels[kind] = {"kernel": kinds_names[kind], "total_ms": ms, "launches": n, "avg_launch_us": 1e3 * ms / n,
                              "alg_bytes_per_launch": b / n, "gbs": b / (ms * 1e-3) / 1e9,
                              "per_level_launches": [e[1] for e in t64[kind]],
                              "per_level_avg_us": [round(1e3 * e[0] / e[1], 2) if e[1] else None for e in t64[kind]]}
-    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
-    K = kernels[dom]
-    # roofline of the dominant kernel on the finest level (its largest launches)
-    msR, nR, bR = t64[dom][0]
-    R_us, R_bytes = 1e3 * msR / nR, bR / nR
-    R_gbs = R_bytes / (R_us * 1e-6) / 1e9
     ms0, n0, b0 = t64["apply"][0]
     ms0_32, n0_32, b0_32 = t32["apply"][0]
     apply_ms64 = ms0 / n0
     apply_ms32 = ms0_32 / n0_32 if n0_32 else float("nan")
-
-    solve_info = {"iterations": iters, "final_rel_residual": st["rel_residual"],
+    flops = apply_flops(M, W, 0)
+    res = {
+        "M": M, "N": N, "lam": lam, "setup_s": setup_s, "elapsed": elapsed, "iters": iters, "lat": lat,
+        "solves_per_s": steps / elapsed, "ms_per_step": elapsed * 1e3 / steps, "t64": t64, "kernels": kernels,
+        "solve": {"iterations": iters, "final_rel_residual": st["rel_residual"],
                   "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                  "setup_s": round(setup_s, 3), "lambda_max": [round(float(v), 4) for v in lam]}
-    mixed_info = {"solves_per_s": round(mixed_solves_per_s, 4), "iterations": it_mx,
-                  "final_rel_residual": stm["rel_residual"],
-                  "p50_ms": float(np.percentile(lat_mx, 50)), "p99_ms": float(np.percentile(lat_mx, 99))}
+                  "setup_s": round(setup_s, 3), "lambda_max": [round(float(v), 4) for v in lam],
+                  "setup_retries": list(M.setup_retries())},
+        "mixed": {"solves_per_s": round(steps / el_mx, 4), "iterations": it_mx, "final_rel_residual": stm["rel_residual"],
+                  "p50_ms": float(np.percentile(lat_mx, 50)), "p99_ms": float(np.percentile(lat_mx, 99))},
+        "mixed_bf16_blocks": bf16_info,
+        # fine-level operator applies inside the timed solves (HIP events on the solve stream)
+        "apply": {"dof_applies_per_s_f64": N / (apply_ms64 * 1e-3), "dof_applies_per_s_f32": N / (apply_ms32 * 1e-3),
+                  "kernel_ms_f64": apply_ms64, "kernel_ms_f32": apply_ms32,
+                  "alg_bytes_f64": b0 / n0, "alg_bytes_f32": b0_32 / n0_32 if n0_32 else None,
+                  "gbs_f64": b0 / (ms0 * 1e-3) / 1e9,
+                  "gbs_f32": b0_32 / (ms0_32 * 1e-3) / 1e9 if n0_32 else None,
+                  "hbm_frac_f64": round(b0 / (ms0 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                  "flops_f64": flops, "fp64_tflops": flops / (apply_ms64 * 1e-3) / 1e12,
+                  "fp64_alu_frac": round(flops / (apply_ms64 * 1e-3) / 1e12 / FP64_PEAK_TFLOPS, 4)},
+    }
     if newton:
-        solve_info["newton_steps"] = [s["newton_steps"] for s in sts]
-        mixed_info["newton_steps"] = [s["newton_steps"] for s in sts_mx]
+        res["solve"]["newton_steps"] = [s["newton_steps"] for s in sts]
+        res["mixed"]["newton_steps"] = [s["newton_steps"] for s in sts_mx]
+    return res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="hp", choices=["hp", "shell", "newton", "serving", "sweep"])
+    ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
+    ap.add_argument("--max-active", type=int, default=8, help="serving: requests in flight")
+    ap.add_argument("--arrival-factor", type=float, default=1.0,
+                    help="serving: Poisson arrival rate as a multiple of the FP64 sequential capacity")
+    ap.add_argument("--solver", choices=["fcg", "fgmres"], default="fcg",
+                    help="outer Krylov solver of the linear solves (fgmres: restarted flexible GMRES, 30)")
+    ap.add_argument("--n-cheb", type=int, default=0, help="0: the workload's default")
+    ap.add_argument("--n-cheb-coarse", type=int, default=-1,
+                    help="Chebyshev steps on the levels below the finest; -1: the workload's default")
+    ap.add_argument("--Lambda", type=float, default=0.0, help="0: the workload's default")
+    ap.add_argument("--max-levels", type=int, default=-1,
+                    help="multigrid levels (the last one solved exactly); -1: the workload's default, 0: all")
+    ap.add_argument("--smoother", default=None, choices=["none", "point", "block"])
+    ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--level", type=int, default=3)
+    ap.add_argument("--p", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-shell", action="store_true", help="hp workload: skip the shell sub-measurement")
+    ap.add_argument("--shell-steps", type=int, default=5, help="timed solves of the shell sub-measurement")
+    ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--profile-apply", action="store_true",
+                    help="only upload the mesh and run --apply-reps FP64 and FP32 applies (for rocprofv3)")
+    ap.add_argument("--unfused", action="store_true",
+                    help="block smoothing with the apply and the block step in separate kernels")
+    ap.add_argument("--sweep-p", default="2,3,4,5,6,7", help="sweep: degrees")
+    ap.add_argument("--sweep-gb", type=float, default=2.0, help="sweep: algorithmic GB per FP64 apply (at least)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run one 1 GiB device-to-device copy (counter calibration)")
+    ap.add_argument("--summarize-traffic", nargs=4, metavar=("FETCH_CSV", "WRITE_CSV", "CAL_FETCH", "CAL_WRITE"),
+                    help="write the HBM traffic summary from rocprofv3 --pmc counter CSVs")
+    ap.add_argument("--summarize-trace", nargs="+", metavar="ARG",
+                    help="KERNEL_STATS_CSV OUT_MD COMMAND [KERNEL_TRACE_CSV]: write a markdown summary of a "
+                         "rocprofv3 --kernel-trace --stats run")
+    args = ap.parse_args()
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(*args.summarize_traffic, out=os.path.join(ROOT, TRAFFIC_FILE))
+        return
+    if args.gpus != 1:
+        print(json.dumps({"error": "the benchmark runs on one GPU only (no multi-GPU path); --gpus %d is not supported" % args.gpus}))
+        sys.exit(2)
+
+    import torch
+
+    import meshgen
+    import paper_1907_01572_amd as hp
+
+    dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        x = torch.ones(COPY_BYTES // 8, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": COPY_BYTES}))
+        return
+    if args.workload == "serving":
+        return run_serving(args, meshgen, hp)
+    if args.workload == "sweep":
+        return run_sweep(args, meshgen, hp)
+    W = make_workload(args, meshgen, hp)
+    ctx = hp.Context(0)
+    if args.profile_apply:
+        up = dict(W["upload"])
+        if args.max_levels >= 0:
+            up["max_levels"] = args.max_levels
+        M = ctx.upload(W["mesh"], **up)
+        x64 = torch.randn(M.n_dof[0], dtype=torch.float64, device=dev)
+        y64 = torch.zeros_like(x64)
+        x32, y32 = x64.float(), torch.zeros_like(x64, dtype=torch.float32)
+        for _ in range(args.apply_reps):
+            M.apply(x64, y64)
+        for _ in range(args.apply_reps):
+            M.apply(x32, y32)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_apply": True, "dof": M.n_dof[0], "reps": args.apply_reps}))
+        return
+    names = ({"apply": "apply_kernel<double, 6, 7, true, false>", "block": "block_sym_kernel<double, double, true>",
+              "smooth": "apply_kernel<double, 6, 7, true, true>"}
+             if args.workload == "shell" else
+             {"apply": APPLY_ALL_BUCKETS,
+              "block": "block_sym_kernel<double, double, true>", "smooth": "apply_kernel<double, n, q, true, true>"})
+    R = run_solves(args, W, hp, ctx, args.steps, args.warmup, names)
+    M, N, kernels, t64 = R["M"], R["N"], R["kernels"], R["t64"]
+    dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
+    # roofline of the dominant kernel on the finest level (its largest launches): the method's
+    # algorithmic bytes per launch (the library's count, see the timing call) over the mean event time
+    msR, nR, bR = t64[dom][0]
+    R_us, R_bytes = 1e3 * msR / nR, bR / nR
+    R_gbs = R_bytes / (R_us * 1e-6) / 1e9
+    roof = {"bound": "hbm", "achieved": round(R_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(R_gbs / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(kernels[dom]["kernel"], R_bytes),
+            "kernel": kernels[dom]["kernel"], "level": "finest", "avg_launch_us": round(R_us, 2),
+            "alg_bytes_per_launch": round(R_bytes)}
+    if dom == "apply":
+        roof["fp64_alu_frac"] = R["apply"]["fp64_alu_frac"]
+        roof["fp64_tflops"] = round(R["apply"]["fp64_tflops"], 3)
     out = {
         "metric": METRIC,
-        "value": round(solves_per_s, 4),
+        "value": round(R["solves_per_s"], 4),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 3),
+        "ms_per_step": round(R["ms_per_step"], 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -392,31 +462,51 @@ def main():
                    "n_cheb": W["smoother"]["n_cheb"], "n_cheb_coarse": W["smoother"].get("n_cheb_coarse", 0),
                    "Lambda": W["smoother"]["Lambda"],
                    "smoother": W["smoother"]["smoother"], "solver": args.solver},
-        "solve": solve_info,
-        "mixed": mixed_info,
-        "mixed_bf16_blocks": bf16_info,
-        # fine-level operator applies inside the timed solves (HIP events on the solve stream)
-        "apply": {"dof_applies_per_s_f64": N / (apply_ms64 * 1e-3),
-                  "dof_applies_per_s_f32": N / (apply_ms32 * 1e-3),
-                  "kernel_ms_f64": apply_ms64, "kernel_ms_f32": apply_ms32,
-                  "alg_bytes_f64": b0 / n0, "alg_bytes_f32": b0_32 / n0_32 if n0_32 else None,
-                  "gbs_f64": b0 / (ms0 * 1e-3) / 1e9,
-                  "gbs_f32": b0_32 / (ms0_32 * 1e-3) / 1e9 if n0_32 else None},
+        "solve": R["solve"],
+        "mixed": R["mixed"],
+        "mixed_bf16_blocks": R["mixed_bf16_blocks"],
+        "apply": R["apply"],
         "kernels_f64_solve": kernels,
-        "roofline": {"bound": "hbm", "achieved": round(R_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(R_gbs / HBM_PEAK_GBS, 4),
-                     "traffic": measured_traffic(K["kernel"], R_bytes) if args.workload == "shell" else None,
-                     "kernel": K["kernel"], "level": "finest", "avg_launch_us": round(R_us, 2),
-                     "alg_bytes_per_launch": round(R_bytes)},
+        "roofline": roof,
     }
     if not args.no_cpu:
-        n_lin = float(np.mean(iters))
-        n_newton = float(np.mean(solve_info.get("newton_steps", [0])))
-        out["cpu_baseline"] = cpu_baseline(mesh, prob, M, W["smoother"]["n_cheb"],
+        n_lin = float(np.mean(R["iters"]))
+        n_newton = float(np.mean(R["solve"].get("newton_steps", [0])))
+        out["cpu_baseline"] = cpu_baseline(W["mesh"], W["prob"], M, W["smoother"]["n_cheb"],
                                            W["smoother"].get("n_cheb_coarse", 0), n_lin, n_newton,
-                                           mass=newton)
-    print(json.dumps(out))
+                                           mass="nl" in W)
     M.free()
+    if args.workload == "hp" and not args.no_shell:
+        # the compactified shell (p = 5, 1,244,160 DOF): its own solves, smoother and fused step
+        a2 = argparse.Namespace(**vars(args))
+        a2.workload, a2.n_cheb, a2.Lambda, a2.smoother = "shell", 0, 0.0, None
+        W2 = make_workload(a2, meshgen, hp)
+        n2 = {"apply": "apply_kernel<double, 6, 7, true, false>", "block": "block_sym_kernel<double, double, true>",
+              "smooth": "apply_kernel<double, 6, 7, true, true>"}
+        S = run_solves(a2, W2, hp, ctx, args.shell_steps, 1, n2)
+        k2 = S["kernels"]
+        d2 = max(k2, key=lambda k: k2[k]["total_ms"])
+        ms2, c2, b2 = S["t64"][d2][0]
+        sm = {"workload": W2["desc"] + " (%d DOF)" % S["N"], "steps": args.shell_steps,
+              "solves_per_s": round(S["solves_per_s"], 4), "solve": S["solve"], "mixed": S["mixed"],
+              "mixed_bf16_blocks": S["mixed_bf16_blocks"], "apply": S["apply"],
+              "n_cheb": W2["smoother"]["n_cheb"], "Lambda": W2["smoother"]["Lambda"], "smoother": "block",
+              "dominant_kernel": {"kernel": k2[d2]["kernel"], "avg_launch_us": round(1e3 * ms2 / c2, 2),
+                                  "alg_bytes_per_launch": round(b2 / c2),
+                                  "hbm_frac": round(b2 / c2 / (ms2 / c2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}}
+        if d2 == "smooth":
+            # the fused step's bytes are mostly the packed element-block inverses (the block-Jacobi
+            # smoother's own data, N (N + 1) / 2 FP64 values per element, N = (p + 1)^3); the
+            # operator's own share is the apply's bytes without the y write
+            nb = (S["M"].level_cells(0)["elem_p"].astype(np.float64) + 1) ** 3
+            blk = float(8.0 * np.sum(nb * (nb + 1) / 2))
+            sm["dominant_kernel"]["block_inverse_bytes_per_launch"] = round(blk)
+            sm["dominant_kernel"]["method_bytes_per_launch"] = round(b2 / c2 - blk)
+            sm["dominant_kernel"]["method_hbm_frac"] = round((b2 / c2 - blk) / (ms2 / c2 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        S["M"].free()
+        out["shell"] = sm
+    out["sweep"] = committed_sweep()
+    print(json.dumps(out))
     ctx.close()
 
 
@@ -517,30 +607,59 @@ def run_serving(args, meshgen, hp):
     ctx.close()
 
 
-def cpu_baseline(mesh, prob, M, n_cheb, n_cheb_coarse, n_lin, n_newton, mass=False):
-    """The oracle's matrix-free apply on a bounded sample of the same mesh, on the host."""
+def _oracle_apply_rate(job):
+    """One host worker: the oracle's matrix-free apply restricted to ``elems`` (their rows exact),
+    repeated for about ``seconds`` on one thread; returns (sample DOF, applies, seconds, setup s)."""
+    mesh, prob, elems, mass, seconds, seed = job
     from threadpoolctl import threadpool_limits
 
     from oracle.operator import SIPG
 
-    rng = np.random.default_rng(0)
-    E = len(mesh["elem_p"])
-    sample = np.sort(rng.choice(E, size=min(E, 192), replace=False))
     with threadpool_limits(limits=1):
         t0 = time.perf_counter()
-        op = SIPG(mesh, prob, active=sample, mass=(lambda x: np.zeros(x.shape[:-1])) if mass else None)
+        op = SIPG(mesh, prob, active=elems, mass=(lambda x: np.zeros(x.shape[:-1])) if mass else None)
         t_setup = time.perf_counter() - t0
-        x = rng.standard_normal(op.ndof)
+        x = np.random.default_rng(seed).standard_normal(op.ndof)
         reps = 0
         t0 = time.perf_counter()
         while True:
             op.apply(x)
             reps += 1
-            if time.perf_counter() - t0 > 12.0 or reps >= 400:
+            if time.perf_counter() - t0 > seconds or reps >= 400:
                 break
-        t_apply = (time.perf_counter() - t0) / reps
-    sample_dof = int(np.sum((mesh["elem_p"][sample].astype(np.int64) + 1) ** 3))
-    dof_apply_per_s = sample_dof / t_apply
+        el = time.perf_counter() - t0
+    dof = int(np.sum((np.asarray(mesh["elem_p"])[elems].astype(np.int64) + 1) ** 3))
+    return dof, reps, el, t_setup
+
+
+def host_cores():
+    """Logical CPUs the host reports, and the workers used (the box's share: at most 16)."""
+    n = os.cpu_count() or 1
+    try:
+        n_aff = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n_aff = n
+    return n, n_aff, max(1, min(n_aff, 16))
+
+
+def cpu_baseline(mesh, prob, M, n_cheb, n_cheb_coarse, n_lin, n_newton, mass=False):
+    """The oracle's matrix-free apply on bounded samples of the same mesh, on the host: one
+    thread, and one worker process per core of the box's share (each on its own sample)."""
+    import multiprocessing as mp
+
+    rng = np.random.default_rng(0)
+    E = len(mesh["elem_p"])
+    sample = np.sort(rng.choice(E, size=min(E, 192), replace=False))
+    dof1, reps1, el1, setup1 = _oracle_apply_rate((mesh, prob, sample, mass, 10.0, 0))
+    rate1 = dof1 * reps1 / el1
+    n_cpu, n_aff, workers = host_cores()
+    jobs = [(mesh, prob, np.sort(rng.choice(E, size=min(E, 96), replace=False)), mass, 8.0, w + 1)
+            for w in range(workers)]
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(workers) as pool:  # fresh interpreters: no GPU state
+        res = pool.map(_oracle_apply_rate, jobs)
+    wall = time.perf_counter() - t0
+    rate_all = sum(d * r / e for d, r, e, _ in res)
     # DOF-applies of one GPU solve, counted from its structure: the initial residual, then per
     # FCG iteration one fine apply plus, on every smoothed level, (n_cheb - 1) pre-smoothing
     # applies (the first step starts from zero), one residual and n_cheb post-smoothing applies;
@@ -551,12 +670,100 @@ def cpu_baseline(mesh, prob, M, n_cheb, n_cheb_coarse, n_lin, n_newton, mass=Fal
     per_iter = M.n_dof[0] + sum(2 * steps[lv] * M.n_dof[lv] for lv in range(M.n_levels - 1))
     per_newton = 2 * M.n_dof[0] + sum(15 * M.n_dof[lv] for lv in range(M.n_levels - 1))
     dof_applies = M.n_dof[0] + n_lin * per_iter + n_newton * per_newton
-    return {"value": dof_apply_per_s / dof_applies, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "oracle matrix-free apply on %d of %d elements (%d DOF), %d reps in %.1fs (setup %.1fs), "
-                      "one thread: %.3e DOF-applies/s, divided by the %.3e DOF-applies of one GPU solve"
-                      % (len(sample), E, sample_dof, reps, t_apply * reps, t_setup, dof_apply_per_s,
-                         dof_applies),
-            "dof_applies_per_s": dof_apply_per_s}
+    return {"value": rate_all / dof_applies, "unit": "solves/s", "cores": workers, "kind": "oracle",
+            "sample": "oracle matrix-free apply (numpy FP64) on seeded element samples of the same mesh: %d worker "
+                      "processes of one thread each (%d logical CPUs reported, %d in this process's affinity), "
+                      "96 elements each, about 8 s each (%.1f s wall): %.3e DOF-applies/s together; divided by "
+                      "the %.3e DOF-applies of one GPU solve" % (workers, n_cpu, n_aff, wall, rate_all, dof_applies),
+            "dof_applies_per_s": rate_all,
+            "single_thread": {"value": rate1 / dof_applies, "dof_applies_per_s": rate1, "cores": 1,
+                              "sample": "%d of %d elements (%d DOF), %d applies in %.1f s (setup %.1f s)"
+                                        % (len(sample), E, dof1, reps1, el1, setup1)}}
+
+
+SWEEP_FILE = os.path.join("profiles", "apply_sweep_uniform_box.json")
+
+
+def run_sweep(args, meshgen, hp):
+    """Out-of-cache apply rates: the unit box as M^3 affine macros refined to a level, degree p
+    (the plain-method family), sized so that one FP64 apply moves at least --sweep-gb GB of
+    algorithmic bytes; FP64 and FP32 applies timed with HIP events; written to SWEEP_FILE."""
+    import torch
+
+    ctx = hp.Context(0)
+    rows = []
+    for p in [int(v) for v in args.sweep_p.split(",")]:
+        n3 = (p + 1) ** 3
+        # algorithmic bytes per element: x and y (16 n^3), the 6 metric values, the element
+        # record and six face-task records (the library's count)
+        per_el = 16.0 * n3 + 48.0 + 88.0 + 6 * 32.0
+        need = args.sweep_gb * 1e9 / per_el
+        best = None
+        for level in range(2, 8):
+            for Mm in range(1, 9):
+                E = Mm ** 3 * 8 ** level
+                if E >= need and (best is None or E < best[0]):
+                    best = (E, Mm, level)
+        E, Mm, level = best
+        t0 = time.time()
+        mesh = meshgen.uniform_box((Mm, Mm, Mm), level, p)
+        M = ctx.upload(mesh, build_f32=True, max_levels=1)  # applies only: one level
+        up = time.time() - t0
+        row = {"p": p, "macros": Mm, "level": level, "elements": M.n_elem[0], "dof": M.n_dof[0],
+               "cells_per_axis": Mm * 2 ** level, "upload_s": round(up, 1)}
+        W = {"upload": {}, "mesh": mesh}
+        flops = apply_flops(M, W, 0)
+        for dt, tag, sc in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
+            x = torch.randn(M.n_dof[0], dtype=dt, device="cuda")
+            y = torch.zeros_like(x)
+            for _ in range(3):
+                M.apply(x, y)
+            torch.cuda.synchronize()
+            M.timing_enable(1)
+            M.kernel_timing("apply", 0, hp.F64 if sc == 8 else hp.F32)
+            for _ in range(args.apply_reps):
+                M.apply(x, y)
+            ms, n, b = M.kernel_timing("apply", 0, hp.F64 if sc == 8 else hp.F32)
+            M.timing_enable(0)
+            t = ms / n * 1e-3
+            row[tag] = {"ms": round(ms / n, 4), "gdof_per_s": round(M.n_dof[0] / t / 1e9, 3),
+                        "alg_bytes": round(b / n), "gbs": round(b / n / t / 1e9, 1),
+                        "hbm_frac": round(b / n / t / 1e9 / HBM_PEAK_GBS, 4)}
+            if sc == 8:
+                row[tag]["fp64_tflops"] = round(flops / t / 1e12, 3)
+                row[tag]["fp64_alu_frac"] = round(flops / t / 1e12 / FP64_PEAK_TFLOPS, 4)
+            del x, y
+        print(json.dumps(row), flush=True)
+        rows.append(row)
+        M.free()
+        del mesh
+    out = {"family": "unit box, M^3 affine macros refined uniformly, degree p, constant k (q = p + 1)",
+           "min_alg_gb_per_apply": args.sweep_gb, "reps": args.apply_reps, "rows": rows,
+           "sources_sha256": kernel_sources_sha256(),
+           "command": "python bench.py --workload sweep --sweep-p %s --sweep-gb %g --apply-reps %d"
+                      % (args.sweep_p, args.sweep_gb, args.apply_reps)}
+    with open(os.path.join(ROOT, SWEEP_FILE), "w") as fh:
+        json.dump(out, fh, indent=1)
+    print(json.dumps({"sweep_written": SWEEP_FILE, "rows": len(rows)}))
+    ctx.close()
+
+
+def committed_sweep():
+    """The committed out-of-cache sweep (bench.py --workload sweep), or None when the kernel
+    sources changed since it was measured."""
+    path = os.path.join(ROOT, SWEEP_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        d = json.load(fh)
+    if d.get("sources_sha256") != kernel_sources_sha256():
+        return None
+    return {"source": SWEEP_FILE, "command": d["command"], "family": d["family"],
+            "rows": [{"p": r["p"], "dof": r["dof"], "cells_per_axis": r["cells_per_axis"],
+                      "alg_gb": round(r["f64"]["alg_bytes"] / 1e9, 3), "f64_gdof_per_s": r["f64"]["gdof_per_s"],
+                      "f64_hbm_frac": r["f64"]["hbm_frac"], "f64_alu_frac": r["f64"]["fp64_alu_frac"],
+                      "f32_gdof_per_s": r["f32"]["gdof_per_s"], "f32_hbm_frac": r["f32"]["hbm_frac"]}
+                     for r in d["rows"]]}
 
 
 if __name__ == "__main__":

@@ -118,8 +118,9 @@ typedef struct {
  *   coef_kind   HPDG_COEF_*: k = 1, or k = coef_params[1] for |x| < coef_params[0]
  *               and coef_params[2] otherwise.
  *   max_levels  cap on the number of multigrid levels (0 = until the macro-mesh). The last
- *               level is solved exactly through a dense FP64 inverse (N_c^2 scalars): N_c^2
- *               must stay below 2^31, else the upload fails with HPDG_ERR_UNSUPPORTED.
+ *               level is solved exactly through a dense FP64 inverse (N_c^2 scalars), formed by
+ *               hpdg_setup_smoother: N_c^2 must stay below 2^31, else that call fails with
+ *               HPDG_ERR_UNSUPPORTED (a mesh used only for applies never forms it).
  *   build_f32   also build FP32 copies of every level (needed by HPDG_F32 calls and
  *               mixed-precision solves).
  *   mass_term   1: every level carries a mass form  sum_sigma w det J c u v  with c set per
@@ -315,7 +316,9 @@ int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_
  * threads, other contexts) race and must be serialised by the caller. */
 int hpdg_apply_noalloc(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream);
 
-/* Spectral bounds of every smoothed level.  With lambda_max[l] > 0 on entry the value
+/* Solver setup: the exact coarse solve (the coarsest operator assembled on the device,
+ * Cholesky and explicit inverse; once per mesh), the smoother's scaling data, and the spectral
+ * bounds of every smoothed level.  With lambda_max[l] > 0 on entry the value
  * is used as given (frozen); otherwise it is computed by Alg. 5 and written back.
  * ``lambda_max`` is a host array of n_levels - 1 entries.  Synchronises ``stream``. */
 int hpdg_setup_smoother(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max,

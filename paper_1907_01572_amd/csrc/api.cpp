@@ -981,7 +981,6 @@ void upload_mesh_device(hpdg_mesh* M, hipStream_t s) {
   M->sc = M->alloc<double>(16);
   HIPCHK(hipHostMalloc((void**)&M->host_sc, 16 * sizeof(double), hipHostMallocDefault));
   launch_fill<double>(16, 0.0, M->sc, s);
-  build_coarse(M, s);
   M->lam.assign(M->nlevels(), 0.0);
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(hipGetLastError());
@@ -1104,6 +1103,9 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
     if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)
       throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
   }
+  // the exact coarse solve is part of the solver's setup: a mesh used only for applies never
+  // forms the dense inverse (whose size limits the coarsest level)
+  if (!mesh->Ainv64) build_coarse(mesh, s);
   if (mesh->sp.scaling == HPDG_SMOOTH_BLOCK)
     for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
   if (mesh->sp.scaling != HPDG_SMOOTH_NONE)  // the fused Jacobi-scaled steps' second trace buffer

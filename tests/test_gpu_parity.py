@@ -466,10 +466,16 @@ def test_budget_admission(ctx):
 
 
 def test_coarse_level_too_large_for_dense_solve(ctx):
-    # one level of 82,944 DOF: its dense matrix has more than 2^31 entries
+    # one level of 82,944 DOF: its dense matrix has more than 2^31 entries; the mesh still
+    # applies (the coarse inverse is formed by the solver setup, which refuses it)
+    M = ctx.upload(meshgen.cubed_sphere_shell(level=2, p=5), max_levels=1)
+    x = torch.ones(M.n_dof[0], dtype=torch.float64, device="cuda")
+    y = torch.zeros_like(x)
+    M.apply(x, y)
     with pytest.raises(hp.HpdgError) as ei:
-        ctx.upload(meshgen.cubed_sphere_shell(level=2, p=5), max_levels=1)
+        M.setup_smoother()
     assert ei.value.code == hp.ERR_UNSUPPORTED
+    M.free()
 
 
 def test_coarse_chebyshev_degree(ctx):

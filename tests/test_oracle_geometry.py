@@ -208,3 +208,13 @@ def test_compactified_face_metric_fp64_noise_against_extended_precision():
     print("FP64 vs extended precision: face metric %.3e, volume metric %.3e" % (worst_face, worst_G))
     assert 1e-9 < worst_face < 1e-6
     assert worst_G < 1e-13
+
+
+def test_uniform_box_equals_octree_box():
+    # the array-generated uniform box has the octree box's cells and macro tables
+    a = meshgen.box_grid((2, 1, 1), 2, 3)
+    b = meshgen.uniform_box((2, 1, 1), 2, 3)
+    cells = lambda m: set(map(tuple, np.column_stack([m["elem_macro"], m["elem_level"], m["elem_anchor"], m["elem_p"]])))
+    assert cells(a) == cells(b)
+    for k in ("macro_kind", "macro_params", "macro_nbr", "macro_nbr_face", "macro_nbr_orient", "macro_bc"):
+        assert np.array_equal(a[k], b[k])
