@@ -536,11 +536,12 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       const Map m = own ? tk.me : tk.ot;
       const T* F = RB + t * rbS + (own ? 0 : 2 * NM * NM);
       const T* N = F + NM * NM;
-      const T* Ma = tab(L, 0 + 2 * m.halfA, ns, qm);
-      const T* Da = tab(L, 1 + 2 * m.halfA, ns, qm);
-      const int xg = l2 % qm, j = l2 / qm;
+      const T* Ma = L.tab + (own ? tk.meA : tk.otA);
+      const T* Da = L.tab + (own ? tk.meAd : tk.otAd);
+      const int j = qdiv(l2, tk.qinv), xg = l2 - j * qm;
       const int ra = m.flipA ? qm - 1 - xg : xg;
       T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll 4
       for (int i = 0; i < ns; ++i) {
         const T fv = F[j * ns + i], ma = Ma[ra * ns + i];
         s0 += ma * fv;
@@ -564,11 +565,12 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
         const int ns = own ? n : tk.no;
         const Map m = own ? tk.me : tk.ot;
         const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-        const T* Mb = tab(L, 0 + 2 * m.halfB, ns, qm);
-        const T* Db = tab(L, 1 + 2 * m.halfB, ns, qm);
-        const int xg = l2 % qm, yg = l2 / qm;
+        const T* Mb = L.tab + (own ? tk.meB : tk.otB);
+        const T* Db = L.tab + (own ? tk.meBd : tk.otBd);
+        const int yg = qdiv(l2, tk.qinv), xg = l2 - yg * qm;
         const int rb = m.flipB ? qm - 1 - yg : yg;
         T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+#pragma unroll 4
         for (int j = 0; j < ns; ++j) {
           const T mb = Mb[rb * ns + j];
           const T a0 = T1[j * qm + xg];
@@ -585,7 +587,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       const int npts = tk.gmode ? qq : 1;
       const T* mg = L.mgeo + tk.geo;
       const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      const int xg = li % qm, yg = li / qm;
+      const int yg = qdiv(li, tk.qinv), xg = li - yg * qm;
       const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
       const int rho = cc + qm * dd, pp = tk.gmode ? rho : 0;
       T wS;
@@ -633,11 +635,12 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     for_items(HPDG_COUNTS(C5), [&](int t, int li) {
       const Task& tk = tasks[t];
       const int qm = tk.qm;
-      const T* Ma = tab(L, 0 + 2 * tk.me.halfA, n, qm);
-      const T* Da = tab(L, 1 + 2 * tk.me.halfA, n, qm);
+      const T* Ma = L.tab + tk.meA;
+      const T* Da = L.tab + tk.meAd;
       const T* CF = RB + t * rbS;
       const int i = li % n, yg = li / n;
       T s1 = 0, s2 = 0, s3 = 0;
+#pragma unroll 4
       for (int xg = 0; xg < qm; ++xg) {
         const int ra = tk.me.flipA ? qm - 1 - xg : xg;
         const T ma = Ma[ra * n + i];
@@ -657,11 +660,12 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     for_items(HPDG_COUNTS(C6), [&](int t, int li) {
       const Task& tk = tasks[t];
       const int qm = tk.qm;
-      const T* Mb = tab(L, 0 + 2 * tk.me.halfB, n, qm);
-      const T* Db = tab(L, 1 + 2 * tk.me.halfB, n, qm);
+      const T* Mb = L.tab + tk.meB;
+      const T* Db = L.tab + tk.meBd;
       const T* S = RA + t * raS;
       const int i = li % n, j = li / n;
       T yf = 0, yn = 0;
+#pragma unroll 4
       for (int yg = 0; yg < qm; ++yg) {
         const int rb = tk.me.flipB ? qm - 1 - yg : yg;
         const T mb = Mb[rb * n + j];

@@ -34,7 +34,15 @@ struct Task {
   int valid, f, side, interior, other, qm, gmode, no, of;
   Map me, ot;
   long long ooff, geo;  // neighbour trace offset, mortar metric offset
+  // offsets (in the 1-D table) of the mortar interpolation matrices [qm][n_side]: value and
+  // derivative rows along the side's face axis a (its half for the h step) and along b, for
+  // the own side (me*) and the neighbour (ot*)
+  int meA, meAd, meB, meBd, otA, otAd, otB, otBd;
+  int qinv;  // ceil(65536 / qm): l / qm = (l * qinv) >> 16 exactly for 0 <= l < 1024
 };
+
+// l / q and l % q for the mortar's point count q through its 16.16 reciprocal (no integer division)
+__device__ inline int qdiv(int l, int qinv) { return (l * qinv) >> 16; }
 
 // volume index of the node with index k along axis d and (i, j) along the face axes t0 < t1
 // (arithmetic only: indexed private arrays would live in scratch memory)
@@ -81,6 +89,8 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
   tk.side = tk.interior = tk.other = tk.qm = tk.gmode = tk.no = tk.of = 0;
   tk.me = tk.ot = Map{0, 0, 0, 0, 0};
   tk.ooff = tk.geo = 0;
+  tk.meA = tk.meAd = tk.meB = tk.meBd = tk.otA = tk.otAd = tk.otB = tk.otBd = 0;
+  tk.qinv = 1;
   if (tk.valid) {
     const FaceTask F = L.ftask[Ig.fstart[f] + r];
     tk.side = F.side;
@@ -96,6 +106,21 @@ __device__ inline Task make_task(const LevelView<T>& L, long long e, int f, int 
     if (tk.other) {
       tk.no = F.no;
       tk.ooff = F.ooff;
+    }
+    auto toff = [&](int kind, int n, int q) { return L.tv.off[(kind * (kMaxN + 1) + n) * (kMaxQ + 1) + q]; };
+    const int qm = tk.qm, n = Ig.n;
+    if (qm > 0) {
+      tk.qinv = (65536 + qm - 1) / qm;
+      tk.meA = toff(2 * tk.me.halfA, n, qm);
+      tk.meAd = toff(1 + 2 * tk.me.halfA, n, qm);
+      tk.meB = toff(2 * tk.me.halfB, n, qm);
+      tk.meBd = toff(1 + 2 * tk.me.halfB, n, qm);
+      if (tk.other) {
+        tk.otA = toff(2 * tk.ot.halfA, tk.no, qm);
+        tk.otAd = toff(1 + 2 * tk.ot.halfA, tk.no, qm);
+        tk.otB = toff(2 * tk.ot.halfB, tk.no, qm);
+        tk.otBd = toff(1 + 2 * tk.ot.halfB, tk.no, qm);
+      }
     }
   }
   return tk;
