@@ -175,10 +175,10 @@ typedef struct {
   int32_t n_cheb_coarse; /* Chebyshev steps per smoothing call on the levels below the finest
                             (0: n_cheb) */
   int32_t unfused;       /* HPDG_SMOOTH_POINT, or HPDG_SMOOTH_BLOCK with FP64 / FP32 blocks,
-                            on a level of one degree (p <= 7): 0 runs each Chebyshev step that
-                            needs A x as one fused kernel per element (apply, r = b - A x,
-                            z = M^-1 r and the update; the same arithmetic); 1 keeps the apply
-                            and the scaling step apart */
+                            on a level of degrees p <= 7: 0 runs each Chebyshev step that needs
+                            A x as the mortar kernel and then one fused kernel per element
+                            (volume term and face sums, r = b - A x, z = M^-1 r and the update;
+                            the same arithmetic); 1 keeps the apply and the scaling step apart */
 } hpdg_smoother_params;
 
 typedef struct {
@@ -302,16 +302,19 @@ int hpdg_set_coefficient(hpdg_mesh* mesh, int kind, int where, const double* hos
 int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream);
 
 /* y = A_level x (Eq. lh2 applied matrix-free): volume stiffness by sum factorisation,
- * SIPG fluxes on every mortar with hp-mortar projections (Fig. mortar).  x, y: level
- * vectors of precision ``prec``; x != y. */
+ * SIPG fluxes on every mortar with hp-mortar projections (Fig. mortar).  Three stream-ordered
+ * launches: the face traces of x, the mortar kernel (both sides of each mortar, into per-face
+ * slots of the mesh), the element kernel (volume term plus the element's face slots).  x, y:
+ * level vectors of precision ``prec``; x != y. */
 int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream);
 
 /* y = A_level x as hpdg_apply, for callers that cannot allocate device memory (code under HIP
- * graph capture, tight serving loops, harnesses that forbid hipMalloc): the face traces go to a
- * fixed device array of the library (64 MiB per GPU, held until the process ends; its address
- * is taken when the context is created) instead of the mesh's trace buffer, and the call makes
- * no allocation of any kind.  Same kernels and result as hpdg_apply.  A level whose traces need
- * more than 64 MiB (12 (p+1)^2 scalars per element) returns HPDG_ERR_INVALID_ARG.  Every call
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the face traces and the
+ * face slots go to a fixed device array of the library (64 MiB per GPU, held until the process
+ * ends; its address is taken when the context is created) instead of the mesh's buffers, and
+ * the call makes no allocation of any kind.  Same kernels and result as hpdg_apply.  A level
+ * whose traces and slots need more than 64 MiB (12 (p+1)^2 trace scalars per element and
+ * 2 (p+1)^2 slot scalars per face-mortar pair) returns HPDG_ERR_INVALID_ARG.  Every call
  * on a GPU shares that GPU's array: calls that overlap on one GPU (other streams, other
  * threads, other contexts) race and must be serialised by the caller. */
 int hpdg_apply_noalloc(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_dev, void* stream);
@@ -424,7 +427,8 @@ int hpdg_server_destroy(hpdg_server* server);
  *   apply: 2 s N (x read, y written) + s (volume + mortar metric scalars) + record bytes;
  *   block step: s sum_e N_e (N_e + 1) / 2 (packed inverse blocks, N_e = n_e^3) + s N per
  *   vector read or written;
- *   fused step (the one fused kernel; the face-trace launch before it is not timed): the
+ *   fused step (the mortar kernel and the fused element kernels; the face-trace launch before
+ *   the first step is not timed): the
  *   apply's bytes without the y write, plus the packed blocks (point Jacobi: s N, the inverse
  *   diagonal) and s N per vector (b, p, x written, p read after the first step).
  * (s = 8 for HPDG_F64, 4 for HPDG_F32; N = level DOF.)  hpdg_kernel_timing() waits for

@@ -52,7 +52,6 @@ struct DevLevel {
   ElemInfo* einfo = nullptr;
   MortarInfo* minfo = nullptr;
   int* fmlist = nullptr;
-  FaceTask* ftask = nullptr;
   T* vgeo = nullptr;
   T* mgeo = nullptr;
   T* dinv = nullptr;
@@ -68,7 +67,9 @@ struct DevLevel {
   // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
   T* mcoef = nullptr;
   T* diag = nullptr;
+  MortarTask* mtask = nullptr;
   T* trace = nullptr;  // face traces (written before each apply)
+  T* slot = nullptr;   // lifted face terms (written by the mortar kernel before each element kernel)
   T* trace2 = nullptr;  // block smoothing: the next step's traces, written by the fused step
   double* nl_alpha = nullptr;  // alpha and w det J beta at the GL points (FP64 levels only)
   double* nl_wbeta = nullptr;
@@ -238,11 +239,13 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.einfo = d.einfo;
   v.minfo = d.minfo;
   v.fmlist = d.fmlist;
-  v.ftask = d.ftask;
+  v.mtask = d.mtask;
+  v.n_mtask = (long long)h.mtask.size();
   v.vgeo = d.vgeo;
   v.mgeo = d.mgeo;
   v.mcoef = mass_on ? d.mcoef : nullptr;
   v.trace = d.trace;
+  v.slot = d.slot;
   v.tab = table<T>();
   v.tv = tabview();
   v.n_elem = (long long)h.cells.size();
@@ -303,7 +306,7 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
   d.einfo = M->upload_raw(h.einfo, s);
   d.minfo = M->upload_raw(h.minfo, s);
   d.fmlist = M->upload_raw(h.fmlist, s);
-  d.ftask = M->upload_raw(h.ftask, s);
+  d.mtask = M->upload_raw(h.mtask, s);
   d.belems = M->upload_raw(h.bucket_elems, s);
   d.vgeo = M->upload<T>(h.vgeo, s);
   d.mgeo = M->upload<T>(h.mgeo, s);
@@ -321,6 +324,7 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
     d.diag = M->upload<T>(h.diag, s);
   }
   d.trace = M->alloc<T>(size_t(h.ntrace));
+  d.slot = M->alloc<T>(size_t(h.nslot));
   const size_t n = size_t(h.ndof);
   d.f = M->alloc<T>(n);
   d.v = M->alloc<T>(n);
@@ -375,7 +379,7 @@ void collect_timing(hpdg_mesh* M) {
 double apply_bytes(const hpdg_mesh* M, int l, size_t scalar) {
   const LevelHost& h = M->H[l];
   return double(scalar) * (2.0 * double(h.ndof) + double(h.vgeo.size()) + double(h.mgeo.size())) +
-         double(h.einfo.size() * sizeof(ElemInfo) + h.ftask.size() * sizeof(FaceTask));
+         double(h.einfo.size() * sizeof(ElemInfo) + h.mtask.size() * sizeof(MortarTask));
 }
 
 template <typename T>
@@ -386,23 +390,26 @@ void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   timed(M, HPDG_TIMING_APPLY, l, prec, M->timing ? apply_bytes(M, l, sizeof(T)) : 0.0, s, [&] {
     launch_traces<T>(V, x, s);
+    launch_faces<T>(V, s);
     for (size_t b = 0; b < h.bucket_n.size(); ++b)
-      launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
+      launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], be + h.bucket_start[b],
                              h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
   });
 }
 
-// the apply of level l with the face traces in the caller-free scratch ``trace`` (no timing,
-// no allocation)
+// the apply of level l with the face traces and the face slots in the caller-free scratch
+// ``trace`` and ``slot`` (no timing, no allocation)
 template <typename T>
-void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, hipStream_t s) {
+void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, T* slot, hipStream_t s) {
   const LevelHost& h = M->H[l];
   LevelView<T> V = M->view<T>(l);
   V.trace = trace;
+  V.slot = slot;
   const int* be = M->lev<T>(l).belems;
   launch_traces<T>(V, x, s);
+  launch_faces<T>(V, s);
   for (size_t b = 0; b < h.bucket_n.size(); ++b)
-    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], h.uniform, be + h.bucket_start[b],
+    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], be + h.bucket_start[b],
                            h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
 }
 
@@ -421,7 +428,7 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   const LevelHost& h = M->H[l];
   bool fuse = ((block && !bf16) || dinv) && !M->sp.unfused && !h.bucket_n.empty();
   for (size_t bk = 0; fuse && bk < h.bucket_n.size(); ++bk)
-    fuse = apply_block_fusable(h.nmax, h.qmax, h.qmmax, h.bucket_n[bk], h.bucket_q[bk], h.uniform);
+    fuse = apply_block_fusable(h.bucket_n[bk], h.bucket_q[bk]);
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   // fused steps write the traces of their result for the next fused step, alternating between
   // the level's two trace buffers (a step reads one while its neighbours' new traces go to the
@@ -451,9 +458,9 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
       T* next = k < n_iter ? (cur == d.trace ? d.trace2 : d.trace) : nullptr;
       const BlockStep<T> bs{dinv, d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0};
       timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
+        launch_faces<T>(V, s);
         for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
-          launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], h.uniform,
-                                     M->lev<T>(l).belems + h.bucket_start[bk],
+          launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], M->lev<T>(l).belems + h.bucket_start[bk],
                                      h.bucket_start[bk + 1] - h.bucket_start[bk], x, bs, s);
       });
       cur = next;
@@ -996,10 +1003,10 @@ size_t estimate_device_bytes(const hpdg_mesh* M, int scaling) {
     b += h.einfo.size() * sizeof(ElemInfo) * (M->has_f32 ? 2 : 1);
     b += h.minfo.size() * sizeof(MortarInfo) * (M->has_f32 ? 2 : 1);
     b += (h.fmlist.size() + h.bucket_elems.size()) * 4 * (M->has_f32 ? 2 : 1);
-    b += h.ftask.size() * sizeof(FaceTask) * (M->has_f32 ? 2 : 1);
+    b += h.mtask.size() * sizeof(MortarTask) * (M->has_f32 ? 2 : 1);
     b += (h.vgeo.size() + h.mgeo.size()) * prec;
     b += size_t(h.ndof) * prec * 5;  // dinv, f, v, t, p
-    b += size_t(h.ntrace) * prec;      // face traces
+    b += size_t(h.ntrace + h.nslot) * prec;  // face traces and slots
     b += size_t(h.nmq) * prec + (h.nmq ? size_t(h.ndof) * prec : 0);
     b += (h.tinfo.size() * sizeof(TransferInfo) + (h.cstart.size() + h.clist.size()) * 4) * (M->has_f32 ? 2 : 1);
     if (scaling != HPDG_SMOOTH_NONE && l + 1 < M->nlevels())
@@ -1746,18 +1753,22 @@ int hpdg_apply_noalloc(hpdg_mesh* mesh, int level, int prec, const void* x_dev, 
   return guarded(mesh->ctx, [&] {
     void* scr = noalloc_scratch(mesh->ctx->device);
     if (!scr) throw Error(HPDG_ERR_HIP, "the no-allocation scratch is not set up on this device");
-    const size_t need = size_t(mesh->H[level].ntrace) * (prec == HPDG_F32 ? sizeof(float) : sizeof(double));
+    const LevelHost& h = mesh->H[level];
+    const size_t need = size_t(h.ntrace + h.nslot) * (prec == HPDG_F32 ? sizeof(float) : sizeof(double));
     if (need > noalloc_scratch_bytes())
       throw Error(HPDG_ERR_INVALID_ARG, "level " + std::to_string(level) + " needs " + std::to_string(need) +
-                                            " bytes of face traces; the no-allocation apply holds at most " +
-                                            std::to_string(noalloc_scratch_bytes()) + " bytes");
+                                            " bytes of face traces and face slots; the no-allocation apply holds "
+                                            "at most " + std::to_string(noalloc_scratch_bytes()) + " bytes");
     hipStream_t s = S(stream);
-    if (prec == HPDG_F32)
-      apply_level_scratch<float>(mesh, level, static_cast<const float*>(x_dev), static_cast<float*>(y_dev),
-                                 static_cast<float*>(scr), s);
-    else
-      apply_level_scratch<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev),
-                                  static_cast<double*>(scr), s);
+    if (prec == HPDG_F32) {
+      float* tr = static_cast<float*>(scr);
+      apply_level_scratch<float>(mesh, level, static_cast<const float*>(x_dev), static_cast<float*>(y_dev), tr,
+                                 tr + h.ntrace, s);
+    } else {
+      double* tr = static_cast<double*>(scr);
+      apply_level_scratch<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), tr,
+                                  tr + h.ntrace, s);
+    }
     HIPCHK(hipGetLastError());
   });
 }

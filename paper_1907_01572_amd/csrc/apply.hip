@@ -1,18 +1,23 @@
-// gfx950 operator kernel of the hpdg library: y = A x on one multigrid level.
+// gfx950 operator kernels of the hpdg library: y = A x on one multigrid level, in three launches.
 //
-// One workgroup per element computes y_e = (A x)_e completely, so every output is written
-// once, without atomics, and the result is bitwise reproducible:
-//   * volume: the stiffness term by sum factorisation through the GL points
-//     (Eq. harald-stiff): three 1-D passes to the GL points, the reference gradient by the
-//     GL collocation derivative, the metric contraction G (Eq. stiffness-3, with w J and k
-//     folded in), and the transposed passes back to the LGL test functions;
-//   * faces: the SIPG terms of Eq. lh2 on every mortar of the element (Eq. temp-E), both
-//     sides' traces interpolated onto the mortar's GL points through the hp projections of
-//     Fig. mortar (1-D matrices for the sub-face halves and the degree change), the flux
-//     formed for the own side only and lifted back through the transposed interpolation.
-//     The six faces are processed together, one mortar per face per round (a face of a
-//     coarse element facing four finer elements takes four rounds).
-// Each mortar is therefore evaluated once from each side.
+//   1. trace_kernel: every element's face traces (the values at the n^2 LGL nodes of each face
+//      and the reference normal derivative there).
+//   2. mortar_kernel, one wavefront per mortar: the SIPG terms of Eq. lh2 on that mortar
+//      (Eq. temp-E) for both of its sides at once.  Both sides' traces are interpolated onto the
+//      mortar's GL points through the hp projections of Fig. mortar (1-D matrices for the
+//      sub-face halves and the degree change), the flux is formed once per point (the value
+//      flux of the two sides differs only in sign), and each side's part is lifted back through
+//      its transposed interpolation onto its own face: n^2 values that multiply the test
+//      functions' face values and n^2 that multiply their reference normal derivative, written
+//      to that side's slot (one slot per entry of the element's face-mortar list).
+//   3. apply_kernel, one workgroup per element: the stiffness term by sum factorisation through
+//      the GL points (Eq. harald-stiff): three 1-D passes to the GL points, the reference
+//      gradient by the GL collocation derivative, the metric contraction G (Eq. stiffness-3,
+//      with w J and k folded in), the transposed passes back to the LGL test functions; then
+//      the element's face slots are summed per face (list order) and added, and y_e is
+//      stored once.
+// Every output is written by exactly one workgroup, without atomics, in a fixed order of
+// additions: the result is bitwise reproducible.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -27,42 +32,45 @@ namespace hpdg {
 
 namespace {
 
-// threads per workgroup (one element per workgroup)
+// threads per workgroup of the element kernel (one element per workgroup)
 #ifndef HPDG_APPLY_THREADS
 #define HPDG_APPLY_THREADS 256
 #endif
 constexpr int kThreads = HPDG_APPLY_THREADS;
+constexpr int kWaves = kThreads >= 64 ? kThreads / 64 : 1;  // whole waves (checked by the launchers)
+
+// LDS of the element kernel, in scalars, for at most NM LGL nodes and QM GL points per axis.
 // compact: kernels of a fixed degree with at most two volume nodes per thread; the element's
-// coefficients sit at the start of the shared region (dead once the volume phase has read
-// them: the face phases take both sides' traces from the trace buffer) and each thread keeps
-// its volume results in registers, so the workgroup needs less LDS
+// coefficients sit at the start of the shared region (dead once the volume phase has read them)
+// and each thread keeps its volume results in registers.  After the volume phase the region
+// holds the per-face sums of the face slots (12 NM^2) at ``ysum``; with the fused smoother
+// step, r and one partial z per wave go first.
 struct Layout {
-  int NM, QM, QMM;
+  int NM, QM;
   bool compact;
-  size_t fixed, vol, ra, rb, y, tasks;
-  __host__ __device__ Layout(int nm, int qm, int qmm, bool cmp = false) : NM(nm), QM(qm), QMM(qmm), compact(cmp) {
+  size_t fixed, vol, ysum, region;
+  __host__ __device__ Layout(int nm, int qm, bool cmp, bool fuse) : NM(nm), QM(qm), compact(cmp) {
     const size_t n3 = size_t(NM) * NM * NM;
     fixed = (compact ? 0 : 2 * n3) + size_t(QM) * NM + size_t(QM) * QM + QM + 2 * NM;
     const size_t tsz = size_t(NM) * QM * (NM > QM ? NM : QM);
     vol = (compact ? n3 : 0) + 4 * size_t(QM) * QM * QM + 2 * tsz;
-    if (compact) {  // fused face phases: RA holds T1, then S; RB the traces, then the fluxes
-      ra = kFaces * mx3(6 * size_t(NM) * QMM, 3 * size_t(QMM) * NM, 0);
-      rb = kFaces * mx3(4 * size_t(NM) * NM, 4 * size_t(QMM) * QMM, 0);
-    } else {  // large enough for both face paths
-      ra = kFaces * mx3(size_t(NM) * NM * NM, 6 * size_t(NM) * QMM, 4 * size_t(QMM) * QMM);
-      rb = kFaces * mx3(4 * size_t(NM) * NM, 8 * size_t(QMM) * QMM, 3 * size_t(QMM) * NM);
-    }
-    y = 2 * kFaces * size_t(NM) * NM;
-    tasks = (kFaces * sizeof(Task) + 15) / 16 * 16;
+    ysum = fuse ? (1 + kWaves) * n3 : 0;
+    const size_t faces = ysum + 12 * size_t(NM) * NM;
+    region = vol > faces ? vol : faces;
   }
-  __host__ __device__ static size_t mx3(size_t a, size_t b, size_t c) {
-    return a > b ? (a > c ? a : c) : (b > c ? b : c);
-  }
-  // the face phases also stage the six 1-D mortar matrices of a uniform level
-  __host__ __device__ size_t faces() const { return ra + rb + y + 6 * size_t(QMM) * NM; }
-  __host__ __device__ size_t region() const { return vol > faces() ? vol : faces(); }
-  __host__ __device__ size_t bytes(size_t scalar) const { return tasks + scalar * (fixed + region()); }
+  __host__ __device__ size_t bytes(size_t scalar) const { return scalar * (fixed + region); }
 };
+
+// LDS of the mortar kernel, in scalars: both sides' traces (4 NM^2), later the flux
+// coefficients (4 arrays of QMM^2 per side); the first interpolation pass of both sides
+// (3 arrays of NM QMM per side), later the first transposed pass (as many)
+__host__ __device__ inline size_t mortar_r1(int NM, int QMM) {
+  const size_t a = 4 * size_t(NM) * NM, b = 8 * size_t(QMM) * QMM;
+  return a > b ? a : b;
+}
+__host__ __device__ inline size_t mortar_lds_scalars(int NM, int QMM) {
+  return mortar_r1(NM, QMM) + 6 * size_t(NM) * QMM;
+}
 
 // The Jacobi-scaled Chebyshev step behind a fused apply: region[0 .. n^3) holds r = b - A x of
 // element e (the face buffers are free by then). z = M^-1 r (the packed block over the
@@ -73,7 +81,6 @@ template <typename T, int NC>
 __device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* region, const T* dfo, int NM,
                                 const BlockStep<T>& bs) {
   const int N = NC ? NC : n_rt, N2 = N * N, N3 = N2 * N;
-  constexpr int kWaves = kThreads >= 64 ? kThreads / 64 : 1;  // the launcher requires whole waves
   const T* rs = region;
   const int lane = int(threadIdx.x & 63);
   const int wv = __builtin_amdgcn_readfirstlane(int(threadIdx.x >> 6));
@@ -119,230 +126,215 @@ __device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* reg
   }
 }
 
-// Face terms of a level whose elements all have N nodes and whose mortars all have Q GL
-// points per axis (uniform degree): every size is a compile-time constant, the six 1-D
-// matrices (values / derivatives at the full, lower-half and upper-half point sets) are
-// staged in LDS once, and each phase maps threads to (task, item) with constant strides.
-// Adds the face terms to sy and writes y (FUSE: runs the Jacobi-scaled Chebyshev step bs on
-// the result instead, in the same workgroup).
-template <typename T, int N, int Q, bool COMPACT, bool FUSE>
-__device__ void faces_uniform(const LevelView<T>& L, const ElemInfo& I, long long e, T* __restrict__ y,
-                              const T* sy, const T (&syr)[2], const T* dfo, T* region, Task* tasks,
-                              const Layout& lay, const BlockStep<T>& bs) {
-  constexpr int N2 = N * N, N3 = N2 * N, QQ = Q * Q, NQ = N * Q;
-  const int NM = lay.NM, QMM = lay.QMM;
-  const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
-  T* mats = region;  // [kind 0..5][Q][N]
-  // RB: traces (4 NM^2), then the flux coefficients (4 QMM^2); RA: first-pass values of both
-  // sides (6 NM QMM), then the first transposed pass (3 QMM NM)
-  T* RA = mats + 6 * QMM * NM;
-  T* RB = RA + lay.ra;
-  T* Yf = RB + lay.rb;
-  T* Yn = Yf + kFaces * NM * NM;
-  for (int i = threadIdx.x; i < 6 * NQ; i += blockDim.x) mats[i] = tab(L, i / NQ, N, Q)[i % NQ];
-  for (int i = threadIdx.x; i < 2 * kFaces * NM * NM; i += blockDim.x) Yf[i] = 0;
-  int rounds = 0;
-#pragma unroll
-  for (int f = 0; f < kFaces; ++f) rounds = I.fcnt[f] > rounds ? I.fcnt[f] : rounds;
-  for (int r = 0; r < rounds; ++r) {
-    for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
-    __syncthreads();
-    // P1: traces (values, reference normal derivative) of both sides from the trace buffer
-    for (int g = threadIdx.x; g < kFaces * 2 * N2; g += blockDim.x) {
-      const int t = g / (2 * N2), li = g % (2 * N2);
-      const Task& tk = tasks[t];
-      if (!tk.valid) continue;
-      const bool own = li < N2;
-      if (!own && !tk.other) continue;
-      const int l2 = own ? li : li - N2;
-      const long long off = own ? I.toff + 2LL * tk.f * N2 : tk.ooff;
-      T* tr = RB + t * rbS + (own ? 0 : 2 * NM * NM);
-      tr[l2] = L.trace[off + l2];
-      tr[NM * NM + l2] = L.trace[off + N2 + l2];
-    }
-    __syncthreads();
-    // P2: first interpolation pass (along face axis a): u, du/da, du/dn
-    for (int g = threadIdx.x; g < kFaces * 2 * NQ; g += blockDim.x) {
-      const int t = g / (2 * NQ), li = g % (2 * NQ);
-      const Task& tk = tasks[t];
-      if (!tk.valid) continue;
-      const bool own = li < NQ;
-      if (!own && !tk.other) continue;
-      const int l2 = own ? li : li - NQ;
-      const Map m = own ? tk.me : tk.ot;
-      const T* F = RB + t * rbS + (own ? 0 : 2 * NM * NM);
-      const T* Nd = F + NM * NM;
-      const T* Ma = mats + (2 * m.halfA) * NQ;
-      const T* Da = Ma + NQ;
-      const int xg = l2 % Q, j = l2 / Q;
-      const int ra = m.flipA ? Q - 1 - xg : xg;
-      T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const T fv = F[j * N + i], ma = Ma[ra * N + i];
-        s0 += ma * fv;
-        s1 += Da[ra * N + i] * fv;
-        s2 += ma * Nd[j * N + i];
-      }
-      T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-      T1[j * Q + xg] = s0;
-      T1[NM * QMM + j * Q + xg] = s1;
-      T1[2 * NM * QMM + j * Q + xg] = s2;
-    }
-    __syncthreads();
-    // P3+P4: second pass (along face axis b) of both sides at one mortar point: u, du/da,
-    // du/db, du/dn; then the SIPG flux there (own side, own frame) into RB
-    for (int g = threadIdx.x; g < kFaces * QQ; g += blockDim.x) {
-      const int t = g / QQ, li = g % QQ;
-      const Task& tk = tasks[t];
-      if (!tk.valid) continue;
-      // side values at the point with index l2 of that side's frame
-      auto at_point = [&](bool own, int l2, T& v0, T& v1, T& v2, T& v3) {
-        const Map m = own ? tk.me : tk.ot;
-        const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-        const T* Mb = mats + (2 * m.halfB) * NQ;
-        const T* Db = Mb + NQ;
-        const int xg = l2 % Q, yg = l2 / Q;
-        const int rb = m.flipB ? Q - 1 - yg : yg;
-        T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) {
-          const T mb = Mb[rb * N + j];
-          const T a0 = T1[j * Q + xg];
-          g0 += mb * a0;
-          g1 += mb * T1[NM * QMM + j * Q + xg];
-          g2 += Db[rb * N + j] * a0;
-          g3 += mb * T1[2 * NM * QMM + j * Q + xg];
-        }
-        v0 = g0;
-        v1 = g1;
-        v2 = g2;
-        v3 = g3;
-      };
-      const int side = tk.side;
-      const int npts = tk.gmode ? QQ : 1;
-      const T* mg = L.mgeo + tk.geo;
-      const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      const int xg = li % Q, yg = li / Q;
-      const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
-      const int pp = tk.gmode ? cc + Q * dd : 0;
-      T wS;
-      if (tk.gmode) {
-        wS = mg[6 * npts + pp];
-      } else {
-        const T* wm = L.tab + L.tv.w_off[Q];
-        wS = wm[cc] * wm[dd] * mg[6];
-      }
-      const T sig = mg[7 * npts + pp];
-      const T ma = mg[(3 * side + t0) * npts + pp];
-      const T mb = mg[(3 * side + t1) * npts + pp];
-      const T mn = mg[(3 * side + d) * npts + pp];
-      T u_me, ga, gb, gn;
-      at_point(true, li, u_me, ga, gb, gn);
-      const T g_me = ma * ga + mb * gb + mn * gn;
-      T Af, Bc;
-      if (tk.interior) {
-        T u_o = 0, g_o = 0;
-        if (tk.other) {
-          const int os = 1 - side, od = tk.of >> 1;
-          const int ot0 = od == 0 ? 1 : 0, ot1 = od == 2 ? 1 : 2;
-          const int oi = tk.ot.swap ? dd + Q * cc : cc + Q * dd;
-          T oa, ob, on;
-          at_point(false, oi, u_o, oa, ob, on);
-          g_o = mg[(3 * os + ot0) * npts + pp] * oa + mg[(3 * os + ot1) * npts + pp] * ob +
-                mg[(3 * os + od) * npts + pp] * on;
-        }
-        const T jmp = u_me - u_o;
-        Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
-        Bc = T(-0.5) * wS * jmp;
-      } else {
-        Af = wS * (sig * u_me - g_me);
-        Bc = -wS * u_me;
-      }
-      T* CF = RB + t * rbS;
-      CF[li] = Af;
-      CF[QMM * QMM + li] = Bc * ma;
-      CF[2 * QMM * QMM + li] = Bc * mb;
-      CF[3 * QMM * QMM + li] = Bc * mn;
-    }
-    __syncthreads();
-    // P5: first transposed pass (along the own face axis a)
-    for (int g = threadIdx.x; g < kFaces * NQ; g += blockDim.x) {
-      const int t = g / NQ, li = g % NQ;
-      const Task& tk = tasks[t];
-      if (!tk.valid) continue;
-      const T* Ma = mats + (2 * tk.me.halfA) * NQ;
-      const T* Da = Ma + NQ;
-      const T* CF = RB + t * rbS;
-      const int i = li % N, yg = li / N;
-      T s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll
-      for (int xg = 0; xg < Q; ++xg) {
-        const int ra = tk.me.flipA ? Q - 1 - xg : xg;
-        const T ma = Ma[ra * N + i];
-        const int gi = yg * Q + xg;
-        s1 += ma * CF[gi] + Da[ra * N + i] * CF[QMM * QMM + gi];
-        s2 += ma * CF[2 * QMM * QMM + gi];
-        s3 += ma * CF[3 * QMM * QMM + gi];
-      }
-      T* S = RA + t * raS;
-      S[li] = s1;
-      S[QMM * NM + li] = s2;
-      S[2 * QMM * NM + li] = s3;
-    }
-    __syncthreads();
-    // P6: second transposed pass (along b) into the per-face sums
-    for (int g = threadIdx.x; g < kFaces * N2; g += blockDim.x) {
-      const int t = g / N2, li = g % N2;
-      const Task& tk = tasks[t];
-      if (!tk.valid) continue;
-      const T* Mb = mats + (2 * tk.me.halfB) * NQ;
-      const T* Db = Mb + NQ;
-      const T* S = RA + t * raS;
-      const int i = li % N, j = li / N;
-      T yf = 0, yn = 0;
-#pragma unroll
-      for (int yg = 0; yg < Q; ++yg) {
-        const int rb = tk.me.flipB ? Q - 1 - yg : yg;
-        const T mb = Mb[rb * N + j];
-        yf += mb * S[yg * N + i] + Db[rb * N + j] * S[QMM * NM + yg * N + i];
-        yn += mb * S[2 * QMM * NM + yg * N + i];
-      }
-      Yf[tk.f * NM * NM + li] += yf;
-      Yn[tk.f * NM * NM + li] += yn;
-    }
-    __syncthreads();
-  }
-  // face sums -> element
-  auto finish = [&](int idx, T acc) {
-    const int c0 = idx % N, c1 = (idx / N) % N, c2 = idx / N2;
-#pragma unroll
-    for (int f = 0; f < kFaces; ++f) {
-      if (I.fcnt[f] == 0) continue;
-      const int d = f >> 1;
-      const int kd = d == 0 ? c0 : (d == 1 ? c1 : c2);
-      const int li = d == 0 ? c2 * N + c1 : (d == 1 ? c2 * N + c0 : c1 * N + c0);
-      acc += dfo[(f & 1) * NM + kd] * Yn[f * NM * NM + li];
-      if (kd == ((f & 1) ? N - 1 : 0)) acc += Yf[f * NM * NM + li];
-    }
-    if constexpr (FUSE)
-      region[idx] = bs.b[I.off + idx] - acc;  // r = b - A x (the face buffers before Yf are free now)
-    else
-      y[I.off + idx] = acc;
+// One wavefront per mortar.  Items of a phase are spread over the 64 lanes; every quantity
+// of the mortar (degrees, rule, maps, matrix offsets) is the same in all lanes.
+template <typename T>
+__global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long count) {
+  extern __shared__ unsigned char smem_raw[];
+  if ((long long)blockIdx.x >= count) return;
+  const long long mi = xcd_remap(blockIdx.x, gridDim.x);  // gridDim.x == count
+  const MortarTask M = L.mtask[mi];
+  const int NM = L.nmax, QMM = L.qmmax;
+  const int lane = threadIdx.x;
+  const int qm = M.q, qq = qm * qm;
+  const int qinv = (65536 + qm - 1) / qm;
+  const bool two = M.interior != 0;
+  const bool other = two && !L.self_only;  // each side's flux sees the other side's trace
+  const int n0 = M.n[0], n1 = two ? M.n[1] : 0;
+  auto unpack = [](unsigned m) {
+    return Map{int(m & 1), int((m >> 1) & 1), int((m >> 2) & 1), int((m >> 3) & 3), int((m >> 5) & 3)};
   };
-  if constexpr (COMPACT) {  // node threadIdx.x + it kThreads of this thread
-#pragma unroll
-    for (int it = 0; it < 2; ++it)
-      if (int(threadIdx.x) + it * kThreads < N3) finish(int(threadIdx.x) + it * kThreads, syr[it]);
-  } else {
-    for (int idx = threadIdx.x; idx < N3; idx += blockDim.x) finish(idx, sy[idx]);
+  const Map m0 = unpack(M.map[0]), m1 = unpack(M.map[1]);
+  auto toff = [&](int kind, int n) { return L.tv.off[(kind * (kMaxN + 1) + n) * (kMaxQ + 1) + qm]; };
+  // value and derivative rows [qm][n_s] along each side's face axes a and b (their halves)
+  const T* A0 = L.tab + toff(2 * m0.halfA, n0);
+  const T* A0d = L.tab + toff(1 + 2 * m0.halfA, n0);
+  const T* B0 = L.tab + toff(2 * m0.halfB, n0);
+  const T* B0d = L.tab + toff(1 + 2 * m0.halfB, n0);
+  const T* A1 = two ? L.tab + toff(2 * m1.halfA, n1) : A0;
+  const T* A1d = two ? L.tab + toff(1 + 2 * m1.halfA, n1) : A0d;
+  const T* B1 = two ? L.tab + toff(2 * m1.halfB, n1) : B0;
+  const T* B1d = two ? L.tab + toff(1 + 2 * m1.halfB, n1) : B0d;
+
+  T* smem = reinterpret_cast<T*>(smem_raw);
+  T* F = smem;                               // side s: values at F + 2 s NM^2, normal derivatives + NM^2
+  T* CF = smem;                              // side s: 4 arrays of QMM^2 at CF + 4 s QMM^2
+  T* T1 = smem + mortar_r1(NM, QMM);         // side s: 3 arrays of NM QMM at T1 + 3 s NM QMM
+  T* S = T1;                                 // side s: 3 arrays of QMM NM (after T1 is read)
+  const int NN = NM * NM, Q2 = QMM * QMM, NQ = NM * QMM;
+
+  // P1: traces of both sides (2 n_s^2 contiguous scalars each)
+  {
+    const int c0 = 2 * n0 * n0, c1 = 2 * n1 * n1;
+    for (int g = lane; g < c0 + c1; g += 64) {
+      const bool s1 = g >= c0;
+      const int l = s1 ? g - c0 : g, nsq = s1 ? n1 * n1 : n0 * n0;
+      const int part = l >= nsq ? 1 : 0;
+      F[(s1 ? 2 * NN : 0) + part * NN + (l - part * nsq)] = L.trace[(s1 ? M.tr[1] : M.tr[0]) + l];
+    }
   }
-  if constexpr (FUSE) fused_step_tail<T, N>(N, I, e, region, dfo, NM, bs);
+  __syncthreads();
+  // P2: first interpolation pass (along the side's face axis a) of u, du/da and du/dn
+  {
+    const int c0 = qm * n0, c1 = qm * n1;
+    for (int g = lane; g < c0 + c1; g += 64) {
+      const bool s1 = g >= c0;
+      const int l2 = s1 ? g - c0 : g, ns = s1 ? n1 : n0;
+      const Map mp = s1 ? m1 : m0;
+      const T* Fs = F + (s1 ? 2 * NN : 0);
+      const T* Ns = Fs + NN;
+      const T* Ma = s1 ? A1 : A0;
+      const T* Da = s1 ? A1d : A0d;
+      const int j = qdiv(l2, qinv), xg = l2 - j * qm;
+      const int ra = mp.flipA ? qm - 1 - xg : xg;
+      T s0 = 0, sd = 0, sn = 0;
+#pragma unroll 4
+      for (int i = 0; i < ns; ++i) {
+        const T fv = Fs[j * ns + i], ma = Ma[ra * ns + i];
+        s0 += ma * fv;
+        sd += Da[ra * ns + i] * fv;
+        sn += ma * Ns[j * ns + i];
+      }
+      T* Ts = T1 + (s1 ? 3 * NQ : 0);
+      Ts[j * qm + xg] = s0;
+      Ts[NQ + j * qm + xg] = sd;
+      Ts[2 * NQ + j * qm + xg] = sn;
+    }
+  }
+  __syncthreads();
+  // P3+P4: at each mortar point (cc, dd): both sides' u, du/da, du/db, du/dn (second pass
+  // along b), the SIPG flux, and each side's coefficients in that side's frame into CF
+  {
+    const int npts = M.gmode ? qq : 1;
+    const T* mg = L.mgeo + M.geo;
+    const T* wm = L.tab + L.tv.w_off[qm];
+    for (int g = lane; g < qq; g += 64) {
+      const int dd = qdiv(g, qinv), cc = g - dd * qm;
+      const int pp = M.gmode ? g : 0;
+      const T wS = M.gmode ? mg[6 * npts + pp] : wm[cc] * wm[dd] * mg[6];
+      const T sig = mg[7 * npts + pp];
+      // side s at this point: index in its frame, its four values, its metric vector
+      auto side_values = [&](int s, int& li, T& u, T& gr, T& ma, T& mb, T& mn) {
+        const Map mp = s ? m1 : m0;
+        const int ns = s ? n1 : n0;
+        const int xg = mp.swap ? dd : cc, yg = mp.swap ? cc : dd;
+        li = xg + qm * yg;
+        const T* Ts = T1 + (s ? 3 * NQ : 0);
+        const T* Mb = s ? B1 : B0;
+        const T* Db = s ? B1d : B0d;
+        const int rb = mp.flipB ? qm - 1 - yg : yg;
+        T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
+#pragma unroll 4
+        for (int j = 0; j < ns; ++j) {
+          const T mbv = Mb[rb * ns + j];
+          const T a0 = Ts[j * qm + xg];
+          g0 += mbv * a0;
+          g1 += mbv * Ts[NQ + j * qm + xg];
+          g2 += Db[rb * ns + j] * a0;
+          g3 += mbv * Ts[2 * NQ + j * qm + xg];
+        }
+        const int f = s ? M.f[1] : M.f[0], d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        ma = mg[(3 * s + t0) * npts + pp];
+        mb = mg[(3 * s + t1) * npts + pp];
+        mn = mg[(3 * s + d) * npts + pp];
+        u = g0;
+        gr = ma * g1 + mb * g2 + mn * g3;
+      };
+      int l0, l1 = 0;
+      T u0, gr0, ma0, mb0, mn0, u1 = 0, gr1 = 0, ma1 = 0, mb1 = 0, mn1 = 0;
+      side_values(0, l0, u0, gr0, ma0, mb0, mn0);
+      if (two) side_values(1, l1, u1, gr1, ma1, mb1, mn1);
+      T Af0, Bc0, Af1 = 0, Bc1 = 0;
+      if (!two) {  // boundary: the Dirichlet form with zero data
+        Af0 = wS * (sig * u0 - gr0);
+        Bc0 = -wS * u0;
+      } else if (other) {
+        const T jmp = u0 - u1;
+        Af0 = wS * (sig * jmp - T(0.5) * (gr0 - gr1));
+        Bc0 = T(-0.5) * wS * jmp;
+        Af1 = -Af0;
+        Bc1 = -Bc0;
+      } else {  // element-diagonal blocks: the other side's trace taken as zero
+        Af0 = wS * (sig * u0 - T(0.5) * gr0);
+        Bc0 = T(-0.5) * wS * u0;
+        Af1 = wS * (sig * u1 - T(0.5) * gr1);
+        Bc1 = T(-0.5) * wS * u1;
+      }
+      CF[l0] = Af0;
+      CF[Q2 + l0] = Bc0 * ma0;
+      CF[2 * Q2 + l0] = Bc0 * mb0;
+      CF[3 * Q2 + l0] = Bc0 * mn0;
+      if (two) {
+        T* C1 = CF + 4 * Q2;
+        C1[l1] = Af1;
+        C1[Q2 + l1] = Bc1 * ma1;
+        C1[2 * Q2 + l1] = Bc1 * mb1;
+        C1[3 * Q2 + l1] = Bc1 * mn1;
+      }
+    }
+  }
+  __syncthreads();
+  // P5: first transposed pass (along the side's face axis a)
+  {
+    const int c0 = n0 * qm, c1 = n1 * qm;
+    const int ninv0 = (65536 + n0 - 1) / n0, ninv1 = two ? (65536 + n1 - 1) / n1 : 1;
+    for (int g = lane; g < c0 + c1; g += 64) {
+      const bool s1 = g >= c0;
+      const int li = s1 ? g - c0 : g, ns = s1 ? n1 : n0;
+      const Map mp = s1 ? m1 : m0;
+      const T* Ma = s1 ? A1 : A0;
+      const T* Da = s1 ? A1d : A0d;
+      const T* C = CF + (s1 ? 4 * Q2 : 0);
+      const int yg = qdiv(li, s1 ? ninv1 : ninv0), i = li - yg * ns;
+      T s1v = 0, s2v = 0, s3v = 0;
+#pragma unroll 4
+      for (int xg = 0; xg < qm; ++xg) {
+        const int ra = mp.flipA ? qm - 1 - xg : xg;
+        const T ma = Ma[ra * ns + i];
+        const int p = yg * qm + xg;
+        s1v += ma * C[p] + Da[ra * ns + i] * C[Q2 + p];
+        s2v += ma * C[2 * Q2 + p];
+        s3v += ma * C[3 * Q2 + p];
+      }
+      T* Ss = S + (s1 ? 3 * NQ : 0);
+      Ss[li] = s1v;  // [yg][i]
+      Ss[NQ + li] = s2v;
+      Ss[2 * NQ + li] = s3v;
+    }
+  }
+  __syncthreads();
+  // P6: second transposed pass (along b) into each side's slot
+  {
+    const int c0 = n0 * n0, c1 = n1 * n1;
+    const int ninv0 = (65536 + n0 - 1) / n0, ninv1 = two ? (65536 + n1 - 1) / n1 : 1;
+    for (int g = lane; g < c0 + c1; g += 64) {
+      const bool s1 = g >= c0;
+      const int li = s1 ? g - c0 : g, ns = s1 ? n1 : n0;
+      const Map mp = s1 ? m1 : m0;
+      const T* Mb = s1 ? B1 : B0;
+      const T* Db = s1 ? B1d : B0d;
+      const T* Ss = S + (s1 ? 3 * NQ : 0);
+      const int j = qdiv(li, s1 ? ninv1 : ninv0), i = li - j * ns;
+      T yf = 0, yn = 0;
+#pragma unroll 4
+      for (int yg = 0; yg < qm; ++yg) {
+        const int rb = mp.flipB ? qm - 1 - yg : yg;
+        const T mbv = Mb[rb * ns + j];
+        yf += mbv * Ss[yg * ns + i] + Db[rb * ns + j] * Ss[NQ + yg * ns + i];
+        yn += mbv * Ss[2 * NQ + yg * ns + i];
+      }
+      T* out = L.slot + (s1 ? M.slot[1] : M.slot[0]);
+      out[li] = yf;
+      out[ns * ns + li] = yn;
+    }
+  }
 }
 
 // NT, QT > 0: element degree + 1 and volume GL points fixed at compile time (the bucket's
-// elements); 0: read from the element record.  UNI: uniform-degree level (faces_uniform).
-template <typename T, int NT, int QT, bool UNI, bool FUSE = false>
+// elements), and the LDS laid out for them; 0: read from the element record, LDS for the
+// level's largest.  FUSE: run the Jacobi-scaled Chebyshev step bs on the result instead of
+// storing y.  The face slots of the element must be written (mortar_kernel) before the launch.
+template <typename T, int NT, int QT, bool FUSE = false>
 __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const int* __restrict__ elems,
                                                          long long count, const T* x, T* __restrict__ y,
                                                          BlockStep<T> bs) {
@@ -354,12 +346,11 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const int n = NT ? NT : I.n, q = QT ? QT : I.q;
   const int n2 = n * n, n3 = n2 * n, q3 = q * q * q;
   constexpr bool COMPACT = NT > 0 && NT * NT * NT <= 2 * kThreads;
-  static_assert(!FUSE || UNI, "the fused smoother step runs on one-degree levels");
-  const Layout lay(L.nmax, L.qmax, L.qmmax, COMPACT);
-  const int NM = lay.NM, QM = lay.QM, QMM = lay.QMM;
+  static_assert(!FUSE || COMPACT, "the fused smoother step runs on the compact layout");
+  const Layout lay(NT ? NT : L.nmax, QT ? QT : L.qmax, COMPACT, FUSE);
+  const int NM = lay.NM, QM = lay.QM;
 
-  Task* tasks = reinterpret_cast<Task*>(smem_raw);
-  T* p = reinterpret_cast<T*>(smem_raw + lay.tasks);
+  T* p = reinterpret_cast<T*>(smem_raw);
   T* su = p;
   T* sy = p + NM * NM * NM;
   if (!COMPACT) p += 2 * NM * NM * NM;
@@ -379,12 +370,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   const int tsz = NM * QM * (NM > QM ? NM : QM);
   T* tA = A3 + QM * QM * QM;
   T* tB = tA + tsz;
-  // face phases (alias the volume buffers): ping-pong regions RA / RB and the face sums
-  T* RA = region;
-  T* RB = RA + lay.ra;
-  T* Yf = RB + lay.rb;
-  T* Yn = Yf + kFaces * NM * NM;
-  const int raS = int(lay.ra / kFaces), rbS = int(lay.rb / kFaces);
+  T* Ys = region + lay.ysum;  // after the volume phase: face f's value lift at f 2 n^2, normal lift + n^2
 
   {
     const T* B = tab(L, 0, n, q);
@@ -398,7 +384,6 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
     for (int i = threadIdx.x; i < 2 * n; i += blockDim.x) dfo[(i / n) * NM + i % n] = dfg[i];
   }
   __syncthreads();
-
   // ---- volume: u -> GL values (three 1-D passes) ----
   for (int idx = threadIdx.x; idx < n2 * q; idx += blockDim.x) {
     const int a = idx % q, kj = idx / q;
@@ -495,194 +480,24 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   } else {
     for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) sy[idx] = back_a(idx);
   }
-  __syncthreads();  // the face phases reuse the volume buffers
+  __syncthreads();  // the face sums reuse the volume buffers
 
-  // ---- faces ----
-  if constexpr (UNI) {
-    faces_uniform<T, NT, QT, COMPACT, FUSE>(L, I, e, y, sy, syr, dfo, region, tasks, lay, bs);
-    return;
+  // ---- faces: the element's slots, summed per face in list order ----
+  {
+    const ElemInfo& Ig = L.einfo[e];  // (read through memory: a per-thread face index into the
+                                      // private copy would place it in scratch)
+    const int f0 = I.fstart[0];
+    for (int g = threadIdx.x; g < 12 * n2; g += blockDim.x) {
+      const int f = g / (2 * n2), r2 = g - f * 2 * n2;
+      const int cnt = Ig.fcnt[f];
+      const T* sl = L.slot + I.soff + 2LL * (Ig.fstart[f] - f0) * n2 + r2;
+      T acc = 0;
+      for (int r = 0; r < cnt; ++r) acc += sl[2LL * r * n2];
+      Ys[g] = acc;
+    }
   }
-  int rounds = 0;
-#pragma unroll
-  for (int f = 0; f < kFaces; ++f) rounds = I.fcnt[f] > rounds ? I.fcnt[f] : rounds;
-  for (int i = threadIdx.x; i < 2 * kFaces * NM * NM; i += blockDim.x) Yf[i] = 0;  // Yf and Yn
-  for (int r = 0; r < rounds; ++r) {
-    for (int f = threadIdx.x; f < kFaces; f += blockDim.x) tasks[f] = make_task(L, e, f, r);
-    __syncthreads();
-    // P1: traces (values and reference normal derivative) of both sides from the trace buffer
-#define C1(t) (tasks[t].valid ? n2 + (tasks[t].other ? tasks[t].no * tasks[t].no : 0) : 0)
-    for_items(HPDG_COUNTS(C1), [&](int t, int li) {
-      const Task& tk = tasks[t];
-      T* tr = RB + t * rbS;  // Fm, Nm, Fo, No at strides NM^2
-      if (li < n2) {
-        const long long off = I.toff + 2LL * tk.f * n2;
-        tr[li] = L.trace[off + li];
-        tr[NM * NM + li] = L.trace[off + n2 + li];
-      } else {
-        const int lo = li - n2, no2 = tk.no * tk.no;
-        tr[2 * NM * NM + lo] = L.trace[tk.ooff + lo];
-        tr[3 * NM * NM + lo] = L.trace[tk.ooff + no2 + lo];
-      }
-    });
-    __syncthreads();
-    // P2: first interpolation pass (along face axis a) of u, du/da, du/dn, both sides
-#define C2(t) (tasks[t].valid ? tasks[t].qm * (n + (tasks[t].other ? tasks[t].no : 0)) : 0)
-    for_items(HPDG_COUNTS(C2), [&](int t, int li) {
-      const Task& tk = tasks[t];
-      const int qm = tk.qm;
-      const bool own = li < n * qm;
-      const int ns = own ? n : tk.no;
-      const int l2 = own ? li : li - n * qm;
-      const Map m = own ? tk.me : tk.ot;
-      const T* F = RB + t * rbS + (own ? 0 : 2 * NM * NM);
-      const T* N = F + NM * NM;
-      const T* Ma = L.tab + (own ? tk.meA : tk.otA);
-      const T* Da = L.tab + (own ? tk.meAd : tk.otAd);
-      const int j = qdiv(l2, tk.qinv), xg = l2 - j * qm;
-      const int ra = m.flipA ? qm - 1 - xg : xg;
-      T s0 = 0, s1 = 0, s2 = 0;
-#pragma unroll 4
-      for (int i = 0; i < ns; ++i) {
-        const T fv = F[j * ns + i], ma = Ma[ra * ns + i];
-        s0 += ma * fv;
-        s1 += Da[ra * ns + i] * fv;
-        s2 += ma * N[j * ns + i];
-      }
-      T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-      T1[j * qm + xg] = s0;
-      T1[NM * QMM + j * qm + xg] = s1;
-      T1[2 * NM * QMM + j * qm + xg] = s2;
-    });
-    __syncthreads();
-    // P3+P4: second pass (along face axis b) of both sides at one mortar point: u, du/da,
-    // du/db, du/dn; then the SIPG flux there (own side, own frame) into RB
-#define C4(t) (tasks[t].valid ? tasks[t].qm * tasks[t].qm : 0)
-    for_items(HPDG_COUNTS(C4), [&](int t, int li) {
-      const Task& tk = tasks[t];
-      const int qm = tk.qm, qq = qm * qm, side = tk.side;
-      // side values at the point with index l2 of that side's frame
-      auto at_point = [&](bool own, int l2, T& v0, T& v1, T& v2, T& v3) {
-        const int ns = own ? n : tk.no;
-        const Map m = own ? tk.me : tk.ot;
-        const T* T1 = RA + t * raS + (own ? 0 : 3 * NM * QMM);
-        const T* Mb = L.tab + (own ? tk.meB : tk.otB);
-        const T* Db = L.tab + (own ? tk.meBd : tk.otBd);
-        const int yg = qdiv(l2, tk.qinv), xg = l2 - yg * qm;
-        const int rb = m.flipB ? qm - 1 - yg : yg;
-        T g0 = 0, g1 = 0, g2 = 0, g3 = 0;
-#pragma unroll 4
-        for (int j = 0; j < ns; ++j) {
-          const T mb = Mb[rb * ns + j];
-          const T a0 = T1[j * qm + xg];
-          g0 += mb * a0;
-          g1 += mb * T1[NM * QMM + j * qm + xg];
-          g2 += Db[rb * ns + j] * a0;
-          g3 += mb * T1[2 * NM * QMM + j * qm + xg];
-        }
-        v0 = g0;
-        v1 = g1;
-        v2 = g2;
-        v3 = g3;
-      };
-      const int npts = tk.gmode ? qq : 1;
-      const T* mg = L.mgeo + tk.geo;
-      const int f = tk.f, d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-      const int yg = qdiv(li, tk.qinv), xg = li - yg * qm;
-      const int cc = tk.me.swap ? yg : xg, dd = tk.me.swap ? xg : yg;
-      const int rho = cc + qm * dd, pp = tk.gmode ? rho : 0;
-      T wS;
-      if (tk.gmode) {
-        wS = mg[6 * npts + pp];
-      } else {
-        const T* wm = L.tab + L.tv.w_off[qm];
-        wS = wm[cc] * wm[dd] * mg[6];
-      }
-      const T sig = mg[7 * npts + pp];
-      const T ma = mg[(3 * side + t0) * npts + pp];
-      const T mb = mg[(3 * side + t1) * npts + pp];
-      const T mn = mg[(3 * side + d) * npts + pp];
-      T u_me, ga, gb, gn;
-      at_point(true, li, u_me, ga, gb, gn);
-      const T g_me = ma * ga + mb * gb + mn * gn;
-      T Af, Bc;
-      if (tk.interior) {
-        T u_o = 0, g_o = 0;
-        if (tk.other) {
-          const int os = 1 - side, od = tk.of >> 1;
-          const int ot0 = od == 0 ? 1 : 0, ot1 = od == 2 ? 1 : 2;
-          const int xo = tk.ot.swap ? dd : cc, yo = tk.ot.swap ? cc : dd;
-          T oa, ob, on;
-          at_point(false, xo + qm * yo, u_o, oa, ob, on);
-          g_o = mg[(3 * os + ot0) * npts + pp] * oa + mg[(3 * os + ot1) * npts + pp] * ob +
-                mg[(3 * os + od) * npts + pp] * on;
-        }
-        const T jmp = u_me - u_o;
-        Af = wS * (sig * jmp - T(0.5) * (g_me - g_o));
-        Bc = T(-0.5) * wS * jmp;
-      } else {
-        Af = wS * (sig * u_me - g_me);
-        Bc = -wS * u_me;
-      }
-      T* CF = RB + t * rbS;
-      CF[li] = Af;
-      CF[QMM * QMM + li] = Bc * ma;
-      CF[2 * QMM * QMM + li] = Bc * mb;
-      CF[3 * QMM * QMM + li] = Bc * mn;
-    });
-    __syncthreads();
-    // P5: first transposed pass (along the own face axis a)
-#define C5(t) (tasks[t].valid ? tasks[t].qm * n : 0)
-    for_items(HPDG_COUNTS(C5), [&](int t, int li) {
-      const Task& tk = tasks[t];
-      const int qm = tk.qm;
-      const T* Ma = L.tab + tk.meA;
-      const T* Da = L.tab + tk.meAd;
-      const T* CF = RB + t * rbS;
-      const int i = li % n, yg = li / n;
-      T s1 = 0, s2 = 0, s3 = 0;
-#pragma unroll 4
-      for (int xg = 0; xg < qm; ++xg) {
-        const int ra = tk.me.flipA ? qm - 1 - xg : xg;
-        const T ma = Ma[ra * n + i];
-        const int g = yg * qm + xg;
-        s1 += ma * CF[g] + Da[ra * n + i] * CF[QMM * QMM + g];
-        s2 += ma * CF[2 * QMM * QMM + g];
-        s3 += ma * CF[3 * QMM * QMM + g];
-      }
-      T* S = RA + t * raS;
-      S[li] = s1;  // [y][i]
-      S[QMM * NM + li] = s2;
-      S[2 * QMM * NM + li] = s3;
-    });
-    __syncthreads();
-    // P6: second transposed pass (along b) into the per-face sums
-#define C6(t) (tasks[t].valid ? n2 : 0)
-    for_items(HPDG_COUNTS(C6), [&](int t, int li) {
-      const Task& tk = tasks[t];
-      const int qm = tk.qm;
-      const T* Mb = L.tab + tk.meB;
-      const T* Db = L.tab + tk.meBd;
-      const T* S = RA + t * raS;
-      const int i = li % n, j = li / n;
-      T yf = 0, yn = 0;
-#pragma unroll 4
-      for (int yg = 0; yg < qm; ++yg) {
-        const int rb = tk.me.flipB ? qm - 1 - yg : yg;
-        const T mb = Mb[rb * n + j];
-        yf += mb * S[yg * n + i] + Db[rb * n + j] * S[QMM * NM + yg * n + i];
-        yn += mb * S[2 * QMM * NM + yg * n + i];
-      }
-      Yf[tk.f * NM * NM + li] += yf;
-      Yn[tk.f * NM * NM + li] += yn;
-    });
-    __syncthreads();
-  }
+  __syncthreads();
   // face sums -> element: values on the face layer, normal-derivative part along the lines
-#undef C1
-#undef C2
-#undef C4
-#undef C5
-#undef C6
   auto finish = [&](int idx, T acc) {
     const int c0 = idx % n, c1 = (idx / n) % n, c2 = idx / n2;
 #pragma unroll
@@ -692,10 +507,13 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
       // node index along the normal axis and its (t0, t1) position on the face
       const int kd = d == 0 ? c0 : (d == 1 ? c1 : c2);
       const int li = d == 0 ? c2 * n + c1 : (d == 1 ? c2 * n + c0 : c1 * n + c0);
-      acc += dfo[(f & 1) * NM + kd] * Yn[f * NM * NM + li];
-      if (kd == ((f & 1) ? n - 1 : 0)) acc += Yf[f * NM * NM + li];
+      acc += dfo[(f & 1) * NM + kd] * Ys[f * 2 * n2 + n2 + li];
+      if (kd == ((f & 1) ? n - 1 : 0)) acc += Ys[f * 2 * n2 + li];
     }
-    y[I.off + idx] = acc;
+    if constexpr (FUSE)
+      region[idx] = bs.b[I.off + idx] - acc;  // r = b - A x (the face sums start after r and the partial z)
+    else
+      y[I.off + idx] = acc;
   };
   if constexpr (COMPACT) {  // node threadIdx.x + it kThreads of this thread
 #pragma unroll
@@ -704,6 +522,7 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
   } else {
     for (int idx = threadIdx.x; idx < n3; idx += blockDim.x) finish(idx, sy[idx]);
   }
+  if constexpr (FUSE) fused_step_tail<T, NT>(NT, I, e, region, dfo, NM, bs);
 }
 
 template <typename T>
@@ -730,71 +549,77 @@ __global__ void __launch_bounds__(kThreads) trace_kernel(LevelView<T> L, const T
   }
 }
 
-template <typename T, int N, int Q, bool UNI, bool FUSE = false>
-void launch_fixed(const LevelView<T>& L, const int* elems, long long count, const T* x, T* y, size_t lds,
-                  hipStream_t s, const BlockStep<T>& bs = BlockStep<T>{}) {
-  hipLaunchKernelGGL((apply_kernel<T, N, Q, UNI, FUSE>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
-                     count, x, y, bs);
+template <typename T, int N, int Q, bool FUSE = false>
+void launch_fixed(const LevelView<T>& L, const int* elems, long long count, const T* x, T* y, hipStream_t s,
+                  const BlockStep<T>& bs = BlockStep<T>{}) {
+  constexpr bool compact = N * N * N <= 2 * kThreads;
+  const size_t lds = Layout(N, Q, compact, FUSE).bytes(sizeof(T));
+  hipLaunchKernelGGL((apply_kernel<T, N, Q, FUSE>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems, count,
+                     x, y, bs);
+}
+
+template <typename T>
+void launch_mortars(const LevelView<T>& L, hipStream_t s) {
+  if (L.n_mtask == 0) return;
+  const size_t lds = mortar_lds_scalars(L.nmax, L.qmmax) * sizeof(T);
+  hipLaunchKernelGGL((mortar_kernel<T>), dim3(unsigned(L.n_mtask)), dim3(64), lds, s, L, L.n_mtask);
 }
 
 }  // namespace
 
 size_t apply_lds_bytes(int NM, int QM, int QMM, size_t scalar, bool compact) {
-  return Layout(NM, QM, QMM, compact).bytes(scalar);
+  const size_t a = Layout(NM, QM, compact, false).bytes(scalar), m = mortar_lds_scalars(NM, QMM) * scalar;
+  return a > m ? a : m;
 }
 
 template <typename T>
 void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s) {
-  if (L.n_elem == 0) return;  // also with self_only: the uniform face path reads the own traces
+  if (L.n_elem == 0) return;
   hipLaunchKernelGGL((trace_kernel<T>), dim3(unsigned(L.n_elem)), dim3(kThreads), 0, s, L, x);
+}
+
+template <typename T>
+void launch_faces(const LevelView<T>& L, hipStream_t s) {
+  launch_mortars<T>(L, s);
 }
 
 template <typename T>
 void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
   if (L.n_elem == 0) return;
   launch_traces<T>(L, x, s);
-  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
-  hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
+  launch_mortars<T>(L, s);
+  const size_t lds = Layout(L.nmax, L.qmax, false, false).bytes(sizeof(T));
+  hipLaunchKernelGGL((apply_kernel<T, 0, 0>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
                      (const int*)nullptr, L.n_elem, x, y, BlockStep<T>{});
 }
 
 template <typename T>
-void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
-                         const T* x, T* y, hipStream_t s) {
+void launch_apply_bucket(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x, T* y,
+                         hipStream_t s) {
   if (count == 0) return;
-  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), false);
-  // the fixed-degree kernels of degree n with n^3 <= 2 kThreads use the compact layout
-  const size_t lds_c = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), n * n * n <= 2 * kThreads);
-#define HPDG_CASE(NN, QQ)                                                                      \
-  if (n == NN && q == QQ)                                                                       \
-    return uniform ? launch_fixed<T, NN, QQ, true>(L, elems, count, x, y, lds_c, s)             \
-                   : launch_fixed<T, NN, QQ, false>(L, elems, count, x, y, lds_c, s);
+#define HPDG_CASE(NN, QQ) \
+  if (n == NN && q == QQ) return launch_fixed<T, NN, QQ>(L, elems, count, x, y, s);
   HPDG_CASE(2, 2) HPDG_CASE(2, 3) HPDG_CASE(3, 3) HPDG_CASE(3, 4) HPDG_CASE(4, 4) HPDG_CASE(4, 5)
   HPDG_CASE(5, 5) HPDG_CASE(5, 6) HPDG_CASE(6, 6) HPDG_CASE(6, 7) HPDG_CASE(7, 7) HPDG_CASE(7, 8)
   HPDG_CASE(8, 8) HPDG_CASE(8, 9)
 #undef HPDG_CASE
-  hipLaunchKernelGGL((apply_kernel<T, 0, 0, false>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems,
-                     count, x, y, BlockStep<T>{});
+  const size_t lds = Layout(L.nmax, L.qmax, false, false).bytes(sizeof(T));
+  hipLaunchKernelGGL((apply_kernel<T, 0, 0>), dim3(unsigned(count)), dim3(kThreads), lds, s, L, elems, count, x, y,
+                     BlockStep<T>{});
 }
 
-bool apply_block_fusable(int nmax, int qmax, int qmmax, int n, int q, int uniform) {
-  // mixed-degree levels keep the separate kernels: fused per degree bucket they measured slower
-  if (!uniform || n * n * n > 2 * kThreads || kThreads % 64 != 0 || n < 2 || n > 8 || q < n || q > n + 1)
-    return false;
-  const Layout lay(nmax, qmax, qmmax, true);
-  // r and one partial z per wave in the face buffers before the face sums (RA, RB)
-  return lay.ra + lay.rb >= (1LL + kThreads / 64) * n * n * n;
+bool apply_block_fusable(int n, int q) {
+  // the compact layout of a fixed-degree kernel, whole waves (the step's block mat-vec)
+  return n * n * n <= 2 * kThreads && kThreads % 64 == 0 && n >= 2 && n <= 8 && q >= n && q <= n + 1;
 }
 
 template <typename T>
-void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
-                             const T* x, const BlockStep<T>& bs, hipStream_t s) {
+void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x,
+                             const BlockStep<T>& bs, hipStream_t s) {
   if (count == 0) return;
-  if (!apply_block_fusable(L.nmax, L.qmax, L.qmmax, n, q, uniform))
-    throw Error(-7, "fused smoother step: level of several degrees, or degree outside the compact layout");
-  const size_t lds = apply_lds_bytes(L.nmax, L.qmax, L.qmmax, sizeof(T), true);
+  if (!apply_block_fusable(n, q)) throw Error(-7, "fused smoother step: degree outside the compact layout");
 #define HPDG_CASE(NN, QQ) \
-  if (n == NN && q == QQ) return launch_fixed<T, NN, QQ, true, true>(L, elems, count, x, nullptr, lds, s, bs);
+  if (n == NN && q == QQ) return launch_fixed<T, NN, QQ, true>(L, elems, count, x, nullptr, s, bs);
   HPDG_CASE(2, 2) HPDG_CASE(2, 3) HPDG_CASE(3, 3) HPDG_CASE(3, 4) HPDG_CASE(4, 4) HPDG_CASE(4, 5)
   HPDG_CASE(5, 5) HPDG_CASE(5, 6) HPDG_CASE(6, 6) HPDG_CASE(6, 7) HPDG_CASE(7, 7) HPDG_CASE(7, 8)
   HPDG_CASE(8, 8) HPDG_CASE(8, 9)
@@ -802,12 +627,14 @@ void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, int uniform, c
   throw Error(-7, "fused block step: no kernel for this (n, q)");
 }
 
-template void launch_apply_block_cheb<double>(const LevelView<double>&, int, int, int, const int*, long long,
+template void launch_apply_block_cheb<double>(const LevelView<double>&, int, int, const int*, long long,
                                               const double*, const BlockStep<double>&, hipStream_t);
-template void launch_apply_block_cheb<float>(const LevelView<float>&, int, int, int, const int*, long long,
+template void launch_apply_block_cheb<float>(const LevelView<float>&, int, int, const int*, long long,
                                              const float*, const BlockStep<float>&, hipStream_t);
 template void launch_traces<double>(const LevelView<double>&, const double*, hipStream_t);
 template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t);
+template void launch_faces<double>(const LevelView<double>&, hipStream_t);
+template void launch_faces<float>(const LevelView<float>&, hipStream_t);
 template void launch_apply<double>(const LevelView<double>&, const double*, double*, hipStream_t);
 template void launch_apply<float>(const LevelView<float>&, const float*, float*, hipStream_t);
 // ---- face-trace scratch of the apply for callers that cannot allocate -------------------
@@ -839,9 +666,9 @@ void* noalloc_scratch(int device) {
   return device >= 0 && device < int(g_scratch_ptr.size()) ? g_scratch_ptr[device] : nullptr;
 }
 
-template void launch_apply_bucket<double>(const LevelView<double>&, int, int, int, const int*, long long,
-                                          const double*, double*, hipStream_t);
-template void launch_apply_bucket<float>(const LevelView<float>&, int, int, int, const int*, long long,
-                                         const float*, float*, hipStream_t);
+template void launch_apply_bucket<double>(const LevelView<double>&, int, int, const int*, long long, const double*,
+                                          double*, hipStream_t);
+template void launch_apply_bucket<float>(const LevelView<float>&, int, int, const int*, long long, const float*,
+                                         float*, hipStream_t);
 
 }  // namespace hpdg

@@ -20,11 +20,13 @@ struct LevelView {
   const ElemInfo* einfo;
   const MortarInfo* minfo;
   const int* fmlist;
-  const FaceTask* ftask;  // fmlist entries as kernel task records
+  const MortarTask* mtask;  // mortars with an operator term (mortar kernel)
+  long long n_mtask;
   const T* vgeo;
   const T* mgeo;
   const T* mcoef;  // w det J c at the GL points of elements with a mass term (null: no mass term)
   T* trace;        // face traces of every element (written by launch_traces before an apply)
+  T* slot;         // lifted face terms per face-mortar list entry (written by launch_faces)
   const T* tab;
   TabView tv;
   long long n_elem;
@@ -50,13 +52,17 @@ size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar, bool compac
 // and on uniform-degree levels the own ones too)
 template <typename T>
 void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s);
+// the face terms of every mortar from L.trace into L.slot (both sides of each mortar)
+template <typename T>
+void launch_faces(const LevelView<T>& L, hipStream_t s);
+// traces, face terms and the element kernel over the whole level
 template <typename T>
 void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
-// apply restricted to the elements elems[0..count) that share degree n - 1 and q GL points;
-// uniform: every element of the level has (n, q) and every mortar q points per axis
+// the element kernel restricted to the elements elems[0..count) that share degree n - 1 and q
+// GL points (the level's face slots written before)
 template <typename T>
-void launch_apply_bucket(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
-                         const T* x, T* y, hipStream_t s);
+void launch_apply_bucket(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x, T* y,
+                         hipStream_t s);
 // the fixed face-trace scratch of the no-allocation apply: its capacity in bytes; set-up of the
 // current device's address (once per device, that device current; throws on failure); the
 // address kept for a device (null before set-up)
@@ -81,15 +87,14 @@ struct BlockStep {
   T alpha, beta;
   int first;
 };
-// whether the elements of one bucket (degree n - 1, q GL points) can take the fused step: a
-// uniform level, the compact apply layout (n^3 <= 512, q = n or n + 1) and LDS room for r and
-// 4 partial z
-bool apply_block_fusable(int nmax, int qmax, int qmmax, int n, int q, int uniform);
-// the apply and the step for the elements elems[0..count) of the level's one bucket (uniform
-// must be 1); L.trace must hold the traces of x
+// whether the elements of one bucket (degree n - 1, q GL points) can take the fused step: the
+// compact apply layout (n^3 <= 512, q = n or n + 1)
+bool apply_block_fusable(int n, int q);
+// the element kernel and the step for the elements elems[0..count) of one bucket; the level's
+// face slots must hold the face terms of x (launch_faces after the traces of x)
 template <typename T>
-void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, int uniform, const int* elems, long long count,
-                             const T* x, const BlockStep<T>& bs, hipStream_t s);
+void launch_apply_block_cheb(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x,
+                             const BlockStep<T>& bs, hipStream_t s);
 template <typename T>
 void launch_prolong_add(const TransferView<T>& V, const T* uc, T* uf, hipStream_t s);
 template <typename T>

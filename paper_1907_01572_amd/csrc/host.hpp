@@ -62,6 +62,8 @@ struct ElemInfo {
   long long vgeo;    // offset of the volume metric (in scalars)
   long long mq;      // offset of the mass coefficient w det J c at the GL points (q^3 values)
   long long toff;    // offset of the element's face traces (6 faces x [values n^2, normal derivatives n^2])
+  long long soff;    // offset of the element's lifted face terms: one slot of 2 n^2 scalars per entry of
+                     // its face-mortar list, in list order (the mortar kernel writes, the apply sums)
   int n, q;          // LGL nodes and GL points per axis
   int vmode;         // 0: constant metric (affine, 6 values), 1: per GL point (6 q^3 values)
   int mass;          // 1: the level carries a mass term c u v
@@ -78,16 +80,16 @@ struct MortarInfo {
   long long geo;              // offset of the mortar metric (in scalars)
 };
 
-// one entry of the face-mortar list in the form the operator kernels use: which face, which
-// side of which mortar, the neighbour's degree and trace offset, the mortar's rule and metric
-// offset (one 32-byte load instead of the list entry, the mortar and the neighbour's record)
-struct FaceTask {
-  long long ooff;             // neighbour's traces on the shared face (values, then normal derivatives)
+// one mortar with an operator term, as the mortar kernel reads it: both sides' traces in, both
+// sides' lifted face terms out (side 1 only on interior mortars)
+struct MortarTask {
+  long long tr[2];            // each side's traces on the mortar's face (values n^2, normal derivatives n^2)
+  long long slot[2];          // each side's output slot (value lift n^2, normal-derivative lift n^2)
   long long geo;              // offset of the mortar metric
-  signed char f, side, interior, qm, gmode, no, of, pad;
-  unsigned char me, ot;       // side maps: swap | flipA << 1 | flipB << 2 | halfA << 3 | halfB << 5
-  short pad2;
-  int pad3;
+  signed char n[2], f[2];     // each side's LGL nodes per axis and face (0 for a missing side)
+  signed char q, gmode, interior, pad;
+  unsigned char map[2];       // side maps: swap | flipA << 1 | flipB << 2 | halfA << 3 | halfB << 5
+  int pad2;
 };
 
 struct TransferInfo {         // one per fine element

@@ -450,23 +450,6 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
     }
   }
-  // One degree and one volume rule on the level: flat constant-coefficient mortars, whose
-  // n-point rule is already exact, take the volume rule's q >= n points too (the same integrals
-  // up to rounding), so that a level mixing flat and curved faces (or a mass term) still runs
-  // the uniform fast path.
-  L.uniform = L.bucket_n.size() == 1 ? 1 : 0;
-  if (L.uniform) {
-    const int q0 = L.bucket_q[0];
-    for (MortarInfo& I : L.minfo) {
-      if (I.q == 0 || I.q == q0) continue;
-      if (I.gmode == 0 && I.q == L.bucket_n[0] && I.q < q0) {
-        I.q = q0;
-        L.qmmax = std::max(L.qmmax, q0);
-      } else {
-        L.uniform = 0;
-      }
-    }
-  }
   L.fmlist.clear();
   for (size_t e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f) {
@@ -475,29 +458,47 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       L.einfo[e].fcnt[f] = int(l.size());
       L.fmlist.insert(L.fmlist.end(), l.begin(), l.end());
     }
-  L.ftask.assign(L.fmlist.size(), FaceTask{});
-  for (size_t k = 0; k < L.fmlist.size(); ++k) {
-    const int ent = L.fmlist[k], side = ent & 1;
-    const MortarInfo& M = L.minfo[size_t(ent >> 1)];
-    FaceTask& t = L.ftask[k];
-    t.f = (signed char)(side ? M.fp : M.fm);
-    t.side = (signed char)side;
-    t.interior = M.ep >= 0 ? 1 : 0;
-    t.qm = (signed char)M.q;
-    t.gmode = (signed char)M.gmode;
-    t.of = (signed char)(side ? M.fm : M.fp);
+  // output slots of the mortar kernel: per element, 2 n^2 scalars per list entry in list order
+  L.nslot = 0;
+  for (size_t e = 0; e < E; ++e) {
+    ElemInfo& I = L.einfo[e];
+    I.soff = L.nslot;
+    int cnt = 0;
+    for (int f = 0; f < 6; ++f) cnt += I.fcnt[f];
+    L.nslot += 2LL * cnt * I.n * I.n;
+  }
+  // one task per mortar that some face list holds (each side's list entry gives its slot)
+  std::vector<long long> where(2 * L.minfo.size(), -1);
+  for (size_t e = 0; e < E; ++e) {
+    const ElemInfo& I = L.einfo[e];
+    for (int f = 0; f < 6; ++f)
+      for (int r = 0; r < I.fcnt[f]; ++r) {
+        const int k = I.fstart[f] + r;
+        where[size_t(L.fmlist[k])] = I.soff + 2LL * (k - I.fstart[0]) * I.n * I.n;
+      }
+  }
+  L.mtask.clear();
+  for (size_t m = 0; m < L.minfo.size(); ++m) {
+    if (where[2 * m] < 0 && where[2 * m + 1] < 0) continue;
+    const MortarInfo& M = L.minfo[m];
+    if (where[2 * m] < 0 || (M.ep >= 0) != (where[2 * m + 1] >= 0))
+      throw Error(-2, "internal: a mortar listed on one side of an interior face only");
+    MortarTask t{};
     t.geo = M.geo;
-    auto pack = [&](int sd) {
-      const SideMap m = side_map(M, sd);
-      return (unsigned char)(m.swap | (m.flipA << 1) | (m.flipB << 2) | (m.halfA << 3) | (m.halfB << 5));
-    };
-    t.me = pack(side);
-    t.ot = pack(1 - side);
-    if (M.ep >= 0) {
-      const ElemInfo& O = L.einfo[size_t(side ? M.em : M.ep)];
-      t.no = (signed char)O.n;
-      t.ooff = O.toff + 2LL * t.of * O.n * O.n;
+    t.q = (signed char)M.q;
+    t.gmode = (signed char)M.gmode;
+    t.interior = M.ep >= 0 ? 1 : 0;
+    for (int sd = 0; sd < 1 + t.interior; ++sd) {
+      const ElemInfo& O = L.einfo[size_t(sd ? M.ep : M.em)];
+      const int f = sd ? M.fp : M.fm;
+      const SideMap sm = side_map(M, sd);
+      t.n[sd] = (signed char)O.n;
+      t.f[sd] = (signed char)f;
+      t.tr[sd] = O.toff + 2LL * f * O.n * O.n;
+      t.slot[sd] = where[2 * m + sd];
+      t.map[sd] = (unsigned char)(sm.swap | (sm.flipA << 1) | (sm.flipB << 2) | (sm.halfA << 3) | (sm.halfB << 5));
     }
+    L.mtask.push_back(t);
   }
   (void)T;
 }

@@ -44,18 +44,18 @@ struct LevelHost {
   std::vector<ElemInfo> einfo;
   std::vector<MortarInfo> minfo;
   std::vector<int> fmlist;       // (mortar << 1) | side, grouped per element face
-  std::vector<FaceTask> ftask;   // the same entries as kernel task records
+  std::vector<MortarTask> mtask; // mortars with an operator term, both sides, for the mortar kernel
   std::vector<double> vgeo, mgeo;
   std::vector<double> diag;
   long long ndof = 0;
   long long nmq = 0;  // mass-coefficient scalars (sum of q^3 over elements with a mass term)
   long long ntrace = 0;  // face-trace scalars (12 n^2 per element)
+  long long nslot = 0;   // lifted face-term scalars (2 n^2 per face-mortar list entry)
   int nmax = 0, qmax = 0, qmmax = 0;
   // elements grouped by (n, q): kernels are specialised per group
   std::vector<int> bucket_n, bucket_q;
   std::vector<long long> bucket_start;
   std::vector<int> bucket_elems;
-  int uniform = 0;  // one (n, q) for every element, q points per axis on every mortar
   // prolongation from the next coarser level: one record per element of this level
   std::vector<TransferInfo> tinfo;
   // restriction gathers: for each coarser element, the elements of this level inside it
