@@ -37,7 +37,8 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 TRAFFIC_FILE = os.path.join("profiles", "solve_hp_hbm_traffic.txt")
 APPLY_ALL_BUCKETS = "trace_kernel<double> + apply_kernel<double, n, q, false> (one launch per degree bucket)"
 KERNEL_SOURCES = [os.path.join("paper_1907_01572_amd", "csrc", f)
-                  for f in ("apply.hip", "apply_common.hpp", "kernels.hip", "blocks.hpp", "device.hpp", "host.hpp")]
+                  for f in ("apply.hip", "fastapply.hip", "apply_common.hpp", "kernels.hip", "blocks.hpp", "device.hpp",
+                            "host.hpp")]
 COPY_BYTES = 1 << 30  # calibration copy: 1 GiB read, 1 GiB written
 # kernel timing inside the timed solves: HIP events around every 8th launch of each kernel
 # kind and level (two event records per sampled launch)

@@ -155,6 +155,11 @@ typedef struct {
    * does not repeat on a fresh assembly is retried once; both stay 0 in a healthy run */
   int32_t block_retries;
   int32_t coarse_retries;
+  /* operator apply per level: elements evaluated element-centrically (affine, axis-aligned,
+   * constant k, no mass term, p <= 7: volume and conforming faces from the 1-D mass and
+   * stiffness matrices, neighbours read directly) and mortars left to the mortar kernel */
+  int64_t n_elem_centric[32];
+  int64_t n_mortar_tasks[32];
 } hpdg_mesh_info;
 
 /* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters.

@@ -65,7 +65,8 @@ class MeshInfo(ctypes.Structure):
                 ("n_dof", ctypes.c_int64 * 32), ("n_mortar", ctypes.c_int64 * 32),
                 ("vgeo_scalars", ctypes.c_int64 * 32), ("mgeo_scalars", ctypes.c_int64 * 32),
                 ("table_bytes", ctypes.c_int64 * 32), ("device_bytes", ctypes.c_size_t),
-                ("block_retries", ctypes.c_int32), ("coarse_retries", ctypes.c_int32)]
+                ("block_retries", ctypes.c_int32), ("coarse_retries", ctypes.c_int32),
+                ("n_elem_centric", ctypes.c_int64 * 32), ("n_mortar_tasks", ctypes.c_int64 * 32)]
 
 
 class SmootherParams(ctypes.Structure):
@@ -342,6 +343,8 @@ class Mesh:
         self.device_bytes = int(info.device_bytes)
         self.block_retries = int(info.block_retries)
         self.coarse_retries = int(info.coarse_retries)
+        self.n_elem_centric = [int(info.n_elem_centric[i]) for i in range(self.n_levels)]
+        self.n_mortar_tasks = [int(info.n_mortar_tasks[i]) for i in range(self.n_levels)]
 
     def algorithmic_bytes(self, level=0, scalar=8):
         """Bytes one apply of ``level`` must move at least once: x read and y written, the

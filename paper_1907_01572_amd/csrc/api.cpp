@@ -63,7 +63,13 @@ struct DevLevel {
   T* binv = nullptr;           // packed lower triangles of the inverse blocks
   long long* boff16 = nullptr;  // offsets of the full bf16 blocks (FP32 levels)
   uint16_t* binv16 = nullptr;   // full bf16 copies of the inverse blocks (FP32 levels)
-  int* belems = nullptr;      // element ids grouped by (n, q)
+  int* belems = nullptr;      // element ids grouped by (n, q) (elements of the element kernel)
+  int* felems = nullptr;      // element-centric apply: element ids grouped by n
+  int* telems = nullptr;      // elements whose face traces the mortar kernel reads
+  FaceLink* flink = nullptr;  // element-centric apply, group order: face records (6 per element),
+  long long* fe_off = nullptr;  // dof offsets and the diagonal metric (3 per element)
+  T* fe_g = nullptr;
+  T* fcoef = nullptr;         // face coefficient tuples
   // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
   T* mcoef = nullptr;
   T* diag = nullptr;
@@ -244,6 +250,11 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.vgeo = d.vgeo;
   v.mgeo = d.mgeo;
   v.mcoef = mass_on ? d.mcoef : nullptr;
+  v.flink = d.flink;
+  v.fe_off = d.fe_off;
+  v.fe_g = d.fe_g;
+  v.fe_id = d.felems;
+  v.fcoef = d.fcoef;
   v.trace = d.trace;
   v.slot = d.slot;
   v.tab = table<T>();
@@ -308,6 +319,12 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
   d.fmlist = M->upload_raw(h.fmlist, s);
   d.mtask = M->upload_raw(h.mtask, s);
   d.belems = M->upload_raw(h.bucket_elems, s);
+  d.felems = M->upload_raw(h.fast_elems, s);
+  d.telems = M->upload_raw(h.trace_elems, s);
+  d.flink = M->upload_raw(h.flink, s);
+  d.fe_off = M->upload_raw(h.fast_off, s);
+  d.fe_g = M->upload<T>(h.fast_g, s);
+  d.fcoef = M->upload<T>(h.fcoef, s);
   d.vgeo = M->upload<T>(h.vgeo, s);
   d.mgeo = M->upload<T>(h.mgeo, s);
   std::vector<double> dinv(h.diag.size());
@@ -374,43 +391,61 @@ void collect_timing(hpdg_mesh* M) {
   M->pending.clear();
 }
 
-// algorithmic bytes of one apply of level l: x read and y written once, the stored
-// metric once, the element / mortar / face-list records once
+// algorithmic bytes of one apply of level l: x read and y written once, the stored metric once,
+// the records once (element records of the element kernel's elements, the element-centric
+// records of the others, mortar tasks)
 double apply_bytes(const hpdg_mesh* M, int l, size_t scalar) {
   const LevelHost& h = M->H[l];
-  return double(scalar) * (2.0 * double(h.ndof) + double(h.vgeo.size()) + double(h.mgeo.size())) +
-         double(h.einfo.size() * sizeof(ElemInfo) + h.mtask.size() * sizeof(MortarTask));
+  return double(scalar) * (2.0 * double(h.ndof) + double(h.vgeo.size()) + double(h.mgeo.size()) +
+                           double(h.fcoef.size()) + double(h.fast_g.size())) +
+         double(h.bucket_elems.size() * sizeof(ElemInfo) + h.mtask.size() * sizeof(MortarTask) +
+                h.fast_elems.size() * (6 * sizeof(FaceLink) + sizeof(long long)));
+}
+
+// group b of level l's element-centric apply
+template <typename T>
+FastBucket<T> fast_bucket(const hpdg_mesh* M, int l, size_t b) {
+  const LevelHost& h = M->H[l];
+  const int n = h.fast_n[b];
+  const T* tb = M->table<T>();
+  return FastBucket<T>{n, h.fast_nx[b], h.fast_start[b], h.fast_start[b + 1] - h.fast_start[b],
+                       tb + M->tab.index(OpTable::MASS1, n, n), tb + M->tab.index(OpTable::STIFF1, n, n),
+                       tb + M->tab.dface_off[n]};
+}
+
+// y = A_l x through the view V (whose trace and slot buffers are used): the face traces that the
+// mortar kernel reads and the mortar kernel (faces left to it), then the element-centric apply of
+// the fast elements and the element kernel of the others
+template <typename T>
+void level_apply(hpdg_mesh* M, int l, const LevelView<T>& V, const T* x, T* y, hipStream_t s) {
+  const LevelHost& h = M->H[l];
+  DevLevel<T>& d = M->lev<T>(l);
+  if (!h.mtask.empty()) {
+    launch_traces<T>(V, x, s, d.telems, (long long)h.trace_elems.size());
+    launch_faces<T>(V, s);
+  }
+  for (size_t b = 0; b < h.fast_n.size(); ++b) launch_fast_apply<T>(V, fast_bucket<T>(M, l, b), x, y, s);
+  for (size_t b = 0; b < h.bucket_n.size(); ++b)
+    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], d.belems + h.bucket_start[b],
+                           h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
 }
 
 template <typename T>
 void apply_level(hpdg_mesh* M, int l, const T* x, T* y, hipStream_t s) {
-  const LevelHost& h = M->H[l];
-  const LevelView<T> V = M->view<T>(l);
-  const int* be = M->lev<T>(l).belems;
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
-  timed(M, HPDG_TIMING_APPLY, l, prec, M->timing ? apply_bytes(M, l, sizeof(T)) : 0.0, s, [&] {
-    launch_traces<T>(V, x, s);
-    launch_faces<T>(V, s);
-    for (size_t b = 0; b < h.bucket_n.size(); ++b)
-      launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], be + h.bucket_start[b],
-                             h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
-  });
+  const LevelView<T> V = M->view<T>(l);
+  timed(M, HPDG_TIMING_APPLY, l, prec, M->timing ? apply_bytes(M, l, sizeof(T)) : 0.0, s,
+        [&] { level_apply<T>(M, l, V, x, y, s); });
 }
 
 // the apply of level l with the face traces and the face slots in the caller-free scratch
 // ``trace`` and ``slot`` (no timing, no allocation)
 template <typename T>
 void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, T* slot, hipStream_t s) {
-  const LevelHost& h = M->H[l];
   LevelView<T> V = M->view<T>(l);
   V.trace = trace;
   V.slot = slot;
-  const int* be = M->lev<T>(l).belems;
-  launch_traces<T>(V, x, s);
-  launch_faces<T>(V, s);
-  for (size_t b = 0; b < h.bucket_n.size(); ++b)
-    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], be + h.bucket_start[b],
-                           h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
+  level_apply<T>(M, l, V, x, y, s);
 }
 
 // Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)
@@ -426,10 +461,59 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
   const bool block = M->sp.scaling == HPDG_SMOOTH_BLOCK;
   const bool bf16 = std::is_same<T, float>::value && M->bf16_blocks && d.binv16;
   const LevelHost& h = M->H[l];
-  bool fuse = ((block && !bf16) || dinv) && !M->sp.unfused && !h.bucket_n.empty();
+  const bool has_fast = !h.fast_n.empty();
+  // levels without element-centric elements: the element kernel's fused step (block or point)
+  bool fuse = !has_fast && ((block && !bf16) || dinv) && !M->sp.unfused && !h.bucket_n.empty();
   for (size_t bk = 0; fuse && bk < h.bucket_n.size(); ++bk)
     fuse = apply_block_fusable(h.bucket_n[bk], h.bucket_q[bk]);
+  // levels with element-centric elements: fused point-Jacobi steps that write the new iterate to
+  // the other of two vectors (x and the level's temporary), since neighbours read x during the
+  // launch; the level's other elements take the element kernel's fused step with the same output
+  bool fuse_ec = has_fast && dinv && !M->sp.unfused;
+  for (size_t bk = 0; fuse_ec && bk < h.bucket_n.size(); ++bk)
+    fuse_ec = apply_block_fusable(h.bucket_n[bk], h.bucket_q[bk]);
   const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
+  if (fuse_ec) {
+    const int fused = n_iter - (zero ? 1 : 0);
+    T* buf[2] = {x, d.t};
+    int cur = 0;  // buf[cur] holds the iterate; the last fused step writes buf[0] = x
+    LevelView<T> V = M->view<T>(l);
+    for (int k = 1; k <= n_iter; ++k) {
+      if (k == 1)
+        alpha = 1.0 / dd;
+      else if (k == 2)
+        alpha = 2.0 * dd / (2.0 * dd * dd - c * c);
+      else
+        alpha = 1.0 / (dd - alpha * c * c / 4.0);
+      const double beta = alpha * dd - 1.0;
+      if (zero && k == 1) {
+        // x = 0: p = alpha dinv b, iterate p, placed so that the remaining steps end in x
+        cur = fused % 2;
+        launch_cheb_update<T>(n, b, nullptr, dinv, d.p, x, T(alpha), T(beta), 1, s, buf[cur]);
+        continue;
+      }
+      const double bytes = M->timing ? apply_bytes(M, l, sizeof(T)) - double(sizeof(T)) * double(n) +
+                                           double(sizeof(T)) * double(n) * (1 + 1 + (k == 1 ? 1 : 2) + 1)
+                                     : 0.0;
+      T* xi = buf[cur];
+      T* xo = buf[1 - cur];
+      const FastStep<T> st{dinv, b, d.p, xo, T(alpha), T(beta), k == 1 ? 1 : 0};
+      const BlockStep<T> bs{dinv, d.poff, d.binv, b, d.p, xi, nullptr, T(alpha), T(beta), k == 1 ? 1 : 0, xo};
+      timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
+        if (!h.mtask.empty()) {
+          launch_traces<T>(V, xi, s, d.telems, (long long)h.trace_elems.size());
+          launch_faces<T>(V, s);
+        }
+        for (size_t bk = 0; bk < h.fast_n.size(); ++bk) launch_fast_cheb<T>(V, fast_bucket<T>(M, l, bk), xi, st, s);
+        for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
+          launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], d.belems + h.bucket_start[bk],
+                                     h.bucket_start[bk + 1] - h.bucket_start[bk], xi, bs, s);
+      });
+      cur = 1 - cur;
+    }
+    if (cur != 0) launch_copy<T>(n, buf[cur], x, s);
+    return;
+  }
   // fused steps write the traces of their result for the next fused step, alternating between
   // the level's two trace buffers (a step reads one while its neighbours' new traces go to the
   // other); ``cur`` holds the traces of x when they are current, else null
@@ -456,7 +540,7 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
       }
       V.trace = cur;
       T* next = k < n_iter ? (cur == d.trace ? d.trace2 : d.trace) : nullptr;
-      const BlockStep<T> bs{dinv, d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0};
+      const BlockStep<T> bs{dinv, d.poff, d.binv, b, d.p, x, next, T(alpha), T(beta), k == 1 ? 1 : 0, nullptr};
       timed(M, HPDG_TIMING_SMOOTH, l, prec, bytes, s, [&] {
         launch_faces<T>(V, s);
         for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
@@ -671,7 +755,7 @@ void gather_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const long l
   const int nmax3 = h.nmax * h.nmax * h.nmax;
   for (int j = 0; j < nmax3; ++j) {
     launch_set_unit<double>(V, j, 1.0, d.f, s);
-    launch_apply<double>(V, d.f, d.t, s);
+    level_apply<double>(M, l, V, d.f, d.t, s);
     launch_gather_column<double>(V, j, d.t, dboff, B, s);
     launch_set_unit<double>(V, j, 0.0, d.f, s);
   }
@@ -1117,6 +1201,7 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
     for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_blocks(mesh, l, s);
   if (mesh->sp.scaling != HPDG_SMOOTH_NONE)  // the fused Jacobi-scaled steps' second trace buffer
     for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
+      if (!mesh->H[l].fast_n.empty()) continue;  // levels with element-centric elements do not chain traces
       const size_t nt = size_t(mesh->H[l].ntrace);
       if (!mesh->lev<double>(l).trace2) mesh->lev<double>(l).trace2 = mesh->alloc<double>(nt);
       if (mesh->has_f32 && !mesh->lev<float>(l).trace2) mesh->lev<float>(l).trace2 = mesh->alloc<float>(nt);
@@ -1645,6 +1730,8 @@ int hpdg_mesh_info_get(const hpdg_mesh* mesh, hpdg_mesh_info* out) {
     out->table_bytes[l] = (int64_t)(mesh->H[l].einfo.size() * sizeof(ElemInfo) +
                                     mesh->H[l].minfo.size() * sizeof(MortarInfo) +
                                     mesh->H[l].fmlist.size() * sizeof(int));
+    out->n_elem_centric[l] = (int64_t)mesh->H[l].fast_elems.size();
+    out->n_mortar_tasks[l] = (int64_t)mesh->H[l].mtask.size();
   }
   out->device_bytes = mesh->bytes;
   out->block_retries = mesh->block_retries;

@@ -102,7 +102,7 @@ __device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* reg
     const T pn = bs.first ? bs.alpha * z : bs.alpha * z + bs.beta * bs.p[I.off + i];
     bs.p[I.off + i] = pn;
     const T xn = bs.x[I.off + i] + pn;
-    bs.x[I.off + i] = xn;
+    (bs.xo ? bs.xo : bs.x)[I.off + i] = xn;
     region[i] = xn;  // r is no longer read (each thread reads only its own partials after it)
   }
   if (bs.trace_out) {
@@ -526,9 +526,10 @@ __global__ void __launch_bounds__(kThreads) apply_kernel(LevelView<T> L, const i
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kThreads) trace_kernel(LevelView<T> L, const T* __restrict__ x) {
-  const long long e = blockIdx.x;
-  if (e >= L.n_elem) return;
+__global__ void __launch_bounds__(kThreads) trace_kernel(LevelView<T> L, const T* __restrict__ x,
+                                                         const int* __restrict__ list, long long count) {
+  if ((long long)blockIdx.x >= count) return;
+  const long long e = list ? list[blockIdx.x] : (long long)blockIdx.x;
   const ElemInfo I = L.einfo[e];
   const int n = I.n, n2 = n * n;
   const T* u = x + I.off;
@@ -573,9 +574,10 @@ size_t apply_lds_bytes(int NM, int QM, int QMM, size_t scalar, bool compact) {
 }
 
 template <typename T>
-void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s) {
-  if (L.n_elem == 0) return;
-  hipLaunchKernelGGL((trace_kernel<T>), dim3(unsigned(L.n_elem)), dim3(kThreads), 0, s, L, x);
+void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s, const int* list, long long count) {
+  if (!list) count = L.n_elem;
+  if (count == 0) return;
+  hipLaunchKernelGGL((trace_kernel<T>), dim3(unsigned(count)), dim3(kThreads), 0, s, L, x, list, count);
 }
 
 template <typename T>
@@ -583,15 +585,6 @@ void launch_faces(const LevelView<T>& L, hipStream_t s) {
   launch_mortars<T>(L, s);
 }
 
-template <typename T>
-void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s) {
-  if (L.n_elem == 0) return;
-  launch_traces<T>(L, x, s);
-  launch_mortars<T>(L, s);
-  const size_t lds = Layout(L.nmax, L.qmax, false, false).bytes(sizeof(T));
-  hipLaunchKernelGGL((apply_kernel<T, 0, 0>), dim3(unsigned(L.n_elem)), dim3(kThreads), lds, s, L,
-                     (const int*)nullptr, L.n_elem, x, y, BlockStep<T>{});
-}
 
 template <typename T>
 void launch_apply_bucket(const LevelView<T>& L, int n, int q, const int* elems, long long count, const T* x, T* y,
@@ -631,12 +624,10 @@ template void launch_apply_block_cheb<double>(const LevelView<double>&, int, int
                                               const double*, const BlockStep<double>&, hipStream_t);
 template void launch_apply_block_cheb<float>(const LevelView<float>&, int, int, const int*, long long,
                                              const float*, const BlockStep<float>&, hipStream_t);
-template void launch_traces<double>(const LevelView<double>&, const double*, hipStream_t);
-template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t);
+template void launch_traces<double>(const LevelView<double>&, const double*, hipStream_t, const int*, long long);
+template void launch_traces<float>(const LevelView<float>&, const float*, hipStream_t, const int*, long long);
 template void launch_faces<double>(const LevelView<double>&, hipStream_t);
 template void launch_faces<float>(const LevelView<float>&, hipStream_t);
-template void launch_apply<double>(const LevelView<double>&, const double*, double*, hipStream_t);
-template void launch_apply<float>(const LevelView<float>&, const float*, float*, hipStream_t);
 // ---- face-trace scratch of the apply for callers that cannot allocate -------------------
 // The traces live in this fixed device array (each GPU the library runs on holds its own copy
 // until the process ends).  Host code never passes the array's name to a kernel: it uses the

@@ -25,6 +25,14 @@ struct LevelView {
   const T* vgeo;
   const T* mgeo;
   const T* mcoef;  // w det J c at the GL points of elements with a mass term (null: no mass term)
+  // element-centric apply, in the order of its element groups: face records (6 per element),
+  // dof offsets, diagonal metric (3 per element), element ids; the face coefficient tuples
+  // (S, sigma, mn, mo)
+  const FaceLink* flink;
+  const long long* fe_off;
+  const T* fe_g;
+  const int* fe_id;
+  const T* fcoef;
   T* trace;        // face traces of every element (written by launch_traces before an apply)
   T* slot;         // lifted face terms per face-mortar list entry (written by launch_faces)
   const T* tab;
@@ -47,17 +55,15 @@ struct TransferView {
 
 size_t apply_lds_bytes(int nmax, int qmax, int qmmax, size_t scalar, bool compact);
 
-// face traces of every element of the level: for each face, the values at its n^2 LGL nodes
-// and the reference normal derivative there (read by the face terms: the neighbours' traces,
-// and on uniform-degree levels the own ones too)
+// face traces of the elements list[0..count) (every element when list is null, count ignored):
+// for each face, the values at its n^2 LGL nodes and the reference normal derivative there
+// (read by the mortar kernel)
 template <typename T>
-void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s);
+void launch_traces(const LevelView<T>& L, const T* x, hipStream_t s, const int* list = nullptr,
+                   long long count = 0);
 // the face terms of every mortar from L.trace into L.slot (both sides of each mortar)
 template <typename T>
 void launch_faces(const LevelView<T>& L, hipStream_t s);
-// traces, face terms and the element kernel over the whole level
-template <typename T>
-void launch_apply(const LevelView<T>& L, const T* x, T* y, hipStream_t s);
 // the element kernel restricted to the elements elems[0..count) that share degree n - 1 and q
 // GL points (the level's face slots written before)
 template <typename T>
@@ -74,6 +80,38 @@ void* noalloc_scratch(int device);
 // p = alpha z + beta p (first:
 // alpha z), x += p, per element in the workgroup that computed (A x)_e. Every element's apply
 // reads only its own x and the face traces written before the launch, so x is updated in place.
+// The point-Jacobi Chebyshev step of Alg. 4 fused behind the element-centric apply:
+// z = dinv (b - A x), p = alpha z + beta p (first: alpha z), xo = x + p.  xo must differ from x
+// (neighbours read x during the launch).
+template <typename T>
+struct FastStep {
+  const T* dinv;
+  const T* b;
+  T* p;
+  T* xo;
+  T alpha, beta;
+  int first;
+};
+// One degree group of the element-centric apply: elements [start, start + count) of the
+// level's group order, n LGL nodes per axis; nx == n: every interior neighbour has n nodes,
+// nx > n: some has another number (at most nx); the 1-D mass and stiffness matrices and the
+// end-point derivatives l_i'(-1), l_i'(+1) of the n-node basis.
+template <typename T>
+struct FastBucket {
+  int n, nx;
+  long long start, count;
+  const T* M1;
+  const T* K1;
+  const T* df;
+};
+// The element-centric apply (fastapply.hip) of one group: y = (A x) on its elements (the face
+// slots of their faces left to the mortar kernel written before), or the fused step st.
+template <typename T>
+void launch_fast_apply(const LevelView<T>& L, const FastBucket<T>& fb, const T* x, T* y, hipStream_t s);
+template <typename T>
+void launch_fast_cheb(const LevelView<T>& L, const FastBucket<T>& fb, const T* x, const FastStep<T>& st,
+                      hipStream_t s);
+
 template <typename T>
 struct BlockStep {
   const T* dinv;          // non-null: point Jacobi (z = dinv r) instead of the element blocks
@@ -86,6 +124,7 @@ struct BlockStep {
                  // L.trace, so the two must differ)
   T alpha, beta;
   int first;
+  T* xo;         // non-null: the updated x is written here instead of in place
 };
 // whether the elements of one bucket (degree n - 1, q GL points) can take the fused step: the
 // compact apply layout (n^3 <= 512, q = n or n + 1)
@@ -108,10 +147,11 @@ void launch_copy(long long n, const T* x, T* y, hipStream_t s);
 // y = a x + b y
 template <typename T>
 void launch_axpby(long long n, T a, const T* x, T b, T* y, hipStream_t s);
-// r = dinv (b - Ax) (dinv may be null; Ax null means x = 0); p = alpha r + beta p (first: p = alpha r); x += p
+// r = dinv (b - Ax) (dinv may be null; Ax null means x = 0); p = alpha r + beta p (first: p = alpha r);
+// xo = x + p (xo null: x in place)
 template <typename T>
 void launch_cheb_update(long long n, const T* b, const T* Ax, const T* dinv, T* p, T* x, T alpha,
-                        T beta, int first, hipStream_t s);
+                        T beta, int first, hipStream_t s, T* xo = nullptr);
 // y = a .* x
 template <typename T>
 void launch_scale(long long n, const T* a, const T* x, T* y, hipStream_t s);

@@ -92,6 +92,17 @@ struct MortarTask {
   int pad2;
 };
 
+// one face of an element of the element-centric apply (fastapply.hip)
+struct FaceLink {
+  long long nb;  // kind 1: the neighbour's dof offset
+  int meta;      // kind | neighbour n << 2 | neighbour face << 7 | frame map << 10 (swap, flipA, flipB)
+                 // kind 0: no operator term; 1: interior, both sides read here; 2: boundary
+                 // (Dirichlet or Robin); 3: the mortar kernel's lifted terms (face slots)
+  int coef;      // kinds 1, 2: index of (S, sigma, own and neighbour normal coefficient) in the
+                 // level's face-coefficient table
+};
+constexpr int kFastMaxN = 8;  // element-centric apply: p <= 7
+
 struct TransferInfo {         // one per fine element
   long long foff, coff;       // dof offsets in the fine and coarse level
   int nf, nc, bits;           // bits: -1 same cell, else child bits (x | y<<1 | z<<2)

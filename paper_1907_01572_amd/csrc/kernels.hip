@@ -298,14 +298,14 @@ __global__ void axpby_kernel(long long n, T a, const T* x, T b, T* y) {
 }
 template <typename T>
 __global__ void cheb_kernel(long long n, const T* b, const T* Ax, const T* dinv, T* p, T* x, T alpha,
-                            T beta, int first) {
+                            T beta, int first, T* xo) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
        i += (long long)gridDim.x * blockDim.x) {
     T r = Ax ? b[i] - Ax[i] : b[i];  // Ax == null: x is zero
     if (dinv) r *= dinv[i];
     const T pn = first ? alpha * r : alpha * r + beta * p[i];
     p[i] = pn;
-    x[i] += pn;
+    xo[i] = x[i] + pn;
   }
 }
 template <typename T>
@@ -547,9 +547,9 @@ void launch_axpby(long long n, T a, const T* x, T b, T* y, hipStream_t s) {
 }
 template <typename T>
 void launch_cheb_update(long long n, const T* b, const T* Ax, const T* dinv, T* p, T* x, T alpha,
-                        T beta, int first, hipStream_t s) {
+                        T beta, int first, hipStream_t s, T* xo) {
   hipLaunchKernelGGL(cheb_kernel<T>, dim3(grid_for(n)), dim3(256), 0, s, n, b, Ax, dinv, p, x, alpha,
-                     beta, first);
+                     beta, first, xo ? xo : x);
 }
 template <typename T>
 void launch_scale(long long n, const T* a, const T* x, T* y, hipStream_t s) {
@@ -592,7 +592,7 @@ void launch_fcg_update(long long n, const double* v, const double* w, double* d,
   template void launch_copy<T>(long long, const T*, T*, hipStream_t);                           \
   template void launch_axpby<T>(long long, T, const T*, T, T*, hipStream_t);                    \
   template void launch_cheb_update<T>(long long, const T*, const T*, const T*, T*, T*, T, T, int, \
-                                      hipStream_t);                                             \
+                                      hipStream_t, T*);                                         \
   template void launch_dense_matvec<T>(int, const T*, const T*, T*, hipStream_t);           \
   template void launch_scale<T>(long long, const T*, const T*, T*, hipStream_t);               \
   template void launch_set_unit<T>(const LevelView<T>&, int, T, T*, hipStream_t);              \

@@ -4,6 +4,8 @@
 #include "setup.hpp"
 
 #include <algorithm>
+#include <array>
+#include <map>
 #include <cmath>
 #include <system_error>
 #include <thread>
@@ -55,6 +57,75 @@ void OpTable::build() {
     lagrange_eval(n, xn, 2, ends, L.data(), D.data());
     dface_off[n] = int(data.size());
     data.insert(data.end(), D.data(), D.data() + 2 * n);
+  }
+  // exact 1-D mass and stiffness matrices (Gauss rule of n points: the integrands have degree
+  // <= 2n - 2) and the projections between LGL bases of different sizes
+  {
+    double xm[kMaxN + 1], wm[kMaxN + 1];
+    std::vector<double> Ln(kMaxN * kMaxN), Dn(kMaxN * kMaxN), Lm(kMaxN * kMaxN), Dm(kMaxN * kMaxN);
+    std::vector<double> Mm(kMaxN * kMaxN), Km(kMaxN * kMaxN), C(kMaxN * kMaxN), P(kMaxN * kMaxN);
+    for (int n = 2; n <= kMaxN; ++n) {
+      gauss_lobatto(n, xn, wn);
+      gauss_legendre(n, eta, wq);
+      lagrange_eval(n, xn, n, eta, Ln.data(), Dn.data());
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+          double m = 0, k = 0;
+          for (int a = 0; a < n; ++a) {
+            m += wq[a] * Ln[a * n + i] * Ln[a * n + j];
+            k += wq[a] * Dn[a * n + i] * Dn[a * n + j];
+          }
+          Mm[i * n + j] = m;
+          Km[i * n + j] = k;
+        }
+      push(MASS1, n, n, Mm.data());
+      push(STIFF1, n, n, Km.data());
+      for (int m = 2; m <= kMaxN; ++m) {
+        gauss_lobatto(m, xm, wm);
+        if (m <= n) {
+          // the m-node polynomials are of degree < n: their values at the n nodes
+          lagrange_eval(m, xm, n, xn, P.data(), Dm.data());
+        } else {
+          // P = M_n^-1 C with C_ij = int l_i^(n) l_j^(m) (Gauss rule of m points: exact)
+          gauss_legendre(m, eta, wq);
+          lagrange_eval(n, xn, m, eta, Ln.data(), Dn.data());
+          lagrange_eval(m, xm, m, eta, Lm.data(), Dm.data());
+          for (int i = 0; i < n; ++i)
+            for (int j = 0; j < m; ++j) {
+              double c = 0;
+              for (int a = 0; a < m; ++a) c += wq[a] * Ln[a * n + i] * Lm[a * m + j];
+              C[i * m + j] = c;
+            }
+          // Cholesky of the (SPD) mass matrix, then one solve per column of C
+          std::vector<double> R(Mm.begin(), Mm.begin() + n * n);
+          for (int j = 0; j < n; ++j) {
+            double d = R[j * n + j];
+            for (int k = 0; k < j; ++k) d -= R[j * n + k] * R[j * n + k];
+            R[j * n + j] = std::sqrt(d);
+            for (int i = j + 1; i < n; ++i) {
+              double v = R[i * n + j];
+              for (int k = 0; k < j; ++k) v -= R[i * n + k] * R[j * n + k];
+              R[i * n + j] = v / R[j * n + j];
+            }
+          }
+          for (int j = 0; j < m; ++j) {
+            double z[kMaxN + 1];
+            for (int i = 0; i < n; ++i) {
+              double v = C[i * m + j];
+              for (int k = 0; k < i; ++k) v -= R[i * n + k] * z[k];
+              z[i] = v / R[i * n + i];
+            }
+            for (int i = n - 1; i >= 0; --i) {
+              double v = z[i];
+              for (int k = i + 1; k < n; ++k) v -= R[k * n + i] * z[k];
+              z[i] = v / R[i * n + i];
+            }
+            for (int i = 0; i < n; ++i) P[i * m + j] = z[i];
+          }
+        }
+        push(PROJ, m, n, P.data());
+      }
+    }
   }
   for (int q = 1; q <= kMaxQ; ++q) {
     gauss_legendre(q, eta, wq);
@@ -320,23 +391,6 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     }
   }
   L.ndof = off;
-  {
-    std::vector<std::pair<std::pair<int, int>, int>> keyed;
-    for (size_t e = 0; e < E; ++e) keyed.push_back({{L.einfo[e].n, L.einfo[e].q}, int(e)});
-    std::stable_sort(keyed.begin(), keyed.end(),
-                     [](const auto& a, const auto& b) { return a.first < b.first; });
-    L.bucket_n.clear(); L.bucket_q.clear(); L.bucket_start.clear(); L.bucket_elems.clear();
-    for (size_t i = 0; i < keyed.size(); ++i) {
-      if (i == 0 || keyed[i].first != keyed[i - 1].first) {
-        L.bucket_n.push_back(keyed[i].first.first);
-        L.bucket_q.push_back(keyed[i].first.second);
-        L.bucket_start.push_back((long long)i);
-      }
-      L.bucket_elems.push_back(keyed[i].second);
-    }
-    L.bucket_start.push_back((long long)keyed.size());
-  }
-
   // mortars
   const size_t M = L.mortars.size();
   L.minfo.assign(M, MortarInfo{});
@@ -458,6 +512,138 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       L.einfo[e].fcnt[f] = int(l.size());
       L.fmlist.insert(L.fmlist.end(), l.begin(), l.end());
     }
+  // ---- element-centric apply (fastapply.hip) ----
+  // An element takes it when its map is affine and axis-aligned (constant diagonal metric, k
+  // folded in), it has no mass term and p <= 7.  A face of such an element is evaluated there
+  // (from both sides' coefficients) when it carries one mortar that is conforming (no sub-face)
+  // with a constant metric whose normal coefficients have no tangential part, and the other
+  // side is such an element too (or there is none: Dirichlet and Robin faces).  Every other
+  // mortar stays with the mortar kernel, whose lifted terms (face slots) the element adds.
+  L.fast.assign(E, 0);
+  for (size_t e = 0; e < E; ++e) {
+    const ElemInfo& I = L.einfo[e];
+    if (I.vmode != 0 || I.mass || I.n < 2 || I.n > kFastMaxN) continue;
+    const double* G = L.vgeo.data() + I.vgeo;
+    if (G[1] != 0.0 || G[2] != 0.0 || G[4] != 0.0) continue;
+    L.fast[e] = 1;
+  }
+  std::vector<unsigned char> mfast(M, 0);
+  for (size_t mi = 0; mi < M; ++mi) {
+    const MortarInfo& I = L.minfo[mi];
+    if (I.q == 0 || I.gmode != 0 || I.sub >= 0 || !L.fast[I.em] || (I.ep >= 0 && !L.fast[I.ep])) continue;
+    const double* g = L.mgeo.data() + I.geo;
+    const int dm = I.fm >> 1;
+    bool ok = true;
+    for (int r = 0; r < 3; ++r) {
+      if (r != dm && g[r] != 0.0) ok = false;
+      if (I.ep >= 0 && r != (I.fp >> 1) && g[3 + r] != 0.0) ok = false;
+    }
+    mfast[mi] = ok ? 1 : 0;
+  }
+  L.flink.assign(E * 6, FaceLink{0, 0, 0});
+  L.fcoef.clear();
+  {
+    std::map<std::array<double, 4>, int> coef_index;
+    for (size_t e = 0; e < E; ++e) {
+      if (!L.fast[e]) continue;
+      const ElemInfo& I = L.einfo[e];
+      for (int f = 0; f < 6; ++f) {
+        FaceLink& fl = L.flink[e * 6 + f];
+        if (I.fcnt[f] == 0) continue;  // kind 0
+        const int ent = L.fmlist[size_t(I.fstart[f])];
+        const int mi = ent >> 1, side = ent & 1;
+        if (I.fcnt[f] != 1 || !mfast[size_t(mi)]) {
+          fl.meta = 3;
+          continue;
+        }
+        const MortarInfo& MI = L.minfo[size_t(mi)];
+        const double* g = L.mgeo.data() + MI.geo;
+        const bool interior = MI.ep >= 0;
+        const int dm = MI.fm >> 1, dp_ = interior ? MI.fp >> 1 : 0;
+        std::array<double, 4> c{g[6], g[7], 0.0, 0.0};
+        if (side == 0) {
+          c[2] = g[dm];
+          c[3] = interior ? g[3 + dp_] : 0.0;
+        } else {
+          c[2] = g[3 + dp_];
+          c[3] = g[dm];
+        }
+        auto it = coef_index.find(c);
+        if (it == coef_index.end()) {
+          it = coef_index.emplace(c, int(L.fcoef.size() / 4)).first;
+          L.fcoef.insert(L.fcoef.end(), c.begin(), c.end());
+        }
+        fl.coef = it->second;
+        if (!interior) {
+          fl.meta = 2;
+          continue;
+        }
+        // the neighbour's face coordinates of this face's nodes: (ia, ib) = swap ? (b, a) : (a, b),
+        // then ia and ib reversed by flipA and flipB (the mortar's orientation seen from this side)
+        const int o = MI.orient;
+        int swp = o & 1, fa = (o >> 1) & 1, fb = (o >> 2) & 1;
+        if (side == 1 && swp) std::swap(fa, fb);
+        const int other = side == 0 ? MI.ep : MI.em;
+        const int nf = side == 0 ? MI.fp : MI.fm;
+        fl.nb = L.einfo[size_t(other)].off;
+        fl.meta = 1 | (L.einfo[size_t(other)].n << 2) | (nf << 7) | ((swp | (fa << 1) | (fb << 2)) << 10);
+      }
+    }
+  }
+  // buckets: fast elements by n (with the largest interior neighbour n), the others by (n, q)
+  {
+    L.fast_n.clear(); L.fast_nx.clear(); L.fast_start.clear(); L.fast_elems.clear();
+    std::vector<std::pair<int, int>> kf;
+    std::vector<std::pair<std::pair<int, int>, int>> keyed;
+    for (size_t e = 0; e < E; ++e) {
+      if (L.fast[e])
+        kf.push_back({L.einfo[e].n, int(e)});
+      else
+        keyed.push_back({{L.einfo[e].n, L.einfo[e].q}, int(e)});
+    }
+    std::stable_sort(kf.begin(), kf.end(), [](const auto& a, const auto& b) { return a.first < b.first; });
+    for (size_t i = 0; i < kf.size(); ++i) {
+      if (i == 0 || kf[i].first != kf[i - 1].first) {
+        L.fast_n.push_back(kf[i].first);
+        L.fast_nx.push_back(kf[i].first);
+        L.fast_start.push_back((long long)i);
+      }
+      L.fast_elems.push_back(kf[i].second);
+      for (int f = 0; f < 6; ++f) {
+        const FaceLink& fl = L.flink[size_t(kf[i].second) * 6 + f];
+        const int nn = (fl.meta >> 2) & 31;
+        if ((fl.meta & 3) == 1 && nn != kf[i].first)  // a neighbour of another degree: mixed kernel
+          L.fast_nx.back() = std::max(L.fast_nx.back(), std::max(nn, kf[i].first + 1));
+      }
+    }
+    L.fast_start.push_back((long long)kf.size());
+    // group order: face records, dof offsets and the diagonal metric of each fast element
+    std::vector<FaceLink> byg(kf.size() * 6);
+    L.fast_off.assign(kf.size(), 0);
+    L.fast_g.assign(3 * kf.size(), 0.0);
+    for (size_t i = 0; i < kf.size(); ++i) {
+      const size_t e = size_t(kf[i].second);
+      for (int f = 0; f < 6; ++f) byg[6 * i + f] = L.flink[6 * e + f];
+      L.fast_off[i] = L.einfo[e].off;
+      const double* G = L.vgeo.data() + L.einfo[e].vgeo;
+      L.fast_g[3 * i] = G[0];
+      L.fast_g[3 * i + 1] = G[3];
+      L.fast_g[3 * i + 2] = G[5];
+    }
+    L.flink.swap(byg);
+    std::stable_sort(keyed.begin(), keyed.end(),
+                     [](const auto& a, const auto& b) { return a.first < b.first; });
+    L.bucket_n.clear(); L.bucket_q.clear(); L.bucket_start.clear(); L.bucket_elems.clear();
+    for (size_t i = 0; i < keyed.size(); ++i) {
+      if (i == 0 || keyed[i].first != keyed[i - 1].first) {
+        L.bucket_n.push_back(keyed[i].first.first);
+        L.bucket_q.push_back(keyed[i].first.second);
+        L.bucket_start.push_back((long long)i);
+      }
+      L.bucket_elems.push_back(keyed[i].second);
+    }
+    L.bucket_start.push_back((long long)keyed.size());
+  }
   // output slots of the mortar kernel: per element, 2 n^2 scalars per list entry in list order
   L.nslot = 0;
   for (size_t e = 0; e < E; ++e) {
@@ -478,8 +664,10 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       }
   }
   L.mtask.clear();
+  std::vector<unsigned char> traced(E, 0);
   for (size_t m = 0; m < L.minfo.size(); ++m) {
     if (where[2 * m] < 0 && where[2 * m + 1] < 0) continue;
+    if (mfast[m]) continue;  // evaluated by the element-centric apply on both sides
     const MortarInfo& M = L.minfo[m];
     if (where[2 * m] < 0 || (M.ep >= 0) != (where[2 * m + 1] >= 0))
       throw Error(-2, "internal: a mortar listed on one side of an interior face only");
@@ -497,9 +685,13 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       t.tr[sd] = O.toff + 2LL * f * O.n * O.n;
       t.slot[sd] = where[2 * m + sd];
       t.map[sd] = (unsigned char)(sm.swap | (sm.flipA << 1) | (sm.flipB << 2) | (sm.halfA << 3) | (sm.halfB << 5));
+      traced[size_t(sd ? M.ep : M.em)] = 1;
     }
     L.mtask.push_back(t);
   }
+  L.trace_elems.clear();
+  for (size_t e = 0; e < E; ++e)
+    if (traced[e]) L.trace_elems.push_back(int(e));
   (void)T;
 }
 

@@ -26,8 +26,13 @@ struct OpTable {
   // GL_*: LGL basis of n nodes at q GL points (full interval, lower half, upper half);
   // PR_*: coarse basis of n nodes at the q fine LGL nodes (prolongation, same cell / child);
   // IN_*: fine basis of n nodes at the q coarse LGL nodes mapped into the child (injection)
+  // MASS1 / STIFF1 (index (kind, n, n)): the exact 1-D mass and stiffness matrices of the LGL
+  // basis, int l_i l_j and int l_i' l_j' over [-1, 1] (symmetric n x n);
+  // PROJ (index (kind, m, n), n rows of m columns): the L2 projection of the m-node LGL basis
+  // onto the n-node one (the interpolation at the n nodes when m <= n, where it is exact)
   enum Kind { GL_VAL = 0, GL_DER = 1, GLLO_VAL = 2, GLLO_DER = 3, GLHI_VAL = 4, GLHI_DER = 5,
-              PR_FULL = 6, PR_LO = 7, PR_HI = 8, IN_FULL = 9, IN_LO = 10, IN_HI = 11, NKIND = 12 };
+              PR_FULL = 6, PR_LO = 7, PR_HI = 8, IN_FULL = 9, IN_LO = 10, IN_HI = 11,
+              MASS1 = 12, STIFF1 = 13, PROJ = 14, NKIND = 15 };
   std::vector<double> data;
   std::vector<int> off;        // [NKIND][kMaxN + 1][kMaxQ + 1]
   std::vector<int> dg_off;     // GL collocation derivative [q][q], by q
@@ -52,7 +57,22 @@ struct LevelHost {
   long long ntrace = 0;  // face-trace scalars (12 n^2 per element)
   long long nslot = 0;   // lifted face-term scalars (2 n^2 per face-mortar list entry)
   int nmax = 0, qmax = 0, qmmax = 0;
-  // elements grouped by (n, q): kernels are specialised per group
+  // Element-centric apply (fastapply.hip) for axis-aligned affine elements with constant k and
+  // no mass term: fast[e]; per element face its link (6 per element, used for fast elements);
+  // the distinct face coefficient tuples (S, sigma, mn, mo); fast elements grouped by n (fast_nx:
+  // n when every interior neighbour has degree n too, else a bound > n on the neighbours' n,
+  // which selects the mixed-degree kernel and sizes its scratch); the elements whose face traces
+  // the mortar kernel reads (sides of the mortars it evaluates)
+  std::vector<unsigned char> fast;
+  std::vector<FaceLink> flink;       // group order (fast_elems), 6 per element
+  std::vector<long long> fast_off;   // group order: dof offset
+  std::vector<double> fast_g;        // group order: G00, G11, G22
+  std::vector<double> fcoef;
+  std::vector<int> fast_n, fast_nx;
+  std::vector<long long> fast_start;
+  std::vector<int> fast_elems;
+  std::vector<int> trace_elems;
+  // the other elements grouped by (n, q): kernels are specialised per group
   std::vector<int> bucket_n, bucket_q;
   std::vector<long long> bucket_start;
   std::vector<int> bucket_elems;

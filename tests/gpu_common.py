@@ -67,6 +67,11 @@ MESHES = {
                     meshgen.problem_config1()),
     "hp_k": (lambda: meshgen.hp_sphere_cube(level=2, p_lo=1, p_hi=5, seed=2, r_cut=0.6),
              meshgen.problem_config3(r0=0.6)),
+    # four affine macros (faces across macros), degree 2 (16 elements per wavefront)
+    "box_macros_p2": (lambda: meshgen.box_grid((2, 2, 1), 1, 2), meshgen.problem_config1()),
+    # every pair of degrees 2..7 across conforming faces, 2:1 faces around the refined shell
+    "hp_p2_7_k1": (lambda: meshgen.hp_sphere_cube(level=2, p_lo=2, p_hi=7, seed=3, r_cut=0.6),
+                   meshgen.problem_config1()),
     "shell_l2_p3_r1e3": (lambda: meshgen.cubed_sphere_shell(level=2, p=3, r_out=1e3),
                          meshgen.problem_config2()),
     "shell_l2_p4_r1e9": (lambda: meshgen.cubed_sphere_shell(level=2, p=4), meshgen.problem_config2()),

@@ -243,7 +243,8 @@ def test_rhs_parity_with_mass_term(ctx):
 @pytest.mark.parametrize("name,smoother", [("cube_l2_p3", "none"), ("hp_k", "point"),
                                            ("shell_l2_p3_r1e3", "point"), ("hp_k", "block"),
                                            ("shell_l2_p3_r1e3", "block"), ("cube_l1_p6", "block"),
-                                           ("cube_l1_p7", "block")])
+                                           ("cube_l1_p7", "block"), ("hp_p2_7_k1", "point"),
+                                           ("box_macros_p2", "point")])
 def test_smoother_and_vcycle_parity(ctx, name, smoother):
     maker, prob = MESHES[name]
     m = maker()
@@ -267,8 +268,30 @@ def test_smoother_and_vcycle_parity(ctx, name, smoother):
     M.free()
 
 
+def test_element_centric_path_used(ctx):
+    # affine axis-aligned constant-k meshes run entirely element-centrically (the mortar kernel
+    # only for 2:1 faces); a variable-k mesh mixes the two paths; curved meshes use the element
+    # and mortar kernels only
+    for name, expect in (("cube_l2_p3", "all"), ("box_macros_p2", "all"), ("hp_p2_7_k1", "all+2:1"),
+                         ("hp_k", "mixed"), ("shell_l2_p3_r1e3", "none")):
+        maker, prob = MESHES[name]
+        M = ctx.upload(maker(), coef=coef_of(prob))
+        ec, tasks, ne = M.n_elem_centric, M.n_mortar_tasks, M.n_elem
+        print(name, "element-centric", ec, "of", ne, "mortar tasks", tasks, flush=True)
+        if expect == "all":
+            assert ec == ne and all(t == 0 for t in tasks)
+        elif expect == "all+2:1":
+            assert ec == ne and tasks[0] > 0
+        elif expect == "none":
+            assert all(v == 0 for v in ec) and tasks[0] > 0
+        else:
+            assert 0 < ec[0] < ne[0] and tasks[0] > 0
+        M.free()
+
+
 @pytest.mark.parametrize("name,smoother", [("shell_l2_p3_r1e3", "block"), ("cube_l1_p7", "block"),
-                                           ("shell_l2_p3_r1e3", "point")])
+                                           ("shell_l2_p3_r1e3", "point"), ("hp_k", "point"),
+                                           ("hp_p2_7_k1", "point"), ("box_macros_p2", "point")])
 def test_fused_block_step_matches_separate_kernels(ctx, name, smoother):
     # on one-degree levels each Jacobi-scaled Chebyshev step that needs A x runs as one kernel
     # per element; the arithmetic is the separate kernels' (the block partial sums may be
@@ -296,15 +319,21 @@ def test_fused_block_step_matches_separate_kernels(ctx, name, smoother):
             res[dt] = (np.concatenate(xs), host(z))
         launches = {k: M.kernel_timing(k, 0, hp.F64)[1] for k in ("smooth", "block")}
         M.timing_enable(0)
+        ec = M.n_elem_centric[0] > 0
         out[fused] = (res, launches)
         M.free()
     (rf, lf), (ru, lu) = out[True], out[False]
     print(name, "launches fused", lf, "separate", lu, flush=True)
-    # the fused path ran (smoothing from a given x, and every V-cycle step but the first of
-    # each pre-smoothing), the separate one never did
-    assert lf["smooth"] > 0 and lu["smooth"] == 0
-    if smoother == "block":
-        assert lu["block"] > lf["block"]
+    if ec and smoother == "block":
+        # element-centric levels fuse only the point-Jacobi step: block smoothing keeps the
+        # apply and the block step apart there
+        assert lf["smooth"] == 0 and lu["smooth"] == 0
+    else:
+        # the fused path ran (smoothing from a given x, and every V-cycle step but the first of
+        # each pre-smoothing), the separate one never did
+        assert lf["smooth"] > 0 and lu["smooth"] == 0
+        if smoother == "block":
+            assert lu["block"] > lf["block"]
     for dt, tol in ((torch.float64, 1e-13), (torch.float32, 1e-5)):
         ex, ez = rel(rf[dt][0], ru[dt][0]), rel(rf[dt][1], ru[dt][1])
         print(name, dt, "smooth", ex, "vcycle", ez, flush=True)
