@@ -67,7 +67,8 @@ struct DevLevel {
   int* felems = nullptr;      // element-centric apply: element ids grouped by n
   int* telems = nullptr;      // elements whose face traces the mortar kernel reads
   FaceLink* flink = nullptr;  // element-centric apply, group order: face records (6 per element),
-  long long* fe_off = nullptr;  // dof offsets and the diagonal metric (3 per element)
+  long long* fe_off = nullptr;  // dof offsets, face-trace offsets and the diagonal metric (3 per element)
+  long long* fe_toff = nullptr;
   T* fe_g = nullptr;
   T* fcoef = nullptr;         // face coefficient tuples
   // mass term (Newton linearisation): w det J c at the GL points, the diagonal of A
@@ -252,6 +253,7 @@ LevelView<T> hpdg_mesh::view(int l) const {
   v.mcoef = mass_on ? d.mcoef : nullptr;
   v.flink = d.flink;
   v.fe_off = d.fe_off;
+  v.fe_toff = d.fe_toff;
   v.fe_g = d.fe_g;
   v.fe_id = d.felems;
   v.fcoef = d.fcoef;
@@ -323,6 +325,7 @@ void build_device_level(hpdg_mesh* M, int l, hipStream_t s) {
   d.telems = M->upload_raw(h.trace_elems, s);
   d.flink = M->upload_raw(h.flink, s);
   d.fe_off = M->upload_raw(h.fast_off, s);
+  d.fe_toff = M->upload_raw(h.fast_toff, s);
   d.fe_g = M->upload<T>(h.fast_g, s);
   d.fcoef = M->upload<T>(h.fcoef, s);
   d.vgeo = M->upload<T>(h.vgeo, s);
@@ -424,7 +427,7 @@ void level_apply(hpdg_mesh* M, int l, const LevelView<T>& V, const T* x, T* y, h
     launch_traces<T>(V, x, s, d.telems, (long long)h.trace_elems.size());
     launch_faces<T>(V, s);
   }
-  for (size_t b = 0; b < h.fast_n.size(); ++b) launch_fast_apply<T>(V, fast_bucket<T>(M, l, b), x, y, s);
+  for (size_t b = h.fast_n.size(); b-- > 0;) launch_fast_apply<T>(V, fast_bucket<T>(M, l, b), x, y, s);
   for (size_t b = 0; b < h.bucket_n.size(); ++b)
     launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], d.belems + h.bucket_start[b],
                            h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
@@ -504,7 +507,7 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
           launch_traces<T>(V, xi, s, d.telems, (long long)h.trace_elems.size());
           launch_faces<T>(V, s);
         }
-        for (size_t bk = 0; bk < h.fast_n.size(); ++bk) launch_fast_cheb<T>(V, fast_bucket<T>(M, l, bk), xi, st, s);
+        for (size_t bk = h.fast_n.size(); bk-- > 0;) launch_fast_cheb<T>(V, fast_bucket<T>(M, l, bk), xi, st, s);
         for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
           launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], d.belems + h.bucket_start[bk],
                                      h.bucket_start[bk + 1] - h.bucket_start[bk], xi, bs, s);

@@ -30,6 +30,7 @@ struct LevelView {
   // (S, sigma, mn, mo)
   const FaceLink* flink;
   const long long* fe_off;
+  const long long* fe_toff;
   const T* fe_g;
   const int* fe_id;
   const T* fcoef;
@@ -105,7 +106,10 @@ struct FastBucket {
   const T* df;
 };
 // The element-centric apply (fastapply.hip) of one group: y = (A x) on its elements (the face
-// slots of their faces left to the mortar kernel written before), or the fused step st.
+// slots of their faces left to the mortar kernel written before), or the fused step st.  The
+// groups of a level run in descending degree: each writes the face traces that the groups of
+// lower degree read (faces between degrees).
+
 template <typename T>
 void launch_fast_apply(const LevelView<T>& L, const FastBucket<T>& fb, const T* x, T* y, hipStream_t s);
 template <typename T>

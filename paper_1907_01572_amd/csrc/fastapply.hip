@@ -121,92 +121,119 @@ __device__ __forceinline__ void neighbour_part(const LevelView<T>& L, const T* _
   q2 = T(0.5) * S * mn * uo;
 }
 
-// Face terms of the two faces normal to axis d, added to F (the thread's line along d, nodes
-// m = 0..N-1) from the thread's line u of the element; the thread holds face node (a, b) of
-// both faces; q1, q2: the neighbour parts of same-degree faces (neighbour_part).  MIX:
-// neighbours of another degree go through the projection P, staged in the element's scratch
-// (all threads of the workgroup call this; it synchronises twice).
-template <typename T, int N, bool MIX>
-__device__ __forceinline__ void faces_along(const LevelView<T>& L, const T* __restrict__ tab, const T* __restrict__ x,
-                                            const T* __restrict__ df, const FaceLink (&fl)[2], const T (&q1)[2],
-                                            const T (&q2)[2], int a, int b, bool act, const T (&u)[N], T (&F)[N],
-                                            T* scr, int nx) {
+// Neighbours of another degree nn on the two faces normal to axis d (mixed-degree groups): their
+// face data at their nn^2 nodes in this side's axes, then the projection P (N x nn) along b and
+// along a, into q1, q2 (as neighbour_part).  A neighbour of higher degree is read from the face
+// trace it wrote (2 scalars per node), one of lower degree from its coefficients (one node per
+// thread).  Every thread of the workgroup calls this; it synchronises twice.
+template <typename T, int N>
+__device__ __forceinline__ void mixed_parts(const LevelView<T>& L, const T* __restrict__ tab, const T* __restrict__ x,
+                                            const FaceLink* fl, int a, int b, bool act, T* scr, int nx, T* q1, T* q2) {
   constexpr int N2 = N * N;
   const int lt = a + N * b;
-  T Pa[2] = {q1[0], q1[1]}, Pb[2] = {q2[0], q2[1]};
-  if constexpr (MIX) {
-    // neighbours of another degree nn: their face data at their nn^2 nodes (this side's axes),
-    // then P (N x nn) along b and along a
-    const int psz = 2 * nx * nx + 2 * nx * N;
+  const int psz = 2 * nx * nx + 2 * nx * N;
 #pragma unroll
-    for (int fi = 0; fi < 2; ++fi) {
-      const int meta = fl[fi].meta, nn = (meta >> 2) & 31;
-      if (act && (meta & 3) == 1 && !L.self_only && nn != N) {
-        const int nf = (meta >> 7) & 7, map = (meta >> 10) & 7;
-        const T* cf = L.fcoef + 4 * fl[fi].coef;
-        const T sig = cf[1], mo = cf[3];
-        const T* dfo = tab + L.tv.dface_off[nn] + (nf & 1) * nn;
-        T* Ga = scr + fi * psz;
-        T* Gb = Ga + nx * nx;
+  for (int fi = 0; fi < 2; ++fi) {
+    const int meta = fl[fi].meta, nn = (meta >> 2) & 31;
+    if (act && (meta & 3) == 1 && !L.self_only && nn != N) {
+      const int nf = (meta >> 7) & 7, map = (meta >> 10) & 7;
+      const T* cf = L.fcoef + 4 * fl[fi].coef;
+      const T sig = cf[1], mo = cf[3];
+      T* Ga = scr + fi * psz;
+      T* Gb = Ga + nx * nx;
+      if (nn > N) {
+        const T* __restrict__ nt = L.trace + fl[fi].nb;
+#pragma unroll 4
         for (int g = lt; g < nn * nn; g += N2) {
           const int ga = g % nn, gb = g / nn;
           int ia, ib;
           map_node(map, nn, ga, gb, ia, ib);
-          T uo, dno;
-          neighbour_trace_rt(x + fl[fi].nb, dfo, nn, nf, ia, ib, uo, dno);
+          const T uo = nt[ia + nn * ib], dno = nt[nn * nn + ia + nn * ib];
           Ga[g] = sig * uo - T(0.5) * mo * dno;
           Gb[g] = uo;
         }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int fi = 0; fi < 2; ++fi) {
-      const int meta = fl[fi].meta, nn = (meta >> 2) & 31;
-      if (act && (meta & 3) == 1 && !L.self_only && nn != N) {
-        const T* P = tab + L.tv.off[(kProj * (kMaxN + 1) + nn) * (kMaxQ + 1) + N];  // [N][nn]
-        const T* Ga = scr + fi * psz;
-        const T* Gb = Ga + nx * nx;
-        T* Ta = scr + fi * psz + 2 * nx * nx;
-        T* Tb = Ta + nx * N;
-        for (int g = lt; g < nn * N; g += N2) {  // T[ga][j] = sum_gb P[j][gb] G[ga][gb]
-          const int ga = g % nn, j = g / nn;
-          T sa = 0, sb = 0;
-          for (int gb = 0; gb < nn; ++gb) {
-            const T pv = P[j * nn + gb];
-            sa += pv * Ga[ga + nn * gb];
-            sb += pv * Gb[ga + nn * gb];
-          }
-          Ta[g] = sa;
-          Tb[g] = sb;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int fi = 0; fi < 2; ++fi) {
-      const int meta = fl[fi].meta, nn = (meta >> 2) & 31;
-      if (act && (meta & 3) == 1 && !L.self_only && nn != N) {
-        const T* P = tab + L.tv.off[(kProj * (kMaxN + 1) + nn) * (kMaxQ + 1) + N];
-        const T* Ta = scr + fi * psz + 2 * nx * nx;
-        const T* Tb = Ta + nx * N;
-        T sa = 0, sb = 0;
-        for (int ga = 0; ga < nn; ++ga) {
-          const T pv = P[a * nn + ga];
-          sa += pv * Ta[ga + nn * b];
-          sb += pv * Tb[ga + nn * b];
-        }
-        const T* cf = L.fcoef + 4 * fl[fi].coef;
-        Pa[fi] = -cf[0] * sa;
-        Pb[fi] = T(0.5) * cf[0] * cf[2] * sb;
+      } else if (lt < nn * nn) {
+        const int ga = lt % nn, gb = lt / nn;
+        int ia, ib;
+        map_node(map, nn, ga, gb, ia, ib);
+        const int d = nf >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const T* p = x + fl[fi].nb + vidx(nn, d, t0, t1, 0, ia, ib);
+        const int sd = d == 0 ? 1 : (d == 1 ? nn : nn * nn);
+        const T* dfo = tab + L.tv.dface_off[nn] + (nf & 1) * nn;
+        const T uo = p[((nf & 1) ? nn - 1 : 0) * sd];
+        T dno = 0;
+#pragma unroll 4
+        for (int m = 0; m < nn; ++m) dno += dfo[m] * p[m * sd];
+        Ga[lt] = sig * uo - T(0.5) * mo * dno;
+        Gb[lt] = uo;
       }
     }
   }
+  __syncthreads();
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi) {
+    const int meta = fl[fi].meta, nn = (meta >> 2) & 31;
+    if (act && (meta & 3) == 1 && !L.self_only && nn != N) {
+      const T* P = tab + L.tv.off[(kProj * (kMaxN + 1) + nn) * (kMaxQ + 1) + N];  // [N][nn]
+      const T* Ga = scr + fi * psz;
+      const T* Gb = Ga + nx * nx;
+      T* Ta = scr + fi * psz + 2 * nx * nx;
+      T* Tb = Ta + nx * N;
+      for (int g = lt; g < nn * N; g += N2) {  // T[ga][j] = sum_gb P[j][gb] G[ga][gb]
+        const int ga = g % nn, j = g / nn;
+        T sa = 0, sb = 0;
+#pragma unroll 4
+        for (int gb = 0; gb < nn; ++gb) {
+          const T pv = P[j * nn + gb];
+          sa += pv * Ga[ga + nn * gb];
+          sb += pv * Gb[ga + nn * gb];
+        }
+        Ta[g] = sa;
+        Tb[g] = sb;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int fi = 0; fi < 2; ++fi) {
+    const int meta = fl[fi].meta, nn = (meta >> 2) & 31;
+    if (act && (meta & 3) == 1 && !L.self_only && nn != N) {
+      const T* P = tab + L.tv.off[(kProj * (kMaxN + 1) + nn) * (kMaxQ + 1) + N];
+      const T* Ta = scr + fi * psz + 2 * nx * nx;
+      const T* Tb = Ta + nx * N;
+      T sa = 0, sb = 0;
+#pragma unroll 4
+      for (int ga = 0; ga < nn; ++ga) {
+        const T pv = P[a * nn + ga];
+        sa += pv * Ta[ga + nn * b];
+        sb += pv * Tb[ga + nn * b];
+      }
+      const T* cf = L.fcoef + 4 * fl[fi].coef;
+      q1[fi] = -cf[0] * sa;
+      q2[fi] = T(0.5) * cf[0] * cf[2] * sb;
+    }
+  }
+}
+
+// Face terms of the two faces normal to axis d, added to F (the thread's line along d, nodes
+// m = 0..N-1) from the thread's line u of the element; the thread holds face node (a, b) of
+// both faces; q1, q2: the neighbour parts (neighbour_part, mixed_parts).
+template <typename T, int N>
+__device__ __forceinline__ void faces_along(const LevelView<T>& L, const T* __restrict__ tab, const T* __restrict__ x,
+                                            const T* __restrict__ df, const FaceLink* fl, const T* q1m,
+                                            const T* q2m, int a, int b, bool act, const T (&u)[N], T (&F)[N]) {
   if (!act) return;
 #pragma unroll
   for (int fi = 0; fi < 2; ++fi) {
     const int kind = fl[fi].meta & 3;
     if (kind != 1 && kind != 2) continue;
+    // the neighbour's part: same degree read here, another degree from mixed_parts
+    T q1, q2;
+    neighbour_part<T, N>(L, tab, x, fl[fi], a, b, q1, q2);
+    if (q1m) {
+      q1 += q1m[fi];
+      q2 += q2m[fi];
+    }
     const T* cf = L.fcoef + 4 * fl[fi].coef;
     const T S = cf[0], sig = cf[1], mn = cf[2];
     const T* dfs = df + fi * N;
@@ -217,18 +244,60 @@ __device__ __forceinline__ void faces_along(const LevelView<T>& L, const T* __re
     for (int m = 0; m < N; ++m) dns += dfs[m] * u[m];
     const T h = kind == 1 ? T(0.5) : T(1);
     const T Smn = S * mn;
-    const T A = S * sig * us - h * Smn * dns + Pa[fi];
-    const T B = -h * Smn * us + Pb[fi];
+    const T A = S * sig * us - h * Smn * dns + q1;
+    const T B = -h * Smn * us + q2;
     F[layer] += A;
 #pragma unroll
     for (int m = 0; m < N; ++m) F[m] += dfs[m] * B;
   }
 }
 
+// LDS layout of an element's exchange buffers: node (i, j, k) at i + P1 j + P2 k, three buffers
+// of P2 n scalars, elements ES scalars apart.  The strides are chosen (by a search over small
+// paddings) so that the three exchange patterns (lines along z, x and y spread over the lanes)
+// meet few bank conflicts in groups of 16 lanes of 8 bytes: the unpadded layout puts a line
+// along x at a stride of n scalars, a 16-way conflict for n = 8.
+struct Pad {
+  int p1, p2, es;
+};
+template <int N>
+constexpr Pad fast_pad() {
+  return N == 2 ? Pad{2, 5, 36}
+       : N == 3 ? Pad{3, 9, 91}
+       : N == 4 ? Pad{4, 19, 228}
+       : N == 5 ? Pad{5, 25, 377}
+       : N == 6 ? Pad{6, 36, 648}
+       : N == 7 ? Pad{7, 49, 1029}
+                : Pad{9, 72, 1728};
+}
+// projection scratch of a mixed-degree group (two faces at the largest neighbour degree), and
+// whether it fits in the exchange buffers (free while the projections run, before the volume
+// passes); otherwise it follows them
+template <int N>
+constexpr int fast_scr_scalars() {
+  constexpr int nx = kFastMaxN + 1;
+  return 2 * (2 * nx * nx + 2 * nx * N);
+}
+template <int N>
+constexpr bool fast_scr_shared() { return fast_scr_scalars<N>() <= 3 * fast_pad<N>().p2 * N; }
+// scalars per element: the exchange buffers and a separate projection scratch when needed (kept a
+// multiple of 16 scalars so the element stride keeps its bank offset)
+template <int N, bool MIX>
+constexpr int fast_elem_scalars() {
+  constexpr int scr = MIX && !fast_scr_shared<N>() ? fast_scr_scalars<N>() : 0;
+  return fast_pad<N>().es + (scr + 15) / 16 * 16;
+}
+
+// at least this many waves per SIMD: the register budget of each instantiation (uniform-degree
+// groups: 128 VGPRs; mixed-degree groups, which hold the projection stage's state: 168, and 256
+// from p = 5 up)
+template <int N, bool MIX>
+constexpr int fast_waves() { return MIX ? (N >= 6 ? 2 : 3) : 4; }
+
 template <typename T, int N, bool MIX, bool FUSE>
-__global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> fb, const T* __restrict__ x,
+__global__ void __launch_bounds__(64, (fast_waves<N, MIX>())) fast_kernel(LevelView<T> L, FastBucket<T> fb, const T* __restrict__ x,
                                                   T* __restrict__ y, FastStep<T> st) {
-  constexpr int N2 = N * N, N3 = N2 * N;
+  constexpr int N2 = N * N;
   constexpr int EPW = N2 <= 64 ? 64 / N2 : 1;
   extern __shared__ unsigned char smem_raw[];
   T* smem = reinterpret_cast<T*>(smem_raw);
@@ -240,11 +309,15 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
   const long long loc = (long long)xcd_remap(blockIdx.x, gridDim.x) * EPW + es;
   const bool act = es < EPW && loc < fb.count;
   const long long gi = fb.start + (act ? loc : 0);
-  const int psz = MIX ? 2 * nx * nx + 2 * nx * N : 0;
-  T* B0 = smem + (act ? es : 0) * (3 * N3 + 2 * psz);
-  T* B1 = B0 + N3;
-  T* B2 = B1 + N3;
-  T* scr = B2 + N3;
+  constexpr Pad PD = fast_pad<N>();
+  constexpr int P1 = PD.p1, P2 = PD.p2, BS = P2 * N;
+  T* B0 = smem + (act ? es : 0) * fast_elem_scalars<N, MIX>();
+  T* B1 = B0 + BS;
+  T* B2 = B1 + BS;
+  T* scr = fast_scr_shared<N>() ? B0 : B2 + BS;
+  const int zi = li + P1 * lj;  // z line of thread (i, j): zi + P2 k
+  const int xi = P1 * li + P2 * lj;  // x line of thread (j, k): xi + i
+  const int yi = li + P2 * lj;  // y line of thread (i, k): yi + P1 j
   const T* __restrict__ M1 = fb.M1;
   const T* __restrict__ K1 = fb.K1;
   const T* __restrict__ df = fb.df;
@@ -262,29 +335,48 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
 #pragma unroll
     for (int f = 0; f < 6; ++f) fl[f] = L.flink[6 * gi + f];
   }
-  T u[N];
+  T q1[6], q2[6];  // mixed-degree groups: the parts of neighbours of another degree
 #pragma unroll
-  for (int k = 0; k < N; ++k) u[k] = act ? x[off + lt + N2 * k] : T(0);
-  T q1[6], q2[6];
+  for (int f = 0; f < 6; ++f) q1[f] = q2[f] = 0;
+  if constexpr (MIX) {
+    // this element's face traces for its neighbours of lower degree (read by their groups,
+    // launched after this one): the value and the normal derivative at face node (li, lj)
+    if (act) {
+      T* const trb = L.trace + L.fe_toff[gi];
 #pragma unroll
-  for (int f = 0; f < 6; ++f) {
-    if (act)
-      neighbour_part<T, N>(L, tab, x, fl[f], li, lj, q1[f], q2[f]);
-    else
-      q1[f] = q2[f] = 0;
+      for (int f = 0; f < 6; ++f) {
+        if (!(fl[f].meta & (1 << 13))) continue;
+        const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+        const T* p = x + off + vidx(N, d, t0, t1, 0, li, lj);
+        const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
+        const T* dfs = df + (f & 1) * N;
+        T dn = 0;
+#pragma unroll
+        for (int m = 0; m < N; ++m) dn += dfs[m] * p[m * sd];
+        trb[2 * f * N2 + lt] = p[((f & 1) ? N - 1 : 0) * sd];
+        trb[(2 * f + 1) * N2 + lt] = dn;
+      }
+    }
+    // neighbours of another degree, all six faces before the volume passes (the face node of a
+    // thread is (li, lj) on every face)
+#pragma unroll
+    for (int d = 0; d < 3; ++d) mixed_parts<T, N>(L, tab, x, fl + 2 * d, li, lj, act, scr, nx, q1 + 2 * d, q2 + 2 * d);
+    __syncthreads();  // the scratch may be the exchange buffers
   }
 
   // ---- z: lines along z (thread (i, j)) ----
-  T c[N];
+  T u[N], c[N];
+#pragma unroll
+  for (int k = 0; k < N; ++k) u[k] = act ? x[off + lt + N2 * k] : T(0);
   pass<T, N>(K1, u, c);
 #pragma unroll
   for (int k = 0; k < N; ++k) c[k] *= g2;
-  faces_along<T, N, MIX>(L, tab, x, df, {fl[4], fl[5]}, {q1[4], q1[5]}, {q2[4], q2[5]}, li, lj, act, u, c, scr, nx);
+  faces_along<T, N>(L, tab, x, df, fl + 4, MIX ? q1 + 4 : nullptr, q2 + 4, li, lj, act, u, c);
   if (act) {
 #pragma unroll
     for (int k = 0; k < N; ++k) {
-      B0[lt + N2 * k] = u[k];
-      B1[lt + N2 * k] = c[k];
+      B0[zi + P2 * k] = u[k];
+      B1[zi + P2 * k] = c[k];
     }
   }
   __syncthreads();
@@ -294,22 +386,21 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
     T ux[N], cx[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      ux[i] = act ? B0[i + N * lt] : T(0);
-      cx[i] = act ? B1[i + N * lt] : T(0);
+      ux[i] = act ? B0[xi + i] : T(0);
+      cx[i] = act ? B1[xi + i] : T(0);
     }
     pass<T, N>(K1, ux, w1);
 #pragma unroll
     for (int i = 0; i < N; ++i) w1[i] *= g0;
-    faces_along<T, N, MIX>(L, tab, x, df, {fl[0], fl[1]}, {q1[0], q1[1]}, {q2[0], q2[1]}, li, lj, act, ux, w1, scr,
-                           nx);
+    faces_along<T, N>(L, tab, x, df, fl, MIX ? q1 : nullptr, q2, li, lj, act, ux, w1);
     pass<T, N>(M1, cx, v1);
   }
   __syncthreads();
   if (act) {
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      B1[i + N * lt] = w1[i];
-      B2[i + N * lt] = v1[i];
+      B1[xi + i] = w1[i];
+      B2[xi + i] = v1[i];
     }
   }
   __syncthreads();
@@ -319,7 +410,7 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
     T uy[N], w1y[N], v1y[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
-      const int idx = li + N * j + N2 * lj;
+      const int idx = yi + P1 * j;
       uy[j] = act ? B0[idx] : T(0);
       w1y[j] = act ? B1[idx] : T(0);
       v1y[j] = act ? B2[idx] : T(0);
@@ -329,13 +420,12 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
     pass<T, N>(K1, uy, w2);
 #pragma unroll
     for (int j = 0; j < N; ++j) w2[j] *= g1;
-    faces_along<T, N, MIX>(L, tab, x, df, {fl[2], fl[3]}, {q1[2], q1[3]}, {q2[2], q2[3]}, li, lj, act, uy, w2, scr,
-                           nx);
+    faces_along<T, N>(L, tab, x, df, fl + 2, MIX ? q1 + 2 : nullptr, q2 + 2, li, lj, act, uy, w2);
   }
   __syncthreads();
   if (act) {
 #pragma unroll
-    for (int j = 0; j < N; ++j) B0[li + N * j + N2 * lj] = w2[j];
+    for (int j = 0; j < N; ++j) B0[yi + P1 * j] = w2[j];
   }
   __syncthreads();
   // ---- x: M_x of the y-face term ----
@@ -343,16 +433,16 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
   {
     T w2x[N];
 #pragma unroll
-    for (int i = 0; i < N; ++i) w2x[i] = act ? B0[i + N * lt] : T(0);
+    for (int i = 0; i < N; ++i) w2x[i] = act ? B0[xi + i] : T(0);
     pass<T, N>(M1, w2x, t3);
   }
   __syncthreads();
   if (act) {
 #pragma unroll
     for (int m = 0; m < N; ++m) {
-      B0[m + N * lt] = t3[m];
-      B1[li + N * m + N2 * lj] = t2[m];
-      B2[li + N * m + N2 * lj] = ya[m];
+      B0[xi + m] = t3[m];
+      B1[yi + P1 * m] = t2[m];
+      B2[yi + P1 * m] = ya[m];
     }
   }
   __syncthreads();
@@ -362,10 +452,10 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
   {
     T sm[N];
 #pragma unroll
-    for (int k = 0; k < N; ++k) sm[k] = B1[lt + N2 * k] + B0[lt + N2 * k];
+    for (int k = 0; k < N; ++k) sm[k] = B1[zi + P2 * k] + B0[zi + P2 * k];
     pass<T, N>(M1, sm, acc);
 #pragma unroll
-    for (int k = 0; k < N; ++k) acc[k] += B2[lt + N2 * k];
+    for (int k = 0; k < N; ++k) acc[k] += B2[zi + P2 * k];
   }
   bool slots = false;
 #pragma unroll
@@ -415,10 +505,9 @@ __global__ void __launch_bounds__(64) fast_kernel(LevelView<T> L, FastBucket<T> 
 template <typename T, int N, bool MIX, bool FUSE>
 void launch_n(const LevelView<T>& L, const FastBucket<T>& fb, const T* x, T* y, const FastStep<T>& st,
               hipStream_t s) {
-  constexpr int N2 = N * N, N3 = N2 * N;
+  constexpr int N2 = N * N;
   constexpr int EPW = N2 <= 64 ? 64 / N2 : 1;
-  const int psz = MIX ? 2 * fb.nx * fb.nx + 2 * fb.nx * N : 0;
-  const size_t lds = size_t(EPW) * size_t(3 * N3 + 2 * psz) * sizeof(T);
+  const size_t lds = size_t(EPW) * size_t(fast_elem_scalars<N, MIX>()) * sizeof(T);
   const long long groups = (fb.count + EPW - 1) / EPW;
   hipLaunchKernelGGL((fast_kernel<T, N, MIX, FUSE>), dim3(unsigned(groups)), dim3(64), lds, s, L, fb, x, y, st);
 }

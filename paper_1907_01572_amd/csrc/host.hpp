@@ -94,8 +94,10 @@ struct MortarTask {
 
 // one face of an element of the element-centric apply (fastapply.hip)
 struct FaceLink {
-  long long nb;  // kind 1: the neighbour's dof offset
+  long long nb;  // kind 1: the neighbour's dof offset, or (neighbour of higher degree) the offset
+                 // of the face trace it writes (values nn^2, normal derivatives nn^2)
   int meta;      // kind | neighbour n << 2 | neighbour face << 7 | frame map << 10 (swap, flipA, flipB)
+                 // | 1 << 13 when the neighbour has a lower degree (this side writes its face trace)
                  // kind 0: no operator term; 1: interior, both sides read here; 2: boundary
                  // (Dirichlet or Robin); 3: the mortar kernel's lifted terms (face slots)
   int coef;      // kinds 1, 2: index of (S, sigma, own and neighbour normal coefficient) in the

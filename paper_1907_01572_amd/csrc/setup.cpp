@@ -585,8 +585,11 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
         if (side == 1 && swp) std::swap(fa, fb);
         const int other = side == 0 ? MI.ep : MI.em;
         const int nf = side == 0 ? MI.fp : MI.fm;
-        fl.nb = L.einfo[size_t(other)].off;
-        fl.meta = 1 | (L.einfo[size_t(other)].n << 2) | (nf << 7) | ((swp | (fa << 1) | (fb << 2)) << 10);
+        const ElemInfo& O = L.einfo[size_t(other)];
+        // a neighbour of higher degree is read through the face trace it writes (value and
+        // normal derivative at its face nodes, 2 nn^2 scalars) instead of its whole element
+        fl.nb = O.n > I.n ? O.toff + 2LL * nf * O.n * O.n : O.off;
+        fl.meta = 1 | (O.n << 2) | (nf << 7) | ((swp | (fa << 1) | (fb << 2)) << 10) | (O.n < I.n ? 1 << 13 : 0);
       }
     }
   }
@@ -620,11 +623,13 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     // group order: face records, dof offsets and the diagonal metric of each fast element
     std::vector<FaceLink> byg(kf.size() * 6);
     L.fast_off.assign(kf.size(), 0);
+    L.fast_toff.assign(kf.size(), 0);
     L.fast_g.assign(3 * kf.size(), 0.0);
     for (size_t i = 0; i < kf.size(); ++i) {
       const size_t e = size_t(kf[i].second);
       for (int f = 0; f < 6; ++f) byg[6 * i + f] = L.flink[6 * e + f];
       L.fast_off[i] = L.einfo[e].off;
+      L.fast_toff[i] = L.einfo[e].toff;
       const double* G = L.vgeo.data() + L.einfo[e].vgeo;
       L.fast_g[3 * i] = G[0];
       L.fast_g[3 * i + 1] = G[3];

@@ -66,6 +66,7 @@ struct LevelHost {
   std::vector<unsigned char> fast;
   std::vector<FaceLink> flink;       // group order (fast_elems), 6 per element
   std::vector<long long> fast_off;   // group order: dof offset
+  std::vector<long long> fast_toff;  // group order: face-trace offset (faces to lower degrees)
   std::vector<double> fast_g;        // group order: G00, G11, G22
   std::vector<double> fcoef;
   std::vector<int> fast_n, fast_nx;
