@@ -36,6 +36,13 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # --summarize-traffic; valid only while the kernel sources hash to the recorded value
 TRAFFIC_FILE = os.path.join("profiles", "solve_hp_hbm_traffic.txt")
 APPLY_ALL_BUCKETS = "trace_kernel<double> + apply_kernel<double, n, q, false> (one launch per degree bucket)"
+# the operator apply of a level with element-centric groups: one fast_kernel launch per degree
+# (descending), and for the cells it does not cover (variable k, 2:1 faces) the face traces, the
+# mortar kernel and the element kernel per (n, q) bucket
+APPLY_EC = ("fast_kernel<double, n, mixed, false> per degree + trace_kernel<double> + mortar_kernel<double> + "
+            "apply_kernel<double, n, q, false> per bucket")
+SMOOTH_EC = ("fast_kernel<double, n, mixed, true> per degree + trace_kernel<double> + mortar_kernel<double> + "
+             "apply_kernel<double, n, q, true> per bucket (fused point-Jacobi Chebyshev step)")
 KERNEL_SOURCES = [os.path.join("paper_1907_01572_amd", "csrc", f)
                   for f in ("apply.hip", "fastapply.hip", "apply_common.hpp", "kernels.hip", "blocks.hpp", "device.hpp",
                             "host.hpp")]
@@ -189,7 +196,8 @@ def make_workload(args, meshgen, hp):
         w["mesh"] = meshgen.hp_sphere_cube()
         w["prob"] = meshgen.problem_config3()
         w["upload"] = dict(coef=hp.coef_from_problem(w["prob"]), build_f32=True)
-        w["smoother"] = dict(n_cheb=args.n_cheb or 4, smoother=args.smoother or "point", Lambda=args.Lambda or 20.0)
+        # Chebyshev degree 6 (41 FCG iterations) is the fastest of a sweep over 3..12 and Lambda 10..30
+        w["smoother"] = dict(n_cheb=args.n_cheb or 6, smoother=args.smoother or "point", Lambda=args.Lambda or 20.0)
         w["desc"] = ("[-1,1]^3, 32^3 cells, p~U{2..7} (seed 0), cells cut by r=0.5 refined 2:1, k=1|5 across "
                      "r=0.5, -div(k grad u)=-6, MG-FCG to 1e-10")
     else:
@@ -202,24 +210,6 @@ def make_workload(args, meshgen, hp):
         w["desc"] = ("cube [-10,10]^3 + cube-to-sphere + compactified shell to 1e11 (13 macros), refined 5x "
                      "around 3 seeded punctures, p=6, -lap u = beta (1 + alpha u)^-7, Newton-Krylov to 1e-10")
     return w
-
-
-def apply_flops(M, W, level=0):
-    """FP64 flops of one apply of ``level`` as the kernels compute it (an FMA is 2 flops): per
-    element the sum-factorised volume passes (three interpolations to the GL points, the GL
-    collocation derivative, the metric contraction and the transposed passes), and per face the
-    mortar interpolation of both sides, the flux and the transposed lift (neighbours taken of
-    the element's own degree, the mortar rule of the volume's).  q = n on affine elements with a
-    constant k and no mass term, n + 1 otherwise (the library's rule)."""
-    cells = M.level_cells(level)
-    n = cells["elem_p"].astype(np.float64) + 1.0
-    up = W["upload"]
-    kconst = up.get("coef") is None or up["coef"][0] == 0
-    affine = np.asarray(W["mesh"]["macro_kind"])[cells["elem_macro"]] == 0
-    q = n + np.where(affine & kconst & (not up.get("mass_term", False)), 0.0, 1.0)
-    vol = 2 * (n ** 3 * q + n ** 2 * q ** 2 + n * q ** 3) + 6 * q ** 4 + 9 * q ** 3
-    face = 6 * (9 * n ** 2 * q + 12 * n * q ** 2 + 20 * q ** 2)
-    return float(2.0 * np.sum(vol + face))
 
 
 def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
@@ -312,7 +302,7 @@ def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
     ms0_32, n0_32, b0_32 = t32["apply"][0]
     apply_ms64 = ms0 / n0
     apply_ms32 = ms0_32 / n0_32 if n0_32 else float("nan")
-    flops = apply_flops(M, W, 0)
+    flops = M.apply_flops[0]
     res = {
         "M": M, "N": N, "lam": lam, "setup_s": setup_s, "elapsed": elapsed, "iters": iters, "lat": lat,
         "solves_per_s": steps / elapsed, "ms_per_step": elapsed * 1e3 / steps, "t64": t64, "kernels": kernels,
@@ -427,8 +417,7 @@ def main():
     names = ({"apply": "apply_kernel<double, 6, 7, true, false>", "block": "block_sym_kernel<double, double, true>",
               "smooth": "apply_kernel<double, 6, 7, true, true>"}
              if args.workload == "shell" else
-             {"apply": APPLY_ALL_BUCKETS,
-              "block": "block_sym_kernel<double, double, true>", "smooth": "apply_kernel<double, n, q, true, true>"})
+             {"apply": APPLY_EC, "block": "block_sym_kernel<double, double, true>", "smooth": SMOOTH_EC})
     R = run_solves(args, W, hp, ctx, args.steps, args.warmup, names)
     M, N, kernels, t64 = R["M"], R["N"], R["kernels"], R["t64"]
     dom = max(kernels, key=lambda k: kernels[k]["total_ms"])
@@ -712,8 +701,7 @@ def run_sweep(args, meshgen, hp):
         up = time.time() - t0
         row = {"p": p, "macros": Mm, "level": level, "elements": M.n_elem[0], "dof": M.n_dof[0],
                "cells_per_axis": Mm * 2 ** level, "upload_s": round(up, 1)}
-        W = {"upload": {}, "mesh": mesh}
-        flops = apply_flops(M, W, 0)
+        flops = M.apply_flops[0]
         for dt, tag, sc in ((torch.float64, "f64", 8), (torch.float32, "f32", 4)):
             x = torch.randn(M.n_dof[0], dtype=dt, device="cuda")
             y = torch.zeros_like(x)

@@ -129,7 +129,13 @@ typedef struct {
  *               element.  Needed by the nonlinear calls.
  *   robin_gamma gamma of the Robin faces (macro face kind HPDG_BC_ROBIN): the operator gains
  *               int gamma u v on them (Eq. lh) and the right-hand side int g_R v.
+ *   ec_mode     element-centric apply (elements with an affine axis-aligned map, constant k and
+ *               no mass term): HPDG_EC_AUTO on levels with at least 4096 such elements (one
+ *               degree) or 16384 (several degrees; below these the launches are latency bound),
+ *               HPDG_EC_ALWAYS wherever an element qualifies, HPDG_EC_NEVER nowhere.  The
+ *               operator is the same up to rounding either way.
  */
+enum { HPDG_EC_AUTO = 0, HPDG_EC_ALWAYS = 1, HPDG_EC_NEVER = 2 };
 typedef struct {
   double penalty_C;
   int32_t quad_extra;
@@ -139,6 +145,7 @@ typedef struct {
   int32_t build_f32;
   int32_t mass_term;
   double robin_gamma;
+  int32_t ec_mode;
 } hpdg_disc_params;
 
 typedef struct {
@@ -160,6 +167,11 @@ typedef struct {
    * stiffness matrices, neighbours read directly) and mortars left to the mortar kernel */
   int64_t n_elem_centric[32];
   int64_t n_mortar_tasks[32];
+  /* FP64 (or FP32) operations of one apply per level as its kernels compute it (an FMA counts
+   * two): element-centric elements 8 n^4 FMAs of the 1-D passes plus n^2 (3n + 6) per face;
+   * the others the sum-factorised passes through the q GL points and the metric contraction,
+   * plus the mortar interpolations and lifts of their faces */
+  double apply_flops[32];
 } hpdg_mesh_info;
 
 /* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters.

@@ -57,7 +57,7 @@ class DiscParams(ctypes.Structure):
     _fields_ = [("penalty_C", ctypes.c_double), ("quad_extra", ctypes.c_int32),
                 ("coef_kind", ctypes.c_int32), ("coef_params", ctypes.c_double * 4),
                 ("max_levels", ctypes.c_int32), ("build_f32", ctypes.c_int32), ("mass_term", ctypes.c_int32),
-                ("robin_gamma", ctypes.c_double)]
+                ("robin_gamma", ctypes.c_double), ("ec_mode", ctypes.c_int32)]
 
 
 class MeshInfo(ctypes.Structure):
@@ -66,7 +66,8 @@ class MeshInfo(ctypes.Structure):
                 ("vgeo_scalars", ctypes.c_int64 * 32), ("mgeo_scalars", ctypes.c_int64 * 32),
                 ("table_bytes", ctypes.c_int64 * 32), ("device_bytes", ctypes.c_size_t),
                 ("block_retries", ctypes.c_int32), ("coarse_retries", ctypes.c_int32),
-                ("n_elem_centric", ctypes.c_int64 * 32), ("n_mortar_tasks", ctypes.c_int64 * 32)]
+                ("n_elem_centric", ctypes.c_int64 * 32), ("n_mortar_tasks", ctypes.c_int64 * 32),
+                ("apply_flops", ctypes.c_double * 32)]
 
 
 class SmootherParams(ctypes.Structure):
@@ -195,10 +196,12 @@ class Context:
         return rc
 
     def upload(self, mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False,
-               stream=None, mass_term=False, robin_gamma=0.0):
+               stream=None, mass_term=False, robin_gamma=0.0, ec_mode=None):
         """``mass_term``: levels carry the Newton mass form (needed by the nonlinear calls);
-        ``robin_gamma``: gamma of the Robin faces (macro face kind 3)."""
-        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term, robin_gamma)
+        ``robin_gamma``: gamma of the Robin faces (macro face kind 3); ``ec_mode``: EC_AUTO,
+        EC_ALWAYS or EC_NEVER (None: EC_MODE_DEFAULT)."""
+        return Mesh(self, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term, robin_gamma,
+                    ec_mode)
 
     def close(self):
         if self.h:
@@ -221,8 +224,14 @@ def coef_from_problem(problem):
     return COEF_CONSTANT, [0.0] * 4
 
 
+# element-centric apply (hpdg_disc_params.ec_mode): by level, always, never
+EC_AUTO, EC_ALWAYS, EC_NEVER = 0, 1, 2
+# the mode of uploads that do not name one
+EC_MODE_DEFAULT = EC_AUTO
+
+
 def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, build_f32=False, mass_term=False,
-                 robin_gamma=0.0):
+                 robin_gamma=0.0, ec_mode=None):
     """C descriptors of a meshgen mesh; returns (MeshDesc, DiscParams, arrays to keep alive)."""
     keep = dict(
         macro_kind=np.ascontiguousarray(mesh["macro_kind"], np.int32),
@@ -251,6 +260,7 @@ def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, bu
     dp.build_f32 = 1 if build_f32 else 0
     dp.mass_term = 1 if mass_term else 0
     dp.robin_gamma = robin_gamma
+    dp.ec_mode = EC_MODE_DEFAULT if ec_mode is None else ec_mode
     return d, dp, keep
 
 
@@ -319,10 +329,10 @@ class Mesh:
     """An uploaded mesh: level hierarchy, geometry and solver state on the device."""
 
     def __init__(self, ctx, mesh, penalty_C, quad_extra, coef, max_levels, build_f32, stream, mass_term=False,
-                 robin_gamma=0.0):
+                 robin_gamma=0.0, ec_mode=None):
         self.ctx, self.lib = ctx, ctx.lib
         d, dp, self._keep = _descriptors(mesh, penalty_C, quad_extra, coef, max_levels, build_f32, mass_term,
-                                         robin_gamma)
+                                         robin_gamma, ec_mode)
         self.h = ctypes.c_void_p()
         ctx.check(self.lib.hpdg_mesh_upload(ctx.h, ctypes.byref(d), ctypes.byref(dp),
                                             ctypes.byref(self.h), _stream(stream)))
@@ -345,6 +355,7 @@ class Mesh:
         self.coarse_retries = int(info.coarse_retries)
         self.n_elem_centric = [int(info.n_elem_centric[i]) for i in range(self.n_levels)]
         self.n_mortar_tasks = [int(info.n_mortar_tasks[i]) for i in range(self.n_levels)]
+        self.apply_flops = [float(info.apply_flops[i]) for i in range(self.n_levels)]
 
     def algorithmic_bytes(self, level=0, scalar=8):
         """Bytes one apply of ``level`` must move at least once: x read and y written, the

@@ -144,6 +144,10 @@ struct hpdg_mesh {
   int coarse_retries = 0;  // coarse factorisations repeated after a failed attempt
   std::vector<Timed> pending;
   std::vector<hipEvent_t> event_pool;
+  // side stream of the apply (default priority): the element kernel's buckets run there beside
+  // the element-centric groups; created on first use
+  hipStream_t side = nullptr;
+  hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   Acc acc[HPDG_TIMING_KINDS][32][2];
 
   template <typename T>
@@ -205,6 +209,9 @@ struct hpdg_mesh {
       (void)hipEventDestroy(ev.b);
     }
     for (auto ev : event_pool) (void)hipEventDestroy(ev);
+    if (fork_ev) (void)hipEventDestroy(fork_ev);
+    if (join_ev) (void)hipEventDestroy(join_ev);
+    if (side) (void)hipStreamDestroy(side);
     for (void* ptr : allocs) (void)hipFree(ptr);
     if (host_sc) (void)hipHostFree(host_sc);
     if (host_bad) (void)hipHostFree(host_bad);
@@ -419,18 +426,47 @@ FastBucket<T> fast_bucket(const hpdg_mesh* M, int l, size_t b) {
 // y = A_l x through the view V (whose trace and slot buffers are used): the face traces that the
 // mortar kernel reads and the mortar kernel (faces left to it), then the element-centric apply of
 // the fast elements and the element kernel of the others
+// run slow(ss) on the mesh's side stream and fast(s) on s, both after the work enqueued on s so
+// far, s continuing after both (when the level has work of both kinds; else both on s)
+template <typename FS, typename FF>
+void side_by_side(hpdg_mesh* M, bool both, hipStream_t s, FS&& slow, FF&& fast) {
+  if (!both) {
+    slow(s);
+    fast(s);
+    return;
+  }
+  if (!M->side) {
+    HIPCHK(hipStreamCreateWithFlags(&M->side, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&M->fork_ev, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&M->join_ev, hipEventDisableTiming));
+  }
+  HIPCHK(hipEventRecord(M->fork_ev, s));
+  HIPCHK(hipStreamWaitEvent(M->side, M->fork_ev, 0));
+  slow(M->side);
+  HIPCHK(hipEventRecord(M->join_ev, M->side));
+  fast(s);
+  HIPCHK(hipStreamWaitEvent(s, M->join_ev, 0));
+}
+
+// y = A_l x through the view V; ``overlap``: the element kernel's buckets on the side stream
 template <typename T>
-void level_apply(hpdg_mesh* M, int l, const LevelView<T>& V, const T* x, T* y, hipStream_t s) {
+void level_apply(hpdg_mesh* M, int l, const LevelView<T>& V, const T* x, T* y, hipStream_t s, bool overlap = true) {
   const LevelHost& h = M->H[l];
   DevLevel<T>& d = M->lev<T>(l);
   if (!h.mtask.empty()) {
     launch_traces<T>(V, x, s, d.telems, (long long)h.trace_elems.size());
     launch_faces<T>(V, s);
   }
-  for (size_t b = h.fast_n.size(); b-- > 0;) launch_fast_apply<T>(V, fast_bucket<T>(M, l, b), x, y, s);
-  for (size_t b = 0; b < h.bucket_n.size(); ++b)
-    launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], d.belems + h.bucket_start[b],
-                           h.bucket_start[b + 1] - h.bucket_start[b], x, y, s);
+  side_by_side(
+      M, overlap && !h.fast_n.empty() && !h.bucket_n.empty(), s,
+      [&](hipStream_t ss) {
+        for (size_t b = 0; b < h.bucket_n.size(); ++b)
+          launch_apply_bucket<T>(V, h.bucket_n[b], h.bucket_q[b], d.belems + h.bucket_start[b],
+                                 h.bucket_start[b + 1] - h.bucket_start[b], x, y, ss);
+      },
+      [&](hipStream_t ss) {
+        for (size_t b = h.fast_n.size(); b-- > 0;) launch_fast_apply<T>(V, fast_bucket<T>(M, l, b), x, y, ss);
+      });
 }
 
 template <typename T>
@@ -448,7 +484,7 @@ void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, T* slo
   LevelView<T> V = M->view<T>(l);
   V.trace = trace;
   V.slot = slot;
-  level_apply<T>(M, l, V, x, y, s);
+  level_apply<T>(M, l, V, x, y, s, false);
 }
 
 // Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)
@@ -507,10 +543,17 @@ void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, 
           launch_traces<T>(V, xi, s, d.telems, (long long)h.trace_elems.size());
           launch_faces<T>(V, s);
         }
-        for (size_t bk = h.fast_n.size(); bk-- > 0;) launch_fast_cheb<T>(V, fast_bucket<T>(M, l, bk), xi, st, s);
-        for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
-          launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], d.belems + h.bucket_start[bk],
-                                     h.bucket_start[bk + 1] - h.bucket_start[bk], xi, bs, s);
+        side_by_side(
+            M, !h.bucket_n.empty(), s,
+            [&](hipStream_t ss) {
+              for (size_t bk = 0; bk < h.bucket_n.size(); ++bk)
+                launch_apply_block_cheb<T>(V, h.bucket_n[bk], h.bucket_q[bk], d.belems + h.bucket_start[bk],
+                                           h.bucket_start[bk + 1] - h.bucket_start[bk], xi, bs, ss);
+            },
+            [&](hipStream_t ss) {
+              for (size_t bk = h.fast_n.size(); bk-- > 0;)
+                launch_fast_cheb<T>(V, fast_bucket<T>(M, l, bk), xi, st, ss);
+            });
       });
       cur = 1 - cur;
     }
@@ -988,6 +1031,9 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
     M->has_f32 = disc->build_f32 != 0;
     M->dp.mass_term = disc->mass_term != 0 ? 1 : 0;
     M->dp.robin_gamma = disc->robin_gamma;
+    if (disc->ec_mode < HPDG_EC_AUTO || disc->ec_mode > HPDG_EC_NEVER)
+      throw Error(HPDG_ERR_INVALID_ARG, "unknown element-centric mode");
+    M->dp.ec_mode = disc->ec_mode;
     if (!std::isfinite(M->dp.robin_gamma)) throw Error(HPDG_ERR_INVALID_ARG, "non-finite Robin coefficient");
   }
   M->max_levels = (disc && disc->max_levels > 0) ? std::min(disc->max_levels, 32) : 32;
@@ -1735,6 +1781,17 @@ int hpdg_mesh_info_get(const hpdg_mesh* mesh, hpdg_mesh_info* out) {
                                     mesh->H[l].fmlist.size() * sizeof(int));
     out->n_elem_centric[l] = (int64_t)mesh->H[l].fast_elems.size();
     out->n_mortar_tasks[l] = (int64_t)mesh->H[l].mtask.size();
+    double fma = 0;
+    const LevelHost& h = mesh->H[l];
+    for (size_t e = 0; e < h.einfo.size(); ++e) {
+      const double n = h.einfo[e].n, q = h.einfo[e].q;
+      if (h.fast[e])
+        fma += 8 * n * n * n * n + 6 * n * n * (3 * n + 6);
+      else
+        fma += 2 * (n * n * n * q + n * n * q * q + n * q * q * q) + 6 * q * q * q * q + 9 * q * q * q +
+               6 * (9 * n * n * q + 12 * n * q * q + 20 * q * q);
+    }
+    out->apply_flops[l] = 2 * fma;
   }
   out->device_bytes = mesh->bytes;
   out->block_retries = mesh->block_retries;
@@ -2085,6 +2142,7 @@ int hpdg_server_submit(hpdg_server* sv, const hpdg_request* rq, uint64_t* ticket
     put(&dc.build_f32, 4);
     put(&dc.mass_term, 4);
     put(&dc.robin_gamma, 8);
+    put(&dc.ec_mode, 4);
     put(r->mkind.data(), 4 * r->mkind.size());
     put(r->mparams.data(), 8 * r->mparams.size());
     put(r->mnbr.data(), 4 * r->mnbr.size());

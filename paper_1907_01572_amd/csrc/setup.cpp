@@ -520,12 +520,23 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
   // side is such an element too (or there is none: Dirichlet and Robin faces).  Every other
   // mortar stays with the mortar kernel, whose lifted terms (face slots) the element adds.
   L.fast.assign(E, 0);
-  for (size_t e = 0; e < E; ++e) {
-    const ElemInfo& I = L.einfo[e];
-    if (I.vmode != 0 || I.mass || I.n < 2 || I.n > kFastMaxN) continue;
-    const double* G = L.vgeo.data() + I.vgeo;
-    if (G[1] != 0.0 || G[2] != 0.0 || G[4] != 0.0) continue;
-    L.fast[e] = 1;
+  if (dp.ec_mode != 2) {
+    long long nfast = 0;
+    int nlo = kMaxN, nhi = 0;
+    for (size_t e = 0; e < E; ++e) {
+      const ElemInfo& I = L.einfo[e];
+      if (I.vmode != 0 || I.mass || I.n < 2 || I.n > kFastMaxN) continue;
+      const double* G = L.vgeo.data() + I.vgeo;
+      if (G[1] != 0.0 || G[2] != 0.0 || G[4] != 0.0) continue;
+      L.fast[e] = 1;
+      nfast += 1;
+      nlo = std::min(nlo, I.n);
+      nhi = std::max(nhi, I.n);
+    }
+    // by level: from 4096 such elements up on levels of one degree and from 16384 up on levels
+    // of several degrees (one launch per degree); below that the launches are latency bound and
+    // the element and mortar kernels take less time
+    if (dp.ec_mode == 0 && nfast < (nlo == nhi ? 4096 : 16384)) L.fast.assign(E, 0);
   }
   std::vector<unsigned char> mfast(M, 0);
   for (size_t mi = 0; mi < M; ++mi) {

@@ -19,6 +19,7 @@ struct DiscParams {
   int kfield = 0;
   int cfield = 0;
   double robin_gamma = 0.0;  // k n.grad u + gamma u = g_R on Robin faces (macro face kind 3)
+  int ec_mode = 0;           // element-centric apply: 0 by level (see build_level), 1 always, 2 never
 };
 
 // 1-D operator tables, indexed by (kind, n, q); every matrix is row-major [q][n].

@@ -4,6 +4,11 @@ import numpy as np
 import meshgen
 import paper_1907_01572_amd as hp
 
+# GPU tests upload with the element-centric apply wherever an element qualifies (the default
+# leaves it off on small mixed-degree levels, which test meshes are); tests of the other modes
+# name theirs
+hp.EC_MODE_DEFAULT = hp.EC_ALWAYS
+
 # FP64 apply parity (relative L2 over the output vector).
 TOL_APPLY = 1e-12
 # Compactified shells (r_out = 1e9): the face-metric noise described below; measured in L2

@@ -287,6 +287,44 @@ def test_element_centric_path_used(ctx):
         else:
             assert 0 < ec[0] < ne[0] and tasks[0] > 0
         M.free()
+    # by level (the default outside the tests): small mixed-degree levels keep the element and
+    # mortar kernels, one-degree levels take the element-centric apply; never: none anywhere
+    for name, mode, expect in (("hp_p2_7_k1", hp.EC_AUTO, "none"), ("cube_l2_p3", hp.EC_ALWAYS, "all"),
+                               ("cube_l2_p3", hp.EC_NEVER, "none")):
+        maker, prob = MESHES[name]
+        M = ctx.upload(maker(), coef=coef_of(prob), ec_mode=mode)
+        ec = M.n_elem_centric
+        print(name, "mode", mode, "element-centric", ec, flush=True)
+        if expect == "all":
+            assert ec == M.n_elem
+        elif expect == "none":
+            assert all(v == 0 for v in ec)
+        M.free()
+    # by level on a one-degree mesh of 8192 cells (next level 1024): the element-centric apply on
+    # the finest level only
+    M = ctx.upload(meshgen.uniform_box((2, 1, 1), 4, 2), ec_mode=hp.EC_AUTO, max_levels=2)
+    print("box 2x1x1 level 4: element-centric", M.n_elem_centric, "of", M.n_elem, flush=True)
+    assert M.n_elem_centric[0] == M.n_elem[0] == 8192 and M.n_elem_centric[1] == 0
+    M.free()
+
+
+@pytest.mark.parametrize("name", ["cube_l2_p3", "hp_p2_7_k1"])
+def test_apply_parity_without_element_centric(ctx, name):
+    # the element and mortar kernels alone (EC_NEVER) on meshes the element-centric apply covers
+    maker, prob = MESHES[name]
+    m = maker()
+    M = ctx.upload(m, coef=coef_of(prob), ec_mode=hp.EC_NEVER)
+    op = SIPG(m, prob)
+    perm = dof_perm(M.level_cells(0), m)
+    x = np.random.default_rng(5).standard_normal(op.ndof)
+    y_or = op.apply(x)[perm]
+    xd = dev(x[perm])
+    yd = torch.zeros_like(xd)
+    M.apply(xd, yd)
+    err = rel(host(yd), y_or)
+    print(name, "rel", err, flush=True)
+    assert err <= TOL_APPLY
+    M.free()
 
 
 @pytest.mark.parametrize("name,smoother", [("shell_l2_p3_r1e3", "block"), ("cube_l1_p7", "block"),
