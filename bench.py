@@ -35,7 +35,6 @@ FP64_PEAK_TFLOPS = 78.6  # MI355X FP64 vector
 # HBM traffic per launch from rocprofv3 FETCH_SIZE / WRITE_SIZE counters, written by
 # --summarize-traffic; valid only while the kernel sources hash to the recorded value
 TRAFFIC_FILE = os.path.join("profiles", "solve_hp_hbm_traffic.txt")
-APPLY_ALL_BUCKETS = "trace_kernel<double> + apply_kernel<double, n, q, false> (one launch per degree bucket)"
 # the operator apply of a level with element-centric groups: one fast_kernel launch per degree
 # (descending), and for the cells it does not cover (variable k, 2:1 faces) the face traces, the
 # mortar kernel and the element kernel per (n, q) bucket
@@ -81,6 +80,19 @@ def measured_traffic(kernel, alg_bytes):
     return None if v is None else float(v)
 
 
+def composite_members(name):
+    """Which of a composite apply / step's member kernels a kernel name is (None if it is not one):
+    the element-centric groups, the face traces, the mortar kernel and the element kernel."""
+    short = name.split("(hpdg::")[0].replace("void hpdg::(anonymous namespace)::", "")
+    if not short.endswith(">") or "<double" not in short:
+        return None
+    if short.startswith("trace_kernel") or short.startswith("mortar_kernel"):
+        return "both"
+    if short.startswith("fast_kernel") or short.startswith("apply_kernel"):
+        return "step" if short.endswith("true>") else "apply"
+    return None
+
+
 def summarize_trace(stats_csv, out_md, command, trace_csv=None):
     """Top kernels of a rocprofv3 kernel-stats table as markdown (name, calls, total, mean), and
     from the per-dispatch trace (optional) the mean duration of each kernel's fine-level
@@ -114,12 +126,24 @@ def summarize_trace(stats_csv, out_md, command, trace_csv=None):
     if fine:
         lines += ["", "Fine-level dispatches (each kernel's largest grid, from the per-dispatch trace):", "",
                   "| kernel | grid (threads) | dispatches | mean us |", "|---|---|---|---|"]
-        top = [r["Name"] for r in rows[:8]]
+        top = [r["Name"] for r in rows[:24]]
         for nm in top:
             if nm in fine:
                 g, c, m = fine[nm]
                 name = nm.split("(hpdg::")[0].replace("void hpdg::(anonymous namespace)::", "").replace("|", "/")
                 lines.append("| `%s` | %d | %d | %.1f |" % (name[:90], g, c, m / 1e3))
+        # composites: one fine-level apply / fused smoother step is one dispatch of each member;
+        # the element kernel's buckets run on a side stream beside the element-centric groups, so
+        # the step's span is the main stream's chain (face traces, mortar kernel, groups)
+        for kind, label in (("apply", APPLY_EC), ("step", SMOOTH_EC)):
+            mem = [nm for nm in fine if composite_members(nm) in (kind, "both")]
+            if any(composite_members(nm) == kind for nm in mem):
+                tot = sum(fine[nm][2] for nm in mem)
+                chain = sum(fine[nm][2] for nm in mem if "apply_kernel" not in nm)
+                lines += ["", "Fine-level %s (%d kernels): main-stream chain (face traces + mortar kernel + "
+                          "element-centric groups) %.1f us; sum over all members %.1f us (the element kernel's "
+                          "buckets overlap the groups on the side stream)  [%s]"
+                          % ("apply" if kind == "apply" else "fused step", len(mem), chain / 1e3, tot / 1e3, label)]
     with open(out_md, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))
@@ -169,12 +193,12 @@ def summarize_traffic(fetch_csv, write_csv, cal_fetch_csv, cal_write_csv, out, k
                   "fetch_bytes_per_launch[%s]: %.0f" % (short, f),
                   "write_bytes_per_launch[%s]: %.0f" % (short, w),
                   "bytes_per_launch[%s]: %.0f" % (short, f + w)]
-    # one finest-level FP64 apply of a mixed-degree level: the trace kernel and every bucket's
-    # apply_kernel<double, n, q, false>
-    parts = [k for k in fa if ("apply_kernel<double," in k and "false>" in k) or "trace_kernel<double>" in k]
-    if parts:
-        tot = sum(np.mean(fa[k]) * sf + (np.mean(wa[k]) * sw if k in wa else 0.0) for k in parts)
-        lines.append("bytes_per_launch[%s]: %.0f" % (APPLY_ALL_BUCKETS, tot))
+    # one finest-level FP64 apply / fused step: one fine-level dispatch of each member kernel
+    for kind, label in (("apply", APPLY_EC), ("step", SMOOTH_EC)):
+        parts = [k for k in fa if composite_members(k) in (kind, "both")]
+        if any(composite_members(k) == kind for k in parts):
+            tot = sum(np.mean(fa[k]) * sf + (np.mean(wa[k]) * sw if k in wa else 0.0) for k in parts)
+            lines.append("bytes_per_launch[%s]: %.0f" % (label, tot))
     with open(out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -289,13 +289,13 @@ constexpr int fast_elem_scalars() {
 }
 
 // at least this many waves per SIMD: the register budget of each instantiation (uniform-degree
-// groups: 128 VGPRs; mixed-degree groups, which hold the projection stage's state: 168, and 256
-// from p = 5 up)
-template <int N, bool MIX>
-constexpr int fast_waves() { return MIX ? (N >= 6 ? 2 : 3) : 4; }
+// groups: 128 VGPRs, 168 for the fused step from p = 6 up; mixed-degree groups, which hold the
+// projection stage's results: 168, and 256 from p = 5 up)
+template <int N, bool MIX, bool FUSE>
+constexpr int fast_waves() { return MIX ? (N >= 6 ? 2 : 3) : (FUSE && N >= 7 ? 3 : 4); }
 
 template <typename T, int N, bool MIX, bool FUSE>
-__global__ void __launch_bounds__(64, (fast_waves<N, MIX>())) fast_kernel(LevelView<T> L, FastBucket<T> fb, const T* __restrict__ x,
+__global__ void __launch_bounds__(64, (fast_waves<N, MIX, FUSE>())) fast_kernel(LevelView<T> L, FastBucket<T> fb, const T* __restrict__ x,
                                                   T* __restrict__ y, FastStep<T> st) {
   constexpr int N2 = N * N;
   constexpr int EPW = N2 <= 64 ? 64 / N2 : 1;
@@ -339,24 +339,6 @@ __global__ void __launch_bounds__(64, (fast_waves<N, MIX>())) fast_kernel(LevelV
 #pragma unroll
   for (int f = 0; f < 6; ++f) q1[f] = q2[f] = 0;
   if constexpr (MIX) {
-    // this element's face traces for its neighbours of lower degree (read by their groups,
-    // launched after this one): the value and the normal derivative at face node (li, lj)
-    if (act) {
-      T* const trb = L.trace + L.fe_toff[gi];
-#pragma unroll
-      for (int f = 0; f < 6; ++f) {
-        if (!(fl[f].meta & (1 << 13))) continue;
-        const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
-        const T* p = x + off + vidx(N, d, t0, t1, 0, li, lj);
-        const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
-        const T* dfs = df + (f & 1) * N;
-        T dn = 0;
-#pragma unroll
-        for (int m = 0; m < N; ++m) dn += dfs[m] * p[m * sd];
-        trb[2 * f * N2 + lt] = p[((f & 1) ? N - 1 : 0) * sd];
-        trb[(2 * f + 1) * N2 + lt] = dn;
-      }
-    }
     // neighbours of another degree, all six faces before the volume passes (the face node of a
     // thread is (li, lj) on every face)
 #pragma unroll
@@ -499,6 +481,25 @@ __global__ void __launch_bounds__(64, (fast_waves<N, MIX>())) fast_kernel(LevelV
   } else {
 #pragma unroll
     for (int k = 0; k < N; ++k) y[off + lt + N2 * k] = acc[k];
+  }
+  if constexpr (MIX) {
+    // this element's face traces for its neighbours of lower degree (read by their groups,
+    // launched after this one): the value and the normal derivative at face node (li, lj) of x
+    // (written last: stores among the volume passes cost registers)
+    T* const trb = L.trace + L.fe_toff[gi];
+#pragma unroll
+    for (int f = 0; f < 6; ++f) {
+      if (!(fl[f].meta & (1 << 13))) continue;
+      const int d = f >> 1, t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+      const T* p = x + off + vidx(N, d, t0, t1, 0, li, lj);
+      const int sd = d == 0 ? 1 : (d == 1 ? N : N2);
+      const T* dfs = df + (f & 1) * N;
+      T dn = 0;
+#pragma unroll
+      for (int m = 0; m < N; ++m) dn += dfs[m] * p[m * sd];
+      trb[2 * f * N2 + lt] = p[((f & 1) ? N - 1 : 0) * sd];
+      trb[(2 * f + 1) * N2 + lt] = dn;
+    }
   }
 }
 
