@@ -237,6 +237,8 @@ class SIPG:
                          mvec_p=np.einsum("mpdi,mpi->mpd", Jip, -nhat),
                          idx_p=self.offsets[ep][:, None] + np.arange(npl ** 3)[None, :])
             g["robin"] = bc == ROBIN
+            g["hmin"] = hmin      # h_m at each point (Eq. penaltyparameter, reading R3)
+            g["pm"] = pm          # p_m = max(p-, p+)
             g["kx"] = km          # the minus side's k (its own side of the mortar)
             g["kp"] = kp          # the plus side's k (= km where k is continuous)
             g["sigma"] = self.C * pm * pm / hmin * np.maximum(km, kp)
