@@ -318,6 +318,25 @@ int hpdg_set_coefficient(hpdg_mesh* mesh, int kind, int where, const double* hos
  * (stream-ordered). */
 int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream);
 
+/* A posteriori error estimate of u_dev (a level-0 FP64 vector) for the problem of ``rhs``
+ * (Sec. II.E, Eqs. Eta2_Ingredients, Eta2_Integrals, Eta2_Local), per level-0 element, into the
+ * device FP64 array eta2_dev[n_elem[0]]:
+ *   eta2(e) = h_e^2 p_e^2 int_e R^2 + sum over the interior mortars of e of
+ *             int_m ((h_m / p_m) [[k grad u]]^2 + sigma [[u]]^2) + sum over its Dirichlet mortars of
+ *             int_m sigma (u - g_D)^2,
+ * R = g + div(k grad u) - c u; sigma the operator's penalty (Eq. penaltyparameter, with
+ * max(k-, k+)) and h_m, p_m as there, pointwise on the mortar rule; h_e the largest distance
+ * between two vertices of e; div(k grad u) by the collocation derivative on the element's GL
+ * points (exact on affine elements with a constant k); Neumann and Robin faces add no term.
+ * eta2_vol_dev (may be NULL): the volume parts h_e^2 p_e^2 int_e R^2.  Runs on the device in
+ * FP64 (face traces, one kernel per element for the volume part, one wavefront per mortar for
+ * the face parts, one sum per element); the point data of the problem are built on the host on
+ * the first call for a (kind, params) and kept with the mesh.  Stream-ordered; the first call
+ * for a problem synchronises ``stream``.  Errors: HPDG_ERR_INVALID_ARG (unknown rhs kind,
+ * missing arguments, eta2_dev == eta2_vol_dev), HPDG_ERR_UNSUPPORTED (degree above 8). */
+int hpdg_estimate(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, const double* u_dev, double* eta2_dev,
+                  double* eta2_vol_dev, void* stream);
+
 /* y = A_level x (Eq. lh2 applied matrix-free): volume stiffness by sum factorisation,
  * SIPG fluxes on every mortar with hp-mortar projections (Fig. mortar).  Three stream-ordered
  * launches: the face traces of x, the mortar kernel (both sides of each mortar, into per-face

@@ -35,7 +35,7 @@ EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload"
             "hpdg_nonlinear_residual", "hpdg_nonlinear_linearize", "hpdg_newton_solve",
             "hpdg_server_create", "hpdg_server_submit", "hpdg_server_poll", "hpdg_server_wait",
             "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing", "hpdg_apply_noalloc",
-            "hpdg_set_coefficient"]
+            "hpdg_set_coefficient", "hpdg_estimate"]
 
 
 class HpdgError(RuntimeError):
@@ -148,6 +148,7 @@ def load_library(path=LIB_PATH):
     lib.hpdg_apply.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_apply_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_set_coefficient.argtypes = [vp, i32, i32, vp, vp, vp]
+    lib.hpdg_estimate.argtypes = [vp, ctypes.POINTER(RhsDesc), vp, vp, vp, vp]
     lib.hpdg_setup_smoother.argtypes = [vp, ctypes.POINTER(SmootherParams), vp, vp]
     lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
@@ -378,6 +379,18 @@ class Mesh:
         r.n_params = len(params)
         r.params = params.ctypes.data if len(params) else None
         self.ctx.check(self.lib.hpdg_assemble_rhs(self.h, ctypes.byref(r), _ptr(F), _stream(stream)))
+
+    def estimate(self, problem, u, eta2, eta2_vol=None, stream=None):
+        """eta2[e] (FP64 device tensor of n_elem[0]): the a posteriori estimate of the level-0
+        vector u for ``problem``; eta2_vol (optional): its volume parts."""
+        params = np.ascontiguousarray(problem["params"], np.float64).reshape(-1)
+        r = RhsDesc()
+        r.kind = RHS_IDS[problem["kind"]]
+        r.n_params = len(params)
+        r.params = params.ctypes.data if len(params) else None
+        self.ctx.check(self.lib.hpdg_estimate(self.h, ctypes.byref(r), _ptr(u), _ptr(eta2),
+                                              _ptr(eta2_vol) if eta2_vol is not None else None,
+                                              _stream(stream)))
 
     def apply(self, x, y, level=0, stream=None):
         prec = F32 if x.dtype.itemsize == 4 else F64

@@ -149,6 +149,17 @@ struct hpdg_mesh {
   hipStream_t side = nullptr;
   hipEvent_t fork_ev = nullptr, join_ev = nullptr;
   Acc acc[HPDG_TIMING_KINDS][32][2];
+  // a posteriori estimator: the point data of one problem on level 0 (rebuilt when the problem
+  // changes) and the per-element / per-mortar parts
+  struct EstCache {
+    std::vector<double> key;  // rhs kind and parameters (empty: not built)
+    EstVolume ev{};
+    EstFace ef{};
+    MortarTask* tasks = nullptr;
+    long long n_tasks = 0;
+    double* vpart = nullptr;
+    std::vector<void*> ptrs;
+  } est;
 
   template <typename T>
   T* alloc(size_t count) {
@@ -1198,6 +1209,7 @@ void rebuild_mesh(hpdg_mesh* M, hipStream_t s) {
   swap(M->Ainv64, F->Ainv64);
   swap(M->ncoarse, F->ncoarse);
   swap(M->lam, F->lam);
+  swap(M->est, F->est);
   swap(M->bad, F->bad);
   swap(M->host_bad, F->host_bad);
   swap(M->nl_b, F->nl_b);
@@ -1230,6 +1242,48 @@ void assemble_rhs_impl(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev,
   assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);
   HIPCHK(hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
+}
+
+// eta2(e) of u on level 0 (Eqs. Eta2_Ingredients .. Eta2_Local)
+void estimate_impl(hpdg_mesh* M, const hpdg_rhs_desc* rhs, const double* u, double* eta2, double* eta2_vol,
+                   hipStream_t s) {
+  if (rhs->kind < 0 || rhs->kind > 6) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
+  if (rhs->n_params > 0 && !rhs->params) throw Error(HPDG_ERR_INVALID_ARG, "rhs parameters missing");
+  const LevelHost& h = M->H[0];
+  if (est_lds_bytes(h.nmax, h.qmax) > 64 * 1024)
+    throw Error(HPDG_ERR_UNSUPPORTED, "estimator: degree too high for one element's workspace");
+  std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
+  std::vector<double> key{double(rhs->kind)};
+  key.insert(key.end(), P.begin(), P.end());
+  auto& E = M->est;
+  if (E.key != key) {
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* ptr : E.ptrs) M->release(ptr);
+    E = hpdg_mesh::EstCache{};
+    EstTables t;
+    estimator_tables(M->mm, M->dp, h, rhs->kind, P, t);
+    auto keep = [&](auto* ptr) {
+      E.ptrs.push_back(ptr);
+      return ptr;
+    };
+    E.ev.vol = keep(M->upload_raw(t.vol, s));
+    E.ev.voff = keep(M->upload_raw(t.voff, s));
+    E.ev.he2p2 = keep(M->upload_raw(t.he2p2, s));
+    E.tasks = keep(M->upload_raw(t.tasks, s));
+    E.n_tasks = (long long)t.tasks.size();
+    E.ef.face = keep(M->upload_raw(t.face, s));
+    E.ef.foff = keep(M->upload_raw(t.foff, s));
+    E.ef.tmortar = keep(M->upload_raw(t.task_mortar, s));
+    E.ef.out = keep(M->alloc<double>(h.minfo.size()));
+    E.vpart = keep(M->alloc<double>(h.cells.size()));
+    E.key = key;
+  }
+  LevelView<double> V = M->view<double>(0);
+  V.mtask = E.tasks;
+  V.n_mtask = E.n_tasks;
+  launch_fill<double>((long long)h.minfo.size(), 0.0, E.ef.out, s);
+  launch_estimator(V, u, E.ev, E.ef, E.n_tasks, eta2_vol ? eta2_vol : E.vpart, eta2, s);
+  HIPCHK(hipGetLastError());
 }
 
 void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max, hipStream_t s) {
@@ -1841,6 +1895,17 @@ int hpdg_apply(hpdg_mesh* mesh, int level, int prec, const void* x_dev, void* y_
     else
       apply_level<double>(mesh, level, static_cast<const double*>(x_dev), static_cast<double*>(y_dev), s);
     HIPCHK(hipGetLastError());
+  });
+}
+
+int hpdg_estimate(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, const double* u_dev, double* eta2_dev,
+                  double* eta2_vol_dev, void* stream) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  if (!rhs || !u_dev || !eta2_dev || eta2_dev == eta2_vol_dev)
+    return fail(mesh->ctx, HPDG_ERR_INVALID_ARG, "invalid estimator arguments");
+  return guarded(mesh->ctx, [&] {
+    HIPCHK(hipSetDevice(mesh->ctx->device));
+    estimate_impl(mesh, rhs, u_dev, eta2_dev, eta2_vol_dev, S(stream));
   });
 }
 

@@ -127,9 +127,12 @@ __device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* reg
 }
 
 // One wavefront per mortar.  Items of a phase are spread over the 64 lanes; every quantity
-// of the mortar (degrees, rule, maps, matrix offsets) is the same in all lanes.
-template <typename T>
-__global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long count) {
+// of the mortar (degrees, rule, maps, matrix offsets) is the same in all lanes.  EST: instead
+// of the SIPG terms, the mortar's part of the a posteriori estimator (Eqs. Eta2_Integrals):
+// sum over its points of w S ((h_m / p_m) [[k grad u]]^2 + sigma [[u]]^2) inside, w S sigma
+// (u - g_D)^2 on Dirichlet faces, written to est.out at the mortar's index.
+template <typename T, bool EST = false>
+__global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long count, EstFace est) {
   extern __shared__ unsigned char smem_raw[];
   if ((long long)blockIdx.x >= count) return;
   const long long mi = xcd_remap(blockIdx.x, gridDim.x);  // gridDim.x == count
@@ -204,6 +207,7 @@ __global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long co
   __syncthreads();
   // P3+P4: at each mortar point (cc, dd): both sides' u, du/da, du/db, du/dn (second pass
   // along b), the SIPG flux, and each side's coefficients in that side's frame into CF
+  double eacc = 0;  // EST: this lane's points
   {
     const int npts = M.gmode ? qq : 1;
     const T* mg = L.mgeo + M.geo;
@@ -244,6 +248,17 @@ __global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long co
       T u0, gr0, ma0, mb0, mn0, u1 = 0, gr1 = 0, ma1 = 0, mb1 = 0, mn1 = 0;
       side_values(0, l0, u0, gr0, ma0, mb0, mn0);
       if (two) side_values(1, l1, u1, gr1, ma1, mb1, mn1);
+      if constexpr (EST) {
+        const double* ef = est.face + est.foff[mi] + 2 * g;  // (h_m / p_m, g_D) at this point
+        if (two) {
+          const double J1 = double(gr0) + double(gr1), J2 = double(u0) - double(u1);
+          eacc += double(wS) * (ef[0] * J1 * J1 + double(sig) * J2 * J2);
+        } else {
+          const double J3 = double(u0) - ef[1];
+          eacc += double(wS) * double(sig) * J3 * J3;
+        }
+        continue;
+      }
       T Af0, Bc0, Af1 = 0, Bc1 = 0;
       if (!two) {  // boundary: the Dirichlet form with zero data
         Af0 = wS * (sig * u0 - gr0);
@@ -272,6 +287,12 @@ __global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long co
         C1[3 * Q2 + l1] = Bc1 * mn1;
       }
     }
+  }
+  if constexpr (EST) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) eacc += __shfl_xor(eacc, o, 64);
+    if (lane == 0) est.out[est.tmortar[mi]] = eacc;
+    return;
   }
   __syncthreads();
   // P5: first transposed pass (along the side's face axis a)
@@ -563,7 +584,111 @@ template <typename T>
 void launch_mortars(const LevelView<T>& L, hipStream_t s) {
   if (L.n_mtask == 0) return;
   const size_t lds = mortar_lds_scalars(L.nmax, L.qmmax) * sizeof(T);
-  hipLaunchKernelGGL((mortar_kernel<T>), dim3(unsigned(L.n_mtask)), dim3(64), lds, s, L, L.n_mtask);
+  hipLaunchKernelGGL((mortar_kernel<T>), dim3(unsigned(L.n_mtask)), dim3(64), lds, s, L, L.n_mtask, EstFace{});
+}
+
+// ---- a posteriori estimator (Eqs. Eta2_Ingredients .. Eta2_Local), FP64 ------------------
+// Volume part per element: h_e^2 p_e^2 sum over the volume GL points of W det J R^2 with
+// R = g + (1 / det J) sum_d D_d F_d - c u, F_d = det J k (J^-1 J^-T grad_xi u)_d the
+// contravariant flux at the GL points and D_d the GL collocation derivative along axis d.
+__global__ void __launch_bounds__(kThreads) est_volume_kernel(LevelView<double> L, const double* __restrict__ x,
+                                                              EstVolume ev, double* __restrict__ out) {
+  extern __shared__ unsigned char smem_raw[];
+  __shared__ double red[kThreads];
+  const long long e = blockIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo I = L.einfo[e];
+  const int n = I.n, q = I.q, n3 = n * n * n, q3 = q * q * q;
+  const int NM = L.nmax, QM = L.qmax;
+  double* su = reinterpret_cast<double*>(smem_raw);
+  double* tA = su + NM * NM * NM;
+  double* tB = tA + NM * NM * QM;
+  double* U = tB + NM * QM * QM;
+  double* F0 = U + QM * QM * QM;
+  double* F1 = F0 + QM * QM * QM;
+  double* F2 = F1 + QM * QM * QM;
+  const double* B = tab(L, 0, n, q);
+  const double* Dg = L.tab + L.tv.dg_off[q];
+  const double* w = L.tab + L.tv.w_off[q];
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) su[i] = x[I.off + i];
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * n * q; idx += blockDim.x) {
+    const int a = idx % q, kj = idx / q;
+    double acc = 0;
+    for (int i = 0; i < n; ++i) acc += B[a * n + i] * su[kj * n + i];
+    tA[idx] = acc;  // [k][j][a]
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < n * q * q; idx += blockDim.x) {
+    const int a = idx % q, b = (idx / q) % q, k = idx / (q * q);
+    double acc = 0;
+    for (int j = 0; j < n; ++j) acc += B[b * n + j] * tA[(k * n + j) * q + a];
+    tB[idx] = acc;  // [k][b][a]
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
+    const int ba = idx % (q * q), c = idx / (q * q);
+    double acc = 0;
+    for (int k = 0; k < n; ++k) acc += B[c * n + k] * tB[k * q * q + ba];
+    U[idx] = acc;  // u at the GL points [c][b][a]
+  }
+  __syncthreads();
+  const double* G = L.vgeo + I.vgeo;
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
+    const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
+    double g0 = 0, g1 = 0, g2 = 0;
+    for (int t = 0; t < q; ++t) {
+      g0 += Dg[a * q + t] * U[(c * q + b) * q + t];
+      g1 += Dg[b * q + t] * U[(c * q + t) * q + a];
+      g2 += Dg[c * q + t] * U[(t * q + b) * q + a];
+    }
+    double G00, G01, G02, G11, G12, G22, sc = 1.0;
+    if (I.vmode == 0) {
+      G00 = G[0]; G01 = G[1]; G02 = G[2]; G11 = G[3]; G12 = G[4]; G22 = G[5];
+    } else {
+      G00 = G[idx]; G01 = G[q3 + idx]; G02 = G[2 * q3 + idx];
+      G11 = G[3 * q3 + idx]; G12 = G[4 * q3 + idx]; G22 = G[5 * q3 + idx];
+      sc = 1.0 / (w[a] * w[b] * w[c]);  // the stored metric carries the weights
+    }
+    F0[idx] = sc * (G00 * g0 + G01 * g1 + G02 * g2);
+    F1[idx] = sc * (G01 * g0 + G11 * g1 + G12 * g2);
+    F2[idx] = sc * (G02 * g0 + G12 * g1 + G22 * g2);
+  }
+  __syncthreads();
+  const double* vt = ev.vol + ev.voff[e];
+  double acc = 0;
+  for (int idx = threadIdx.x; idx < q3; idx += blockDim.x) {
+    const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
+    double dv = 0;
+    for (int t = 0; t < q; ++t) {
+      dv += Dg[a * q + t] * F0[(c * q + b) * q + t];
+      dv += Dg[b * q + t] * F1[(c * q + t) * q + a];
+      dv += Dg[c * q + t] * F2[(t * q + b) * q + a];
+    }
+    const double wdet = vt[3 * idx], idet = vt[3 * idx + 1], gsrc = vt[3 * idx + 2];
+    double R = gsrc + dv * idet;
+    if (I.mass && L.mcoef) R -= L.mcoef[I.mq + idx] / wdet * U[idx];
+    acc += wdet * R * R;
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int st = kThreads / 2; st > 0; st >>= 1) {
+    if (int(threadIdx.x) < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[e] = ev.he2p2[e] * red[0];
+}
+
+// eta2(e) = volume part + the parts of the mortars on its faces (face-mortar list)
+__global__ void est_sum_kernel(LevelView<double> L, const double* __restrict__ vol, const double* __restrict__ face,
+                               double* __restrict__ eta2) {
+  const long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (e >= L.n_elem) return;
+  const ElemInfo& I = L.einfo[e];
+  double s = vol[e];
+  for (int f = 0; f < kFaces; ++f)
+    for (int r = 0; r < I.fcnt[f]; ++r) s += face[L.fmlist[I.fstart[f] + r] >> 1];
+  eta2[e] = s;
 }
 
 }  // namespace
@@ -661,5 +786,23 @@ template void launch_apply_bucket<double>(const LevelView<double>&, int, int, co
                                           double*, hipStream_t);
 template void launch_apply_bucket<float>(const LevelView<float>&, int, int, const int*, long long, const float*,
                                          float*, hipStream_t);
+
+size_t est_lds_bytes(int nmax, int qmax) {
+  return sizeof(double) * (size_t(nmax) * nmax * nmax + size_t(nmax) * nmax * qmax + size_t(nmax) * qmax * qmax +
+                           4 * size_t(qmax) * qmax * qmax);
+}
+
+void launch_estimator(const LevelView<double>& L, const double* x, const EstVolume& ev, const EstFace& ef,
+                      long long n_tasks, double* vol, double* eta2, hipStream_t s) {
+  if (L.n_elem == 0) return;
+  launch_traces<double>(L, x, s);
+  hipLaunchKernelGGL(est_volume_kernel, dim3(unsigned(L.n_elem)), dim3(kThreads), est_lds_bytes(L.nmax, L.qmax), s,
+                     L, x, ev, vol);
+  if (n_tasks > 0) {
+    const size_t lds = mortar_lds_scalars(L.nmax, L.qmmax) * sizeof(double);
+    hipLaunchKernelGGL((mortar_kernel<double, true>), dim3(unsigned(n_tasks)), dim3(64), lds, s, L, n_tasks, ef);
+  }
+  hipLaunchKernelGGL(est_sum_kernel, dim3(unsigned((L.n_elem + 255) / 256)), dim3(256), 0, s, L, vol, ef.out, eta2);
+}
 
 }  // namespace hpdg

@@ -43,6 +43,25 @@ struct LevelView {
   int self_only;  // 1: neighbour traces taken as zero (the element-diagonal blocks A_ee)
 };
 
+// a posteriori estimator (apply.hip): the host's point data (EstTables) on the device
+struct EstVolume {
+  const double* vol;        // per element, at its volume GL points: (W det J, 1 / det J, g)
+  const long long* voff;    // per element: first scalar of its triples
+  const double* he2p2;      // per element: h_e^2 p_e^2
+};
+struct EstFace {
+  const double* face;       // per task, at its GL points: (h_m / p_m, g_D)
+  const long long* foff;    // per task: first scalar of its pairs
+  const int* tmortar;       // per task: the mortar's index
+  double* out;              // per mortar: its part (mortars without a task keep their value)
+};
+// LDS of the volume kernel; the estimator of x on level L (L.mtask: one task per interior or
+// Dirichlet mortar): face traces of x, volume parts into vol, mortar parts into ef.out (zeroed
+// by the caller), eta2(e) into eta2
+size_t est_lds_bytes(int nmax, int qmax);
+void launch_estimator(const LevelView<double>& L, const double* x, const EstVolume& ev, const EstFace& ef,
+                      long long n_tasks, double* vol, double* eta2, hipStream_t s);
+
 template <typename T>
 struct TransferView {
   const TransferInfo* tinfo;   // per fine element

@@ -304,6 +304,25 @@ SideMap side_map(const MortarInfo& M, int side) {
   return s;
 }
 
+MortarTask mortar_task(const LevelHost& L, const MortarInfo& M) {
+  MortarTask t{};
+  t.geo = M.geo;
+  t.q = (signed char)M.q;
+  t.gmode = (signed char)M.gmode;
+  t.interior = M.ep >= 0 ? 1 : 0;
+  for (int sd = 0; sd < 1 + t.interior; ++sd) {
+    const ElemInfo& O = L.einfo[size_t(sd ? M.ep : M.em)];
+    const int f = sd ? M.fp : M.fm;
+    const SideMap sm = side_map(M, sd);
+    t.n[sd] = (signed char)O.n;
+    t.f[sd] = (signed char)f;
+    t.tr[sd] = O.toff + 2LL * f * O.n * O.n;
+    t.slot[sd] = -1;
+    t.map[sd] = (unsigned char)(sm.swap | (sm.flipA << 1) | (sm.flipB << 2) | (sm.halfA << 3) | (sm.halfB << 5));
+  }
+  return t;
+}
+
 // ---------------------------------------------------------------------------------
 void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, LevelHost& L) {
   const size_t E = L.cells.size();
@@ -687,20 +706,9 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     const MortarInfo& M = L.minfo[m];
     if (where[2 * m] < 0 || (M.ep >= 0) != (where[2 * m + 1] >= 0))
       throw Error(-2, "internal: a mortar listed on one side of an interior face only");
-    MortarTask t{};
-    t.geo = M.geo;
-    t.q = (signed char)M.q;
-    t.gmode = (signed char)M.gmode;
-    t.interior = M.ep >= 0 ? 1 : 0;
+    MortarTask t = mortar_task(L, M);
     for (int sd = 0; sd < 1 + t.interior; ++sd) {
-      const ElemInfo& O = L.einfo[size_t(sd ? M.ep : M.em)];
-      const int f = sd ? M.fp : M.fm;
-      const SideMap sm = side_map(M, sd);
-      t.n[sd] = (signed char)O.n;
-      t.f[sd] = (signed char)f;
-      t.tr[sd] = O.toff + 2LL * f * O.n * O.n;
       t.slot[sd] = where[2 * m + sd];
-      t.map[sd] = (unsigned char)(sm.swap | (sm.flipA << 1) | (sm.flipB << 2) | (sm.halfA << 3) | (sm.halfB << 5));
       traced[size_t(sd ? M.ep : M.em)] = 1;
     }
     L.mtask.push_back(t);
@@ -1173,6 +1181,79 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
             idx[t1_] = j;
             F[size_t(I.off) + (idx[2] * n + idx[1]) * n + idx[0]] += v * La[x * n + i] * La[y * n + j];
           }
+      }
+  }
+}
+
+// ---- a posteriori estimator: point data (Eqs. Eta2_Integrals) -----------------------------
+void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost& L, int kind,
+                      const std::vector<double>& P, EstTables& out) {
+  (void)dp;
+  const size_t E = L.cells.size();
+  out = EstTables{};
+  out.voff.resize(E);
+  out.he2p2.resize(E);
+  double eta[kMaxQ + 1], wq[kMaxQ + 1];
+  for (size_t e = 0; e < E; ++e) {
+    const ElemInfo& I = L.einfo[e];
+    const Cell& c = L.cells[e];
+    const int q = I.q;
+    gauss_legendre(q, eta, wq);
+    out.voff[e] = (long long)out.vol.size();
+    for (int cc = 0; cc < q; ++cc)
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          double xi[3] = {eta[a], eta[b], eta[cc]}, x[3], J[3][3];
+          cell_eval(mm, c, xi, x, J);
+          const double dj = det3(J);
+          out.vol.push_back(wq[a] * wq[b] * wq[cc] * dj);
+          out.vol.push_back(1.0 / dj);
+          out.vol.push_back(source(kind, P, x));
+        }
+    // h_e: the largest distance between two of the element's vertices
+    double X[8][3];
+    for (int v = 0; v < 8; ++v) {
+      double xi[3] = {(v & 1) ? 1.0 : -1.0, (v & 2) ? 1.0 : -1.0, (v & 4) ? 1.0 : -1.0}, J[3][3];
+      cell_eval(mm, c, xi, X[v], J);
+    }
+    double h2 = 0;
+    for (int v = 0; v < 8; ++v)
+      for (int w = v + 1; w < 8; ++w) {
+        const double dx = X[v][0] - X[w][0], dy = X[v][1] - X[w][1], dz = X[v][2] - X[w][2];
+        h2 = std::max(h2, dx * dx + dy * dy + dz * dz);
+      }
+    out.he2p2[e] = h2 * double(c.p) * double(c.p);
+  }
+  for (size_t m = 0; m < L.minfo.size(); ++m) {
+    const MortarInfo& M = L.minfo[m];
+    if (M.q == 0 || (M.ep < 0 && M.bc != 1)) continue;  // Neumann, Robin: no estimator term
+    out.tasks.push_back(mortar_task(L, M));
+    out.task_mortar.push_back(int(m));
+    out.foff.push_back((long long)out.face.size());
+    const int q = M.q;
+    gauss_legendre(q, eta, wq);
+    const Cell& cm = L.cells[M.em];
+    const int dmn = M.fm >> 1;
+    const int pm = std::max(cm.p, M.ep >= 0 ? L.cells[M.ep].p : 0);
+    for (int d = 0; d < q; ++d)
+      for (int ci = 0; ci < q; ++ci) {
+        const double s_ = eta[ci], t_ = eta[d];
+        double xim[3], x[3], J[3][3], Ji[3][3];
+        face_ref(M.fm, s_, t_, xim);
+        cell_eval(mm, cm, xim, x, J);
+        inv3(J, Ji);
+        double h = 2.0 / std::sqrt(Ji[dmn][0] * Ji[dmn][0] + Ji[dmn][1] * Ji[dmn][1] + Ji[dmn][2] * Ji[dmn][2]);
+        if (M.ep >= 0) {
+          double a, b, xip[3], xp[3], Jp[3][3], Jpi[3][3];
+          plus_coords(M.orient, M.sub, s_, t_, a, b);
+          face_ref(M.fp, a, b, xip);
+          cell_eval(mm, L.cells[M.ep], xip, xp, Jp);
+          inv3(Jp, Jpi);
+          const int dq = M.fp >> 1;
+          h = std::min(h, 2.0 / std::sqrt(Jpi[dq][0] * Jpi[dq][0] + Jpi[dq][1] * Jpi[dq][1] + Jpi[dq][2] * Jpi[dq][2]));
+        }
+        out.face.push_back(h / double(pm));
+        out.face.push_back(M.ep >= 0 ? 0.0 : exact_u(kind, P, x));
       }
   }
 }

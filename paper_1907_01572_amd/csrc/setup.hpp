@@ -123,6 +123,25 @@ void nl_coefficients(int kind, const std::vector<double>& P, const double x[3], 
 void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
                   int kind, const std::vector<double>& params, std::vector<double>& F);
 
+// the mortar kernel's record of mortar M (both sides' traces, maps, rule; slots unset)
+MortarTask mortar_task(const LevelHost& L, const MortarInfo& M);
+
+// Point data of the a posteriori estimator (Eqs. Eta2_*) on level L for the problem (kind, P):
+// per element at its volume GL points (W det J, 1 / det J, g) and h_e^2 p_e^2; one mortar-kernel
+// task per interior or Dirichlet mortar with, at its GL points (mortar frame, a + q b),
+// (h_m / p_m, g_D) (h_m as for the penalty, p_m = max(p-, p+); g_D = 0 inside).
+struct EstTables {
+  std::vector<double> vol;
+  std::vector<long long> voff;  // per element: first scalar of its (W det J, 1 / det J, g) triples
+  std::vector<double> he2p2;
+  std::vector<MortarTask> tasks;
+  std::vector<int> task_mortar;
+  std::vector<double> face;
+  std::vector<long long> foff;  // per task: first scalar of its (h_m / p_m, g_D) pairs
+};
+void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost& L, int kind,
+                      const std::vector<double>& P, EstTables& out);
+
 // one-side mortar map: rows of the 1-D matrices along the own face axes
 struct SideMap {
   int swap, flipA, flipB, halfA, halfB;  // half: 0 full, 1 lower, 2 upper
