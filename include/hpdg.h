@@ -337,6 +337,48 @@ int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, 
 int hpdg_estimate(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, const double* u_dev, double* eta2_dev,
                   double* eta2_vol_dev, void* stream);
 
+/* hp-adaptation (Sec. II.E, Alg. hpamr), host-side steps between solves.
+ *
+ * hpdg_amr_mark: marked[e] = 1 for the elements to refine, from eta2[n] (host arrays):
+ *   HPDG_MARK_FRACTION  the ceil(param n) elements of largest eta2 (0 <= param <= 1; ties: lower
+ *                       index first; the product param n is taken with a guard of 1e-9 against
+ *                       its representation error);
+ *   HPDG_MARK_MEAN      the elements with eta2 > param * mean(eta2).
+ * hpdg_amr_smooth_pred: the smooth-pred decision for every marked element (host arrays of n):
+ *   eta2 > eta2_pred[e]  -> action 1 (h-refine); its children predict
+ *                           gamma_h (1/2)^3 (1/2)^(2 p_e) eta2(e);
+ *   otherwise            -> action 2 (p-refine); it predicts gamma_p eta2(e).
+ *   An element without a prediction carries eta2_pred = +inf (every element at the start), so it
+ *   is p-refined first.  Unmarked elements: action 0, prediction unchanged.  pred_out[e] is the
+ *   prediction element e (or each of its children) carries to the next step; typical
+ *   gamma_h = 0.25, gamma_p = 0.1.
+ * hpdg_amr_adapt: apply action[e] (0 keep, 1 h-refine: 8 children of the same degree, 2 p-refine:
+ *   degree + 1, at most max_degree <= 15) to the cells of ``mesh`` (its macro fields describe the
+ *   macro-mesh, which the new mesh shares), then refine where 2:1 face balance is violated
+ *   (Sec. II.A.1; those children keep the degree).  Each old cell is replaced in place by the
+ *   cells inside it, children ordered by their bits (x fastest); origin[i] is the old cell that
+ *   new cell i lies in.  Output host arrays hold ``capacity`` cells (anchor 3 per cell; 8 n
+ *   always suffice); *n_out is the new count (also when the capacity is too small, which returns
+ *   HPDG_ERR_INVALID_ARG).  HPDG_ERR_INVALID_MESH: the input is not a valid 2:1-balanced mesh or
+ *   a cell would pass level 14.
+ * These three calls need no context and no device; their errors are reported by
+ * hpdg_last_error(NULL). */
+enum { HPDG_MARK_FRACTION = 0, HPDG_MARK_MEAN = 1 };
+int hpdg_amr_mark(const double* eta2, int64_t n, int mode, double param, uint8_t* marked);
+int hpdg_amr_smooth_pred(const double* eta2, const double* eta2_pred, const int32_t* p, const uint8_t* marked,
+                         int64_t n, double gamma_h, double gamma_p, int8_t* action, double* pred_out);
+int hpdg_amr_adapt(const hpdg_mesh_desc* mesh, const int8_t* action, int32_t max_degree, int64_t capacity,
+                   int32_t* macro, int32_t* level, int32_t* anchor, int32_t* p, int64_t* origin, int64_t* n_out);
+/* u_to_dev = u_from_dev carried from mesh ``from`` onto mesh ``to`` (level-0 FP64 vectors): both
+ * meshes have the same macro-mesh and every cell of ``to`` is a cell of ``from`` or a child of
+ * one (one level finer), of equal or higher degree -- the output of hpdg_amr_adapt.  Each new
+ * cell takes the interpolant of its old cell's polynomial at its LGL nodes (child-half and
+ * degree interpolation as in the multigrid prolongation, Sec. II.D), which is exact for these
+ * pairs.  Synchronises ``stream``.  Errors: HPDG_ERR_INVALID_ARG (other meshes, other
+ * contexts, u_from_dev == u_to_dev). */
+int hpdg_transfer(const hpdg_mesh* from, hpdg_mesh* to, const double* u_from_dev, double* u_to_dev,
+                  void* stream);
+
 /* y = A_level x (Eq. lh2 applied matrix-free): volume stiffness by sum factorisation,
  * SIPG fluxes on every mortar with hp-mortar projections (Fig. mortar).  Three stream-ordered
  * launches: the face traces of x, the mortar kernel (both sides of each mortar, into per-face

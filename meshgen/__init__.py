@@ -36,7 +36,7 @@ Conventions (the neutral mesh format, documented once here):
 from .forest import Forest, orient_map_int, face_corner_orientation  # noqa: F401
 from .meshes import (  # noqa: F401
     unit_cube, box_grid, uniform_box, cubed_sphere_shell, hp_sphere_cube, puncture_mesh, star_mesh,
-    mesh_summary,
+    mesh_summary, adapt,
 )
 from .problems import (  # noqa: F401
     problem_config1, problem_config2, problem_config3, random_vector,

@@ -35,7 +35,8 @@ EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload"
             "hpdg_nonlinear_residual", "hpdg_nonlinear_linearize", "hpdg_newton_solve",
             "hpdg_server_create", "hpdg_server_submit", "hpdg_server_poll", "hpdg_server_wait",
             "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing", "hpdg_apply_noalloc",
-            "hpdg_set_coefficient", "hpdg_estimate"]
+            "hpdg_set_coefficient", "hpdg_estimate", "hpdg_amr_mark", "hpdg_amr_smooth_pred",
+            "hpdg_amr_adapt", "hpdg_transfer"]
 
 
 class HpdgError(RuntimeError):
@@ -149,6 +150,10 @@ def load_library(path=LIB_PATH):
     lib.hpdg_apply_noalloc.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_set_coefficient.argtypes = [vp, i32, i32, vp, vp, vp]
     lib.hpdg_estimate.argtypes = [vp, ctypes.POINTER(RhsDesc), vp, vp, vp, vp]
+    lib.hpdg_amr_mark.argtypes = [vp, i64, i32, ctypes.c_double, vp]
+    lib.hpdg_amr_smooth_pred.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
+    lib.hpdg_amr_adapt.argtypes = [ctypes.POINTER(MeshDesc), vp, i32, i64, vp, vp, vp, vp, vp, vp]
+    lib.hpdg_transfer.argtypes = [vp, vp, vp, vp, vp]
     lib.hpdg_setup_smoother.argtypes = [vp, ctypes.POINTER(SmootherParams), vp, vp]
     lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
@@ -263,6 +268,64 @@ def _descriptors(mesh, penalty_C=10.0, quad_extra=1, coef=None, max_levels=0, bu
     dp.robin_gamma = robin_gamma
     dp.ec_mode = EC_MODE_DEFAULT if ec_mode is None else ec_mode
     return d, dp, keep
+
+
+# hp-adaptation (host steps of the library; no context needed)
+MARK_FRACTION, MARK_MEAN = 0, 1
+
+
+def _host_check(lib, rc):
+    if rc != OK:
+        raise HpdgError(rc, lib.hpdg_last_error(None).decode())
+
+
+def amr_mark(eta2, mode, param):
+    """Marked elements (bool array) of eta2: MARK_FRACTION (largest ceil(param E)) or MARK_MEAN
+    (eta2 > param * mean)."""
+    lib = load_library()
+    e = np.ascontiguousarray(eta2, np.float64)
+    out = np.zeros(len(e), np.uint8)
+    _host_check(lib, lib.hpdg_amr_mark(e.ctypes.data, len(e), int(mode), float(param), out.ctypes.data))
+    return out.astype(bool)
+
+
+def amr_smooth_pred(eta2, eta2_pred, p, marked, gamma_h=0.25, gamma_p=0.1):
+    """(action, prediction) per element: 0 keep, 1 h-refine, 2 p-refine; eta2_pred = inf means
+    no prediction."""
+    lib = load_library()
+    e = np.ascontiguousarray(eta2, np.float64)
+    pr = np.ascontiguousarray(eta2_pred, np.float64)
+    pp = np.ascontiguousarray(p, np.int32)
+    mk = np.ascontiguousarray(marked, np.uint8)
+    act = np.zeros(len(e), np.int8)
+    out = np.zeros(len(e), np.float64)
+    _host_check(lib, lib.hpdg_amr_smooth_pred(e.ctypes.data, pr.ctypes.data, pp.ctypes.data, mk.ctypes.data,
+                                              len(e), float(gamma_h), float(gamma_p), act.ctypes.data,
+                                              out.ctypes.data))
+    return act, out
+
+
+def amr_adapt(mesh, action, max_degree=15):
+    """(new mesh, origin): ``mesh`` (a meshgen mesh dict) with action[e] applied and 2:1 balance
+    restored; origin[i] = the old cell of new cell i."""
+    lib = load_library()
+    d, _, keep = _descriptors(mesh)
+    act = np.ascontiguousarray(action, np.int8)
+    if len(act) != d.n_elem:
+        raise ValueError("one action per element")
+    cap = 8 * d.n_elem
+    macro, level, p = (np.zeros(cap, np.int32) for _ in range(3))
+    anchor = np.zeros((cap, 3), np.int32)
+    origin = np.zeros(cap, np.int64)
+    n = ctypes.c_int64()
+    _host_check(lib, lib.hpdg_amr_adapt(ctypes.byref(d), act.ctypes.data, int(max_degree), cap, macro.ctypes.data,
+                                        level.ctypes.data, anchor.ctypes.data, p.ctypes.data, origin.ctypes.data,
+                                        ctypes.byref(n)))
+    k = n.value
+    out = dict(mesh)
+    out.update(elem_macro=macro[:k].copy(), elem_level=level[:k].copy(), elem_anchor=anchor[:k].copy(),
+               elem_p=p[:k].copy())
+    return out, origin[:k].copy()
 
 
 REQ_STATES = {0: "queued", 1: "running", 2: "done", 3: "failed"}
@@ -391,6 +454,10 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_estimate(self.h, ctypes.byref(r), _ptr(u), _ptr(eta2),
                                               _ptr(eta2_vol) if eta2_vol is not None else None,
                                               _stream(stream)))
+
+    def transfer_to(self, other, u, u_other, stream=None):
+        """u_other (level-0 vector of ``other``, an adapted copy of this mesh) = u carried over."""
+        self.ctx.check(self.lib.hpdg_transfer(self.h, other.h, _ptr(u), _ptr(u_other), _stream(stream)))
 
     def apply(self, x, y, level=0, stream=None):
         prec = F32 if x.dtype.itemsize == 4 else F64

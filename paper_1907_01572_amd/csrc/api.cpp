@@ -1014,26 +1014,15 @@ void check_mesh(const hpdg_mesh_desc* D) {
 }
 
 void build_levels(hpdg_mesh* M);
+void macro_mesh_from(const hpdg_mesh_desc* desc, MacroMesh& mm);
+std::vector<Cell> cells_from(const hpdg_mesh_desc* desc);
 
 // host side of an upload: macro mesh, level hierarchy, geometry / mortar / transfer tables
 std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* desc, const hpdg_disc_params* disc) {
   check_mesh(desc);
   auto M = std::make_unique<hpdg_mesh>();
   M->ctx = ctx;
-  const int nm = desc->n_macro;
-  M->mm.macros.resize(nm);
-  for (int m = 0; m < nm; ++m) {
-    M->mm.macros[m].kind = desc->macro_kind[m];
-    if (desc->macro_kind[m] < 0 || desc->macro_kind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
-    for (int f = 0; f < 6; ++f)
-      if (desc->macro_bc[6 * m + f] < 0 || desc->macro_bc[6 * m + f] > 3)
-        throw Error(HPDG_ERR_INVALID_MESH, "unknown boundary kind");
-    std::memcpy(M->mm.macros[m].par, desc->macro_params + 16 * m, 16 * sizeof(double));
-  }
-  M->mm.nbr.assign(desc->macro_nbr, desc->macro_nbr + 6 * nm);
-  M->mm.nbr_face.assign(desc->macro_nbr_face, desc->macro_nbr_face + 6 * nm);
-  M->mm.nbr_orient.assign(desc->macro_nbr_orient, desc->macro_nbr_orient + 6 * nm);
-  M->mm.bc.assign(desc->macro_bc, desc->macro_bc + 6 * nm);
+  macro_mesh_from(desc, M->mm);
   if (disc) {
     M->dp.C = disc->penalty_C > 0 ? disc->penalty_C : 10.0;
     M->dp.quad_extra = disc->quad_extra >= 0 ? disc->quad_extra : 1;
@@ -1051,9 +1040,33 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
   M->tab.build();
   // hierarchy
   LevelHost L0;
-  L0.cells.resize(desc->n_elem);
+  L0.cells = cells_from(desc);
+  M->H.push_back(std::move(L0));
+  build_levels(M.get());
+  return M;
+}
+
+void macro_mesh_from(const hpdg_mesh_desc* desc, MacroMesh& mm) {
+  const int nm = desc->n_macro;
+  mm.macros.resize(nm);
+  for (int m = 0; m < nm; ++m) {
+    mm.macros[m].kind = desc->macro_kind[m];
+    if (desc->macro_kind[m] < 0 || desc->macro_kind[m] > 2) throw Error(HPDG_ERR_INVALID_MESH, "unknown map kind");
+    for (int f = 0; f < 6; ++f)
+      if (desc->macro_bc[6 * m + f] < 0 || desc->macro_bc[6 * m + f] > 3)
+        throw Error(HPDG_ERR_INVALID_MESH, "unknown boundary kind");
+    std::memcpy(mm.macros[m].par, desc->macro_params + 16 * m, 16 * sizeof(double));
+  }
+  mm.nbr.assign(desc->macro_nbr, desc->macro_nbr + 6 * nm);
+  mm.nbr_face.assign(desc->macro_nbr_face, desc->macro_nbr_face + 6 * nm);
+  mm.nbr_orient.assign(desc->macro_nbr_orient, desc->macro_nbr_orient + 6 * nm);
+  mm.bc.assign(desc->macro_bc, desc->macro_bc + 6 * nm);
+}
+
+std::vector<Cell> cells_from(const hpdg_mesh_desc* desc) {
+  std::vector<Cell> cells(size_t(desc->n_elem));
   for (long long e = 0; e < desc->n_elem; ++e) {
-    Cell& c = L0.cells[e];
+    Cell& c = cells[e];
     c.macro = desc->elem_macro[e];
     c.level = desc->elem_level[e];
     c.a[0] = desc->elem_anchor[3 * e];
@@ -1061,9 +1074,7 @@ std::unique_ptr<hpdg_mesh> build_mesh_host(hpdg_ctx* ctx, const hpdg_mesh_desc* 
     c.a[2] = desc->elem_anchor[3 * e + 2];
     c.p = desc->elem_p[e];
   }
-  M->H.push_back(std::move(L0));
-  build_levels(M.get());
-  return M;
+  return cells;
 }
 
 // the level hierarchy below H[0] (surrogate coarsening, Sec. II.D.3) and every level's tables;
@@ -1284,6 +1295,46 @@ void estimate_impl(hpdg_mesh* M, const hpdg_rhs_desc* rhs, const double* u, doub
   launch_fill<double>((long long)h.minfo.size(), 0.0, E.ef.out, s);
   launch_estimator(V, u, E.ev, E.ef, E.n_tasks, eta2_vol ? eta2_vol : E.vpart, eta2, s);
   HIPCHK(hipGetLastError());
+}
+
+// u_to = u_from carried from mesh ``from`` onto mesh ``to`` (the same macro-mesh; every cell of
+// ``to`` is a cell of ``from`` or one of its children, of equal or higher degree): the child-half
+// and degree interpolation of the multigrid prolongation, exact for these pairs
+void transfer_impl(const hpdg_mesh* A, hpdg_mesh* B, const double* u_from, double* u_to, hipStream_t s) {
+  const MacroMesh &ma = A->mm, &mb = B->mm;
+  bool same = ma.macros.size() == mb.macros.size() && ma.nbr == mb.nbr && ma.nbr_face == mb.nbr_face &&
+              ma.nbr_orient == mb.nbr_orient && ma.bc == mb.bc;
+  for (size_t m = 0; same && m < ma.macros.size(); ++m)
+    same = ma.macros[m].kind == mb.macros[m].kind &&
+           std::memcmp(ma.macros[m].par, mb.macros[m].par, sizeof(ma.macros[m].par)) == 0;
+  if (!same) throw Error(HPDG_ERR_INVALID_ARG, "transfer: the meshes have different macro-meshes");
+  LevelHost fine;
+  fine.cells = B->H[0].cells;
+  fine.einfo = B->H[0].einfo;
+  try {
+    build_transfer(fine, A->H[0]);
+  } catch (const Error& e) {
+    throw Error(HPDG_ERR_INVALID_ARG, std::string("transfer: ") + e.what());
+  }
+  TransferInfo* ti = B->upload_raw(fine.tinfo, s);  // synchronises s
+  hipError_t err;
+  {
+    TransferView<double> V;
+    V.tinfo = ti;
+    V.cstart = nullptr;
+    V.clist = nullptr;
+    V.tab = B->table<double>();
+    V.tv = B->tabview();
+    V.n_fine = (long long)fine.cells.size();
+    V.n_coarse = (long long)A->H[0].cells.size();
+    V.nmax = std::max(A->H[0].nmax, B->H[0].nmax);
+    launch_fill<double>(B->H[0].ndof, 0.0, u_to, s);
+    launch_prolong_add<double>(V, u_from, u_to, s);
+    err = hipGetLastError();
+    if (err == hipSuccess) err = hipStreamSynchronize(s);
+  }
+  if (err == hipSuccess) B->release(ti);
+  HIPCHK(err);
 }
 
 void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, double* lambda_max, hipStream_t s) {
@@ -1906,6 +1957,84 @@ int hpdg_estimate(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, const double* u_dev
   return guarded(mesh->ctx, [&] {
     HIPCHK(hipSetDevice(mesh->ctx->device));
     estimate_impl(mesh, rhs, u_dev, eta2_dev, eta2_vol_dev, S(stream));
+  });
+}
+
+int hpdg_transfer(const hpdg_mesh* from, hpdg_mesh* to, const double* u_from_dev, double* u_to_dev,
+                  void* stream) {
+  if (!from || !to) return HPDG_ERR_INVALID_ARG;
+  if (!u_from_dev || !u_to_dev || u_from_dev == u_to_dev || from->ctx != to->ctx)
+    return fail(to->ctx, HPDG_ERR_INVALID_ARG, "invalid transfer arguments");
+  return guarded(to->ctx, [&] {
+    HIPCHK(hipSetDevice(to->ctx->device));
+    transfer_impl(from, to, u_from_dev, u_to_dev, S(stream));
+  });
+}
+
+int hpdg_amr_mark(const double* eta2, int64_t n, int mode, double param, uint8_t* marked) {
+  if (!eta2 || !marked || n <= 0 || !std::isfinite(param) || (mode != HPDG_MARK_FRACTION && mode != HPDG_MARK_MEAN) ||
+      (mode == HPDG_MARK_FRACTION && !(param >= 0 && param <= 1)))
+    return fail(nullptr, HPDG_ERR_INVALID_ARG, "invalid marking arguments");
+  for (int64_t e = 0; e < n; ++e)
+    if (!std::isfinite(eta2[e])) return fail(nullptr, HPDG_ERR_INVALID_ARG, "non-finite estimate");
+  std::fill(marked, marked + n, uint8_t(0));
+  if (mode == HPDG_MARK_MEAN) {
+    double sum = 0;
+    for (int64_t e = 0; e < n; ++e) sum += eta2[e];
+    const double thr = param * (sum / double(n));
+    for (int64_t e = 0; e < n; ++e) marked[e] = eta2[e] > thr ? 1 : 0;
+    return HPDG_OK;
+  }
+  return guarded(nullptr, [&] {
+    const int64_t k = std::min<int64_t>(n, (int64_t)std::ceil(param * double(n) - 1e-9));
+    std::vector<int64_t> order(static_cast<size_t>(n));
+    for (int64_t e = 0; e < n; ++e) order[e] = e;
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return eta2[a] > eta2[b]; });
+    for (int64_t i = 0; i < k; ++i) marked[order[i]] = 1;
+  });
+}
+
+int hpdg_amr_smooth_pred(const double* eta2, const double* eta2_pred, const int32_t* p, const uint8_t* marked,
+                         int64_t n, double gamma_h, double gamma_p, int8_t* action, double* pred_out) {
+  if (!eta2 || !eta2_pred || !p || !marked || !action || !pred_out || n <= 0 || !(gamma_h > 0) || !(gamma_p > 0))
+    return fail(nullptr, HPDG_ERR_INVALID_ARG, "invalid smooth-pred arguments");
+  for (int64_t e = 0; e < n; ++e) {
+    action[e] = 0;
+    pred_out[e] = eta2_pred[e];
+    if (!marked[e]) continue;
+    if (eta2[e] > eta2_pred[e]) {  // worse than predicted: not smooth, h-refine
+      action[e] = 1;
+      pred_out[e] = gamma_h * std::pow(0.5, 3 + 2 * p[e]) * eta2[e];
+    } else {  // as predicted (or no prediction yet): p-refine
+      action[e] = 2;
+      pred_out[e] = gamma_p * eta2[e];
+    }
+  }
+  return HPDG_OK;
+}
+
+int hpdg_amr_adapt(const hpdg_mesh_desc* mesh, const int8_t* action, int32_t max_degree, int64_t capacity,
+                   int32_t* macro, int32_t* level, int32_t* anchor, int32_t* p, int64_t* origin, int64_t* n_out) {
+  if (!mesh || !action || !n_out || !macro || !level || !anchor || !p || !origin || max_degree < 1 ||
+      max_degree > kMaxN - 1)
+    return fail(nullptr, HPDG_ERR_INVALID_ARG, "invalid adaptation arguments");
+  return guarded(nullptr, [&] {
+    check_mesh(mesh);
+    MacroMesh mm;
+    macro_mesh_from(mesh, mm);
+    const std::vector<Cell> cells = cells_from(mesh);
+    std::vector<Cell> out;
+    std::vector<int> org;
+    adapt_cells(mm, cells, reinterpret_cast<const signed char*>(action), max_degree, out, org);
+    *n_out = (int64_t)out.size();
+    if (*n_out > capacity) throw Error(HPDG_ERR_INVALID_ARG, "adaptation: output capacity too small");
+    for (size_t e = 0; e < out.size(); ++e) {
+      macro[e] = out[e].macro;
+      level[e] = out[e].level;
+      for (int d = 0; d < 3; ++d) anchor[3 * e + d] = out[e].a[d];
+      p[e] = out[e].p;
+      origin[e] = org[e];
+    }
   });
 }
 

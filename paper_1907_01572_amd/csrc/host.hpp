@@ -52,6 +52,12 @@ struct Mortar {
 std::vector<Mortar> find_mortars(const MacroMesh& mm, const std::vector<Cell>& cells);
 // one coarsening step: false when nothing coarsens
 bool coarsen_cells(const MacroMesh& mm, const std::vector<Cell>& fine, std::vector<Cell>& coarse);
+// hp-adaptation (Alg. hpamr): action per cell 0 keep, 1 h-refine (8 children of the same
+// degree), 2 p-refine (degree + 1, at most max_p); then 2:1 restoration.  out: the new cells,
+// each old cell replaced in place by the cells inside it (children by their bits, x fastest);
+// origin: the old cell each new cell lies in
+void adapt_cells(const MacroMesh& mm, const std::vector<Cell>& cells, const signed char* action, int max_p,
+                 std::vector<Cell>& out, std::vector<int>& origin);
 // for each fine cell: coarse cell index and child bits (-1 when the cell is identical)
 void parent_cells(const std::vector<Cell>& fine, const std::vector<Cell>& coarse,
                   std::vector<int>& parent, std::vector<int>& bits);

@@ -52,6 +52,52 @@ bool across(const MacroMesh& mm, int m, int l, const int a[3], int f, int& mb, i
   return true;
 }
 
+// 2:1 restoration: a leaf adjacent to a leaf two or more levels finer is refined (its
+// children keep its degree), until no such pair is left
+void balance_leaves(const MacroMesh& mm, std::unordered_map<uint64_t, Cell>& leaves) {
+  auto covering = [&](int m, int l, const int a[3]) -> Cell* {
+    for (int lev = l; lev >= 0; --lev) {
+      int sh = l - lev;
+      auto it = leaves.find(key_of(m, lev, a[0] >> sh, a[1] >> sh, a[2] >> sh));
+      if (it != leaves.end()) return &it->second;
+    }
+    return nullptr;
+  };
+  bool changed = true;
+  while (changed) {
+    changed = false;
+    std::vector<Cell> snapshot;
+    snapshot.reserve(leaves.size());
+    for (auto& kv : leaves) snapshot.push_back(kv.second);
+    std::sort(snapshot.begin(), snapshot.end(), [](const Cell& x, const Cell& y) {
+      if (x.level != y.level) return x.level > y.level;
+      if (x.macro != y.macro) return x.macro < y.macro;
+      for (int d = 0; d < 3; ++d)
+        if (x.a[d] != y.a[d]) return x.a[d] < y.a[d];
+      return false;
+    });
+    for (const Cell& c : snapshot) {
+      if (!leaves.count(key_of(c.macro, c.level, c.a[0], c.a[1], c.a[2]))) continue;
+      for (int f = 0; f < 6; ++f) {
+        int mb, b[3], fb, o;
+        if (!across(mm, c.macro, c.level, c.a, f, mb, b, fb, o)) continue;
+        Cell* lf = covering(mb, c.level, b);
+        if (lf && lf->level <= c.level - 2) {
+          Cell par = *lf;
+          leaves.erase(key_of(par.macro, par.level, par.a[0], par.a[1], par.a[2]));
+          for (int z = 0; z < 8; ++z) {
+            Cell k{par.macro, par.level + 1,
+                   {2 * par.a[0] + (z & 1), 2 * par.a[1] + ((z >> 1) & 1), 2 * par.a[2] + (z >> 2)},
+                   par.p};
+            leaves[key_of(k.macro, k.level, k.a[0], k.a[1], k.a[2])] = k;
+          }
+          changed = true;
+        }
+      }
+    }
+  }
+}
+
 }  // namespace
 
 std::vector<Mortar> find_mortars(const MacroMesh& mm, const std::vector<Cell>& cells) {
@@ -131,48 +177,7 @@ bool coarsen_cells(const MacroMesh& mm, const std::vector<Cell>& fine, std::vect
       const Cell& c = fine[e];
       leaves[key_of(c.macro, c.level, c.a[0], c.a[1], c.a[2])] = c;
     }
-  // 2:1 restoration: a leaf adjacent to a leaf two or more levels finer is refined
-  auto covering = [&](int m, int l, const int a[3]) -> Cell* {
-    for (int lev = l; lev >= 0; --lev) {
-      int sh = l - lev;
-      auto it = leaves.find(key_of(m, lev, a[0] >> sh, a[1] >> sh, a[2] >> sh));
-      if (it != leaves.end()) return &it->second;
-    }
-    return nullptr;
-  };
-  bool changed = true;
-  while (changed) {
-    changed = false;
-    std::vector<Cell> snapshot;
-    snapshot.reserve(leaves.size());
-    for (auto& kv : leaves) snapshot.push_back(kv.second);
-    std::sort(snapshot.begin(), snapshot.end(), [](const Cell& x, const Cell& y) {
-      if (x.level != y.level) return x.level > y.level;
-      if (x.macro != y.macro) return x.macro < y.macro;
-      for (int d = 0; d < 3; ++d)
-        if (x.a[d] != y.a[d]) return x.a[d] < y.a[d];
-      return false;
-    });
-    for (const Cell& c : snapshot) {
-      if (!leaves.count(key_of(c.macro, c.level, c.a[0], c.a[1], c.a[2]))) continue;
-      for (int f = 0; f < 6; ++f) {
-        int mb, b[3], fb, o;
-        if (!across(mm, c.macro, c.level, c.a, f, mb, b, fb, o)) continue;
-        Cell* lf = covering(mb, c.level, b);
-        if (lf && lf->level <= c.level - 2) {
-          Cell par = *lf;
-          leaves.erase(key_of(par.macro, par.level, par.a[0], par.a[1], par.a[2]));
-          for (int z = 0; z < 8; ++z) {
-            Cell k{par.macro, par.level + 1,
-                   {2 * par.a[0] + (z & 1), 2 * par.a[1] + ((z >> 1) & 1), 2 * par.a[2] + (z >> 2)},
-                   par.p};
-            leaves[key_of(k.macro, k.level, k.a[0], k.a[1], k.a[2])] = k;
-          }
-          changed = true;
-        }
-      }
-    }
-  }
+  balance_leaves(mm, leaves);
   if (leaves.size() == fine.size()) {
     bool same = true;
     for (const Cell& c : fine)
@@ -214,6 +219,55 @@ void parent_cells(const std::vector<Cell>& fine, const std::vector<Cell>& coarse
     parent[e] = it->second;
     bits[e] = (c.a[0] & 1) | ((c.a[1] & 1) << 1) | ((c.a[2] & 1) << 2);
   }
+}
+
+void adapt_cells(const MacroMesh& mm, const std::vector<Cell>& cells, const signed char* action, int max_p,
+                 std::vector<Cell>& out, std::vector<int>& origin) {
+  (void)find_mortars(mm, cells);  // the input must be a valid 2:1-balanced mesh
+  std::unordered_map<uint64_t, Cell> leaves;
+  leaves.reserve(cells.size() * 2);
+  for (size_t e = 0; e < cells.size(); ++e) {
+    const Cell& c = cells[e];
+    const int act = action[e];
+    if (act < 0 || act > 2) throw Error(-1, "unknown refinement action");
+    if (act == 1) {
+      if (c.level >= 14) throw Error(-2, "refinement beyond level 14");
+      for (int z = 0; z < 8; ++z) {
+        Cell k{c.macro, c.level + 1, {2 * c.a[0] + (z & 1), 2 * c.a[1] + ((z >> 1) & 1), 2 * c.a[2] + (z >> 2)}, c.p};
+        leaves[key_of(k.macro, k.level, k.a[0], k.a[1], k.a[2])] = k;
+      }
+    } else {
+      Cell k = c;
+      if (act == 2) k.p = std::min(c.p + 1, std::max(max_p, c.p));
+      leaves[key_of(k.macro, k.level, k.a[0], k.a[1], k.a[2])] = k;
+    }
+  }
+  balance_leaves(mm, leaves);
+  for (const auto& kv : leaves)
+    if (kv.second.level > 14) throw Error(-2, "refinement beyond level 14");
+  // each old cell is replaced in place by the leaves inside it, children in the order of their
+  // bits (x fastest)
+  out.clear();
+  origin.clear();
+  std::vector<Cell> stack;
+  for (size_t e = 0; e < cells.size(); ++e) {
+    stack.assign(1, cells[e]);
+    while (!stack.empty()) {
+      const Cell c = stack.back();
+      stack.pop_back();
+      auto it = leaves.find(key_of(c.macro, c.level, c.a[0], c.a[1], c.a[2]));
+      if (it != leaves.end()) {
+        out.push_back(it->second);
+        origin.push_back(int(e));
+        continue;
+      }
+      if (c.level >= 14) throw Error(-2, "mesh adaptation: a cell without leaves");
+      for (int z = 7; z >= 0; --z)
+        stack.push_back(Cell{c.macro, c.level + 1,
+                             {2 * c.a[0] + (z & 1), 2 * c.a[1] + ((z >> 1) & 1), 2 * c.a[2] + (z >> 2)}, c.p});
+    }
+  }
+  if (out.size() != leaves.size()) throw Error(-2, "mesh adaptation: leaves outside the old cells");
 }
 
 }  // namespace hpdg
