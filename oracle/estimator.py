@@ -26,6 +26,11 @@ collocation derivative of the volume rule (exact on affine elements with a const
 contravariant flux is a polynomial of degree <= p in each coordinate); h_e is the largest
 distance between two vertices of the element; Robin and Neumann mortars add no term.
 
+Fiducial grid (Sec. II.E, applied to the compactified shell in Sec. III.C): the integrands
+(R, the jumps) are evaluated on the physical grid, while the integration weights (W det J,
+w S), h_e and h_m (and with it sigma) come from a second grid of the same cells under other
+macro maps, at the same reference points.
+
 Driver (Alg. hpamr, smooth-pred): an element marked for refinement is h-refined when its
 eta2 exceeds the predicted eta2_pred, its children then predicting
 gamma_h (1/2)^d (1/2)^(2 p_e) eta2(e); otherwise it is p-refined and predicts gamma_p eta2(e).
@@ -49,13 +54,28 @@ def element_diameters(mesh):
     return d.reshape(E, -1).max(axis=1)
 
 
-def estimate(op, u, problem=None):
+def _face_metric(mesh, elems, xi, f):
+    """S = det J |grad xi_d| and |grad xi_d| (d the face's axis) at reference points xi of elems."""
+    _, J = geometry.element_map(mesh, elems[:, None], xi[None])
+    nrm = np.linalg.norm(np.linalg.inv(J)[:, :, f // 2, :], axis=-1)
+    return np.linalg.det(J) * nrm, nrm
+
+
+def estimate(op, u, problem=None, fiducial=None):
     """eta2(e) of the nodal vector u on the mesh of ``op`` (an operator.SIPG); returns a dict
-    with eta2 (per element), eta2_vol (per element) and eta2_face (per mortar of op.mortars)."""
+    with eta2 (per element), eta2_vol (per element), eta2_face (per mortar of op.mortars) and
+    its flux-jump and value-jump parts eta2_flux, eta2_jump.  ``fiducial``: a mesh with the same
+    cells (and macro connectivity) whose geometry weights the integrals and gives h_e, h_m."""
     problem = problem if problem is not None else op.problem
     u = np.asarray(u, float)
     mesh = op.mesh
-    h_e = element_diameters(mesh)
+    geo = mesh if fiducial is None else fiducial
+    if fiducial is not None:
+        for k in ("elem_macro", "elem_level", "elem_anchor", "elem_p", "macro_nbr", "macro_nbr_face",
+                  "macro_nbr_orient"):
+            if not np.array_equal(np.asarray(mesh[k]), np.asarray(fiducial[k])):
+                raise ValueError("the fiducial grid must have the same cells and connectivity")
+    h_e = element_diameters(geo)
     p_e = mesh["elem_p"].astype(float)
     eta2_vol = np.zeros(op.E)
     for g in op.vgroups:
@@ -68,6 +88,10 @@ def estimate(op, u, problem=None):
         d2 = np.einsum("ck,bj,ai,ekji->ecba", Dt, B, B, U, optimize=True)
         grad = np.stack([d0, d1, d2], axis=-1).reshape(len(U), q ** 3, 3)
         W, det = g["W"], g["det"]
+        wdet = W * det  # the integration weight: physical, or the fiducial grid's
+        if fiducial is not None:
+            _, Jf = geometry.element_map(geo, elems[:, None], g["xi"][None])
+            wdet = W * np.linalg.det(Jf)
         # contravariant flux det J k (J^-1 J^-T grad_xi u)_d = (G grad_xi u)_d / W
         F = (np.einsum("epdc,epc->epd", g["G"], grad) / W[None, :, None]).reshape(len(U), q, q, q, 3)
         eta, _ = rules.gl(q)
@@ -79,13 +103,25 @@ def estimate(op, u, problem=None):
         if g["M"] is not None:
             uq = np.einsum("ck,bj,ai,ekji->ecba", B, B, B, U, optimize=True).reshape(len(U), -1)
             R = R - (g["M"] / (W * det)) * uq
-        eta2_vol[elems] = h_e[elems] ** 2 * p_e[elems] ** 2 * np.sum(W * det * R * R, axis=1)
+        eta2_vol[elems] = h_e[elems] ** 2 * p_e[elems] ** 2 * np.sum(wdet * R * R, axis=1)
     eta2 = eta2_vol.copy()
     eta2_face = np.zeros(len(op.mortars))
+    eta2_flux = np.zeros(len(op.mortars))
+    eta2_jump = np.zeros(len(op.mortars))
     for g in op.fgroups:
         if g["robin"]:
             continue
-        wS, sig = g["wS"], g["sigma"]
+        wS, sig, hmin = g["wS"], g["sigma"], g["hmin"]
+        if fiducial is not None:
+            fm, fp = g["key"][3], g["key"][4]
+            Sf, nrf = _face_metric(geo, g["em"], g["xim"], fm)
+            hf = 2.0 / nrf
+            if "ep" in g:
+                _, nrp = _face_metric(geo, g["ep"], g["xip"], fp)
+                hf = np.minimum(hf, 2.0 / nrp)
+            wS = g["wst"][None, :] * Sf
+            sig = sig * hmin / hf  # sigma = C p_m^2 max(k) / h_m with the fiducial h_m
+            hmin = hf
         Um = u[g["idx_m"]]
         um = Um @ g["Vm"].T
         gm = np.einsum("mpd,dpa,ma->mp", g["mvec_m"], g["Dm"], Um)  # n-.grad u-
@@ -95,15 +131,20 @@ def estimate(op, u, problem=None):
             gp = np.einsum("mpd,dpa,ma->mp", g["mvec_p"], g["Dp"], Up)  # n+.grad u+
             J1 = g["kx"] * gm + g["kp"] * gp
             J2 = um - up
-            val = np.sum(wS * (g["hmin"] / g["pm"] * J1 * J1 + sig * J2 * J2), axis=1)
+            flux = np.sum(wS * hmin / g["pm"] * J1 * J1, axis=1)
+            jump = np.sum(wS * sig * J2 * J2, axis=1)
+            val = flux + jump
             np.add.at(eta2, g["em"], val)
             np.add.at(eta2, g["ep"], val)
+            eta2_flux[g["mis"]] = flux
         else:
             J3 = um - problems.dirichlet_g(problem, g["x"])
             val = np.sum(wS * sig * J3 * J3, axis=1)
+            jump = val
             np.add.at(eta2, g["em"], val)
         eta2_face[g["mis"]] = val
-    return dict(eta2=eta2, eta2_vol=eta2_vol, eta2_face=eta2_face)
+        eta2_jump[g["mis"]] = jump
+    return dict(eta2=eta2, eta2_vol=eta2_vol, eta2_face=eta2_face, eta2_flux=eta2_flux, eta2_jump=eta2_jump)
 
 
 def mark_fraction(eta2, fraction):

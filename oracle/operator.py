@@ -160,7 +160,7 @@ class SIPG:
                 M = W * det * self.c_at(elems[:, None], xie, x)
             idx = self.offsets[elems][:, None] + np.arange(n ** 3)[None, :]
             self.vgroups.append(dict(n=n, q=q, elems=elems, B=B, Dt=Dt, G=G, M=M, idx=idx,
-                                     x=x, W=W, det=det))
+                                     x=x, W=W, det=det, xi=xi))
 
     def _volume(self, u, y):
         for g in self.vgroups:
@@ -218,7 +218,7 @@ class SIPG:
             pm = nm - 1
             km = self.k_at(em[:, None], np.broadcast_to(xim, x.shape), x)
             kp = km
-            g = dict(key=key, mis=np.array(mis), em=em, wS=wS, x=x, Vm=Vm, Dm=Dm,
+            g = dict(key=key, mis=np.array(mis), em=em, wS=wS, x=x, Vm=Vm, Dm=Dm, xim=xim, wst=wst,
                      mvec_m=np.einsum("mpdi,mpi->mpd", Jim, nhat), nhat=nhat,
                      idx_m=self.offsets[em][:, None] + np.arange(nm ** 3)[None, :])
             if npl:
@@ -233,7 +233,7 @@ class SIPG:
                 hmin = np.minimum(hmin, 2.0 / nrp)
                 pm = max(pm, npl - 1)
                 kp = self.k_at(ep[:, None], np.broadcast_to(xip, xp.shape), xp)
-                g.update(ep=ep, Vp=Vp, Dp=Dp, xp=xp,
+                g.update(ep=ep, Vp=Vp, Dp=Dp, xp=xp, xip=xip,
                          mvec_p=np.einsum("mpdi,mpi->mpd", Jip, -nhat),
                          idx_p=self.offsets[ep][:, None] + np.arange(npl ** 3)[None, :])
             g["robin"] = bc == ROBIN

@@ -162,3 +162,49 @@ def test_marking_fraction_and_mean():
     assert list(np.flatnonzero(est.mark_fraction(eta2, 0.4))) == [1, 3]
     assert list(np.flatnonzero(est.mark_fraction(eta2, 0.5))) == [1, 2, 3]
     assert list(np.flatnonzero(est.mark_mean(eta2, 1.0))) == [1, 2, 3]
+
+
+def _scaled(mesh, s):
+    """The same cells under macro maps composed with x -> s x."""
+    out = dict(mesh)
+    par = np.array(mesh["macro_params"], float, copy=True)
+    for m, kind in enumerate(mesh["macro_kind"]):
+        if kind == meshgen.meshes.AFFINE:
+            par[m, 0:12] *= s
+        elif kind == meshgen.meshes.SHELL:
+            par[m, [10, 11, 13]] *= s  # r_in, r_out, r_break
+        else:
+            par[m, [10, 11]] *= s      # cube half-side, sphere radius
+    out["macro_params"] = par
+    return out
+
+
+@pytest.mark.parametrize("name", ["box_2to1_p3", "hp_p2_4", "shell"])
+def test_fiducial_grid_weights_scale_with_the_grid(name):
+    # a fiducial grid equal to the physical one changes nothing; the physical grid scaled by s
+    # as the fiducial one multiplies the volume parts by s^5 (h_e^2 det J), the flux-jump parts
+    # by s^3 (h_m S) and the value-jump parts by s (sigma S), the integrands staying the same
+    mesh = MESHES[name]() if name in MESHES else meshgen.cubed_sphere_shell(level=1, p=3, r_out=1e3)
+    prob = meshgen.problem_config1()
+    op = SIPG(mesh, prob)
+    u = op.interpolate(lambda x: problems.exact_u(prob, x)) + 0.05 * np.random.default_rng(2).standard_normal(op.ndof)
+    r = est.estimate(op, u, prob)
+    same = est.estimate(op, u, prob, fiducial=mesh)
+    for k in r:
+        assert np.allclose(same[k], r[k], rtol=1e-13, atol=0)
+    s = 3.0
+    f = est.estimate(op, u, prob, fiducial=_scaled(mesh, s))
+    assert np.allclose(f["eta2_vol"], s ** 5 * r["eta2_vol"], rtol=1e-11)
+    assert np.allclose(f["eta2_flux"], s ** 3 * r["eta2_flux"], rtol=1e-11)
+    assert np.allclose(f["eta2_jump"], s * r["eta2_jump"], rtol=1e-11)
+    assert np.allclose(f["eta2_face"], f["eta2_flux"] + f["eta2_jump"], rtol=1e-14)
+    assert r["eta2_flux"].max() > 0 and r["eta2_jump"].max() > 0
+
+
+def test_fiducial_grid_refuses_other_cells():
+    mesh = MESHES["box_2to1_p3"]()
+    prob = meshgen.problem_config1()
+    op = SIPG(mesh, prob)
+    other = meshgen.box_grid((2, 1, 1), 1, 3)
+    with pytest.raises(ValueError):
+        est.estimate(op, np.zeros(op.ndof), prob, fiducial=other)
