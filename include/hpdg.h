@@ -336,6 +336,14 @@ int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, 
  * missing arguments, eta2_dev == eta2_vol_dev), HPDG_ERR_UNSUPPORTED (degree above 8). */
 int hpdg_estimate(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, const double* u_dev, double* eta2_dev,
                   double* eta2_vol_dev, void* stream);
+/* The grid the estimator's integrals are taken on (Sec. II.E, the fiducial grid; Sec. III.C uses
+ * an unstretched twin of a compactified shell): the macro maps of ``grid`` (its macro fields;
+ * its cells are ignored) with the mesh's cells.  The integrands (R and the jumps) stay on the
+ * physical grid; W det J, w S, h_e and h_m (and with it sigma) come from ``grid`` at the same
+ * reference points.  NULL restores the physical grid.  Takes effect at the next hpdg_estimate.
+ * Errors: HPDG_ERR_INVALID_MESH (another macro count or connectivity; a fiducial cell with
+ * det J <= 0 is reported by hpdg_estimate). */
+int hpdg_set_estimator_grid(hpdg_mesh* mesh, const hpdg_mesh_desc* grid);
 
 /* hp-adaptation (Sec. II.E, Alg. hpamr), host-side steps between solves.
  *

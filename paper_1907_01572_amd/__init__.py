@@ -36,7 +36,7 @@ EXPORTED = ["hpdg_create", "hpdg_destroy", "hpdg_last_error", "hpdg_mesh_upload"
             "hpdg_server_create", "hpdg_server_submit", "hpdg_server_poll", "hpdg_server_wait",
             "hpdg_server_destroy", "hpdg_timing_enable", "hpdg_kernel_timing", "hpdg_apply_noalloc",
             "hpdg_set_coefficient", "hpdg_estimate", "hpdg_amr_mark", "hpdg_amr_smooth_pred",
-            "hpdg_amr_adapt", "hpdg_transfer"]
+            "hpdg_amr_adapt", "hpdg_transfer", "hpdg_set_estimator_grid"]
 
 
 class HpdgError(RuntimeError):
@@ -154,6 +154,7 @@ def load_library(path=LIB_PATH):
     lib.hpdg_amr_smooth_pred.argtypes = [vp, vp, vp, vp, i64, ctypes.c_double, ctypes.c_double, vp, vp]
     lib.hpdg_amr_adapt.argtypes = [ctypes.POINTER(MeshDesc), vp, i32, i64, vp, vp, vp, vp, vp, vp]
     lib.hpdg_transfer.argtypes = [vp, vp, vp, vp, vp]
+    lib.hpdg_set_estimator_grid.argtypes = [vp, ctypes.POINTER(MeshDesc)]
     lib.hpdg_setup_smoother.argtypes = [vp, ctypes.POINTER(SmootherParams), vp, vp]
     lib.hpdg_smooth.argtypes = [vp, i32, i32, vp, vp, i32, vp]
     lib.hpdg_vcycle.argtypes = [vp, i32, vp, vp, vp]
@@ -454,6 +455,15 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_estimate(self.h, ctypes.byref(r), _ptr(u), _ptr(eta2),
                                               _ptr(eta2_vol) if eta2_vol is not None else None,
                                               _stream(stream)))
+
+    def set_estimator_grid(self, grid=None):
+        """The fiducial grid of the estimator: a mesh dict with this mesh's macro connectivity
+        (its macro maps are used); None: the physical grid."""
+        if grid is None:
+            self.ctx.check(self.lib.hpdg_set_estimator_grid(self.h, None))
+            return
+        d, _, keep = _descriptors(grid)
+        self.ctx.check(self.lib.hpdg_set_estimator_grid(self.h, ctypes.byref(d)))
 
     def transfer_to(self, other, u, u_other, stream=None):
         """u_other (level-0 vector of ``other``, an adapted copy of this mesh) = u carried over."""

@@ -160,6 +160,7 @@ struct hpdg_mesh {
     double* vpart = nullptr;
     std::vector<void*> ptrs;
   } est;
+  std::unique_ptr<MacroMesh> est_grid;  // the estimator's fiducial grid (null: the physical one)
 
   template <typename T>
   T* alloc(size_t count) {
@@ -1272,7 +1273,7 @@ void estimate_impl(hpdg_mesh* M, const hpdg_rhs_desc* rhs, const double* u, doub
     for (void* ptr : E.ptrs) M->release(ptr);
     E = hpdg_mesh::EstCache{};
     EstTables t;
-    estimator_tables(M->mm, M->dp, h, rhs->kind, P, t);
+    estimator_tables(M->mm, M->est_grid.get(), M->dp, h, rhs->kind, P, t);
     auto keep = [&](auto* ptr) {
       E.ptrs.push_back(ptr);
       return ptr;
@@ -1957,6 +1958,27 @@ int hpdg_estimate(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, const double* u_dev
   return guarded(mesh->ctx, [&] {
     HIPCHK(hipSetDevice(mesh->ctx->device));
     estimate_impl(mesh, rhs, u_dev, eta2_dev, eta2_vol_dev, S(stream));
+  });
+}
+
+int hpdg_set_estimator_grid(hpdg_mesh* mesh, const hpdg_mesh_desc* grid) {
+  if (!mesh) return HPDG_ERR_INVALID_ARG;
+  return guarded(mesh->ctx, [&] {
+    if (!grid) {
+      mesh->est_grid.reset();
+    } else {
+      if (!grid->macro_kind || !grid->macro_params || !grid->macro_nbr || !grid->macro_nbr_face ||
+          !grid->macro_nbr_orient || !grid->macro_bc)
+        throw Error(HPDG_ERR_INVALID_ARG, "incomplete estimator grid");
+      auto g = std::make_unique<MacroMesh>();
+      macro_mesh_from(grid, *g);
+      const MacroMesh& mm = mesh->mm;
+      if (g->macros.size() != mm.macros.size() || g->nbr != mm.nbr || g->nbr_face != mm.nbr_face ||
+          g->nbr_orient != mm.nbr_orient)
+        throw Error(HPDG_ERR_INVALID_MESH, "the estimator grid must have the mesh's macro connectivity");
+      mesh->est_grid = std::move(g);
+    }
+    mesh->est.key.clear();  // the point data are rebuilt on the next estimate
   });
 }
 

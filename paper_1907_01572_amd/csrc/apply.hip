@@ -130,7 +130,8 @@ __device__ void fused_step_tail(int n_rt, const ElemInfo& I, long long e, T* reg
 // of the mortar (degrees, rule, maps, matrix offsets) is the same in all lanes.  EST: instead
 // of the SIPG terms, the mortar's part of the a posteriori estimator (Eqs. Eta2_Integrals):
 // sum over its points of w S ((h_m / p_m) [[k grad u]]^2 + sigma [[u]]^2) inside, w S sigma
-// (u - g_D)^2 on Dirichlet faces, written to est.out at the mortar's index.
+// (u - g_D)^2 on Dirichlet faces (w S, h_m and sigma of the estimator's grid), written to
+// est.out at the mortar's index.
 template <typename T, bool EST = false>
 __global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long count, EstFace est) {
   extern __shared__ unsigned char smem_raw[];
@@ -249,13 +250,16 @@ __global__ void __launch_bounds__(64) mortar_kernel(LevelView<T> L, long long co
       side_values(0, l0, u0, gr0, ma0, mb0, mn0);
       if (two) side_values(1, l1, u1, gr1, ma1, mb1, mn1);
       if constexpr (EST) {
-        const double* ef = est.face + est.foff[mi] + 2 * g;  // (h_m / p_m, g_D) at this point
+        // (h_m / p_m, g_D, S ratio, h_m ratio) at this point: w S and sigma of the grid the
+        // integrals are taken on
+        const double* ef = est.face + est.foff[mi] + 4 * g;
+        const double w = double(wS) * ef[2], sg = double(sig) * ef[3];
         if (two) {
           const double J1 = double(gr0) + double(gr1), J2 = double(u0) - double(u1);
-          eacc += double(wS) * (ef[0] * J1 * J1 + double(sig) * J2 * J2);
+          eacc += w * (ef[0] * J1 * J1 + sg * J2 * J2);
         } else {
           const double J3 = double(u0) - ef[1];
-          eacc += double(wS) * double(sig) * J3 * J3;
+          eacc += w * sg * J3 * J3;
         }
         continue;
       }

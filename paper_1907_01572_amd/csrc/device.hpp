@@ -50,7 +50,7 @@ struct EstVolume {
   const double* he2p2;      // per element: h_e^2 p_e^2
 };
 struct EstFace {
-  const double* face;       // per task, at its GL points: (h_m / p_m, g_D)
+  const double* face;       // per task, at its GL points: (h_m / p_m, g_D, S ratio, h_m ratio)
   const long long* foff;    // per task: first scalar of its pairs
   const int* tmortar;       // per task: the mortar's index
   double* out;              // per mortar: its part (mortars without a task keep their value)

@@ -1186,9 +1186,10 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
 }
 
 // ---- a posteriori estimator: point data (Eqs. Eta2_Integrals) -----------------------------
-void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost& L, int kind,
-                      const std::vector<double>& P, EstTables& out) {
+void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscParams& dp, const LevelHost& L,
+                      int kind, const std::vector<double>& P, EstTables& out) {
   (void)dp;
+  const MacroMesh& gm = grid ? *grid : mm;
   const size_t E = L.cells.size();
   out = EstTables{};
   out.voff.resize(E);
@@ -1203,10 +1204,16 @@ void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost
     for (int cc = 0; cc < q; ++cc)
       for (int b = 0; b < q; ++b)
         for (int a = 0; a < q; ++a) {
-          double xi[3] = {eta[a], eta[b], eta[cc]}, x[3], J[3][3];
+          double xi[3] = {eta[a], eta[b], eta[cc]}, x[3], J[3][3], xg[3], Jg[3][3];
           cell_eval(mm, c, xi, x, J);
           const double dj = det3(J);
-          out.vol.push_back(wq[a] * wq[b] * wq[cc] * dj);
+          double djg = dj;
+          if (grid) {
+            cell_eval(gm, c, xi, xg, Jg);
+            djg = det3(Jg);
+            if (!(djg > 0)) throw Error(-2, "estimator grid: non-positive Jacobian determinant");
+          }
+          out.vol.push_back(wq[a] * wq[b] * wq[cc] * djg);
           out.vol.push_back(1.0 / dj);
           out.vol.push_back(source(kind, P, x));
         }
@@ -1214,7 +1221,7 @@ void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost
     double X[8][3];
     for (int v = 0; v < 8; ++v) {
       double xi[3] = {(v & 1) ? 1.0 : -1.0, (v & 2) ? 1.0 : -1.0, (v & 4) ? 1.0 : -1.0}, J[3][3];
-      cell_eval(mm, c, xi, X[v], J);
+      cell_eval(gm, c, xi, X[v], J);
     }
     double h2 = 0;
     for (int v = 0; v < 8; ++v)
@@ -1224,6 +1231,16 @@ void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost
       }
     out.he2p2[e] = h2 * double(c.p) * double(c.p);
   }
+  // at reference point xi of cell c: S = det J |grad xi_d| and 2 / |grad xi_d| on mesh m
+  auto face_metric = [](const MacroMesh& m, const Cell& c, const double xi[3], int d, double& S, double& h,
+                        double x[3]) {
+    double J[3][3], Ji[3][3];
+    cell_eval(m, c, xi, x, J);
+    inv3(J, Ji);
+    const double nr = std::sqrt(Ji[d][0] * Ji[d][0] + Ji[d][1] * Ji[d][1] + Ji[d][2] * Ji[d][2]);
+    S = det3(J) * nr;
+    h = 2.0 / nr;
+  };
   for (size_t m = 0; m < L.minfo.size(); ++m) {
     const MortarInfo& M = L.minfo[m];
     if (M.q == 0 || (M.ep < 0 && M.bc != 1)) continue;  // Neumann, Robin: no estimator term
@@ -1233,27 +1250,33 @@ void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost
     const int q = M.q;
     gauss_legendre(q, eta, wq);
     const Cell& cm = L.cells[M.em];
-    const int dmn = M.fm >> 1;
     const int pm = std::max(cm.p, M.ep >= 0 ? L.cells[M.ep].p : 0);
     for (int d = 0; d < q; ++d)
       for (int ci = 0; ci < q; ++ci) {
-        const double s_ = eta[ci], t_ = eta[d];
-        double xim[3], x[3], J[3][3], Ji[3][3];
-        face_ref(M.fm, s_, t_, xim);
-        cell_eval(mm, cm, xim, x, J);
-        inv3(J, Ji);
-        double h = 2.0 / std::sqrt(Ji[dmn][0] * Ji[dmn][0] + Ji[dmn][1] * Ji[dmn][1] + Ji[dmn][2] * Ji[dmn][2]);
+        double xim[3], x[3], xg[3], S, h, Sg, hg;
+        face_ref(M.fm, eta[ci], eta[d], xim);
+        face_metric(mm, cm, xim, M.fm >> 1, S, h, x);
+        Sg = S;
+        hg = h;
+        if (grid) face_metric(gm, cm, xim, M.fm >> 1, Sg, hg, xg);
         if (M.ep >= 0) {
-          double a, b, xip[3], xp[3], Jp[3][3], Jpi[3][3];
-          plus_coords(M.orient, M.sub, s_, t_, a, b);
+          double a, b, xip[3], xp[3], Sp, hp;
+          plus_coords(M.orient, M.sub, eta[ci], eta[d], a, b);
           face_ref(M.fp, a, b, xip);
-          cell_eval(mm, L.cells[M.ep], xip, xp, Jp);
-          inv3(Jp, Jpi);
-          const int dq = M.fp >> 1;
-          h = std::min(h, 2.0 / std::sqrt(Jpi[dq][0] * Jpi[dq][0] + Jpi[dq][1] * Jpi[dq][1] + Jpi[dq][2] * Jpi[dq][2]));
+          face_metric(mm, L.cells[M.ep], xip, M.fp >> 1, Sp, hp, xp);
+          h = std::min(h, hp);
+          if (grid) {
+            face_metric(gm, L.cells[M.ep], xip, M.fp >> 1, Sp, hp, xp);
+            hg = std::min(hg, hp);
+          } else {
+            hg = h;
+          }
         }
-        out.face.push_back(h / double(pm));
+        if (!(Sg > 0)) throw Error(-2, "estimator grid: non-positive face Jacobian");
+        out.face.push_back(hg / double(pm));
         out.face.push_back(M.ep >= 0 ? 0.0 : exact_u(kind, P, x));
+        out.face.push_back(Sg / S);
+        out.face.push_back(h / hg);
       }
   }
 }

@@ -126,10 +126,14 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
 // the mortar kernel's record of mortar M (both sides' traces, maps, rule; slots unset)
 MortarTask mortar_task(const LevelHost& L, const MortarInfo& M);
 
-// Point data of the a posteriori estimator (Eqs. Eta2_*) on level L for the problem (kind, P):
-// per element at its volume GL points (W det J, 1 / det J, g) and h_e^2 p_e^2; one mortar-kernel
-// task per interior or Dirichlet mortar with, at its GL points (mortar frame, a + q b),
-// (h_m / p_m, g_D) (h_m as for the penalty, p_m = max(p-, p+); g_D = 0 inside).
+// Point data of the a posteriori estimator (Eqs. Eta2_*) on level L for the problem (kind, P).
+// The integrands live on the physical grid mm; the integration weights, h_e and h_m on ``grid``
+// (a fiducial grid of the same cells, Sec. II.E; mm itself when null).  Per element at its
+// volume GL points (W det J_grid, 1 / det J, g) and h_e^2 p_e^2; one mortar-kernel task per
+// interior or Dirichlet mortar with, at its GL points (mortar frame, a + q b),
+// (h_m / p_m, g_D, S_grid / S, h_m / h_m,grid) (h_m as for the penalty from the physical grid,
+// the first entry from ``grid``; p_m = max(p-, p+); g_D = 0 inside): the mortar kernel's w S and
+// sigma times the last two are the fiducial grid's.
 struct EstTables {
   std::vector<double> vol;
   std::vector<long long> voff;  // per element: first scalar of its (W det J, 1 / det J, g) triples
@@ -137,10 +141,10 @@ struct EstTables {
   std::vector<MortarTask> tasks;
   std::vector<int> task_mortar;
   std::vector<double> face;
-  std::vector<long long> foff;  // per task: first scalar of its (h_m / p_m, g_D) pairs
+  std::vector<long long> foff;  // per task: first scalar of its 4-tuples
 };
-void estimator_tables(const MacroMesh& mm, const DiscParams& dp, const LevelHost& L, int kind,
-                      const std::vector<double>& P, EstTables& out);
+void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscParams& dp, const LevelHost& L,
+                      int kind, const std::vector<double>& P, EstTables& out);
 
 // one-side mortar map: rows of the 1-D matrices along the own face axes
 struct SideMap {

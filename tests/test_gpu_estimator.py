@@ -44,7 +44,7 @@ def _vector(op, prob, seed, noise):
     return u + noise * np.random.default_rng(seed).standard_normal(op.ndof) * max(np.abs(u).max(), 1.0)
 
 
-def _compare(M, m, op, prob, u_o, label):
+def _compare(M, m, op, prob, u_o, label, fiducial=None):
     cells = M.level_cells(0)
     perm = dof_perm(cells, m)
     ep = elem_perm(cells, m)
@@ -53,7 +53,7 @@ def _compare(M, m, op, prob, u_o, label):
     vol = torch.zeros_like(eta2)
     M.estimate(prob, u, eta2, vol)
     torch.cuda.synchronize()
-    ref = est.estimate(op, u_o, prob)
+    ref = est.estimate(op, u_o, prob, fiducial=fiducial)
     g, gv = eta2.cpu().numpy(), vol.cpu().numpy()
     o, ov = ref["eta2"][ep], ref["eta2_vol"][ep]
     err = np.max(np.abs(g - o) / (TOL_EST_REL * o + TOL_EST_ABS * o.max()))
@@ -105,4 +105,49 @@ def test_estimator_refuses_bad_arguments(ctx):
     with pytest.raises(hp.HpdgError) as ei:
         M.estimate(dict(kind="sinsinsin", params=np.zeros(0)), u, eta2, eta2)
     assert ei.value.code == hp.ERR_INVALID_ARG
+    M.free()
+
+
+def _linear_shell_twin(mesh, r_in=2.0, r_out=3.0):
+    """The cells of a (compactified) shell under the linear radial map from r_in to r_out."""
+    out = dict(mesh)
+    par = np.array(mesh["macro_params"], float, copy=True)
+    par[:, 9] = 0.0  # linear radial map
+    par[:, 10], par[:, 11] = r_in, r_out
+    out["macro_params"] = par
+    return out
+
+
+def _scaled_box(mesh, s):
+    out = dict(mesh)
+    par = np.array(mesh["macro_params"], float, copy=True)
+    par[:, 0:12] *= s
+    out["macro_params"] = par
+    return out
+
+
+@pytest.mark.parametrize("name,twin", [("shell_l2_p4_r1e9", _linear_shell_twin),
+                                       ("shell_l2_p3_r1e3", _linear_shell_twin),
+                                       ("box_2to1_p3", lambda m: _scaled_box(m, 3.0)),
+                                       ("hp_k", lambda m: _scaled_box(m, 0.5))])
+def test_estimator_parity_on_a_fiducial_grid(ctx, name, twin):
+    # the compactified estimator of the shell (integrals on an unstretched twin with radii 2..3)
+    # and scaled twins of affine meshes; resetting the grid restores the physical estimate
+    maker, prob = MESHES[name]
+    m = maker()
+    op = SIPG(m, prob)
+    M = ctx.upload(m, coef=coef_of(prob))
+    u_o = _vector(op, prob, 9, 0.05)
+    phys = _compare(M, m, op, prob, u_o, name + " physical grid")
+    fid = twin(m)
+    M.set_estimator_grid(fid)
+    comp = _compare(M, m, op, prob, u_o, name + " fiducial grid", fiducial=fid)
+    assert not torch.equal(comp, phys)
+    M.set_estimator_grid(None)
+    again = _compare(M, m, op, prob, u_o, name + " physical grid again")
+    assert torch.equal(again, phys)
+    other = meshgen.box_grid((1, 1, 2), 0, 2)  # two macros stacked in z: other connectivity
+    with pytest.raises(hp.HpdgError) as ei:
+        M.set_estimator_grid(other)
+    assert ei.value.code == hp.ERR_INVALID_MESH
     M.free()
