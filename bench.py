@@ -311,6 +311,31 @@ def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
                      "final_rel_residual": sts_bf[-1]["rel_residual"],
                      "p50_ms": float(np.percentile(lat_bf, 50)), "p99_ms": float(np.percentile(lat_bf, 99))}
 
+    est_info = None
+    if prob is not None and not newton:
+        # the a posteriori estimate of the last solution (Eqs. Eta2_*): the first call builds the
+        # problem's point data on the host; the timed calls run the kernels only
+        eta2 = torch.zeros(M.n_elem[0], dtype=torch.float64, device=dev)
+        a = time.perf_counter()
+        M.estimate(prob, u, eta2)
+        torch.cuda.synchronize()
+        build_s = time.perf_counter() - a
+        reps = 10
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            M.estimate(prob, u, eta2)
+        e1.record()
+        torch.cuda.synchronize()
+        est_ms = e0.elapsed_time(e1) / reps
+        eb, vpts, mpts = M.estimate_info()
+        est_info = {"ms": round(est_ms, 4), "dof_per_s": N / (est_ms * 1e-3),
+                    "elements_per_s": M.n_elem[0] / (est_ms * 1e-3), "alg_bytes": eb,
+                    "gbs": round(eb / (est_ms * 1e-3) / 1e9, 2),
+                    "hbm_frac": round(eb / (est_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                    "volume_points": vpts, "mortar_points": mpts, "point_data_build_s": round(build_s, 3),
+                    "eta": float(torch.sqrt(eta2.sum())), "reps": reps}
+
     def totals(entries):
         return (sum(e[0] for e in entries), sum(e[1] for e in entries), sum(e[2] for e in entries))
 
@@ -337,6 +362,7 @@ def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
         "mixed": {"solves_per_s": round(steps / el_mx, 4), "iterations": it_mx, "final_rel_residual": stm["rel_residual"],
                   "p50_ms": float(np.percentile(lat_mx, 50)), "p99_ms": float(np.percentile(lat_mx, 99))},
         "mixed_bf16_blocks": bf16_info,
+        "estimator": est_info,
         # fine-level operator applies inside the timed solves (HIP events on the solve stream)
         "apply": {"dof_applies_per_s_f64": N / (apply_ms64 * 1e-3), "dof_applies_per_s_f32": N / (apply_ms32 * 1e-3),
                   "kernel_ms_f64": apply_ms64, "kernel_ms_f32": apply_ms32,
@@ -480,6 +506,7 @@ def main():
         "mixed": R["mixed"],
         "mixed_bf16_blocks": R["mixed_bf16_blocks"],
         "apply": R["apply"],
+        "estimator": R["estimator"],
         "kernels_f64_solve": kernels,
         "roofline": roof,
     }
@@ -503,7 +530,7 @@ def main():
         ms2, c2, b2 = S["t64"][d2][0]
         sm = {"workload": W2["desc"] + " (%d DOF)" % S["N"], "steps": args.shell_steps,
               "solves_per_s": round(S["solves_per_s"], 4), "solve": S["solve"], "mixed": S["mixed"],
-              "mixed_bf16_blocks": S["mixed_bf16_blocks"], "apply": S["apply"],
+              "mixed_bf16_blocks": S["mixed_bf16_blocks"], "apply": S["apply"], "estimator": S["estimator"],
               "n_cheb": W2["smoother"]["n_cheb"], "Lambda": W2["smoother"]["Lambda"], "smoother": "block",
               "dominant_kernel": {"kernel": k2[d2]["kernel"], "avg_launch_us": round(1e3 * ms2 / c2, 2),
                                   "alg_bytes_per_launch": round(b2 / c2),

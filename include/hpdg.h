@@ -172,6 +172,13 @@ typedef struct {
    * the others the sum-factorised passes through the q GL points and the metric contraction,
    * plus the mortar interpolations and lifts of their faces */
   double apply_flops[32];
+  /* a posteriori estimate (hpdg_estimate) of the last problem estimated, 0 before the first:
+   * algorithmic bytes of one call (u, the point data, the volume and mortar metric read once,
+   * h_e^2 p_e^2 and eta2; the face traces in between not counted) and the element volume
+   * points and mortar points it evaluates */
+  int64_t est_alg_bytes;
+  int64_t est_volume_points;
+  int64_t est_mortar_points;
 } hpdg_mesh_info;
 
 /* Chebyshev smoother (Alg. 4) and CG spectral bound (Alg. 5) parameters.
@@ -314,8 +321,10 @@ int hpdg_set_coefficient(hpdg_mesh* mesh, int kind, int where, const double* hos
  * g_N = 0 for HPDG_RHS_GAUSSIANS; Robin faces (kind 3) add int g_R psi with
  * g_R = k n.grad u + gamma u (Eq. RobinBC with the sign of Eq. lh; 0 for the Gaussians);
  * other kinds with Neumann or Robin faces return HPDG_ERR_UNSUPPORTED.
- * Every face integral uses the face's own rule.  Computed on the host in FP64, then copied
- * (stream-ordered). */
+ * Every face integral uses the face's own rule.  The face terms are computed on the host in
+ * FP64 and copied; the volume term int g psi runs on the device in FP64 (the GL points mapped
+ * by the macro maps there, one workgroup per element) and is added.  Synchronises ``stream``.
+ * HPDG_ERR_INVALID_ARG also for a polynomial of degree above 15. */
 int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, void* stream);
 
 /* A posteriori error estimate of u_dev (a level-0 FP64 vector) for the problem of ``rhs``
@@ -460,9 +469,14 @@ int hpdg_newton_solve(hpdg_mesh* mesh, const hpdg_newton_params* params, const h
  * flight; the first queued request that fits is taken, and the head of the queue is not
  * passed over more than 2 max_active times.  Each request's element data and solver
  * state stay on the device from upload to its last iteration; requests in flight share
- * the GPU concurrently.  The result is copied to the caller's host buffer, then the
- * request's device memory is released.  Results do not depend on the mix: every kernel
- * and reduction of a solve is deterministic and private to its request. */
+ * the GPU concurrently.  The result is copied to the caller's host buffer.  The request's
+ * mesh then stays uploaded, with its smoother set up, as long as device memory allows: a
+ * later request with the same mesh and discretisation (byte-identical descriptions) takes
+ * it and only assembles its right-hand side (host faces, device volume) and solves.  Such
+ * idle meshes count against hbm_budget_bytes with their requests' footprint; the least
+ * recently used are freed when a queued request needs the room, or beyond 64 GiB; all are
+ * freed by hpdg_server_destroy.  Results do not depend on the mix or on the reuse: every
+ * kernel and reduction of a solve is deterministic and private to its request. */
 typedef struct hpdg_server hpdg_server;
 typedef struct {
   int32_t max_active;          /* requests in flight (worker threads / streams), >= 1 */

@@ -68,7 +68,8 @@ class MeshInfo(ctypes.Structure):
                 ("table_bytes", ctypes.c_int64 * 32), ("device_bytes", ctypes.c_size_t),
                 ("block_retries", ctypes.c_int32), ("coarse_retries", ctypes.c_int32),
                 ("n_elem_centric", ctypes.c_int64 * 32), ("n_mortar_tasks", ctypes.c_int64 * 32),
-                ("apply_flops", ctypes.c_double * 32)]
+                ("apply_flops", ctypes.c_double * 32), ("est_alg_bytes", ctypes.c_int64),
+                ("est_volume_points", ctypes.c_int64), ("est_mortar_points", ctypes.c_int64)]
 
 
 class SmootherParams(ctypes.Structure):
@@ -456,6 +457,7 @@ class Mesh:
                                               _ptr(eta2_vol) if eta2_vol is not None else None,
                                               _stream(stream)))
 
+
     def set_estimator_grid(self, grid=None):
         """The fiducial grid of the estimator: a mesh dict with this mesh's macro connectivity
         (its macro maps are used); None: the physical grid."""
@@ -464,6 +466,13 @@ class Mesh:
             return
         d, _, keep = _descriptors(grid)
         self.ctx.check(self.lib.hpdg_set_estimator_grid(self.h, ctypes.byref(d)))
+
+    def estimate_info(self):
+        """(algorithmic bytes, volume points, mortar points) of one estimate of the last problem
+        estimated (zeros before the first)."""
+        info = MeshInfo()
+        self.ctx.check(self.lib.hpdg_mesh_info_get(self.h, ctypes.byref(info)))
+        return int(info.est_alg_bytes), int(info.est_volume_points), int(info.est_mortar_points)
 
     def transfer_to(self, other, u, u_other, stream=None):
         """u_other (level-0 vector of ``other``, an adapted copy of this mesh) = u carried over."""

@@ -96,7 +96,7 @@ struct hpdg_mesh {
   std::vector<size_t> alloc_bytes;
   size_t bytes = 0;
   int* tab_off = nullptr;
-  int *dg_off = nullptr, *w_off = nullptr, *dface_off = nullptr;
+  int *dg_off = nullptr, *w_off = nullptr, *dface_off = nullptr, *gl_off = nullptr;
   double* tab64 = nullptr;
   float* tab32 = nullptr;
   std::vector<DevLevel<double>> L64;
@@ -159,8 +159,13 @@ struct hpdg_mesh {
     long long n_tasks = 0;
     double* vpart = nullptr;
     std::vector<void*> ptrs;
+    long long alg_bytes = 0, vpoints = 0, mpoints = 0;  // of one estimate (hpdg_mesh_info)
   } est;
   std::unique_ptr<MacroMesh> est_grid;  // the estimator's fiducial grid (null: the physical one)
+  // macros and level-0 cells on the device (the right-hand side's volume part maps its points
+  // there); uploaded on first use
+  Macro* dmacros = nullptr;
+  Cell* dcells = nullptr;
 
   template <typename T>
   T* alloc(size_t count) {
@@ -236,7 +241,7 @@ struct hpdg_mesh {
 
   int nlevels() const { return int(H.size()); }
 
-  TabView tabview() const { return TabView{tab_off, dg_off, w_off, dface_off}; }
+  TabView tabview() const { return TabView{tab_off, dg_off, w_off, dface_off, gl_off}; }
 
   template <typename T>
   LevelView<T> view(int l) const;
@@ -1125,6 +1130,7 @@ void upload_mesh_device(hpdg_mesh* M, hipStream_t s) {
   M->dg_off = M->upload_raw(M->tab.dg_off, s);
   M->w_off = M->upload_raw(M->tab.w_off, s);
   M->dface_off = M->upload_raw(M->tab.dface_off, s);
+  M->gl_off = M->upload_raw(M->tab.gl_off, s);
   M->tab64 = M->upload_raw(M->tab.data, s);
   if (M->has_f32) M->tab32 = M->upload<float>(M->tab.data, s);
   M->L64.resize(M->nlevels());
@@ -1214,6 +1220,7 @@ void rebuild_mesh(hpdg_mesh* M, hipStream_t s) {
   swap(M->dg_off, F->dg_off);
   swap(M->w_off, F->w_off);
   swap(M->dface_off, F->dface_off);
+  swap(M->gl_off, F->gl_off);
   swap(M->tab64, F->tab64);
   swap(M->tab32, F->tab32);
   swap(M->L64, F->L64);
@@ -1222,6 +1229,8 @@ void rebuild_mesh(hpdg_mesh* M, hipStream_t s) {
   swap(M->ncoarse, F->ncoarse);
   swap(M->lam, F->lam);
   swap(M->est, F->est);
+  swap(M->dmacros, F->dmacros);
+  swap(M->dcells, F->dcells);
   swap(M->bad, F->bad);
   swap(M->host_bad, F->host_bad);
   swap(M->nl_b, F->nl_b);
@@ -1249,11 +1258,23 @@ void rebuild_mesh(hpdg_mesh* M, hipStream_t s) {
 void assemble_rhs_impl(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, hipStream_t s) {
   if (rhs->kind < 0 || rhs->kind > 6) throw Error(HPDG_ERR_INVALID_ARG, "unknown rhs kind");
   if (rhs->n_params > 0 && !rhs->params) throw Error(HPDG_ERR_INVALID_ARG, "rhs parameters missing");
+  if (rhs->kind == 3 && rhs->n_params > 16 * 16 * 16) throw Error(HPDG_ERR_INVALID_ARG, "polynomial degree above 15");
   std::vector<double> P(rhs->params, rhs->params + std::max(rhs->n_params, 0));
   std::vector<double> F;
-  assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);
-  HIPCHK(hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  HIPCHK(hipStreamSynchronize(s));
+  assemble_rhs(mesh->mm, mesh->dp, mesh->tab, mesh->H[0], rhs->kind, P, F);  // boundary faces
+  if (!mesh->dmacros) {
+    mesh->dmacros = mesh->upload_raw(mesh->mm.macros, s);
+    mesh->dcells = mesh->upload_raw(mesh->H[0].cells, s);
+  }
+  double* Pd = mesh->upload_raw(P, s);
+  hipError_t err = hipMemcpyAsync(F_dev, F.data(), F.size() * sizeof(double), hipMemcpyHostToDevice, s);
+  if (err == hipSuccess) {
+    launch_rhs_volume(mesh->view<double>(0), mesh->dmacros, mesh->dcells, rhs->kind, Pd, int(P.size()), F_dev, s);
+    err = hipGetLastError();
+  }
+  if (err == hipSuccess) err = hipStreamSynchronize(s);
+  if (err == hipSuccess) mesh->release(Pd);
+  HIPCHK(err);
 }
 
 // eta2(e) of u on level 0 (Eqs. Eta2_Ingredients .. Eta2_Local)
@@ -1289,6 +1310,14 @@ void estimate_impl(hpdg_mesh* M, const hpdg_rhs_desc* rhs, const double* u, doub
     E.ef.out = keep(M->alloc<double>(h.minfo.size()));
     E.vpart = keep(M->alloc<double>(h.cells.size()));
     E.key = key;
+    long long mg = 0;
+    for (const MortarTask& t : t.tasks) mg += 8LL * (t.gmode ? (long long)t.q * t.q : 1);
+    E.vpoints = (long long)t.vol.size() / 3;
+    E.mpoints = (long long)t.face.size() / 4;
+    E.alg_bytes = 8 * (h.ndof + (long long)t.vol.size() + (long long)h.vgeo.size() + (long long)t.face.size() + mg +
+                       2 * (long long)h.cells.size()) +
+                  (long long)(h.einfo.size() * sizeof(ElemInfo) + t.tasks.size() * sizeof(MortarTask) +
+                              h.fmlist.size() * sizeof(int) + (t.voff.size() + t.foff.size()) * sizeof(long long));
   }
   LevelView<double> V = M->view<double>(0);
   V.mtask = E.tasks;
@@ -1624,8 +1653,18 @@ void linearize(hpdg_mesh* M, const double* u, hipStream_t s) {
 // ---- solve server ------------------------------------------------------------------
 namespace {
 
+// a mesh uploaded with its smoother set up, and its right-hand side and solution vectors
+struct Prepared {
+  std::unique_ptr<hpdg_mesh> M;
+  double* F = nullptr;
+  double* u = nullptr;
+  size_t bytes = 0;      // the footprint estimate of the requests on it
+  uint64_t last_use = 0;
+};
+
 struct ServerRequest {
   uint64_t ticket = 0;
+  Prepared pre;          // an idle prepared mesh of the same key, claimed when the request is picked
   std::string key;       // bytes of the mesh description and discretisation (host-table cache key)
   std::vector<int32_t> mkind, mnbr, mnface, mnor, mbc, emacro, elevel, eanchor, ep;
   std::vector<double> mparams, rhs_params;
@@ -1681,6 +1720,35 @@ struct hpdg_server {
   std::map<std::string, Cached> cache;
   size_t cache_bytes = 0;
   uint64_t cache_clock = 0;
+  // meshes a finished request leaves uploaded with their smoother set up and their right-hand
+  // side and solution vectors: a later request on the same mesh (same key) takes one instead of
+  // uploading and setting up again.  Their device bytes (the requests' footprint estimates)
+  // count against the budget; the least recently used are freed when a request needs the room
+  // or when they pass kIdleBytes.  Guarded by mu.
+  static constexpr size_t kIdleBytes = size_t(64) << 30;
+  std::map<std::string, std::vector<Prepared>> idle;
+  size_t idle_bytes = 0;
+  uint64_t idle_clock = 0;
+  // frees the least recently used idle mesh (not one of key ``keep``); false when there is none
+  // (caller holds mu)
+  bool evict_idle(const std::string* keep = nullptr) {
+    std::string key;
+    size_t at = 0;
+    uint64_t best = UINT64_MAX;
+    for (auto& kv : idle)
+      for (size_t i = 0; i < kv.second.size(); ++i)
+        if ((!keep || kv.first != *keep) && kv.second[i].last_use < best) {
+          best = kv.second[i].last_use;
+          key = kv.first;
+          at = i;
+        }
+    if (best == UINT64_MAX) return false;
+    auto& v = idle[key];
+    idle_bytes -= v[at].bytes;
+    v.erase(v.begin() + at);
+    if (v.empty()) idle.erase(key);
+    return true;
+  }
   std::condition_variable cv_work, cv_done;
   std::deque<uint64_t> queue;
   std::map<uint64_t, std::unique_ptr<ServerRequest>> reqs;
@@ -1697,13 +1765,28 @@ struct hpdg_server {
   // times); caller holds mu
   ServerRequest* pick() {
     const size_t budget = p.hbm_budget_bytes;
-    const size_t free_b = budget ? (budget > in_flight_bytes ? budget - in_flight_bytes : 0) : SIZE_MAX;
     for (size_t k = 0; k < queue.size(); ++k) {
       ServerRequest* r = reqs[queue[k]].get();
-      const bool fits = !budget || r->estimate <= free_b || (in_flight_bytes == 0 && k == 0);
+      // a request on a mesh that waits idle reuses it: those bytes are already counted
+      const bool reuse = idle.count(r->key) != 0;
+      const size_t others = idle_bytes - (reuse ? r->estimate : 0);
+      if (budget && k == 0) {  // other idle meshes give way to the head of the queue
+        while (in_flight_bytes + others + r->estimate > budget && idle_bytes > (reuse ? r->estimate : 0)) {
+          if (!evict_idle(reuse ? &r->key : nullptr)) break;
+        }
+      }
+      const size_t used = in_flight_bytes + idle_bytes - (idle.count(r->key) ? r->estimate : 0);
+      const bool fits = !budget || used + r->estimate <= budget || (in_flight_bytes == 0 && k == 0);
       if (fits) {
         if (k > 0) reqs[queue[0]]->bypassed += 1;
         queue.erase(queue.begin() + k);
+        auto it = idle.find(r->key);
+        if (it != idle.end()) {  // its bytes move from the idle to the in-flight count
+          r->pre = std::move(it->second.back());
+          it->second.pop_back();
+          if (it->second.empty()) idle.erase(it);
+          idle_bytes -= r->pre.bytes;
+        }
         return r;
       }
       if (k == 0 && reqs[queue[0]]->bypassed >= 2 * p.max_active) return nullptr;
@@ -1716,21 +1799,36 @@ struct hpdg_server {
     int rc = HPDG_OK;
     std::string msg;
     try {
-      std::unique_ptr<hpdg_mesh> M = host_tables(r);
-      upload_mesh_device(M.get(), s);
-      setup_smoother_impl(M.get(), &p.smoother, nullptr, s);
+      Prepared P = std::move(r->pre);
+      if (!P.M) {
+        P.M = host_tables(r);
+        upload_mesh_device(P.M.get(), s);
+        setup_smoother_impl(P.M.get(), &p.smoother, nullptr, s);
+        P.F = P.M->alloc<double>(size_t(P.M->H[0].ndof));
+        P.u = P.M->alloc<double>(size_t(P.M->H[0].ndof));
+      }
+      hpdg_mesh* M = P.M.get();
       const long long n = M->H[0].ndof;
-      double* F = M->alloc<double>(size_t(n));
-      double* u = M->alloc<double>(size_t(n));
-      assemble_rhs_impl(M.get(), &r->rhs, F, s);
+      double* F = P.F;
+      double* u = P.u;
+      assemble_rhs_impl(M, &r->rhs, F, s);
       launch_fill<double>(n, 0.0, u, s);
       hpdg_solve_params sp{HPDG_SOLVER_FCG, p.precision, p.tol_rel, p.max_iter, 0};
-      const bool ok = krylov_solve(M.get(), sp, F, u, iters, rel, s);
+      const bool ok = krylov_solve(M, sp, F, u, iters, rel, s);
       if (!ok) rc = HPDG_ERR_NOT_CONVERGED;
       HIPCHK(hipMemcpyAsync(r->u_out, u, size_t(n) * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipStreamSynchronize(s));
       std::lock_guard<std::mutex> lock(mu);
       r->st.n_dof = n;
+      // keep the prepared mesh for a later request on it
+      P.bytes = r->estimate;
+      P.last_use = ++idle_clock;
+      if (P.bytes <= kIdleBytes) {
+        idle_bytes += P.bytes;
+        idle[r->key].push_back(std::move(P));
+        while (idle_bytes > kIdleBytes && evict_idle()) {
+        }
+      }
     } catch (const Error& e) {
       rc = e.code;
       msg = e.what();
@@ -1900,6 +1998,9 @@ int hpdg_mesh_info_get(const hpdg_mesh* mesh, hpdg_mesh_info* out) {
     out->apply_flops[l] = 2 * fma;
   }
   out->device_bytes = mesh->bytes;
+  out->est_alg_bytes = mesh->est.alg_bytes;
+  out->est_volume_points = mesh->est.vpoints;
+  out->est_mortar_points = mesh->est.mpoints;
   out->block_retries = mesh->block_retries;
   out->coarse_retries = mesh->coarse_retries;
   return HPDG_OK;
@@ -2421,6 +2522,8 @@ int hpdg_server_destroy(hpdg_server* sv) {
   sv->cv_work.notify_all();
   for (auto& w : sv->workers) w.join();
   sv->cv_done.notify_all();
+  (void)hipSetDevice(sv->ctx->device);
+  sv->idle.clear();
   delete sv;
   return HPDG_OK;
 }

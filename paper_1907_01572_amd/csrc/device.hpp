@@ -13,6 +13,7 @@ struct TabView {
   const int* dg_off;     // [kMaxQ + 1]
   const int* w_off;      // [kMaxQ + 1]
   const int* dface_off;  // [kMaxN + 1]
+  const int* gl_off;     // [kMaxQ + 1]: GL nodes
 };
 
 template <typename T>
@@ -61,6 +62,12 @@ struct EstFace {
 size_t est_lds_bytes(int nmax, int qmax);
 void launch_estimator(const LevelView<double>& L, const double* x, const EstVolume& ev, const EstFace& ef,
                       long long n_tasks, double* vol, double* eta2, hipStream_t s);
+
+// F += int g psi (the volume part of Eq. Fh2) on the elements of level L: g of the right-hand
+// side kind with parameters P[nP] (device) at the GL points of each element's rule, the points
+// mapped by the macro maps (macros: the mesh's macros, cells: its level-0 cells, on the device)
+void launch_rhs_volume(const LevelView<double>& L, const Macro* macros, const Cell* cells, int kind,
+                       const double* P, int nP, double* F, hipStream_t s);
 
 template <typename T>
 struct TransferView {

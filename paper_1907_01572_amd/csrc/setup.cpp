@@ -2,13 +2,12 @@
 // Surface-Jacobian), mortar metric and penalty (Eq. penaltyparameter), transfer records
 // (Sec. II.D.6), the operator diagonal and the right-hand side (Eq. Fh2).
 #include "setup.hpp"
+#include "maps.hpp"
 
 #include <algorithm>
 #include <array>
 #include <map>
 #include <cmath>
-#include <system_error>
-#include <thread>
 
 namespace hpdg {
 
@@ -259,14 +258,8 @@ void inv3(const double J[3][3], double Ji[3][3]) {
 }
 
 void cell_eval(const MacroMesh& mm, const Cell& c, const double xi[3], double x[3], double J[3][3]) {
-  const double h = 1.0 / double(1 << c.level);
-  double xm[3];
-  for (int d = 0; d < 3; ++d) xm[d] = -1.0 + (2.0 * c.a[d] + 1.0 + xi[d]) * h;
-  const double zc = -1.0 + (2.0 * c.a[2] + 1.0) * h;
-  double Jm[3][3];
-  macro_eval(mm.macros[c.macro], xm, zc, x, Jm);
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) J[i][j] = Jm[i][j] * h;
+  const Macro& M = mm.macros[c.macro];
+  cell_map(M.kind, M.par, c.level, c.a, xi, x, J);
 }
 
 namespace {
@@ -926,34 +919,7 @@ bool exact_grad(int kind, const std::vector<double>& P, const double x[3], doubl
 }
 
 double source(int kind, const std::vector<double>& P, const double x[3]) {
-  const double X = x[0], Y = x[1], Z = x[2];
-  switch (kind) {
-    case 0: return 3.0 * M_PI * M_PI * exact_u(0, P, x);
-    case 1: return 0.0;
-    case 2: return -6.0;
-    case 3: {
-      const int K = int(std::lround(std::cbrt(double(P.size()))));
-      double g = 0;
-      for (int a = 0; a < K; ++a)
-        for (int b = 0; b < K; ++b)
-          for (int c = 0; c < K; ++c) {
-            const double C = P[(a * K + b) * K + c];
-            if (a >= 2) g -= C * a * (a - 1) * std::pow(X, a - 2) * std::pow(Y, b) * std::pow(Z, c);
-            if (b >= 2) g -= C * b * (b - 1) * std::pow(X, a) * std::pow(Y, b - 2) * std::pow(Z, c);
-            if (c >= 2) g -= C * c * (c - 1) * std::pow(X, a) * std::pow(Y, b) * std::pow(Z, c - 2);
-          }
-      return g;
-    }
-    case 4: {
-      double g = 0;
-      for (size_t r = 0; r + 4 < P.size(); r += 5) {
-        const double dx = X - P[r + 1], dy = Y - P[r + 2], dz = Z - P[r + 3], s = P[r + 4];
-        g += P[r] * std::exp(-(dx * dx + dy * dy + dz * dz) / (2.0 * s * s));
-      }
-      return g;
-    }
-    default: return 0.0;
-  }
+  return rhs_source(kind, P.data(), int(P.size()), x);
 }
 
 }  // namespace
@@ -1030,68 +996,7 @@ void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, c
                   int kind, const std::vector<double>& P, std::vector<double>& F) {
   F.assign(size_t(L.ndof), 0.0);
   const double* td = T.data.data();
-  // volume terms: each element writes only its own entries, so contiguous element ranges run
-  // on separate host threads (the result does not depend on the split)
-  auto volume = [&](size_t e_begin, size_t e_end) {
-    std::vector<double> gq, t1, t2;
-    for (size_t e = e_begin; e < e_end; ++e) {
-      const ElemInfo& I = L.einfo[e];
-      const int n = I.n, q = I.q;
-      const double* B = td + T.index(OpTable::GL_VAL, n, q);
-      const double* w = td + T.w_off[q];
-      const double* eta = td + T.gl_off[q];
-      gq.assign(size_t(q) * q * q, 0.0);
-      for (int c = 0; c < q; ++c)
-        for (int b = 0; b < q; ++b)
-          for (int a = 0; a < q; ++a) {
-            double xi[3] = {eta[a], eta[b], eta[c]}, x[3], J[3][3];
-            cell_eval(mm, L.cells[e], xi, x, J);
-            gq[(c * q + b) * q + a] = w[a] * w[b] * w[c] * det3(J) * source(kind, P, x);
-          }
-      t1.assign(size_t(q) * q * n, 0.0);
-      t2.assign(size_t(q) * n * n, 0.0);
-      for (int cb = 0; cb < q * q; ++cb)
-        for (int i = 0; i < n; ++i) {
-          double s = 0;
-          for (int a = 0; a < q; ++a) s += B[a * n + i] * gq[cb * q + a];
-          t1[size_t(cb) * n + i] = s;
-        }
-      for (int c = 0; c < q; ++c)
-        for (int j = 0; j < n; ++j)
-          for (int i = 0; i < n; ++i) {
-            double s = 0;
-            for (int b = 0; b < q; ++b) s += B[b * n + j] * t1[(size_t(c) * q + b) * n + i];
-            t2[(size_t(c) * n + j) * n + i] = s;
-          }
-      for (int k = 0; k < n; ++k)
-        for (int j = 0; j < n; ++j)
-          for (int i = 0; i < n; ++i) {
-            double s = 0;
-            for (int c = 0; c < q; ++c) s += B[c * n + k] * t2[(size_t(c) * n + j) * n + i];
-            F[size_t(I.off) + (k * n + j) * n + i] += s;
-          }
-    }
-  };
-  const size_t E = L.einfo.size();
-  const size_t nt = std::min<size_t>(std::max(1u, std::thread::hardware_concurrency()), std::max<size_t>(1, E / 256));
-  const size_t nthreads = std::min<size_t>(nt, 8);
-  if (nthreads <= 1) {
-    volume(0, E);
-  } else {
-    // a thread that cannot be started leaves its element range (and the later ones) to this
-    // thread; the threads already started are joined either way (no exception escapes)
-    std::vector<std::thread> pool;
-    size_t started = 0;
-    for (; started < nthreads; ++started) {
-      try {
-        pool.emplace_back(volume, E * started / nthreads, E * (started + 1) / nthreads);
-      } catch (const std::system_error&) {
-        break;
-      }
-    }
-    if (started < nthreads) volume(E * started / nthreads, E);
-    for (std::thread& th : pool) th.join();
-  }
+  // volume terms int g psi: on the device (rhs.hip), added to these face terms
   // Dirichlet faces: int g_D (sigma psi - k n.grad psi), with the face's own rule (a flat face
   // whose rule was raised to the volume rule's keeps its constant metric, valid at any q)
   for (size_t mi = 0; mi < L.minfo.size(); ++mi) {

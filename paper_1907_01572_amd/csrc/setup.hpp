@@ -119,7 +119,8 @@ void mass_points(const MacroMesh& mm, const LevelHost& L, std::vector<double>& x
 // (P = [s, rows (cx, cy, cz, m, a)]), kind 1 quadratic manufactured (P = [alpha, C (27)])
 void nl_coefficients(int kind, const std::vector<double>& P, const double x[3], double& alpha, double& beta);
 
-// right-hand side F_h (Eq. Fh2) on level 0
+// the boundary part of the right-hand side F_h (Eq. Fh2) on level 0 (Dirichlet, Neumann and
+// Robin faces); the volume part int g psi is added on the device (launch_rhs_volume)
 void assemble_rhs(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, const LevelHost& L,
                   int kind, const std::vector<double>& params, std::vector<double>& F);
 
