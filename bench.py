@@ -248,6 +248,8 @@ def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
     up = dict(W["upload"])
     if args.max_levels >= 0:
         up["max_levels"] = args.max_levels
+    if args.ec_mode:
+        up["ec_mode"] = {"auto": hp.EC_AUTO, "always": hp.EC_ALWAYS, "never": hp.EC_NEVER}[args.ec_mode]
     M = ctx.upload(mesh, **up)
     if args.n_cheb_coarse >= 0:
         W["smoother"]["n_cheb_coarse"] = args.n_cheb_coarse
@@ -398,6 +400,8 @@ def main():
     ap.add_argument("--max-levels", type=int, default=-1,
                     help="multigrid levels (the last one solved exactly); -1: the workload's default, 0: all")
     ap.add_argument("--smoother", default=None, choices=["none", "point", "block"])
+    ap.add_argument("--ec-mode", default=None, choices=["auto", "always", "never"],
+                    help="element-centric apply by level (the library's default), everywhere it applies, or nowhere")
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--level", type=int, default=3)
     ap.add_argument("--p", type=int, default=5)
