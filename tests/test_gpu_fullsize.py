@@ -12,6 +12,7 @@ benchmark (FP64 level 0, FP32 copies built).
 * puncture mesh, p = 6, 12,739,363 DOF: nonlinear residual rows and, after
   linearisation, Jacobian rows;
 * the shell's first coarse level (1,056 cells): operator rows;
+* the a posteriori estimate per sampled element (hp cube; shell on its unstretched twin);
 * the shell's smoother as the benchmark runs it (the fused apply + block-Jacobi step)
   against the separate kernels, FP64 and FP32, fine and first coarse level, and a V-cycle.
 """
@@ -19,6 +20,7 @@ import numpy as np
 import pytest
 
 import meshgen
+from oracle import estimator as est
 from oracle import problems
 from oracle.newton import _gl_values, _project
 from oracle.operator import SIPG
@@ -79,6 +81,40 @@ def test_fullsize_apply_rows(ctx, name):
     err32 = rel_rows(host(y32), host(y), rows)
     print(name, "sampled rows FP64", err, "FP32 vs FP64", err32, flush=True)
     assert err <= tol and err32 <= 1e-5
+    M.free()
+
+
+def _linear_twin(m):
+    out = dict(m)
+    par = np.array(m["macro_params"], float, copy=True)
+    par[:, 9], par[:, 10], par[:, 11] = 0.0, 2.0, 3.0  # linear radial map from 2 to 3
+    out["macro_params"] = par
+    return out
+
+
+@pytest.mark.parametrize("name", ["shell_p5_compact", "hp_k_p2_7"])
+def test_fullsize_estimator_rows(ctx, name):
+    # the a posteriori estimate at the benchmark's sizes, per sampled element against the
+    # oracle's (its volume part and every mortar touching it): the hp cube on its physical grid,
+    # the compactified shell on its unstretched twin (Sec. III.C)
+    if name == "shell_p5_compact":
+        m, prob = meshgen.cubed_sphere_shell(level=3, p=5), meshgen.problem_config2()
+        fid = _linear_twin(m)
+    else:
+        m, prob, fid = meshgen.hp_sphere_cube(), meshgen.problem_config3(), None
+    M = ctx.upload(m, coef=coef_of(prob), build_f32=True)
+    if fid is not None:
+        M.set_estimator_grid(fid)
+    elems = _sample(len(m["elem_p"]), 4)
+    op = SIPG(m, prob, active=elems)
+    x = np.random.default_rng(5).standard_normal(op.ndof)
+    eta2 = torch.zeros(M.n_elem[0], dtype=torch.float64, device="cuda")
+    M.estimate(prob, torch.tensor(x, device="cuda"), eta2)
+    ref = est.estimate(op, x, prob, fiducial=fid)["eta2"][elems]
+    got = host(eta2)[elems]
+    err = float(np.max(np.abs(got - ref) / ref))
+    print(name, "sampled estimates", len(elems), "max rel error", err, flush=True)
+    assert err <= 1e-10
     M.free()
 
 
