@@ -86,6 +86,8 @@ def composite_members(name):
     short = name.split("(hpdg::")[0].replace("void hpdg::(anonymous namespace)::", "")
     if not short.endswith(">") or "<double" not in short:
         return None
+    if short.startswith("mortar_kernel") and short.endswith("true>"):
+        return None  # the estimator's form
     if short.startswith("trace_kernel") or short.startswith("mortar_kernel"):
         return "both"
     if short.startswith("fast_kernel") or short.startswith("apply_kernel"):
@@ -314,7 +316,7 @@ def run_solves(args, W, hp, ctx, steps, warmup, kinds_names, cpu=True):
                      "p50_ms": float(np.percentile(lat_bf, 50)), "p99_ms": float(np.percentile(lat_bf, 99))}
 
     est_info = None
-    if prob is not None and not newton:
+    if prob is not None and not newton and not args.no_estimator:
         # the a posteriori estimate of the last solution (Eqs. Eta2_*): the first call builds the
         # problem's point data on the host; the timed calls run the kernels only
         eta2 = torch.zeros(M.n_elem[0], dtype=torch.float64, device=dev)
@@ -407,6 +409,8 @@ def main():
     ap.add_argument("--p", type=int, default=5)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-shell", action="store_true", help="hp workload: skip the shell sub-measurement")
+    ap.add_argument("--no-estimator", action="store_true",
+                    help="skip the a posteriori estimate after the solves (profiles of the solve alone)")
     ap.add_argument("--shell-steps", type=int, default=5, help="timed solves of the shell sub-measurement")
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--profile-apply", action="store_true",
