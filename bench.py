@@ -415,6 +415,9 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--profile-apply", action="store_true",
                     help="only upload the mesh and run --apply-reps FP64 and FP32 applies (for rocprofv3)")
+    ap.add_argument("--profile-estimate", action="store_true",
+                    help="only upload the mesh and run --apply-reps a posteriori estimates of a seeded vector "
+                         "(for rocprofv3)")
     ap.add_argument("--unfused", action="store_true",
                     help="block smoothing with the apply and the block step in separate kernels")
     ap.add_argument("--sweep-p", default="2,3,4,5,6,7", help="sweep: degrees")
@@ -457,6 +460,17 @@ def main():
         return run_sweep(args, meshgen, hp)
     W = make_workload(args, meshgen, hp)
     ctx = hp.Context(0)
+    if args.profile_estimate:
+        M = ctx.upload(W["mesh"], **W["upload"])
+        u = torch.randn(M.n_dof[0], dtype=torch.float64, device=dev, generator=torch.Generator(dev).manual_seed(0))
+        eta2 = torch.zeros(M.n_elem[0], dtype=torch.float64, device=dev)
+        for _ in range(args.apply_reps):
+            M.estimate(W["prob"], u, eta2)
+        torch.cuda.synchronize()
+        eb, vp, mp = M.estimate_info()
+        print(json.dumps({"profile_estimate": True, "dof": M.n_dof[0], "reps": args.apply_reps, "alg_bytes": eb,
+                          "volume_points": vp, "mortar_points": mp}))
+        return
     if args.profile_apply:
         up = dict(W["upload"])
         if args.max_levels >= 0:
