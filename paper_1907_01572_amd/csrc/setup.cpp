@@ -8,6 +8,10 @@
 #include <array>
 #include <map>
 #include <cmath>
+#include <exception>
+#include <mutex>
+#include <system_error>
+#include <thread>
 
 namespace hpdg {
 
@@ -317,6 +321,42 @@ MortarTask mortar_task(const LevelHost& L, const MortarInfo& M) {
 }
 
 // ---------------------------------------------------------------------------------
+// f(i) for i in [0, n) on up to 16 host threads (contiguous ranges; every f(i) writes only its
+// own outputs, so the result does not depend on the split).  The first exception thrown by any
+// f is rethrown here after every thread has been joined; a thread that cannot be started
+// leaves its range to the calling thread.
+template <typename F>
+void parallel_for(size_t n, F&& f) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>(std::min<size_t>(hw, 16), std::max<size_t>(1, n / 64));
+  std::exception_ptr err;
+  std::mutex mu;
+  auto range = [&](size_t lo, size_t hi) {
+    try {
+      for (size_t i = lo; i < hi; ++i) f(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(mu);
+      if (!err) err = std::current_exception();
+    }
+  };
+  if (nt <= 1) {
+    range(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    size_t started = 0;
+    for (; started < nt; ++started) {
+      try {
+        pool.emplace_back(range, n * started / nt, n * (started + 1) / nt);
+      } catch (const std::system_error&) {
+        break;
+      }
+    }
+    if (started < nt) range(n * started / nt, n);
+    for (std::thread& th : pool) th.join();
+  }
+  if (err) std::rethrow_exception(err);
+}
+
 void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, LevelHost& L) {
   const size_t E = L.cells.size();
   L.mortars = find_mortars(mm, L.cells);
@@ -326,24 +366,31 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
   L.nmq = 0;
   L.ntrace = 0;
   L.nmax = L.qmax = L.qmmax = 0;
+  // elements: nodes and dof offsets (a nodal k is read through them), then the rule and metric
+  // mode (the check for one value of k evaluates k at every GL point)
   long long off = 0;
-  double eta[kMaxQ + 1], wq[kMaxQ + 1];
   for (size_t e = 0; e < E; ++e) {
     const Cell& c = L.cells[e];
     if (c.p < 1 || c.p > kMaxN - 1) throw Error(-2, "degree outside [1, 15]");
     ElemInfo& I = L.einfo[e];
-    const bool affine = mm.macros[c.macro].kind == 0;
     I.n = c.p + 1;
+    I.off = off;
+    off += (long long)I.n * I.n * I.n;
+  }
+  std::vector<double> kel_of(E, 1.0);
+  parallel_for(E, [&](size_t e) {
+    const Cell& c = L.cells[e];
+    ElemInfo& I = L.einfo[e];
+    const bool affine = mm.macros[c.macro].kind == 0;
     // affine, constant k and no mass term: every volume integrand is integrated exactly by n points
     I.q = I.n + ((affine && kc && !dp.mass_term) ? 0 : dp.quad_extra);
     if (I.q > kMaxQ) throw Error(-2, "too many quadrature points");
-    I.off = off;
-    off += (long long)I.n * I.n * I.n;
     // constant metric: affine map and one value of k at every GL point of the element (k is
     // folded into the 6 stored values; the rule keeps its q points)
     double kel = 1.0;
     bool kflat = kc;
     if (affine && !kc) {
+      double eta[kMaxQ + 1], wq[kMaxQ + 1];
       gauss_legendre(I.q, eta, wq);
       kflat = true;
       for (int cc = 0; cc < I.q && kflat; ++cc)
@@ -358,13 +405,26 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     }
     I.vmode = (affine && kflat) ? 0 : 1;
     I.mass = dp.mass_term ? 1 : 0;
+    kel_of[e] = kel;
+  });
+  long long nv = 0;
+  for (size_t e = 0; e < E; ++e) {
+    ElemInfo& I = L.einfo[e];
     I.mq = L.nmq;
     if (I.mass) L.nmq += (long long)I.q * I.q * I.q;
     I.toff = L.ntrace;
     L.ntrace += 12LL * I.n * I.n;
-    I.vgeo = (long long)L.vgeo.size();
+    I.vgeo = nv;
+    nv += I.vmode == 0 ? 6 : 6LL * I.q * I.q * I.q;
     L.nmax = std::max(L.nmax, I.n);
     L.qmax = std::max(L.qmax, I.q);
+  }
+  L.vgeo.assign(size_t(nv), 0.0);
+  parallel_for(E, [&](size_t e) {
+    const ElemInfo& I = L.einfo[e];
+    const Cell& c = L.cells[e];
+    double* out = L.vgeo.data() + I.vgeo;
+    const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
     double x[3], J[3][3], Ji[3][3];
     if (I.vmode == 0) {
       double xi[3] = {0, 0, 0};
@@ -372,43 +432,59 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       const double dj = det3(J);
       if (!(dj > 0)) throw Error(-2, "non-positive Jacobian determinant");
       inv3(J, Ji);
-      const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
       for (int m = 0; m < 6; ++m) {
         double g = 0;
         for (int i = 0; i < 3; ++i) g += Ji[pr[m][0]][i] * Ji[pr[m][1]][i];
-        L.vgeo.push_back(dj * kel * g);
+        out[m] = dj * kel_of[e] * g;
       }
-    } else {
-      const int q = I.q, q3 = q * q * q;
-      gauss_legendre(q, eta, wq);
-      const size_t base = L.vgeo.size();
-      L.vgeo.resize(base + 6 * size_t(q3));
-      for (int cc = 0; cc < q; ++cc)
-        for (int b = 0; b < q; ++b)
-          for (int a = 0; a < q; ++a) {
-            double xi[3] = {eta[a], eta[b], eta[cc]};
-            cell_eval(mm, c, xi, x, J);
-            const double dj = det3(J);
-            if (!(dj > 0)) throw Error(-2, "non-positive Jacobian determinant");
-            inv3(J, Ji);
-            const double s = wq[a] * wq[b] * wq[cc] * dj * k_point(dp, L, int(e), xi, x);
-            const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-            const int idx = a + q * (b + q * cc);
-            for (int m = 0; m < 6; ++m) {
-              double g = 0;
-              for (int i = 0; i < 3; ++i) g += Ji[pr[m][0]][i] * Ji[pr[m][1]][i];
-              L.vgeo[base + size_t(m) * q3 + idx] = s * g;
-            }
-          }
+      return;
     }
-  }
+    const int q = I.q, q3 = q * q * q;
+    double eta[kMaxQ + 1], wq[kMaxQ + 1];
+    gauss_legendre(q, eta, wq);
+    for (int cc = 0; cc < q; ++cc)
+      for (int b = 0; b < q; ++b)
+        for (int a = 0; a < q; ++a) {
+          double xi[3] = {eta[a], eta[b], eta[cc]};
+          cell_eval(mm, c, xi, x, J);
+          const double dj = det3(J);
+          if (!(dj > 0)) throw Error(-2, "non-positive Jacobian determinant");
+          inv3(J, Ji);
+          const double sc = wq[a] * wq[b] * wq[cc] * dj * k_point(dp, L, int(e), xi, x);
+          const int idx = a + q * (b + q * cc);
+          for (int m = 0; m < 6; ++m) {
+            double g = 0;
+            for (int i = 0; i < 3; ++i) g += Ji[pr[m][0]][i] * Ji[pr[m][1]][i];
+            out[size_t(m) * q3 + idx] = sc * g;
+          }
+        }
+  });
   L.ndof = off;
-  // mortars
+  // mortars: rule and metric mode, then the metric
   const size_t M = L.mortars.size();
   L.minfo.assign(M, MortarInfo{});
   L.mgeo.clear();
   std::vector<std::vector<int>> lists(E * 6);
-  for (size_t mi = 0; mi < M; ++mi) {
+  std::vector<double> kmt_of(M, 1.0), kpt_of(M, 1.0);
+  std::vector<int> pm_of(M, 0);
+  // each side's k at a mortar point: a tabulated k may jump across the mortar, so each side
+  // takes its own element's value (an analytic k is single-valued: the minus side's value)
+  auto side_k = [&](const Mortar& mt, double s_, double t_, double& km, double& kp) {
+    const Cell& cm = L.cells[mt.em];
+    double xim[3], xp[3], Jp[3][3];
+    face_ref(mt.fm, s_, t_, xim);
+    cell_eval(mm, cm, xim, xp, Jp);
+    km = k_point(dp, L, mt.em, xim, xp);
+    kp = km;
+    if (mt.ep >= 0 && dp.kfield) {
+      double a, b, xip[3], xq[3], Jq[3][3];
+      plus_coords(mt.orient, mt.sub, s_, t_, a, b);
+      face_ref(mt.fp, a, b, xip);
+      cell_eval(mm, L.cells[mt.ep], xip, xq, Jq);
+      kp = k_point(dp, L, mt.ep, xip, xq);
+    }
+  };
+  parallel_for(M, [&](size_t mi) {
     const Mortar& mt = L.mortars[mi];
     MortarInfo& I = L.minfo[mi];
     I.em = mt.em; I.fm = mt.fm; I.ep = mt.ep; I.fp = mt.fp;
@@ -418,42 +494,27 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
     const bool robin = !interior && mt.bc == 3;
     if (!interior && mt.bc != 1 && !robin) {  // Neumann: no operator term
       I.q = 0; I.gmode = 0; I.geo = -1;
-      continue;
+      return;
     }
     const int nm = cm.p + 1;
     const int np = interior ? L.cells[mt.ep].p + 1 : 0;
     const bool curved = mm.macros[cm.macro].kind != 0 ||
                         (interior && mm.macros[L.cells[mt.ep].macro].kind != 0);
-    const int pm = std::max(nm, np) - 1;
+    pm_of[mi] = std::max(nm, np) - 1;
     I.q = std::max(nm, np) + ((curved || !kc) ? dp.quad_extra : 0);
     if (I.q > kMaxQ) throw Error(-2, "too many mortar quadrature points");
     I.rq = I.q;
-    // each side's k at a mortar point: a tabulated k may jump across the mortar, so each side
-    // takes its own element's value (an analytic k is single-valued: the minus side's value)
-    auto side_k = [&](double s_, double t_, double& km, double& kp) {
-      double xim[3], xp[3], Jp[3][3];
-      face_ref(mt.fm, s_, t_, xim);
-      cell_eval(mm, cm, xim, xp, Jp);
-      km = k_point(dp, L, mt.em, xim, xp);
-      kp = km;
-      if (interior && dp.kfield) {
-        double a, b, xip[3], xq[3], Jq[3][3];
-        plus_coords(mt.orient, mt.sub, s_, t_, a, b);
-        face_ref(mt.fp, a, b, xip);
-        cell_eval(mm, L.cells[mt.ep], xip, xq, Jq);
-        kp = k_point(dp, L, mt.ep, xip, xq);
-      }
-    };
     // constant metric on a flat mortar where each side's k takes one value at all its points
     // (folded in)
     double kmt = 1.0, kpt = 1.0;
     bool kflat = kc;
     if (!curved && !kc) {
+      double eta[kMaxQ + 1], wq[kMaxQ + 1];
       gauss_legendre(I.q, eta, wq);
       kflat = true;
       for (int pidx = 0; pidx < I.q * I.q && kflat; ++pidx) {
         double km, kp;
-        side_k(eta[pidx % I.q], eta[pidx / I.q], km, kp);
+        side_k(mt, eta[pidx % I.q], eta[pidx / I.q], km, kp);
         if (pidx == 0) {
           kmt = km;
           kpt = kp;
@@ -462,15 +523,33 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       }
     }
     I.gmode = (curved || !kflat) ? 1 : 0;
-    I.geo = (long long)L.mgeo.size();
+    kmt_of[mi] = kmt;
+    kpt_of[mi] = kpt;
+  });
+  long long ng = 0;
+  for (size_t mi = 0; mi < M; ++mi) {
+    MortarInfo& I = L.minfo[mi];
+    if (I.q == 0) continue;
+    I.geo = ng;
+    ng += 8LL * (I.gmode ? (long long)I.q * I.q : 1);
     L.qmmax = std::max(L.qmmax, I.q);
-    lists[size_t(mt.em) * 6 + mt.fm].push_back(int(mi) << 1);
-    if (interior) lists[size_t(mt.ep) * 6 + mt.fp].push_back((int(mi) << 1) | 1);
+    lists[size_t(I.em) * 6 + I.fm].push_back(int(mi) << 1);
+    if (I.ep >= 0) lists[size_t(I.ep) * 6 + I.fp].push_back((int(mi) << 1) | 1);
+  }
+  L.mgeo.assign(size_t(ng), 0.0);
+  parallel_for(M, [&](size_t mi) {
+    const MortarInfo& I = L.minfo[mi];
+    if (I.q == 0) return;
+    const Mortar& mt = L.mortars[mi];
+    const Cell& cm = L.cells[mt.em];
+    const bool interior = mt.ep >= 0;
+    const bool robin = !interior && mt.bc == 3;
+    const int pm = pm_of[mi];
     const int q = I.q;
+    double eta[kMaxQ + 1], wq[kMaxQ + 1];
     gauss_legendre(q, eta, wq);
     const int npts = I.gmode ? q * q : 1;
-    const size_t base = L.mgeo.size();
-    L.mgeo.resize(base + 8 * size_t(npts));
+    double* out = L.mgeo.data() + I.geo;
     const int dmn = mt.fm >> 1;
     const double sgn = (mt.fm & 1) ? 1.0 : -1.0;
     for (int pidx = 0; pidx < npts; ++pidx) {
@@ -485,8 +564,8 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       double nh[3] = {sgn * Ji[dmn][0] / nr, sgn * Ji[dmn][1] / nr, sgn * Ji[dmn][2] / nr};
       const double S = dj * nr;
       double h = 2.0 / nr;
-      double kx = kmt, kxp = kpt;
-      if (I.gmode) side_k(s, t, kx, kxp);
+      double kx = kmt_of[mi], kxp = kpt_of[mi];
+      if (I.gmode) side_k(mt, s, t, kx, kxp);
       double mminus[3], mplus[3] = {0, 0, 0};
       for (int r = 0; r < 3; ++r)
         mminus[r] = kx * (Ji[r][0] * nh[0] + Ji[r][1] * nh[1] + Ji[r][2] * nh[2]);
@@ -513,9 +592,9 @@ void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, Le
       }
       const double wS = I.gmode ? wq[c] * wq[d] * S : S;
       double vals[8] = {mminus[0], mminus[1], mminus[2], mplus[0], mplus[1], mplus[2], wS, sigma};
-      for (int k = 0; k < 8; ++k) L.mgeo[base + size_t(k) * npts + pidx] = vals[k];
+      for (int k = 0; k < 8; ++k) out[size_t(k) * npts + pidx] = vals[k];
     }
-  }
+  });
   L.fmlist.clear();
   for (size_t e = 0; e < E; ++e)
     for (int f = 0; f < 6; ++f) {
@@ -1099,13 +1178,19 @@ void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscPara
   out = EstTables{};
   out.voff.resize(E);
   out.he2p2.resize(E);
-  double eta[kMaxQ + 1], wq[kMaxQ + 1];
+  long long nv = 0;
   for (size_t e = 0; e < E; ++e) {
+    out.voff[e] = nv;
+    nv += 3LL * L.einfo[e].q * L.einfo[e].q * L.einfo[e].q;
+  }
+  out.vol.assign(size_t(nv), 0.0);
+  parallel_for(E, [&](size_t e) {
     const ElemInfo& I = L.einfo[e];
     const Cell& c = L.cells[e];
     const int q = I.q;
+    double eta[kMaxQ + 1], wq[kMaxQ + 1];
     gauss_legendre(q, eta, wq);
-    out.voff[e] = (long long)out.vol.size();
+    double* o = out.vol.data() + out.voff[e];
     for (int cc = 0; cc < q; ++cc)
       for (int b = 0; b < q; ++b)
         for (int a = 0; a < q; ++a) {
@@ -1118,9 +1203,10 @@ void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscPara
             djg = det3(Jg);
             if (!(djg > 0)) throw Error(-2, "estimator grid: non-positive Jacobian determinant");
           }
-          out.vol.push_back(wq[a] * wq[b] * wq[cc] * djg);
-          out.vol.push_back(1.0 / dj);
-          out.vol.push_back(source(kind, P, x));
+          const size_t k = 3 * size_t(a + q * (b + q * cc));
+          o[k] = wq[a] * wq[b] * wq[cc] * djg;
+          o[k + 1] = 1.0 / dj;
+          o[k + 2] = source(kind, P, x);
         }
     // h_e: the largest distance between two of the element's vertices
     double X[8][3];
@@ -1135,7 +1221,7 @@ void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscPara
         h2 = std::max(h2, dx * dx + dy * dy + dz * dz);
       }
     out.he2p2[e] = h2 * double(c.p) * double(c.p);
-  }
+  });
   // at reference point xi of cell c: S = det J |grad xi_d| and 2 / |grad xi_d| on mesh m
   auto face_metric = [](const MacroMesh& m, const Cell& c, const double xi[3], int d, double& S, double& h,
                         double x[3]) {
@@ -1146,16 +1232,24 @@ void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscPara
     S = det3(J) * nr;
     h = 2.0 / nr;
   };
+  long long nf = 0;
   for (size_t m = 0; m < L.minfo.size(); ++m) {
     const MortarInfo& M = L.minfo[m];
     if (M.q == 0 || (M.ep < 0 && M.bc != 1)) continue;  // Neumann, Robin: no estimator term
     out.tasks.push_back(mortar_task(L, M));
     out.task_mortar.push_back(int(m));
-    out.foff.push_back((long long)out.face.size());
+    out.foff.push_back(nf);
+    nf += 4LL * M.q * M.q;
+  }
+  out.face.assign(size_t(nf), 0.0);
+  parallel_for(out.tasks.size(), [&](size_t t) {
+    const MortarInfo& M = L.minfo[size_t(out.task_mortar[t])];
     const int q = M.q;
+    double eta[kMaxQ + 1], wq[kMaxQ + 1];
     gauss_legendre(q, eta, wq);
     const Cell& cm = L.cells[M.em];
     const int pm = std::max(cm.p, M.ep >= 0 ? L.cells[M.ep].p : 0);
+    double* o = out.face.data() + out.foff[t];
     for (int d = 0; d < q; ++d)
       for (int ci = 0; ci < q; ++ci) {
         double xim[3], x[3], xg[3], S, h, Sg, hg;
@@ -1178,12 +1272,13 @@ void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscPara
           }
         }
         if (!(Sg > 0)) throw Error(-2, "estimator grid: non-positive face Jacobian");
-        out.face.push_back(hg / double(pm));
-        out.face.push_back(M.ep >= 0 ? 0.0 : exact_u(kind, P, x));
-        out.face.push_back(Sg / S);
-        out.face.push_back(h / hg);
+        const size_t k = 4 * size_t(ci + q * d);
+        o[k] = hg / double(pm);
+        o[k + 1] = M.ep >= 0 ? 0.0 : exact_u(kind, P, x);
+        o[k + 2] = Sg / S;
+        o[k + 3] = h / hg;
       }
-  }
+  });
 }
 
 }  // namespace hpdg
