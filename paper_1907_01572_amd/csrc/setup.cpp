@@ -819,70 +819,76 @@ void build_transfer(LevelHost& fine, const LevelHost& coarse) {
 void build_diagonal(const OpTable& T, LevelHost& L) {
   L.diag.assign(size_t(L.ndof), 0.0);
   const double* td = T.data.data();
-  std::vector<double> t1, t2;
-  for (size_t e = 0; e < L.einfo.size(); ++e) {
+  // one element per task: its volume part, then its sides of its mortars in mortar order (each
+  // entry sums its terms in the same order whatever the number of threads)
+  parallel_for(L.einfo.size(), [&](size_t e) {
     const ElemInfo& I = L.einfo[e];
-    const int n = I.n, q = I.q, q3 = q * q * q;
-    const double* B = td + T.index(OpTable::GL_VAL, n, q);
-    const double* Dt = td + T.index(OpTable::GL_DER, n, q);
-    const double* w = td + T.w_off[q];
-    const double* G = L.vgeo.data() + I.vgeo;
-    double* out = L.diag.data() + I.off;
-    const double* fac[2] = {B, Dt};
-    const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
-    t1.assign(size_t(q) * q * n, 0.0);
-    t2.assign(size_t(q) * n * n, 0.0);
-    for (int m = 0; m < 6; ++m) {
-      const int d0 = pr[m][0], d1 = pr[m][1];
-      const double mult = d0 == d1 ? 1.0 : 2.0;
-      // factor along axis x of phi_d phi_d' : derivative where the axis is d or d'
-      const double* X0 = fac[d0 == 0]; const double* X1 = fac[d1 == 0];
-      const double* Y0 = fac[d0 == 1]; const double* Y1 = fac[d1 == 1];
-      const double* Z0 = fac[d0 == 2]; const double* Z1 = fac[d1 == 2];
-      auto g = [&](int idx) {
-        if (I.vmode == 0) {
-          const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
-          return G[m] * w[a] * w[b] * w[c];
-        }
-        return G[size_t(m) * q3 + idx];
-      };
-      // t1[c][b][i] = sum_a X0[a][i] X1[a][i] g[c][b][a]
-      for (int cb = 0; cb < q * q; ++cb)
-        for (int i = 0; i < n; ++i) {
-          double s = 0;
-          for (int a = 0; a < q; ++a) s += X0[a * n + i] * X1[a * n + i] * g(cb * q + a);
-          t1[size_t(cb) * n + i] = s;
-        }
-      // t2[c][j][i] = sum_b Y0[b][j] Y1[b][j] t1[c][b][i]
-      for (int c = 0; c < q; ++c)
-        for (int j = 0; j < n; ++j)
+    std::vector<double> t1, t2;
+    {
+      const int n = I.n, q = I.q, q3 = q * q * q;
+      const double* B = td + T.index(OpTable::GL_VAL, n, q);
+      const double* Dt = td + T.index(OpTable::GL_DER, n, q);
+      const double* w = td + T.w_off[q];
+      const double* G = L.vgeo.data() + I.vgeo;
+      double* out = L.diag.data() + I.off;
+      const double* fac[2] = {B, Dt};
+      const int pr[6][2] = {{0, 0}, {0, 1}, {0, 2}, {1, 1}, {1, 2}, {2, 2}};
+      t1.assign(size_t(q) * q * n, 0.0);
+      t2.assign(size_t(q) * n * n, 0.0);
+      for (int m = 0; m < 6; ++m) {
+        const int d0 = pr[m][0], d1 = pr[m][1];
+        const double mult = d0 == d1 ? 1.0 : 2.0;
+        // factor along axis x of phi_d phi_d' : derivative where the axis is d or d'
+        const double* X0 = fac[d0 == 0]; const double* X1 = fac[d1 == 0];
+        const double* Y0 = fac[d0 == 1]; const double* Y1 = fac[d1 == 1];
+        const double* Z0 = fac[d0 == 2]; const double* Z1 = fac[d1 == 2];
+        auto g = [&](int idx) {
+          if (I.vmode == 0) {
+            const int a = idx % q, b = (idx / q) % q, c = idx / (q * q);
+            return G[m] * w[a] * w[b] * w[c];
+          }
+          return G[size_t(m) * q3 + idx];
+        };
+        // t1[c][b][i] = sum_a X0[a][i] X1[a][i] g[c][b][a]
+        for (int cb = 0; cb < q * q; ++cb)
           for (int i = 0; i < n; ++i) {
             double s = 0;
-            for (int b = 0; b < q; ++b) s += Y0[b * n + j] * Y1[b * n + j] * t1[(size_t(c) * q + b) * n + i];
-            t2[(size_t(c) * n + j) * n + i] = s;
+            for (int a = 0; a < q; ++a) s += X0[a * n + i] * X1[a * n + i] * g(cb * q + a);
+            t1[size_t(cb) * n + i] = s;
           }
-      for (int k = 0; k < n; ++k)
-        for (int j = 0; j < n; ++j)
-          for (int i = 0; i < n; ++i) {
-            double s = 0;
-            for (int c = 0; c < q; ++c) s += Z0[c * n + k] * Z1[c * n + k] * t2[(size_t(c) * n + j) * n + i];
-            out[(k * n + j) * n + i] += mult * s;
-          }
+        // t2[c][j][i] = sum_b Y0[b][j] Y1[b][j] t1[c][b][i]
+        for (int c = 0; c < q; ++c)
+          for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+              double s = 0;
+              for (int b = 0; b < q; ++b) s += Y0[b * n + j] * Y1[b * n + j] * t1[(size_t(c) * q + b) * n + i];
+              t2[(size_t(c) * n + j) * n + i] = s;
+            }
+        for (int k = 0; k < n; ++k)
+          for (int j = 0; j < n; ++j)
+            for (int i = 0; i < n; ++i) {
+              double s = 0;
+              for (int c = 0; c < q; ++c) s += Z0[c * n + k] * Z1[c * n + k] * t2[(size_t(c) * n + j) * n + i];
+              out[(k * n + j) * n + i] += mult * s;
+            }
+      }
     }
-  }
-  // faces: psi^2 sigma and the consistency/symmetry self terms, face nodes only
-  for (size_t mi = 0; mi < L.minfo.size(); ++mi) {
-    const MortarInfo& M = L.minfo[mi];
-    if (M.q == 0) continue;
-    const int q = M.q;
-    const bool interior = M.ep >= 0;
-    const double factor = interior ? 1.0 : 2.0;
-    const double* wq = td + T.w_off[q];
-    const double* mg = L.mgeo.data() + M.geo;
-    const int npts = M.gmode ? q * q : 1;
-    for (int side = 0; side < (interior ? 2 : 1); ++side) {
-      const int e = side ? M.ep : M.em, f = side ? M.fp : M.fm;
-      const ElemInfo& I = L.einfo[e];
+    // faces: psi^2 sigma and the consistency/symmetry self terms, face nodes only
+    std::vector<int> ents;
+    for (int f = 0; f < 6; ++f)
+      for (int r = 0; r < I.fcnt[f]; ++r) ents.push_back(L.fmlist[size_t(I.fstart[f] + r)]);
+    std::sort(ents.begin(), ents.end());
+    for (int ent : ents) {
+      const MortarInfo& M = L.minfo[size_t(ent >> 1)];
+      const int side = ent & 1;
+      if (M.q == 0) continue;
+      const int q = M.q;
+      const bool interior = M.ep >= 0;
+      const double factor = interior ? 1.0 : 2.0;
+      const double* wq = td + T.w_off[q];
+      const double* mg = L.mgeo.data() + M.geo;
+      const int npts = M.gmode ? q * q : 1;
+      const int f = side ? M.fp : M.fm;
       const int n = I.n, d = f >> 1, t0 = d == 0 ? 1 : 0, t1_ = d == 2 ? 1 : 2;
       const SideMap sm = side_map(M, side);
       const double* La = td + T.index(OpTable::GL_VAL + 2 * sm.halfA, n, q);
@@ -915,7 +921,7 @@ void build_diagonal(const OpTable& T, LevelHost& L) {
           L.diag[size_t(I.off) + (idx[2] * n + idx[1]) * n + idx[0]] += s;
         }
     }
-  }
+  });
 }
 
 // ---------------------------------------------------------------------------------
