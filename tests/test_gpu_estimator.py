@@ -151,3 +151,26 @@ def test_estimator_parity_on_a_fiducial_grid(ctx, name, twin):
         M.set_estimator_grid(other)
     assert ei.value.code == hp.ERR_INVALID_MESH
     M.free()
+
+
+def test_compact_estimator_moves_the_marks_inwards(ctx):
+    # the library's estimates of the interpolated solution on the shell compactified to r = 1e9:
+    # marking the largest 10% picks the stretched outer cells on the physical grid and the inner
+    # cells on the unstretched twin (Sec. III.C)
+    maker, prob = MESHES["shell_l2_p4_r1e9"]
+    m = maker()
+    op = SIPG(m, prob)
+    M = ctx.upload(m, coef=coef_of(prob))
+    u = torch.tensor(op.interpolate(lambda x: P.exact_u(prob, x))[dof_perm(M.level_cells(0), m)], device="cuda")
+    cells = M.level_cells(0)
+    zc = -1 + (2 * cells["elem_anchor"][:, 2] + 1) / 2.0 ** cells["elem_level"]
+    eta2 = torch.zeros(M.n_elem[0], dtype=torch.float64, device="cuda")
+    shares = []
+    for grid in (None, _linear_shell_twin(m)):
+        M.set_estimator_grid(grid)
+        M.estimate(prob, u, eta2)
+        marked = hp.amr_mark(eta2.cpu().numpy(), hp.MARK_FRACTION, 0.1)
+        shares.append(float(np.mean(zc[marked] > 0)))
+    print("share of marked cells in the outer half: physical grid", shares[0], "twin", shares[1], flush=True)
+    assert shares[0] > 0.8 and shares[1] == 0.0
+    M.free()

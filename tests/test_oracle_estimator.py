@@ -208,3 +208,29 @@ def test_fiducial_grid_refuses_other_cells():
     other = meshgen.box_grid((2, 1, 1), 1, 3)
     with pytest.raises(ValueError):
         est.estimate(op, np.zeros(op.ndof), prob, fiducial=other)
+
+
+def test_compact_estimator_marks_the_inner_cells_of_a_compactified_shell():
+    # Sec. III.C: on a shell compactified to r = 1e9 the estimate on the physical grid is
+    # dominated by the stretched outer cells (their Jacobians), so marking refines there; on the
+    # unstretched twin (radii 2..3) it marks the inner cells, where the solution varies, as
+    # both estimates do on the mildly stretched shell (r = 1e3)
+    prob = meshgen.problem_config2()
+
+    def marked_outer_share(r_out, compact):
+        mesh = meshgen.cubed_sphere_shell(level=2, p=3, r_out=r_out)
+        op = SIPG(mesh, prob)
+        u = op.interpolate(lambda x: problems.exact_u(prob, x))
+        fid = None
+        if compact:
+            fid = dict(mesh)
+            par = np.array(mesh["macro_params"], float, copy=True)
+            par[:, 9], par[:, 10], par[:, 11] = 0.0, 2.0, 3.0
+            fid["macro_params"] = par
+        mk = est.mark_fraction(est.estimate(op, u, prob, fiducial=fid)["eta2"], 0.1)
+        zc = -1 + (2 * mesh["elem_anchor"][:, 2] + 1) / 2.0 ** mesh["elem_level"]  # radial macro coordinate
+        return float(np.mean(zc[mk] > 0))
+
+    assert marked_outer_share(1e9, compact=False) > 0.8
+    assert marked_outer_share(1e9, compact=True) == 0.0
+    assert marked_outer_share(1e3, compact=False) == 0.0
