@@ -333,8 +333,10 @@ int hpdg_assemble_rhs(hpdg_mesh* mesh, const hpdg_rhs_desc* rhs, double* F_dev, 
  *   eta2(e) = h_e^2 p_e^2 int_e R^2 + sum over the interior mortars of e of
  *             int_m ((h_m / p_m) [[k grad u]]^2 + sigma [[u]]^2) + sum over its Dirichlet mortars of
  *             int_m sigma (u - g_D)^2,
- * R = g + div(k grad u) - c u; sigma the operator's penalty (Eq. penaltyparameter, with
- * max(k-, k+)) and h_m, p_m as there, pointwise on the mortar rule; h_e the largest distance
+ * R = g + div(k grad u) - c u (c: the mass coefficient the operator applies, so after
+ * hpdg_nonlinear_linearize the Jacobian's mass term); sigma the operator's penalty
+ * (Eq. penaltyparameter, with max(k-, k+)) and h_m, p_m as there, pointwise on the mortar
+ * rule; h_e the largest distance
  * between two vertices of e; div(k grad u) by the collocation derivative on the element's GL
  * points (exact on affine elements with a constant k); Neumann and Robin faces add no term.
  * eta2_vol_dev (may be NULL): the volume parts h_e^2 p_e^2 int_e R^2.  Runs on the device in
