@@ -1,0 +1,139 @@
+"""Additive Schwarz smoother (Sec. II.D, the Schwarz smoother: Alg. schwarz_smoother,
+Eq. schwarz_weight).
+
+Test infrastructure: only the tests, the smoke check and the CPU baseline of the benchmark use
+this package.  Plain FP64 numpy on the dense operator of ``operator.assemble_dense``.
+
+Subdomains, one per element e_c: the collocation points of e_c, the boundary points of other
+elements that coincide with its faces, edges or corners, and N_overlap - 1 further layers of
+points around those.  This oracle builds them for meshes of axis-aligned affine elements of one
+degree and one refinement level without 2:1 faces (every neighbour of e_c meets it along a whole
+face, edge or corner).  The extended coordinate of a point of a neighbour e' along axis d is
+xi_ext = xi_e'(d) + 2 o_d, with xi_e' the point's reference coordinate in e' and o_d in
+{-1, 0, 1} the side of e_c on which e' lies; the points of e_c keep their own coordinate.  The
+subdomain holds the points with |xi_ext| <= 1 + delta on every axis, delta = 1 + xi_(N_overlap - 1)
+(xi_0 = -1 < xi_1 < ... the LGL nodes): the coincident layer at |xi_ext| = 1 and N_overlap - 1
+layers beyond it.  delta is also the overlap width of the weights.
+
+Weights (Eq. schwarz_weight): w(xi) = (phi((xi + 1) / delta) - phi((xi - 1) / delta)) / 2,
+phi(t) = sgn(t) for |t| > 1 and (15 t - 10 t^3 + 3 t^5) / 8 otherwise; the weight of a point is
+the product of w over the three axes.  For N_overlap = 1 (delta = 0) this is the limit
+w = 1 inside, 1/2 on |xi| = 1, 0 outside.  On a side of e_c that lies on the domain boundary the
+falling half of w is dropped (its phi term is replaced by its limit, -1 on the upper and +1 on
+the lower side): no other subdomain shares the points there, and the weights of all subdomains
+then sum to one at every point.
+
+Local solves: R_s A R_s^T d_s = R_s r solved exactly (the paper solves them by CG to a relative
+tolerance of 1e-3; the exact solve is that iteration's limit and keeps the smoother linear).
+
+Smoother: N_iter times r = b - A x, x <- x + sum_s R_s^T W_s d_s.
+"""
+import numpy as np
+
+from . import geometry, rules
+
+
+def phi(t):
+    t = np.asarray(t, float)
+    return np.where(np.abs(t) > 1.0, np.sign(t), (15.0 * t - 10.0 * t ** 3 + 3.0 * t ** 5) / 8.0)
+
+
+def weight_1d(xi, delta, lower_open=True, upper_open=True):
+    """w(xi) of Eq. schwarz_weight with overlap width delta (delta = 0: the step limit).  A side
+    that is not open (a domain-boundary side) keeps the weight at its plateau."""
+    xi = np.asarray(xi, float)
+    if delta == 0.0:
+        lo = np.where(xi > -1.0, 1.0, np.where(xi == -1.0, 0.5, 0.0)) if lower_open else np.ones_like(xi)
+        hi = np.where(xi < 1.0, 1.0, np.where(xi == 1.0, 0.5, 0.0)) if upper_open else np.ones_like(xi)
+        return lo * hi
+    a = phi((xi + 1.0) / delta) if lower_open else np.ones_like(xi)
+    b = phi((xi - 1.0) / delta) if upper_open else -np.ones_like(xi)
+    return 0.5 * (a - b)
+
+
+def overlap_width(n, n_overlap):
+    """delta = 1 + xi_(N_overlap - 1) for the n LGL nodes of the degree (0 for N_overlap = 1)."""
+    if not 1 <= n_overlap <= n - 1:
+        raise ValueError("N_overlap must lie in [1, n - 1]")
+    x, _ = rules.lgl(n)
+    return 1.0 + x[n_overlap - 1]
+
+
+def _boxes(mesh):
+    """Centre and half-widths of every element; refuses meshes outside the scope above."""
+    E = len(mesh["elem_p"])
+    if len(set(int(p) for p in mesh["elem_p"])) != 1 or len(set(int(l) for l in mesh["elem_level"])) != 1:
+        raise ValueError("the Schwarz subdomains here need one degree and one level")
+    x0, J = geometry.element_map(mesh, np.arange(E)[:, None], np.zeros((1, 3)))
+    J = J[:, 0]
+    diag = np.einsum("eii->ei", J)
+    if np.abs(J - diag[:, :, None] * np.eye(3)[None]).max() > 1e-12 * np.abs(J).max() or diag.min() <= 0:
+        raise ValueError("the Schwarz subdomains here need axis-aligned affine elements")
+    return x0[:, 0], diag
+
+
+def _neighbours(centre, half, c):
+    """Elements touching e_c (closures meet) and their side o in {-1, 0, 1}^3; refuses a
+    neighbour that does not meet e_c along a whole face, edge or corner."""
+    out = []
+    tol = 1e-10 * half[c].min()
+    for e in range(len(centre)):
+        if e == c:
+            continue
+        gap = np.abs(centre[e] - centre[c]) - (half[e] + half[c])
+        if np.any(gap > tol):
+            continue
+        o = np.zeros(3, int)
+        for d in range(3):
+            dc = centre[e, d] - centre[c, d]
+            if abs(dc) <= tol:
+                if abs(half[e, d] - half[c, d]) > tol:
+                    raise ValueError("a neighbour that overlaps e_c only in part")
+            else:
+                o[d] = 1 if dc > 0 else -1
+                if abs(gap[d]) > tol:
+                    raise ValueError("overlapping elements")
+        out.append((e, o))
+    return out
+
+
+def subdomains(op, n_overlap):
+    """Per element (mesh order): (global dof indices, weights) of its subdomain, own points first
+    in the element's dof order, then the neighbours' points by element and dof order."""
+    mesh = op.mesh
+    n = int(mesh["elem_p"][0]) + 1
+    delta = overlap_width(n, n_overlap)
+    centre, half = _boxes(mesh)
+    xl, _ = rules.lgl(n)
+    xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)  # x fastest
+    out = []
+    for c in range(len(mesh["elem_p"])):
+        nb = _neighbours(centre, half, c)
+        open_lo = [any(o[d] == -1 and not np.any(np.delete(o, d)) for _, o in nb) for d in range(3)]
+        open_hi = [any(o[d] == 1 and not np.any(np.delete(o, d)) for _, o in nb) for d in range(3)]
+        idx, wts = [], []
+        for e, o in [(c, np.zeros(3, int))] + nb:
+            ext = xi + 2.0 * o[None, :]
+            inside = np.all(np.abs(ext) <= 1.0 + delta + 1e-12, axis=1)
+            if not inside.any():
+                continue
+            w = np.ones(int(inside.sum()))
+            for d in range(3):
+                w = w * weight_1d(ext[inside, d], delta, open_lo[d], open_hi[d])
+            idx.append(op.offsets[e] + np.flatnonzero(inside))
+            wts.append(w)
+        out.append((np.concatenate(idx), np.concatenate(wts)))
+    return out
+
+
+def smooth(A, subs, b, x, n_iter):
+    """Alg. schwarz_smoother with exact local solves on the dense operator A."""
+    x = np.array(x, float, copy=True)
+    blocks = [(idx, w, np.linalg.inv(A[np.ix_(idx, idx)])) for idx, w in subs]
+    for _ in range(n_iter):
+        r = b - A @ x
+        dx = np.zeros_like(x)
+        for idx, w, inv in blocks:
+            np.add.at(dx, idx, w * (inv @ r[idx]))
+        x = x + dx
+    return x

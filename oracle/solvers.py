@@ -23,9 +23,9 @@
 import numpy as np
 import scipy.linalg
 
-from . import rules
+from . import rules, schwarz
 from .mesh import hierarchy, parent_map
-from .operator import SIPG, element_blocks
+from .operator import SIPG, assemble_dense, element_blocks
 
 
 class Transfer:
@@ -200,9 +200,12 @@ class Multigrid:
 
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
                  n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None,
-                 starts=None, max_levels=32, kfield=None, cfield=None, robin_gamma=0.0):
-        """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi) or "block"
-        (element-block Jacobi); ``jacobi`` selects "point" / "none" when it is not given.
+                 starts=None, max_levels=32, kfield=None, cfield=None, robin_gamma=0.0,
+                 schwarz_overlap=2):
+        """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi), "block"
+        (element-block Jacobi) or "schwarz" (Alg. schwarz_smoother with ``n_cheb`` cycles per
+        call and ``schwarz_overlap`` = N_overlap; no spectral bound); ``jacobi`` selects
+        "point" / "none" when it is not given.
         ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``).
         ``kfield`` / ``cfield``: tabulated coefficients of the finest level (SIPG), carried to
         the coarser levels by ``coarsen_field``."""
@@ -217,6 +220,7 @@ class Multigrid:
         self.transfers = [Transfer(self.ops[i], self.ops[i + 1]) for i in range(len(self.ops) - 1)]
         self.n_cheb, self.Lambda = n_cheb, Lambda
         self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")
+        self.schwarz_overlap = schwarz_overlap
         self.refresh(n_eigs, seed, lam, starts)
 
     def refresh(self, n_eigs=15, seed=0, lam=None, starts=None):
@@ -232,6 +236,12 @@ class Multigrid:
         self.A0 = 0.5 * (A0 + A0.T)
         self.chol = scipy.linalg.cho_factor(self.A0)
         self.lanczos = []
+        if self.smoother == "schwarz":
+            self.schwarz = []
+            for op in self.ops[:-1]:
+                A = assemble_dense(op)
+                self.schwarz.append((A, schwarz.subdomains(op, self.schwarz_overlap)))
+            lam = [0.0] * (len(self.ops) - 1)
         if lam is None:
             lam = []
             for l, (op, minv) in enumerate(zip(self.ops[:-1], self.minv)):
@@ -242,6 +252,8 @@ class Multigrid:
         self.lam = list(lam)
 
     def _make_minv(self, op):
+        if self.smoother == "schwarz":
+            return None
         if self.smoother == "point":
             dinv = 1.0 / op.diagonal()
             return lambda r: dinv * r
@@ -262,6 +274,9 @@ class Multigrid:
         return len(self.ops)
 
     def smooth(self, level, b, x):
+        if self.smoother == "schwarz":
+            A, subs = self.schwarz[level]
+            return schwarz.smooth(A, subs, b, x, self.n_cheb)
         return chebyshev(self.ops[level].apply, b, x, self.lam[level], self.Lambda, self.n_cheb,
                          self.minv[level])
 

@@ -1,0 +1,156 @@
+"""Pins of the oracle's additive Schwarz smoother (Sec. II.D: Eq. schwarz_weight, Alg.
+schwarz_smoother): closed forms of the weight function, the partition of unity, subdomain sizes
+that follow from the construction, an independent geometric membership test, exactness on a
+one-element mesh, and the robustness the text reports for the multigrid solve."""
+import numpy as np
+import pytest
+
+import meshgen
+from oracle import geometry, rules
+from oracle import schwarz as sw
+from oracle.operator import SIPG, assemble_dense
+from oracle.solvers import Multigrid, fcg
+
+
+def test_phi_and_weight_closed_forms():
+    # phi is the C1 smoothstep from -1 to 1: phi(+-1) = +-1, phi(0) = 0, slope 15/8 at 0 and 0
+    # at +-1 (one-sided differences), odd, constant outside [-1, 1]
+    t = np.linspace(-1.0, 1.0, 2001)
+    assert sw.phi(1.0) == 1.0 and sw.phi(-1.0) == -1.0 and sw.phi(0.0) == 0.0
+    assert np.allclose(sw.phi(-t), -sw.phi(t), rtol=0, atol=1e-15)
+    assert np.all(np.diff(sw.phi(t)) > 0)
+    h = 1e-6
+    assert abs((sw.phi(h) - sw.phi(-h)) / (2 * h) - 15.0 / 8.0) < 1e-9
+    assert abs((sw.phi(1.0) - sw.phi(1.0 - h)) / h) < 1e-5
+    assert np.all(sw.phi(np.array([1.5, 7.0, -2.0])) == np.array([1.0, 1.0, -1.0]))
+    for delta in (0.25, 0.5, 1.0):
+        # plateau 1 on |xi| <= 1 - delta, one half on the element faces, zero at the overlap's edge
+        assert np.all(sw.weight_1d(np.linspace(-1 + delta, 1 - delta, 11), delta) == 1.0)
+        assert np.allclose(sw.weight_1d(np.array([-1.0, 1.0]), delta), 0.5, rtol=0, atol=1e-15)
+        assert np.all(sw.weight_1d(np.array([-1 - delta, 1 + delta, 3.0]), delta) == 0.0)
+        # a domain-boundary side keeps the plateau up to and beyond the face
+        assert np.all(sw.weight_1d(np.array([1.0, 1.0 + delta / 2]), delta, upper_open=False) == 1.0)
+        assert sw.weight_1d(np.array([-1.0]), delta, upper_open=False)[0] == pytest.approx(0.5, abs=1e-15)
+
+
+@pytest.mark.parametrize("delta", [0.0, 0.3, 1.0, 1.7])
+def test_weights_of_a_row_of_elements_sum_to_one(delta):
+    # 1-D: the subdomains centred on the elements of an infinite row see a point at offsets
+    # xi - 2 c; their weights telescope to one everywhere (the points on the faces included)
+    xi = np.concatenate([np.linspace(-1.0, 1.0, 101), [-1.0, 1.0]])
+    total = sum(sw.weight_1d(xi - 2.0 * c, delta) for c in range(-3, 4))
+    assert np.allclose(total, 1.0, rtol=0, atol=1e-14)
+
+
+def test_overlap_width_from_the_lgl_nodes():
+    # delta = 1 + xi_(N_overlap - 1): 0 for one layer; for n = 4 the second node -1/sqrt(5)
+    assert sw.overlap_width(4, 1) == 0.0
+    assert sw.overlap_width(4, 2) == pytest.approx(1.0 - 1.0 / np.sqrt(5.0), rel=1e-14)
+    assert sw.overlap_width(3, 2) == pytest.approx(1.0, rel=1e-14)
+    with pytest.raises(ValueError):
+        sw.overlap_width(4, 4)
+
+
+MESHES = {
+    "cube_l2_p3": lambda: meshgen.unit_cube(2, 3),
+    "box_2x1x1_l1_p2": lambda: meshgen.box_grid((2, 1, 1), 1, 2),
+    "box_lopsided_l1_p3": lambda: meshgen.box_grid((1, 1, 1), 1, 3, lo=(-0.3, 0.0, 0.1), hi=(1.0, 0.5, 2.0)),
+}
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+@pytest.mark.parametrize("n_overlap", [1, 2])
+def test_weights_form_a_partition_of_unity(name, n_overlap):
+    op = SIPG(MESHES[name](), meshgen.problem_config1())
+    total = np.zeros(op.ndof)
+    for idx, w in sw.subdomains(op, n_overlap):
+        assert len(np.unique(idx)) == len(idx)
+        np.add.at(total, idx, w)
+    assert np.allclose(total, 1.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("n_overlap", [1, 2, 3])
+def test_subdomain_sizes(n_overlap):
+    # on a 4^3 grid of p = 3 (n = 4): an interior element's subdomain spans n + 2 N_overlap
+    # nodes per axis, a corner element's n + N_overlap (only one side has neighbours)
+    mesh = meshgen.unit_cube(2, 3)
+    op = SIPG(mesh, meshgen.problem_config1())
+    subs = sw.subdomains(op, n_overlap)
+    lo, hi = geometry.element_map(mesh, np.arange(len(mesh["elem_p"]))[:, None],
+                                  np.array([[-1.0, -1.0, -1.0], [1.0, 1.0, 1.0]]))[0].transpose(1, 0, 2)
+    interior = np.all((lo > 1e-12) & (hi < 1 - 1e-12), axis=1)
+    corner = np.all((np.abs(lo) < 1e-12) | (np.abs(hi - 1) < 1e-12), axis=1)
+    assert interior.sum() == 8 and corner.sum() == 8
+    for e in range(len(subs)):
+        if interior[e]:
+            assert len(subs[e][0]) == (4 + 2 * n_overlap) ** 3
+        if corner[e]:
+            assert len(subs[e][0]) == (4 + n_overlap) ** 3
+
+
+@pytest.mark.parametrize("name", list(MESHES))
+def test_membership_matches_the_physical_box(name):
+    # an independent derivation on these uniform grids: a point belongs to subdomain c exactly
+    # when its physical position, in units of e_c's half-widths from e_c's centre, lies within
+    # 1 + delta on every axis
+    mesh = MESHES[name]()
+    op = SIPG(mesh, meshgen.problem_config1())
+    n = int(mesh["elem_p"][0]) + 1
+    x = op.nodes()
+    E = len(mesh["elem_p"])
+    c0, J = geometry.element_map(mesh, np.arange(E)[:, None], np.zeros((1, 3)))
+    centre, half = c0[:, 0], np.einsum("eii->ei", J[:, 0])
+    for n_overlap in range(1, n):
+        delta = sw.overlap_width(n, n_overlap)
+        for c, (idx, w) in enumerate(sw.subdomains(op, n_overlap)):
+            rel = np.abs(x - centre[c]) / half[c]
+            expect = np.flatnonzero(np.all(rel <= 1 + delta + 1e-10, axis=1))
+            assert np.array_equal(np.sort(idx), expect)
+            assert np.array_equal(idx[:n ** 3], np.arange(op.offsets[c], op.offsets[c + 1]))
+
+
+def test_one_element_mesh_is_solved_in_one_cycle():
+    # the only subdomain is the whole mesh, every side is a domain boundary (weights 1): one
+    # cycle is the exact solve
+    mesh = meshgen.box_grid((1, 1, 1), 0, 3)
+    op = SIPG(mesh, meshgen.problem_config1())
+    A = assemble_dense(op)
+    b = op.rhs()
+    subs = sw.subdomains(op, 2)
+    assert len(subs) == 1 and np.all(subs[0][1] == 1.0)
+    x = sw.smooth(A, subs, b, np.random.default_rng(0).standard_normal(op.ndof), 1)
+    assert np.allclose(x, np.linalg.solve(A, b), rtol=0, atol=1e-12 * np.abs(x).max())
+
+
+def test_smoother_is_a_linear_iteration_with_a_fixed_point():
+    # the exact solution is a fixed point; the error after one cycle is a linear function of
+    # the error before it
+    mesh = MESHES["box_2x1x1_l1_p2"]()
+    op = SIPG(mesh, meshgen.problem_config1())
+    A = assemble_dense(op)
+    subs = sw.subdomains(op, 2)
+    rng = np.random.default_rng(1)
+    u = rng.standard_normal(op.ndof)
+    b = A @ u
+    assert np.allclose(sw.smooth(A, subs, b, u, 2), u, rtol=0, atol=1e-12)
+    e1, e2 = rng.standard_normal((2, op.ndof))
+    f = lambda e: sw.smooth(A, subs, b, u + e, 1) - u
+    assert np.allclose(f(e1 + 2 * e2), f(e1) + 2 * f(e2), rtol=0, atol=1e-11)
+
+
+@pytest.mark.parametrize("p", [2, 3])
+def test_schwarz_multigrid_is_robust(p):
+    # Sec. IV (the Chebyshev / Schwarz comparison): with N_overlap = 2 and 3 Schwarz cycles per
+    # smoothing call the multigrid-preconditioned FCG solve needs a handful of iterations, far
+    # fewer than with 4 point-Jacobi Chebyshev steps
+    mesh = meshgen.unit_cube(2, p)
+    prob = meshgen.problem_config1()
+    mg_s = Multigrid(mesh, prob, n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    mg_c = Multigrid(mesh, prob, n_cheb=4, smoother="point")
+    b = mg_s.ops[0].rhs()
+    u, its, hist = fcg(mg_s.ops[0].apply, b, mg_s.vcycle, tol=1e-10, max_iter=50)
+    _, itc, _ = fcg(mg_c.ops[0].apply, b, mg_c.vcycle, tol=1e-10, max_iter=50)
+    print("p", p, "Schwarz iterations", its, "Chebyshev iterations", itc, "history", hist)
+    assert its <= 4 and itc >= 3 * its
+    A = assemble_dense(mg_s.ops[0])
+    assert np.allclose(u, np.linalg.solve(A, b), rtol=0, atol=1e-8 * np.abs(u).max())
