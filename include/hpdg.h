@@ -188,8 +188,25 @@ typedef struct {
  *   HPDG_SMOOTH_BLOCK  M = the element-diagonal blocks A_ee (element-block Jacobi; their
  *                      inverses are formed on the device at setup and kept as packed lower
  *                      triangles, N (N + 1) / 2 values per element and level, N = (p+1)^3).
- * The bound of Alg. 5 is then taken for M^-1 A (preconditioned CG with the same M). */
-enum { HPDG_SMOOTH_NONE = 0, HPDG_SMOOTH_POINT = 1, HPDG_SMOOTH_BLOCK = 2 };
+ * The bound of Alg. 5 is then taken for M^-1 A (preconditioned CG with the same M).
+ *   HPDG_SMOOTH_SCHWARZ  the additive Schwarz smoother of Sec. II.D instead of Chebyshev
+ *                      (Alg. schwarz_smoother, Eq. schwarz_weight): n_cheb (n_cheb_coarse below
+ *                      the finest level) cycles x += sum_s R_s^T W_s A_ss^-1 R_s (b - A x) over
+ *                      element-centred subdomains of schwarz_overlap = N_overlap layers of
+ *                      points beyond the centre element (N_overlap >= 1; a level of degree
+ *                      p < N_overlap uses N_overlap = p).  The local
+ *                      problems are solved exactly (their inverses, restricted to the rows of
+ *                      non-zero weight, are formed at setup on the device and kept: m_w m
+ *                      values per subdomain, m = (p + 1 + 2 N_overlap)^3 points inside the
+ *                      mesh, m_w = (p + 3)^3 weighted ones for N_overlap >= 2).  On a side of
+ *                      the centre element that lies on the domain boundary the weight keeps its
+ *                      plateau, so the weights sum to one at every point.  Scope: every smoothed
+ *                      level has one degree, one refinement level, axis-aligned affine elements
+ *                      and 1:1 faces in the elements' own frames, subdomains of at most 8192
+ *                      points (HPDG_ERR_UNSUPPORTED at setup otherwise); FP64 only
+ *                      (HPDG_ERR_UNSUPPORTED for FP32 smoothing, mixed-precision solves and
+ *                      Newton linearisations).  No spectral bound is computed (lambda_max 0). */
+enum { HPDG_SMOOTH_NONE = 0, HPDG_SMOOTH_POINT = 1, HPDG_SMOOTH_BLOCK = 2, HPDG_SMOOTH_SCHWARZ = 3 };
 typedef struct {
   int32_t n_cheb;        /* Chebyshev steps per smoothing call (default 4) */
   int32_t n_eigs;        /* CG steps for the bound (default 15) */
@@ -203,6 +220,7 @@ typedef struct {
                             A x as the mortar kernel and then one fused kernel per element
                             (volume term and face sums, r = b - A x, z = M^-1 r and the update;
                             the same arithmetic); 1 keeps the apply and the scaling step apart */
+  int32_t schwarz_overlap; /* HPDG_SMOOTH_SCHWARZ: N_overlap (the paper's runs use 2) */
 } hpdg_smoother_params;
 
 typedef struct {

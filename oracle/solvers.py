@@ -204,7 +204,8 @@ class Multigrid:
                  schwarz_overlap=2):
         """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi), "block"
         (element-block Jacobi) or "schwarz" (Alg. schwarz_smoother with ``n_cheb`` cycles per
-        call and ``schwarz_overlap`` = N_overlap; no spectral bound); ``jacobi`` selects
+        call and ``schwarz_overlap`` = N_overlap, at most p on a level of degree p; no spectral
+        bound); ``jacobi`` selects
         "point" / "none" when it is not given.
         ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``).
         ``kfield`` / ``cfield``: tabulated coefficients of the finest level (SIPG), carried to
@@ -240,7 +241,9 @@ class Multigrid:
             self.schwarz = []
             for op in self.ops[:-1]:
                 A = assemble_dense(op)
-                self.schwarz.append((A, schwarz.subdomains(op, self.schwarz_overlap)))
+                # a level of degree p < N_overlap holds at most p layers beyond the coincident one
+                nov = min(self.schwarz_overlap, int(op.mesh["elem_p"].max()))
+                self.schwarz.append((A, schwarz.subdomains(op, nov)))
             lam = [0.0] * (len(self.ops) - 1)
         if lam is None:
             lam = []

@@ -23,7 +23,7 @@ SOLVER_FCG, SOLVER_PCG, SOLVER_FGMRES = 0, 1, 2
 COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 COEF_KINDS = {"diffusion": 0, "mass": 1}
 COEF_WHERE = {"element": 0, "node": 1, "analytic": 2}
-SMOOTHERS = {"none": 0, "point": 1, "block": 2}
+SMOOTHERS = {"none": 0, "point": 1, "block": 2, "schwarz": 3}
 TIMING_KINDS = {"apply": 0, "block": 1, "smooth": 2}
 RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4,
            "polynomial_dirichlet": 5, "star": 6}
@@ -75,7 +75,7 @@ class MeshInfo(ctypes.Structure):
 class SmootherParams(ctypes.Structure):
     _fields_ = [("n_cheb", ctypes.c_int32), ("n_eigs", ctypes.c_int32), ("Lambda", ctypes.c_double),
                 ("scaling", ctypes.c_int32), ("seed", ctypes.c_uint64), ("n_cheb_coarse", ctypes.c_int32),
-                ("unfused", ctypes.c_int32)]
+                ("unfused", ctypes.c_int32), ("schwarz_overlap", ctypes.c_int32)]
 
 
 class SolveParams(ctypes.Structure):
@@ -340,7 +340,7 @@ class Server:
     def __init__(self, ctx, max_active=4, hbm_budget_bytes=0, precision=PREC_F64, n_cheb=4, Lambda=20.0,
                  n_eigs=15, smoother="point", seed=0, tol=1e-10, max_iter=1000):
         self.ctx, self.lib = ctx, ctx.lib
-        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[smoother], seed)
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[smoother], seed, 0, 0, 2)
         p = ServerParams(max_active, hbm_budget_bytes, precision, sp, tol, max_iter)
         self.h = ctypes.c_void_p()
         ctx.check(self.lib.hpdg_server_create(ctx.h, ctypes.byref(p), ctypes.byref(self.h)))
@@ -507,13 +507,16 @@ class Mesh:
         self.ctx.check(self.lib.hpdg_apply_noalloc(self.h, level, prec, _ptr(x), _ptr(y), _stream(stream)))
 
     def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
-                       smoother=None, stream=None, n_cheb_coarse=0, fused=True):
-        """``smoother``: "none", "point" or "block" (default: "point" if jacobi else "none").
-        ``n_cheb_coarse``: Chebyshev steps on the levels below the finest (0: ``n_cheb``).
+                       smoother=None, stream=None, n_cheb_coarse=0, fused=True, schwarz_overlap=2):
+        """``smoother``: "none", "point", "block" (Chebyshev) or "schwarz" (additive Schwarz
+        with ``n_cheb`` cycles per call and ``schwarz_overlap`` = N_overlap; FP64 only)
+        (default: "point" if jacobi else "none").
+        ``n_cheb_coarse``: Chebyshev steps (Schwarz cycles) on the levels below the finest (0: ``n_cheb``).
         ``fused``: block smoothing on one-degree levels runs the apply and the block step as one
         kernel (False: separate kernels)."""
         kind = smoother if smoother is not None else ("point" if jacobi else "none")
-        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed, n_cheb_coarse, 0 if fused else 1)
+        sp = SmootherParams(n_cheb, n_eigs, Lambda, SMOOTHERS[kind], seed, n_cheb_coarse, 0 if fused else 1,
+                            schwarz_overlap)
         lam = np.zeros(max(self.n_levels - 1, 1))
         if lambda_max is not None:
             lam[:len(lambda_max)] = lambda_max

@@ -9,7 +9,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libhpdg.so")
-SOURCES = ["basis.cpp", "geom.cpp", "topo.cpp", "setup.cpp", "api.cpp", "kernels.hip", "apply.hip", "fastapply.hip", "newton.hip", "rhs.hip"]
+SOURCES = ["basis.cpp", "geom.cpp", "topo.cpp", "setup.cpp", "schwarz.cpp", "api.cpp", "kernels.hip", "apply.hip", "fastapply.hip", "newton.hip", "rhs.hip", "schwarz.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 

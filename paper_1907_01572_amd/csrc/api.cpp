@@ -28,6 +28,7 @@
 #include "../../include/hpdg.h"
 #include "device.hpp"
 #include "setup.hpp"
+#include "schwarz.hpp"
 
 using namespace hpdg;
 
@@ -105,7 +106,7 @@ struct hpdg_mesh {
   int ncoarse = 0;
   // smoother
   std::vector<double> lam;
-  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0, 0, 0};
+  hpdg_smoother_params sp{4, 15, 20.0, HPDG_SMOOTH_POINT, 0, 0, 0, 2};
   bool smoother_ready = false;
   rocblas_handle blas = nullptr;  // batched Cholesky of the element blocks (setup only)
   // nonlinear source (Newton)
@@ -166,6 +167,20 @@ struct hpdg_mesh {
   // there); uploaded on first use
   Macro* dmacros = nullptr;
   Cell* dcells = nullptr;
+  // additive Schwarz smoother, per smoothed level (FP64): subdomain entries (global dofs), the
+  // rows of W_s A_ss^-1 of the weighted entries, the local corrections and, per dof, the
+  // corrections that sum into it
+  struct SchwarzDev {
+    int n_sub = 0, max_m = 0, overlap = 0;
+    int* gidx = nullptr;
+    long long *goff = nullptr, *woff = nullptr, *moff = nullptr;
+    double* minv = nullptr;
+    double* d = nullptr;
+    long long* ptr = nullptr;
+    int* list = nullptr;
+    long long minv_scalars = 0, entries = 0;
+  };
+  std::vector<SchwarzDev> sw;
 
   template <typename T>
   T* alloc(size_t count) {
@@ -504,9 +519,35 @@ void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, T* slo
   level_apply<T>(M, l, V, x, y, s, false);
 }
 
+// Alg. schwarz_smoother on level l (FP64): n_iter times r = b - A x, x += sum_s R_s^T W_s
+// A_ss^-1 R_s r (zero: x == 0 on entry, so the first residual is b)
+void schwarz_smooth(hpdg_mesh* M, int l, const double* b, double* x, int n_iter, bool zero, hipStream_t s) {
+  const hpdg_mesh::SchwarzDev& w = M->sw.at(size_t(l));
+  if (!w.minv) throw Error(HPDG_ERR_INVALID_ARG, "Schwarz smoother not set up on this level");
+  DevLevel<double>& d = M->lev<double>(l);
+  const long long n = M->H[l].ndof;
+  for (int k = 0; k < n_iter; ++k) {
+    const double* r = b;
+    if (!(zero && k == 0)) {
+      apply_level<double>(M, l, x, d.t, s);
+      launch_axpby<double>(n, 1.0, b, -1.0, d.t, s);  // t = b - A x
+      r = d.t;
+    }
+    launch_schwarz_local(w.n_sub, w.max_m, r, w.gidx, w.goff, w.woff, w.moff, w.minv, w.d, s);
+    launch_schwarz_scatter(n, w.ptr, w.list, w.d, x, s);
+  }
+}
+
 // Alg. 4 with frozen lambda on level l: x <- x + Chebyshev correction (zero: x == 0 on entry)
 template <typename T>
 void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, hipStream_t s) {
+  if (M->sp.scaling == HPDG_SMOOTH_SCHWARZ) {
+    if constexpr (std::is_same<T, double>::value)
+      schwarz_smooth(M, l, b, x, n_iter, zero, s);
+    else
+      throw Error(HPDG_ERR_UNSUPPORTED, "the Schwarz smoother runs in FP64 only");
+    return;
+  }
   DevLevel<T>& d = M->lev<T>(l);
   const long long n = M->H[l].ndof;
   const double lmax = M->lam[l];
@@ -948,6 +989,193 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
   HIPCHK(hipStreamSynchronize(s));
 }
 
+// additive Schwarz smoother of level l (Alg. schwarz_smoother, Eq. schwarz_weight): the
+// subdomains (schwarz_layout), the operator blocks A_ab of every element b and its face
+// neighbours a (SIPG couples no other pairs), gathered column by column from applies to unit
+// vectors on the elements of one colour of a distance-2 colouring of the face graph (no two
+// elements of a colour share a neighbour, so each neighbour's rows come from one of them), each
+// subdomain's A_ss assembled from the blocks on the host, inverted on the device (batched
+// Cholesky + inverse, rocSOLVER, per subdomain size), and the weighted rows kept
+void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
+  hpdg_mesh::SchwarzDev& W = M->sw[size_t(l)];
+  if (W.minv && W.overlap == M->sp.schwarz_overlap) return;
+  const LevelHost& h = M->H[l];
+  SchwarzLayout lay;
+  schwarz_layout(M->mm, h, M->sp.schwarz_overlap, lay);
+  const int E = int(h.cells.size());
+  const int n = lay.n, n3 = n * n * n;
+  int max_m = 0;
+  long long minv_scalars = 0, nrows = 0;
+  for (int c = 0; c < E; ++c) {
+    const int m = int(lay.off[c + 1] - lay.off[c]);
+    max_m = std::max(max_m, m);
+    minv_scalars += (long long)lay.nw[c] * m;
+    nrows += lay.nw[c];
+  }
+  if (size_t(max_m) * sizeof(double) > 64 * 1024)
+    throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomains of more than 8192 points");
+  const double blk_bytes = double(E) * 7.0 * double(n3) * double(n3) * sizeof(double);
+  if (blk_bytes > 16.0 * (1ull << 30)) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz setup: operator blocks above 16 GiB");
+  const std::vector<int>& F = lay.fnb;
+  // distance-2 colouring of the face graph (greedy, element order)
+  std::vector<int> color(E, -1);
+  int ncol = 0;
+  {
+    std::vector<int> seen;
+    for (int e = 0; e < E; ++e) {
+      seen.clear();
+      for (int f = 0; f < 6; ++f) {
+        const int a = F[size_t(e) * 6 + f];
+        if (a < 0) continue;
+        seen.push_back(color[a]);
+        for (int g = 0; g < 6; ++g) {
+          const int b = F[size_t(a) * 6 + g];
+          if (b >= 0 && b != e) seen.push_back(color[b]);
+        }
+      }
+      int c = 0;
+      while (std::find(seen.begin(), seen.end(), c) != seen.end()) ++c;
+      color[e] = c;
+      ncol = std::max(ncol, c + 1);
+    }
+  }
+  // blocks: element b, slot k (0: b itself, 1 + f: the neighbour across face f), column j, row i
+  auto bidx = [&](int b, int k, int j, int i) { return ((size_t(b) * 7 + k) * n3 + j) * n3 + i; };
+  std::vector<double> blk(size_t(E) * 7 * n3 * n3, 0.0);
+  {
+    DevLevel<double>& d = M->lev<double>(l);
+    const LevelView<double> V = M->view<double>(l);
+    std::vector<double> hx(size_t(h.ndof), 0.0), hy(size_t(h.ndof));
+    std::vector<std::vector<int>> members(ncol);
+    for (int e = 0; e < E; ++e) members[color[e]].push_back(e);
+    for (int c = 0; c < ncol; ++c)
+      for (int j = 0; j < n3; ++j) {
+        for (int b : members[c]) hx[size_t(h.einfo[b].off) + j] = 1.0;
+        HIPCHK(hipMemcpyAsync(d.f, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        level_apply<double>(M, l, V, d.f, d.t, s);
+        HIPCHK(hipMemcpyAsync(hy.data(), d.t, hy.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        for (int b : members[c]) {
+          hx[size_t(h.einfo[b].off) + j] = 0.0;
+          for (int k = 0; k < 7; ++k) {
+            const int a = k == 0 ? b : F[size_t(b) * 6 + k - 1];
+            if (a < 0) continue;
+            const double* src = hy.data() + h.einfo[a].off;
+            std::copy(src, src + n3, blk.begin() + bidx(b, k, j, 0));
+          }
+        }
+      }
+  }
+  // device layout of the subdomains
+  std::vector<int> gidx(lay.elem.size());
+  for (size_t k = 0; k < gidx.size(); ++k) gidx[k] = int(h.einfo[lay.elem[k]].off + lay.loc[k]);
+  std::vector<long long> woff(size_t(E) + 1, 0), moff(size_t(E) + 1, 0);
+  std::vector<double> wrow(static_cast<size_t>(nrows));
+  for (int c = 0; c < E; ++c) {
+    const int m = int(lay.off[c + 1] - lay.off[c]);
+    woff[c + 1] = woff[c] + lay.nw[c];
+    moff[c + 1] = moff[c] + (long long)lay.nw[c] * m;
+    for (int r = 0; r < lay.nw[c]; ++r) wrow[size_t(woff[c] + r)] = lay.w[size_t(lay.off[c] + r)];
+  }
+  std::vector<long long> ptr(size_t(h.ndof) + 1, 0);
+  for (int c = 0; c < E; ++c)
+    for (int r = 0; r < lay.nw[c]; ++r) ptr[size_t(gidx[size_t(lay.off[c] + r)]) + 1] += 1;
+  for (long long i = 0; i < h.ndof; ++i) ptr[size_t(i) + 1] += ptr[size_t(i)];
+  std::vector<int> list(static_cast<size_t>(nrows));
+  {
+    std::vector<long long> fill(ptr.begin(), ptr.end() - 1);
+    for (int c = 0; c < E; ++c)
+      for (int r = 0; r < lay.nw[c]; ++r) list[size_t(fill[size_t(gidx[size_t(lay.off[c] + r)])]++)] = int(woff[c] + r);
+  }
+  for (void* q : {(void*)W.gidx, (void*)W.goff, (void*)W.woff, (void*)W.moff, (void*)W.ptr, (void*)W.list,
+                  (void*)W.d, (void*)W.minv})
+    if (q) M->release(q);  // a previous overlap's
+  W = hpdg_mesh::SchwarzDev{};
+  W.n_sub = E;
+  W.max_m = max_m;
+  W.overlap = M->sp.schwarz_overlap;
+  W.minv_scalars = minv_scalars;
+  W.entries = (long long)gidx.size();
+  W.gidx = M->upload_raw(gidx, s);
+  W.goff = M->upload_raw(lay.off, s);
+  W.woff = M->upload_raw(woff, s);
+  W.moff = M->upload_raw(moff, s);
+  W.ptr = M->upload_raw(ptr, s);
+  W.list = M->upload_raw(list, s);
+  W.d = M->alloc<double>(size_t(nrows));
+  W.minv = M->alloc<double>(size_t(minv_scalars));
+  double* dw = M->upload_raw(wrow, s);
+  if (!M->blas) {
+    if (rocblas_create_handle(&M->blas) != rocblas_status_success) throw Error(HPDG_ERR_HIP, "rocblas handle");
+  }
+  rocblas_set_stream(M->blas, s);
+  // per subdomain size: assemble A_ss (column-major) on the host, invert on the device, pack
+  std::map<int, std::vector<int>> groups;
+  for (int c = 0; c < E; ++c) groups[int(lay.off[c + 1] - lay.off[c])].push_back(c);
+  for (const auto& g : groups) {
+    const int m = g.first;
+    const std::vector<int>& subs = g.second;
+    const int cnt = int(subs.size());
+    std::vector<double> A(size_t(cnt) * m * m);
+    for (int b = 0; b < cnt; ++b) {
+      const int c = subs[b];
+      const long long o = lay.off[c];
+      double* Ab = A.data() + size_t(b) * m * m;
+      for (int q = 0; q < m; ++q) {
+        const int eb = lay.elem[size_t(o + q)], jb = lay.loc[size_t(o + q)];
+        for (int p = 0; p < m; ++p) {
+          const int ea = lay.elem[size_t(o + p)];
+          int k = -1;
+          if (ea == eb)
+            k = 0;
+          else
+            for (int f = 0; f < 6; ++f)
+              if (F[size_t(eb) * 6 + f] == ea) k = 1 + f;
+          Ab[size_t(p) + size_t(q) * m] = k < 0 ? 0.0 : blk[bidx(eb, k, jb, lay.loc[size_t(o + p)])];
+        }
+      }
+    }
+    double* dA = M->alloc<double>(A.size());
+    HIPCHK(hipMemcpyAsync(dA, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    std::vector<double*> ptrs(cnt);
+    std::vector<long long> pofs(cnt), gm(cnt), gw(cnt);
+    std::vector<int> gnw(cnt);
+    for (int b = 0; b < cnt; ++b) {
+      ptrs[b] = dA + size_t(b) * m * m;
+      pofs[b] = (long long)b * m * m;
+      gm[b] = moff[subs[b]];
+      gw[b] = woff[subs[b]];
+      gnw[b] = lay.nw[subs[b]];
+    }
+    double** dptrs = M->upload_raw(ptrs, s);
+    rocblas_int* info = M->alloc<rocblas_int>(size_t(cnt));
+    std::vector<rocblas_int> hinfo(cnt);
+    auto check = [&](rocblas_status st, const char* what) {
+      HIPCHK(hipMemcpyAsync(hinfo.data(), info, cnt * sizeof(rocblas_int), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      if (st != rocblas_status_success)
+        throw Error(HPDG_ERR_HIP, std::string("Schwarz ") + what + " failed with rocblas status " + std::to_string(int(st)));
+      for (int b = 0; b < cnt; ++b)
+        if (hinfo[b] != 0)
+          throw Error(HPDG_ERR_BREAKDOWN, std::string("Schwarz ") + what + ": the subdomain of element " +
+                                              std::to_string(subs[b]) + " (level " + std::to_string(l) +
+                                              ") is not positive definite");
+    };
+    check(rocsolver_dpotrf_batched(M->blas, rocblas_fill_lower, m, dptrs, m, info, cnt), "Cholesky");
+    check(rocsolver_dpotri_batched(M->blas, rocblas_fill_lower, m, dptrs, m, info, cnt), "inverse");
+    long long* dpofs = M->upload_raw(pofs, s);
+    long long* dgm = M->upload_raw(gm, s);
+    long long* dgw = M->upload_raw(gw, s);
+    int* dgnw = M->upload_raw(gnw, s);
+    launch_schwarz_pack(m, cnt, dA, dpofs, dgm, dgnw, dgw, dw, W.minv, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* q : {(void*)dA, (void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw})
+      M->release(q);
+  }
+  M->release(dw);
+}
+
 // exact coarse solve: the coarsest operator assembled column by column on the device (one
 // apply per unit vector), symmetrised, factorised (Cholesky) and inverted with rocSOLVER;
 // the explicit inverse is applied as a dense mat-vec in the V-cycle
@@ -1251,6 +1479,7 @@ void rebuild_mesh(hpdg_mesh* M, hipStream_t s) {
   swap(M->gm_m, F->gm_m);
   swap(M->block_scalars, F->block_scalars);
   swap(M->block_full_scalars, F->block_full_scalars);
+  swap(M->sw, F->sw);
   F.reset();  // frees M's previous device state
   if (M->smoother_ready) setup_smoother_impl(M, nullptr, nullptr, s);
 }
@@ -1375,8 +1604,22 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
     mesh->sp.unfused = mesh->sp.unfused ? 1 : 0;
     if (mesh->sp.n_eigs <= 0) mesh->sp.n_eigs = 15;
     if (!(mesh->sp.Lambda > 1.0)) mesh->sp.Lambda = 20.0;
-    if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_BLOCK)
+    if (mesh->sp.scaling < HPDG_SMOOTH_NONE || mesh->sp.scaling > HPDG_SMOOTH_SCHWARZ)
       throw Error(HPDG_ERR_INVALID_ARG, "unknown smoother scaling");
+    if (mesh->sp.scaling == HPDG_SMOOTH_SCHWARZ && mesh->sp.schwarz_overlap < 1)
+      throw Error(HPDG_ERR_INVALID_ARG, "Schwarz overlap must be at least 1");
+  }
+  if (mesh->sp.scaling == HPDG_SMOOTH_SCHWARZ) {
+    if (!mesh->Ainv64) build_coarse(mesh, s);
+    if (mesh->sw.size() < size_t(mesh->nlevels())) mesh->sw.resize(size_t(mesh->nlevels()));
+    for (int l = 0; l + 1 < mesh->nlevels(); ++l) build_schwarz(mesh, l, s);
+    for (int l = 0; l + 1 < mesh->nlevels(); ++l) {
+      mesh->lam[l] = 0.0;  // no spectral bound
+      if (lambda_max) lambda_max[l] = 0.0;
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    mesh->smoother_ready = true;
+    return;
   }
   // the exact coarse solve is part of the solver's setup: a mesh used only for applies never
   // forms the dense inverse (whose size limits the coarsest level)
@@ -1406,6 +1649,8 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
 bool krylov_solve(hpdg_mesh* mesh, const hpdg_solve_params& params, const double* b_dev, double* u_dev, int& iters,
                   double& rel, hipStream_t s) {
   const bool mixed = params.precision == HPDG_PREC_MIXED || params.precision == HPDG_PREC_MIXED_BF16;
+  if (mixed && mesh->sp.scaling == HPDG_SMOOTH_SCHWARZ)
+    throw Error(HPDG_ERR_UNSUPPORTED, "the Schwarz smoother runs in FP64 only (HPDG_PREC_F64)");
   mesh->bf16_blocks = params.precision == HPDG_PREC_MIXED_BF16;
   iters = 0;
   rel = 0;
@@ -1622,6 +1867,8 @@ void linearize(hpdg_mesh* M, const double* u, hipStream_t s) {
   if (!M->smoother_ready) throw Error(HPDG_ERR_INVALID_ARG, "call hpdg_setup_smoother first");
   if (M->sp.scaling == HPDG_SMOOTH_BLOCK)
     throw Error(HPDG_ERR_UNSUPPORTED, "block-Jacobi smoothing is not rebuilt for Newton linearisations");
+  if (M->sp.scaling == HPDG_SMOOTH_SCHWARZ)
+    throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing is not rebuilt for Newton linearisations");
   const int L = M->nlevels();
   clear_bad(M, s);
   const double* ul = u;

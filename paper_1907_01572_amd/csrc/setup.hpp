@@ -147,6 +147,26 @@ struct EstTables {
 void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscParams& dp, const LevelHost& L,
                       int kind, const std::vector<double>& P, EstTables& out);
 
+// Additive Schwarz subdomains of a level (Sec. II.D, Alg. schwarz_smoother, Eq. schwarz_weight),
+// one per element e_c, for levels of axis-aligned affine elements of one degree and one
+// refinement level whose faces all meet 1:1 (HPDG_ERR_UNSUPPORTED otherwise).  A point of a
+// neighbour lying on side o (o_d in {-1, 0, 1}) of e_c has the extended coordinate
+// xi_ext = xi + 2 o; the subdomain holds the points with |xi_ext| <= 1 + delta on every axis,
+// delta = 1 + xi_(N_overlap - 1) (N_overlap at most p), each weighted by the product over the axes of
+// w(xi) = (phi((xi + 1) / delta) - phi((xi - 1) / delta)) / 2; on a side of e_c without a
+// neighbour (domain boundary) that side's phi term is replaced by its limit.  Entries of a
+// subdomain: e_c's points, then the neighbours' by element and local index, and then stably
+// reordered so that the entries with a non-zero weight come first.
+struct SchwarzLayout {
+  std::vector<long long> off;     // per subdomain: first entry (E + 1)
+  std::vector<int> nw;            // per subdomain: entries with a non-zero weight
+  std::vector<int> elem, loc;     // element and local dof index of each entry
+  std::vector<double> w;          // weight of each entry
+  std::vector<int> fnb;           // per element and face (6 per element): face neighbour or -1
+  int n = 0;                      // LGL nodes per axis
+};
+void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out);
+
 // one-side mortar map: rows of the 1-D matrices along the own face axes
 struct SideMap {
   int swap, flipA, flipB, halfA, halfB;  // half: 0 full, 1 lower, 2 upper

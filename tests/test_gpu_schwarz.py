@@ -1,0 +1,131 @@
+"""GPU parity of the additive Schwarz smoother (Sec. II.D, Alg. schwarz_smoother, Eq.
+schwarz_weight) against the oracle's: smoothing cycles and V-cycles on uniform axis-aligned
+meshes, the multigrid-preconditioned FCG solve, and the refusals outside the smoother's scope."""
+import numpy as np
+import pytest
+
+import meshgen
+from oracle import schwarz as sw
+from oracle.operator import SIPG, assemble_dense
+from oracle.solvers import Multigrid, fcg
+from tests.gpu_common import dof_perm, rel
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+hp = pytest.importorskip("paper_1907_01572_amd")
+
+# both sides solve the local problems exactly in FP64 (Cholesky of A_ss, condition numbers up to
+# about 1e5 here): the corrections agree to about 1e-16 times that; the norm-wise bound leaves
+# two orders of margin
+TOL_SCHWARZ = 1e-10
+
+MESHES = {
+    "cube_l2_p3": lambda: meshgen.unit_cube(2, 3),
+    "box_2x1x1_l1_p2": lambda: meshgen.box_grid((2, 1, 1), 1, 2),
+    "box_lopsided_l1_p3": lambda: meshgen.box_grid((1, 1, 1), 1, 3, lo=(-0.3, 0.0, 0.1), hi=(1.0, 0.5, 2.0)),
+    "cube_l1_p6": lambda: meshgen.unit_cube(1, 6),
+}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    c = hp.Context(0)
+    yield c
+    c.close()
+
+
+def dev(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float64, device="cuda")
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+@pytest.mark.parametrize("name,n_overlap", [("cube_l2_p3", 1), ("cube_l2_p3", 2), ("box_2x1x1_l1_p2", 1),
+                                            ("box_2x1x1_l1_p2", 2), ("box_lopsided_l1_p3", 3),
+                                            ("cube_l1_p6", 2)])
+def test_schwarz_smooth_and_vcycle_parity(ctx, name, n_overlap):
+    m = MESHES[name]()
+    prob = meshgen.problem_config1()
+    print("case", name, "N_overlap", n_overlap, flush=True)
+    mg = Multigrid(m, prob, n_cheb=3, smoother="schwarz", schwarz_overlap=n_overlap)
+    op = mg.ops[0]
+    M = ctx.upload(m)
+    lam = M.setup_smoother(n_cheb=3, smoother="schwarz", schwarz_overlap=n_overlap)
+    assert np.all(lam == 0.0)
+    perm = dof_perm(M.level_cells(0), m)
+    rng = np.random.default_rng(3)
+    b, x0, r = rng.standard_normal((3, op.ndof))
+    A, subs = mg.schwarz[0]
+    xs = sw.smooth(A, subs, b, x0, 2)
+    xd = dev(x0[perm])
+    M.smooth(dev(b[perm]), xd, level=0, n_iter=2)
+    e1 = rel(host(xd), xs[perm])
+    z = torch.zeros(op.ndof, dtype=torch.float64, device="cuda")
+    M.vcycle(dev(r[perm]), z)
+    e2 = rel(host(z), mg.vcycle(r)[perm])
+    print(name, "levels", M.n_levels, "smooth", e1, "vcycle", e2, flush=True)
+    assert e1 <= TOL_SCHWARZ and e2 <= TOL_SCHWARZ
+    M.free()
+
+
+def test_schwarz_fcg_follows_the_oracle(ctx):
+    # N_overlap = 2, three cycles per smoothing call: the library's FCG takes the oracle's
+    # iterations and reaches its solution; point-Jacobi Chebyshev needs several times as many
+    m = MESHES["cube_l2_p3"]()
+    prob = meshgen.problem_config1()
+    mg = Multigrid(m, prob, n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    op = mg.ops[0]
+    Fo = op.rhs()
+    uo, ko, hist = fcg(op.apply, Fo, mg.vcycle, tol=1e-10, max_iter=50)
+    M = ctx.upload(m)
+    perm = dof_perm(M.level_cells(0), m)
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    M.assemble_rhs(prob, F)
+    assert rel(host(F), Fo[perm]) <= 1e-13
+    M.setup_smoother(n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    u = torch.zeros_like(F)
+    st = M.solve(F, u, tol=1e-10, max_iter=50)
+    M.setup_smoother(n_cheb=4, smoother="point")
+    u2 = torch.zeros_like(F)
+    st2 = M.solve(F, u2, tol=1e-10, max_iter=200)
+    err = rel(host(u), uo[perm])
+    print("Schwarz", st, "oracle iterations", ko, "solution err", err, "point Chebyshev", st2, flush=True)
+    assert st["iterations"] == ko and err <= 1e-9
+    assert st2["iterations"] >= 3 * st["iterations"]
+    M.free()
+
+
+def test_schwarz_refusals(ctx):
+    # 2:1 faces and curved elements are outside the smoother's scope; the overlap is at least
+    # one (a larger one than the degree is clamped to it); FP32 smoothing and mixed-precision
+    # solves are refused
+    for mesh in (meshgen.box_grid((2, 1, 1), 1, 3, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+                 meshgen.cubed_sphere_shell(level=1, p=2, r_out=1e3)):
+        M = ctx.upload(mesh)
+        with pytest.raises(hp.HpdgError) as ei:
+            M.setup_smoother(smoother="schwarz")
+        assert ei.value.code == hp.ERR_UNSUPPORTED
+        M.free()
+    M = ctx.upload(meshgen.unit_cube(1, 3), build_f32=True)
+    with pytest.raises(hp.HpdgError) as ei:
+        M.setup_smoother(smoother="schwarz", schwarz_overlap=0)
+    assert ei.value.code == hp.ERR_INVALID_ARG
+    M.setup_smoother(smoother="schwarz", schwarz_overlap=9)
+    F = torch.ones(M.n_dof[0], dtype=torch.float64, device="cuda")
+    u = torch.zeros_like(F)
+    with pytest.raises(hp.HpdgError) as ei:
+        M.solve(F, u, precision=hp.PREC_MIXED)
+    assert ei.value.code == hp.ERR_UNSUPPORTED
+    with pytest.raises(hp.HpdgError) as ei:
+        M.smooth(F.float(), u.float(), level=0, n_iter=1)
+    assert ei.value.code == hp.ERR_UNSUPPORTED
+    st = M.solve(F, u, tol=1e-10, max_iter=50)
+    print("after the refusals", st, flush=True)
+    assert st["rel_residual"] <= 1e-10
+    M.free()
