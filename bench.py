@@ -13,10 +13,13 @@ apply sweep and the oracle's CPU rate.
 
 Other workloads (``--workload``): "shell" alone, "newton" (the 13-macro cube + compactified
 exterior refined around three seeded punctures, p = 6, 12,739,363 DOF, Newton-Krylov to
-|R| <= 1e-10 |R_0|), "serving" (the 512-request stream) and "sweep" (the out-of-cache apply
-rates of the uniform box, written to profiles/).  Printed: one JSON line.
+|R| <= 1e-10 |R_0|), "serving" (the 512-request stream), "sweep" (the out-of-cache apply
+rates of the uniform box, written to profiles/), "amr" (the hp-adaptive loop) and "schwarz"
+(MG-FCG with the additive Schwarz smoother against point-Jacobi Chebyshev on a uniform box).
+Printed: one JSON line.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload hp|shell|newton|serving|sweep]
+    python bench.py [--gpus 1] [--steps K] [--warmup W]
+                    [--workload hp|shell|newton|serving|sweep|amr|schwarz]
 """
 import argparse
 import json
@@ -388,7 +391,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="hp", choices=["hp", "shell", "newton", "serving", "sweep", "amr"])
+    ap.add_argument("--workload", default="hp", choices=["hp", "shell", "newton", "serving", "sweep", "amr", "schwarz"])
+    ap.add_argument("--schwarz-level", type=int, default=3, help="schwarz: refinement level of the unit cube")
+    ap.add_argument("--schwarz-p", type=int, default=3, help="schwarz: degree")
+    ap.add_argument("--schwarz-overlap", type=int, default=2, help="schwarz: N_overlap")
     ap.add_argument("--amr-steps", type=int, default=6, help="amr: adaptation steps")
     ap.add_argument("--amr-fraction", type=float, default=0.2, help="amr: fraction of elements marked")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
@@ -462,6 +468,8 @@ def main():
         return run_sweep(args, meshgen, hp)
     if args.workload == "amr":
         return run_amr(args, meshgen, hp)
+    if args.workload == "schwarz":
+        return run_schwarz(args, meshgen, hp)
     W = make_workload(args, meshgen, hp)
     ctx = hp.Context(0)
     if args.profile_estimate:
@@ -818,6 +826,65 @@ def run_amr(args, meshgen, hp):
                                   % (100 * args.amr_fraction), "name": "amr"},
            "amr_steps": steps}
     print(json.dumps(out))
+    ctx.close()
+
+
+def run_schwarz(args, meshgen, hp):
+    """Multigrid-preconditioned FCG with the additive Schwarz smoother (N_overlap 2, three cycles
+    per smoothing call, the settings of the paper's smoother comparison) against point-Jacobi
+    Chebyshev on the unit box of affine cells at one level and degree (the smoother's scope):
+    setup time, iterations and solve time of each, and the roofline of the Schwarz local-solve
+    kernel (HIP events around every launch during one extra solve)."""
+    import torch
+
+    dev = torch.device("cuda:0")
+    prob = meshgen.problem_config1()
+    mesh = meshgen.unit_cube(args.schwarz_level, args.schwarz_p)
+    ctx = hp.Context(0)
+    M = ctx.upload(mesh)
+    N = M.n_dof[0]
+    F = torch.zeros(N, dtype=torch.float64, device=dev)
+    M.assemble_rhs(prob, F)
+    out = {}
+    for name, kw in (("schwarz", dict(n_cheb=3, smoother="schwarz", schwarz_overlap=args.schwarz_overlap)),
+                     ("chebyshev_point", dict(n_cheb=4, smoother="point"))):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        M.setup_smoother(**kw)
+        torch.cuda.synchronize()
+        setup_s = time.perf_counter() - t0
+        times, st = [], None
+        for k in range(args.warmup + args.steps):
+            u = torch.zeros_like(F)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = M.solve(F, u, tol=1e-10, max_iter=args.max_iter)
+            torch.cuda.synchronize()
+            if k >= args.warmup:
+                times.append(time.perf_counter() - t0)
+        out[name] = {"setup_s": round(setup_s, 3), "iterations": st["iterations"],
+                     "rel_residual": st["rel_residual"], "solve_ms": round(1e3 * float(np.median(times)), 3)}
+        print("schwarz workload: %s setup %.2f s, %d iterations, %.2f ms per solve" %
+              (name, setup_s, st["iterations"], out[name]["solve_ms"]), file=sys.stderr, flush=True)
+        if name == "schwarz":
+            M.timing_enable(1)
+            u = torch.zeros_like(F)
+            M.solve(F, u, tol=1e-10, max_iter=args.max_iter)
+            ms, n, b = M.kernel_timing("schwarz", 0)
+            M.timing_enable(0)
+            gbs = b / n / (ms / n * 1e-3) / 1e9
+            out[name]["roofline"] = {"kernel": "schwarz_local_kernel (level 0)", "bound": "hbm",
+                                     "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                     "frac": round(gbs / HBM_PEAK_GBS, 4), "launches": n,
+                                     "avg_us": round(1e3 * ms / n, 2), "alg_bytes_per_launch": b / n}
+    M.free()
+    res = {"workload": "schwarz",
+           "config": {"mesh": "unit cube, %d^3 affine cells, p = %d" % (2 ** args.schwarz_level, args.schwarz_p),
+                      "dof": N, "problem": "-lap u = 3 pi^2 sin sin sin, u = 0 on the boundary",
+                      "tol": 1e-10, "schwarz_overlap": args.schwarz_overlap, "schwarz_cycles": 3,
+                      "chebyshev_steps": 4, "steps": args.steps, "warmup": args.warmup},
+           **out}
+    print(json.dumps(res))
     ctx.close()
 
 

@@ -202,7 +202,7 @@ typedef struct {
  *                      the centre element that lies on the domain boundary the weight keeps its
  *                      plateau, so the weights sum to one at every point.  Scope: every smoothed
  *                      level has one degree, one refinement level, axis-aligned affine elements
- *                      and 1:1 faces in the elements' own frames, subdomains of at most 8192
+ *                      and 1:1 faces in the elements' own frames, subdomains of at most 8190
  *                      points (HPDG_ERR_UNSUPPORTED at setup otherwise); FP64 only
  *                      (HPDG_ERR_UNSUPPORTED for FP32 smoothing, mixed-precision solves and
  *                      Newton linearisations).  No spectral bound is computed (lambda_max 0). */
@@ -541,8 +541,9 @@ int hpdg_server_destroy(hpdg_server* server);
 /* Kernel timing for measurement.  While enabled (every = k > 0), every k-th operator
  * application of each (kind, level, precision) (HPDG_TIMING_APPLY: hpdg_apply and the
  * applies inside hpdg_smooth, hpdg_vcycle and hpdg_solve), every k-th block-Jacobi
- * Chebyshev step (HPDG_TIMING_BLOCK) and every k-th fused apply + Jacobi-scaled Chebyshev step
- * (HPDG_TIMING_SMOOTH, see hpdg_smoother_params.unfused) is bracketed by two HIP events on
+ * Chebyshev step (HPDG_TIMING_BLOCK), every k-th fused apply + Jacobi-scaled Chebyshev step
+ * (HPDG_TIMING_SMOOTH, see hpdg_smoother_params.unfused) and every k-th launch of the Schwarz
+ * smoother's local solves (HPDG_TIMING_SCHWARZ) is bracketed by two HIP events on
  * its stream, and the algorithmic bytes of the launch are recorded (every = 0 disables):
  *   apply: 2 s N (x read, y written) + s (volume + mortar metric scalars) + record bytes;
  *   block step: s sum_e N_e (N_e + 1) / 2 (packed inverse blocks, N_e = n_e^3) + s N per
@@ -550,12 +551,16 @@ int hpdg_server_destroy(hpdg_server* server);
  *   fused step (the mortar kernel and the fused element kernels; the face-trace launch before
  *   the first step is not timed): the
  *   apply's bytes without the y write, plus the packed blocks (point Jacobi: s N, the inverse
- *   diagonal) and s N per vector (b, p, x written, p read after the first step).
+ *   diagonal) and s N per vector (b, p, x written, p read after the first step);
+ *   Schwarz local solves: 8 sum_s m_w,s m_s (the stored rows) + 12 sum_s m_s (gathered
+ *   residual and its indices) + 8 sum_s m_w,s (corrections written) + 24 per subdomain
+ *   (its offsets).
  * (s = 8 for HPDG_F64, 4 for HPDG_F32; N = level DOF.)  hpdg_kernel_timing() waits for
  * the recorded events and returns, for one (kind, level, prec), the summed event time in
  * ms, the number of launches and the summed algorithmic bytes since the previous read of
  * that entry, then resets the entry.  Recording costs two event records per launch. */
-enum { HPDG_TIMING_APPLY = 0, HPDG_TIMING_BLOCK = 1, HPDG_TIMING_SMOOTH = 2, HPDG_TIMING_KINDS = 3 };
+enum { HPDG_TIMING_APPLY = 0, HPDG_TIMING_BLOCK = 1, HPDG_TIMING_SMOOTH = 2, HPDG_TIMING_SCHWARZ = 3,
+       HPDG_TIMING_KINDS = 4 };
 int hpdg_timing_enable(hpdg_mesh* mesh, int every);
 int hpdg_kernel_timing(hpdg_mesh* mesh, int kind, int level, int prec, double* total_ms, int64_t* launches,
                        double* alg_bytes);

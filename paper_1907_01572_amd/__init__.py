@@ -24,7 +24,7 @@ COEF_CONSTANT, COEF_RADIAL_STEP = 0, 1
 COEF_KINDS = {"diffusion": 0, "mass": 1}
 COEF_WHERE = {"element": 0, "node": 1, "analytic": 2}
 SMOOTHERS = {"none": 0, "point": 1, "block": 2, "schwarz": 3}
-TIMING_KINDS = {"apply": 0, "block": 1, "smooth": 2}
+TIMING_KINDS = {"apply": 0, "block": 1, "smooth": 2, "schwarz": 3}
 RHS_IDS = {"sinsinsin": 0, "shell_harmonic": 1, "radial_step": 2, "polynomial": 3, "gaussians": 4,
            "polynomial_dirichlet": 5, "star": 6}
 NL_IDS = {"puncture": 0, "nl_quadratic": 1, "star": 2}

@@ -171,7 +171,7 @@ struct hpdg_mesh {
   // rows of W_s A_ss^-1 of the weighted entries, the local corrections and, per dof, the
   // corrections that sum into it
   struct SchwarzDev {
-    int n_sub = 0, max_m = 0, overlap = 0;
+    int n_sub = 0, max_m = 0, max_nw = 0, overlap = 0;
     int* gidx = nullptr;
     long long *goff = nullptr, *woff = nullptr, *moff = nullptr;
     double* minv = nullptr;
@@ -179,6 +179,7 @@ struct hpdg_mesh {
     long long* ptr = nullptr;
     int* list = nullptr;
     long long minv_scalars = 0, entries = 0;
+    double alg_bytes = 0;  // of one launch of the local solves
   };
   std::vector<SchwarzDev> sw;
 
@@ -533,7 +534,9 @@ void schwarz_smooth(hpdg_mesh* M, int l, const double* b, double* x, int n_iter,
       launch_axpby<double>(n, 1.0, b, -1.0, d.t, s);  // t = b - A x
       r = d.t;
     }
-    launch_schwarz_local(w.n_sub, w.max_m, r, w.gidx, w.goff, w.woff, w.moff, w.minv, w.d, s);
+    timed(M, HPDG_TIMING_SCHWARZ, l, HPDG_F64, w.alg_bytes, s, [&] {
+      launch_schwarz_local(w.n_sub, w.max_m, w.max_nw, r, w.gidx, w.goff, w.woff, w.moff, w.minv, w.d, s);
+    });
     launch_schwarz_scatter(n, w.ptr, w.list, w.d, x, s);
   }
 }
@@ -1004,16 +1007,18 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   schwarz_layout(M->mm, h, M->sp.schwarz_overlap, lay);
   const int E = int(h.cells.size());
   const int n = lay.n, n3 = n * n * n;
-  int max_m = 0;
-  long long minv_scalars = 0, nrows = 0;
+  int max_m = 0, max_nw = 0;
+  long long minv_scalars = 0, alg_scalars = 0, nrows = 0;
   for (int c = 0; c < E; ++c) {
     const int m = int(lay.off[c + 1] - lay.off[c]);
     max_m = std::max(max_m, m);
-    minv_scalars += (long long)lay.nw[c] * m;
+    max_nw = std::max(max_nw, lay.nw[c]);
+    minv_scalars += (long long)lay.nw[c] * (m + (m & 1));  // rows padded to an even stride
+    alg_scalars += (long long)lay.nw[c] * m;
     nrows += lay.nw[c];
   }
-  if (size_t(max_m) * sizeof(double) > 64 * 1024)
-    throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomains of more than 8192 points");
+  if (size_t(max_m + (max_m & 1)) * sizeof(double) > 64 * 1024)
+    throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomains of more than 8190 points");
   const double blk_bytes = double(E) * 7.0 * double(n3) * double(n3) * sizeof(double);
   if (blk_bytes > 16.0 * (1ull << 30)) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz setup: operator blocks above 16 GiB");
   const std::vector<int>& F = lay.fnb;
@@ -1074,7 +1079,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   for (int c = 0; c < E; ++c) {
     const int m = int(lay.off[c + 1] - lay.off[c]);
     woff[c + 1] = woff[c] + lay.nw[c];
-    moff[c + 1] = moff[c] + (long long)lay.nw[c] * m;
+    moff[c + 1] = moff[c] + (long long)lay.nw[c] * (m + (m & 1));
     for (int r = 0; r < lay.nw[c]; ++r) wrow[size_t(woff[c] + r)] = lay.w[size_t(lay.off[c] + r)];
   }
   std::vector<long long> ptr(size_t(h.ndof) + 1, 0);
@@ -1093,9 +1098,11 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   W = hpdg_mesh::SchwarzDev{};
   W.n_sub = E;
   W.max_m = max_m;
+  W.max_nw = max_nw;
   W.overlap = M->sp.schwarz_overlap;
   W.minv_scalars = minv_scalars;
   W.entries = (long long)gidx.size();
+  W.alg_bytes = 8.0 * double(alg_scalars) + 12.0 * double(W.entries) + 8.0 * double(nrows) + 24.0 * double(E);
   W.gidx = M->upload_raw(gidx, s);
   W.goff = M->upload_raw(lay.off, s);
   W.woff = M->upload_raw(woff, s);

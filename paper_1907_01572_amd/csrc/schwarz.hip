@@ -11,63 +11,91 @@ namespace hpdg {
 
 namespace {
 
-constexpr int kSwBS = 256;  // four waves per subdomain
+constexpr int kSwBS = 512;   // eight waves per workgroup
+constexpr int kSwRows = 4;   // rows in flight per wave
 
 // inverse of subdomain s (lower triangle, column-major m x m at P + pofs[b]) -> rows r < nw of
-// W_s A_ss^-1, row-major at minv + moff[b] (both triangles)
-__global__ void __launch_bounds__(kSwBS) schwarz_pack_kernel(int m, int b0, const double* __restrict__ P,
-                                                           const long long* __restrict__ pofs,
-                                                           const long long* __restrict__ moff,
-                                                           const int* __restrict__ nw,
-                                                           const long long* __restrict__ wofs,
-                                                           const double* __restrict__ w,
-                                                           double* __restrict__ minv) {
+// W_s A_ss^-1, row-major with the even row stride mp = m + (m & 1) at minv + moff[b] (both
+// triangles; the pad column zero)
+__global__ void __launch_bounds__(256) schwarz_pack_kernel(int m, int b0, const double* __restrict__ P,
+                                                         const long long* __restrict__ pofs,
+                                                         const long long* __restrict__ moff,
+                                                         const int* __restrict__ nw,
+                                                         const long long* __restrict__ wofs,
+                                                         const double* __restrict__ w,
+                                                         double* __restrict__ minv) {
   const int b = b0 + blockIdx.y;
+  const int mp = m + (m & 1);
   const double* Pb = P + pofs[b];
-  const long long total = (long long)nw[b] * m;
+  const long long total = (long long)nw[b] * mp;
   double* out = minv + moff[b];
   const double* wb = w + wofs[b];
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
-    const int r = int(t / m), k = int(t - (long long)r * m);
-    const double v = r >= k ? Pb[r + (long long)k * m] : Pb[k + (long long)r * m];
+    const int r = int(t / mp), k = int(t - (long long)r * mp);
+    double v = 0.0;
+    if (k < m) v = r >= k ? Pb[r + (long long)k * m] : Pb[k + (long long)r * m];
     out[t] = wb[r] * v;
   }
 }
 
-// one workgroup per subdomain: r_s = R_s r into LDS, then d_s = W_s A_ss^-1 r_s, one wavefront
-// per row (lanes along the row: coalesced reads of the stored rows), reduced across the wave
+// workgroup (s, c): rows [c rpc, (c + 1) rpc) of subdomain s.  r_s = R_s r is staged in LDS
+// (zero-padded to the even stride), then each wave takes kSwRows rows at a time, its lanes
+// reading the rows in 16-byte pairs (coalesced), and reduces them across the wave
 __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const double* __restrict__ r,
                                                             const int* __restrict__ gidx,
                                                             const long long* __restrict__ goff,
                                                             const long long* __restrict__ woff,
                                                             const long long* __restrict__ moff,
                                                             const double* __restrict__ minv,
-                                                            double* __restrict__ d) {
-  extern __shared__ double rs[];
+                                                            double* __restrict__ d, int rpc) {
+  extern __shared__ double2 lds2[];  // 16-byte aligned
+  double* rs = reinterpret_cast<double*>(lds2);
   const int s = blockIdx.x;
   const long long g0 = goff[s];
   const int m = int(goff[s + 1] - g0);
+  const int mp = m + (m & 1);
   const long long w0 = woff[s];
   const int nw = int(woff[s + 1] - w0);
-  for (int k = threadIdx.x; k < m; k += kSwBS) rs[k] = r[gidx[g0 + k]];
+  const int row_begin = blockIdx.y * rpc;
+  const int row_end = min(nw, row_begin + rpc);
+  if (row_begin >= row_end) return;  // the whole workgroup: no barrier is skipped by part of it
+  for (int k = threadIdx.x; k < mp; k += kSwBS) rs[k] = k < m ? r[gidx[g0 + k]] : 0.0;
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const double2* rs2 = lds2;
   const double* M = minv + moff[s];
-  for (int row = wave; row < nw; row += kSwBS / 64) {
-    const double* Mr = M + (long long)row * m;
-    double acc = 0.0;
-    for (int k = lane; k < m; k += 64) acc += Mr[k] * rs[k];
-    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
-    if (lane == 0) d[w0 + row] = acc;
+  const int half = mp >> 1;
+  for (int row = row_begin + wave * kSwRows; row < row_end; row += (kSwBS / 64) * kSwRows) {
+    const double2* Mr[kSwRows];
+#pragma unroll
+    for (int q = 0; q < kSwRows; ++q)  // rows past the end read the last row; their sums are dropped
+      Mr[q] = reinterpret_cast<const double2*>(M + (long long)min(row + q, row_end - 1) * mp);
+    double acc[kSwRows];
+#pragma unroll
+    for (int q = 0; q < kSwRows; ++q) acc[q] = 0.0;
+    for (int k = lane; k < half; k += 64) {
+      const double2 x = rs2[k];
+#pragma unroll
+      for (int q = 0; q < kSwRows; ++q) {
+        const double2 a = Mr[q][k];
+        acc[q] += a.x * x.x + a.y * x.y;
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < kSwRows; ++q)
+      for (int off = 32; off > 0; off >>= 1) acc[q] += __shfl_xor(acc[q], off, 64);
+#pragma unroll
+    for (int q = 0; q < kSwRows; ++q)
+      if (lane == q && row + q < row_end) d[w0 + row + q] = acc[q];
   }
 }
 
 // x_i += sum over the subdomains holding dof i (in subdomain order) of their weighted corrections
-__global__ void __launch_bounds__(kSwBS) schwarz_scatter_kernel(long long n, const long long* __restrict__ ptr,
-                                                              const int* __restrict__ list,
-                                                              const double* __restrict__ d,
-                                                              double* __restrict__ x) {
+__global__ void __launch_bounds__(256) schwarz_scatter_kernel(long long n, const long long* __restrict__ ptr,
+                                                            const int* __restrict__ list,
+                                                            const double* __restrict__ d,
+                                                            double* __restrict__ x) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= n) return;
   double acc = 0.0;
@@ -80,23 +108,31 @@ __global__ void __launch_bounds__(kSwBS) schwarz_scatter_kernel(long long n, con
 void launch_schwarz_pack(int m, int count, const double* P, const long long* pofs, const long long* moff,
                          const int* nw, const long long* wofs, const double* w, double* minv, hipStream_t s) {
   for (int b0 = 0; b0 < count; b0 += 32768)  // grid y stays below its 65535 limit
-    hipLaunchKernelGGL(schwarz_pack_kernel, dim3(64, unsigned(std::min(32768, count - b0))), dim3(kSwBS), 0, s, m,
+    hipLaunchKernelGGL(schwarz_pack_kernel, dim3(64, unsigned(std::min(32768, count - b0))), dim3(256), 0, s, m,
                        b0, P, pofs, moff, nw, wofs, w, minv);
 }
 
-void launch_schwarz_local(int n_sub, int max_m, const double* r, const int* gidx, const long long* goff,
+void launch_schwarz_local(int n_sub, int max_m, int max_nw, const double* r, const int* gidx, const long long* goff,
                           const long long* woff, const long long* moff, const double* minv, double* d,
                           hipStream_t s) {
-  if (n_sub <= 0) return;
-  hipLaunchKernelGGL(schwarz_local_kernel, dim3(n_sub), dim3(kSwBS), size_t(max_m) * sizeof(double), s, r, gidx,
-                     goff, woff, moff, minv, d);
+  if (n_sub <= 0 || max_nw <= 0) return;
+  // split the rows of each subdomain over several workgroups when there are few subdomains:
+  // about 2048 workgroups (8 per CU), chunks of whole wave passes
+  const int pass = (kSwBS / 64) * kSwRows;
+  int chunks = std::max(1, std::min((2048 + n_sub - 1) / n_sub, (max_nw + pass - 1) / pass));
+  chunks = std::min(chunks, 65535);
+  int rpc = (max_nw + chunks - 1) / chunks;
+  rpc = (rpc + pass - 1) / pass * pass;
+  chunks = (max_nw + rpc - 1) / rpc;
+  const size_t lds = size_t(max_m + (max_m & 1)) * sizeof(double);
+  hipLaunchKernelGGL(schwarz_local_kernel, dim3(unsigned(n_sub), unsigned(chunks)), dim3(kSwBS), lds, s, r, gidx,
+                     goff, woff, moff, minv, d, rpc);
 }
 
 void launch_schwarz_scatter(long long n, const long long* ptr, const int* list, const double* d, double* x,
                             hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(schwarz_scatter_kernel, dim3(unsigned((n + kSwBS - 1) / kSwBS)), dim3(kSwBS), 0, s, n, ptr,
-                     list, d, x);
+  hipLaunchKernelGGL(schwarz_scatter_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, ptr, list, d, x);
 }
 
 }  // namespace hpdg
