@@ -1124,24 +1124,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     const std::vector<int>& subs = g.second;
     const int cnt = int(subs.size());
     std::vector<double> A(size_t(cnt) * m * m);
-    for (int b = 0; b < cnt; ++b) {
-      const int c = subs[b];
-      const long long o = lay.off[c];
-      double* Ab = A.data() + size_t(b) * m * m;
-      for (int q = 0; q < m; ++q) {
-        const int eb = lay.elem[size_t(o + q)], jb = lay.loc[size_t(o + q)];
-        for (int p = 0; p < m; ++p) {
-          const int ea = lay.elem[size_t(o + p)];
-          int k = -1;
-          if (ea == eb)
-            k = 0;
-          else
-            for (int f = 0; f < 6; ++f)
-              if (F[size_t(eb) * 6 + f] == ea) k = 1 + f;
-          Ab[size_t(p) + size_t(q) * m] = k < 0 ? 0.0 : blk[bidx(eb, k, jb, lay.loc[size_t(o + p)])];
-        }
-      }
-    }
+    schwarz_assemble(lay, blk, subs, m, A.data());
     double* dA = M->alloc<double>(A.size());
     HIPCHK(hipMemcpyAsync(dA, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s));
     std::vector<double*> ptrs(cnt);

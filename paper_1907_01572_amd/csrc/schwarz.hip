@@ -12,7 +12,8 @@ namespace hpdg {
 namespace {
 
 constexpr int kSwBS = 512;   // eight waves per workgroup
-constexpr int kSwRows = 4;   // rows in flight per wave
+constexpr int kSwRows = 8;   // rows in flight per wave
+typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // inverse of subdomain s (lower triangle, column-major m x m at P + pofs[b]) -> rows r < nw of
 // W_s A_ss^-1, row-major with the even row stride mp = m + (m & 1) at minv + moff[b] (both
@@ -67,18 +68,18 @@ __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const double* __re
   const double* M = minv + moff[s];
   const int half = mp >> 1;
   for (int row = row_begin + wave * kSwRows; row < row_end; row += (kSwBS / 64) * kSwRows) {
-    const double2* Mr[kSwRows];
+    const dbl2* Mr[kSwRows];
 #pragma unroll
     for (int q = 0; q < kSwRows; ++q)  // rows past the end read the last row; their sums are dropped
-      Mr[q] = reinterpret_cast<const double2*>(M + (long long)min(row + q, row_end - 1) * mp);
+      Mr[q] = reinterpret_cast<const dbl2*>(M + (long long)min(row + q, row_end - 1) * mp);
     double acc[kSwRows];
 #pragma unroll
     for (int q = 0; q < kSwRows; ++q) acc[q] = 0.0;
     for (int k = lane; k < half; k += 64) {
       const double2 x = rs2[k];
 #pragma unroll
-      for (int q = 0; q < kSwRows; ++q) {
-        const double2 a = Mr[q][k];
+      for (int q = 0; q < kSwRows; ++q) {  // streamed once per cycle: nontemporal
+        const dbl2 a = __builtin_nontemporal_load(Mr[q] + k);
         acc[q] += a.x * x.x + a.y * x.y;
       }
     }

@@ -320,43 +320,6 @@ MortarTask mortar_task(const LevelHost& L, const MortarInfo& M) {
   return t;
 }
 
-// ---------------------------------------------------------------------------------
-// f(i) for i in [0, n) on up to 16 host threads (contiguous ranges; every f(i) writes only its
-// own outputs, so the result does not depend on the split).  The first exception thrown by any
-// f is rethrown here after every thread has been joined; a thread that cannot be started
-// leaves its range to the calling thread.
-template <typename F>
-void parallel_for(size_t n, F&& f) {
-  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
-  const size_t nt = std::min<size_t>(std::min<size_t>(hw, 16), std::max<size_t>(1, n / 64));
-  std::exception_ptr err;
-  std::mutex mu;
-  auto range = [&](size_t lo, size_t hi) {
-    try {
-      for (size_t i = lo; i < hi; ++i) f(i);
-    } catch (...) {
-      std::lock_guard<std::mutex> lock(mu);
-      if (!err) err = std::current_exception();
-    }
-  };
-  if (nt <= 1) {
-    range(0, n);
-  } else {
-    std::vector<std::thread> pool;
-    size_t started = 0;
-    for (; started < nt; ++started) {
-      try {
-        pool.emplace_back(range, n * started / nt, n * (started + 1) / nt);
-      } catch (const std::system_error&) {
-        break;
-      }
-    }
-    if (started < nt) range(n * started / nt, n);
-    for (std::thread& th : pool) th.join();
-  }
-  if (err) std::rethrow_exception(err);
-}
-
 void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, LevelHost& L) {
   const size_t E = L.cells.size();
   L.mortars = find_mortars(mm, L.cells);

@@ -1,6 +1,11 @@
 // Per-level host tables (geometry, mortars, transfers, diagonal) built at upload time.
 #pragma once
 
+#include <algorithm>
+#include <exception>
+#include <mutex>
+#include <system_error>
+#include <thread>
 #include <vector>
 
 #include "host.hpp"
@@ -104,6 +109,42 @@ void cell_eval(const MacroMesh& mm, const Cell& c, const double xi[3], double x[
 double det3(const double J[3][3]);
 void inv3(const double J[3][3], double Ji[3][3]);
 
+// f(i) for i in [0, n) on up to 16 host threads (contiguous ranges; every f(i) writes only its
+// own outputs, so the result does not depend on the split).  The first exception thrown by any
+// f is rethrown here after every thread has been joined; a thread that cannot be started
+// leaves its range to the calling thread.
+template <typename F>
+void parallel_for(size_t n, F&& f) {
+  const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+  const size_t nt = std::min<size_t>(std::min<size_t>(hw, 16), std::max<size_t>(1, n / 64));
+  std::exception_ptr err;
+  std::mutex mu;
+  auto range = [&](size_t lo, size_t hi) {
+    try {
+      for (size_t i = lo; i < hi; ++i) f(i);
+    } catch (...) {
+      std::lock_guard<std::mutex> lock(mu);
+      if (!err) err = std::current_exception();
+    }
+  };
+  if (nt <= 1) {
+    range(0, n);
+  } else {
+    std::vector<std::thread> pool;
+    size_t started = 0;
+    for (; started < nt; ++started) {
+      try {
+        pool.emplace_back(range, n * started / nt, n * (started + 1) / nt);
+      } catch (const std::system_error&) {
+        break;
+      }
+    }
+    if (started < nt) range(n * started / nt, n);
+    for (std::thread& th : pool) th.join();
+  }
+  if (err) std::rethrow_exception(err);
+}
+
 // fill einfo / minfo / fmlist / vgeo / mgeo for a level (cells set)
 void build_level(const MacroMesh& mm, const DiscParams& dp, const OpTable& T, LevelHost& L);
 // transfer records between a fine level and the next coarser one
@@ -166,6 +207,11 @@ struct SchwarzLayout {
   int n = 0;                      // LGL nodes per axis
 };
 void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out);
+// A_ss of the subdomains ``subs`` (all of m points), column-major at A + b m^2, from the operator
+// blocks blk[((e 7 + k) n^3 + j) n^3 + i] = A[(a, i), (e, j)], a = e (k = 0) or the neighbour
+// across face k - 1 of e (zero for pairs that are not face neighbours)
+void schwarz_assemble(const SchwarzLayout& lay, const std::vector<double>& blk, const std::vector<int>& subs, int m,
+                      double* A);
 
 // one-side mortar map: rows of the 1-D matrices along the own face axes
 struct SideMap {
