@@ -201,10 +201,11 @@ class Multigrid:
     def __init__(self, mesh, problem=None, C=10.0, quad_extra=1, n_cheb=4, Lambda=20.0,
                  n_eigs=15, lam=None, seed=0, mass=None, levels=None, jacobi=True, smoother=None,
                  starts=None, max_levels=32, kfield=None, cfield=None, robin_gamma=0.0,
-                 schwarz_overlap=2):
+                 schwarz_overlap=2, schwarz_local="exact"):
         """``smoother``: "none" (Alg. 4 as printed), "point" (Jacobi), "block"
         (element-block Jacobi) or "schwarz" (Alg. schwarz_smoother with ``n_cheb`` cycles per
-        call and ``schwarz_overlap`` = N_overlap, at most p on a level of degree p; no spectral
+        call and ``schwarz_overlap`` = N_overlap, at most p on a level of degree p; local
+        solves exact or, ``schwarz_local="cg"``, CG to 1e-3 as in the paper; no spectral
         bound); ``jacobi`` selects
         "point" / "none" when it is not given.
         ``starts``: Alg. 5 start vectors per smoothed level (see ``refresh``).
@@ -222,6 +223,7 @@ class Multigrid:
         self.n_cheb, self.Lambda = n_cheb, Lambda
         self.smoother = smoother if smoother is not None else ("point" if jacobi else "none")
         self.schwarz_overlap = schwarz_overlap
+        self.schwarz_local = schwarz_local
         self.refresh(n_eigs, seed, lam, starts)
 
     def refresh(self, n_eigs=15, seed=0, lam=None, starts=None):
@@ -279,7 +281,7 @@ class Multigrid:
     def smooth(self, level, b, x):
         if self.smoother == "schwarz":
             A, subs = self.schwarz[level]
-            return schwarz.smooth(A, subs, b, x, self.n_cheb)
+            return schwarz.smooth(A, subs, b, x, self.n_cheb, local=self.schwarz_local)
         return chebyshev(self.ops[level].apply, b, x, self.lam[level], self.Lambda, self.n_cheb,
                          self.minv[level])
 

@@ -140,7 +140,7 @@ def test_smoother_is_a_linear_iteration_with_a_fixed_point():
 
 @pytest.mark.parametrize("p", [2, 3])
 def test_schwarz_multigrid_is_robust(p):
-    # Sec. IV (the Chebyshev / Schwarz comparison): with N_overlap = 2 and 3 Schwarz cycles per
+    # Sec. III.C (the comparison of preconditioners): with N_overlap = 2 and 3 Schwarz cycles per
     # smoothing call the multigrid-preconditioned FCG solve needs a handful of iterations, far
     # fewer than with 4 point-Jacobi Chebyshev steps
     mesh = meshgen.unit_cube(2, p)
@@ -154,3 +154,33 @@ def test_schwarz_multigrid_is_robust(p):
     assert its <= 4 and itc >= 3 * its
     A = assemble_dense(mg_s.ops[0])
     assert np.allclose(u, np.linalg.solve(A, b), rtol=0, atol=1e-8 * np.abs(u).max())
+
+
+def test_local_cg_reaches_its_tolerance_and_the_exact_solve():
+    # the paper's local solver: CG from zero until the subdomain residual falls by 1e-3; with a
+    # tolerance near rounding it reproduces the exact local solve
+    mesh = MESHES["box_2x1x1_l1_p2"]()
+    op = SIPG(mesh, meshgen.problem_config1())
+    A = assemble_dense(op)
+    rng = np.random.default_rng(4)
+    for idx, _ in sw.subdomains(op, 2)[:4]:
+        As = A[np.ix_(idx, idx)]
+        rs = rng.standard_normal(len(idx))
+        d = sw.local_cg(As, rs, 1e-3)
+        assert np.linalg.norm(rs - As @ d) <= 1e-3 * np.linalg.norm(rs)
+        assert np.allclose(sw.local_cg(As, rs, 1e-14), np.linalg.solve(As, rs), rtol=0, atol=1e-10 * np.abs(d).max())
+    assert np.all(sw.local_cg(As, np.zeros(len(idx))) == 0.0)
+
+
+def test_cg_local_solves_keep_the_multigrid_iterations():
+    # R34: the exact local solve is the limit of the paper's CG to 1e-3; the two multigrid
+    # preconditioners take the same number of FCG iterations on the 4^3, p = 2 cube
+    mesh = meshgen.unit_cube(2, 2)
+    prob = meshgen.problem_config1()
+    its = {}
+    for local in ("exact", "cg"):
+        mg = Multigrid(mesh, prob, n_cheb=3, smoother="schwarz", schwarz_overlap=2, schwarz_local=local)
+        b = mg.ops[0].rhs()
+        _, its[local], _ = fcg(mg.ops[0].apply, b, mg.vcycle, tol=1e-10, max_iter=50)
+    print("FCG iterations", its)
+    assert its["cg"] <= its["exact"] + 1 and its["exact"] <= 4
