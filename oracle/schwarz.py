@@ -98,9 +98,10 @@ def _neighbours(centre, half, c):
     return out
 
 
-def subdomains(op, n_overlap):
-    """Per element (mesh order): (global dof indices, weights) of its subdomain, own points first
-    in the element's dof order, then the neighbours' points by element and dof order."""
+def subdomains(op, n_overlap, centres=None):
+    """Per element (mesh order, or the elements ``centres``): (global dof indices, weights) of
+    its subdomain, own points first in the element's dof order, then the neighbours' points by
+    element and dof order."""
     mesh = op.mesh
     n = int(mesh["elem_p"][0]) + 1
     delta = overlap_width(n, n_overlap)
@@ -108,8 +109,8 @@ def subdomains(op, n_overlap):
     xl, _ = rules.lgl(n)
     xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)  # x fastest
     out = []
-    for c in range(len(mesh["elem_p"])):
-        nb = _neighbours(centre, half, c)
+    for c in (range(len(mesh["elem_p"])) if centres is None else centres):
+        nb = _neighbours(centre, half, int(c))
         open_lo = [any(o[d] == -1 and not np.any(np.delete(o, d)) for _, o in nb) for d in range(3)]
         open_hi = [any(o[d] == 1 and not np.any(np.delete(o, d)) for _, o in nb) for d in range(3)]
         idx, wts = [], []

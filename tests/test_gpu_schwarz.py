@@ -129,3 +129,72 @@ def test_schwarz_refusals(ctx):
     print("after the refusals", st, flush=True)
     assert st["rel_residual"] <= 1e-10
     M.free()
+
+
+def _one_cycle_from_a_unit_residual(op, i0, n_overlap):
+    """The oracle's x after one Schwarz cycle from x = 0 with b = e_i0 (mesh order), computed
+    from the subdomains holding i0 only: their entries' columns of A by applies to unit
+    vectors (rows exact for the operator's active elements), then the exact local solves."""
+    e0 = int(np.searchsorted(op.offsets, i0, side="right") - 1)
+    cands = [e0] + [e for e, _ in sw._neighbours(*sw._boxes(op.mesh), e0)]
+    subs = [(idx, w) for idx, w in sw.subdomains(op, n_overlap, centres=cands) if i0 in idx]
+    U = np.unique(np.concatenate([idx for idx, _ in subs]))
+    pos = {int(g): k for k, g in enumerate(U)}
+    A_UU = np.empty((len(U), len(U)))
+    e = np.zeros(op.ndof)
+    for k, j in enumerate(U):
+        e[j] = 1.0
+        A_UU[:, k] = op.apply(e)[U]
+        e[j] = 0.0
+    x = np.zeros(op.ndof)
+    for idx, w in subs:
+        loc = np.array([pos[int(g)] for g in idx])
+        rs = (idx == i0).astype(float)
+        x[idx] += w * np.linalg.solve(A_UU[np.ix_(loc, loc)], rs)
+    return x, U, len(subs)
+
+
+def _active_op(mesh, prob, i0_elem):
+    """The oracle's operator with the rows of every element within two face steps of the
+    sampled element exact (the elements of the subdomains that hold its points)."""
+    centre, half = sw._boxes(mesh)
+    near = [i0_elem] + [e for e, _ in sw._neighbours(centre, half, i0_elem)]
+    ring = set(near)
+    for c in near:
+        ring.update(e for e, _ in sw._neighbours(centre, half, c))
+    return SIPG(mesh, prob, active=np.array(sorted(ring)))
+
+
+@pytest.mark.timeout(300)
+def test_schwarz_full_size_sampled_cycle(ctx):
+    # the benchmark's configuration (16^3 cells, p = 3, 262,144 DOF, N_overlap 2): one cycle
+    # from x = 0 with a unit right-hand side at a sampled point, inside the box and in a corner
+    # element of the domain (one-sided weights), against the oracle's local solves of the
+    # subdomains holding that point; the update is zero outside their union
+    m = meshgen.unit_cube(4, 3)
+    prob = meshgen.problem_config1()
+    M = ctx.upload(m)
+    M.setup_smoother(n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    perm = dof_perm(M.level_cells(0), m)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    anchors = m["elem_anchor"]
+    inner = int(np.flatnonzero(np.all(anchors == 7, axis=1))[0])
+    corner = int(np.flatnonzero(np.all(anchors == 0, axis=1))[0])
+    for e0, local in ((inner, 1 + 4 * (1 + 4 * 1)), (corner, 2 + 4 * (1 + 4 * 2))):
+        op = _active_op(m, prob, e0)
+        i0 = int(op.offsets[e0] + local)
+        xo, U, ns = _one_cycle_from_a_unit_residual(op, i0, 2)
+        b = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+        b[int(inv[i0])] = 1.0
+        x = torch.zeros_like(b)
+        M.smooth(b, x, level=0, n_iter=1)
+        xg = np.empty(op.ndof)
+        xg[perm] = host(x)
+        err = np.linalg.norm(xg[U] - xo[U]) / np.linalg.norm(xo[U])
+        outside = np.delete(xg, U)
+        print("element", e0, "dof", i0, "subdomains", ns, "union", len(U), "rel err", err,
+              "largest outside", np.abs(outside).max(), flush=True)
+        assert err <= TOL_SCHWARZ and np.all(outside == 0.0)
+        assert ns == (8 if e0 == inner else 4)
+    M.free()
