@@ -23,15 +23,25 @@ falling half of w is dropped (its phi term is replaced by its limit, -1 on the u
 the lower side): no other subdomain shares the points there, and the weights of all subdomains
 then sum to one at every point.
 
+``subdomains_topo`` builds the same subdomains from the mesh topology alone, for any macro
+maps and face orientations (one degree, one level, no 2:1 faces): a neighbour's points are
+placed in e_c's extended coordinates by the composed maps of the faces crossed to reach it.
+On the six-patch shell three cells meet around the radial lines through the cube's corners;
+there the subdomains cover three quadrants instead of four and their weights sum to 3/4, so
+they are divided by their sum wherever it is not one.
+
 Local solves: R_s A R_s^T d_s = R_s r solved exactly by default (the limit of the paper's
 iteration, which keeps the smoother linear), or as the paper does, by CG from zero to a
 relative residual of 1e-3 (``local="cg"``).
 
 Smoother: N_iter times r = b - A x, x <- x + sum_s R_s^T W_s d_s.
 """
+import itertools
+
 import numpy as np
 
 from . import geometry, rules
+from .mesh import neighbor_cell, tangential_axes
 
 
 def phi(t):
@@ -125,6 +135,129 @@ def subdomains(op, n_overlap, centres=None):
             idx.append(op.offsets[e] + np.flatnonzero(inside))
             wts.append(w)
         out.append((np.concatenate(idx), np.concatenate(wts)))
+    return out
+
+
+def _face_map(f, fb, o):
+    """Affine map of the reference coordinates of the neighbour across face f of an element
+    (its face fb, orientation o: swap | flip of the first | flip of the second face axis, from
+    this face's coordinates to the neighbour's) into this element's extended coordinates:
+    ext[i] = sign[i] xi_nb[perm[i]] + shift[i].  The shared face lies at ext[d] = +-1."""
+    d, s = divmod(f, 2)
+    db, sb = divmod(fb, 2)
+    t0, t1 = tangential_axes(d)
+    u0, u1 = tangential_axes(db)
+    sc, sn = (1 if s else -1), (1 if sb else -1)
+    perm, sign, shift = [0, 0, 0], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0]
+    perm[d], sign[d], shift[d] = db, float(-sc * sn), 2.0 * sc
+    a0, a1 = (t1, t0) if o & 1 else (t0, t1)  # own axes carrying the neighbour's u0, u1
+    perm[a0], sign[a0] = u0, (-1.0 if o & 2 else 1.0)
+    perm[a1], sign[a1] = u1, (-1.0 if o & 4 else 1.0)
+    return perm, sign, shift
+
+
+def _compose(m1, m2):
+    """m1 after m2 (both as in _face_map)."""
+    p1, s1, h1 = m1
+    p2, s2, h2 = m2
+    return ([p2[p1[i]] for i in range(3)], [s1[i] * s2[p1[i]] for i in range(3)],
+            [s1[i] * h2[p1[i]] + h1[i] for i in range(3)])
+
+
+def _topo_neighbours(mesh, index, c):
+    """Face, edge and corner neighbours of element c as (element, map into c's extended
+    coordinates), found by stepping across faces in every order of the offset's axes.  An
+    offset whose orders disagree, or that leads back to c or to one of its face neighbours (a
+    vertex where three cells meet instead of four), has no neighbour."""
+    lev = int(mesh["elem_level"][c])
+
+    def across(e, f):
+        r = neighbor_cell(mesh, int(mesh["elem_macro"][e]), lev, tuple(int(x) for x in mesh["elem_anchor"][e]), f)
+        if r is None:
+            return None
+        mb, anc, fb, o = r
+        return index[(mb, lev) + tuple(anc)], fb, o
+
+    ident = ([0, 1, 2], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0])
+    found = {}
+    for off in itertools.product((-1, 0, 1), repeat=3):
+        axes = [a for a in range(3) if off[a]]
+        if not axes:
+            continue
+        results = set()
+        for order in itertools.permutations(axes):
+            e, M = c, ident
+            for a in order:
+                j = M[0][a]
+                face = 2 * j + (1 if off[a] * M[1][a] > 0 else 0)
+                r = across(e, face)
+                if r is None:
+                    e = None
+                    break
+                e, fb, o = r[0], r[1], r[2]
+                M = _compose(M, _face_map(face, fb, o))
+            if e is None:
+                continue
+            if [float(2 * x) for x in off] != M[2]:
+                results.add(None)
+            else:
+                results.add((e, tuple(M[0]), tuple(M[1])))
+        if len(results) == 1 and None not in results:
+            (e, perm, sign), = results
+            found[off] = (e, (list(perm), list(sign), [2.0 * x for x in off]))
+    faces = {found[o][0] for o in found if sum(map(abs, o)) == 1}
+    out = []
+    for off in sorted(found, key=lambda o: found[o][0]):
+        e = found[off][0]
+        if e == c or (sum(map(abs, off)) > 1 and e in faces):
+            continue
+        out.append((e, np.array(off), found[off][1]))
+    if len({e for e, _, _ in out}) != len(out):
+        raise ValueError("an element neighbours the centre on two sides")
+    return out
+
+
+def subdomains_topo(op, n_overlap, normalise=True):
+    """Subdomains of every element built from the mesh topology (any macro maps and face
+    orientations; one degree and one level): neighbours' points placed in e_c's extended
+    coordinates through the composed face maps, weights as in ``subdomains``.  Where cells
+    meet three around an edge instead of four, the weights of the subdomains covering a point
+    no longer sum to one; with ``normalise`` they are divided there by their sum."""
+    mesh = op.mesh
+    if len(set(int(p) for p in mesh["elem_p"])) != 1 or len(set(int(l) for l in mesh["elem_level"])) != 1:
+        raise ValueError("the Schwarz subdomains here need one degree and one level")
+    n = int(mesh["elem_p"][0]) + 1
+    delta = overlap_width(n, n_overlap)
+    xl, _ = rules.lgl(n)
+    xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)  # x fastest
+    E = len(mesh["elem_p"])
+    index = {(int(mesh["elem_macro"][e]), int(mesh["elem_level"][e])) + tuple(int(x) for x in mesh["elem_anchor"][e]): e
+             for e in range(E)}
+    out = []
+    for c in range(E):
+        nb = _topo_neighbours(mesh, index, c)
+        open_lo = [any(o[d] == -1 and not np.any(np.delete(o, d)) for _, o, _ in nb) for d in range(3)]
+        open_hi = [any(o[d] == 1 and not np.any(np.delete(o, d)) for _, o, _ in nb) for d in range(3)]
+        idx, wts = [], []
+        ident = ([0, 1, 2], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0])
+        for e, _, (perm, sign, shift) in [(c, None, ident)] + nb:
+            ext = np.stack([sign[i] * xi[:, perm[i]] + shift[i] for i in range(3)], axis=1)
+            inside = np.all(np.abs(ext) <= 1.0 + delta + 1e-12, axis=1)
+            if not inside.any():
+                continue
+            w = np.ones(int(inside.sum()))
+            for d in range(3):
+                w = w * weight_1d(ext[inside, d], delta, open_lo[d], open_hi[d])
+            idx.append(op.offsets[e] + np.flatnonzero(inside))
+            wts.append(w)
+        out.append((np.concatenate(idx), np.concatenate(wts)))
+    if normalise:
+        total = np.zeros(op.ndof)
+        for idx, w in out:
+            np.add.at(total, idx, w)
+        fix = np.abs(total - 1.0) > 1e-12
+        if fix.any():
+            out = [(idx, np.where(fix[idx], w / np.where(fix[idx], total[idx], 1.0), w)) for idx, w in out]
     return out
 
 

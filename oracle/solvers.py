@@ -245,7 +245,7 @@ class Multigrid:
                 A = assemble_dense(op)
                 # a level of degree p < N_overlap holds at most p layers beyond the coincident one
                 nov = min(self.schwarz_overlap, int(op.mesh["elem_p"].max()))
-                self.schwarz.append((A, schwarz.subdomains(op, nov)))
+                self.schwarz.append((A, schwarz.subdomains_topo(op, nov)))
             lam = [0.0] * (len(self.ops) - 1)
         if lam is None:
             lam = []

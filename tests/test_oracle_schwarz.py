@@ -184,3 +184,77 @@ def test_cg_local_solves_keep_the_multigrid_iterations():
         _, its[local], _ = fcg(mg.ops[0].apply, b, mg.vcycle, tol=1e-10, max_iter=50)
     print("FCG iterations", its)
     assert its["cg"] <= its["exact"] + 1 and its["exact"] <= 4
+
+
+@pytest.mark.parametrize("name", list(MESHES) + ["box_2x2x1_l1_p2"])
+@pytest.mark.parametrize("n_overlap", [1, 2])
+def test_topological_subdomains_equal_the_geometric_ones_on_boxes(name, n_overlap):
+    # the construction from face maps (any orientation) reproduces the box construction
+    mesh = MESHES[name]() if name in MESHES else meshgen.box_grid((2, 2, 1), 1, 2)
+    op = SIPG(mesh, meshgen.problem_config1())
+    for (i1, w1), (i2, w2) in zip(sw.subdomains(op, n_overlap), sw.subdomains_topo(op, n_overlap)):
+        assert np.array_equal(np.sort(i1), np.sort(i2))
+        assert np.allclose(w1[np.argsort(i1)], w2[np.argsort(i2)], rtol=0, atol=1e-15)
+
+
+def test_face_maps_compose_to_the_identity_around_a_regular_edge():
+    # four quarter turns around an edge of the box: stepping +x, +y, -x, -y returns to the
+    # start with the identity map (same-macro faces); a rotated face map and its inverse compose
+    # to the identity
+    ident = ([0, 1, 2], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0])
+    M = ident
+    for f, fb in ((1, 0), (3, 2), (0, 1), (2, 3)):
+        M = sw._compose(M, sw._face_map(f, fb, 0))
+    assert M == ident
+    for o in range(8):
+        fwd = sw._face_map(1, 4, o)  # +x face meeting a -z face, orientation o
+        # the inverse map: from the neighbour's face 4 back across to face 1
+        back = [m for m in (sw._face_map(4, 1, q) for q in range(8)) if sw._compose(fwd, m)[:2] == ident[:2]]
+        assert len(back) == 1
+        assert sw._compose(fwd, back[0]) == ident
+
+
+SHELL = {
+    "shell_l2_p3": lambda: meshgen.cubed_sphere_shell(level=2, p=3, r_out=1e3, inner_refine=False),
+}
+
+
+@pytest.mark.parametrize("n_overlap", [1, 2])
+def test_shell_weights_are_three_quarters_next_to_the_three_cell_edges(n_overlap):
+    # on the six-patch shell cells meet three around the eight radial lines through the cube's
+    # corners: the points whose subdomains miss the fourth quadrant sum to exactly 3/4 (before
+    # normalisation), all in the cells touching those lines; everywhere else the weights sum to
+    # one; inner subdomains have (n + 2 N_overlap)^3 points; after normalisation all sum to one
+    mesh = SHELL["shell_l2_p3"]()
+    op = SIPG(mesh, meshgen.problem_config2())
+    subs = sw.subdomains_topo(op, n_overlap, normalise=False)
+    total = np.zeros(op.ndof)
+    for idx, w in subs:
+        np.add.at(total, idx, w)
+    off = np.abs(total - 1.0) > 1e-12
+    assert np.allclose(total[off], 0.75, rtol=0, atol=1e-14) and off.sum() > 0
+    elems = np.unique(np.searchsorted(op.offsets, np.flatnonzero(off), side="right") - 1)
+    a = mesh["elem_anchor"][elems]
+    assert np.all((a[:, :2] == 0) | (a[:, :2] == 3))
+    A = mesh["elem_anchor"]
+    inner = np.flatnonzero(np.all((A >= 1) & (A <= 2), axis=1))
+    assert len(inner) == 6 * 8 and {len(subs[e][0]) for e in inner} == {(4 + 2 * n_overlap) ** 3}
+    total = np.zeros(op.ndof)
+    for idx, w in sw.subdomains_topo(op, n_overlap):
+        np.add.at(total, idx, w)
+    assert np.allclose(total, 1.0, rtol=0, atol=1e-14)
+
+
+def test_schwarz_restores_multigrid_on_the_stretched_shell():
+    # Sec. III.C: on the shell compactified to r = 1e9 the Chebyshev-smoothed multigrid loses
+    # efficiency while the Schwarz smoother keeps a handful of iterations
+    mesh = meshgen.cubed_sphere_shell(level=1, p=3, r_out=1e9, inner_refine=False)
+    prob = meshgen.problem_config2()
+    its = {}
+    for name, kw in (("schwarz", dict(n_cheb=3, smoother="schwarz", schwarz_overlap=2)),
+                     ("point", dict(n_cheb=4, smoother="point")), ("block", dict(n_cheb=4, smoother="block"))):
+        mg = Multigrid(mesh, prob, **kw)
+        b = mg.ops[0].rhs()
+        _, its[name], _ = fcg(mg.ops[0].apply, b, mg.vcycle, tol=1e-10, max_iter=300)
+    print("FCG iterations", its)
+    assert its["schwarz"] <= 6 and its["block"] >= 4 * its["schwarz"] and its["point"] >= 10 * its["schwarz"]
