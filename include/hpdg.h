@@ -198,11 +198,14 @@ typedef struct {
  *                      problems are solved exactly (their inverses, restricted to the rows of
  *                      non-zero weight, are formed at setup on the device and kept: m_w m
  *                      values per subdomain, m = (p + 1 + 2 N_overlap)^3 points inside the
- *                      mesh, m_w = (p + 3)^3 weighted ones for N_overlap >= 2).  On a side of
- *                      the centre element that lies on the domain boundary the weight keeps its
- *                      plateau, so the weights sum to one at every point.  Scope: every smoothed
- *                      level has one degree, one refinement level, axis-aligned affine elements
- *                      and 1:1 faces in the elements' own frames, subdomains of at most 8190
+ *                      mesh, m_w = (p + 3)^3 weighted ones for N_overlap >= 2).  Neighbours'
+ *                      points are placed in the centre's reference frame through the maps of the
+ *                      faces crossed to reach them (any macro maps and face orientations).  On a
+ *                      side of the centre element that lies on the domain boundary the weight
+ *                      keeps its plateau; where three cells meet around an edge (the six-patch
+ *                      shell) the weights covering a point are divided by their sum; so they
+ *                      sum to one at every point.  Scope: every smoothed level has one degree,
+ *                      one refinement level and faces that meet 1:1, subdomains of at most 8190
  *                      points (HPDG_ERR_UNSUPPORTED at setup otherwise); FP64 only
  *                      (HPDG_ERR_UNSUPPORTED for FP32 smoothing, mixed-precision solves and
  *                      Newton linearisations).  No spectral bound is computed (lambda_max 0). */

@@ -6,6 +6,8 @@
 #include <algorithm>
 #include <array>
 #include <cmath>
+#include <cstdlib>
+#include <unordered_map>
 
 namespace hpdg {
 
@@ -33,6 +35,63 @@ double weight(double xi, double delta, bool lower_open, bool upper_open) {
 
 }  // namespace
 
+namespace {
+
+// affine map of a neighbour's reference coordinates into the centre's extended coordinates:
+// ext[i] = sign[i] xi[perm[i]] + shift[i]
+struct FaceMap {
+  int perm[3];
+  double sign[3], shift[3];
+};
+
+const FaceMap kIdentity = {{0, 1, 2}, {1.0, 1.0, 1.0}, {0.0, 0.0, 0.0}};
+
+// the neighbour across face f (its face fb, orientation o from this face's coordinates to its
+// own) seen from this element: its normal axis reversed or not so that the shared face lies at
+// ext = +-1 on axis f / 2, its face axes permuted and flipped back by o
+FaceMap face_map(int f, int fb, int o) {
+  const int d = f >> 1, db = fb >> 1;
+  const double sc = (f & 1) ? 1.0 : -1.0, sn = (fb & 1) ? 1.0 : -1.0;
+  const int t0 = d == 0 ? 1 : 0, t1 = d == 2 ? 1 : 2;
+  const int u0 = db == 0 ? 1 : 0, u1 = db == 2 ? 1 : 2;
+  FaceMap M = kIdentity;
+  M.perm[d] = db;
+  M.sign[d] = -sc * sn;
+  M.shift[d] = 2.0 * sc;
+  const int a0 = (o & 1) ? t1 : t0, a1 = (o & 1) ? t0 : t1;
+  M.perm[a0] = u0;
+  M.sign[a0] = (o & 2) ? -1.0 : 1.0;
+  M.perm[a1] = u1;
+  M.sign[a1] = (o & 4) ? -1.0 : 1.0;
+  M.shift[a0] = M.shift[a1] = 0.0;
+  return M;
+}
+
+// outer after inner
+FaceMap compose(const FaceMap& outer, const FaceMap& inner) {
+  FaceMap M;
+  for (int i = 0; i < 3; ++i) {
+    const int k = outer.perm[i];
+    M.perm[i] = inner.perm[k];
+    M.sign[i] = outer.sign[i] * inner.sign[k];
+    M.shift[i] = outer.sign[i] * inner.shift[k] + outer.shift[i];
+  }
+  return M;
+}
+
+bool same_map(const FaceMap& a, const FaceMap& b) {
+  for (int i = 0; i < 3; ++i)
+    if (a.perm[i] != b.perm[i] || a.sign[i] != b.sign[i] || a.shift[i] != b.shift[i]) return false;
+  return true;
+}
+
+uint64_t cell_key(const Cell& c) {
+  return (uint64_t(c.macro) << 47) ^ (uint64_t(c.level) << 42) ^ (uint64_t(c.a[0]) << 28) ^
+         (uint64_t(c.a[1]) << 14) ^ uint64_t(c.a[2]);
+}
+
+}  // namespace
+
 void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out) {
   const int E = int(L.cells.size());
   if (E == 0) throw Error(HPDG_ERR_INVALID_MESH, "empty level");
@@ -40,43 +99,31 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
   const int lev = L.cells[0].level;
   if (n_overlap < 1) throw Error(HPDG_ERR_INVALID_ARG, "Schwarz overlap must be at least 1");
   n_overlap = std::min(n_overlap, n - 1);  // a level of degree p holds at most p layers
-  // scope: one degree, one refinement level, axis-aligned affine boxes
-  std::vector<std::array<double, 3>> centre(E), half(E);
-  for (int e = 0; e < E; ++e) {
-    const Cell& c = L.cells[e];
-    if (L.einfo[e].n != n || c.level != lev)
+  // scope: one degree, one refinement level, faces that meet 1:1 (any macro maps and face
+  // orientations)
+  for (int e = 0; e < E; ++e)
+    if (L.einfo[e].n != n || L.cells[e].level != lev)
       throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs levels of one degree and one refinement level");
-    if (mm.macros[c.macro].kind != 0)
-      throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs affine elements");
-    const double xi0[3] = {0.0, 0.0, 0.0};
-    double x[3], J[3][3];
-    cell_eval(mm, c, xi0, x, J);
-    double big = 0;
-    for (int i = 0; i < 3; ++i)
-      for (int j = 0; j < 3; ++j) big = std::max(big, std::fabs(J[i][j]));
-    for (int i = 0; i < 3; ++i) {
-      for (int j = 0; j < 3; ++j)
-        if (i != j && std::fabs(J[i][j]) > 1e-12 * big)
-          throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs axis-aligned elements");
-      if (!(J[i][i] > 0)) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs axis-aligned elements");
-      centre[e][i] = x[i];
-      half[e][i] = J[i][i];
-    }
-  }
-  // face neighbours: every mortar 1:1, the plus side on the opposite face, same tangential size
+  for (const Mortar& m : L.mortars)
+    if (m.ep >= 0 && m.sub != -1) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs faces that meet 1:1");
+  std::unordered_map<uint64_t, int> index;
+  index.reserve(size_t(E) * 2);
+  for (int e = 0; e < E; ++e) index[cell_key(L.cells[e])] = e;
+  // per element and face: the neighbour, its face and the orientation
   std::vector<int>& F = out.fnb;
   F.assign(size_t(E) * 6, -1);
-  for (const Mortar& m : L.mortars) {
-    if (m.ep < 0) continue;
-    if (m.sub != -1 || m.fp != (m.fm ^ 1) || m.orient != 0)
-      throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs conforming faces in the elements' own frames");
-    const int d = m.fm >> 1;
-    for (int t = 0; t < 3; ++t)
-      if (t != d && std::fabs(half[m.em][t] - half[m.ep][t]) > 1e-12 * half[m.em][t])
-        throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs faces that match in size");
-    F[size_t(m.em) * 6 + m.fm] = m.ep;
-    F[size_t(m.ep) * 6 + m.fp] = m.em;
-  }
+  std::vector<int> FB(size_t(E) * 6, -1), FO(size_t(E) * 6, 0);
+  for (int e = 0; e < E; ++e)
+    for (int f = 0; f < 6; ++f) {
+      Cell nb;
+      int fb = 0, o = 0;
+      if (!cell_across(mm, L.cells[e], f, nb, fb, o)) continue;
+      auto it = index.find(cell_key(nb));
+      if (it == index.end()) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs faces that meet 1:1");
+      F[size_t(e) * 6 + f] = it->second;
+      FB[size_t(e) * 6 + f] = fb;
+      FO[size_t(e) * 6 + f] = o;
+    }
   std::vector<double> xl(n), wl(n);
   gauss_lobatto(n, xl.data(), wl.data());
   const double delta = 1.0 + xl[n_overlap - 1];
@@ -86,71 +133,128 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
   out.elem.clear();
   out.loc.clear();
   out.w.clear();
-  // step along face neighbours: the element on side o of c (o_d in {-1, 0, 1}), reached over the
-  // axes in every order; -1 when none, an error when two orders disagree
-  auto step = [&](int e, int d, int s) { return e < 0 ? -1 : F[size_t(e) * 6 + 2 * d + (s > 0 ? 1 : 0)]; };
-  for (int c = 0; c < E; ++c) {
+  struct Nb {
+    int e;
+    int o[3];
+    FaceMap M;
+  };
+  std::vector<std::vector<int>> el_all(E), lc_all(E);
+  std::vector<std::vector<double>> wt_all(E);
+  parallel_for(size_t(E), [&](size_t ci) {
+    const int c = int(ci);
+    // neighbours at every offset: the face paths in every order of the offset's axes; an offset
+    // whose paths disagree (or that leads back to c or one of its face neighbours: three cells
+    // around an edge) has none
+    std::vector<Nb> nb;
+    for (int oz = -1; oz <= 1; ++oz)
+      for (int oy = -1; oy <= 1; ++oy)
+        for (int ox = -1; ox <= 1; ++ox) {
+          const int off[3] = {ox, oy, oz};
+          int axes[3], na = 0;
+          for (int d = 0; d < 3; ++d)
+            if (off[d]) axes[na++] = d;
+          if (na == 0) continue;
+          int found = -1;
+          FaceMap fm = kIdentity;
+          bool bad = false, any = false;
+          int order[3] = {0, 1, 2};
+          do {
+            if (order[0] >= na || (na > 1 && order[1] >= na) || (na > 2 && order[2] >= na)) continue;
+            int e = c;
+            FaceMap M = kIdentity;
+            for (int k = 0; k < na && e >= 0; ++k) {
+              const int a = axes[order[k]];
+              const int j = M.perm[a];
+              const int face = 2 * j + (double(off[a]) * M.sign[a] > 0 ? 1 : 0);
+              const size_t slot = size_t(e) * 6 + face;
+              if (F[slot] < 0) {
+                e = -1;
+                break;
+              }
+              M = compose(M, face_map(face, FB[slot], FO[slot]));
+              e = F[slot];
+            }
+            if (e < 0) continue;
+            for (int d = 0; d < 3; ++d)
+              if (M.shift[d] != 2.0 * off[d]) bad = true;
+            if (any && (e != found || !same_map(M, fm))) bad = true;
+            found = e;
+            fm = M;
+            any = true;
+          } while (std::next_permutation(order, order + 3));
+          if (!any || bad) continue;
+          Nb x;
+          x.e = found;
+          for (int d = 0; d < 3; ++d) x.o[d] = off[d];
+          x.M = fm;
+          nb.push_back(x);
+        }
+    std::vector<int> faces;
+    for (const Nb& x : nb)
+      if (std::abs(x.o[0]) + std::abs(x.o[1]) + std::abs(x.o[2]) == 1) faces.push_back(x.e);
+    std::vector<Nb> keep;
+    for (const Nb& x : nb) {
+      const bool edge = std::abs(x.o[0]) + std::abs(x.o[1]) + std::abs(x.o[2]) > 1;
+      if (x.e == c || (edge && std::find(faces.begin(), faces.end(), x.e) != faces.end())) continue;
+      keep.push_back(x);
+    }
+    std::stable_sort(keep.begin(), keep.end(), [](const Nb& a, const Nb& b) { return a.e < b.e; });
+    for (size_t k = 1; k < keep.size(); ++k)
+      if (keep[k].e == keep[k - 1].e)
+        throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing: an element neighbours another on two sides");
     bool open_lo[3], open_hi[3];
     for (int d = 0; d < 3; ++d) {
       open_lo[d] = F[size_t(c) * 6 + 2 * d] >= 0;
       open_hi[d] = F[size_t(c) * 6 + 2 * d + 1] >= 0;
     }
-    std::vector<std::pair<int, std::array<int, 3>>> nb;  // (element, side)
-    for (int oz = -1; oz <= 1; ++oz)
-      for (int oy = -1; oy <= 1; ++oy)
-        for (int ox = -1; ox <= 1; ++ox) {
-          const int o[3] = {ox, oy, oz};
-          if (!ox && !oy && !oz) continue;
-          int axes[3], na = 0;
-          for (int d = 0; d < 3; ++d)
-            if (o[d]) axes[na++] = d;
-          int found = -1;
-          bool any = false;
-          std::array<int, 3> perm = {0, 1, 2};
-          do {
-            if (perm[0] >= na || (na > 1 && perm[1] >= na) || (na > 2 && perm[2] >= na)) continue;
-            int e = c;
-            for (int k = 0; k < na; ++k) e = step(e, axes[perm[k]], o[axes[perm[k]]]);
-            if (e < 0) continue;
-            if (any && e != found)
-              throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing: inconsistent edge or corner neighbours");
-            found = e;
-            any = true;
-          } while (std::next_permutation(perm.begin(), perm.end()));
-          if (found >= 0) nb.push_back({found, {ox, oy, oz}});
-        }
-    std::sort(nb.begin(), nb.end());
-    for (size_t k = 1; k < nb.size(); ++k)
-      if (nb[k].first == nb[k - 1].first)
-        throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing: an element neighbours another on two sides");
-    nb.insert(nb.begin(), {c, {0, 0, 0}});
-    std::vector<int> el, lc;
-    std::vector<double> wt;
-    for (const auto& pr : nb) {
-      const int e = pr.first;
-      const std::array<int, 3>& o = pr.second;
+    Nb self;
+    self.e = c;
+    self.o[0] = self.o[1] = self.o[2] = 0;
+    self.M = kIdentity;
+    keep.insert(keep.begin(), self);
+    std::vector<int>& el = el_all[c];
+    std::vector<int>& lc = lc_all[c];
+    std::vector<double>& wt = wt_all[c];
+    for (const Nb& x : keep)
       for (int k = 0; k < n; ++k)
         for (int j = 0; j < n; ++j)
           for (int i = 0; i < n; ++i) {
-            const double ext[3] = {xl[i] + 2.0 * o[0], xl[j] + 2.0 * o[1], xl[k] + 2.0 * o[2]};
+            const double xi[3] = {xl[i], xl[j], xl[k]};
+            double ext[3];
             bool in = true;
-            for (int d = 0; d < 3; ++d) in = in && std::fabs(ext[d]) <= 1.0 + delta + 1e-12;
+            for (int d = 0; d < 3; ++d) {
+              ext[d] = x.M.sign[d] * xi[x.M.perm[d]] + x.M.shift[d];
+              in = in && std::fabs(ext[d]) <= 1.0 + delta + 1e-12;
+            }
             if (!in) continue;
             double w = 1.0;
             for (int d = 0; d < 3; ++d) w *= weight(ext[d], delta, open_lo[d], open_hi[d]);
-            el.push_back(e);
+            el.push_back(x.e);
             lc.push_back(i + n * (j + n * k));
             wt.push_back(w);
           }
+  });
+  // where cells meet three around an edge the weights covering a point sum to less than one:
+  // divide them there by their sum
+  std::vector<double> total(size_t(L.ndof), 0.0);
+  for (int c = 0; c < E; ++c)
+    for (size_t k = 0; k < el_all[c].size(); ++k)
+      total[size_t(L.einfo[el_all[c][k]].off + lc_all[c][k])] += wt_all[c][k];
+  for (int c = 0; c < E; ++c)
+    for (size_t k = 0; k < el_all[c].size(); ++k) {
+      const double t = total[size_t(L.einfo[el_all[c][k]].off + lc_all[c][k])];
+      if (std::fabs(t - 1.0) > 1e-12) wt_all[c][k] /= t;
     }
+  for (int c = 0; c < E; ++c) {
+    const std::vector<int>& el = el_all[c];
     // non-zero weights first (stable)
     int cnt = 0;
     for (int pass = 0; pass < 2; ++pass)
       for (size_t k = 0; k < el.size(); ++k)
-        if ((wt[k] != 0.0) == (pass == 0)) {
+        if ((wt_all[c][k] != 0.0) == (pass == 0)) {
           out.elem.push_back(el[k]);
-          out.loc.push_back(lc[k]);
-          out.w.push_back(wt[k]);
+          out.loc.push_back(lc_all[c][k]);
+          out.w.push_back(wt_all[c][k]);
           if (pass == 0) ++cnt;
         }
     out.nw[c] = cnt;

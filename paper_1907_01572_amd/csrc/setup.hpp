@@ -188,16 +188,25 @@ struct EstTables {
 void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscParams& dp, const LevelHost& L,
                       int kind, const std::vector<double>& P, EstTables& out);
 
+// the cell of the same level (and degree) across face f of c: its face fb and the orientation
+// from c's face coordinates to its (swap | flip of the first | flip of the second axis);
+// false on the boundary (topo.cpp)
+bool cell_across(const MacroMesh& mm, const Cell& c, int f, Cell& nb, int& fb, int& orient);
+
 // Additive Schwarz subdomains of a level (Sec. II.D, Alg. schwarz_smoother, Eq. schwarz_weight),
-// one per element e_c, for levels of axis-aligned affine elements of one degree and one
-// refinement level whose faces all meet 1:1 (HPDG_ERR_UNSUPPORTED otherwise).  A point of a
-// neighbour lying on side o (o_d in {-1, 0, 1}) of e_c has the extended coordinate
-// xi_ext = xi + 2 o; the subdomain holds the points with |xi_ext| <= 1 + delta on every axis,
-// delta = 1 + xi_(N_overlap - 1) (N_overlap at most p), each weighted by the product over the axes of
+// one per element e_c, for levels of one degree and one refinement level whose faces all meet
+// 1:1 (HPDG_ERR_UNSUPPORTED otherwise; any macro maps and face orientations).  The neighbours
+// at each offset o (o_d in {-1, 0, 1}) are found by stepping across faces in every order of
+// the offset's axes, and their reference coordinates carried into e_c's extended coordinates
+// by the composed face maps (xi_ext = xi + 2 o in e_c's frame); an offset whose paths disagree,
+// or that leads back to e_c or a face neighbour (three cells around an edge), has none.  The
+// subdomain holds the points with |xi_ext| <= 1 + delta on every axis, delta =
+// 1 + xi_(N_overlap - 1) (N_overlap at most p), each weighted by the product over the axes of
 // w(xi) = (phi((xi + 1) / delta) - phi((xi - 1) / delta)) / 2; on a side of e_c without a
-// neighbour (domain boundary) that side's phi term is replaced by its limit.  Entries of a
-// subdomain: e_c's points, then the neighbours' by element and local index, and then stably
-// reordered so that the entries with a non-zero weight come first.
+// neighbour (domain boundary) that side's phi term is replaced by its limit; where the weights
+// covering a point do not sum to one (three cells around an edge) they are divided by their
+// sum.  Entries of a subdomain: e_c's points, then the neighbours' by element and local index,
+// and then stably reordered so that the entries with a non-zero weight come first.
 struct SchwarzLayout {
   std::vector<long long> off;     // per subdomain: first entry (E + 1)
   std::vector<int> nw;            // per subdomain: entries with a non-zero weight

@@ -270,4 +270,9 @@ void adapt_cells(const MacroMesh& mm, const std::vector<Cell>& cells, const sign
   if (out.size() != leaves.size()) throw Error(-2, "mesh adaptation: leaves outside the old cells");
 }
 
+bool cell_across(const MacroMesh& mm, const Cell& c, int f, Cell& nb, int& fb, int& orient) {
+  nb = c;
+  return across(mm, c.macro, c.level, c.a, f, nb.macro, nb.a, fb, orient);
+}
+
 }  // namespace hpdg
