@@ -395,6 +395,8 @@ def main():
     ap.add_argument("--schwarz-level", type=int, default=3, help="schwarz: refinement level of the unit cube")
     ap.add_argument("--schwarz-p", type=int, default=3, help="schwarz: degree")
     ap.add_argument("--schwarz-overlap", type=int, default=2, help="schwarz: N_overlap")
+    ap.add_argument("--schwarz-mesh", default="box", choices=["box", "shell"],
+                    help="schwarz: the unit box or the compactified six-patch shell")
     ap.add_argument("--amr-steps", type=int, default=6, help="amr: adaptation steps")
     ap.add_argument("--amr-fraction", type=float, default=0.2, help="amr: fraction of elements marked")
     ap.add_argument("--requests", type=int, default=512, help="serving: number of requests")
@@ -831,23 +833,37 @@ def run_amr(args, meshgen, hp):
 
 def run_schwarz(args, meshgen, hp):
     """Multigrid-preconditioned FCG with the additive Schwarz smoother (N_overlap 2, three cycles
-    per smoothing call, the settings of the paper's smoother comparison) against point-Jacobi
-    Chebyshev on the unit box of affine cells at one level and degree (the smoother's scope):
-    setup time, iterations and solve time of each, and the roofline of the Schwarz local-solve
-    kernel (HIP events around every launch during one extra solve)."""
+    per smoothing call, the settings of the paper's smoother comparison) against Chebyshev
+    smoothing, on the unit box (point Jacobi) or on the six-patch shell compactified to 1e9
+    (block and point Jacobi; Sec. III.C): setup time, iterations and solve time of each, and the
+    roofline of the Schwarz local-solve kernel (HIP events around every launch during one extra
+    solve)."""
     import torch
 
     dev = torch.device("cuda:0")
-    prob = meshgen.problem_config1()
-    mesh = meshgen.unit_cube(args.schwarz_level, args.schwarz_p)
+    if args.schwarz_mesh == "shell":
+        # the six-patch shell compactified to r = 1e9 without the extra inner refinement (the
+        # smoother needs 1:1 faces); block Jacobi with the shell settings of the main benchmark
+        prob = meshgen.problem_config2()
+        mesh = meshgen.cubed_sphere_shell(level=args.schwarz_level, p=args.schwarz_p, r_out=1e9, inner_refine=False)
+        label = "cubed-sphere shell compactified to r = 1e9, 6 x %d^3 cells, p = %d" % (2 ** args.schwarz_level,
+                                                                                       args.schwarz_p)
+        problem = "-lap u = 0, Dirichlet data of u = 1/r + x z / r^5 on both spheres"
+        others = (("chebyshev_block", dict(n_cheb=26, Lambda=600.0, smoother="block")),
+                  ("chebyshev_point", dict(n_cheb=4, smoother="point")))
+    else:
+        prob = meshgen.problem_config1()
+        mesh = meshgen.unit_cube(args.schwarz_level, args.schwarz_p)
+        label = "unit cube, %d^3 affine cells, p = %d" % (2 ** args.schwarz_level, args.schwarz_p)
+        problem = "-lap u = 3 pi^2 sin sin sin, u = 0 on the boundary"
+        others = (("chebyshev_point", dict(n_cheb=4, smoother="point")),)
     ctx = hp.Context(0)
-    M = ctx.upload(mesh)
+    M = ctx.upload(mesh, coef=hp.coef_from_problem(prob))
     N = M.n_dof[0]
     F = torch.zeros(N, dtype=torch.float64, device=dev)
     M.assemble_rhs(prob, F)
     out = {}
-    for name, kw in (("schwarz", dict(n_cheb=3, smoother="schwarz", schwarz_overlap=args.schwarz_overlap)),
-                     ("chebyshev_point", dict(n_cheb=4, smoother="point"))):
+    for name, kw in (("schwarz", dict(n_cheb=3, smoother="schwarz", schwarz_overlap=args.schwarz_overlap)),) + others:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         M.setup_smoother(**kw)
@@ -879,10 +895,9 @@ def run_schwarz(args, meshgen, hp):
                                      "avg_us": round(1e3 * ms / n, 2), "alg_bytes_per_launch": b / n}
     M.free()
     res = {"workload": "schwarz",
-           "config": {"mesh": "unit cube, %d^3 affine cells, p = %d" % (2 ** args.schwarz_level, args.schwarz_p),
-                      "dof": N, "problem": "-lap u = 3 pi^2 sin sin sin, u = 0 on the boundary",
-                      "tol": 1e-10, "schwarz_overlap": args.schwarz_overlap, "schwarz_cycles": 3,
-                      "chebyshev_steps": 4, "steps": args.steps, "warmup": args.warmup},
+           "config": {"mesh": label, "dof": N, "problem": problem, "tol": 1e-10,
+                      "schwarz_overlap": args.schwarz_overlap, "schwarz_cycles": 3,
+                      "chebyshev": {k: v for k, v in others}, "steps": args.steps, "warmup": args.warmup},
            **out}
     print(json.dumps(res))
     ctx.close()

@@ -1117,11 +1117,18 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   }
   rocblas_set_stream(M->blas, s);
   // per subdomain size: assemble A_ss (column-major) on the host, invert on the device, pack
-  std::map<int, std::vector<int>> groups;
-  for (int c = 0; c < E; ++c) groups[int(lay.off[c + 1] - lay.off[c])].push_back(c);
-  for (const auto& g : groups) {
+  // (chunks of at most 1 GiB of subdomain matrices)
+  std::map<int, std::vector<std::vector<int>>> groups;
+  for (int c = 0; c < E; ++c) {
+    const int m = int(lay.off[c + 1] - lay.off[c]);
+    const size_t cap = std::max<size_t>(1, (size_t(1) << 30) / (size_t(m) * m * sizeof(double)));
+    std::vector<std::vector<int>>& chunks = groups[m];
+    if (chunks.empty() || chunks.back().size() >= cap) chunks.emplace_back();
+    chunks.back().push_back(c);
+  }
+  for (const auto& g : groups)
+    for (const std::vector<int>& subs : g.second) {
     const int m = g.first;
-    const std::vector<int>& subs = g.second;
     const int cnt = int(subs.size());
     std::vector<double> A(size_t(cnt) * m * m);
     schwarz_assemble(lay, blk, subs, m, A.data());
@@ -1162,7 +1169,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     HIPCHK(hipStreamSynchronize(s));
     for (void* q : {(void*)dA, (void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw})
       M->release(q);
-  }
+    }
   M->release(dw);
 }
 
