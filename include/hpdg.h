@@ -206,9 +206,11 @@ typedef struct {
  *                      shell) the weights covering a point are divided by their sum; so they
  *                      sum to one at every point.  Scope: every smoothed level has one degree,
  *                      one refinement level and faces that meet 1:1, subdomains of at most 8190
- *                      points (HPDG_ERR_UNSUPPORTED at setup otherwise); FP64 only
- *                      (HPDG_ERR_UNSUPPORTED for FP32 smoothing, mixed-precision solves and
- *                      Newton linearisations).  No spectral bound is computed (lambda_max 0). */
+ *                      points (HPDG_ERR_UNSUPPORTED at setup otherwise).  On meshes with FP32
+ *                      levels the stored rows are also kept rounded to FP32, for FP32 smoothing
+ *                      and the FP32 V-cycle of mixed-precision solves.  Not rebuilt for Newton
+ *                      linearisations (HPDG_ERR_UNSUPPORTED).  No spectral bound is computed
+ *                      (lambda_max 0). */
 enum { HPDG_SMOOTH_NONE = 0, HPDG_SMOOTH_POINT = 1, HPDG_SMOOTH_BLOCK = 2, HPDG_SMOOTH_SCHWARZ = 3 };
 typedef struct {
   int32_t n_cheb;        /* Chebyshev steps per smoothing call (default 4) */

@@ -509,7 +509,7 @@ class Mesh:
     def setup_smoother(self, n_cheb=4, n_eigs=15, Lambda=20.0, jacobi=True, seed=0, lambda_max=None,
                        smoother=None, stream=None, n_cheb_coarse=0, fused=True, schwarz_overlap=2):
         """``smoother``: "none", "point", "block" (Chebyshev) or "schwarz" (additive Schwarz
-        with ``n_cheb`` cycles per call and ``schwarz_overlap`` = N_overlap; FP64 only)
+        with ``n_cheb`` cycles per call and ``schwarz_overlap`` = N_overlap; FP64, and FP32 on meshes with FP32 levels)
         (default: "point" if jacobi else "none").
         ``n_cheb_coarse``: Chebyshev steps (Schwarz cycles) on the levels below the finest (0: ``n_cheb``).
         ``fused``: block smoothing on one-degree levels runs the apply and the block step as one

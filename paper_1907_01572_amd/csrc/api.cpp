@@ -176,10 +176,16 @@ struct hpdg_mesh {
     long long *goff = nullptr, *woff = nullptr, *moff = nullptr;
     double* minv = nullptr;
     double* d = nullptr;
+    float* minv32 = nullptr;  // FP32 copies for the FP32 V-cycle (meshes with FP32 levels)
+    float* d32 = nullptr;
     long long* ptr = nullptr;
     int* list = nullptr;
     long long minv_scalars = 0, entries = 0;
-    double alg_bytes = 0;  // of one launch of the local solves
+    double alg_bytes = 0, alg_bytes32 = 0;  // of one launch of the local solves
+    const double* rows(double*) const { return minv; }
+    const float* rows(float*) const { return minv32; }
+    double* corr(double*) const { return d; }
+    float* corr(float*) const { return d32; }
   };
   std::vector<SchwarzDev> sw;
 
@@ -520,24 +526,30 @@ void apply_level_scratch(hpdg_mesh* M, int l, const T* x, T* y, T* trace, T* slo
   level_apply<T>(M, l, V, x, y, s, false);
 }
 
-// Alg. schwarz_smoother on level l (FP64): n_iter times r = b - A x, x += sum_s R_s^T W_s
-// A_ss^-1 R_s r (zero: x == 0 on entry, so the first residual is b)
-void schwarz_smooth(hpdg_mesh* M, int l, const double* b, double* x, int n_iter, bool zero, hipStream_t s) {
+// Alg. schwarz_smoother on level l (FP64, or FP32 with the FP32 copies of the stored rows):
+// n_iter times r = b - A x, x += sum_s R_s^T W_s A_ss^-1 R_s r (zero: x == 0 on entry, so the
+// first residual is b)
+template <typename T>
+void schwarz_smooth(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, hipStream_t s) {
   const hpdg_mesh::SchwarzDev& w = M->sw.at(size_t(l));
   if (!w.minv) throw Error(HPDG_ERR_INVALID_ARG, "Schwarz smoother not set up on this level");
-  DevLevel<double>& d = M->lev<double>(l);
+  const T* rows = w.rows(static_cast<T*>(nullptr));
+  T* corr = w.corr(static_cast<T*>(nullptr));
+  if (!rows) throw Error(HPDG_ERR_UNSUPPORTED, "FP32 Schwarz smoothing needs a mesh built with FP32 levels");
+  DevLevel<T>& d = M->lev<T>(l);
   const long long n = M->H[l].ndof;
+  const int prec = sizeof(T) == 4 ? HPDG_F32 : HPDG_F64;
   for (int k = 0; k < n_iter; ++k) {
-    const double* r = b;
+    const T* r = b;
     if (!(zero && k == 0)) {
-      apply_level<double>(M, l, x, d.t, s);
-      launch_axpby<double>(n, 1.0, b, -1.0, d.t, s);  // t = b - A x
+      apply_level<T>(M, l, x, d.t, s);
+      launch_axpby<T>(n, T(1), b, T(-1), d.t, s);  // t = b - A x
       r = d.t;
     }
-    timed(M, HPDG_TIMING_SCHWARZ, l, HPDG_F64, w.alg_bytes, s, [&] {
-      launch_schwarz_local(w.n_sub, w.max_m, w.max_nw, r, w.gidx, w.goff, w.woff, w.moff, w.minv, w.d, s);
+    timed(M, HPDG_TIMING_SCHWARZ, l, prec, sizeof(T) == 4 ? w.alg_bytes32 : w.alg_bytes, s, [&] {
+      launch_schwarz_local<T>(w.n_sub, w.max_m, w.max_nw, r, w.gidx, w.goff, w.woff, w.moff, rows, corr, s);
     });
-    launch_schwarz_scatter(n, w.ptr, w.list, w.d, x, s);
+    launch_schwarz_scatter<T>(n, w.ptr, w.list, corr, x, s);
   }
 }
 
@@ -545,10 +557,7 @@ void schwarz_smooth(hpdg_mesh* M, int l, const double* b, double* x, int n_iter,
 template <typename T>
 void smooth_level(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero, hipStream_t s) {
   if (M->sp.scaling == HPDG_SMOOTH_SCHWARZ) {
-    if constexpr (std::is_same<T, double>::value)
-      schwarz_smooth(M, l, b, x, n_iter, zero, s);
-    else
-      throw Error(HPDG_ERR_UNSUPPORTED, "the Schwarz smoother runs in FP64 only");
+    schwarz_smooth<T>(M, l, b, x, n_iter, zero, s);
     return;
   }
   DevLevel<T>& d = M->lev<T>(l);
@@ -1093,7 +1102,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       for (int r = 0; r < lay.nw[c]; ++r) list[size_t(fill[size_t(gidx[size_t(lay.off[c] + r)])]++)] = int(woff[c] + r);
   }
   for (void* q : {(void*)W.gidx, (void*)W.goff, (void*)W.woff, (void*)W.moff, (void*)W.ptr, (void*)W.list,
-                  (void*)W.d, (void*)W.minv})
+                  (void*)W.d, (void*)W.minv, (void*)W.minv32, (void*)W.d32})
     if (q) M->release(q);  // a previous overlap's
   W = hpdg_mesh::SchwarzDev{};
   W.n_sub = E;
@@ -1103,6 +1112,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   W.minv_scalars = minv_scalars;
   W.entries = (long long)gidx.size();
   W.alg_bytes = 8.0 * double(alg_scalars) + 12.0 * double(W.entries) + 8.0 * double(nrows) + 24.0 * double(E);
+  W.alg_bytes32 = 4.0 * double(alg_scalars) + 8.0 * double(W.entries) + 4.0 * double(nrows) + 24.0 * double(E);
   W.gidx = M->upload_raw(gidx, s);
   W.goff = M->upload_raw(lay.off, s);
   W.woff = M->upload_raw(woff, s);
@@ -1171,6 +1181,13 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       M->release(q);
     }
   M->release(dw);
+  if (M->has_f32) {  // rounded copies for the FP32 V-cycle
+    W.minv32 = M->alloc<float>(size_t(minv_scalars));
+    W.d32 = M->alloc<float>(size_t(nrows));
+    launch_convert_d2f(minv_scalars, W.minv, W.minv32, s);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+  }
 }
 
 // exact coarse solve: the coarsest operator assembled column by column on the device (one
@@ -1646,8 +1663,6 @@ void setup_smoother_impl(hpdg_mesh* mesh, const hpdg_smoother_params* params, do
 bool krylov_solve(hpdg_mesh* mesh, const hpdg_solve_params& params, const double* b_dev, double* u_dev, int& iters,
                   double& rel, hipStream_t s) {
   const bool mixed = params.precision == HPDG_PREC_MIXED || params.precision == HPDG_PREC_MIXED_BF16;
-  if (mixed && mesh->sp.scaling == HPDG_SMOOTH_SCHWARZ)
-    throw Error(HPDG_ERR_UNSUPPORTED, "the Schwarz smoother runs in FP64 only (HPDG_PREC_F64)");
   mesh->bf16_blocks = params.precision == HPDG_PREC_MIXED_BF16;
   iters = 0;
   rel = 0;

@@ -13,7 +13,6 @@ namespace {
 
 constexpr int kSwBS = 512;   // eight waves per workgroup
 constexpr int kSwRows = 8;   // rows in flight per wave
-typedef double dbl2 __attribute__((ext_vector_type(2)));
 
 // inverse of subdomain s (lower triangle, column-major m x m at P + pofs[b]) -> rows r < nw of
 // W_s A_ss^-1, row-major with the even row stride mp = m + (m & 1) at minv + moff[b] (both
@@ -40,18 +39,32 @@ __global__ void __launch_bounds__(256) schwarz_pack_kernel(int m, int b0, const 
   }
 }
 
+template <typename T>
+struct Pair;
+template <>
+struct Pair<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+template <>
+struct Pair<float> {
+  typedef float type __attribute__((ext_vector_type(2)));
+};
+
 // workgroup (s, c): rows [c rpc, (c + 1) rpc) of subdomain s.  r_s = R_s r is staged in LDS
 // (zero-padded to the even stride), then each wave takes kSwRows rows at a time, its lanes
-// reading the rows in 16-byte pairs (coalesced), and reduces them across the wave
-__global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const double* __restrict__ r,
+// reading the rows in pairs (16 bytes in FP64, 8 in FP32; coalesced, nontemporal: each row is
+// streamed once per cycle), and reduces them across the wave
+template <typename T>
+__global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const T* __restrict__ r,
                                                             const int* __restrict__ gidx,
                                                             const long long* __restrict__ goff,
                                                             const long long* __restrict__ woff,
                                                             const long long* __restrict__ moff,
-                                                            const double* __restrict__ minv,
-                                                            double* __restrict__ d, int rpc) {
+                                                            const T* __restrict__ minv,
+                                                            T* __restrict__ d, int rpc) {
+  typedef typename Pair<T>::type P2;
   extern __shared__ double2 lds2[];  // 16-byte aligned
-  double* rs = reinterpret_cast<double*>(lds2);
+  T* rs = reinterpret_cast<T*>(lds2);
   const int s = blockIdx.x;
   const long long g0 = goff[s];
   const int m = int(goff[s + 1] - g0);
@@ -61,25 +74,25 @@ __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const double* __re
   const int row_begin = blockIdx.y * rpc;
   const int row_end = min(nw, row_begin + rpc);
   if (row_begin >= row_end) return;  // the whole workgroup: no barrier is skipped by part of it
-  for (int k = threadIdx.x; k < mp; k += kSwBS) rs[k] = k < m ? r[gidx[g0 + k]] : 0.0;
+  for (int k = threadIdx.x; k < mp; k += kSwBS) rs[k] = k < m ? r[gidx[g0 + k]] : T(0);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const double2* rs2 = lds2;
-  const double* M = minv + moff[s];
+  const P2* rs2 = reinterpret_cast<const P2*>(rs);
+  const T* M = minv + moff[s];
   const int half = mp >> 1;
   for (int row = row_begin + wave * kSwRows; row < row_end; row += (kSwBS / 64) * kSwRows) {
-    const dbl2* Mr[kSwRows];
+    const P2* Mr[kSwRows];
 #pragma unroll
     for (int q = 0; q < kSwRows; ++q)  // rows past the end read the last row; their sums are dropped
-      Mr[q] = reinterpret_cast<const dbl2*>(M + (long long)min(row + q, row_end - 1) * mp);
-    double acc[kSwRows];
+      Mr[q] = reinterpret_cast<const P2*>(M + (long long)min(row + q, row_end - 1) * mp);
+    T acc[kSwRows];
 #pragma unroll
-    for (int q = 0; q < kSwRows; ++q) acc[q] = 0.0;
+    for (int q = 0; q < kSwRows; ++q) acc[q] = T(0);
     for (int k = lane; k < half; k += 64) {
-      const double2 x = rs2[k];
+      const P2 x = rs2[k];
 #pragma unroll
-      for (int q = 0; q < kSwRows; ++q) {  // streamed once per cycle: nontemporal
-        const dbl2 a = __builtin_nontemporal_load(Mr[q] + k);
+      for (int q = 0; q < kSwRows; ++q) {
+        const P2 a = __builtin_nontemporal_load(Mr[q] + k);
         acc[q] += a.x * x.x + a.y * x.y;
       }
     }
@@ -93,13 +106,13 @@ __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const double* __re
 }
 
 // x_i += sum over the subdomains holding dof i (in subdomain order) of their weighted corrections
+template <typename T>
 __global__ void __launch_bounds__(256) schwarz_scatter_kernel(long long n, const long long* __restrict__ ptr,
                                                             const int* __restrict__ list,
-                                                            const double* __restrict__ d,
-                                                            double* __restrict__ x) {
+                                                            const T* __restrict__ d, T* __restrict__ x) {
   const long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double acc = 0.0;
+  T acc = T(0);
   for (long long k = ptr[i]; k < ptr[i + 1]; ++k) acc += d[list[k]];
   x[i] += acc;
 }
@@ -113,9 +126,9 @@ void launch_schwarz_pack(int m, int count, const double* P, const long long* pof
                        b0, P, pofs, moff, nw, wofs, w, minv);
 }
 
-void launch_schwarz_local(int n_sub, int max_m, int max_nw, const double* r, const int* gidx, const long long* goff,
-                          const long long* woff, const long long* moff, const double* minv, double* d,
-                          hipStream_t s) {
+template <typename T>
+void launch_schwarz_local(int n_sub, int max_m, int max_nw, const T* r, const int* gidx, const long long* goff,
+                          const long long* woff, const long long* moff, const T* minv, T* d, hipStream_t s) {
   if (n_sub <= 0 || max_nw <= 0) return;
   // split the rows of each subdomain over several workgroups when there are few subdomains:
   // about 2048 workgroups (8 per CU), chunks of whole wave passes
@@ -125,15 +138,24 @@ void launch_schwarz_local(int n_sub, int max_m, int max_nw, const double* r, con
   int rpc = (max_nw + chunks - 1) / chunks;
   rpc = (rpc + pass - 1) / pass * pass;
   chunks = (max_nw + rpc - 1) / rpc;
-  const size_t lds = size_t(max_m + (max_m & 1)) * sizeof(double);
-  hipLaunchKernelGGL(schwarz_local_kernel, dim3(unsigned(n_sub), unsigned(chunks)), dim3(kSwBS), lds, s, r, gidx,
+  const size_t lds = size_t(max_m + (max_m & 1)) * sizeof(T);
+  hipLaunchKernelGGL(schwarz_local_kernel<T>, dim3(unsigned(n_sub), unsigned(chunks)), dim3(kSwBS), lds, s, r, gidx,
                      goff, woff, moff, minv, d, rpc);
 }
 
-void launch_schwarz_scatter(long long n, const long long* ptr, const int* list, const double* d, double* x,
-                            hipStream_t s) {
+template <typename T>
+void launch_schwarz_scatter(long long n, const long long* ptr, const int* list, const T* d, T* x, hipStream_t s) {
   if (n <= 0) return;
-  hipLaunchKernelGGL(schwarz_scatter_kernel, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, ptr, list, d, x);
+  hipLaunchKernelGGL(schwarz_scatter_kernel<T>, dim3(unsigned((n + 255) / 256)), dim3(256), 0, s, n, ptr, list, d,
+                     x);
 }
+
+#define HPDG_SW_INST(T)                                                                                        \
+  template void launch_schwarz_local<T>(int, int, int, const T*, const int*, const long long*, const long long*, \
+                                        const long long*, const T*, T*, hipStream_t);                          \
+  template void launch_schwarz_scatter<T>(long long, const long long*, const int*, const T*, T*, hipStream_t);
+HPDG_SW_INST(double)
+HPDG_SW_INST(float)
+#undef HPDG_SW_INST
 
 }  // namespace hpdg

@@ -144,10 +144,48 @@ def test_schwarz_on_the_compactified_shell(ctx):
     M.free()
 
 
+@pytest.mark.parametrize("name", ["cube_l2_p3", "shell_l1_p3_r1e9"])
+def test_schwarz_fp32_and_mixed_solve(ctx, name):
+    # the FP32 V-cycle smooths with FP32 copies of the stored rows: FP32 smoothing cycles and
+    # V-cycles against the FP64 oracle (FP32 rounding of the operator, the rows and the vectors,
+    # the bound of the FP32 Chebyshev V-cycle test), and FP64 FCG around the FP32 V-cycle reaches
+    # 1e-10 (true residual by an FP64 apply) in about the FP64 iterations
+    m = MESHES[name]()
+    prob = PROBLEM.get(name, meshgen.problem_config1())
+    mg = Multigrid(m, prob, n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    op = mg.ops[0]
+    M = ctx.upload(m, coef=coef_of(prob), build_f32=True)
+    M.setup_smoother(n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    perm = dof_perm(M.level_cells(0), m)
+    rng = np.random.default_rng(5)
+    b, x0, r = rng.standard_normal((3, op.ndof))
+    A, subs = mg.schwarz[0]
+    xs = sw.smooth(A, subs, b, x0, 2)
+    x32 = torch.tensor(x0[perm], dtype=torch.float32, device="cuda")
+    M.smooth(torch.tensor(b[perm], dtype=torch.float32, device="cuda"), x32, level=0, n_iter=2)
+    e1 = rel(host(x32).astype(np.float64), xs[perm])
+    z32 = torch.zeros(op.ndof, dtype=torch.float32, device="cuda")
+    M.vcycle(torch.tensor(r[perm], dtype=torch.float32, device="cuda"), z32)
+    e2 = rel(host(z32).astype(np.float64), mg.vcycle(r)[perm])
+    F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    M.assemble_rhs(prob, F)
+    its = {}
+    for prec in (hp.PREC_F64, hp.PREC_MIXED):
+        u = torch.zeros_like(F)
+        st = M.solve(F, u, tol=1e-10, max_iter=100, precision=prec)
+        y = torch.zeros_like(F)
+        M.apply(u, y)
+        its[prec] = (st["iterations"], float(torch.linalg.norm(F - y) / torch.linalg.norm(F)))
+    print(name, "FP32 smooth", e1, "FP32 vcycle", e2, "(iterations, true residual) FP64 / mixed", its, flush=True)
+    assert e1 <= 1e-4 and e2 <= 1e-4
+    assert its[hp.PREC_MIXED][1] <= 1e-10 and its[hp.PREC_MIXED][0] <= its[hp.PREC_F64][0] + 3
+    M.free()
+
+
 def test_schwarz_refusals(ctx):
-    # 2:1 faces and curved elements are outside the smoother's scope; the overlap is at least
-    # one (a larger one than the degree is clamped to it); FP32 smoothing and mixed-precision
-    # solves are refused
+    # 2:1 faces are outside the smoother's scope (the shell with its extra inner refinement, a
+    # refined box); the overlap is at least one (a larger one than the degree is clamped to it);
+    # FP32 smoothing needs FP32 levels
     for mesh in (meshgen.box_grid((2, 1, 1), 1, 3, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
                  meshgen.cubed_sphere_shell(level=1, p=2, r_out=1e3)):
         M = ctx.upload(mesh)
@@ -155,16 +193,13 @@ def test_schwarz_refusals(ctx):
             M.setup_smoother(smoother="schwarz")
         assert ei.value.code == hp.ERR_UNSUPPORTED
         M.free()
-    M = ctx.upload(meshgen.unit_cube(1, 3), build_f32=True)
+    M = ctx.upload(meshgen.unit_cube(1, 3))
     with pytest.raises(hp.HpdgError) as ei:
         M.setup_smoother(smoother="schwarz", schwarz_overlap=0)
     assert ei.value.code == hp.ERR_INVALID_ARG
     M.setup_smoother(smoother="schwarz", schwarz_overlap=9)
     F = torch.ones(M.n_dof[0], dtype=torch.float64, device="cuda")
     u = torch.zeros_like(F)
-    with pytest.raises(hp.HpdgError) as ei:
-        M.solve(F, u, precision=hp.PREC_MIXED)
-    assert ei.value.code == hp.ERR_UNSUPPORTED
     with pytest.raises(hp.HpdgError) as ei:
         M.smooth(F.float(), u.float(), level=0, n_iter=1)
     assert ei.value.code == hp.ERR_UNSUPPORTED
