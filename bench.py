@@ -858,7 +858,7 @@ def run_schwarz(args, meshgen, hp):
         problem = "-lap u = 3 pi^2 sin sin sin, u = 0 on the boundary"
         others = (("chebyshev_point", dict(n_cheb=4, smoother="point")),)
     ctx = hp.Context(0)
-    M = ctx.upload(mesh, coef=hp.coef_from_problem(prob))
+    M = ctx.upload(mesh, coef=hp.coef_from_problem(prob), build_f32=True)
     N = M.n_dof[0]
     F = torch.zeros(N, dtype=torch.float64, device=dev)
     M.assemble_rhs(prob, F)
@@ -886,17 +886,38 @@ def run_schwarz(args, meshgen, hp):
         print("schwarz workload: %s setup %.2f s, %d iterations (%s), %s ms per solve" %
               (name, setup_s, st["iterations"], "converged" if st["status"] == 0 else "status %d" % st["status"],
                out[name]["solve_ms"]), file=sys.stderr, flush=True)
+        if st["status"] == 0:  # the FP32 V-cycle inside FP64 FCG
+            mt = []
+            for k in range(args.warmup + args.steps):
+                u = torch.zeros_like(F)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                stm = M.solve(F, u, tol=1e-10, max_iter=args.max_iter, precision=hp.PREC_MIXED, raise_on_error=False)
+                torch.cuda.synchronize()
+                if k >= args.warmup:
+                    mt.append(time.perf_counter() - t0)
+            out[name]["mixed"] = {"iterations": stm["iterations"], "rel_residual": stm["rel_residual"],
+                                  "converged": stm["status"] == 0, "solve_ms": round(1e3 * float(np.median(mt)), 3)}
+            print("schwarz workload: %s mixed %d iterations, %.3f ms per solve" %
+                  (name, stm["iterations"], out[name]["mixed"]["solve_ms"]), file=sys.stderr, flush=True)
         if name == "schwarz":
             M.timing_enable(1)
             u = torch.zeros_like(F)
             M.solve(F, u, tol=1e-10, max_iter=args.max_iter)
             ms, n, b = M.kernel_timing("schwarz", 0)
+            u = torch.zeros_like(F)
+            M.solve(F, u, tol=1e-10, max_iter=args.max_iter, precision=hp.PREC_MIXED, raise_on_error=False)
+            ms32, n32, b32 = M.kernel_timing("schwarz", 0, hp.F32)
             M.timing_enable(0)
-            gbs = b / n / (ms / n * 1e-3) / 1e9
-            out[name]["roofline"] = {"kernel": "schwarz_local_kernel (level 0)", "bound": "hbm",
-                                     "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                     "frac": round(gbs / HBM_PEAK_GBS, 4), "launches": n,
-                                     "avg_us": round(1e3 * ms / n, 2), "alg_bytes_per_launch": b / n}
+            for key, (t, c, by) in (("roofline", (ms, n, b)), ("roofline_fp32", (ms32, n32, b32))):
+                if c == 0:
+                    continue
+                gbs = by / c / (t / c * 1e-3) / 1e9
+                out[name][key] = {"kernel": "schwarz_local_kernel<%s> (level 0)" % ("float" if key.endswith("32") else
+                                                                                  "double"),
+                                  "bound": "hbm", "achieved": round(gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                  "frac": round(gbs / HBM_PEAK_GBS, 4), "launches": c,
+                                  "avg_us": round(1e3 * t / c, 2), "alg_bytes_per_launch": by / c}
     retries = list(M.setup_retries())
     M.free()
     res = {"workload": "schwarz", "setup_retries": retries,
