@@ -276,3 +276,51 @@ def test_schwarz_full_size_sampled_cycle(ctx):
         assert err <= TOL_SCHWARZ and np.all(outside == 0.0)
         assert ns == (8 if e0 == inner else 4)
     M.free()
+
+
+@pytest.mark.timeout(400)
+def test_schwarz_full_size_sampled_cycle_on_the_compactified_shell(ctx):
+    # the shell configuration of the Schwarz benchmark (6 x 8^3 cells, p = 5, r = 1e9, 663,552
+    # DOF, N_overlap 2): one cycle from x = 0 with a unit right-hand side at a point of a corner
+    # cell of a patch, next to a line where three cells meet (its subdomains: the cell and its
+    # neighbours across two rotated patch faces; weights divided by their sum 3/4), against the
+    # oracle's local solves of those subdomains; zero outside their union
+    m = meshgen.cubed_sphere_shell(level=3, p=5, r_out=1e9, inner_refine=False)
+    prob = meshgen.problem_config2()
+    A = m["elem_anchor"]
+    e0 = int(np.flatnonzero((m["elem_macro"] == 0) & (A[:, 0] == 0) & (A[:, 1] == 0) & (A[:, 2] == 3))[0])
+    op0 = SIPG(m, prob, active=[e0])
+    subs = sw.subdomains_topo(op0, 2)
+    i0 = int(op0.offsets[e0] + 1 + 6 * (1 + 6 * 2))
+    hold = [(idx, w) for idx, w in subs if i0 in idx]
+    U = np.unique(np.concatenate([idx for idx, _ in hold]))
+    op = SIPG(m, prob, active=np.unique(np.searchsorted(op0.offsets, U, side="right") - 1))
+    pos = {int(g): k for k, g in enumerate(U)}
+    A_UU = np.empty((len(U), len(U)))
+    e = np.zeros(op.ndof)
+    for k, j in enumerate(U):
+        e[j] = 1.0
+        A_UU[:, k] = op.apply(e)[U]
+        e[j] = 0.0
+    xo = np.zeros(op.ndof)
+    for idx, w in hold:
+        loc = np.array([pos[int(g)] for g in idx])
+        xo[idx] += w * np.linalg.solve(A_UU[np.ix_(loc, loc)], (idx == i0).astype(float))
+    M = ctx.upload(m, coef=coef_of(prob))
+    M.setup_smoother(n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+    perm = dof_perm(M.level_cells(0), m)
+    inv = np.empty_like(perm)
+    inv[perm] = np.arange(len(perm))
+    b = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+    b[int(inv[i0])] = 1.0
+    x = torch.zeros_like(b)
+    M.smooth(b, x, level=0, n_iter=1)
+    xg = np.empty(op.ndof)
+    xg[perm] = host(x)
+    err = np.linalg.norm(xg[U] - xo[U]) / np.linalg.norm(xo[U])
+    wsum = sum(w[list(idx).index(i0)] for idx, w in hold)
+    print("subdomains", len(hold), "union", len(U), "weights at the point sum to", wsum, "rel err", err,
+          "largest outside", np.abs(np.delete(xg, U)).max(), flush=True)
+    assert len(hold) == 3 and abs(wsum - 1.0) <= 1e-14
+    assert err <= TOL_SCHWARZ_COMPACTIFIED and np.all(np.delete(xg, U) == 0.0)
+    M.free()
