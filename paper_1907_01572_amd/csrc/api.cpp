@@ -1054,31 +1054,41 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     }
   }
   // blocks: element b, slot k (0: b itself, 1 + f: the neighbour across face f), column j, row i
-  auto bidx = [&](int b, int k, int j, int i) { return ((size_t(b) * 7 + k) * n3 + j) * n3 + i; };
-  std::vector<double> blk(size_t(E) * 7 * n3 * n3, 0.0);
+  // (gathered on the device, one colour and column at a time, then copied to the host once)
+  const size_t blk_size = size_t(E) * 7 * n3 * n3;
+  std::vector<double> blk(blk_size);
   {
     DevLevel<double>& d = M->lev<double>(l);
     const LevelView<double> V = M->view<double>(l);
-    std::vector<double> hx(size_t(h.ndof), 0.0), hy(size_t(h.ndof));
-    std::vector<std::vector<int>> members(ncol);
-    for (int e = 0; e < E; ++e) members[color[e]].push_back(e);
-    for (int c = 0; c < ncol; ++c)
+    std::vector<int> members;
+    std::vector<int> cstart(size_t(ncol) + 1, 0);
+    for (int c = 0; c < ncol; ++c) {
+      for (int e = 0; e < E; ++e)
+        if (color[e] == c) members.push_back(e);
+      cstart[c + 1] = int(members.size());
+    }
+    std::vector<long long> eoff(static_cast<size_t>(E));
+    for (int e = 0; e < E; ++e) eoff[e] = h.einfo[e].off;
+    int* dmem = M->upload_raw(members, s);
+    int* dfnb = M->upload_raw(F, s);
+    long long* deoff = M->upload_raw(eoff, s);
+    double* dblk = M->alloc<double>(blk_size);
+    launch_fill<double>((long long)blk_size, 0.0, dblk, s);
+    launch_fill<double>(h.ndof, 0.0, d.f, s);
+    for (int c = 0; c < ncol; ++c) {
+      const int cnt = cstart[c + 1] - cstart[c];
+      const int* mc = dmem + cstart[c];
       for (int j = 0; j < n3; ++j) {
-        for (int b : members[c]) hx[size_t(h.einfo[b].off) + j] = 1.0;
-        HIPCHK(hipMemcpyAsync(d.f, hx.data(), hx.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        launch_schwarz_units(cnt, mc, deoff, j, 1.0, d.f, s);
         level_apply<double>(M, l, V, d.f, d.t, s);
-        HIPCHK(hipMemcpyAsync(hy.data(), d.t, hy.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipStreamSynchronize(s));
-        for (int b : members[c]) {
-          hx[size_t(h.einfo[b].off) + j] = 0.0;
-          for (int k = 0; k < 7; ++k) {
-            const int a = k == 0 ? b : F[size_t(b) * 6 + k - 1];
-            if (a < 0) continue;
-            const double* src = hy.data() + h.einfo[a].off;
-            std::copy(src, src + n3, blk.begin() + bidx(b, k, j, 0));
-          }
-        }
+        launch_schwarz_gather(cnt, mc, dfnb, deoff, n3, j, d.t, dblk, s);
+        launch_schwarz_units(cnt, mc, deoff, j, 0.0, d.f, s);
       }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(blk.data(), dblk, blk_size * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (void* q : {(void*)dmem, (void*)dfnb, (void*)deoff, (void*)dblk}) M->release(q);
   }
   // device layout of the subdomains
   std::vector<int> gidx(lay.elem.size());

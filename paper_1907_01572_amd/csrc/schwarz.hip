@@ -39,6 +39,30 @@ __global__ void __launch_bounds__(256) schwarz_pack_kernel(int m, int b0, const 
   }
 }
 
+// setup: x[off(b) + j] = value for the elements b of one colour
+__global__ void __launch_bounds__(256) schwarz_units_kernel(const int* __restrict__ members, int cnt,
+                                                          const long long* __restrict__ eoff, int j, double value,
+                                                          double* __restrict__ x) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x)
+    x[eoff[members[t]] + j] = value;
+}
+
+// setup: column j of the operator blocks of the elements b of one colour from y = A x (x the
+// unit vectors of schwarz_units_kernel): blk[((b 7 + k) n3 + j) n3 + i] = y[off(a) + i], a = b
+// (k = 0) or the neighbour across face k - 1
+__global__ void __launch_bounds__(256) schwarz_gather_kernel(const int* __restrict__ members,
+                                                           const int* __restrict__ fnb,
+                                                           const long long* __restrict__ eoff, int n3, int j,
+                                                           const double* __restrict__ y, double* __restrict__ blk) {
+  const int b = members[blockIdx.x];
+  const int k = blockIdx.y;
+  const int a = k == 0 ? b : fnb[6 * (long long)b + k - 1];
+  if (a < 0) return;
+  double* dst = blk + ((7 * (long long)b + k) * n3 + j) * (long long)n3;
+  const double* src = y + eoff[a];
+  for (int i = threadIdx.x; i < n3; i += blockDim.x) dst[i] = src[i];
+}
+
 template <typename T>
 struct Pair;
 template <>
@@ -124,6 +148,20 @@ void launch_schwarz_pack(int m, int count, const double* P, const long long* pof
   for (int b0 = 0; b0 < count; b0 += 32768)  // grid y stays below its 65535 limit
     hipLaunchKernelGGL(schwarz_pack_kernel, dim3(64, unsigned(std::min(32768, count - b0))), dim3(256), 0, s, m,
                        b0, P, pofs, moff, nw, wofs, w, minv);
+}
+
+void launch_schwarz_units(int cnt, const int* members, const long long* eoff, int j, double value, double* x,
+                          hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(schwarz_units_kernel, dim3(unsigned(std::min(4096, (cnt + 255) / 256))), dim3(256), 0, s,
+                     members, cnt, eoff, j, value, x);
+}
+
+void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, int n3, int j,
+                           const double* y, double* blk, hipStream_t s) {
+  if (cnt <= 0) return;
+  hipLaunchKernelGGL(schwarz_gather_kernel, dim3(unsigned(cnt), 7), dim3(256), 0, s, members, fnb, eoff, n3, j, y,
+                     blk);
 }
 
 template <typename T>

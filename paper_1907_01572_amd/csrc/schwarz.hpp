@@ -6,6 +6,14 @@
 
 namespace hpdg {
 
+// Setup: unit vectors x[off(b) + j] = value for the cnt elements ``members`` (one colour of a
+// distance-2 colouring of the face graph), and column j of their operator blocks from y = A x:
+// blk[((b 7 + k) n3 + j) n3 + i] = y[off(a) + i], a = b (k = 0) or fnb[6 b + k - 1] (skipped
+// when -1); eoff: each element's dof offset
+void launch_schwarz_units(int cnt, const int* members, const long long* eoff, int j, double value, double* x,
+                          hipStream_t s);
+void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, int n3, int j,
+                           const double* y, double* blk, hipStream_t s);
 // Setup: rows r < nw[b] of W_s A_ss^-1 for the count subdomains of size m whose inverses (lower
 // triangles, column-major) lie at P + pofs[b], written row-major with the even row stride
 // m + (m & 1) (zero pad) at minv + moff[b] (moff even); the weights of the rows at w + wofs[b].
