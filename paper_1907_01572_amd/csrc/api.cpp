@@ -1056,7 +1056,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   // blocks: element b, slot k (0: b itself, 1 + f: the neighbour across face f), column j, row i
   // (gathered on the device, one colour and column at a time, then copied to the host once)
   const size_t blk_size = size_t(E) * 7 * n3 * n3;
-  std::vector<double> blk(blk_size);
+  std::unique_ptr<double[]> blk(new double[blk_size]);  // filled by the copy below
   {
     DevLevel<double>& d = M->lev<double>(l);
     const LevelView<double> V = M->view<double>(l);
@@ -1086,7 +1086,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       }
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(blk.data(), dblk, blk_size * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(blk.get(), dblk, blk_size * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
     for (void* q : {(void*)dmem, (void*)dfnb, (void*)deoff, (void*)dblk}) M->release(q);
   }
@@ -1146,14 +1146,20 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     if (chunks.empty() || chunks.back().size() >= cap) chunks.emplace_back();
     chunks.back().push_back(c);
   }
+  // one host staging buffer (pinned) and one device buffer for the largest chunk, reused
+  size_t stage = 0;
+  for (const auto& g : groups)
+    for (const std::vector<int>& subs : g.second) stage = std::max(stage, subs.size() * size_t(g.first) * g.first);
+  double* hA = nullptr;
+  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hA), stage * sizeof(double), hipHostMallocDefault));
+  std::unique_ptr<double, void (*)(double*)> hA_owner(hA, [](double* q) { (void)hipHostFree(q); });
+  double* dA = M->alloc<double>(stage);
   for (const auto& g : groups)
     for (const std::vector<int>& subs : g.second) {
     const int m = g.first;
     const int cnt = int(subs.size());
-    std::vector<double> A(size_t(cnt) * m * m);
-    schwarz_assemble(lay, blk, subs, m, A.data());
-    double* dA = M->alloc<double>(A.size());
-    HIPCHK(hipMemcpyAsync(dA, A.data(), A.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    schwarz_assemble(lay, blk.get(), subs, m, hA);
+    HIPCHK(hipMemcpyAsync(dA, hA, size_t(cnt) * m * m * sizeof(double), hipMemcpyHostToDevice, s));
     std::vector<double*> ptrs(cnt);
     std::vector<long long> pofs(cnt), gm(cnt), gw(cnt);
     std::vector<int> gnw(cnt);
@@ -1187,9 +1193,9 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     launch_schwarz_pack(m, cnt, dA, dpofs, dgm, dgnw, dgw, dw, W.minv, s);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    for (void* q : {(void*)dA, (void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw})
-      M->release(q);
+    for (void* q : {(void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw}) M->release(q);
     }
+  M->release(dA);
   M->release(dw);
   if (M->has_f32) {  // rounded copies for the FP32 V-cycle
     W.minv32 = M->alloc<float>(size_t(minv_scalars));

@@ -262,7 +262,7 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
   }
 }
 
-void schwarz_assemble(const SchwarzLayout& lay, const std::vector<double>& blk, const std::vector<int>& subs, int m,
+void schwarz_assemble(const SchwarzLayout& lay, const double* blk, const std::vector<int>& subs, int m,
                       double* A) {
   const size_t n3 = size_t(lay.n) * lay.n * lay.n;
   parallel_for(subs.size(), [&](size_t b) {

@@ -219,7 +219,7 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
 // A_ss of the subdomains ``subs`` (all of m points), column-major at A + b m^2, from the operator
 // blocks blk[((e 7 + k) n^3 + j) n^3 + i] = A[(a, i), (e, j)], a = e (k = 0) or the neighbour
 // across face k - 1 of e (zero for pairs that are not face neighbours)
-void schwarz_assemble(const SchwarzLayout& lay, const std::vector<double>& blk, const std::vector<int>& subs, int m,
+void schwarz_assemble(const SchwarzLayout& lay, const double* blk, const std::vector<int>& subs, int m,
                       double* A);
 
 // one-side mortar map: rows of the 1-D matrices along the own face axes
