@@ -176,8 +176,9 @@ struct hpdg_mesh {
     long long *goff = nullptr, *woff = nullptr, *moff = nullptr;
     double* minv = nullptr;
     double* d = nullptr;
-    float* minv32 = nullptr;  // FP32 copies for the FP32 V-cycle (meshes with FP32 levels)
+    float* minv32 = nullptr;  // FP32 copies for the FP32 V-cycle (meshes with FP32 levels), own stride
     float* d32 = nullptr;
+    long long* moff32 = nullptr;
     long long* ptr = nullptr;
     int* list = nullptr;
     long long minv_scalars = 0, entries = 0;
@@ -186,6 +187,8 @@ struct hpdg_mesh {
     const float* rows(float*) const { return minv32; }
     double* corr(double*) const { return d; }
     float* corr(float*) const { return d32; }
+    const long long* offs(double*) const { return moff; }
+    const long long* offs(float*) const { return moff32; }
   };
   std::vector<SchwarzDev> sw;
 
@@ -547,7 +550,8 @@ void schwarz_smooth(hpdg_mesh* M, int l, const T* b, T* x, int n_iter, bool zero
       r = d.t;
     }
     timed(M, HPDG_TIMING_SCHWARZ, l, prec, sizeof(T) == 4 ? w.alg_bytes32 : w.alg_bytes, s, [&] {
-      launch_schwarz_local<T>(w.n_sub, w.max_m, w.max_nw, r, w.gidx, w.goff, w.woff, w.moff, rows, corr, s);
+      launch_schwarz_local<T>(w.n_sub, w.max_m, w.max_nw, r, w.gidx, w.goff, w.woff, w.offs(static_cast<T*>(nullptr)),
+                              rows, corr, s);
     });
     launch_schwarz_scatter<T>(n, w.ptr, w.list, corr, x, s);
   }
@@ -1017,16 +1021,17 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   const int E = int(h.cells.size());
   const int n = lay.n, n3 = n * n * n;
   int max_m = 0, max_nw = 0;
-  long long minv_scalars = 0, alg_scalars = 0, nrows = 0;
+  long long minv_scalars = 0, minv32_scalars = 0, alg_scalars = 0, nrows = 0;
   for (int c = 0; c < E; ++c) {
     const int m = int(lay.off[c + 1] - lay.off[c]);
     max_m = std::max(max_m, m);
     max_nw = std::max(max_nw, lay.nw[c]);
-    minv_scalars += (long long)lay.nw[c] * (m + (m & 1));  // rows padded to an even stride
+    minv_scalars += (long long)lay.nw[c] * schwarz_stride(m, 8);  // rows padded to the vector width
+    minv32_scalars += (long long)lay.nw[c] * schwarz_stride(m, 4);
     alg_scalars += (long long)lay.nw[c] * m;
     nrows += lay.nw[c];
   }
-  if (size_t(max_m + (max_m & 1)) * sizeof(double) > 64 * 1024)
+  if (size_t(schwarz_stride(max_m, 8)) * sizeof(double) > 64 * 1024)
     throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomains of more than 8190 points");
   const double blk_bytes = double(E) * 7.0 * double(n3) * double(n3) * sizeof(double);
   if (blk_bytes > 16.0 * (1ull << 30)) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz setup: operator blocks above 16 GiB");
@@ -1093,12 +1098,13 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   // device layout of the subdomains
   std::vector<int> gidx(lay.elem.size());
   for (size_t k = 0; k < gidx.size(); ++k) gidx[k] = int(h.einfo[lay.elem[k]].off + lay.loc[k]);
-  std::vector<long long> woff(size_t(E) + 1, 0), moff(size_t(E) + 1, 0);
+  std::vector<long long> woff(size_t(E) + 1, 0), moff(size_t(E) + 1, 0), moff32(size_t(E) + 1, 0);
   std::vector<double> wrow(static_cast<size_t>(nrows));
   for (int c = 0; c < E; ++c) {
     const int m = int(lay.off[c + 1] - lay.off[c]);
     woff[c + 1] = woff[c] + lay.nw[c];
-    moff[c + 1] = moff[c] + (long long)lay.nw[c] * (m + (m & 1));
+    moff[c + 1] = moff[c] + (long long)lay.nw[c] * schwarz_stride(m, 8);
+    moff32[c + 1] = moff32[c] + (long long)lay.nw[c] * schwarz_stride(m, 4);
     for (int r = 0; r < lay.nw[c]; ++r) wrow[size_t(woff[c] + r)] = lay.w[size_t(lay.off[c] + r)];
   }
   std::vector<long long> ptr(size_t(h.ndof) + 1, 0);
@@ -1112,7 +1118,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       for (int r = 0; r < lay.nw[c]; ++r) list[size_t(fill[size_t(gidx[size_t(lay.off[c] + r)])]++)] = int(woff[c] + r);
   }
   for (void* q : {(void*)W.gidx, (void*)W.goff, (void*)W.woff, (void*)W.moff, (void*)W.ptr, (void*)W.list,
-                  (void*)W.d, (void*)W.minv, (void*)W.minv32, (void*)W.d32})
+                  (void*)W.d, (void*)W.minv, (void*)W.minv32, (void*)W.d32, (void*)W.moff32})
     if (q) M->release(q);  // a previous overlap's
   W = hpdg_mesh::SchwarzDev{};
   W.n_sub = E;
@@ -1131,6 +1137,11 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   W.list = M->upload_raw(list, s);
   W.d = M->alloc<double>(size_t(nrows));
   W.minv = M->alloc<double>(size_t(minv_scalars));
+  if (M->has_f32) {  // rounded copies for the FP32 V-cycle, packed from the same inverses
+    W.moff32 = M->upload_raw(moff32, s);
+    W.minv32 = M->alloc<float>(size_t(minv32_scalars));
+    W.d32 = M->alloc<float>(size_t(nrows));
+  }
   double* dw = M->upload_raw(wrow, s);
   if (!M->blas) {
     if (rocblas_create_handle(&M->blas) != rocblas_status_success) throw Error(HPDG_ERR_HIP, "rocblas handle");
@@ -1161,12 +1172,13 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     schwarz_assemble(lay, blk.get(), subs, m, hA);
     HIPCHK(hipMemcpyAsync(dA, hA, size_t(cnt) * m * m * sizeof(double), hipMemcpyHostToDevice, s));
     std::vector<double*> ptrs(cnt);
-    std::vector<long long> pofs(cnt), gm(cnt), gw(cnt);
+    std::vector<long long> pofs(cnt), gm(cnt), gm32(cnt), gw(cnt);
     std::vector<int> gnw(cnt);
     for (int b = 0; b < cnt; ++b) {
       ptrs[b] = dA + size_t(b) * m * m;
       pofs[b] = (long long)b * m * m;
       gm[b] = moff[subs[b]];
+      gm32[b] = moff32[subs[b]];
       gw[b] = woff[subs[b]];
       gnw[b] = lay.nw[subs[b]];
     }
@@ -1190,20 +1202,20 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     long long* dgm = M->upload_raw(gm, s);
     long long* dgw = M->upload_raw(gw, s);
     int* dgnw = M->upload_raw(gnw, s);
-    launch_schwarz_pack(m, cnt, dA, dpofs, dgm, dgnw, dgw, dw, W.minv, s);
+    launch_schwarz_pack<double>(m, cnt, dA, dpofs, dgm, dgnw, dgw, dw, W.minv, s);
+    long long* dgm32 = nullptr;
+    if (W.minv32) {
+      dgm32 = M->upload_raw(gm32, s);
+      launch_schwarz_pack<float>(m, cnt, dA, dpofs, dgm32, dgnw, dgw, dw, W.minv32, s);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    for (void* q : {(void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw}) M->release(q);
+    for (void* q : {(void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw, (void*)dgm32})
+      if (q) M->release(q);
     }
   M->release(dA);
   M->release(dw);
-  if (M->has_f32) {  // rounded copies for the FP32 V-cycle
-    W.minv32 = M->alloc<float>(size_t(minv_scalars));
-    W.d32 = M->alloc<float>(size_t(nrows));
-    launch_convert_d2f(minv_scalars, W.minv, W.minv32, s);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(s));
-  }
+
 }
 
 // exact coarse solve: the coarsest operator assembled column by column on the device (one

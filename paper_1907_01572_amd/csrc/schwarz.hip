@@ -14,28 +14,36 @@ namespace {
 constexpr int kSwBS = 512;   // eight waves per workgroup
 constexpr int kSwRows = 8;   // rows in flight per wave
 
+// row stride of the stored rows of a subdomain of m points in type T: m rounded up to the
+// 16-byte vector width (2 doubles, 4 floats)
+template <typename T>
+__host__ __device__ inline int sw_stride(int m) {
+  constexpr int vw = 16 / int(sizeof(T));
+  return (m + vw - 1) / vw * vw;
+}
+
 // inverse of subdomain s (lower triangle, column-major m x m at P + pofs[b]) -> rows r < nw of
-// W_s A_ss^-1, row-major with the even row stride mp = m + (m & 1) at minv + moff[b] (both
-// triangles; the pad column zero)
+// W_s A_ss^-1 in type T, row-major with the stride sw_stride<T>(m) at minv + moff[b] (both
+// triangles; the pad columns zero)
+template <typename T>
 __global__ void __launch_bounds__(256) schwarz_pack_kernel(int m, int b0, const double* __restrict__ P,
                                                          const long long* __restrict__ pofs,
                                                          const long long* __restrict__ moff,
                                                          const int* __restrict__ nw,
                                                          const long long* __restrict__ wofs,
-                                                         const double* __restrict__ w,
-                                                         double* __restrict__ minv) {
+                                                         const double* __restrict__ w, T* __restrict__ minv) {
   const int b = b0 + blockIdx.y;
-  const int mp = m + (m & 1);
+  const int mp = sw_stride<T>(m);
   const double* Pb = P + pofs[b];
   const long long total = (long long)nw[b] * mp;
-  double* out = minv + moff[b];
+  T* out = minv + moff[b];
   const double* wb = w + wofs[b];
   for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < total;
        t += (long long)gridDim.x * blockDim.x) {
     const int r = int(t / mp), k = int(t - (long long)r * mp);
     double v = 0.0;
     if (k < m) v = r >= k ? Pb[r + (long long)k * m] : Pb[k + (long long)r * m];
-    out[t] = wb[r] * v;
+    out[t] = T(wb[r] * v);
   }
 }
 
@@ -64,20 +72,22 @@ __global__ void __launch_bounds__(256) schwarz_gather_kernel(const int* __restri
 }
 
 template <typename T>
-struct Pair;
+struct Vec16;
 template <>
-struct Pair<double> {
+struct Vec16<double> {
   typedef double type __attribute__((ext_vector_type(2)));
+  static __device__ inline double dot(type a, type x) { return a.x * x.x + a.y * x.y; }
 };
 template <>
-struct Pair<float> {
-  typedef float type __attribute__((ext_vector_type(2)));
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  static __device__ inline float dot(type a, type x) { return a.x * x.x + a.y * x.y + a.z * x.z + a.w * x.w; }
 };
 
 // workgroup (s, c): rows [c rpc, (c + 1) rpc) of subdomain s.  r_s = R_s r is staged in LDS
-// (zero-padded to the even stride), then each wave takes kSwRows rows at a time, its lanes
-// reading the rows in pairs (16 bytes in FP64, 8 in FP32; coalesced, nontemporal: each row is
-// streamed once per cycle), and reduces them across the wave
+// (zero-padded to the row stride), then each wave takes kSwRows rows at a time, its lanes
+// reading the rows in 16-byte vectors (2 doubles or 4 floats; coalesced, nontemporal: each row
+// is streamed once per cycle), and reduces them across the wave
 template <typename T>
 __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const T* __restrict__ r,
                                                             const int* __restrict__ gidx,
@@ -86,13 +96,14 @@ __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const T* __restric
                                                             const long long* __restrict__ moff,
                                                             const T* __restrict__ minv,
                                                             T* __restrict__ d, int rpc) {
-  typedef typename Pair<T>::type P2;
+  typedef typename Vec16<T>::type V;
+  constexpr int vw = 16 / int(sizeof(T));
   extern __shared__ double2 lds2[];  // 16-byte aligned
   T* rs = reinterpret_cast<T*>(lds2);
   const int s = blockIdx.x;
   const long long g0 = goff[s];
   const int m = int(goff[s + 1] - g0);
-  const int mp = m + (m & 1);
+  const int mp = sw_stride<T>(m);
   const long long w0 = woff[s];
   const int nw = int(woff[s + 1] - w0);
   const int row_begin = blockIdx.y * rpc;
@@ -101,24 +112,21 @@ __global__ void __launch_bounds__(kSwBS) schwarz_local_kernel(const T* __restric
   for (int k = threadIdx.x; k < mp; k += kSwBS) rs[k] = k < m ? r[gidx[g0 + k]] : T(0);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const P2* rs2 = reinterpret_cast<const P2*>(rs);
+  const V* rsv = reinterpret_cast<const V*>(rs);
   const T* M = minv + moff[s];
-  const int half = mp >> 1;
+  const int nv = mp / vw;
   for (int row = row_begin + wave * kSwRows; row < row_end; row += (kSwBS / 64) * kSwRows) {
-    const P2* Mr[kSwRows];
+    const V* Mr[kSwRows];
 #pragma unroll
     for (int q = 0; q < kSwRows; ++q)  // rows past the end read the last row; their sums are dropped
-      Mr[q] = reinterpret_cast<const P2*>(M + (long long)min(row + q, row_end - 1) * mp);
+      Mr[q] = reinterpret_cast<const V*>(M + (long long)min(row + q, row_end - 1) * mp);
     T acc[kSwRows];
 #pragma unroll
     for (int q = 0; q < kSwRows; ++q) acc[q] = T(0);
-    for (int k = lane; k < half; k += 64) {
-      const P2 x = rs2[k];
+    for (int k = lane; k < nv; k += 64) {
+      const V x = rsv[k];
 #pragma unroll
-      for (int q = 0; q < kSwRows; ++q) {
-        const P2 a = __builtin_nontemporal_load(Mr[q] + k);
-        acc[q] += a.x * x.x + a.y * x.y;
-      }
+      for (int q = 0; q < kSwRows; ++q) acc[q] += Vec16<T>::dot(__builtin_nontemporal_load(Mr[q] + k), x);
     }
 #pragma unroll
     for (int q = 0; q < kSwRows; ++q)
@@ -143,12 +151,15 @@ __global__ void __launch_bounds__(256) schwarz_scatter_kernel(long long n, const
 
 }  // namespace
 
+template <typename T>
 void launch_schwarz_pack(int m, int count, const double* P, const long long* pofs, const long long* moff,
-                         const int* nw, const long long* wofs, const double* w, double* minv, hipStream_t s) {
+                         const int* nw, const long long* wofs, const double* w, T* minv, hipStream_t s) {
   for (int b0 = 0; b0 < count; b0 += 32768)  // grid y stays below its 65535 limit
-    hipLaunchKernelGGL(schwarz_pack_kernel, dim3(64, unsigned(std::min(32768, count - b0))), dim3(256), 0, s, m,
+    hipLaunchKernelGGL(schwarz_pack_kernel<T>, dim3(64, unsigned(std::min(32768, count - b0))), dim3(256), 0, s, m,
                        b0, P, pofs, moff, nw, wofs, w, minv);
 }
+
+int schwarz_stride(int m, int scalar_bytes) { return scalar_bytes == 4 ? sw_stride<float>(m) : sw_stride<double>(m); }
 
 void launch_schwarz_units(int cnt, const int* members, const long long* eoff, int j, double value, double* x,
                           hipStream_t s) {
@@ -176,7 +187,7 @@ void launch_schwarz_local(int n_sub, int max_m, int max_nw, const T* r, const in
   int rpc = (max_nw + chunks - 1) / chunks;
   rpc = (rpc + pass - 1) / pass * pass;
   chunks = (max_nw + rpc - 1) / rpc;
-  const size_t lds = size_t(max_m + (max_m & 1)) * sizeof(T);
+  const size_t lds = size_t(sw_stride<T>(max_m)) * sizeof(T);
   hipLaunchKernelGGL(schwarz_local_kernel<T>, dim3(unsigned(n_sub), unsigned(chunks)), dim3(kSwBS), lds, s, r, gidx,
                      goff, woff, moff, minv, d, rpc);
 }
@@ -189,6 +200,8 @@ void launch_schwarz_scatter(long long n, const long long* ptr, const int* list, 
 }
 
 #define HPDG_SW_INST(T)                                                                                        \
+  template void launch_schwarz_pack<T>(int, int, const double*, const long long*, const long long*, const int*,  \
+                                       const long long*, const double*, T*, hipStream_t);                        \
   template void launch_schwarz_local<T>(int, int, int, const T*, const int*, const long long*, const long long*, \
                                         const long long*, const T*, T*, hipStream_t);                          \
   template void launch_schwarz_scatter<T>(long long, const long long*, const int*, const T*, T*, hipStream_t);

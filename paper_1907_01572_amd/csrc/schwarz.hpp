@@ -14,11 +14,16 @@ void launch_schwarz_units(int cnt, const int* members, const long long* eoff, in
                           hipStream_t s);
 void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, int n3, int j,
                            const double* y, double* blk, hipStream_t s);
+// row stride of the stored rows of a subdomain of m points for scalars of scalar_bytes bytes: m
+// rounded up to the 16-byte vector width (2 doubles, 4 floats)
+int schwarz_stride(int m, int scalar_bytes);
 // Setup: rows r < nw[b] of W_s A_ss^-1 for the count subdomains of size m whose inverses (lower
-// triangles, column-major) lie at P + pofs[b], written row-major with the even row stride
-// m + (m & 1) (zero pad) at minv + moff[b] (moff even); the weights of the rows at w + wofs[b].
+// triangles, column-major) lie at P + pofs[b], written row-major in type T with the row stride
+// schwarz_stride(m, sizeof(T)) (zero pad) at minv + moff[b] (moff a multiple of the vector
+// width); the weights of the rows at w + wofs[b].
+template <typename T>
 void launch_schwarz_pack(int m, int count, const double* P, const long long* pofs, const long long* moff,
-                         const int* nw, const long long* wofs, const double* w, double* minv, hipStream_t s);
+                         const int* nw, const long long* wofs, const double* w, T* minv, hipStream_t s);
 // Smoothing (T = double, or float for the FP32 V-cycle with FP32 copies of the rows): per
 // subdomain s (entries goff[s] .. goff[s + 1] with global dofs gidx, the first
 // woff[s + 1] - woff[s] of them weighted) d[woff[s] + r] = (W_s A_ss^-1 R_s r)_r; max_m is the
