@@ -557,9 +557,9 @@ int hpdg_server_destroy(hpdg_server* server);
  *   the first step is not timed): the
  *   apply's bytes without the y write, plus the packed blocks (point Jacobi: s N, the inverse
  *   diagonal) and s N per vector (b, p, x written, p read after the first step);
- *   Schwarz local solves: 8 sum_s m_w,s m_s (the stored rows) + 12 sum_s m_s (gathered
- *   residual and its indices) + 8 sum_s m_w,s (corrections written) + 24 per subdomain
- *   (its offsets).
+ *   Schwarz local solves: s sum_s m_w,s m_s (the stored rows) + (s + 4) sum_s m_s (gathered
+ *   residual and its indices) + s sum_s m_w,s (corrections written) + 24 per subdomain (its
+ *   offsets).
  * (s = 8 for HPDG_F64, 4 for HPDG_F32; N = level DOF.)  hpdg_kernel_timing() waits for
  * the recorded events and returns, for one (kind, level, prec), the summed event time in
  * ms, the number of launches and the summed algorithmic bytes since the previous read of
