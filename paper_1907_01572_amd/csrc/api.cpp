@@ -1059,9 +1059,9 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     }
   }
   // blocks: element b, slot k (0: b itself, 1 + f: the neighbour across face f), column j, row i
-  // (gathered on the device, one colour and column at a time, then copied to the host once)
+  // (gathered on the device, one colour and column at a time; kept there for the assembly)
   const size_t blk_size = size_t(E) * 7 * n3 * n3;
-  std::unique_ptr<double[]> blk(new double[blk_size]);  // filled by the copy below
+  double* dblk = nullptr;
   {
     DevLevel<double>& d = M->lev<double>(l);
     const LevelView<double> V = M->view<double>(l);
@@ -1077,7 +1077,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     int* dmem = M->upload_raw(members, s);
     int* dfnb = M->upload_raw(F, s);
     long long* deoff = M->upload_raw(eoff, s);
-    double* dblk = M->alloc<double>(blk_size);
+    dblk = M->alloc<double>(blk_size);
     launch_fill<double>((long long)blk_size, 0.0, dblk, s);
     launch_fill<double>(h.ndof, 0.0, d.f, s);
     for (int c = 0; c < ncol; ++c) {
@@ -1091,9 +1091,8 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       }
     }
     HIPCHK(hipGetLastError());
-    HIPCHK(hipMemcpyAsync(blk.get(), dblk, blk_size * sizeof(double), hipMemcpyDeviceToHost, s));
     HIPCHK(hipStreamSynchronize(s));
-    for (void* q : {(void*)dmem, (void*)dfnb, (void*)deoff, (void*)dblk}) M->release(q);
+    for (void* q : {(void*)dmem, (void*)dfnb, (void*)deoff}) M->release(q);
   }
   // device layout of the subdomains
   std::vector<int> gidx(lay.elem.size());
@@ -1157,20 +1156,27 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     if (chunks.empty() || chunks.back().size() >= cap) chunks.emplace_back();
     chunks.back().push_back(c);
   }
-  // one host staging buffer (pinned) and one device buffer for the largest chunk, reused
+  // one device buffer for the largest chunk, reused; A_ss assembled on the device from the blocks
   size_t stage = 0;
   for (const auto& g : groups)
     for (const std::vector<int>& subs : g.second) stage = std::max(stage, subs.size() * size_t(g.first) * g.first);
-  double* hA = nullptr;
-  HIPCHK(hipHostMalloc(reinterpret_cast<void**>(&hA), stage * sizeof(double), hipHostMallocDefault));
-  std::unique_ptr<double, void (*)(double*)> hA_owner(hA, [](double* q) { (void)hipHostFree(q); });
   double* dA = M->alloc<double>(stage);
+  std::vector<unsigned char> lel;
+  std::vector<int> els;
+  std::vector<signed char> slot;
+  schwarz_tables(lay, lel, els, slot);
+  std::vector<short> loc16(lay.loc.begin(), lay.loc.end());  // local indices < n^3 <= 4096
+  unsigned char* dlel = M->upload_raw(lel, s);
+  short* dloc = M->upload_raw(loc16, s);
+  int* dels = M->upload_raw(els, s);
+  signed char* dslot = M->upload_raw(slot, s);
   for (const auto& g : groups)
     for (const std::vector<int>& subs : g.second) {
     const int m = g.first;
     const int cnt = int(subs.size());
-    schwarz_assemble(lay, blk.get(), subs, m, hA);
-    HIPCHK(hipMemcpyAsync(dA, hA, size_t(cnt) * m * m * sizeof(double), hipMemcpyHostToDevice, s));
+    int* dsubs = M->upload_raw(subs, s);
+    launch_schwarz_assemble(m, cnt, dsubs, W.goff, dlel, dloc, dels, dslot, n3, dblk, dA, s);
+    HIPCHK(hipGetLastError());
     std::vector<double*> ptrs(cnt);
     std::vector<long long> pofs(cnt), gm(cnt), gm32(cnt), gw(cnt);
     std::vector<int> gnw(cnt);
@@ -1210,10 +1216,11 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    for (void* q : {(void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw, (void*)dgm32})
+    for (void* q : {(void*)dptrs, (void*)info, (void*)dpofs, (void*)dgm, (void*)dgw, (void*)dgnw, (void*)dgm32,
+                    (void*)dsubs})
       if (q) M->release(q);
     }
-  M->release(dA);
+  for (void* q : {(void*)dA, (void*)dblk, (void*)dlel, (void*)dloc, (void*)dels, (void*)dslot}) M->release(q);
   M->release(dw);
 
 }

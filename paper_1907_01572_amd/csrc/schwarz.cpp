@@ -262,41 +262,36 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
   }
 }
 
-void schwarz_assemble(const SchwarzLayout& lay, const double* blk, const std::vector<int>& subs, int m,
-                      double* A) {
-  const size_t n3 = size_t(lay.n) * lay.n * lay.n;
-  parallel_for(subs.size(), [&](size_t b) {
-    const int c = subs[b];
-    const long long o = lay.off[c];
-    // the subdomain's distinct elements and, per ordered pair, the block slot (or -1)
-    std::vector<int> els, lel(static_cast<size_t>(m));
-    for (int p = 0; p < m; ++p) {
+void schwarz_tables(const SchwarzLayout& lay, std::vector<unsigned char>& lel, std::vector<int>& els,
+                    std::vector<signed char>& slot) {
+  const size_t E = lay.nw.size();
+  lel.assign(lay.elem.size(), 0);
+  els.assign(E * 27, -1);
+  slot.assign(E * 27 * 27, -1);
+  parallel_for(E, [&](size_t c) {
+    const long long o = lay.off[c], m = lay.off[c + 1] - o;
+    int* ec = els.data() + c * 27;
+    int ne = 0;
+    for (long long p = 0; p < m; ++p) {
       const int e = lay.elem[size_t(o + p)];
-      size_t k = 0;
-      while (k < els.size() && els[k] != e) ++k;
-      if (k == els.size()) els.push_back(e);
-      lel[size_t(p)] = int(k);
+      int k = 0;
+      while (k < ne && ec[k] != e) ++k;
+      if (k == ne) {
+        if (ne == 27) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomain of more than 27 elements");
+        ec[ne++] = e;
+      }
+      lel[size_t(o + p)] = static_cast<unsigned char>(k);
     }
-    const size_t ne = els.size();
-    std::vector<int> slot(ne * ne, -1);  // [column element][row element]
-    for (size_t jb = 0; jb < ne; ++jb)
-      for (size_t ia = 0; ia < ne; ++ia) {
+    signed char* sc = slot.data() + c * 27 * 27;
+    for (int jb = 0; jb < ne; ++jb)
+      for (int ia = 0; ia < ne; ++ia) {
         if (ia == jb) {
-          slot[jb * ne + ia] = 0;
+          sc[jb * 27 + ia] = 0;
           continue;
         }
         for (int f = 0; f < 6; ++f)
-          if (lay.fnb[size_t(els[jb]) * 6 + f] == els[ia]) slot[jb * ne + ia] = 1 + f;
+          if (lay.fnb[size_t(ec[jb]) * 6 + f] == ec[ia]) sc[jb * 27 + ia] = static_cast<signed char>(1 + f);
       }
-    double* Ab = A + b * size_t(m) * m;
-    for (int q = 0; q < m; ++q) {
-      const size_t eq = size_t(lel[size_t(q)]);
-      const size_t col = (size_t(els[eq]) * 7) * n3 * n3 + size_t(lay.loc[size_t(o + q)]) * n3;
-      for (int p = 0; p < m; ++p) {
-        const int k = slot[eq * ne + size_t(lel[size_t(p)])];
-        Ab[size_t(p) + size_t(q) * m] = k < 0 ? 0.0 : blk[col + size_t(k) * n3 * n3 + size_t(lay.loc[size_t(o + p)])];
-      }
-    }
   });
 }
 

@@ -71,6 +71,30 @@ __global__ void __launch_bounds__(256) schwarz_gather_kernel(const int* __restri
   for (int i = threadIdx.x; i < n3; i += blockDim.x) dst[i] = src[i];
 }
 
+// setup: A_ss of the subdomains subs[b] (m points each), column-major at A + b m^2, from the
+// operator blocks blk[((e 7 + k) n3 + j) n3 + i] through the assembly tables; one workgroup per
+// column
+__global__ void __launch_bounds__(256) schwarz_assemble_kernel(int m, const int* __restrict__ subs,
+                                                             const long long* __restrict__ goff,
+                                                             const unsigned char* __restrict__ lel,
+                                                             const short* __restrict__ loc,
+                                                             const int* __restrict__ els,
+                                                             const signed char* __restrict__ slot, int n3,
+                                                             const double* __restrict__ blk,
+                                                             double* __restrict__ A) {
+  const int b = blockIdx.y, q = blockIdx.x;
+  const int c = subs[b];
+  const long long o = goff[c];
+  const int eq = lel[o + q];
+  const long long col = ((7 * (long long)els[27 * (long long)c + eq]) * n3 + loc[o + q]) * (long long)n3;
+  const signed char* sc = slot + 729 * (long long)c + 27 * eq;
+  double* out = A + (long long)b * m * m + (long long)q * m;
+  for (int p = threadIdx.x; p < m; p += blockDim.x) {
+    const int k = sc[lel[o + p]];
+    out[p] = k < 0 ? 0.0 : blk[col + (long long)k * n3 * n3 + loc[o + p]];
+  }
+}
+
 template <typename T>
 struct Vec16;
 template <>
@@ -173,6 +197,14 @@ void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const lo
   if (cnt <= 0) return;
   hipLaunchKernelGGL(schwarz_gather_kernel, dim3(unsigned(cnt), 7), dim3(256), 0, s, members, fnb, eoff, n3, j, y,
                      blk);
+}
+
+void launch_schwarz_assemble(int m, int cnt, const int* subs, const long long* goff, const unsigned char* lel,
+                             const short* loc, const int* els, const signed char* slot, int n3, const double* blk,
+                             double* A, hipStream_t s) {
+  for (int b0 = 0; b0 < cnt; b0 += 32768)  // grid y stays below its 65535 limit
+    hipLaunchKernelGGL(schwarz_assemble_kernel, dim3(unsigned(m), unsigned(std::min(32768, cnt - b0))), dim3(256), 0,
+                       s, m, subs + b0, goff, lel, loc, els, slot, n3, blk, A + (long long)b0 * m * m);
 }
 
 template <typename T>

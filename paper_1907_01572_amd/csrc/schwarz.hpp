@@ -14,6 +14,12 @@ void launch_schwarz_units(int cnt, const int* members, const long long* eoff, in
                           hipStream_t s);
 void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, int n3, int j,
                            const double* y, double* blk, hipStream_t s);
+// Setup: A_ss of the cnt subdomains subs[b] of m points each, column-major at A + b m^2, from the
+// operator blocks blk[((e 7 + k) n3 + j) n3 + i] through the tables of schwarz_tables (lel and
+// loc per entry at goff[subs[b]], els 27 and slot 27 x 27 per subdomain)
+void launch_schwarz_assemble(int m, int cnt, const int* subs, const long long* goff, const unsigned char* lel,
+                             const short* loc, const int* els, const signed char* slot, int n3, const double* blk,
+                             double* A, hipStream_t s);
 // row stride of the stored rows of a subdomain of m points for scalars of scalar_bytes bytes: m
 // rounded up to the 16-byte vector width (2 doubles, 4 floats)
 int schwarz_stride(int m, int scalar_bytes);

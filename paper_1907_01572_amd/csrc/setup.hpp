@@ -216,11 +216,13 @@ struct SchwarzLayout {
   int n = 0;                      // LGL nodes per axis
 };
 void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out);
-// A_ss of the subdomains ``subs`` (all of m points), column-major at A + b m^2, from the operator
-// blocks blk[((e 7 + k) n^3 + j) n^3 + i] = A[(a, i), (e, j)], a = e (k = 0) or the neighbour
-// across face k - 1 of e (zero for pairs that are not face neighbours)
-void schwarz_assemble(const SchwarzLayout& lay, const double* blk, const std::vector<int>& subs, int m,
-                      double* A);
+// Assembly tables of the subdomains: per entry, the index of its element among the subdomain's
+// elements (lel); per subdomain, those elements (els, 27 per subdomain, -1 past the last) and,
+// per ordered pair (column element, row element), the operator block holding their coupling
+// (slot, 27 x 27 per subdomain: 0 the element itself, 1 + f its neighbour across face f, -1
+// none: the pair is not coupled)
+void schwarz_tables(const SchwarzLayout& lay, std::vector<unsigned char>& lel, std::vector<int>& els,
+                    std::vector<signed char>& slot);
 
 // one-side mortar map: rows of the 1-D matrices along the own face axes
 struct SideMap {
