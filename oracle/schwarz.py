@@ -24,8 +24,10 @@ the lower side): no other subdomain shares the points there, and the weights of 
 then sum to one at every point.
 
 ``subdomains_topo`` builds the same subdomains from the mesh topology alone, for any macro
-maps and face orientations (one degree, one level, no 2:1 faces): a neighbour's points are
+maps and face orientations and any degrees (one level, no 2:1 faces): a neighbour's points are
 placed in e_c's extended coordinates by the composed maps of the faces crossed to reach it.
+Where degrees differ across a face the subdomains are ragged; each face takes the narrower of
+its two sides' overlap widths.
 On the six-patch shell three cells meet around the radial lines through the cube's corners;
 there the subdomains cover three quadrants instead of four and their weights sum to 3/4, so
 they are divided by their sum wherever it is not one.
@@ -49,17 +51,22 @@ def phi(t):
     return np.where(np.abs(t) > 1.0, np.sign(t), (15.0 * t - 10.0 * t ** 3 + 3.0 * t ** 5) / 8.0)
 
 
-def weight_1d(xi, delta, lower_open=True, upper_open=True):
-    """w(xi) of Eq. schwarz_weight with overlap width delta (delta = 0: the step limit).  A side
-    that is not open (a domain-boundary side) keeps the weight at its plateau."""
+def weight_sides(xi, delta_lo, delta_hi, lower_open=True, upper_open=True):
+    """w(xi) of Eq. schwarz_weight with the overlap width delta_lo on the lower and delta_hi on the
+    upper side (a width 0: the step limit, one half on the face).  A side that is not open (a
+    domain-boundary side) keeps the weight at its plateau."""
     xi = np.asarray(xi, float)
-    if delta == 0.0:
-        lo = np.where(xi > -1.0, 1.0, np.where(xi == -1.0, 0.5, 0.0)) if lower_open else np.ones_like(xi)
-        hi = np.where(xi < 1.0, 1.0, np.where(xi == 1.0, 0.5, 0.0)) if upper_open else np.ones_like(xi)
-        return lo * hi
-    a = phi((xi + 1.0) / delta) if lower_open else np.ones_like(xi)
-    b = phi((xi - 1.0) / delta) if upper_open else -np.ones_like(xi)
+
+    def edge(t, delta):
+        return np.sign(t) if delta == 0.0 else phi(t / delta)
+    a = edge(xi + 1.0, delta_lo) if lower_open else np.ones_like(xi)
+    b = edge(xi - 1.0, delta_hi) if upper_open else -np.ones_like(xi)
     return 0.5 * (a - b)
+
+
+def weight_1d(xi, delta, lower_open=True, upper_open=True):
+    """w(xi) of Eq. schwarz_weight with overlap width delta (delta = 0: the step limit)."""
+    return weight_sides(xi, delta, delta, lower_open, upper_open)
 
 
 def overlap_width(n, n_overlap):
@@ -219,35 +226,52 @@ def _topo_neighbours(mesh, index, c):
 
 def subdomains_topo(op, n_overlap, normalise=True):
     """Subdomains of every element built from the mesh topology (any macro maps and face
-    orientations; one degree and one level): neighbours' points placed in e_c's extended
-    coordinates through the composed face maps, weights as in ``subdomains``.  Where cells
-    meet three around an edge instead of four, the weights of the subdomains covering a point
-    no longer sum to one; with ``normalise`` they are divided there by their sum."""
+    orientations; one level, any degrees): neighbours' points placed in e_c's extended
+    coordinates through the composed face maps, weights as in ``subdomains``.  With degrees that
+    differ across a face the subdomain boundaries are ragged: each face of e_c has one overlap
+    width, the narrower of its two sides' (delta of a degree p: 1 + xi_(N_overlap - 1) of its LGL
+    nodes, N_overlap at most p), so that the two subdomains sharing the face use the same
+    transition; a neighbour's point belongs to the subdomain when it lies within the overlap
+    width of the side it is on, on every axis.  Where the weights of the subdomains covering a
+    point do not sum to one (three cells around an edge, or degrees that differ around an edge)
+    they are divided by their sum (``normalise``)."""
     mesh = op.mesh
-    if len(set(int(p) for p in mesh["elem_p"])) != 1 or len(set(int(l) for l in mesh["elem_level"])) != 1:
-        raise ValueError("the Schwarz subdomains here need one degree and one level")
-    n = int(mesh["elem_p"][0]) + 1
-    delta = overlap_width(n, n_overlap)
-    xl, _ = rules.lgl(n)
-    xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)  # x fastest
+    if len(set(int(l) for l in mesh["elem_level"])) != 1:
+        raise ValueError("the Schwarz subdomains here need one refinement level")
     E = len(mesh["elem_p"])
+    nodes = {}
+    for p in set(int(p) for p in mesh["elem_p"]):
+        xl, _ = rules.lgl(p + 1)
+        xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)  # x fastest
+        nodes[p] = (xi, overlap_width(p + 1, min(n_overlap, p)))
     index = {(int(mesh["elem_macro"][e]), int(mesh["elem_level"][e])) + tuple(int(x) for x in mesh["elem_anchor"][e]): e
              for e in range(E)}
     out = []
     for c in range(E):
         nb = _topo_neighbours(mesh, index, c)
-        open_lo = [any(o[d] == -1 and not np.any(np.delete(o, d)) for _, o, _ in nb) for d in range(3)]
-        open_hi = [any(o[d] == 1 and not np.any(np.delete(o, d)) for _, o, _ in nb) for d in range(3)]
+        dc = nodes[int(mesh["elem_p"][c])][1]
+        open_lo, open_hi, d_lo, d_hi = [False] * 3, [False] * 3, [0.0] * 3, [0.0] * 3
+        for e, o, _ in nb:
+            if sum(map(abs, o)) != 1:
+                continue
+            d = int(np.flatnonzero(o)[0])
+            width = min(dc, nodes[int(mesh["elem_p"][e])][1])
+            if o[d] < 0:
+                open_lo[d], d_lo[d] = True, width
+            else:
+                open_hi[d], d_hi[d] = True, width
         idx, wts = [], []
         ident = ([0, 1, 2], [1.0, 1.0, 1.0], [0.0, 0.0, 0.0])
         for e, _, (perm, sign, shift) in [(c, None, ident)] + nb:
+            xi = nodes[int(mesh["elem_p"][e])][0]
             ext = np.stack([sign[i] * xi[:, perm[i]] + shift[i] for i in range(3)], axis=1)
-            inside = np.all(np.abs(ext) <= 1.0 + delta + 1e-12, axis=1)
+            bound = np.where(ext > 1.0, 1.0 + np.array(d_hi), np.where(ext < -1.0, 1.0 + np.array(d_lo), 1.0))
+            inside = np.all(np.abs(ext) <= bound + 1e-12, axis=1)
             if not inside.any():
                 continue
             w = np.ones(int(inside.sum()))
             for d in range(3):
-                w = w * weight_1d(ext[inside, d], delta, open_lo[d], open_hi[d])
+                w = w * weight_sides(ext[inside, d], d_lo[d], d_hi[d], open_lo[d], open_hi[d])
             idx.append(op.offsets[e] + np.flatnonzero(inside))
             wts.append(w)
         out.append((np.concatenate(idx), np.concatenate(wts)))

@@ -243,9 +243,8 @@ class Multigrid:
             self.schwarz = []
             for op in self.ops[:-1]:
                 A = assemble_dense(op)
-                # a level of degree p < N_overlap holds at most p layers beyond the coincident one
-                nov = min(self.schwarz_overlap, int(op.mesh["elem_p"].max()))
-                self.schwarz.append((A, schwarz.subdomains_topo(op, nov)))
+                # (an element of degree p < N_overlap holds at most p layers beyond the coincident one)
+                self.schwarz.append((A, schwarz.subdomains_topo(op, self.schwarz_overlap)))
             lam = [0.0] * (len(self.ops) - 1)
         if lam is None:
             lam = []

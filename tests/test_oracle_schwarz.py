@@ -258,3 +258,65 @@ def test_schwarz_restores_multigrid_on_the_stretched_shell():
         _, its[name], _ = fcg(mg.ops[0].apply, b, mg.vcycle, tol=1e-10, max_iter=300)
     print("FCG iterations", its)
     assert its["schwarz"] <= 6 and its["block"] >= 4 * its["schwarz"] and its["point"] >= 10 * its["schwarz"]
+
+
+def _mixed_degrees(mesh, degrees, seed):
+    out = dict(mesh)
+    out["elem_p"] = np.random.default_rng(seed).choice(degrees, size=len(mesh["elem_p"])).astype(mesh["elem_p"].dtype)
+    return out
+
+
+@pytest.mark.parametrize("n_overlap,sizes", [(1, [27 + 16, 64 + 9]), (2, [27 + 32, 64 + 9])])
+def test_ragged_subdomains_of_two_cells_of_different_degrees(n_overlap, sizes):
+    # degrees 2 and 3 side by side: the shared face takes the narrower overlap width (that of
+    # degree 3 for N_overlap 2: 1 - 1/sqrt(5), against 1 for degree 2); the degree-2 subdomain
+    # takes N_overlap layers of the 4 x 4 face layers of its neighbour, the degree-3 one only the
+    # coincident 3 x 3 layer (the next degree-2 layer lies at the face's far side, beyond the
+    # width); the weights sum to one without normalisation
+    mesh = dict(meshgen.box_grid((2, 1, 1), 0, 2))
+    mesh["elem_p"] = np.array([2, 3], dtype=mesh["elem_p"].dtype)
+    op = SIPG(mesh, meshgen.problem_config1())
+    subs = sw.subdomains_topo(op, n_overlap, normalise=False)
+    assert [len(i) for i, _ in subs] == sizes
+    total = np.zeros(op.ndof)
+    for idx, w in subs:
+        np.add.at(total, idx, w)
+    assert np.allclose(total, 1.0, rtol=0, atol=1e-14)
+
+
+def test_ragged_subdomains_on_a_random_degree_cube():
+    # degrees 2..4 drawn per cell: with one layer the weights sum to one everywhere; with two,
+    # points whose sum differs from one lie only in cells with a neighbour of another degree, and
+    # normalisation restores the partition of unity
+    mesh = _mixed_degrees(meshgen.unit_cube(2, 2), [2, 3, 4], 1)
+    op = SIPG(mesh, meshgen.problem_config1())
+    for n_overlap in (1, 2):
+        total = np.zeros(op.ndof)
+        for idx, w in sw.subdomains_topo(op, n_overlap, normalise=False):
+            np.add.at(total, idx, w)
+        off = np.abs(total - 1.0) > 1e-12
+        if n_overlap == 1:
+            assert not off.any()
+            continue
+        assert off.any()
+        elems = np.unique(np.searchsorted(op.offsets, np.flatnonzero(off), side="right") - 1)
+        p = mesh["elem_p"]
+        mixed = {int(mt["em"]) for mt in op.mortars if mt["ep"] >= 0 and p[mt["em"]] != p[mt["ep"]]}
+        mixed |= {int(mt["ep"]) for mt in op.mortars if mt["ep"] >= 0 and p[mt["em"]] != p[mt["ep"]]}
+        assert set(int(e) for e in elems) <= mixed
+        total = np.zeros(op.ndof)
+        for idx, w in sw.subdomains_topo(op, n_overlap):
+            np.add.at(total, idx, w)
+        assert np.allclose(total, 1.0, rtol=0, atol=1e-14)
+
+
+def test_schwarz_multigrid_on_a_random_degree_cube():
+    mesh = _mixed_degrees(meshgen.unit_cube(2, 2), [2, 3, 4], 1)
+    prob = meshgen.problem_config1()
+    its = {}
+    for name, kw in (("schwarz", dict(n_cheb=3, smoother="schwarz", schwarz_overlap=2)),
+                     ("point", dict(n_cheb=4, smoother="point"))):
+        mg = Multigrid(mesh, prob, **kw)
+        _, its[name], _ = fcg(mg.ops[0].apply, mg.ops[0].rhs(), mg.vcycle, tol=1e-10, max_iter=200)
+    print("FCG iterations", its)
+    assert its["schwarz"] <= 8 and its["point"] >= 3 * its["schwarz"]
