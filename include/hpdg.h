@@ -204,9 +204,11 @@ typedef struct {
  *                      side of the centre element that lies on the domain boundary the weight
  *                      keeps its plateau; where three cells meet around an edge (the six-patch
  *                      shell) the weights covering a point are divided by their sum; so they
- *                      sum to one at every point.  Scope: every smoothed level has one degree,
- *                      one refinement level and faces that meet 1:1, subdomains of at most 8190
- *                      points (HPDG_ERR_UNSUPPORTED at setup otherwise).  On meshes with FP32
+ *                      sum to one at every point.  Where degrees differ across a face the
+ *                      subdomains are ragged: each face takes the narrower of its two cells'
+ *                      overlap widths.  Scope: every smoothed level has one refinement level and
+ *                      faces that meet 1:1 (any degrees), subdomains of at most 8190 points
+ *                      (HPDG_ERR_UNSUPPORTED at setup otherwise).  On meshes with FP32
  *                      levels the stored rows are also kept rounded to FP32, for FP32 smoothing
  *                      and the FP32 V-cycle of mixed-precision solves.  Not rebuilt for Newton
  *                      linearisations (HPDG_ERR_UNSUPPORTED).  No spectral bound is computed

@@ -1019,7 +1019,9 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   SchwarzLayout lay;
   schwarz_layout(M->mm, h, M->sp.schwarz_overlap, lay);
   const int E = int(h.cells.size());
-  const int n = lay.n, n3 = n * n * n;
+  const int n3max = lay.n * lay.n * lay.n;
+  std::vector<int> en3(static_cast<size_t>(E));
+  for (int e = 0; e < E; ++e) en3[e] = lay.en[e] * lay.en[e] * lay.en[e];
   int max_m = 0, max_nw = 0;
   long long minv_scalars = 0, minv32_scalars = 0, alg_scalars = 0, nrows = 0;
   for (int c = 0; c < E; ++c) {
@@ -1033,9 +1035,19 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   }
   if (size_t(schwarz_stride(max_m, 8)) * sizeof(double) > 64 * 1024)
     throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomains of more than 8190 points");
-  const double blk_bytes = double(E) * 7.0 * double(n3) * double(n3) * sizeof(double);
-  if (blk_bytes > 16.0 * (1ull << 30)) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz setup: operator blocks above 16 GiB");
   const std::vector<int>& F = lay.fnb;
+  // operator blocks: element b, slot k (0: b itself, 1 + f: the neighbour a across face f), n3_a x
+  // n3_b column-major at boff[7 b + k]
+  std::vector<long long> boff(size_t(E) * 7, 0);
+  size_t blk_size = 0;
+  for (int b = 0; b < E; ++b)
+    for (int k = 0; k < 7; ++k) {
+      const int a = k == 0 ? b : F[size_t(b) * 6 + k - 1];
+      boff[size_t(b) * 7 + k] = (long long)blk_size;
+      if (a >= 0) blk_size += size_t(en3[a]) * en3[b];
+    }
+  if (double(blk_size) * sizeof(double) > 16.0 * (1ull << 30))
+    throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz setup: operator blocks above 16 GiB");
   // distance-2 colouring of the face graph (greedy, element order)
   std::vector<int> color(E, -1);
   int ncol = 0;
@@ -1058,10 +1070,10 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       ncol = std::max(ncol, c + 1);
     }
   }
-  // blocks: element b, slot k (0: b itself, 1 + f: the neighbour across face f), column j, row i
-  // (gathered on the device, one colour and column at a time; kept there for the assembly)
-  const size_t blk_size = size_t(E) * 7 * n3 * n3;
+  // the blocks, gathered on the device one colour and column at a time; kept there for the assembly
   double* dblk = nullptr;
+  int* den3 = nullptr;
+  long long* dboff = nullptr;
   {
     DevLevel<double>& d = M->lev<double>(l);
     const LevelView<double> V = M->view<double>(l);
@@ -1077,17 +1089,19 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     int* dmem = M->upload_raw(members, s);
     int* dfnb = M->upload_raw(F, s);
     long long* deoff = M->upload_raw(eoff, s);
+    den3 = M->upload_raw(en3, s);
+    dboff = M->upload_raw(boff, s);
     dblk = M->alloc<double>(blk_size);
     launch_fill<double>((long long)blk_size, 0.0, dblk, s);
     launch_fill<double>(h.ndof, 0.0, d.f, s);
     for (int c = 0; c < ncol; ++c) {
       const int cnt = cstart[c + 1] - cstart[c];
       const int* mc = dmem + cstart[c];
-      for (int j = 0; j < n3; ++j) {
-        launch_schwarz_units(cnt, mc, deoff, j, 1.0, d.f, s);
+      for (int j = 0; j < n3max; ++j) {
+        launch_schwarz_units(cnt, mc, deoff, den3, j, 1.0, d.f, s);
         level_apply<double>(M, l, V, d.f, d.t, s);
-        launch_schwarz_gather(cnt, mc, dfnb, deoff, n3, j, d.t, dblk, s);
-        launch_schwarz_units(cnt, mc, deoff, j, 0.0, d.f, s);
+        launch_schwarz_gather(cnt, mc, dfnb, deoff, den3, dboff, j, d.t, dblk, s);
+        launch_schwarz_units(cnt, mc, deoff, den3, j, 0.0, d.f, s);
       }
     }
     HIPCHK(hipGetLastError());
@@ -1175,7 +1189,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     const int m = g.first;
     const int cnt = int(subs.size());
     int* dsubs = M->upload_raw(subs, s);
-    launch_schwarz_assemble(m, cnt, dsubs, W.goff, dlel, dloc, dels, dslot, n3, dblk, dA, s);
+    launch_schwarz_assemble(m, cnt, dsubs, W.goff, dlel, dloc, dels, dslot, den3, dboff, dblk, dA, s);
     HIPCHK(hipGetLastError());
     std::vector<double*> ptrs(cnt);
     std::vector<long long> pofs(cnt), gm(cnt), gm32(cnt), gw(cnt);
@@ -1220,7 +1234,9 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
                     (void*)dsubs})
       if (q) M->release(q);
     }
-  for (void* q : {(void*)dA, (void*)dblk, (void*)dlel, (void*)dloc, (void*)dels, (void*)dslot}) M->release(q);
+  for (void* q : {(void*)dA, (void*)dblk, (void*)dlel, (void*)dloc, (void*)dels, (void*)dslot, (void*)den3,
+                  (void*)dboff})
+    M->release(q);
   M->release(dw);
 
 }

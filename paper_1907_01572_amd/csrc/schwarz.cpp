@@ -21,15 +21,17 @@ double phi(double t) {
   return t * (15.0 - 10.0 * t2 + 3.0 * t2 * t2) / 8.0;
 }
 
-// 1-D weight w(xi) with overlap width delta; a closed side (domain boundary) keeps the plateau
-double weight(double xi, double delta, bool lower_open, bool upper_open) {
-  if (delta == 0.0) {
-    const double lo = !lower_open ? 1.0 : (xi > -1.0 ? 1.0 : (xi == -1.0 ? 0.5 : 0.0));
-    const double hi = !upper_open ? 1.0 : (xi < 1.0 ? 1.0 : (xi == 1.0 ? 0.5 : 0.0));
-    return lo * hi;
-  }
-  const double a = lower_open ? phi((xi + 1.0) / delta) : 1.0;
-  const double b = upper_open ? phi((xi - 1.0) / delta) : -1.0;
+// one transition of the weight: phi(t / delta), or its limit sgn(t) for delta = 0
+double edge(double t, double delta) {
+  if (delta == 0.0) return t > 0.0 ? 1.0 : (t < 0.0 ? -1.0 : 0.0);
+  return phi(t / delta);
+}
+
+// 1-D weight w(xi) with the overlap widths dlo (lower side) and dhi (upper side); a closed side
+// (domain boundary) keeps the plateau
+double weight(double xi, double dlo, double dhi, bool lower_open, bool upper_open) {
+  const double a = lower_open ? edge(xi + 1.0, dlo) : 1.0;
+  const double b = upper_open ? edge(xi - 1.0, dhi) : -1.0;
   return 0.5 * (a - b);
 }
 
@@ -95,15 +97,13 @@ uint64_t cell_key(const Cell& c) {
 void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out) {
   const int E = int(L.cells.size());
   if (E == 0) throw Error(HPDG_ERR_INVALID_MESH, "empty level");
-  const int n = L.einfo[0].n;
   const int lev = L.cells[0].level;
   if (n_overlap < 1) throw Error(HPDG_ERR_INVALID_ARG, "Schwarz overlap must be at least 1");
-  n_overlap = std::min(n_overlap, n - 1);  // a level of degree p holds at most p layers
-  // scope: one degree, one refinement level, faces that meet 1:1 (any macro maps and face
-  // orientations)
+  // scope: one refinement level, faces that meet 1:1 (any macro maps, face orientations and
+  // degrees)
   for (int e = 0; e < E; ++e)
-    if (L.einfo[e].n != n || L.cells[e].level != lev)
-      throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs levels of one degree and one refinement level");
+    if (L.cells[e].level != lev)
+      throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs levels of one refinement level");
   for (const Mortar& m : L.mortars)
     if (m.ep >= 0 && m.sub != -1) throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing needs faces that meet 1:1");
   std::unordered_map<uint64_t, int> index;
@@ -124,10 +124,22 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
       FB[size_t(e) * 6 + f] = fb;
       FO[size_t(e) * 6 + f] = o;
     }
-  std::vector<double> xl(n), wl(n);
-  gauss_lobatto(n, xl.data(), wl.data());
-  const double delta = 1.0 + xl[n_overlap - 1];
-  out.n = n;
+  // per number of nodes n: the LGL nodes and the overlap width 1 + xi_(N_overlap - 1), at most p
+  // layers (N_overlap <= n - 1)
+  std::vector<std::vector<double>> xln(kMaxN + 1);
+  std::vector<double> width(kMaxN + 1, 0.0);
+  out.en.assign(size_t(E), 0);
+  out.n = 0;
+  for (int e = 0; e < E; ++e) {
+    const int n = L.einfo[e].n;
+    out.en[e] = n;
+    out.n = std::max(out.n, n);
+    if (!xln[n].empty()) continue;
+    std::vector<double> wl(n);
+    xln[n].resize(n);
+    gauss_lobatto(n, xln[n].data(), wl.data());
+    width[n] = 1.0 + xln[n][std::min(n_overlap, n - 1) - 1];
+  }
   out.off.assign(size_t(E) + 1, 0);
   out.nw.assign(size_t(E), 0);
   out.elem.clear();
@@ -202,10 +214,15 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
     for (size_t k = 1; k < keep.size(); ++k)
       if (keep[k].e == keep[k - 1].e)
         throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz smoothing: an element neighbours another on two sides");
+    // per side: open (a face neighbour) and its overlap width, the narrower of the two cells'
     bool open_lo[3], open_hi[3];
+    double d_lo[3], d_hi[3];
     for (int d = 0; d < 3; ++d) {
-      open_lo[d] = F[size_t(c) * 6 + 2 * d] >= 0;
-      open_hi[d] = F[size_t(c) * 6 + 2 * d + 1] >= 0;
+      const int lo = F[size_t(c) * 6 + 2 * d], hi = F[size_t(c) * 6 + 2 * d + 1];
+      open_lo[d] = lo >= 0;
+      open_hi[d] = hi >= 0;
+      d_lo[d] = lo >= 0 ? std::min(width[out.en[c]], width[out.en[lo]]) : 0.0;
+      d_hi[d] = hi >= 0 ? std::min(width[out.en[c]], width[out.en[hi]]) : 0.0;
     }
     Nb self;
     self.e = c;
@@ -215,7 +232,9 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
     std::vector<int>& el = el_all[c];
     std::vector<int>& lc = lc_all[c];
     std::vector<double>& wt = wt_all[c];
-    for (const Nb& x : keep)
+    for (const Nb& x : keep) {
+      const int n = out.en[x.e];
+      const std::vector<double>& xl = xln[n];
       for (int k = 0; k < n; ++k)
         for (int j = 0; j < n; ++j)
           for (int i = 0; i < n; ++i) {
@@ -224,15 +243,17 @@ void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, Schw
             bool in = true;
             for (int d = 0; d < 3; ++d) {
               ext[d] = x.M.sign[d] * xi[x.M.perm[d]] + x.M.shift[d];
-              in = in && std::fabs(ext[d]) <= 1.0 + delta + 1e-12;
+              const double bound = 1.0 + (ext[d] > 1.0 ? d_hi[d] : (ext[d] < -1.0 ? d_lo[d] : 0.0));
+              in = in && std::fabs(ext[d]) <= bound + 1e-12;
             }
             if (!in) continue;
             double w = 1.0;
-            for (int d = 0; d < 3; ++d) w *= weight(ext[d], delta, open_lo[d], open_hi[d]);
+            for (int d = 0; d < 3; ++d) w *= weight(ext[d], d_lo[d], d_hi[d], open_lo[d], open_hi[d]);
             el.push_back(x.e);
             lc.push_back(i + n * (j + n * k));
             wt.push_back(w);
           }
+    }
   });
   // where cells meet three around an edge the weights covering a point sum to less than one:
   // divide them there by their sum

@@ -47,51 +47,63 @@ __global__ void __launch_bounds__(256) schwarz_pack_kernel(int m, int b0, const 
   }
 }
 
-// setup: x[off(b) + j] = value for the elements b of one colour
+// setup: x[off(b) + j] = value for the elements b of one colour with more than j nodes
 __global__ void __launch_bounds__(256) schwarz_units_kernel(const int* __restrict__ members, int cnt,
-                                                          const long long* __restrict__ eoff, int j, double value,
+                                                          const long long* __restrict__ eoff,
+                                                          const int* __restrict__ en3, int j, double value,
                                                           double* __restrict__ x) {
-  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x)
-    x[eoff[members[t]] + j] = value;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < cnt; t += gridDim.x * blockDim.x) {
+    const int b = members[t];
+    if (j < en3[b]) x[eoff[b] + j] = value;
+  }
 }
 
 // setup: column j of the operator blocks of the elements b of one colour from y = A x (x the
-// unit vectors of schwarz_units_kernel): blk[((b 7 + k) n3 + j) n3 + i] = y[off(a) + i], a = b
-// (k = 0) or the neighbour across face k - 1
+// unit vectors of schwarz_units_kernel): block (b, k) at blk + boff[7 b + k], n3_a x n3_b,
+// column-major: blk[boff[7 b + k] + j n3_a + i] = y[off(a) + i], a = b (k = 0) or the neighbour
+// across face k - 1
 __global__ void __launch_bounds__(256) schwarz_gather_kernel(const int* __restrict__ members,
                                                            const int* __restrict__ fnb,
-                                                           const long long* __restrict__ eoff, int n3, int j,
+                                                           const long long* __restrict__ eoff,
+                                                           const int* __restrict__ en3,
+                                                           const long long* __restrict__ boff, int j,
                                                            const double* __restrict__ y, double* __restrict__ blk) {
   const int b = members[blockIdx.x];
   const int k = blockIdx.y;
   const int a = k == 0 ? b : fnb[6 * (long long)b + k - 1];
-  if (a < 0) return;
-  double* dst = blk + ((7 * (long long)b + k) * n3 + j) * (long long)n3;
+  if (a < 0 || j >= en3[b]) return;
+  const int n3a = en3[a];
+  double* dst = blk + boff[7 * (long long)b + k] + (long long)j * n3a;
   const double* src = y + eoff[a];
-  for (int i = threadIdx.x; i < n3; i += blockDim.x) dst[i] = src[i];
+  for (int i = threadIdx.x; i < n3a; i += blockDim.x) dst[i] = src[i];
 }
 
 // setup: A_ss of the subdomains subs[b] (m points each), column-major at A + b m^2, from the
-// operator blocks blk[((e 7 + k) n3 + j) n3 + i] through the assembly tables; one workgroup per
+// operator blocks (at boff, n3_a x n3_b each) through the assembly tables; one workgroup per
 // column
 __global__ void __launch_bounds__(256) schwarz_assemble_kernel(int m, const int* __restrict__ subs,
                                                              const long long* __restrict__ goff,
                                                              const unsigned char* __restrict__ lel,
                                                              const short* __restrict__ loc,
                                                              const int* __restrict__ els,
-                                                             const signed char* __restrict__ slot, int n3,
+                                                             const signed char* __restrict__ slot,
+                                                             const int* __restrict__ en3,
+                                                             const long long* __restrict__ boff,
                                                              const double* __restrict__ blk,
                                                              double* __restrict__ A) {
   const int b = blockIdx.y, q = blockIdx.x;
   const int c = subs[b];
   const long long o = goff[c];
   const int eq = lel[o + q];
-  const long long col = ((7 * (long long)els[27 * (long long)c + eq]) * n3 + loc[o + q]) * (long long)n3;
+  const int* ec = els + 27 * (long long)c;
+  const long long* bq = boff + 7 * (long long)ec[eq];
+  const int jq = loc[o + q];
   const signed char* sc = slot + 729 * (long long)c + 27 * eq;
   double* out = A + (long long)b * m * m + (long long)q * m;
   for (int p = threadIdx.x; p < m; p += blockDim.x) {
-    const int k = sc[lel[o + p]];
-    out[p] = k < 0 ? 0.0 : blk[col + (long long)k * n3 * n3 + loc[o + p]];
+    const int lp = lel[o + p];
+    const int k = sc[lp];
+    out[p] = k < 0 ? 0.0 : blk[bq[k] + (long long)jq * en3[ec[lp]] + loc[o + p]];
   }
 }
 
@@ -185,26 +197,26 @@ void launch_schwarz_pack(int m, int count, const double* P, const long long* pof
 
 int schwarz_stride(int m, int scalar_bytes) { return scalar_bytes == 4 ? sw_stride<float>(m) : sw_stride<double>(m); }
 
-void launch_schwarz_units(int cnt, const int* members, const long long* eoff, int j, double value, double* x,
-                          hipStream_t s) {
+void launch_schwarz_units(int cnt, const int* members, const long long* eoff, const int* en3, int j, double value,
+                          double* x, hipStream_t s) {
   if (cnt <= 0) return;
   hipLaunchKernelGGL(schwarz_units_kernel, dim3(unsigned(std::min(4096, (cnt + 255) / 256))), dim3(256), 0, s,
-                     members, cnt, eoff, j, value, x);
+                     members, cnt, eoff, en3, j, value, x);
 }
 
-void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, int n3, int j,
-                           const double* y, double* blk, hipStream_t s) {
+void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, const int* en3,
+                           const long long* boff, int j, const double* y, double* blk, hipStream_t s) {
   if (cnt <= 0) return;
-  hipLaunchKernelGGL(schwarz_gather_kernel, dim3(unsigned(cnt), 7), dim3(256), 0, s, members, fnb, eoff, n3, j, y,
-                     blk);
+  hipLaunchKernelGGL(schwarz_gather_kernel, dim3(unsigned(cnt), 7), dim3(256), 0, s, members, fnb, eoff, en3, boff, j,
+                     y, blk);
 }
 
 void launch_schwarz_assemble(int m, int cnt, const int* subs, const long long* goff, const unsigned char* lel,
-                             const short* loc, const int* els, const signed char* slot, int n3, const double* blk,
-                             double* A, hipStream_t s) {
+                             const short* loc, const int* els, const signed char* slot, const int* en3,
+                             const long long* boff, const double* blk, double* A, hipStream_t s) {
   for (int b0 = 0; b0 < cnt; b0 += 32768)  // grid y stays below its 65535 limit
     hipLaunchKernelGGL(schwarz_assemble_kernel, dim3(unsigned(m), unsigned(std::min(32768, cnt - b0))), dim3(256), 0,
-                       s, m, subs + b0, goff, lel, loc, els, slot, n3, blk, A + (long long)b0 * m * m);
+                       s, m, subs + b0, goff, lel, loc, els, slot, en3, boff, blk, A + (long long)b0 * m * m);
 }
 
 template <typename T>

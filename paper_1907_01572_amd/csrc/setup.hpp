@@ -194,18 +194,20 @@ void estimator_tables(const MacroMesh& mm, const MacroMesh* grid, const DiscPara
 bool cell_across(const MacroMesh& mm, const Cell& c, int f, Cell& nb, int& fb, int& orient);
 
 // Additive Schwarz subdomains of a level (Sec. II.D, Alg. schwarz_smoother, Eq. schwarz_weight),
-// one per element e_c, for levels of one degree and one refinement level whose faces all meet
-// 1:1 (HPDG_ERR_UNSUPPORTED otherwise; any macro maps and face orientations).  The neighbours
+// one per element e_c, for levels of one refinement level whose faces all meet 1:1
+// (HPDG_ERR_UNSUPPORTED otherwise; any macro maps, face orientations and degrees).  The neighbours
 // at each offset o (o_d in {-1, 0, 1}) are found by stepping across faces in every order of
 // the offset's axes, and their reference coordinates carried into e_c's extended coordinates
 // by the composed face maps (xi_ext = xi + 2 o in e_c's frame); an offset whose paths disagree,
 // or that leads back to e_c or a face neighbour (three cells around an edge), has none.  The
-// subdomain holds the points with |xi_ext| <= 1 + delta on every axis, delta =
-// 1 + xi_(N_overlap - 1) (N_overlap at most p), each weighted by the product over the axes of
-// w(xi) = (phi((xi + 1) / delta) - phi((xi - 1) / delta)) / 2; on a side of e_c without a
+// overlap width of a degree p is delta_p = 1 + xi_(N_overlap - 1) of its LGL nodes (N_overlap at
+// most p); each face of e_c takes the narrower of its two cells' widths (ragged subdomains where
+// degrees differ).  The subdomain holds the points with |xi_ext| <= 1 + delta of the side they
+// lie on, on every axis, each weighted by the product over the axes of
+// w(xi) = (phi((xi + 1) / delta_lo) - phi((xi - 1) / delta_hi)) / 2; on a side of e_c without a
 // neighbour (domain boundary) that side's phi term is replaced by its limit; where the weights
-// covering a point do not sum to one (three cells around an edge) they are divided by their
-// sum.  Entries of a subdomain: e_c's points, then the neighbours' by element and local index,
+// covering a point do not sum to one (three cells around an edge, widths that differ around an
+// edge) they are divided by their sum.  Entries of a subdomain: e_c's points, then the neighbours' by element and local index,
 // and then stably reordered so that the entries with a non-zero weight come first.
 struct SchwarzLayout {
   std::vector<long long> off;     // per subdomain: first entry (E + 1)
@@ -213,7 +215,8 @@ struct SchwarzLayout {
   std::vector<int> elem, loc;     // element and local dof index of each entry
   std::vector<double> w;          // weight of each entry
   std::vector<int> fnb;           // per element and face (6 per element): face neighbour or -1
-  int n = 0;                      // LGL nodes per axis
+  std::vector<int> en;            // per element: LGL nodes per axis
+  int n = 0;                      // the largest of them
 };
 void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out);
 // Assembly tables of the subdomains: per entry, the index of its element among the subdomain's

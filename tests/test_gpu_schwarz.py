@@ -40,6 +40,24 @@ MESHES = {
 PROBLEM = {"shell_l1_p2_r1e3": meshgen.problem_config2(), "shell_l1_p3_r1e9": meshgen.problem_config2()}
 
 
+def _mixed_degrees(mesh, degrees, seed):
+    out = dict(mesh)
+    out["elem_p"] = np.random.default_rng(seed).choice(degrees, size=len(mesh["elem_p"])).astype(mesh["elem_p"].dtype)
+    return out
+
+
+def _two_degrees():
+    # two macros refined once, degree 2 in the first and 3 in the second
+    out = dict(meshgen.box_grid((2, 1, 1), 1, 2))
+    out["elem_p"] = np.where(out["elem_macro"] == 0, 2, 3).astype(out["elem_p"].dtype)
+    return out
+
+
+# one level, degrees that differ across faces: ragged subdomains
+MESHES["box_2x1x1_p2_p3"] = _two_degrees
+MESHES["cube_l2_p2to4"] = lambda: _mixed_degrees(meshgen.unit_cube(2, 2), [2, 3, 4], 1)
+
+
 @pytest.fixture(scope="module")
 def ctx():
     if not torch.cuda.is_available():
@@ -61,7 +79,8 @@ def host(t):
 @pytest.mark.parametrize("name,n_overlap", [("cube_l2_p3", 1), ("cube_l2_p3", 2), ("box_2x1x1_l1_p2", 1),
                                             ("box_2x1x1_l1_p2", 2), ("box_lopsided_l1_p3", 3),
                                             ("cube_l1_p6", 2), ("shell_l1_p2_r1e3", 1), ("shell_l1_p2_r1e3", 2),
-                                            ("shell_l1_p3_r1e9", 2)])
+                                            ("shell_l1_p3_r1e9", 2), ("box_2x1x1_p2_p3", 2), ("cube_l2_p2to4", 1),
+                                            ("cube_l2_p2to4", 2)])
 def test_schwarz_smooth_and_vcycle_parity(ctx, name, n_overlap):
     m = MESHES[name]()
     prob = PROBLEM.get(name, meshgen.problem_config1())
@@ -88,10 +107,11 @@ def test_schwarz_smooth_and_vcycle_parity(ctx, name, n_overlap):
     M.free()
 
 
-def test_schwarz_fcg_follows_the_oracle(ctx):
+@pytest.mark.parametrize("name", ["cube_l2_p3", "cube_l2_p2to4"])
+def test_schwarz_fcg_follows_the_oracle(ctx, name):
     # N_overlap = 2, three cycles per smoothing call: the library's FCG takes the oracle's
     # iterations and reaches its solution; point-Jacobi Chebyshev needs several times as many
-    m = MESHES["cube_l2_p3"]()
+    m = MESHES[name]()
     prob = meshgen.problem_config1()
     mg = Multigrid(m, prob, n_cheb=3, smoother="schwarz", schwarz_overlap=2)
     op = mg.ops[0]
