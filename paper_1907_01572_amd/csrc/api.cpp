@@ -1010,8 +1010,9 @@ void factor_blocks(hpdg_mesh* M, int l, const LevelView<double>& V, const std::v
 // neighbours a (SIPG couples no other pairs), gathered column by column from applies to unit
 // vectors on the elements of one colour of a distance-2 colouring of the face graph (no two
 // elements of a colour share a neighbour, so each neighbour's rows come from one of them), each
-// subdomain's A_ss assembled from the blocks on the host, inverted on the device (batched
-// Cholesky + inverse, rocSOLVER, per subdomain size), and the weighted rows kept
+// subdomain's A_ss assembled from the blocks (all on the device; the host builds the layout and
+// the slot tables), inverted (batched Cholesky + inverse, rocSOLVER, per subdomain size), and
+// the weighted rows kept (FP64, and FP32 for meshes with FP32 levels)
 void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   hpdg_mesh::SchwarzDev& W = M->sw[size_t(l)];
   if (W.minv && W.overlap == M->sp.schwarz_overlap) return;

@@ -4,7 +4,6 @@
 #include "setup.hpp"
 
 #include <algorithm>
-#include <array>
 #include <cmath>
 #include <cstdlib>
 #include <unordered_map>
@@ -34,10 +33,6 @@ double weight(double xi, double dlo, double dhi, bool lower_open, bool upper_ope
   const double b = upper_open ? edge(xi - 1.0, dhi) : -1.0;
   return 0.5 * (a - b);
 }
-
-}  // namespace
-
-namespace {
 
 // affine map of a neighbour's reference coordinates into the centre's extended coordinates:
 // ext[i] = sign[i] xi[perm[i]] + shift[i]
