@@ -344,3 +344,31 @@ def test_schwarz_full_size_sampled_cycle_on_the_compactified_shell(ctx):
     assert len(hold) == 3 and abs(wsum - 1.0) <= 1e-14
     assert err <= TOL_SCHWARZ_COMPACTIFIED and np.all(np.delete(xg, U) == 0.0)
     M.free()
+
+
+@pytest.mark.timeout(300)
+@pytest.mark.parametrize("precision", [hp.PREC_F64, hp.PREC_MIXED])
+def test_schwarz_in_the_solve_server(ctx, precision):
+    # the solve server with the Schwarz smoother (N_overlap 2, three cycles): requests on a box,
+    # the compactified shell and a mixed-degree cube in flight together; each reaches 1e-10 and
+    # equals the mesh API's Schwarz solve of the same problem
+    reqs = [(meshgen.unit_cube(2, 3), meshgen.gaussian_problem(lo=(0, 0, 0), hi=(1, 1, 1), seed=1)),
+            (MESHES["shell_l1_p3_r1e9"](), meshgen.problem_config2()),
+            (MESHES["cube_l2_p2to4"](), meshgen.gaussian_problem(lo=(0, 0, 0), hi=(1, 1, 1), seed=2))]
+    sv = hp.Server(ctx, max_active=3, precision=precision, n_cheb=3, smoother="schwarz")
+    outs = [np.zeros(meshgen.dof_count(m)) for m, _ in reqs]
+    tickets = [sv.submit(m, p, u) for (m, p), u in zip(reqs, outs)]
+    sts = [sv.wait(t, timeout_ms=120000) for t in tickets]
+    sv.close()
+    for (m, prob), u, st in zip(reqs, outs, sts):
+        assert st["state"] == "done" and st["rel_residual"] <= 1e-10, st
+        M = ctx.upload(m, coef=coef_of(prob), build_f32=(precision == hp.PREC_MIXED))
+        M.setup_smoother(n_cheb=3, smoother="schwarz", schwarz_overlap=2)
+        F = torch.zeros(M.n_dof[0], dtype=torch.float64, device="cuda")
+        M.assemble_rhs(prob, F)
+        ua = torch.zeros_like(F)
+        sa = M.solve(F, ua, tol=1e-10, max_iter=1000, precision=precision)
+        d = np.abs(u - host(ua)).max() / np.abs(host(ua)).max()
+        print("server", st["iterations"], "alone", sa["iterations"], "max rel diff", d, flush=True)
+        assert st["iterations"] == sa["iterations"] and d <= 1e-14
+        M.free()
