@@ -27,7 +27,9 @@ then sum to one at every point.
 maps and face orientations and any degrees (one level, no 2:1 faces): a neighbour's points are
 placed in e_c's extended coordinates by the composed maps of the faces crossed to reach it.
 Where degrees differ across a face the subdomains are ragged; each face takes the narrower of
-its two sides' overlap widths.
+its two sides' overlap widths.  ``subdomains_boxes`` extends that to 2:1 faces on meshes of
+axis-aligned affine boxes, with positions scaled to e_c's half-widths as the extended
+coordinate (the library does not build this case yet).
 On the six-patch shell three cells meet around the radial lines through the cube's corners;
 there the subdomains cover three quadrants instead of four and their weights sum to 3/4, so
 they are divided by their sum wherever it is not one.
@@ -265,6 +267,75 @@ def subdomains_topo(op, n_overlap, normalise=True):
         for e, _, (perm, sign, shift) in [(c, None, ident)] + nb:
             xi = nodes[int(mesh["elem_p"][e])][0]
             ext = np.stack([sign[i] * xi[:, perm[i]] + shift[i] for i in range(3)], axis=1)
+            bound = np.where(ext > 1.0, 1.0 + np.array(d_hi), np.where(ext < -1.0, 1.0 + np.array(d_lo), 1.0))
+            inside = np.all(np.abs(ext) <= bound + 1e-12, axis=1)
+            if not inside.any():
+                continue
+            w = np.ones(int(inside.sum()))
+            for d in range(3):
+                w = w * weight_sides(ext[inside, d], d_lo[d], d_hi[d], open_lo[d], open_hi[d])
+            idx.append(op.offsets[e] + np.flatnonzero(inside))
+            wts.append(w)
+        out.append((np.concatenate(idx), np.concatenate(wts)))
+    if normalise:
+        total = np.zeros(op.ndof)
+        for idx, w in out:
+            np.add.at(total, idx, w)
+        fix = np.abs(total - 1.0) > 1e-12
+        if fix.any():
+            out = [(idx, np.where(fix[idx], w / np.where(fix[idx], total[idx], 1.0), w)) for idx, w in out]
+    return out
+
+
+def subdomains_boxes(op, n_overlap, normalise=True):
+    """Subdomains on meshes of axis-aligned affine boxes of any levels and degrees (2:1 faces
+    included), from positions: the extended coordinate of a point is its offset from e_c's
+    centre in units of e_c's half-widths (the macro reference coordinate of the paper's
+    definition, scaled to e_c).  The overlap width of a cell of degree p and half-width h is
+    delta_p h (delta_p = 1 + xi_(N_overlap - 1) of its LGL nodes, N_overlap at most p); each side
+    of e_c takes the narrowest width, in e_c's units, of e_c and the cells touching that side
+    across a face; a point of a neighbouring cell (closures touching) belongs to the subdomain
+    when it lies within the width of the side it is on, on every axis.  Weights as in
+    ``subdomains_topo``, normalised where they do not sum to one."""
+    mesh = op.mesh
+    E = len(mesh["elem_p"])
+    x0, J = geometry.element_map(mesh, np.arange(E)[:, None], np.zeros((1, 3)))
+    centre, J = x0[:, 0], J[:, 0]
+    half = np.einsum("eii->ei", J)
+    if np.abs(J - half[:, :, None] * np.eye(3)[None]).max() > 1e-12 * np.abs(J).max() or half.min() <= 0:
+        raise ValueError("these subdomains need axis-aligned affine elements")
+    nodes = {}
+    for p in set(int(p) for p in mesh["elem_p"]):
+        xl, _ = rules.lgl(p + 1)
+        xi = np.stack(np.meshgrid(xl, xl, xl, indexing="ij")[::-1], axis=-1).reshape(-1, 3)  # x fastest
+        nodes[p] = (xi, overlap_width(p + 1, min(n_overlap, p)))
+    tol = 1e-10 * half.min()
+    out = []
+    for c in range(E):
+        gap = np.abs(centre - centre[c]) - (half + half[c])
+        touch = np.flatnonzero(np.all(gap <= tol, axis=1))
+        touch = touch[touch != c]
+        d_lo, d_hi = [0.0] * 3, [0.0] * 3
+        open_lo, open_hi = [False] * 3, [False] * 3
+        dc = nodes[int(mesh["elem_p"][c])][1]
+        for e in touch:
+            # across a face of e_c: touching along d, overlapping with positive extent on the others
+            for d in range(3):
+                t = [a for a in range(3) if a != d]
+                if abs(gap[e, d]) > tol or np.any(gap[e, t] > -tol):
+                    continue
+                width = min(dc, nodes[int(mesh["elem_p"][e])][1] * half[e, d] / half[c, d])
+                if centre[e, d] < centre[c, d]:
+                    d_lo[d] = width if not open_lo[d] else min(d_lo[d], width)
+                    open_lo[d] = True
+                else:
+                    d_hi[d] = width if not open_hi[d] else min(d_hi[d], width)
+                    open_hi[d] = True
+        idx, wts = [], []
+        for e in [c] + sorted(int(e) for e in touch):
+            xi = nodes[int(mesh["elem_p"][e])][0]
+            ext = (centre[e] + half[e] * xi - centre[c]) / half[c]
+            ext = np.where(np.abs(np.abs(ext) - 1.0) <= 1e-12, np.sign(ext), ext)  # points on e_c's faces
             bound = np.where(ext > 1.0, 1.0 + np.array(d_hi), np.where(ext < -1.0, 1.0 + np.array(d_lo), 1.0))
             inside = np.all(np.abs(ext) <= bound + 1e-12, axis=1)
             if not inside.any():

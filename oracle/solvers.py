@@ -243,8 +243,13 @@ class Multigrid:
             self.schwarz = []
             for op in self.ops[:-1]:
                 A = assemble_dense(op)
-                # (an element of degree p < N_overlap holds at most p layers beyond the coincident one)
-                self.schwarz.append((A, schwarz.subdomains_topo(op, self.schwarz_overlap)))
+                # (an element of degree p < N_overlap holds at most p layers beyond the coincident
+                # one; levels with 2:1 faces take the construction from positions)
+                if len(set(int(x) for x in op.mesh["elem_level"])) > 1:
+                    subs = schwarz.subdomains_boxes(op, self.schwarz_overlap)
+                else:
+                    subs = schwarz.subdomains_topo(op, self.schwarz_overlap)
+                self.schwarz.append((A, subs))
             lam = [0.0] * (len(self.ops) - 1)
         if lam is None:
             lam = []

@@ -320,3 +320,56 @@ def test_schwarz_multigrid_on_a_random_degree_cube():
         _, its[name], _ = fcg(mg.ops[0].apply, mg.ops[0].rhs(), mg.vcycle, tol=1e-10, max_iter=200)
     print("FCG iterations", its)
     assert its["schwarz"] <= 8 and its["point"] >= 3 * its["schwarz"]
+
+
+BOX_2TO1 = {
+    "box_2to1_p3": lambda: meshgen.box_grid((2, 1, 1), 1, 3, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
+    "box_2to1_l2_p2": lambda: meshgen.box_grid((1, 1, 1), 2, 2, refine=[lambda k, c0, c1: c1.max() <= 0.5]),
+}
+
+
+@pytest.mark.parametrize("name", ["cube_l2_p3", "box_lopsided_l1_p3", "cube_l2_p2to4"])
+@pytest.mark.parametrize("n_overlap", [1, 2])
+def test_subdomains_from_positions_equal_the_topological_ones_at_one_level(name, n_overlap):
+    mesh = _mixed_degrees(meshgen.unit_cube(2, 2), [2, 3, 4], 1) if name == "cube_l2_p2to4" else MESHES[name]()
+    op = SIPG(mesh, meshgen.problem_config1())
+    for (i1, w1), (i2, w2) in zip(sw.subdomains_topo(op, n_overlap), sw.subdomains_boxes(op, n_overlap)):
+        assert np.array_equal(np.sort(i1), np.sort(i2))
+        assert np.allclose(w1[np.argsort(i1)], w2[np.argsort(i2)], rtol=0, atol=1e-14)
+
+
+def test_subdomains_across_2to1_faces():
+    # a box refined 2:1 on part of it: with one layer the weights sum to one everywhere (the
+    # fine side's narrower width is shared by both sides of every 2:1 face); with two, the
+    # points whose sum differs from one lie in cells at a 2:1 face; normalisation restores the
+    # partition of unity
+    mesh = BOX_2TO1["box_2to1_p3"]()
+    op = SIPG(mesh, meshgen.problem_config1())
+    lev = mesh["elem_level"]
+    at_2to1 = {int(e) for mt in op.mortars if mt["ep"] >= 0 and lev[mt["em"]] != lev[mt["ep"]]
+               for e in (mt["em"], mt["ep"])}
+    for n_overlap in (1, 2):
+        total = np.zeros(op.ndof)
+        for idx, w in sw.subdomains_boxes(op, n_overlap, normalise=False):
+            np.add.at(total, idx, w)
+        off = np.abs(total - 1.0) > 1e-12
+        assert off.any() == (n_overlap == 2)
+        elems = np.searchsorted(op.offsets, np.flatnonzero(off), side="right") - 1
+        assert {int(e) for e in elems} <= at_2to1
+        total = np.zeros(op.ndof)
+        for idx, w in sw.subdomains_boxes(op, n_overlap):
+            np.add.at(total, idx, w)
+        assert np.allclose(total, 1.0, rtol=0, atol=1e-14)
+
+
+@pytest.mark.parametrize("name", list(BOX_2TO1))
+def test_schwarz_multigrid_across_2to1_faces(name):
+    mesh = BOX_2TO1[name]()
+    prob = meshgen.problem_config1()
+    its = {}
+    for sm, kw in (("schwarz", dict(n_cheb=3, smoother="schwarz", schwarz_overlap=2)),
+                   ("point", dict(n_cheb=4, smoother="point"))):
+        mg = Multigrid(mesh, prob, **kw)
+        _, its[sm], _ = fcg(mg.ops[0].apply, mg.ops[0].rhs(), mg.vcycle, tol=1e-10, max_iter=200)
+    print(name, "FCG iterations", its)
+    assert its["schwarz"] <= 6 and its["point"] >= 3 * its["schwarz"]
