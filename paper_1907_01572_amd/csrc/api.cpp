@@ -1036,34 +1036,38 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   }
   if (size_t(schwarz_stride(max_m, 8)) * sizeof(double) > 64 * 1024)
     throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz subdomains of more than 8190 points");
-  const std::vector<int>& F = lay.fnb;
-  // operator blocks: element b, slot k (0: b itself, 1 + f: the neighbour a across face f), n3_a x
-  // n3_b column-major at boff[7 b + k]
-  std::vector<long long> boff(size_t(E) * 7, 0);
+  const std::vector<long long>& AS = lay.adj_start;
+  const std::vector<int>& AJ = lay.adj;
+  // operator blocks: element b, slot k (0: b itself, 1 + t: its t-th coupled element a), n3_a x
+  // n3_b column-major at boff[sstart[b] + k]
+  std::vector<long long> sstart(size_t(E) + 1, 0), boff;
+  int max_slots = 1;
   size_t blk_size = 0;
-  for (int b = 0; b < E; ++b)
-    for (int k = 0; k < 7; ++k) {
-      const int a = k == 0 ? b : F[size_t(b) * 6 + k - 1];
-      boff[size_t(b) * 7 + k] = (long long)blk_size;
-      if (a >= 0) blk_size += size_t(en3[a]) * en3[b];
+  for (int b = 0; b < E; ++b) {
+    const int deg = int(AS[b + 1] - AS[b]);
+    max_slots = std::max(max_slots, 1 + deg);
+    sstart[b + 1] = sstart[b] + 1 + deg;
+    for (int k = 0; k <= deg; ++k) {
+      const int a = k == 0 ? b : AJ[size_t(AS[b] + k - 1)];
+      if (a < 0 || a >= E) throw Error(HPDG_ERR_HIP, "Schwarz setup: coupled element out of range");
+      boff.push_back((long long)blk_size);
+      blk_size += size_t(en3[a]) * en3[b];
     }
+  }
   if (double(blk_size) * sizeof(double) > 16.0 * (1ull << 30))
     throw Error(HPDG_ERR_UNSUPPORTED, "Schwarz setup: operator blocks above 16 GiB");
-  // distance-2 colouring of the face graph (greedy, element order)
+  // distance-2 colouring of the coupling graph (greedy, element order)
   std::vector<int> color(E, -1);
   int ncol = 0;
   {
     std::vector<int> seen;
     for (int e = 0; e < E; ++e) {
       seen.clear();
-      for (int f = 0; f < 6; ++f) {
-        const int a = F[size_t(e) * 6 + f];
-        if (a < 0) continue;
+      for (long long t = AS[e]; t < AS[e + 1]; ++t) {
+        const int a = AJ[size_t(t)];
         seen.push_back(color[a]);
-        for (int g = 0; g < 6; ++g) {
-          const int b = F[size_t(a) * 6 + g];
-          if (b >= 0 && b != e) seen.push_back(color[b]);
-        }
+        for (long long u = AS[a]; u < AS[a + 1]; ++u)
+          if (AJ[size_t(u)] != e) seen.push_back(color[AJ[size_t(u)]]);
       }
       int c = 0;
       while (std::find(seen.begin(), seen.end(), c) != seen.end()) ++c;
@@ -1075,6 +1079,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   double* dblk = nullptr;
   int* den3 = nullptr;
   long long* dboff = nullptr;
+  long long* dsstart = nullptr;
   {
     DevLevel<double>& d = M->lev<double>(l);
     const LevelView<double> V = M->view<double>(l);
@@ -1088,10 +1093,12 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     std::vector<long long> eoff(static_cast<size_t>(E));
     for (int e = 0; e < E; ++e) eoff[e] = h.einfo[e].off;
     int* dmem = M->upload_raw(members, s);
-    int* dfnb = M->upload_raw(F, s);
+    long long* das = M->upload_raw(AS, s);
+    int* daj = M->upload_raw(AJ, s);
     long long* deoff = M->upload_raw(eoff, s);
     den3 = M->upload_raw(en3, s);
     dboff = M->upload_raw(boff, s);
+    dsstart = M->upload_raw(sstart, s);
     dblk = M->alloc<double>(blk_size);
     launch_fill<double>((long long)blk_size, 0.0, dblk, s);
     launch_fill<double>(h.ndof, 0.0, d.f, s);
@@ -1101,13 +1108,13 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       for (int j = 0; j < n3max; ++j) {
         launch_schwarz_units(cnt, mc, deoff, den3, j, 1.0, d.f, s);
         level_apply<double>(M, l, V, d.f, d.t, s);
-        launch_schwarz_gather(cnt, mc, dfnb, deoff, den3, dboff, j, d.t, dblk, s);
+        launch_schwarz_gather(cnt, max_slots, mc, das, daj, deoff, den3, dsstart, dboff, j, d.t, dblk, s);
         launch_schwarz_units(cnt, mc, deoff, den3, j, 0.0, d.f, s);
       }
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(s));
-    for (void* q : {(void*)dmem, (void*)dfnb, (void*)deoff}) M->release(q);
+    for (void* q : {(void*)dmem, (void*)das, (void*)daj, (void*)deoff}) M->release(q);
   }
   // device layout of the subdomains
   std::vector<int> gidx(lay.elem.size());
@@ -1180,6 +1187,14 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
   std::vector<int> els;
   std::vector<signed char> slot;
   schwarz_tables(lay, lel, els, slot);
+  for (int c = 0; c < E; ++c)  // every coupled pair's slot exists among the column element's blocks
+    for (int jb = 0; jb < kSchwarzMaxElems && els[size_t(c) * kSchwarzMaxElems + jb] >= 0; ++jb) {
+      const int eb = els[size_t(c) * kSchwarzMaxElems + jb];
+      for (int ia = 0; ia < kSchwarzMaxElems; ++ia) {
+        const int k = slot[(size_t(c) * kSchwarzMaxElems + jb) * kSchwarzMaxElems + ia];
+        if (k >= 0 && k > AS[eb + 1] - AS[eb]) throw Error(HPDG_ERR_HIP, "Schwarz setup: block slot out of range");
+      }
+    }
   std::vector<short> loc16(lay.loc.begin(), lay.loc.end());  // local indices < n^3 <= 4096
   unsigned char* dlel = M->upload_raw(lel, s);
   short* dloc = M->upload_raw(loc16, s);
@@ -1190,7 +1205,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
     const int m = g.first;
     const int cnt = int(subs.size());
     int* dsubs = M->upload_raw(subs, s);
-    launch_schwarz_assemble(m, cnt, dsubs, W.goff, dlel, dloc, dels, dslot, den3, dboff, dblk, dA, s);
+    launch_schwarz_assemble(m, cnt, dsubs, W.goff, dlel, dloc, dels, dslot, den3, dsstart, dboff, dblk, dA, s);
     HIPCHK(hipGetLastError());
     std::vector<double*> ptrs(cnt);
     std::vector<long long> pofs(cnt), gm(cnt), gm32(cnt), gw(cnt);
@@ -1236,7 +1251,7 @@ void build_schwarz(hpdg_mesh* M, int l, hipStream_t s) {
       if (q) M->release(q);
     }
   for (void* q : {(void*)dA, (void*)dblk, (void*)dlel, (void*)dloc, (void*)dels, (void*)dslot, (void*)den3,
-                  (void*)dboff})
+                  (void*)dboff, (void*)dsstart})
     M->release(q);
   M->release(dw);
 

@@ -13,6 +13,7 @@ namespace {
 
 constexpr int kSwBS = 512;   // eight waves per workgroup
 constexpr int kSwRows = 8;   // rows in flight per wave
+constexpr int kSchwarzElems = 64;  // elements per subdomain in the assembly tables (kSchwarzMaxElems)
 
 // row stride of the stored rows of a subdomain of m points in type T: m rounded up to the
 // 16-byte vector width (2 doubles, 4 floats)
@@ -59,21 +60,24 @@ __global__ void __launch_bounds__(256) schwarz_units_kernel(const int* __restric
 }
 
 // setup: column j of the operator blocks of the elements b of one colour from y = A x (x the
-// unit vectors of schwarz_units_kernel): block (b, k) at blk + boff[7 b + k], n3_a x n3_b,
-// column-major: blk[boff[7 b + k] + j n3_a + i] = y[off(a) + i], a = b (k = 0) or the neighbour
-// across face k - 1
+// unit vectors of schwarz_units_kernel): slot k of b (0: b itself, 1 + t: its t-th coupled
+// element a = adj[adj_start[b] + t]) holds the n3_a x n3_b block at blk + boff[sstart[b] + k],
+// column-major: blk[boff[sstart[b] + k] + j n3_a + i] = y[off(a) + i]
 __global__ void __launch_bounds__(256) schwarz_gather_kernel(const int* __restrict__ members,
-                                                           const int* __restrict__ fnb,
+                                                           const long long* __restrict__ adj_start,
+                                                           const int* __restrict__ adj,
                                                            const long long* __restrict__ eoff,
                                                            const int* __restrict__ en3,
+                                                           const long long* __restrict__ sstart,
                                                            const long long* __restrict__ boff, int j,
                                                            const double* __restrict__ y, double* __restrict__ blk) {
   const int b = members[blockIdx.x];
   const int k = blockIdx.y;
-  const int a = k == 0 ? b : fnb[6 * (long long)b + k - 1];
-  if (a < 0 || j >= en3[b]) return;
+  const long long a0 = adj_start[b];
+  if (k > adj_start[b + 1] - a0 || j >= en3[b]) return;
+  const int a = k == 0 ? b : adj[a0 + k - 1];
   const int n3a = en3[a];
-  double* dst = blk + boff[7 * (long long)b + k] + (long long)j * n3a;
+  double* dst = blk + boff[sstart[b] + k] + (long long)j * n3a;
   const double* src = y + eoff[a];
   for (int i = threadIdx.x; i < n3a; i += blockDim.x) dst[i] = src[i];
 }
@@ -88,17 +92,19 @@ __global__ void __launch_bounds__(256) schwarz_assemble_kernel(int m, const int*
                                                              const int* __restrict__ els,
                                                              const signed char* __restrict__ slot,
                                                              const int* __restrict__ en3,
+                                                             const long long* __restrict__ sstart,
                                                              const long long* __restrict__ boff,
                                                              const double* __restrict__ blk,
                                                              double* __restrict__ A) {
+  constexpr int K = kSchwarzElems;
   const int b = blockIdx.y, q = blockIdx.x;
   const int c = subs[b];
   const long long o = goff[c];
   const int eq = lel[o + q];
-  const int* ec = els + 27 * (long long)c;
-  const long long* bq = boff + 7 * (long long)ec[eq];
+  const int* ec = els + K * (long long)c;
+  const long long* bq = boff + sstart[ec[eq]];
   const int jq = loc[o + q];
-  const signed char* sc = slot + 729 * (long long)c + 27 * eq;
+  const signed char* sc = slot + (long long)K * K * c + K * eq;
   double* out = A + (long long)b * m * m + (long long)q * m;
   for (int p = threadIdx.x; p < m; p += blockDim.x) {
     const int lp = lel[o + p];
@@ -204,19 +210,21 @@ void launch_schwarz_units(int cnt, const int* members, const long long* eoff, co
                      members, cnt, eoff, en3, j, value, x);
 }
 
-void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, const int* en3,
-                           const long long* boff, int j, const double* y, double* blk, hipStream_t s) {
+void launch_schwarz_gather(int cnt, int max_slots, const int* members, const long long* adj_start, const int* adj,
+                           const long long* eoff, const int* en3, const long long* sstart, const long long* boff, int j,
+                           const double* y, double* blk, hipStream_t s) {
   if (cnt <= 0) return;
-  hipLaunchKernelGGL(schwarz_gather_kernel, dim3(unsigned(cnt), 7), dim3(256), 0, s, members, fnb, eoff, en3, boff, j,
-                     y, blk);
+  hipLaunchKernelGGL(schwarz_gather_kernel, dim3(unsigned(cnt), unsigned(max_slots)), dim3(256), 0, s, members,
+                     adj_start, adj, eoff, en3, sstart, boff, j, y, blk);
 }
 
 void launch_schwarz_assemble(int m, int cnt, const int* subs, const long long* goff, const unsigned char* lel,
                              const short* loc, const int* els, const signed char* slot, const int* en3,
-                             const long long* boff, const double* blk, double* A, hipStream_t s) {
+                             const long long* sstart, const long long* boff, const double* blk, double* A,
+                             hipStream_t s) {
   for (int b0 = 0; b0 < cnt; b0 += 32768)  // grid y stays below its 65535 limit
     hipLaunchKernelGGL(schwarz_assemble_kernel, dim3(unsigned(m), unsigned(std::min(32768, cnt - b0))), dim3(256), 0,
-                       s, m, subs + b0, goff, lel, loc, els, slot, en3, boff, blk, A + (long long)b0 * m * m);
+                       s, m, subs + b0, goff, lel, loc, els, slot, en3, sstart, boff, blk, A + (long long)b0 * m * m);
 }
 
 template <typename T>

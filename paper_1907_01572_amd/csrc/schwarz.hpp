@@ -7,20 +7,23 @@
 namespace hpdg {
 
 // Setup: unit vectors x[off(b) + j] = value for the cnt elements ``members`` with n_b^3 > j (one
-// colour of a distance-2 colouring of the face graph), and column j of their operator blocks
-// from y = A x: blk[boff[7 b + k] + j n3_a + i] = y[off(a) + i], a = b (k = 0) or fnb[6 b + k - 1]
-// (skipped when -1); eoff: each element's dof offset, en3: its n^3
+// colour of a distance-2 colouring of the operator's coupling graph), and column j of their
+// operator blocks from y = A x: slot k of b (0: b, 1 + t: a = adj[adj_start[b] + t]) at
+// blk + boff[sstart[b] + k], n3_a x n3_b column-major; max_slots bounds 1 + the coupled elements
+// of any member; eoff: each element's dof offset, en3: its n^3
 void launch_schwarz_units(int cnt, const int* members, const long long* eoff, const int* en3, int j, double value,
                           double* x, hipStream_t s);
-void launch_schwarz_gather(int cnt, const int* members, const int* fnb, const long long* eoff, const int* en3,
-                           const long long* boff, int j, const double* y, double* blk, hipStream_t s);
+void launch_schwarz_gather(int cnt, int max_slots, const int* members, const long long* adj_start, const int* adj,
+                           const long long* eoff, const int* en3, const long long* sstart, const long long* boff, int j,
+                           const double* y, double* blk, hipStream_t s);
 // Setup: A_ss of the cnt subdomains subs[b] of m points each, column-major at A + b m^2, from the
-// operator blocks (block (e, k) at blk + boff[7 e + k], n3_a x n3_e column-major, a = e or its
-// neighbour across face k - 1; en3: each element's n^3) through the tables of schwarz_tables
-// (lel and loc per entry at goff[subs[b]], els 27 and slot 27 x 27 per subdomain)
+// operator blocks through the tables of schwarz_tables (lel and loc per entry at goff[subs[b]],
+// els 64 and slot 64 x 64 per subdomain; the slot of an element pair indexes the column
+// element's blocks at boff[sstart[e] + slot])
 void launch_schwarz_assemble(int m, int cnt, const int* subs, const long long* goff, const unsigned char* lel,
                              const short* loc, const int* els, const signed char* slot, const int* en3,
-                             const long long* boff, const double* blk, double* A, hipStream_t s);
+                             const long long* sstart, const long long* boff, const double* blk, double* A,
+                             hipStream_t s);
 // row stride of the stored rows of a subdomain of m points for scalars of scalar_bytes bytes: m
 // rounded up to the 16-byte vector width (2 doubles, 4 floats)
 int schwarz_stride(int m, int scalar_bytes);

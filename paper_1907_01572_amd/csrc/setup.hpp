@@ -214,16 +214,18 @@ struct SchwarzLayout {
   std::vector<int> nw;            // per subdomain: entries with a non-zero weight
   std::vector<int> elem, loc;     // element and local dof index of each entry
   std::vector<double> w;          // weight of each entry
-  std::vector<int> fnb;           // per element and face (6 per element): face neighbour or -1
+  std::vector<long long> adj_start;  // per element: first of the elements it is coupled to (E + 1)
+  std::vector<int> adj;              // the elements coupled by the operator (across mortars), sorted
   std::vector<int> en;            // per element: LGL nodes per axis
   int n = 0;                      // the largest of them
 };
 void schwarz_layout(const MacroMesh& mm, const LevelHost& L, int n_overlap, SchwarzLayout& out);
 // Assembly tables of the subdomains: per entry, the index of its element among the subdomain's
-// elements (lel); per subdomain, those elements (els, 27 per subdomain, -1 past the last) and,
-// per ordered pair (column element, row element), the operator block holding their coupling
-// (slot, 27 x 27 per subdomain: 0 the element itself, 1 + f its neighbour across face f, -1
-// none: the pair is not coupled)
+// elements (lel); per subdomain, those elements (els, kSchwarzMaxElems per subdomain, -1 past
+// the last) and, per ordered pair (column element, row element), the operator block holding
+// their coupling (slot, kSchwarzMaxElems^2 per subdomain: 0 the element itself, 1 + t its t-th
+// coupled element in adj, -1 none: the pair is not coupled)
+constexpr int kSchwarzMaxElems = 64;
 void schwarz_tables(const SchwarzLayout& lay, std::vector<unsigned char>& lel, std::vector<int>& els,
                     std::vector<signed char>& slot);
 

@@ -56,6 +56,10 @@ def _two_degrees():
 # one level, degrees that differ across faces: ragged subdomains
 MESHES["box_2x1x1_p2_p3"] = _two_degrees
 MESHES["cube_l2_p2to4"] = lambda: _mixed_degrees(meshgen.unit_cube(2, 2), [2, 3, 4], 1)
+# 2:1 faces (boxes): subdomains from positions
+MESHES["box_2to1_p3"] = lambda: meshgen.box_grid((2, 1, 1), 1, 3,
+                                                 refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5])
+MESHES["box_2to1_l2_p2"] = lambda: meshgen.box_grid((1, 1, 1), 2, 2, refine=[lambda k, c0, c1: c1.max() <= 0.5])
 
 
 @pytest.fixture(scope="module")
@@ -80,7 +84,8 @@ def host(t):
                                             ("box_2x1x1_l1_p2", 2), ("box_lopsided_l1_p3", 3),
                                             ("cube_l1_p6", 2), ("shell_l1_p2_r1e3", 1), ("shell_l1_p2_r1e3", 2),
                                             ("shell_l1_p3_r1e9", 2), ("box_2x1x1_p2_p3", 2), ("cube_l2_p2to4", 1),
-                                            ("cube_l2_p2to4", 2)])
+                                            ("cube_l2_p2to4", 2), ("box_2to1_p3", 1), ("box_2to1_p3", 2),
+                                            ("box_2to1_l2_p2", 2)])
 def test_schwarz_smooth_and_vcycle_parity(ctx, name, n_overlap):
     m = MESHES[name]()
     prob = PROBLEM.get(name, meshgen.problem_config1())
@@ -107,7 +112,7 @@ def test_schwarz_smooth_and_vcycle_parity(ctx, name, n_overlap):
     M.free()
 
 
-@pytest.mark.parametrize("name", ["cube_l2_p3", "cube_l2_p2to4"])
+@pytest.mark.parametrize("name", ["cube_l2_p3", "cube_l2_p2to4", "box_2to1_p3"])
 def test_schwarz_fcg_follows_the_oracle(ctx, name):
     # N_overlap = 2, three cycles per smoothing call: the library's FCG takes the oracle's
     # iterations and reaches its solution; point-Jacobi Chebyshev needs several times as many
@@ -203,11 +208,10 @@ def test_schwarz_fp32_and_mixed_solve(ctx, name):
 
 
 def test_schwarz_refusals(ctx):
-    # 2:1 faces are outside the smoother's scope (the shell with its extra inner refinement, a
-    # refined box); the overlap is at least one (a larger one than the degree is clamped to it);
+    # 2:1 faces on curved cells are outside the smoother's scope (the shell with its extra inner
+    # refinement); the overlap is at least one (a larger one than the degree is clamped to it);
     # FP32 smoothing needs FP32 levels
-    for mesh in (meshgen.box_grid((2, 1, 1), 1, 3, refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5]),
-                 meshgen.cubed_sphere_shell(level=1, p=2, r_out=1e3)):
+    for mesh in (meshgen.cubed_sphere_shell(level=1, p=2, r_out=1e3),):
         M = ctx.upload(mesh)
         with pytest.raises(hp.HpdgError) as ei:
             M.setup_smoother(smoother="schwarz")
