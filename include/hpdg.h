@@ -206,9 +206,12 @@ typedef struct {
  *                      shell) the weights covering a point are divided by their sum; so they
  *                      sum to one at every point.  Where degrees differ across a face the
  *                      subdomains are ragged: each face takes the narrower of its two cells'
- *                      overlap widths.  Scope: every smoothed level has one refinement level and
- *                      faces that meet 1:1 (any degrees), subdomains of at most 8190 points
- *                      (HPDG_ERR_UNSUPPORTED at setup otherwise).  On meshes with FP32
+ *                      overlap widths.  Levels with 2:1 faces need axis-aligned affine cells:
+ *                      there the extended coordinate is the offset from the centre cell in units
+ *                      of its half-widths, and a cell's width is scaled by its half-width.  Scope:
+ *                      every smoothed level has one refinement level and faces that meet 1:1,
+ *                      or axis-aligned affine cells; subdomains of at most 8190 points and 64
+ *                      cells (HPDG_ERR_UNSUPPORTED at setup otherwise).  On meshes with FP32
  *                      levels the stored rows are also kept rounded to FP32, for FP32 smoothing
  *                      and the FP32 V-cycle of mixed-precision solves.  Not rebuilt for Newton
  *                      linearisations (HPDG_ERR_UNSUPPORTED).  No spectral bound is computed
