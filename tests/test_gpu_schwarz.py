@@ -60,6 +60,9 @@ MESHES["cube_l2_p2to4"] = lambda: _mixed_degrees(meshgen.unit_cube(2, 2), [2, 3,
 MESHES["box_2to1_p3"] = lambda: meshgen.box_grid((2, 1, 1), 1, 3,
                                                  refine=[lambda k, c0, c1: k[1] == 1 and c1.max() <= 0.5])
 MESHES["box_2to1_l2_p2"] = lambda: meshgen.box_grid((1, 1, 1), 2, 2, refine=[lambda k, c0, c1: c1.max() <= 0.5])
+# the hp cube's family: 2:1 around the coefficient jump, degrees 2..4, k = 1 | 5 across r = 0.6
+MESHES["hp_p2_4_l2"] = lambda: meshgen.hp_sphere_cube(level=2, p_lo=2, p_hi=4, seed=3, r_cut=0.6)
+PROBLEM["hp_p2_4_l2"] = meshgen.problem_config3(r0=0.6)
 
 
 @pytest.fixture(scope="module")
@@ -85,7 +88,7 @@ def host(t):
                                             ("cube_l1_p6", 2), ("shell_l1_p2_r1e3", 1), ("shell_l1_p2_r1e3", 2),
                                             ("shell_l1_p3_r1e9", 2), ("box_2x1x1_p2_p3", 2), ("cube_l2_p2to4", 1),
                                             ("cube_l2_p2to4", 2), ("box_2to1_p3", 1), ("box_2to1_p3", 2),
-                                            ("box_2to1_l2_p2", 2)])
+                                            ("box_2to1_l2_p2", 2), ("hp_p2_4_l2", 2)])
 def test_schwarz_smooth_and_vcycle_parity(ctx, name, n_overlap):
     m = MESHES[name]()
     prob = PROBLEM.get(name, meshgen.problem_config1())
